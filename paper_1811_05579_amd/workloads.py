@@ -1,0 +1,113 @@
+"""Seeded synthetic workloads for the 1-D AP step (inputs only, no method).
+
+The paper's experiments are analytic set-ups, not datasets; these generators
+reproduce the benchmark configurations of this project with the shapes and
+value distributions stated below.  Everything is deterministic given the
+seed (numpy PCG64, seed 18110000 + configuration number).
+
+  config 1  slab x in [0,1], N = 100, 16 Gauss-Legendre ordinates,
+            a = c = Cv = 1, sigma = 1 (m = 0), eps = 1e-2, T = 1e-2,
+            I = ac T^4, inflow b = ac at x = 0 (mu > 0), vacuum at x = 1,
+            dt = 0.5 dx, 200 steps.
+  config 2  N = 4096, 64 ordinates, sigma = sigma0 T^-3 with sigma0 ~ U[0.5, 2]
+            i.i.d. per cell, eps in {1, 1e-2, 1e-4}, same initial and inflow
+            data, dt = 0.5 dx, 2000 steps.
+
+The velocity grid (Gauss-Legendre pairs: positive nodes by increasing mu,
+weight of +mu on [-1, 1], so the weights sum to one) is part of the input:
+both the oracle and the GPU library receive these exact binary64 values.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 18110000
+
+
+def gauss_legendre_pairs(nv):
+    """Positive nodes of the nv-point Gauss-Legendre rule and their weights."""
+    x, w = np.polynomial.legendre.leggauss(int(nv))
+    pos = x > 0
+    order = np.argsort(x[pos])
+    return (np.ascontiguousarray(x[pos][order], dtype=np.float64),
+            np.ascontiguousarray(w[pos][order], dtype=np.float64))
+
+
+@dataclass
+class Workload:
+    name: str
+    N: int
+    nv: int
+    m: int
+    eps: float
+    dt: float
+    steps: int
+    a: float = 1.0
+    c: float = 1.0
+    Cv: float = 1.0
+    L: float = 1.0
+    mu: np.ndarray = field(default=None, repr=False)
+    omega: np.ndarray = field(default=None, repr=False)
+    sigma0: np.ndarray = field(default=None, repr=False)
+    T: np.ndarray = field(default=None, repr=False)
+    E: np.ndarray = field(default=None, repr=False)
+    O: np.ndarray = field(default=None, repr=False)
+    bL: np.ndarray = field(default=None, repr=False)
+    bR: np.ndarray = field(default=None, repr=False)
+
+    @property
+    def P(self):
+        return self.nv // 2
+
+    def cell_angle_updates(self):
+        """N_cells * N_v: the unit of the throughput metric."""
+        return self.N * self.nv
+
+
+def _slab(name, N, nv, m, eps, steps, sigma0, T_in=1e-2, b_hot=1.0, a=1.0, c=1.0, Cv=1.0,
+          cfl=0.5, L=1.0):
+    mu, om = gauss_legendre_pairs(nv)
+    P = nv // 2
+    T = np.full(N, T_in, dtype=np.float64)
+    E = np.full((N, P), a * c * T_in ** 4, dtype=np.float64)
+    O = np.zeros((N + 1, P), dtype=np.float64)
+    bL = np.full(P, a * c * b_hot ** 4, dtype=np.float64)
+    bR = np.zeros(P, dtype=np.float64)
+    dt = cfl * L / N
+    return Workload(name=name, N=N, nv=nv, m=m, eps=eps, dt=dt, steps=steps, a=a, c=c, Cv=Cv,
+                    L=L, mu=mu, omega=om, sigma0=np.asarray(sigma0, dtype=np.float64),
+                    T=T, E=E, O=O, bL=bL, bR=bR)
+
+
+def config1():
+    """1-D, N = 100, GL16, sigma = 1, eps = 1e-2, 200 steps."""
+    N = 100
+    return _slab("config1", N, 16, 0, 1e-2, 200, np.ones(N))
+
+
+def config2(eps=1e-2, N=4096, nv=64, steps=2000):
+    """1-D, N = 4096, GL64, sigma0 T^-3 with seeded sigma0 ~ U[0.5, 2]."""
+    if eps not in (1.0, 1e-2, 1e-4) and (N, nv) == (4096, 64):
+        raise ValueError("config 2 is defined for eps in {1, 1e-2, 1e-4}")
+    rng = np.random.default_rng(SEED_BASE + 2)
+    sigma0 = rng.uniform(0.5, 2.0, 4096)
+    if N != 4096:
+        sigma0 = np.random.default_rng(SEED_BASE + 2).uniform(0.5, 2.0, N)
+    return _slab(f"config2(eps={eps:g})", N, nv, 3, eps, steps, sigma0)
+
+
+def random_state(N, nv, seed, m=3, eps=1e-2, T_lo=0.05, T_hi=1.0, anisotropy=0.2):
+    """A generic near-equilibrium state with seeded opacity and inflow,
+    used to exercise every code path (not one of the named configurations)."""
+    rng = np.random.default_rng(SEED_BASE + 1000 + seed)
+    mu, om = gauss_legendre_pairs(nv)
+    P = nv // 2
+    T = rng.uniform(T_lo, T_hi, N)
+    E = (T ** 4)[:, None] * (1.0 + anisotropy * rng.uniform(-1, 1, (N, P)))
+    O = 0.1 * rng.normal(size=(N + 1, P)) * np.max(E)
+    sigma0 = rng.uniform(0.3, 3.0, N)
+    bL = rng.uniform(0.5, 1.5, P)
+    bR = rng.uniform(0.0, 0.3, P)
+    return Workload(name=f"random(N={N},nv={nv},seed={seed})", N=N, nv=nv, m=m, eps=eps,
+                    dt=0.5 / N, steps=1, mu=mu, omega=om, sigma0=sigma0, T=T, E=E, O=O,
+                    bL=bL, bR=bR)
