@@ -1,0 +1,152 @@
+/*
+ * grte.h -- C ABI of the MI355X library for the asymptotic-preserving (AP)
+ * time step of the 1-D gray radiative transfer equation
+ *
+ *   (1/c) d_t I + (1/eps) v d_x I = (sigma/eps^2)(a c T^4 - I),
+ *   Cv d_t T = (sigma/eps^2)(rho - a c T^4),   rho = <I> = (1/2) int_{-1}^{1} I dv,
+ *
+ * ((1.1); sigma = sigma0 or sigma0 / T^3 as in (1.4)) with inflow data (4.1),
+ * discretised with the even/odd parities (4.2) on the staggered grid
+ * (4.3)-(4.4) and advanced by Algorithm 2 of Tang, Wang & Zhang,
+ * arXiv 1811.05579 (prediction (4.5)/(5.2), correction (4.13) + (4.11)/(5.3),
+ * projection (4.14)).
+ *
+ * Conventions
+ *  - Every call returns a grte_status (0 = success, < 0 = error); no C++
+ *    exception crosses the ABI.  On error nothing is partially committed
+ *    unless stated.
+ *  - N cells j = 0..N-1 on [0, L]; N+1 nodes i = 0..N (node i between cells
+ *    i-1 and i).  P parity pairs p = 0..P-1 with mu_p > 0.
+ *  - Parity arrays are cell-major, binary64: E[j*P + p] (cell centres,
+ *    (4.3)) and O[i*P + p] (nodes, (4.4)); T[j] and sigma0[j] per cell.
+ *  - The context owns all device memory.  Pointers passed in are borrowed for
+ *    the duration of the call only; `on_device` != 0 means the pointer is
+ *    device memory (copied on the context's stream), otherwise host memory.
+ *  - All device work is ordered on the context's HIP stream (default: the
+ *    null stream).  Calls that read results into host memory synchronise
+ *    that stream; grte_step itself does not, unless `info` is non-NULL.
+ *  - One context must not be used from two threads at once.
+ */
+#ifndef GRTE_H
+#define GRTE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum grte_status {
+    GRTE_OK = 0,
+    GRTE_E_INVAL = -1,       /* NULL pointer, size or value out of range        */
+    GRTE_E_NOMEM = -2,       /* device allocation failed                         */
+    GRTE_E_HIP = -3,         /* a HIP runtime call or kernel launch failed       */
+    GRTE_E_NOCONV = -4,      /* step completed, but the prediction iteration or
+                                a Newton solve stopped at its cap (see info)    */
+    GRTE_E_UNSUPPORTED = -5  /* size beyond this build's limits (N > 4096 or
+                                P > 64)                                          */
+} grte_status;
+
+typedef struct grte_ctx grte_ctx;
+
+/* Problem definition (fixed for the life of a context). */
+typedef struct grte_problem {
+    int nx;            /* number of cells N, 2 <= N <= 4096                      */
+    int npairs;        /* parity pairs P = N_v / 2, 1 <= P <= 64                 */
+    double length;     /* slab length L > 0                                      */
+    double a;          /* radiation constant a > 0                               */
+    double c;          /* speed of light c > 0                                   */
+    double cv;         /* heat capacity Cv > 0                                   */
+    int opacity_law;   /* m: 0 -> sigma = sigma0; 3 -> sigma = sigma0 / T^3 (1.4) */
+} grte_problem;
+
+/* Diagnostics of one step (filled only when a non-NULL pointer is passed). */
+typedef struct grte_step_info {
+    int pred_iters;       /* iterations of the prediction solve                 */
+    int pred_converged;   /* 1 if the prediction met its tolerance              */
+    int newton_max_iters; /* largest Newton iteration count over the cells      */
+    int newton_failed;    /* cells whose Newton solve hit the cap               */
+    int kstar_clamped;    /* sigma/T^3: cells with U* < 0 (K* taken as 0)       */
+    int negative_root;    /* cells whose temperature equation has no root >= 0  */
+} grte_step_info;
+
+/* Stages readable after a step (grte_get_stage), for checking and diagnostics. */
+enum {
+    GRTE_STAGE_ESTAR = 0, /* E* of the prediction, N*P, cell-major               */
+    GRTE_STAGE_OSTAR = 1, /* O* of the prediction, (N+1)*P, cell-major           */
+    GRTE_STAGE_USTAR = 2, /* U* from (4.5c), N                                   */
+    GRTE_STAGE_D = 3,     /* flux divergence D of (4.13), N                      */
+    GRTE_STAGE_RHO = 4    /* rho^{n+1} = sum_p omega_p E^{n+1}_p, N              */
+};
+
+/* Gauss-Legendre parity pairs (host, no device work): the nv/2 positive
+ * nodes of the nv-point rule on [-1, 1] in increasing order, and the weight of
+ * +mu_p, so that sum_p omega_p = 1 and rho = sum_p omega_p E_p.  nv even,
+ * 2 <= nv <= 128; mu and omega must hold nv/2 doubles.  (The paper leaves the
+ * velocity grid open; see the remark after (4.5).) */
+grte_status grte_gauss_legendre(int nv, double *mu, double *omega);
+
+/* Create a context: copies the problem and the velocity grid (host arrays
+ * mu[P], omega[P] with mu_p > 0; the exact binary64 weights are used, their
+ * sum need not be exactly one) and allocates device memory.  The state is
+ * zero and the opacity one until set.  *out receives the context. */
+grte_status grte_create(const grte_problem *pb, const double *mu,
+                        const double *omega, grte_ctx **out);
+
+/* Free the context and its device memory (NULL is accepted). */
+grte_status grte_destroy(grte_ctx *ctx);
+
+/* Order all further work of the context on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  The stream must outlive its use. */
+grte_status grte_set_stream(grte_ctx *ctx, void *hip_stream);
+
+/* Opacity coefficient per cell: sigma0[N] >= 0 ((1.1), or the T-independent
+ * factor of sigma/T^3 in (1.4)). */
+grte_status grte_set_opacity(grte_ctx *ctx, const double *sigma0, int on_device);
+
+/* Inflow data (4.1): b_left[p] = b_L(mu_p) at x = 0, b_right[p] = b_R(-mu_p)
+ * at x = L; host arrays of P doubles. */
+grte_status grte_set_inflow(grte_ctx *ctx, const double *b_left, const double *b_right);
+
+/* State (E^n, O^n, T^n): E[N*P], O[(N+1)*P] cell-major, T[N] >= 0. */
+grte_status grte_set_state(grte_ctx *ctx, const double *E, const double *O,
+                           const double *T, int on_device);
+
+/* Copy the current state out (same layouts as grte_set_state).  Any of the
+ * three pointers may be NULL to skip it. */
+grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int on_device);
+
+/* One AP step of Algorithm 2 with time step dt > 0 and eps > 0.  The state is
+ * replaced by (E^{n+1}, O^{n+1}, T^{n+1}).  With info == NULL the call only
+ * enqueues work; otherwise it synchronises and fills *info.  Returns
+ * GRTE_E_NOCONV (state still advanced) if info != NULL and a solve hit its
+ * cap. */
+grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info);
+
+/* Copy a stage of the last step (GRTE_STAGE_*) into out (sizes above). */
+grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device);
+
+/* Solver controls: relative tolerance of the prediction update (default
+ * 1e-15), its iteration cap (default 200) and the Newton cap (default 100). */
+grte_status grte_set_solver(grte_ctx *ctx, double pred_tol, int pred_maxit, int newton_maxit);
+
+/* Stage timing with HIP events recorded on the context's stream around each
+ * timed stage of every grte_step (off by default; enabling resets the log). */
+enum {
+    GRTE_TIMING_STEP = 0,     /* the whole step, first to last kernel          */
+    GRTE_TIMING_PREDICT = 1,  /* the prediction solve kernel (4.5)/(5.2)       */
+    GRTE_TIMING_NSTAGES = 2
+};
+grte_status grte_set_profiling(grte_ctx *ctx, int on);
+
+/* Synchronise the stream and return, per GRTE_TIMING_* stage, the summed
+ * elapsed milliseconds and the number of timed launches since profiling was
+ * enabled or last read (arrays of GRTE_TIMING_NSTAGES entries); clears the log. */
+grte_status grte_read_timing(grte_ctx *ctx, double *total_ms, int *count);
+
+/* Static text for a status code. */
+const char *grte_status_string(grte_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRTE_H */

@@ -1,0 +1,153 @@
+"""MI355X (gfx950) library for the asymptotic-preserving step of the 1-D gray
+radiative transfer equation (Tang, Wang & Zhang, arXiv 1811.05579, Algorithm 2
+and Section 5).
+
+The Python layer only marshals arguments into the C ABI of include/grte.h;
+every stage of the step runs in the HIP kernels of csrc/grte.hip.  Arrays may
+be numpy arrays (host memory, copied by the library) or torch CUDA tensors
+(device memory, borrowed for the call).
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import GrteError, Problem, StepInfo, check, load
+
+__all__ = ["Grte", "GrteError", "gauss_legendre", "load"]
+
+
+def gauss_legendre(nv):
+    """Gauss-Legendre parity pairs computed by the library (host routine)."""
+    lib = load()
+    P = nv // 2
+    mu = np.zeros(P)
+    om = np.zeros(P)
+    check("grte_gauss_legendre", lib.grte_gauss_legendre(int(nv), mu.ctypes.data, om.ctypes.data))
+    return mu, om
+
+
+def _ptr(x, n, name):
+    """(pointer, on_device) for a float64 numpy array or torch tensor of n elements."""
+    if hasattr(x, "data_ptr"):
+        import torch
+        if x.dtype != torch.float64 or not x.is_contiguous() or x.numel() != n:
+            raise ValueError(f"{name}: need a contiguous float64 tensor of {n} elements")
+        return ctypes.c_void_p(x.data_ptr()), int(x.is_cuda)
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    if a.size != n:
+        raise ValueError(f"{name}: need {n} elements, got {a.size}")
+    return a, 0
+
+
+def _addr(a):
+    return a if isinstance(a, ctypes.c_void_p) else ctypes.c_void_p(a.ctypes.data)
+
+
+class Grte:
+    """One AP solver context (owns its device memory)."""
+
+    def __init__(self, nx, mu, omega, length=1.0, a=1.0, c=1.0, cv=1.0, opacity_law=0):
+        self._lib = load()
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        omega = np.ascontiguousarray(omega, dtype=np.float64)
+        if mu.shape != omega.shape or mu.ndim != 1:
+            raise ValueError("mu and omega must be 1-D arrays of equal length")
+        self.N, self.P = int(nx), int(mu.size)
+        pb = Problem(self.N, self.P, float(length), float(a), float(c), float(cv), int(opacity_law))
+        h = ctypes.c_void_p()
+        check("grte_create", self._lib.grte_create(ctypes.byref(pb), mu.ctypes.data,
+                                                   omega.ctypes.data, ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.grte_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        """Use a torch.cuda.Stream (or a raw hipStream_t integer, 0 = null stream)."""
+        raw = getattr(stream, "cuda_stream", stream)
+        check("grte_set_stream", self._lib.grte_set_stream(self._h, ctypes.c_void_p(int(raw))))
+
+    def set_solver(self, pred_tol=1e-15, pred_maxit=200, newton_maxit=100):
+        check("grte_set_solver", self._lib.grte_set_solver(self._h, float(pred_tol), int(pred_maxit),
+                                                           int(newton_maxit)))
+
+    def set_opacity(self, sigma0):
+        p, dev = _ptr(sigma0, self.N, "sigma0")
+        check("grte_set_opacity", self._lib.grte_set_opacity(self._h, _addr(p), dev))
+
+    def set_inflow(self, b_left, b_right):
+        bl = np.ascontiguousarray(b_left, dtype=np.float64)
+        br = np.ascontiguousarray(b_right, dtype=np.float64)
+        if bl.size != self.P or br.size != self.P:
+            raise ValueError("inflow arrays need P entries")
+        check("grte_set_inflow", self._lib.grte_set_inflow(self._h, bl.ctypes.data, br.ctypes.data))
+
+    def set_state(self, E, O, T):
+        pe, d1 = _ptr(E, self.N * self.P, "E")
+        po, d2 = _ptr(O, (self.N + 1) * self.P, "O")
+        pt, d3 = _ptr(T, self.N, "T")
+        if not (d1 == d2 == d3):
+            raise ValueError("E, O, T must all be host arrays or all device tensors")
+        check("grte_set_state", self._lib.grte_set_state(self._h, _addr(pe), _addr(po), _addr(pt), d1))
+
+    def get_state(self, out=None):
+        """Return (E (N,P), O (N+1,P), T (N,)) as numpy arrays, or fill the torch
+        tensors passed in `out`."""
+        if out is not None:
+            E, O, T = out
+            pe, d = _ptr(E, self.N * self.P, "E")
+            po, _ = _ptr(O, (self.N + 1) * self.P, "O")
+            pt, _ = _ptr(T, self.N, "T")
+            check("grte_get_state", self._lib.grte_get_state(self._h, _addr(pe), _addr(po), _addr(pt), d))
+            return out
+        E = np.empty((self.N, self.P))
+        O = np.empty((self.N + 1, self.P))
+        T = np.empty(self.N)
+        check("grte_get_state", self._lib.grte_get_state(self._h, E.ctypes.data, O.ctypes.data,
+                                                         T.ctypes.data, 0))
+        return E, O, T
+
+    def get_stage(self, name):
+        n = {"E_star": self.N * self.P, "O_star": (self.N + 1) * self.P}.get(name, self.N)
+        out = np.empty(n)
+        check("grte_get_stage", self._lib.grte_get_stage(self._h, _lib.STAGES[name], out.ctypes.data, 0))
+        if name == "E_star":
+            return out.reshape(self.N, self.P)
+        if name == "O_star":
+            return out.reshape(self.N + 1, self.P)
+        return out
+
+    def set_profiling(self, on=True):
+        check("grte_set_profiling", self._lib.grte_set_profiling(self._h, int(bool(on))))
+
+    def read_timing(self):
+        """{stage: (total_ms, launches)} from the library's HIP events."""
+        n = len(_lib.TIMING)
+        ms = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int32)
+        check("grte_read_timing", self._lib.grte_read_timing(self._h, ms.ctypes.data, cnt.ctypes.data))
+        return {k: (float(ms[v]), int(cnt[v])) for k, v in _lib.TIMING.items()}
+
+    def step(self, dt, eps, info=False):
+        """One AP step.  With info=True, synchronise and return the step
+        diagnostics (dict, including 'status'); otherwise only enqueue."""
+        if info:
+            si = StepInfo()
+            st = self._lib.grte_step(self._h, float(dt), float(eps), ctypes.byref(si))
+            if st not in (0, -4):
+                check("grte_step", st)
+            d = si.as_dict()
+            d["status"] = st
+            return d
+        check("grte_step", self._lib.grte_step(self._h, float(dt), float(eps), None))
+        return None

@@ -1,0 +1,79 @@
+"""ctypes declarations of the C ABI in include/grte.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrte.so")
+
+c_int, c_double, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+c_double_p = ctypes.POINTER(ctypes.c_double)
+
+GRTE_OK = 0
+STATUS = {0: "GRTE_OK", -1: "GRTE_E_INVAL", -2: "GRTE_E_NOMEM", -3: "GRTE_E_HIP",
+          -4: "GRTE_E_NOCONV", -5: "GRTE_E_UNSUPPORTED"}
+STAGES = {"E_star": 0, "O_star": 1, "U_star": 2, "D": 3, "rho": 4}
+TIMING = {"step": 0, "predict": 1}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("npairs", c_int), ("length", c_double), ("a", c_double),
+                ("c", c_double), ("cv", c_double), ("opacity_law", c_int)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
+                ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS = {
+    "grte_gauss_legendre": (c_int, [c_int, c_void_p, c_void_p]),
+    "grte_create": (c_int, [ctypes.POINTER(Problem), c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "grte_destroy": (c_int, [c_void_p]),
+    "grte_set_stream": (c_int, [c_void_p, c_void_p]),
+    "grte_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
+    "grte_set_inflow": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "grte_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "grte_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "grte_step": (c_int, [c_void_p, c_double, c_double, ctypes.POINTER(StepInfo)]),
+    "grte_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
+    "grte_set_solver": (c_int, [c_void_p, c_double, c_int, c_int]),
+    "grte_set_profiling": (c_int, [c_void_p, c_int]),
+    "grte_read_timing": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "grte_status_string": (ctypes.c_char_p, [c_int]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libgrte.so from the package directory; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1811_05579_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class GrteError(RuntimeError):
+    def __init__(self, call, status):
+        msg = load().grte_status_string(status).decode()
+        super().__init__(f"{call} -> {STATUS.get(status, status)} ({msg})")
+        self.status = status
+
+
+def check(call, status):
+    if status != GRTE_OK:
+        raise GrteError(call, status)
+    return status

@@ -1,0 +1,1080 @@
+// grte.hip -- MI355X (gfx950) implementation of the AP step of Tang, Wang &
+// Zhang (arXiv 1811.05579) for the 1-D gray radiative transfer equation, and
+// the C ABI declared in include/grte.h.
+//
+// Formulation (exact algebra of Section 4/5, arranged for the GPU)
+// ----------------------------------------------------------------
+// Every equation is multiplied by eps^2 c dt.  The node equation (4.5a)/(5.2a)
+// gives O at interior nodes explicitly in E:
+//     O_i = Aw_i O^n_i - Bc_i mu (E_i - E_{i-1}),
+//     Aw_i = K_i eps^2 / den_i,  Bc_i = K_i c dt / (dx den_i),
+//     den_i = K_i eps^2 + sigma_i c dt,
+// and the inflow relations (4.6) give the two boundary nodes.  Substituting in
+// the cell equation (4.5b)/(5.2b) leaves, for every parity pair p, a
+// tridiagonal system in the cell values
+//     T_p E_p - G rho = r_p ,    T_p = Lam + mu_p^2 L + mu_p B ,
+// where Lam = K eps^2 + sigma0 c dt (diagonal), L is a p-independent
+// tridiagonal diffusion operator (face weights h_j Bc_i, h_j = K_j eps^2 c dt/dx,
+// doubled at the two boundary faces), B is diagonal with 2 h/eps in the two
+// boundary cells, and G = sigma0 c dt ac beta/(1 + ac beta) is the material
+// coupling left after U* is eliminated with (4.5c).
+//
+// Prediction (hot loop).  With W = sum_p omega_p (not exactly one in binary64)
+// the angular moment rho = sum_p omega_p E_p satisfies
+//     S rho = s ,  S x = (1 - W) x + sum_p omega_p T_p^{-1} [(Lam - G) x + mu_p^2 L x + mu_p B x],
+// where Lam - G = K eps^2 + sigma0 c dt/(1 + ac beta) is formed directly, so
+// the small isotropic coefficient of optically thick cells carries no
+// cancellation.  It is solved by Richardson iteration preconditioned with
+// the diffusion operator D = (Lam - G) + <mu^2> L + <mu> B (a consistent
+// diffusion-synthetic acceleration):
+//     res = s - S rho^k = sum_p omega_p T_p^{-1}[r_p - (T_p - G) rho^k] - (1 - W) rho^k,
+//     rho^{k+1} = rho^k + res + D^{-1}(G res),
+// and E*_p = rho^k + T_p^{-1}[r_p - (T_p - G) rho^k] from the last sweep.
+// One cooperative kernel runs the whole iteration: one work-group per
+// parity pair solves its tridiagonal system in registers/LDS, a grid barrier
+// separates the angular reduction, and every work-group then performs the
+// (cheap, N-sized) DSA solve redundantly so that all groups hold the same
+// iterate and take the same convergence decision.
+//
+// Correction substep 1: D_j from O* (text after (4.13)), K* = max(U*,0)^{3/4}
+// for sigma/T^3, and the scalar equation (4.13)/(5.5) multiplied by
+// c sigma0 dt^2:  a c sigma0 dt T^4 + Cv (eps^2 K* + c sigma0 dt)(T - T^n)
+//                 - sigma0 dt (rho^n - c dt D) = 0,  Newton from T^n.
+// Correction substep 2 + projection: with E = ac U^{n+1} + eps E_J and
+// O = O_J, (4.11a,b) + (4.12) and the inflow relations are the same operator
+// T_p (with K^{n+1}) without angular coupling, so E^{n+1} solves one
+// tridiagonal system per pair and O^{n+1} follows from the node relation.
+//
+// Tridiagonal systems are solved inside one work-group by a partitioned
+// method: each thread owns M consecutive rows, eliminates its interior rows
+// (Thomas with three right-hand sides), the chunk-boundary rows form a
+// tridiagonal system of size NT solved by parallel cyclic reduction in LDS,
+// and each thread back-substitutes.  All systems are M-matrices (diagonally
+// dominant), so no pivoting is needed.  All reductions have a fixed order:
+// results are bitwise reproducible.
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/grte.h"
+
+namespace cg = cooperative_groups;
+
+namespace {
+
+constexpr int NT = 256;          // threads per work-group for the tridiagonal solvers
+constexpr int MAX_M = 16;        // rows per thread -> N <= NT * MAX_M = 4096
+constexpr int MAX_N = NT * MAX_M;
+constexpr int MAX_P = 64;
+
+// -------------------------------------------------------------------------
+// work-group tridiagonal solver
+// -------------------------------------------------------------------------
+// Thread k owns rows k*M .. k*M+M-1 (coefficients in a,b,c,d); rows beyond the
+// system must be identity rows (a = c = d = 0, b = 1).  Row 0 must have
+// a = 0 and the last real row c = 0.  On return x holds the solution rows.
+// sh: 4*NT doubles of LDS.
+template <int M>
+__device__ __forceinline__ void wg_tridiag(const double (&a)[M], const double (&b)[M],
+                                           const double (&c)[M], const double (&d)[M],
+                                           double (&x)[M], double *sh)
+{
+    static_assert(M >= 2, "at least two rows per thread");
+    const int k = threadIdx.x;
+    // interior rows 0..M-2 of the chunk: Thomas with right-hand sides
+    //   P: d,  Q: -a_0 e_0 (left neighbour value),  R: -c_{M-2} e_{M-2} (own last row)
+    double cp[M - 1], Pv[M - 1], Qv[M - 1], Rv[M - 1];
+    {
+        const double inv = 1.0 / b[0];
+        cp[0] = (M > 2) ? c[0] * inv : 0.0;
+        Pv[0] = d[0] * inv;
+        Qv[0] = -a[0] * inv;
+        Rv[0] = (M == 2) ? -c[0] * inv : 0.0;
+    }
+#pragma unroll
+    for (int r = 1; r < M - 1; ++r) {
+        const double inv = 1.0 / (b[r] - a[r] * cp[r - 1]);
+        cp[r] = (r < M - 2) ? c[r] * inv : 0.0;
+        Pv[r] = (d[r] - a[r] * Pv[r - 1]) * inv;
+        Qv[r] = (-a[r] * Qv[r - 1]) * inv;
+        Rv[r] = ((r == M - 2 ? -c[r] : 0.0) - a[r] * Rv[r - 1]) * inv;
+    }
+#pragma unroll
+    for (int r = M - 3; r >= 0; --r) {
+        Pv[r] -= cp[r] * Pv[r + 1];
+        Qv[r] -= cp[r] * Qv[r + 1];
+        Rv[r] -= cp[r] * Rv[r + 1];
+    }
+    // first interior row of the next chunk (its value depends on my last row)
+    sh[k] = Pv[0];
+    sh[NT + k] = Qv[0];
+    sh[2 * NT + k] = Rv[0];
+    __syncthreads();
+    const double Pn = (k + 1 < NT) ? sh[k + 1] : 0.0;
+    const double Qn = (k + 1 < NT) ? sh[NT + k + 1] : 0.0;
+    const double Rn = (k + 1 < NT) ? sh[2 * NT + k + 1] : 0.0;
+    __syncthreads();
+    // reduced row k couples the last rows z_{k-1}, z_k, z_{k+1} of the chunks
+    const double ae = a[M - 1], be = b[M - 1], ce = c[M - 1], de = d[M - 1];
+    double A = ae * Qv[M - 2];
+    double B = ae * Rv[M - 2] + be + ce * Qn;
+    double C = ce * Rn;
+    double D = de - ae * Pv[M - 2] - ce * Pn;
+    // parallel cyclic reduction on the NT reduced rows
+    double *sA = sh, *sB = sh + NT, *sC = sh + 2 * NT, *sD = sh + 3 * NT;
+#pragma unroll 1
+    for (int s = 1; s < NT; s <<= 1) {
+        sA[k] = A;
+        sB[k] = B;
+        sC[k] = C;
+        sD[k] = D;
+        __syncthreads();
+        double Am = 0.0, Bm = 1.0, Cm = 0.0, Dm = 0.0;
+        double Ap = 0.0, Bp = 1.0, Cp = 0.0, Dp = 0.0;
+        if (k >= s) { Am = sA[k - s]; Bm = sB[k - s]; Cm = sC[k - s]; Dm = sD[k - s]; }
+        if (k + s < NT) { Ap = sA[k + s]; Bp = sB[k + s]; Cp = sC[k + s]; Dp = sD[k + s]; }
+        __syncthreads();
+        const double k1 = A / Bm;
+        const double k2 = C / Bp;
+        A = -Am * k1;
+        C = -Cp * k2;
+        B = B - Cm * k1 - Ap * k2;
+        D = D - Dm * k1 - Dp * k2;
+    }
+    const double z = D / B;
+    sh[k] = z;
+    __syncthreads();
+    const double zl = (k > 0) ? sh[k - 1] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < M - 1; ++r) x[r] = Pv[r] + Qv[r] * zl + Rv[r] * z;
+    x[M - 1] = z;
+}
+
+// block-wide max of a non-negative value (fixed order; result in every thread)
+__device__ __forceinline__ double block_max(double v, double *sh)
+{
+    const int k = threadIdx.x;
+    sh[k] = v;
+    __syncthreads();
+#pragma unroll 1
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (k < s) sh[k] = fmax(sh[k], sh[k + s]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// -------------------------------------------------------------------------
+// coefficients (one thread per cell)
+// -------------------------------------------------------------------------
+struct CoefArgs {
+    int N, P, m, mode;           // mode 0: prediction (K from T^n), 1: correction (K from T^{n+1})
+    double a, c, cv, eps, dt, dx;
+    const double *T;             // temperature defining K (T^n or T^{n+1})
+    const double *Tn;            // T^n (for U^n and beta)
+    const double *sigma0, *mu, *omega, *bL, *bR;
+    const double *E, *O;         // E^n, O^n (cell-major)
+    double mu1, mu2;             // sum omega mu, sum omega mu^2 (DSA)
+    // outputs
+    double *Ll, *Ld, *Lu, *Lam, *LmG, *G, *Bd, *Aw, *Bc, *beta;
+    double *Dl, *Dd, *Du;        // DSA operator (prediction only)
+    double *rho_n;               // sum_p omega_p E^n (prediction only)
+    double *r;                   // right-hand sides, pair-major [p*N + j]
+};
+
+__device__ __forceinline__ double kpow(double T, int m) { return m == 0 ? 1.0 : T * T * T; }
+
+__device__ __forceinline__ void node_coef(const CoefArgs &A, int i, double &aw, double &bc)
+{
+    // interior node i (1..N-1) between cells i-1 and i
+    const double Kl = kpow(A.T[i - 1], A.m), Kr = kpow(A.T[i], A.m);
+    const double Kn = 0.5 * (Kl + Kr);
+    const double sl = A.sigma0[i - 1], sr = A.sigma0[i];
+    const double ss = sl + sr;
+    const double sn = ss > 0.0 ? 2.0 * sl * sr / ss : 0.0;      // harmonic mean
+    const double den = Kn * A.eps * A.eps + sn * A.c * A.dt;
+    if (den > 0.0) {
+        aw = Kn * A.eps * A.eps / den;
+        bc = Kn * A.c * A.dt / (A.dx * den);
+    } else {
+        aw = 0.0;
+        bc = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) coef_kernel(CoefArgs A)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = A.N;
+    if (j > N) return;
+    // node arrays (N+1 entries; boundary nodes carry zeros)
+    if (j <= N) {
+        double aw = 0.0, bc = 0.0;
+        if (j >= 1 && j <= N - 1) node_coef(A, j, aw, bc);
+        A.Aw[j] = aw;
+        A.Bc[j] = bc;
+    }
+    if (j >= N) return;
+    const double eps = A.eps, c = A.c, dt = A.dt;
+    const double Kc = kpow(A.T[j], A.m);
+    const double s0 = A.sigma0[j];
+    const double h = Kc * eps * eps * c * dt / A.dx;
+    double awl = 0.0, bcl = 0.0, awr = 0.0, bcr = 0.0;
+    if (j >= 1) node_coef(A, j, awl, bcl);
+    if (j <= N - 2) node_coef(A, j + 1, awr, bcr);
+    const double fr = (j <= N - 2) ? h * bcr * (j == 0 ? 2.0 : 1.0) : 0.0;
+    const double fl = (j >= 1) ? h * bcl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+    const double awr_f = (j <= N - 2) ? awr * (j == 0 ? 2.0 : 1.0) : 0.0;
+    const double awl_f = (j >= 1) ? awl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+    const double bd = (j == 0 || j == N - 1) ? 2.0 * h / eps : 0.0;
+    const double lam = Kc * eps * eps + s0 * c * dt;
+    A.Ll[j] = -fl;
+    A.Lu[j] = -fr;
+    A.Ld[j] = fl + fr;
+    A.Bd[j] = bd;
+    A.Lam[j] = lam;
+    const double ac = A.a * c;
+    const double Tn = A.Tn[j];
+    const double Un = Tn * Tn * Tn * Tn;
+    double src;   // sigma0 c dt ac U / (...) part of the right-hand side
+    if (A.mode == 0) {
+        // (4.5c): beta = 4 sigma0 dt (T^n)^(3-m) / (eps^2 Cv)
+        const double t3m = (A.m == 0) ? Tn * Tn * Tn : 1.0;
+        const double beta = 4.0 * s0 * dt * t3m / (eps * eps * A.cv);
+        const double opb = 1.0 + ac * beta;
+        const double lmg = Kc * eps * eps + s0 * c * dt / opb;
+        const double g = s0 * c * dt * (ac * beta) / opb;
+        A.beta[j] = beta;
+        A.LmG[j] = lmg;
+        A.G[j] = g;
+        A.Dl[j] = A.mu2 * (-fl);
+        A.Du[j] = A.mu2 * (-fr);
+        A.Dd[j] = lmg + A.mu2 * (fl + fr) + A.mu1 * bd;
+        src = s0 * c * dt * ac * Un / opb;
+        double rho = 0.0;
+        for (int p = 0; p < A.P; ++p) rho += A.omega[p] * A.E[(size_t)j * A.P + p];
+        A.rho_n[j] = rho;
+    } else {
+        const double T1 = A.T[j];
+        src = s0 * c * dt * ac * (T1 * T1 * T1 * T1);
+    }
+    const double keps = Kc * eps * eps;
+    for (int p = 0; p < A.P; ++p) {
+        const double mu = A.mu[p];
+        const double On_r = (j <= N - 2) ? A.O[(size_t)(j + 1) * A.P + p] : 0.0;
+        const double On_l = (j >= 1) ? A.O[(size_t)j * A.P + p] : 0.0;
+        double rv = keps * A.E[(size_t)j * A.P + p] + src - h * mu * (awr_f * On_r - awl_f * On_l);
+        if (j == 0) rv += 2.0 * h * mu * A.bL[p] / eps;
+        if (j == N - 1) rv += 2.0 * h * mu * A.bR[p] / eps;
+        A.r[(size_t)p * N + j] = rv;
+    }
+}
+
+// -------------------------------------------------------------------------
+// prediction: cooperative Richardson iteration with diffusion acceleration
+// -------------------------------------------------------------------------
+struct PredArgs {
+    int N, P, maxit;
+    double tol, one_minus_W;
+    const double *Ll, *Ld, *Lu, *Lam, *LmG, *G, *Bd, *Dl, *Dd, *Du;
+    const double *r, *mu, *omega, *rho0;
+    double *v, *res, *estar, *rho_out;
+    int *stat;   // [0] iterations, [1] converged
+};
+
+template <int M>
+__global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
+{
+    cg::grid_group grid = cg::this_grid();
+    extern __shared__ double smem[];
+    double *rho = smem;                    // current iterate   (NT*M)
+    double *sh = smem + NT * M;            // 4*NT scratch
+    double rho_prev[M];                    // my rows of the iterate used by the last sweep
+    const int k = threadIdx.x;
+    const int N = A.N;
+    const int j0 = k * M;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int j = j0 + r;
+        rho[j] = (j < N) ? A.rho0[j] : 0.0;
+    }
+    __syncthreads();
+    int it = 0;
+    int converged = 0;
+    double a[M], b[M], c[M], d[M], x[M];
+    while (true) {
+        // ---- transport sweep: v_p = T_p^{-1} [r_p - (T_p - G) rho] for my pairs
+        for (int p = blockIdx.x; p < A.P; p += gridDim.x) {
+            const double mu = A.mu[p], mu2 = mu * mu;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const int j = j0 + r;
+                if (j < N) {
+                    const double ll = A.Ll[j], ld = A.Ld[j], lu = A.Lu[j], bd = A.Bd[j];
+                    a[r] = mu2 * ll;
+                    c[r] = mu2 * lu;
+                    b[r] = A.Lam[j] + mu2 * ld + mu * bd;
+                    const double rj = rho[j];
+                    double Lr = ld * rj;
+                    if (j > 0) Lr += ll * rho[j - 1];
+                    if (j < N - 1) Lr += lu * rho[j + 1];
+                    d[r] = A.r[(size_t)p * N + j] - A.LmG[j] * rj - mu2 * Lr - mu * bd * rj;
+                } else {
+                    a[r] = 0.0; b[r] = 1.0; c[r] = 0.0; d[r] = 0.0;
+                }
+            }
+            wg_tridiag<M>(a, b, c, d, x, sh);
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const int j = j0 + r;
+                if (j < N) A.v[(size_t)p * N + j] = x[r];
+            }
+        }
+        grid.sync();
+        // ---- angular reduction, cells spread over the grid
+        for (int j = blockIdx.x * NT + k; j < N; j += gridDim.x * NT) {
+            double s = 0.0;
+            for (int p = 0; p < A.P; ++p) s += A.omega[p] * A.v[(size_t)p * N + j];
+            A.res[j] = s - A.one_minus_W * rho[j];
+        }
+        grid.sync();
+        // ---- diffusion acceleration (every group, identical result)
+        double rl[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int j = j0 + r;
+            if (j < N) {
+                rl[r] = A.res[j];
+                a[r] = A.Dl[j];
+                b[r] = A.Dd[j];
+                c[r] = A.Du[j];
+                d[r] = A.G[j] * rl[r];
+            } else {
+                rl[r] = 0.0;
+                a[r] = 0.0; b[r] = 1.0; c[r] = 0.0; d[r] = 0.0;
+            }
+        }
+        wg_tridiag<M>(a, b, c, d, x, sh);
+        double md = 0.0, mr = 0.0;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int j = j0 + r;
+            if (j < N) {
+                const double delta = rl[r] + x[r];
+                const double old = rho[j];
+                rho_prev[r] = old;
+                const double nw = old + delta;
+                rho[j] = nw;
+                md = fmax(md, fabs(delta));
+                mr = fmax(mr, fabs(nw));
+            }
+        }
+        md = block_max(md, sh);
+        mr = block_max(mr, sh);   // also orders the rho updates before the next sweep
+        ++it;
+        converged = (md <= A.tol * mr) ? 1 : 0;
+        if (converged || it >= A.maxit) break;
+    }
+    // E*_p = rho (used by the last sweep) + v_p
+    for (int p = blockIdx.x; p < A.P; p += gridDim.x) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int j = j0 + r;
+            if (j < N) A.estar[(size_t)p * N + j] = rho_prev[r] + A.v[(size_t)p * N + j];
+        }
+    }
+    if (blockIdx.x == 0) {
+        for (int j = k; j < N; j += NT) A.rho_out[j] = rho[j];
+        if (k == 0) {
+            A.stat[0] = it;
+            A.stat[1] = converged;
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
+// correction substep 1: moments, D, K*, scalar Newton (one thread per cell)
+// -------------------------------------------------------------------------
+struct NewtonArgs {
+    int N, P, m, maxit, keep;
+    double a, c, cv, eps, dt, dx;
+    const double *estar, *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
+    double *Tnew, *ustar, *Dv, *ostar;
+    int *stat;   // [2] max its, [3] failed, [4] K* clamped, [5] negative root
+};
+
+__device__ __forceinline__ double ostar_node(const NewtonArgs &A, int i, int p)
+{
+    // interior node i (1..N-1)
+    const int N = A.N;
+    const double mu = A.mu[p];
+    return A.Aw[i] * A.O[(size_t)i * A.P + p]
+         - A.Bc[i] * mu * (A.estar[(size_t)p * N + i] - A.estar[(size_t)p * N + i - 1]);
+}
+
+__device__ __forceinline__ double ostar_any(const NewtonArgs &A, int i, int p)
+{
+    const int N = A.N;
+    if (i >= 1 && i <= N - 1) return ostar_node(A, i, p);
+    if (i == 0)      // (4.7) at x = 0
+        return 2.0 / A.eps * (A.bL[p] - A.estar[(size_t)p * N]) - ostar_node(A, 1, p);
+    // i == N, (4.7) at x = L
+    return 2.0 / A.eps * (A.estar[(size_t)p * N + N - 1] - A.bR[p]) - ostar_node(A, N - 1, p);
+}
+
+__global__ void __launch_bounds__(256) newton_kernel(NewtonArgs A)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= A.N) return;
+    const int N = A.N;
+    double rho = 0.0, D = 0.0;
+    for (int p = 0; p < A.P; ++p) {
+        const double w = A.omega[p];
+        rho += w * A.estar[(size_t)p * N + j];
+        const double ol = ostar_any(A, j, p);
+        const double orr = ostar_any(A, j + 1, p);
+        D += w * A.mu[p] * (orr - ol);
+        if (A.keep) {
+            A.ostar[(size_t)j * A.P + p] = ol;
+            if (j == N - 1) A.ostar[(size_t)N * A.P + p] = orr;
+        }
+    }
+    D /= A.dx;
+    const double ac = A.a * A.c;
+    const double Tn = A.Tn[j];
+    const double Un = Tn * Tn * Tn * Tn;
+    const double beta = A.beta[j];
+    const double us = (Un + beta * rho) / (1.0 + ac * beta);
+    A.ustar[j] = us;
+    A.Dv[j] = D;
+    double Ks = 1.0;
+    if (A.m == 3) {
+        if (us < 0.0) {
+            Ks = 0.0;
+            atomicAdd(&A.stat[4], 1);
+        } else {
+            Ks = pow(us, 0.75);
+        }
+    }
+    const double s0 = A.sigma0[j];
+    const double eps2 = A.eps * A.eps;
+    const double lin = A.cv * (eps2 * Ks + A.c * s0 * A.dt);
+    const double q4 = ac * s0 * A.dt;
+    const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
+    double T = Tn;
+    int its = 0;
+    if (!(s0 == 0.0 && Ks == 0.0)) {
+        // root of the linear part alone; a negative value means no root >= 0
+        if (Tn + rhs / lin < 0.0) atomicAdd(&A.stat[5], 1);
+        bool ok = false;
+        for (its = 0; its < A.maxit;) {
+            const double T2 = T * T;
+            const double g = q4 * T2 * T2 + lin * (T - Tn) - rhs;
+            const double dg = 4.0 * q4 * T2 * T + lin;
+            const double step = g / dg;
+            T -= step;
+            ++its;
+            if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(Tn))) { ok = true; break; }
+        }
+        if (!ok) atomicAdd(&A.stat[3], 1);
+    }
+    A.Tnew[j] = T;
+    atomicMax(&A.stat[2], its);
+}
+
+// -------------------------------------------------------------------------
+// correction substep 2: E^{n+1} per pair (one work-group per pair)
+// -------------------------------------------------------------------------
+struct CorrArgs {
+    int N, P;
+    const double *Ll, *Ld, *Lu, *Lam, *Bd, *r, *mu;
+    double *enew;   // pair-major
+};
+
+template <int M>
+__global__ void __launch_bounds__(NT) corr_kernel(CorrArgs A)
+{
+    __shared__ double sh[4 * NT];
+    const int p = blockIdx.x;
+    const int N = A.N;
+    const int j0 = threadIdx.x * M;
+    const double mu = A.mu[p], mu2 = mu * mu;
+    double a[M], b[M], c[M], d[M], x[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int j = j0 + r;
+        if (j < N) {
+            a[r] = mu2 * A.Ll[j];
+            c[r] = mu2 * A.Lu[j];
+            b[r] = A.Lam[j] + mu2 * A.Ld[j] + mu * A.Bd[j];
+            d[r] = A.r[(size_t)p * N + j];
+        } else {
+            a[r] = 0.0; b[r] = 1.0; c[r] = 0.0; d[r] = 0.0;
+        }
+    }
+    wg_tridiag<M>(a, b, c, d, x, sh);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int j = j0 + r;
+        if (j < N) A.enew[(size_t)p * N + j] = x[r];
+    }
+}
+
+// -------------------------------------------------------------------------
+// projection (4.14): E^{n+1}, O^{n+1} in the cell-major state layout
+// -------------------------------------------------------------------------
+struct ProjArgs {
+    int N, P;
+    double eps;
+    const double *enew, *O, *Aw, *Bc, *mu, *omega, *bL, *bR, *estar;
+    double *Eout, *Oout, *rho_out, *estar_cm;
+    int keep;
+};
+
+__device__ __forceinline__ double onew_node(const ProjArgs &A, int i, int p)
+{
+    const int N = A.N;
+    return A.Aw[i] * A.O[(size_t)i * A.P + p]
+         - A.Bc[i] * A.mu[p] * (A.enew[(size_t)p * N + i] - A.enew[(size_t)p * N + i - 1]);
+}
+
+__global__ void __launch_bounds__(256) project_kernel(ProjArgs A)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = A.N, P = A.P;
+    if (t >= (N + 1) * P) return;
+    const int i = t / P, p = t % P;
+    double o;
+    if (i >= 1 && i <= N - 1) o = onew_node(A, i, p);
+    else if (i == 0) o = 2.0 / A.eps * (A.bL[p] - A.enew[(size_t)p * N]) - onew_node(A, 1, p);
+    else o = 2.0 / A.eps * (A.enew[(size_t)p * N + N - 1] - A.bR[p]) - onew_node(A, N - 1, p);
+    A.Oout[(size_t)i * P + p] = o;
+    if (i < N) {
+        A.Eout[(size_t)i * P + p] = A.enew[(size_t)p * N + i];
+        if (A.keep) A.estar_cm[(size_t)i * P + p] = A.estar[(size_t)p * N + i];
+    }
+}
+
+__global__ void __launch_bounds__(256) rho_kernel(int N, int P, const double *E, const double *omega,
+                                                  double *rho)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += omega[p] * E[(size_t)j * P + p];
+    rho[j] = s;
+}
+
+__global__ void clear_ints(int *x, int n)
+{
+    const int t = threadIdx.x;
+    if (t < n) x[t] = 0;
+}
+
+__global__ void fill_kernel(double *x, size_t n, double v)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = v;
+}
+
+}  // namespace
+
+// ===========================================================================
+// host side
+// ===========================================================================
+struct grte_ctx {
+    int N = 0, P = 0, m = 0, M = 2, dev = 0;
+    double L = 1, a = 1, c = 1, cv = 1;
+    double one_minus_W = 0, mu1 = 0, mu2 = 0;
+    double pred_tol = 1e-15;
+    int pred_maxit = 200, newton_maxit = 100;
+    int pred_grid = 1;
+    int keep = 1;
+    hipStream_t stream = nullptr;
+    std::vector<double *> allocs;
+    double *E = nullptr, *O = nullptr, *T = nullptr;       // current state
+    double *E2 = nullptr, *O2 = nullptr, *T2 = nullptr;    // next state
+    double *sigma0, *mu, *omega, *bL, *bR;
+    double *Ll, *Ld, *Lu, *Lam, *LmG, *G, *Bd, *Aw, *Bc, *beta, *Dl, *Dd, *Du, *rho_n;
+    double *r, *v, *res, *estar, *rho, *enew;
+    double *ustar, *Dv, *ostar, *estar_cm, *rho1;
+    int *stat = nullptr;
+    // optional stage timing: event pairs recorded on the context stream
+    int profiling = 0;
+    std::vector<hipEvent_t> ev_pool;      // created on demand, reused
+    std::vector<int> ev_stage;            // stage index of each recorded pair
+    size_t ev_used = 0;                   // pairs recorded since the last read
+};
+
+namespace {
+
+grte_status hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return GRTE_OK;
+    fprintf(stderr, "grte: %s failed: %s\n", what, hipGetErrorString(e));
+    return GRTE_E_HIP;
+}
+
+#define HIPCHK(x)                                               \
+    do {                                                        \
+        grte_status _s = hip_fail((x), #x);                     \
+        if (_s != GRTE_OK) return _s;                           \
+    } while (0)
+
+grte_status alloc(grte_ctx *ctx, double **p, size_t n)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(double)) != hipSuccess) return GRTE_E_NOMEM;
+    ctx->allocs.push_back((double *)q);
+    *p = (double *)q;
+    return GRTE_OK;
+}
+
+grte_status copy_in(grte_ctx *ctx, double *dst, const double *src, size_t n, int on_device)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ctx->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(ctx->stream));
+    return GRTE_OK;
+}
+
+grte_status copy_out(grte_ctx *ctx, double *dst, const double *src, size_t n, int on_device)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(ctx->stream));
+    return GRTE_OK;
+}
+
+// stage timing (profiling only): each pair gets its own index at begin, so
+// pairs may nest (the whole step encloses its stages)
+grte_status prof_begin(grte_ctx *ctx, int stage, int *idx)
+{
+    *idx = -1;
+    if (!ctx->profiling) return GRTE_OK;
+    if (ctx->ev_used * 2 + 2 > ctx->ev_pool.size()) {
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ctx->ev_pool.push_back(e);
+        }
+        ctx->ev_stage.push_back(0);
+    }
+    const int k = (int)ctx->ev_used++;
+    ctx->ev_stage[k] = stage;
+    HIPCHK(hipEventRecord(ctx->ev_pool[2 * k], ctx->stream));
+    *idx = k;
+    return GRTE_OK;
+}
+
+grte_status prof_end(grte_ctx *ctx, int idx)
+{
+    if (idx < 0) return GRTE_OK;
+    HIPCHK(hipEventRecord(ctx->ev_pool[2 * idx + 1], ctx->stream));
+    return GRTE_OK;
+}
+
+template <int M>
+grte_status launch_pred(grte_ctx *ctx, PredArgs &pa)
+{
+    const size_t lds = (size_t)(NT * M + 4 * NT) * sizeof(double);
+    void *args[] = {&pa};
+    HIPCHK(hipLaunchCooperativeKernel((const void *)pred_kernel<M>, dim3(ctx->pred_grid), dim3(NT),
+                                      args, (unsigned)lds, ctx->stream));
+    return GRTE_OK;
+}
+
+template <int M>
+grte_status launch_corr(grte_ctx *ctx, CorrArgs &ca)
+{
+    hipLaunchKernelGGL(corr_kernel<M>, dim3(ctx->P), dim3(NT), 0, ctx->stream, ca);
+    HIPCHK(hipGetLastError());
+    return GRTE_OK;
+}
+
+int rows_per_thread(int N)
+{
+    int M = 2;
+    while (NT * M < N) M *= 2;
+    return M;
+}
+
+template <int M>
+int coop_blocks_per_cu()
+{
+    int nb = 0;
+    const size_t lds = (size_t)(NT * M + 4 * NT) * sizeof(double);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)pred_kernel<M>, NT, lds) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *grte_status_string(grte_status s)
+{
+    switch (s) {
+    case GRTE_OK: return "ok";
+    case GRTE_E_INVAL: return "invalid argument";
+    case GRTE_E_NOMEM: return "device allocation failed";
+    case GRTE_E_HIP: return "HIP runtime error";
+    case GRTE_E_NOCONV: return "a solve stopped at its iteration cap";
+    case GRTE_E_UNSUPPORTED: return "size beyond the limits of this build";
+    }
+    return "unknown status";
+}
+
+grte_status grte_gauss_legendre(int nv, double *mu, double *omega)
+{
+    if (nv < 2 || nv > 128 || (nv & 1) || !mu || !omega) return GRTE_E_INVAL;
+    const int P = nv / 2;
+    // Newton on the Legendre polynomial P_nv (three-term recurrence) in
+    // extended precision; weights 2 / ((1 - x^2) P'_nv(x)^2) on [-1, 1].
+    for (int q = 0; q < P; ++q) {
+        const int k = q + 1;   // k-th largest root
+        long double x = cosl(3.14159265358979323846264338327950288L * (k - 0.25L) / (nv + 0.5L));
+        long double dp = 1.0L;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1.0L, p1 = x;
+            for (int n = 2; n <= nv; ++n) {
+                const long double p2 = ((2 * n - 1) * x * p1 - (n - 1) * p0) / n;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = nv * (x * p1 - p0) / (x * x - 1.0L);
+            const long double dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) <= 1e-19L * fabsl(x)) break;
+        }
+        {
+            long double p0 = 1.0L, p1 = x;
+            for (int n = 2; n <= nv; ++n) {
+                const long double p2 = ((2 * n - 1) * x * p1 - (n - 1) * p0) / n;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = nv * (x * p1 - p0) / (x * x - 1.0L);
+        }
+        const long double w = 2.0L / ((1.0L - x * x) * dp * dp);
+        // increasing mu: the k-th largest root goes to slot P - k
+        mu[P - k] = (double)x;
+        omega[P - k] = (double)w;
+    }
+    return GRTE_OK;
+}
+
+grte_status grte_destroy(grte_ctx *ctx)
+{
+    if (!ctx) return GRTE_OK;
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (double *p : ctx->allocs) (void)hipFree(p);
+    if (ctx->stat) (void)hipFree(ctx->stat);
+    delete ctx;
+    return GRTE_OK;
+}
+
+grte_status grte_create(const grte_problem *pb, const double *mu, const double *omega, grte_ctx **out)
+{
+    if (!pb || !mu || !omega || !out) return GRTE_E_INVAL;
+    *out = nullptr;
+    if (pb->nx < 2 || pb->npairs < 1 || !(pb->length > 0) || !(pb->a > 0) || !(pb->c > 0) ||
+        !(pb->cv > 0) || (pb->opacity_law != 0 && pb->opacity_law != 3))
+        return GRTE_E_INVAL;
+    if (pb->nx > MAX_N || pb->npairs > MAX_P) return GRTE_E_UNSUPPORTED;
+    for (int p = 0; p < pb->npairs; ++p)
+        if (!(mu[p] > 0) || !(omega[p] > 0) || !std::isfinite(mu[p]) || !std::isfinite(omega[p]))
+            return GRTE_E_INVAL;
+    grte_ctx *ctx = new (std::nothrow) grte_ctx();
+    if (!ctx) return GRTE_E_NOMEM;
+    ctx->N = pb->nx;
+    ctx->P = pb->npairs;
+    ctx->m = pb->opacity_law;
+    ctx->L = pb->length;
+    ctx->a = pb->a;
+    ctx->c = pb->c;
+    ctx->cv = pb->cv;
+    ctx->M = rows_per_thread(ctx->N);
+    if (hipGetDevice(&ctx->dev) != hipSuccess) { delete ctx; return GRTE_E_HIP; }
+    // 1 - sum(omega), exactly rounded: two-sum accumulation, then 1 - hi is exact
+    double s = 0.0, e = 0.0;
+    ctx->mu1 = 0.0;
+    ctx->mu2 = 0.0;
+    for (int p = 0; p < ctx->P; ++p) {
+        const double x = omega[p];
+        const double t = s + x;
+        const double bp = t - s;
+        e += (s - (t - bp)) + (x - bp);
+        s = t;
+        ctx->mu1 += omega[p] * mu[p];
+        ctx->mu2 += omega[p] * mu[p] * mu[p];
+    }
+    ctx->one_minus_W = (1.0 - s) - e;
+
+    const size_t N = ctx->N, P = ctx->P;
+    grte_status st = GRTE_OK;
+    double **cells[] = {&ctx->T, &ctx->T2, &ctx->sigma0, &ctx->Ll, &ctx->Ld, &ctx->Lu, &ctx->Lam,
+                        &ctx->LmG, &ctx->G, &ctx->Bd, &ctx->beta, &ctx->Dl, &ctx->Dd, &ctx->Du,
+                        &ctx->rho_n, &ctx->res, &ctx->rho, &ctx->ustar, &ctx->Dv, &ctx->rho1};
+    for (double **q : cells)
+        if (st == GRTE_OK) st = alloc(ctx, q, N);
+    double **nodes[] = {&ctx->Aw, &ctx->Bc};
+    for (double **q : nodes)
+        if (st == GRTE_OK) st = alloc(ctx, q, N + 1);
+    double **pairs[] = {&ctx->mu, &ctx->omega, &ctx->bL, &ctx->bR};
+    for (double **q : pairs)
+        if (st == GRTE_OK) st = alloc(ctx, q, P);
+    double **cp[] = {&ctx->E, &ctx->E2, &ctx->r, &ctx->v, &ctx->estar, &ctx->enew, &ctx->estar_cm};
+    for (double **q : cp)
+        if (st == GRTE_OK) st = alloc(ctx, q, N * P);
+    double **np[] = {&ctx->O, &ctx->O2, &ctx->ostar};
+    for (double **q : np)
+        if (st == GRTE_OK) st = alloc(ctx, q, (N + 1) * P);
+    if (st == GRTE_OK && hipMalloc((void **)&ctx->stat, 8 * sizeof(int)) != hipSuccess) st = GRTE_E_NOMEM;
+    if (st != GRTE_OK) { grte_destroy(ctx); return st; }
+
+    // co-resident blocks for the cooperative prediction kernel
+    int nb = 0;
+    switch (ctx->M) {
+    case 2: nb = coop_blocks_per_cu<2>(); break;
+    case 4: nb = coop_blocks_per_cu<4>(); break;
+    case 8: nb = coop_blocks_per_cu<8>(); break;
+    default: nb = coop_blocks_per_cu<16>(); break;
+    }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->dev) != hipSuccess || nb < 1) {
+        grte_destroy(ctx);
+        return GRTE_E_HIP;
+    }
+    ctx->pred_grid = std::min(ctx->P, nb * ncu);
+
+    if (hipMemcpy(ctx->mu, mu, P * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->omega, omega, P * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        grte_destroy(ctx);
+        return GRTE_E_HIP;
+    }
+    // defaults: zero state and inflow, unit opacity
+    const unsigned b = 256;
+    hipLaunchKernelGGL(fill_kernel, dim3((N * P + b - 1) / b), dim3(b), 0, nullptr, ctx->E, N * P, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(((N + 1) * P + b - 1) / b), dim3(b), 0, nullptr, ctx->O, (N + 1) * P, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3((N + b - 1) / b), dim3(b), 0, nullptr, ctx->T, N, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3((N + b - 1) / b), dim3(b), 0, nullptr, ctx->sigma0, N, 1.0);
+    hipLaunchKernelGGL(fill_kernel, dim3((P + b - 1) / b), dim3(b), 0, nullptr, ctx->bL, P, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3((P + b - 1) / b), dim3(b), 0, nullptr, ctx->bR, P, 0.0);
+    if (hipDeviceSynchronize() != hipSuccess) { grte_destroy(ctx); return GRTE_E_HIP; }
+    *out = ctx;
+    return GRTE_OK;
+}
+
+grte_status grte_set_stream(grte_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return GRTE_E_INVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return GRTE_OK;
+}
+
+grte_status grte_set_solver(grte_ctx *ctx, double pred_tol, int pred_maxit, int newton_maxit)
+{
+    if (!ctx || !(pred_tol > 0) || pred_maxit < 1 || newton_maxit < 1) return GRTE_E_INVAL;
+    ctx->pred_tol = pred_tol;
+    ctx->pred_maxit = pred_maxit;
+    ctx->newton_maxit = newton_maxit;
+    return GRTE_OK;
+}
+
+grte_status grte_set_opacity(grte_ctx *ctx, const double *sigma0, int on_device)
+{
+    if (!ctx || !sigma0) return GRTE_E_INVAL;
+    if (!on_device)
+        for (int j = 0; j < ctx->N; ++j)
+            if (!(sigma0[j] >= 0) || !std::isfinite(sigma0[j])) return GRTE_E_INVAL;
+    return copy_in(ctx, ctx->sigma0, sigma0, ctx->N, on_device);
+}
+
+grte_status grte_set_inflow(grte_ctx *ctx, const double *b_left, const double *b_right)
+{
+    if (!ctx || !b_left || !b_right) return GRTE_E_INVAL;
+    grte_status s = copy_in(ctx, ctx->bL, b_left, ctx->P, 0);
+    if (s != GRTE_OK) return s;
+    return copy_in(ctx, ctx->bR, b_right, ctx->P, 0);
+}
+
+grte_status grte_set_state(grte_ctx *ctx, const double *E, const double *O, const double *T, int on_device)
+{
+    if (!ctx || !E || !O || !T) return GRTE_E_INVAL;
+    if (!on_device)
+        for (int j = 0; j < ctx->N; ++j)
+            if (!(T[j] >= 0) || !std::isfinite(T[j])) return GRTE_E_INVAL;
+    const size_t N = ctx->N, P = ctx->P;
+    grte_status s = copy_in(ctx, ctx->E, E, N * P, on_device);
+    if (s == GRTE_OK) s = copy_in(ctx, ctx->O, O, (N + 1) * P, on_device);
+    if (s == GRTE_OK) s = copy_in(ctx, ctx->T, T, N, on_device);
+    return s;
+}
+
+grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int on_device)
+{
+    if (!ctx) return GRTE_E_INVAL;
+    const size_t N = ctx->N, P = ctx->P;
+    grte_status s = GRTE_OK;
+    if (E) s = copy_out(ctx, E, ctx->E, N * P, on_device);
+    if (s == GRTE_OK && O) s = copy_out(ctx, O, ctx->O, (N + 1) * P, on_device);
+    if (s == GRTE_OK && T) s = copy_out(ctx, T, ctx->T, N, on_device);
+    return s;
+}
+
+grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device)
+{
+    if (!ctx || !out) return GRTE_E_INVAL;
+    const size_t N = ctx->N, P = ctx->P;
+    switch (stage) {
+    case GRTE_STAGE_ESTAR: return copy_out(ctx, out, ctx->estar_cm, N * P, on_device);
+    case GRTE_STAGE_OSTAR: return copy_out(ctx, out, ctx->ostar, (N + 1) * P, on_device);
+    case GRTE_STAGE_USTAR: return copy_out(ctx, out, ctx->ustar, N, on_device);
+    case GRTE_STAGE_D: return copy_out(ctx, out, ctx->Dv, N, on_device);
+    case GRTE_STAGE_RHO: return copy_out(ctx, out, ctx->rho1, N, on_device);
+    }
+    return GRTE_E_INVAL;
+}
+
+grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info)
+{
+    if (!ctx || !(dt > 0) || !(eps > 0) || !std::isfinite(dt) || !std::isfinite(eps)) return GRTE_E_INVAL;
+    const int N = ctx->N, P = ctx->P;
+    const unsigned b = 256;
+    const double dx = ctx->L / N;
+    int ev_step = -1, ev_pred = -1;
+    grte_status st = prof_begin(ctx, GRTE_TIMING_STEP, &ev_step);
+    if (st != GRTE_OK) return st;
+    hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, ctx->stream, ctx->stat, 8);
+
+    // ---- coefficients of the prediction (K from T^n)
+    CoefArgs ca{};
+    ca.N = N; ca.P = P; ca.m = ctx->m; ca.mode = 0;
+    ca.a = ctx->a; ca.c = ctx->c; ca.cv = ctx->cv; ca.eps = eps; ca.dt = dt; ca.dx = dx;
+    ca.T = ctx->T; ca.Tn = ctx->T; ca.sigma0 = ctx->sigma0; ca.mu = ctx->mu; ca.omega = ctx->omega;
+    ca.bL = ctx->bL; ca.bR = ctx->bR; ca.E = ctx->E; ca.O = ctx->O;
+    ca.mu1 = ctx->mu1; ca.mu2 = ctx->mu2;
+    ca.Ll = ctx->Ll; ca.Ld = ctx->Ld; ca.Lu = ctx->Lu; ca.Lam = ctx->Lam; ca.LmG = ctx->LmG; ca.G = ctx->G;
+    ca.Bd = ctx->Bd; ca.Aw = ctx->Aw; ca.Bc = ctx->Bc; ca.beta = ctx->beta;
+    ca.Dl = ctx->Dl; ca.Dd = ctx->Dd; ca.Du = ctx->Du; ca.rho_n = ctx->rho_n; ca.r = ctx->r;
+    hipLaunchKernelGGL(coef_kernel, dim3((N + 1 + b - 1) / b), dim3(b), 0, ctx->stream, ca);
+    HIPCHK(hipGetLastError());
+
+    // ---- prediction
+    PredArgs pa{};
+    pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
+    pa.Ll = ctx->Ll; pa.Ld = ctx->Ld; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.G = ctx->G;
+    pa.Bd = ctx->Bd; pa.Dl = ctx->Dl; pa.Dd = ctx->Dd; pa.Du = ctx->Du;
+    pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
+    pa.v = ctx->v; pa.res = ctx->res; pa.estar = ctx->estar; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
+    if ((st = prof_begin(ctx, GRTE_TIMING_PREDICT, &ev_pred)) != GRTE_OK) return st;
+    switch (ctx->M) {
+    case 2: st = launch_pred<2>(ctx, pa); break;
+    case 4: st = launch_pred<4>(ctx, pa); break;
+    case 8: st = launch_pred<8>(ctx, pa); break;
+    default: st = launch_pred<16>(ctx, pa); break;
+    }
+    if (st != GRTE_OK) return st;
+    if ((st = prof_end(ctx, ev_pred)) != GRTE_OK) return st;
+
+    // ---- correction substep 1
+    NewtonArgs na{};
+    na.N = N; na.P = P; na.m = ctx->m; na.maxit = ctx->newton_maxit; na.keep = ctx->keep;
+    na.a = ctx->a; na.c = ctx->c; na.cv = ctx->cv; na.eps = eps; na.dt = dt; na.dx = dx;
+    na.estar = ctx->estar; na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
+    na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;
+    na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
+    na.ostar = ctx->ostar; na.stat = ctx->stat;
+    hipLaunchKernelGGL(newton_kernel, dim3((N + b - 1) / b), dim3(b), 0, ctx->stream, na);
+    HIPCHK(hipGetLastError());
+
+    // ---- correction substep 2 (K from T^{n+1})
+    ca.mode = 1;
+    ca.T = ctx->T2;
+    hipLaunchKernelGGL(coef_kernel, dim3((N + 1 + b - 1) / b), dim3(b), 0, ctx->stream, ca);
+    HIPCHK(hipGetLastError());
+    CorrArgs cc{};
+    cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Ld = ctx->Ld; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
+    cc.r = ctx->r; cc.mu = ctx->mu; cc.enew = ctx->enew;
+    switch (ctx->M) {
+    case 2: st = launch_corr<2>(ctx, cc); break;
+    case 4: st = launch_corr<4>(ctx, cc); break;
+    case 8: st = launch_corr<8>(ctx, cc); break;
+    default: st = launch_corr<16>(ctx, cc); break;
+    }
+    if (st != GRTE_OK) return st;
+
+    // ---- projection
+    ProjArgs pj{};
+    pj.N = N; pj.P = P; pj.eps = eps; pj.enew = ctx->enew; pj.O = ctx->O; pj.Aw = ctx->Aw; pj.Bc = ctx->Bc;
+    pj.mu = ctx->mu; pj.omega = ctx->omega; pj.bL = ctx->bL; pj.bR = ctx->bR; pj.estar = ctx->estar;
+    pj.Eout = ctx->E2; pj.Oout = ctx->O2; pj.rho_out = ctx->rho1; pj.estar_cm = ctx->estar_cm; pj.keep = ctx->keep;
+    const size_t nt = (size_t)(N + 1) * P;
+    hipLaunchKernelGGL(project_kernel, dim3((unsigned)((nt + b - 1) / b)), dim3(b), 0, ctx->stream, pj);
+    HIPCHK(hipGetLastError());
+    if (ctx->keep) {
+        hipLaunchKernelGGL(rho_kernel, dim3((N + b - 1) / b), dim3(b), 0, ctx->stream, N, P, ctx->E2,
+                           ctx->omega, ctx->rho1);
+        HIPCHK(hipGetLastError());
+    }
+    if ((st = prof_end(ctx, ev_step)) != GRTE_OK) return st;   // whole step
+    std::swap(ctx->E, ctx->E2);
+    std::swap(ctx->O, ctx->O2);
+    std::swap(ctx->T, ctx->T2);
+
+    if (info) {
+        int h[8];
+        HIPCHK(hipMemcpyAsync(h, ctx->stat, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        info->pred_iters = h[0];
+        info->pred_converged = h[1];
+        info->newton_max_iters = h[2];
+        info->newton_failed = h[3];
+        info->kstar_clamped = h[4];
+        info->negative_root = h[5];
+        if (!h[1] || h[3]) return GRTE_E_NOCONV;
+    }
+    return GRTE_OK;
+}
+
+grte_status grte_set_profiling(grte_ctx *ctx, int on)
+{
+    if (!ctx) return GRTE_E_INVAL;
+    ctx->profiling = on ? 1 : 0;
+    ctx->ev_used = 0;
+    return GRTE_OK;
+}
+
+grte_status grte_read_timing(grte_ctx *ctx, double *total_ms, int *count)
+{
+    if (!ctx || !total_ms || !count) return GRTE_E_INVAL;
+    for (int q = 0; q < GRTE_TIMING_NSTAGES; ++q) {
+        total_ms[q] = 0.0;
+        count[q] = 0;
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (size_t k = 0; k < ctx->ev_used; ++k) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[2 * k], ctx->ev_pool[2 * k + 1]));
+        const int q = ctx->ev_stage[k];
+        total_ms[q] += ms;
+        count[q] += 1;
+    }
+    ctx->ev_used = 0;
+    return GRTE_OK;
+}
+
+}  // extern "C"

@@ -96,14 +96,20 @@ def config2(eps=1e-2, N=4096, nv=64, steps=2000):
     return _slab(f"config2(eps={eps:g})", N, nv, 3, eps, steps, sigma0)
 
 
-def random_state(N, nv, seed, m=3, eps=1e-2, T_lo=0.05, T_hi=1.0, anisotropy=0.2):
-    """A generic near-equilibrium state with seeded opacity and inflow,
-    used to exercise every code path (not one of the named configurations)."""
+def random_state(N, nv, seed, m=3, eps=1e-2, T_lo=0.05, T_hi=1.0, anisotropy=0.2,
+                 scaled=True):
+    """A generic state with seeded temperature, opacity and inflow, used to
+    exercise every code path (not one of the named configurations).
+
+    With `scaled`, the angular deviation of E from a T^4 follows the scaling of
+    the equations, E = acT^4 + eps E_J: its relative size is anisotropy*min(1, eps).
+    """
     rng = np.random.default_rng(SEED_BASE + 1000 + seed)
     mu, om = gauss_legendre_pairs(nv)
     P = nv // 2
     T = rng.uniform(T_lo, T_hi, N)
-    E = (T ** 4)[:, None] * (1.0 + anisotropy * rng.uniform(-1, 1, (N, P)))
+    dev = anisotropy * (min(1.0, eps) if scaled else 1.0)
+    E = (T ** 4)[:, None] * (1.0 + dev * rng.uniform(-1, 1, (N, P)))
     O = 0.1 * rng.normal(size=(N + 1, P)) * np.max(E)
     sigma0 = rng.uniform(0.3, 3.0, N)
     bL = rng.uniform(0.5, 1.5, P)

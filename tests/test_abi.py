@@ -1,0 +1,91 @@
+"""The C-ABI library loads, exports every symbol include/grte.h declares, and
+its host-only logic behaves (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grte.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(grte_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1811_05579_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1811_05579_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    from paper_1811_05579_amd import _lib
+    assert sorted(_lib._SIGS) == _declared()
+
+
+def _gl_reference(nv, dps=40):
+    """Gauss-Legendre pairs by Newton iteration at 40 digits (mpmath)."""
+    import mpmath
+    mpmath.mp.dps = dps
+    xs, ws = [], []
+    for k in range(1, nv // 2 + 1):
+        x = mpmath.cos(mpmath.pi * (k - mpmath.mpf(1) / 4) / (nv + mpmath.mpf(1) / 2))
+        for _ in range(60):
+            p = mpmath.legendre(nv, x)
+            dp = nv * (x * p - mpmath.legendre(nv - 1, x)) / (x * x - 1)
+            x -= p / dp
+        dp = nv * (x * mpmath.legendre(nv, x) - mpmath.legendre(nv - 1, x)) / (x * x - 1)
+        xs.append(float(x))
+        ws.append(float(2 / ((1 - x * x) * dp * dp)))
+    return np.array(xs[::-1]), np.array(ws[::-1])
+
+
+@pytest.mark.parametrize("nv", [2, 8, 16, 32, 64, 128])
+def test_gauss_legendre_correctly_rounded(lib, nv):
+    P = nv // 2
+    mu = np.zeros(P)
+    om = np.zeros(P)
+    assert lib.grte_gauss_legendre(nv, mu.ctypes.data, om.ctypes.data) == 0
+    xe, we = _gl_reference(nv)
+    assert np.all(np.abs(mu - xe) <= np.spacing(xe))
+    assert np.all(np.abs(om - we) <= np.spacing(we))
+    # numpy leggauss (used by the workload generator) agrees to ~1e-11
+    x, w = np.polynomial.legendre.leggauss(nv)
+    assert np.max(np.abs(w[x > 0] - we) / we) < 1e-10
+
+
+def test_invalid_arguments_rejected_before_device_work(lib):
+    from paper_1811_05579_amd._lib import Problem
+    mu = np.array([0.5])
+    om = np.array([1.0])
+    h = ctypes.c_void_p()
+    for pb in (Problem(1, 1, 1.0, 1.0, 1.0, 1.0, 0),      # N < 2
+               Problem(8, 1, 1.0, 1.0, 1.0, 1.0, 2),      # opacity law
+               Problem(8, 1, -1.0, 1.0, 1.0, 1.0, 0),     # length
+               Problem(8, 1, 1.0, 0.0, 1.0, 1.0, 0)):     # a
+        assert lib.grte_create(ctypes.byref(pb), mu.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
+    big = Problem(5000, 1, 1.0, 1.0, 1.0, 1.0, 0)
+    assert lib.grte_create(ctypes.byref(big), mu.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -5
+    bad_mu = np.array([-0.5])
+    ok = Problem(8, 1, 1.0, 1.0, 1.0, 1.0, 0)
+    assert lib.grte_create(ctypes.byref(ok), bad_mu.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
+    assert lib.grte_gauss_legendre(7, mu.ctypes.data, om.ctypes.data) == -1
+    assert lib.grte_step(None, 1.0, 1.0, None) == -1
+    assert lib.grte_destroy(None) == 0
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.grte_status_string(s)
