@@ -66,6 +66,8 @@ typedef struct grte_step_info {
     int newton_failed;    /* cells whose Newton solve hit the cap               */
     int kstar_clamped;    /* sigma/T^3: cells with U* < 0 (K* taken as 0)       */
     int negative_root;    /* cells whose temperature equation has no root >= 0  */
+    int sync_error;       /* 1 if a grid barrier of the prediction timed out
+                             (the step's results are then invalid; GRTE_E_HIP) */
 } grte_step_info;
 
 /* Stages readable after a step (grte_get_stage), for checking and diagnostics. */

@@ -22,7 +22,8 @@ class Problem(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
-                ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int)]
+                ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int),
+                ("sync_error", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -66,97 +66,179 @@
 
 #include "../../include/grte.h"
 
-namespace cg = cooperative_groups;
-
 namespace {
 
-constexpr int NT = 256;          // threads per work-group for the tridiagonal solvers
+constexpr int NT = 256;          // threads per work-group of the tridiagonal solvers
+constexpr int LOGNT = 8;
 constexpr int MAX_M = 16;        // rows per thread -> N <= NT * MAX_M = 4096
 constexpr int MAX_N = NT * MAX_M;
 constexpr int MAX_P = 64;
+constexpr int BAR_STRIDE = 16;   // 64-bit barrier flags, one 128-byte line per work-group
 
 // -------------------------------------------------------------------------
-// work-group tridiagonal solver
+// work-group tridiagonal solver: factor once, solve for many right-hand sides
 // -------------------------------------------------------------------------
-// Thread k owns rows k*M .. k*M+M-1 (coefficients in a,b,c,d); rows beyond the
-// system must be identity rows (a = c = d = 0, b = 1).  Row 0 must have
-// a = 0 and the last real row c = 0.  On return x holds the solution rows.
-// sh: 4*NT doubles of LDS.
+// Row j is owned by thread k = j / M as its row r = j % M; all per-row data
+// live in "position" order t = r * NT + k (conflict-free LDS, coalesced global
+// traffic).  The systems solved here have off-diagonals that are a scalar
+// multiple of two LDS-resident arrays, a_j = s Lo[t], c_j = s Up[t] (zero where
+// a row has no neighbour, and in padding rows), and a per-row diagonal b_j.
+// Each chunk's interior rows 0..M-2 are eliminated by Thomas' algorithm; the
+// chunk's last rows z_k form a tridiagonal system of NT rows solved by
+// parallel cyclic reduction.  What does not depend on the right-hand side --
+// the interior pivots and the PCR multipliers -- is computed once by
+// tri_factor and kept in registers; tri_solve then costs four short FMA
+// recurrences and one PCR sweep on the right-hand side only.
 template <int M>
-__device__ __forceinline__ void wg_tridiag(const double (&a)[M], const double (&b)[M],
-                                           const double (&c)[M], const double (&d)[M],
-                                           double (&x)[M], double *sh)
+struct TriFac {
+    double inv[M - 1];          // reciprocal pivots of the interior rows
+    double k1[LOGNT], k2[LOGNT];
+    double invB;
+};
+
+template <int M>
+__device__ __forceinline__ void tri_factor(double s, const double *Lo, const double *Up,
+                                           const double (&b)[M], TriFac<M> &F, double *sh)
 {
     static_assert(M >= 2, "at least two rows per thread");
     const int k = threadIdx.x;
-    // interior rows 0..M-2 of the chunk: Thomas with right-hand sides
-    //   P: d,  Q: -a_0 e_0 (left neighbour value),  R: -c_{M-2} e_{M-2} (own last row)
-    double cp[M - 1], Pv[M - 1], Qv[M - 1], Rv[M - 1];
+    double Q[M - 1], R[M - 1];   // responses of the interior to z_{k-1} (Q) and z_k (R)
+    double cprev;
     {
+        const double a0 = s * Lo[k], c0 = s * Up[k];
         const double inv = 1.0 / b[0];
-        cp[0] = (M > 2) ? c[0] * inv : 0.0;
-        Pv[0] = d[0] * inv;
-        Qv[0] = -a[0] * inv;
-        Rv[0] = (M == 2) ? -c[0] * inv : 0.0;
+        F.inv[0] = inv;
+        cprev = (M > 2) ? c0 * inv : 0.0;
+        Q[0] = -a0 * inv;
+        R[0] = (M == 2) ? -c0 * inv : 0.0;
     }
 #pragma unroll
     for (int r = 1; r < M - 1; ++r) {
-        const double inv = 1.0 / (b[r] - a[r] * cp[r - 1]);
-        cp[r] = (r < M - 2) ? c[r] * inv : 0.0;
-        Pv[r] = (d[r] - a[r] * Pv[r - 1]) * inv;
-        Qv[r] = (-a[r] * Qv[r - 1]) * inv;
-        Rv[r] = ((r == M - 2 ? -c[r] : 0.0) - a[r] * Rv[r - 1]) * inv;
+        const double ar = s * Lo[r * NT + k], cr = s * Up[r * NT + k];
+        const double inv = 1.0 / (b[r] - ar * cprev);
+        F.inv[r] = inv;
+        Q[r] = -ar * Q[r - 1] * inv;
+        R[r] = ((r == M - 2 ? -cr : 0.0) - ar * R[r - 1]) * inv;
+        cprev = (r < M - 2) ? cr * inv : 0.0;
     }
 #pragma unroll
     for (int r = M - 3; r >= 0; --r) {
-        Pv[r] -= cp[r] * Pv[r + 1];
-        Qv[r] -= cp[r] * Qv[r + 1];
-        Rv[r] -= cp[r] * Rv[r + 1];
+        const double cp = s * Up[r * NT + k] * F.inv[r];
+        Q[r] -= cp * Q[r + 1];
+        R[r] -= cp * R[r + 1];
     }
-    // first interior row of the next chunk (its value depends on my last row)
-    sh[k] = Pv[0];
-    sh[NT + k] = Qv[0];
-    sh[2 * NT + k] = Rv[0];
+    const double ae = s * Lo[(M - 1) * NT + k], ce = s * Up[(M - 1) * NT + k];
+    sh[k] = Q[0];
+    sh[NT + k] = R[0];
     __syncthreads();
-    const double Pn = (k + 1 < NT) ? sh[k + 1] : 0.0;
-    const double Qn = (k + 1 < NT) ? sh[NT + k + 1] : 0.0;
-    const double Rn = (k + 1 < NT) ? sh[2 * NT + k + 1] : 0.0;
+    const double Qn = (k + 1 < NT) ? sh[k + 1] : 0.0;
+    const double Rn = (k + 1 < NT) ? sh[NT + k + 1] : 0.0;
     __syncthreads();
-    // reduced row k couples the last rows z_{k-1}, z_k, z_{k+1} of the chunks
-    const double ae = a[M - 1], be = b[M - 1], ce = c[M - 1], de = d[M - 1];
-    double A = ae * Qv[M - 2];
-    double B = ae * Rv[M - 2] + be + ce * Qn;
-    double C = ce * Rn;
-    double D = de - ae * Pv[M - 2] - ce * Pn;
-    // parallel cyclic reduction on the NT reduced rows
-    double *sA = sh, *sB = sh + NT, *sC = sh + 2 * NT, *sD = sh + 3 * NT;
-#pragma unroll 1
-    for (int s = 1; s < NT; s <<= 1) {
-        sA[k] = A;
-        sB[k] = B;
-        sC[k] = C;
-        sD[k] = D;
+    double Aa = ae * Q[M - 2];
+    double Bb = ae * R[M - 2] + b[M - 1] + ce * Qn;
+    double Cc = ce * Rn;
+    double *sA = sh, *sB = sh + NT, *sC = sh + 2 * NT;
+#pragma unroll
+    for (int l = 0; l < LOGNT; ++l) {
+        const int st = 1 << l;
+        sA[k] = Aa;
+        sB[k] = Bb;
+        sC[k] = Cc;
         __syncthreads();
-        double Am = 0.0, Bm = 1.0, Cm = 0.0, Dm = 0.0;
-        double Ap = 0.0, Bp = 1.0, Cp = 0.0, Dp = 0.0;
-        if (k >= s) { Am = sA[k - s]; Bm = sB[k - s]; Cm = sC[k - s]; Dm = sD[k - s]; }
-        if (k + s < NT) { Ap = sA[k + s]; Bp = sB[k + s]; Cp = sC[k + s]; Dp = sD[k + s]; }
+        double Am = 0.0, Bm = 1.0, Cm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0;
+        if (k >= st) { Am = sA[k - st]; Bm = sB[k - st]; Cm = sC[k - st]; }
+        if (k + st < NT) { Ap = sA[k + st]; Bp = sB[k + st]; Cp = sC[k + st]; }
         __syncthreads();
-        const double k1 = A / Bm;
-        const double k2 = C / Bp;
-        A = -Am * k1;
-        C = -Cp * k2;
-        B = B - Cm * k1 - Ap * k2;
-        D = D - Dm * k1 - Dp * k2;
+        const double k1 = Aa / Bm, k2 = Cc / Bp;
+        F.k1[l] = k1;
+        F.k2[l] = k2;
+        Aa = -Am * k1;
+        Cc = -Cp * k2;
+        Bb = Bb - Cm * k1 - Ap * k2;
     }
-    const double z = D / B;
+    F.invB = 1.0 / Bb;
+}
+
+// forward elimination + back substitution over the interior rows 0..M-2
+template <int M>
+__device__ __forceinline__ void tri_interior(double s, const double *Lo, const double *Up, const TriFac<M> &F,
+                                             double (&y)[M - 1])
+{
+    const int k = threadIdx.x;
+    y[0] = y[0] * F.inv[0];
+#pragma unroll
+    for (int r = 1; r < M - 1; ++r) y[r] = (y[r] - s * Lo[r * NT + k] * y[r - 1]) * F.inv[r];
+#pragma unroll
+    for (int r = M - 3; r >= 0; --r) y[r] -= s * Up[r * NT + k] * F.inv[r] * y[r + 1];
+}
+
+template <int M>
+__device__ __forceinline__ void tri_solve(double s, const double *Lo, const double *Up, const TriFac<M> &F,
+                                          const double (&d)[M], double (&x)[M], double *sh)
+{
+    const int k = threadIdx.x;
+    // interior particular solution with z_{k-1} = z_k = 0
+    double y[M - 1];
+#pragma unroll
+    for (int r = 0; r < M - 1; ++r) y[r] = d[r];
+    tri_interior<M>(s, Lo, Up, F, y);
+    // forward value of the last interior row (needed before back substitution)
+    // equals its final value, so ylast is read after the sweep
+    const double ylast = y[M - 2];
+    sh[k] = y[0];
+    __syncthreads();
+    const double yn = (k + 1 < NT) ? sh[k + 1] : 0.0;
+    double D = d[M - 1] - s * Lo[(M - 1) * NT + k] * ylast - s * Up[(M - 1) * NT + k] * yn;
+    // PCR on the right-hand side, two buffers so one barrier per level suffices
+#pragma unroll
+    for (int l = 0; l < LOGNT; ++l) {
+        const int st = 1 << l;
+        double *bf = sh + NT * (1 + (l & 1));
+        bf[k] = D;
+        __syncthreads();
+        const double Dm = (k >= st) ? bf[k - st] : 0.0;
+        const double Dp = (k + st < NT) ? bf[k + st] : 0.0;
+        D = D - F.k1[l] * Dm - F.k2[l] * Dp;
+    }
+    const double z = D * F.invB;
     sh[k] = z;
     __syncthreads();
     const double zl = (k > 0) ? sh[k - 1] : 0.0;
     __syncthreads();
+    // interior again, now with the neighbouring chunk values folded in
 #pragma unroll
-    for (int r = 0; r < M - 1; ++r) x[r] = Pv[r] + Qv[r] * zl + Rv[r] * z;
+    for (int r = 0; r < M - 1; ++r) y[r] = d[r];
+    y[0] -= s * Lo[k] * zl;
+    y[M - 2] -= s * Up[(M - 2) * NT + k] * z;
+    tri_interior<M>(s, Lo, Up, F, y);
+#pragma unroll
+    for (int r = 0; r < M - 1; ++r) x[r] = y[r];
     x[M - 1] = z;
+}
+
+// block-wide max of two values at once: wave shuffles, then one LDS step
+// (fixed order; the result is the same in every thread)
+__device__ __forceinline__ void block_max2(double &a, double &b, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a = fmax(a, __shfl_xor(a, o, 64));
+        b = fmax(b, __shfl_xor(b, o, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = a;
+        sh[8 + w] = b;
+    }
+    __syncthreads();
+    a = sh[0];
+    b = sh[8];
+#pragma unroll
+    for (int q = 1; q < NT / 64; ++q) {
+        a = fmax(a, sh[q]);
+        b = fmax(b, sh[8 + q]);
+    }
+    __syncthreads();
 }
 
 // block-wide max of a non-negative value (fixed order; result in every thread)
@@ -176,30 +258,79 @@ __device__ __forceinline__ double block_max(double v, double *sh)
 }
 
 // -------------------------------------------------------------------------
-// coefficients (one thread per cell)
+// grid barrier for a cooperative launch (all work-groups co-resident)
 // -------------------------------------------------------------------------
-struct CoefArgs {
-    int N, P, m, mode;           // mode 0: prediction (K from T^n), 1: correction (K from T^{n+1})
-    double a, c, cv, eps, dt, dx;
-    const double *T;             // temperature defining K (T^n or T^{n+1})
-    const double *Tn;            // T^n (for U^n and beta)
-    const double *sigma0, *mu, *omega, *bL, *bR;
-    const double *E, *O;         // E^n, O^n (cell-major)
-    double mu1, mu2;             // sum omega mu, sum omega mu^2 (DSA)
-    // outputs
-    double *Ll, *Ld, *Lu, *Lam, *LmG, *G, *Bd, *Aw, *Bc, *beta;
-    double *Dl, *Dd, *Du;        // DSA operator (prediction only)
-    double *rho_n;               // sum_p omega_p E^n (prediction only)
-    double *r;                   // right-hand sides, pair-major [p*N + j]
-};
+// Every work-group publishes the generation number in its own flag (no
+// contended counter); lanes of wave 0 watch one flag each.  Each thread makes
+// its own global writes visible at agent scope before the work-group
+// barrier, and the flag store is a release, so the writes are visible on every
+// XCD to a work-group that has observed the flag and executed the acquire.
+// The wait is bounded: on a timeout, or when another work-group has already
+// reported one, the error flag is raised and false is returned so that every
+// work-group leaves the iteration instead of hanging the device.
+__device__ __forceinline__ bool grid_barrier(unsigned long long *flags, unsigned long long gen, int *err)
+{
+    __shared__ int s_fail;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_fail = 0;
+        __hip_atomic_store(&flags[(size_t)blockIdx.x * BAR_STRIDE], gen, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x < 64) {
+        bool fail = false;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&flags[(size_t)b * BAR_STRIDE], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) < gen) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                    ++spins > (1u << 20)) {
+                    fail = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (fail) {
+            atomicOr(err, 1);
+            s_fail = 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return s_fail == 0;
+}
 
 __device__ __forceinline__ double kpow(double T, int m) { return m == 0 ? 1.0 : T * T * T; }
+
+// position of row j in the per-thread-chunk ("position") order used by the
+// tridiagonal solvers: t = (j % M) * NT + j / M
+__device__ __forceinline__ int row_pos(int j, int M) { return (j % M) * NT + j / M; }
+
+// -------------------------------------------------------------------------
+// coefficients: one work-group per group of cells, all pairs of those cells
+// -------------------------------------------------------------------------
+struct CoefArgs {
+    int N, P, m, mode, cpb;      // mode 0: prediction (K from T^n), 1: correction (K from T^{n+1})
+    double a, c, cv, eps, dt, dx;
+    const double *T;             // temperature defining K (T^n or T^{n+1})
+    const double *Tn;            // T^n (U^n and beta)
+    const double *sigma0, *mu, *omega, *bL, *bR;
+    const double *E, *O;         // E^n, O^n, cell-major
+    double mu1, mu2;             // sum omega mu, sum omega mu^2 (diffusion operator)
+    double *Ll, *Lu, *Lam, *LmG, *Gt, *Bd, *Aw, *Bc, *beta;   // Gt: position order (row_pos)
+    int M;                       // rows per thread of the prediction kernel (for Gt)
+    double *Dl, *Dd, *Du;        // diffusion operator (prediction only)
+    double *rho_n;               // sum_p omega_p E^n_p (prediction only)
+    double *r;                   // right-hand sides, cell-major [j*P + p]
+    int *stat;                   // cleared by the prediction pass
+};
 
 __device__ __forceinline__ void node_coef(const CoefArgs &A, int i, double &aw, double &bc)
 {
     // interior node i (1..N-1) between cells i-1 and i
-    const double Kl = kpow(A.T[i - 1], A.m), Kr = kpow(A.T[i], A.m);
-    const double Kn = 0.5 * (Kl + Kr);
+    const double Kn = 0.5 * (kpow(A.T[i - 1], A.m) + kpow(A.T[i], A.m));
     const double sl = A.sigma0[i - 1], sr = A.sigma0[i];
     const double ss = sl + sr;
     const double sn = ss > 0.0 ? 2.0 * sl * sr / ss : 0.0;      // harmonic mean
@@ -215,187 +346,243 @@ __device__ __forceinline__ void node_coef(const CoefArgs &A, int i, double &aw, 
 
 __global__ void __launch_bounds__(256) coef_kernel(CoefArgs A)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = A.N;
-    if (j > N) return;
-    // node arrays (N+1 entries; boundary nodes carry zeros)
-    if (j <= N) {
-        double aw = 0.0, bc = 0.0;
-        if (j >= 1 && j <= N - 1) node_coef(A, j, aw, bc);
-        A.Aw[j] = aw;
-        A.Bc[j] = bc;
+    __shared__ double s_h[256], s_awr[256], s_awl[256], s_src[256], s_keps[256], s_w[256];
+    const int N = A.N, P = A.P, cpb = A.cpb;
+    const int c0 = blockIdx.x * cpb;
+    const int t = threadIdx.x;
+    if (A.mode == 0 && blockIdx.x == 0 && t < 8) A.stat[t] = 0;
+    // ---- per cell
+    if (t < cpb && c0 + t < N) {
+        const int j = c0 + t;
+        const double eps = A.eps, c = A.c, dt = A.dt;
+        double awl = 0.0, bcl = 0.0, awr = 0.0, bcr = 0.0;
+        if (j >= 1) node_coef(A, j, awl, bcl);
+        if (j <= N - 2) node_coef(A, j + 1, awr, bcr);
+        A.Aw[j] = awl;
+        A.Bc[j] = bcl;
+        if (j == N - 1) {
+            A.Aw[N] = 0.0;
+            A.Bc[N] = 0.0;
+        }
+        const double Kc = kpow(A.T[j], A.m);
+        const double s0 = A.sigma0[j];
+        const double h = Kc * eps * eps * c * dt / A.dx;
+        const double fr = (j <= N - 2) ? h * bcr * (j == 0 ? 2.0 : 1.0) : 0.0;
+        const double fl = (j >= 1) ? h * bcl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+        const double bd = (j == 0 || j == N - 1) ? 2.0 * h / eps : 0.0;
+        const double lam = Kc * eps * eps + s0 * c * dt;
+        A.Ll[j] = -fl;
+        A.Lu[j] = -fr;
+        A.Bd[j] = bd;
+        A.Lam[j] = lam;
+        const double ac = A.a * c;
+        double src;
+        if (A.mode == 0) {
+            const double Tn = A.Tn[j];
+            const double Un = Tn * Tn * Tn * Tn;
+            // (4.5c): beta = 4 sigma0 dt (T^n)^(3-m) / (eps^2 Cv)
+            const double t3m = (A.m == 0) ? Tn * Tn * Tn : 1.0;
+            const double beta = 4.0 * s0 * dt * t3m / (eps * eps * A.cv);
+            const double opb = 1.0 + ac * beta;
+            const double lmg = Kc * eps * eps + s0 * c * dt / opb;
+            A.beta[j] = beta;
+            A.LmG[j] = lmg;
+            A.Gt[(j % A.M) * NT + j / A.M] = s0 * c * dt * (ac * beta) / opb;
+            A.Dl[j] = A.mu2 * (-fl);
+            A.Du[j] = A.mu2 * (-fr);
+            A.Dd[j] = lmg + A.mu2 * (fl + fr) + A.mu1 * bd;
+            src = s0 * c * dt * ac * Un / opb;
+        } else {
+            const double T1 = A.T[j];
+            src = s0 * c * dt * ac * (T1 * T1 * T1 * T1);
+        }
+        s_h[t] = h;
+        s_awr[t] = (j <= N - 2) ? awr * (j == 0 ? 2.0 : 1.0) : 0.0;
+        s_awl[t] = (j >= 1) ? awl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+        s_src[t] = src;
+        s_keps[t] = Kc * eps * eps;
     }
-    if (j >= N) return;
-    const double eps = A.eps, c = A.c, dt = A.dt;
-    const double Kc = kpow(A.T[j], A.m);
-    const double s0 = A.sigma0[j];
-    const double h = Kc * eps * eps * c * dt / A.dx;
-    double awl = 0.0, bcl = 0.0, awr = 0.0, bcr = 0.0;
-    if (j >= 1) node_coef(A, j, awl, bcl);
-    if (j <= N - 2) node_coef(A, j + 1, awr, bcr);
-    const double fr = (j <= N - 2) ? h * bcr * (j == 0 ? 2.0 : 1.0) : 0.0;
-    const double fl = (j >= 1) ? h * bcl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
-    const double awr_f = (j <= N - 2) ? awr * (j == 0 ? 2.0 : 1.0) : 0.0;
-    const double awl_f = (j >= 1) ? awl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
-    const double bd = (j == 0 || j == N - 1) ? 2.0 * h / eps : 0.0;
-    const double lam = Kc * eps * eps + s0 * c * dt;
-    A.Ll[j] = -fl;
-    A.Lu[j] = -fr;
-    A.Ld[j] = fl + fr;
-    A.Bd[j] = bd;
-    A.Lam[j] = lam;
-    const double ac = A.a * c;
-    const double Tn = A.Tn[j];
-    const double Un = Tn * Tn * Tn * Tn;
-    double src;   // sigma0 c dt ac U / (...) part of the right-hand side
-    if (A.mode == 0) {
-        // (4.5c): beta = 4 sigma0 dt (T^n)^(3-m) / (eps^2 Cv)
-        const double t3m = (A.m == 0) ? Tn * Tn * Tn : 1.0;
-        const double beta = 4.0 * s0 * dt * t3m / (eps * eps * A.cv);
-        const double opb = 1.0 + ac * beta;
-        const double lmg = Kc * eps * eps + s0 * c * dt / opb;
-        const double g = s0 * c * dt * (ac * beta) / opb;
-        A.beta[j] = beta;
-        A.LmG[j] = lmg;
-        A.G[j] = g;
-        A.Dl[j] = A.mu2 * (-fl);
-        A.Du[j] = A.mu2 * (-fr);
-        A.Dd[j] = lmg + A.mu2 * (fl + fr) + A.mu1 * bd;
-        src = s0 * c * dt * ac * Un / opb;
-        double rho = 0.0;
-        for (int p = 0; p < A.P; ++p) rho += A.omega[p] * A.E[(size_t)j * A.P + p];
-        A.rho_n[j] = rho;
-    } else {
-        const double T1 = A.T[j];
-        src = s0 * c * dt * ac * (T1 * T1 * T1 * T1);
-    }
-    const double keps = Kc * eps * eps;
-    for (int p = 0; p < A.P; ++p) {
+    __syncthreads();
+    // ---- per (cell, pair): right-hand sides of the per-pair systems
+    const int cl = t / P, p = t - (t / P) * P;
+    const int j = c0 + cl;
+    if (cl < cpb && j < N) {
         const double mu = A.mu[p];
-        const double On_r = (j <= N - 2) ? A.O[(size_t)(j + 1) * A.P + p] : 0.0;
-        const double On_l = (j >= 1) ? A.O[(size_t)j * A.P + p] : 0.0;
-        double rv = keps * A.E[(size_t)j * A.P + p] + src - h * mu * (awr_f * On_r - awl_f * On_l);
-        if (j == 0) rv += 2.0 * h * mu * A.bL[p] / eps;
-        if (j == N - 1) rv += 2.0 * h * mu * A.bR[p] / eps;
-        A.r[(size_t)p * N + j] = rv;
+        const double h = s_h[cl];
+        const double On_r = (j <= N - 2) ? A.O[(size_t)(j + 1) * P + p] : 0.0;
+        const double On_l = (j >= 1) ? A.O[(size_t)j * P + p] : 0.0;
+        const double En = A.E[(size_t)j * P + p];
+        double rv = s_keps[cl] * En + s_src[cl] - h * mu * (s_awr[cl] * On_r - s_awl[cl] * On_l);
+        if (j == 0) rv += 2.0 * h * mu * A.bL[p] / A.eps;
+        if (j == N - 1) rv += 2.0 * h * mu * A.bR[p] / A.eps;
+        A.r[(size_t)j * P + p] = rv;
+        if (A.mode == 0) s_w[t] = A.omega[p] * En;
+    }
+    if (A.mode == 0) {
+        __syncthreads();
+        if (t < cpb && c0 + t < N) {
+            double rho = 0.0;
+            for (int q = 0; q < P; ++q) rho += s_w[t * P + q];
+            A.rho_n[c0 + t] = rho;
+        }
     }
 }
 
 // -------------------------------------------------------------------------
 // prediction: cooperative Richardson iteration with diffusion acceleration
 // -------------------------------------------------------------------------
+// Row j of a system is owned by thread k = j / M as its row r = j % M.  Every
+// per-row array the iteration touches is kept in "position" order
+// t = r * NT + k, so that consecutive threads touch consecutive words (no LDS
+// bank conflicts, coalesced global traffic).
 struct PredArgs {
     int N, P, maxit;
-    double tol, one_minus_W;
-    const double *Ll, *Ld, *Lu, *Lam, *LmG, *G, *Bd, *Dl, *Dd, *Du;
+    double tol, one_minus_W, mu2avg;   // mu2avg = sum_p omega_p mu_p^2 (diffusion operator)
+    const double *Ll, *Lu, *Lam, *LmG, *Bd, *Dd;   // cell order; diffusion off-diagonals are mu2avg * L
+    const double *Gt;                  // G in position order (padded entries zero)
     const double *r, *mu, *omega, *rho0;
-    double *v, *res, *estar, *rho_out;
-    int *stat;   // [0] iterations, [1] converged
+    double *part;                      // omega_p v_p, pair-major, position order [p*NP + t]
+    double *res;                       // position order
+    double *estar;                     // E*, pair-major, position order [p*NP + t]
+    double *rho_out;                   // cell order
+    int *stat;                         // [0] iterations, [1] converged, [6] barrier error
+    unsigned long long *flags;
+    unsigned long long gen0;
 };
 
 template <int M>
 __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
 {
-    cg::grid_group grid = cg::this_grid();
     extern __shared__ double smem[];
-    double *rho = smem;                    // current iterate   (NT*M)
-    double *sh = smem + NT * M;            // 4*NT scratch
-    double rho_prev[M];                    // my rows of the iterate used by the last sweep
+    constexpr int NP = NT * M;           // padded rows
+    double *rho = smem;                  // current iterate (position order)
+    double *sLl = smem + NP;             // operator coefficients (position order)
+    double *sLu = smem + 2 * NP;
+    double *sLmG = smem + 3 * NP;
+    double *sh = smem + 4 * NP;          // 3*NT scratch
     const int k = threadIdx.x;
-    const int N = A.N;
+    const int N = A.N, P = A.P;
     const int j0 = k * M;
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-        const int j = j0 + r;
-        rho[j] = (j < N) ? A.rho0[j] : 0.0;
+    for (int j = k; j < NP; j += NT) {
+        const bool in = j < N;
+        const int t = row_pos(j, M);
+        rho[t] = in ? A.rho0[j] : 0.0;
+        sLl[t] = in ? A.Ll[j] : 0.0;
+        sLu[t] = in ? A.Lu[j] : 0.0;
+        sLmG[t] = in ? A.LmG[j] : 0.0;
     }
+    const double bd0 = A.Bd[0], bdN = A.Bd[N - 1];
     __syncthreads();
-    int it = 0;
-    int converged = 0;
-    double a[M], b[M], c[M], d[M], x[M];
-    while (true) {
-        // ---- transport sweep: v_p = T_p^{-1} [r_p - (T_p - G) rho] for my pairs
-        for (int p = blockIdx.x; p < A.P; p += gridDim.x) {
-            const double mu = A.mu[p], mu2 = mu * mu;
+    const int p = blockIdx.x;            // one parity pair per work-group
+    const double mu = A.mu[p], mu2 = mu * mu, wp = A.omega[p];
+
+    TriFac<M> Ft, Fd;
+    double rr[M], gg[M];
 #pragma unroll
-            for (int r = 0; r < M; ++r) {
-                const int j = j0 + r;
-                if (j < N) {
-                    const double ll = A.Ll[j], ld = A.Ld[j], lu = A.Lu[j], bd = A.Bd[j];
-                    a[r] = mu2 * ll;
-                    c[r] = mu2 * lu;
-                    b[r] = A.Lam[j] + mu2 * ld + mu * bd;
-                    const double rj = rho[j];
-                    double Lr = ld * rj;
-                    if (j > 0) Lr += ll * rho[j - 1];
-                    if (j < N - 1) Lr += lu * rho[j + 1];
-                    d[r] = A.r[(size_t)p * N + j] - A.LmG[j] * rj - mu2 * Lr - mu * bd * rj;
-                } else {
-                    a[r] = 0.0; b[r] = 1.0; c[r] = 0.0; d[r] = 0.0;
-                }
-            }
-            wg_tridiag<M>(a, b, c, d, x, sh);
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                const int j = j0 + r;
-                if (j < N) A.v[(size_t)p * N + j] = x[r];
-            }
-        }
-        grid.sync();
-        // ---- angular reduction, cells spread over the grid
-        for (int j = blockIdx.x * NT + k; j < N; j += gridDim.x * NT) {
-            double s = 0.0;
-            for (int p = 0; p < A.P; ++p) s += A.omega[p] * A.v[(size_t)p * N + j];
-            A.res[j] = s - A.one_minus_W * rho[j];
-        }
-        grid.sync();
-        // ---- diffusion acceleration (every group, identical result)
-        double rl[M];
+    for (int r = 0; r < M; ++r) gg[r] = A.Gt[r * NT + k];
+    {
+        double b[M];
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int j = j0 + r;
             if (j < N) {
-                rl[r] = A.res[j];
-                a[r] = A.Dl[j];
-                b[r] = A.Dd[j];
-                c[r] = A.Du[j];
-                d[r] = A.G[j] * rl[r];
+                const double ll = sLl[r * NT + k], lu = sLu[r * NT + k];
+                const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
+                b[r] = A.Lam[j] + mu2 * (-(ll + lu)) + mu * bdj;
+                rr[r] = A.r[(size_t)j * P + p];
             } else {
-                rl[r] = 0.0;
-                a[r] = 0.0; b[r] = 1.0; c[r] = 0.0; d[r] = 0.0;
+                b[r] = 1.0;
+                rr[r] = 0.0;
             }
         }
-        wg_tridiag<M>(a, b, c, d, x, sh);
+        tri_factor<M>(mu2, sLl, sLu, b, Ft, sh);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int j = j0 + r;
+            b[r] = (j < N) ? A.Dd[j] : 1.0;
+        }
+        tri_factor<M>(A.mu2avg, sLl, sLu, b, Fd, sh);
+    }
+
+    // positions whose angular sum this work-group forms
+    const int chunk = (NP + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int tb = blockIdx.x * chunk;
+    const int te = min(NP, tb + chunk);
+    double *part_p = A.part + (size_t)p * NP;
+    double *estar_p = A.estar + (size_t)p * NP;
+    unsigned long long gen = A.gen0;
+    int it = 0, converged = 0;
+    while (true) {
+        // ---- sweep: v_p = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho]
+        double y[M], v[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int j = j0 + r;
+            if (j < N) {
+                const int t = r * NT + k;
+                const double rj = rho[t];
+                double rl = 0.0, rn = 0.0;
+                if (j > 0) rl = (r > 0) ? rho[t - NT] : rho[(M - 1) * NT + k - 1];
+                if (j < N - 1) rn = (r < M - 1) ? rho[t + NT] : rho[k + 1];
+                const double ll = sLl[t], lu = sLu[t];
+                const double q = -(ll + lu) * rj + ll * rl + lu * rn;
+                const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
+                y[r] = rr[r] - sLmG[t] * rj - mu2 * q - mu * bdj * rj;
+            } else {
+                y[r] = 0.0;
+            }
+        }
+        tri_solve<M>(mu2, sLl, sLu, Ft, y, v, sh);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int t = r * NT + k;          // padded rows give v = 0
+            part_p[t] = wp * v[r];
+            estar_p[t] = rho[t] + v[r];        // E*_p of this sweep
+        }
+        if (!grid_barrier(A.flags, ++gen, A.stat + 6)) break;
+        // ---- angular sum for my positions: res = sum_p omega_p v_p - (1 - W) rho
+        for (int t = tb + k; t < te; t += NT) {
+            double s = 0.0;
+            int q = 0;
+            for (; q + 8 <= P; q += 8) {
+                double t8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t8[u] = A.part[(size_t)(q + u) * NP + t];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s += t8[u];
+            }
+            for (; q < P; ++q) s += A.part[(size_t)q * NP + t];
+            A.res[t] = s - A.one_minus_W * rho[t];
+        }
+        if (!grid_barrier(A.flags, ++gen, A.stat + 6)) break;
+        // ---- diffusion acceleration, identical in every work-group
+        double rl[M], d[M], f[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int t = r * NT + k;
+            rl[r] = A.res[t];
+            d[r] = gg[r] * rl[r];
+        }
+        tri_solve<M>(A.mu2avg, sLl, sLu, Fd, d, f, sh);
         double md = 0.0, mr = 0.0;
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-            const int j = j0 + r;
-            if (j < N) {
-                const double delta = rl[r] + x[r];
-                const double old = rho[j];
-                rho_prev[r] = old;
-                const double nw = old + delta;
-                rho[j] = nw;
+            if (j0 + r < N) {
+                const int t = r * NT + k;
+                const double delta = rl[r] + f[r];
+                const double nw = rho[t] + delta;
+                rho[t] = nw;
                 md = fmax(md, fabs(delta));
                 mr = fmax(mr, fabs(nw));
             }
         }
-        md = block_max(md, sh);
-        mr = block_max(mr, sh);   // also orders the rho updates before the next sweep
+        block_max2(md, mr, sh);   // its barriers also publish the rho update
         ++it;
         converged = (md <= A.tol * mr) ? 1 : 0;
         if (converged || it >= A.maxit) break;
     }
-    // E*_p = rho (used by the last sweep) + v_p
-    for (int p = blockIdx.x; p < A.P; p += gridDim.x) {
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const int j = j0 + r;
-            if (j < N) A.estar[(size_t)p * N + j] = rho_prev[r] + A.v[(size_t)p * N + j];
-        }
-    }
     if (blockIdx.x == 0) {
-        for (int j = k; j < N; j += NT) A.rho_out[j] = rho[j];
+        for (int j = k; j < N; j += NT) A.rho_out[j] = rho[row_pos(j, M)];
         if (k == 0) {
             A.stat[0] = it;
             A.stat[1] = converged;
@@ -404,51 +591,71 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
 }
 
 // -------------------------------------------------------------------------
-// correction substep 1: moments, D, K*, scalar Newton (one thread per cell)
+// correction substep 1: moments, D, K*, scalar Newton
 // -------------------------------------------------------------------------
 struct NewtonArgs {
-    int N, P, m, maxit, keep;
+    int N, P, m, maxit, keep, cpb, M;
     double a, c, cv, eps, dt, dx;
-    const double *estar, *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
+    const double *estar_t;   // E*, pair-major, position order (prediction output)
+    const double *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
+    double *Ecm;             // E* copied to cell-major order (read by the node relations)
     double *Tnew, *ustar, *Dv, *ostar;
     int *stat;   // [2] max its, [3] failed, [4] K* clamped, [5] negative root
 };
 
-__device__ __forceinline__ double ostar_node(const NewtonArgs &A, int i, int p)
+// E* from the position-ordered prediction output into the cell-major layout
+__global__ void __launch_bounds__(256) gather_estar_kernel(NewtonArgs A)
 {
-    // interior node i (1..N-1)
-    const int N = A.N;
-    const double mu = A.mu[p];
-    return A.Aw[i] * A.O[(size_t)i * A.P + p]
-         - A.Bc[i] * mu * (A.estar[(size_t)p * N + i] - A.estar[(size_t)p * N + i - 1]);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = A.N, P = A.P;
+    if (t >= N * P) return;
+    const int j = t / P, p = t - (t / P) * P;
+    A.Ecm[t] = A.estar_t[(size_t)p * NT * A.M + row_pos(j, A.M)];
 }
 
-__device__ __forceinline__ double ostar_any(const NewtonArgs &A, int i, int p)
+__device__ __forceinline__ double node_flux(const double *Eall, const double *O, const double *Aw,
+                                            const double *Bc, double mu, int N, int P, int i, int p)
 {
-    const int N = A.N;
-    if (i >= 1 && i <= N - 1) return ostar_node(A, i, p);
-    if (i == 0)      // (4.7) at x = 0
-        return 2.0 / A.eps * (A.bL[p] - A.estar[(size_t)p * N]) - ostar_node(A, 1, p);
+    // interior node i (1..N-1): O_i = Aw_i O^n_i - Bc_i mu (E_i - E_{i-1})
+    return Aw[i] * O[(size_t)i * P + p] - Bc[i] * mu * (Eall[(size_t)i * P + p] - Eall[(size_t)(i - 1) * P + p]);
+}
+
+__device__ __forceinline__ double node_any(const double *Eall, const double *O, const double *Aw,
+                                           const double *Bc, double mu, double bl, double br, double eps,
+                                           int N, int P, int i, int p)
+{
+    if (i >= 1 && i <= N - 1) return node_flux(Eall, O, Aw, Bc, mu, N, P, i, p);
+    if (i == 0)   // inflow relation (4.7) at x = 0
+        return 2.0 / eps * (bl - Eall[p]) - node_flux(Eall, O, Aw, Bc, mu, N, P, 1, p);
     // i == N, (4.7) at x = L
-    return 2.0 / A.eps * (A.estar[(size_t)p * N + N - 1] - A.bR[p]) - ostar_node(A, N - 1, p);
+    return 2.0 / eps * (Eall[(size_t)(N - 1) * P + p] - br) - node_flux(Eall, O, Aw, Bc, mu, N, P, N - 1, p);
 }
 
 __global__ void __launch_bounds__(256) newton_kernel(NewtonArgs A)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= A.N) return;
-    const int N = A.N;
-    double rho = 0.0, D = 0.0;
-    for (int p = 0; p < A.P; ++p) {
-        const double w = A.omega[p];
-        rho += w * A.estar[(size_t)p * N + j];
-        const double ol = ostar_any(A, j, p);
-        const double orr = ostar_any(A, j + 1, p);
-        D += w * A.mu[p] * (orr - ol);
+    __shared__ double s_w[256], s_f[256];
+    const int N = A.N, P = A.P, cpb = A.cpb;
+    const int c0 = blockIdx.x * cpb, t = threadIdx.x;
+    const int cl = t / P, p = t - (t / P) * P;
+    const int jj = c0 + cl;
+    if (cl < cpb && jj < N) {
+        const double mu = A.mu[p], w = A.omega[p];
+        const double ol = node_any(A.Ecm, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj, p);
+        const double orr = node_any(A.Ecm, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj + 1, p);
+        s_w[t] = w * A.Ecm[(size_t)jj * P + p];
+        s_f[t] = w * mu * (orr - ol);
         if (A.keep) {
-            A.ostar[(size_t)j * A.P + p] = ol;
-            if (j == N - 1) A.ostar[(size_t)N * A.P + p] = orr;
+            A.ostar[(size_t)jj * P + p] = ol;
+            if (jj == N - 1) A.ostar[(size_t)N * P + p] = orr;
         }
+    }
+    __syncthreads();
+    if (t >= cpb || c0 + t >= N) return;
+    const int j = c0 + t;
+    double rho = 0.0, D = 0.0;
+    for (int q = 0; q < P; ++q) {
+        rho += s_w[t * P + q];
+        D += s_f[t * P + q];
     }
     D /= A.dx;
     const double ac = A.a * A.c;
@@ -467,16 +674,16 @@ __global__ void __launch_bounds__(256) newton_kernel(NewtonArgs A)
             Ks = pow(us, 0.75);
         }
     }
+    // (4.13) times c sigma0 dt^2:
+    //   a c sigma0 dt T^4 + Cv (eps^2 K* + c sigma0 dt)(T - T^n) - sigma0 dt (rho^n - c dt D) = 0
     const double s0 = A.sigma0[j];
-    const double eps2 = A.eps * A.eps;
-    const double lin = A.cv * (eps2 * Ks + A.c * s0 * A.dt);
+    const double lin = A.cv * (A.eps * A.eps * Ks + A.c * s0 * A.dt);
     const double q4 = ac * s0 * A.dt;
     const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
     double T = Tn;
     int its = 0;
     if (!(s0 == 0.0 && Ks == 0.0)) {
-        // root of the linear part alone; a negative value means no root >= 0
-        if (Tn + rhs / lin < 0.0) atomicAdd(&A.stat[5], 1);
+        if (Tn + rhs / lin < 0.0) atomicAdd(&A.stat[5], 1);   // no root >= 0
         bool ok = false;
         for (its = 0; its < A.maxit;) {
             const double T2 = T * T;
@@ -498,88 +705,80 @@ __global__ void __launch_bounds__(256) newton_kernel(NewtonArgs A)
 // -------------------------------------------------------------------------
 struct CorrArgs {
     int N, P;
-    const double *Ll, *Ld, *Lu, *Lam, *Bd, *r, *mu;
-    double *enew;   // pair-major
+    const double *Ll, *Lu, *Lam, *Bd, *r, *mu;
+    double *Enew;   // cell-major E^{n+1}
 };
 
 template <int M>
 __global__ void __launch_bounds__(NT) corr_kernel(CorrArgs A)
 {
-    __shared__ double sh[4 * NT];
+    extern __shared__ double smem[];
+    constexpr int NP = NT * M;
+    double *sLl = smem, *sLu = smem + NP, *sh = smem + 2 * NP;
     const int p = blockIdx.x;
-    const int N = A.N;
-    const int j0 = threadIdx.x * M;
+    const int N = A.N, P = A.P, k = threadIdx.x;
+    const int j0 = k * M;
+    for (int j = k; j < NP; j += NT) {
+        const int t = row_pos(j, M);
+        sLl[t] = (j < N) ? A.Ll[j] : 0.0;
+        sLu[t] = (j < N) ? A.Lu[j] : 0.0;
+    }
+    __syncthreads();
     const double mu = A.mu[p], mu2 = mu * mu;
-    double a[M], b[M], c[M], d[M], x[M];
+    double b[M], d[M], x[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int j = j0 + r;
         if (j < N) {
-            a[r] = mu2 * A.Ll[j];
-            c[r] = mu2 * A.Lu[j];
-            b[r] = A.Lam[j] + mu2 * A.Ld[j] + mu * A.Bd[j];
-            d[r] = A.r[(size_t)p * N + j];
+            const double ll = sLl[r * NT + k], lu = sLu[r * NT + k];
+            b[r] = A.Lam[j] + mu2 * (-(ll + lu)) + mu * A.Bd[j];
+            d[r] = A.r[(size_t)j * P + p];
         } else {
-            a[r] = 0.0; b[r] = 1.0; c[r] = 0.0; d[r] = 0.0;
+            b[r] = 1.0;
+            d[r] = 0.0;
         }
     }
-    wg_tridiag<M>(a, b, c, d, x, sh);
+    TriFac<M> F;
+    tri_factor<M>(mu2, sLl, sLu, b, F, sh);
+    tri_solve<M>(mu2, sLl, sLu, F, d, x, sh);
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int j = j0 + r;
-        if (j < N) A.enew[(size_t)p * N + j] = x[r];
+        if (j < N) A.Enew[(size_t)j * P + p] = x[r];
     }
 }
 
 // -------------------------------------------------------------------------
-// projection (4.14): E^{n+1}, O^{n+1} in the cell-major state layout
+// projection (4.14): O^{n+1} at the nodes (E^{n+1} is already in place), rho^{n+1}
 // -------------------------------------------------------------------------
 struct ProjArgs {
-    int N, P;
+    int N, P, keep, cpb;
     double eps;
-    const double *enew, *O, *Aw, *Bc, *mu, *omega, *bL, *bR, *estar;
-    double *Eout, *Oout, *rho_out, *estar_cm;
-    int keep;
+    const double *Enew, *O, *Aw, *Bc, *mu, *omega, *bL, *bR;
+    double *Oout, *rho_out;
 };
-
-__device__ __forceinline__ double onew_node(const ProjArgs &A, int i, int p)
-{
-    const int N = A.N;
-    return A.Aw[i] * A.O[(size_t)i * A.P + p]
-         - A.Bc[i] * A.mu[p] * (A.enew[(size_t)p * N + i] - A.enew[(size_t)p * N + i - 1]);
-}
 
 __global__ void __launch_bounds__(256) project_kernel(ProjArgs A)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = A.N, P = A.P;
-    if (t >= (N + 1) * P) return;
-    const int i = t / P, p = t % P;
-    double o;
-    if (i >= 1 && i <= N - 1) o = onew_node(A, i, p);
-    else if (i == 0) o = 2.0 / A.eps * (A.bL[p] - A.enew[(size_t)p * N]) - onew_node(A, 1, p);
-    else o = 2.0 / A.eps * (A.enew[(size_t)p * N + N - 1] - A.bR[p]) - onew_node(A, N - 1, p);
-    A.Oout[(size_t)i * P + p] = o;
-    if (i < N) {
-        A.Eout[(size_t)i * P + p] = A.enew[(size_t)p * N + i];
-        if (A.keep) A.estar_cm[(size_t)i * P + p] = A.estar[(size_t)p * N + i];
+    __shared__ double s_w[256];
+    const int N = A.N, P = A.P, cpb = A.cpb;
+    const int c0 = blockIdx.x * cpb, t = threadIdx.x;
+    const int cl = t / P, p = t - (t / P) * P;
+    const int j = c0 + cl;
+    if (cl < cpb && j < N) {
+        const double mu = A.mu[p];
+        A.Oout[(size_t)j * P + p] = node_any(A.Enew, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, j, p);
+        if (j == N - 1)
+            A.Oout[(size_t)N * P + p] = node_any(A.Enew, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, N, p);
+        if (A.keep) s_w[t] = A.omega[p] * A.Enew[(size_t)j * P + p];
     }
-}
-
-__global__ void __launch_bounds__(256) rho_kernel(int N, int P, const double *E, const double *omega,
-                                                  double *rho)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    double s = 0.0;
-    for (int p = 0; p < P; ++p) s += omega[p] * E[(size_t)j * P + p];
-    rho[j] = s;
-}
-
-__global__ void clear_ints(int *x, int n)
-{
-    const int t = threadIdx.x;
-    if (t < n) x[t] = 0;
+    if (!A.keep) return;
+    __syncthreads();
+    if (t < cpb && c0 + t < N) {
+        double s = 0.0;
+        for (int q = 0; q < P; ++q) s += s_w[t * P + q];
+        A.rho_out[c0 + t] = s;
+    }
 }
 
 __global__ void fill_kernel(double *x, size_t n, double v)
@@ -606,9 +805,13 @@ struct grte_ctx {
     double *E = nullptr, *O = nullptr, *T = nullptr;       // current state
     double *E2 = nullptr, *O2 = nullptr, *T2 = nullptr;    // next state
     double *sigma0, *mu, *omega, *bL, *bR;
-    double *Ll, *Ld, *Lu, *Lam, *LmG, *G, *Bd, *Aw, *Bc, *beta, *Dl, *Dd, *Du, *rho_n;
-    double *r, *v, *res, *estar, *rho, *enew;
-    double *ustar, *Dv, *ostar, *estar_cm, *rho1;
+    double *Ll, *Lu, *Lam, *LmG, *Gt, *Bd, *Aw, *Bc, *beta, *Dl, *Dd, *Du, *rho_n;
+    double *r, *part, *res, *estar_t, *estar, *rho;
+    double *ustar, *Dv, *ostar, *rho1;
+    unsigned long long *flags = nullptr;   // grid-barrier flags of the prediction kernel
+    unsigned long long bar_gen = 0;        // generations used so far (strictly increasing)
+    int cpb = 1;                           // cells per work-group of the per-cell kernels
+    size_t pred_lds = 0;
     int *stat = nullptr;
     // optional stage timing: event pairs recorded on the context stream
     int profiling = 0;
@@ -686,19 +889,25 @@ grte_status prof_end(grte_ctx *ctx, int idx)
 }
 
 template <int M>
+size_t pred_lds_bytes()
+{
+    return (size_t)(4 * NT * M + 3 * NT) * sizeof(double);
+}
+
+template <int M>
 grte_status launch_pred(grte_ctx *ctx, PredArgs &pa)
 {
-    const size_t lds = (size_t)(NT * M + 4 * NT) * sizeof(double);
     void *args[] = {&pa};
     HIPCHK(hipLaunchCooperativeKernel((const void *)pred_kernel<M>, dim3(ctx->pred_grid), dim3(NT),
-                                      args, (unsigned)lds, ctx->stream));
+                                      args, (unsigned)pred_lds_bytes<M>(), ctx->stream));
     return GRTE_OK;
 }
 
 template <int M>
 grte_status launch_corr(grte_ctx *ctx, CorrArgs &ca)
 {
-    hipLaunchKernelGGL(corr_kernel<M>, dim3(ctx->P), dim3(NT), 0, ctx->stream, ca);
+    const size_t lds = (size_t)(2 * NT * M + 3 * NT) * sizeof(double);
+    hipLaunchKernelGGL(corr_kernel<M>, dim3(ctx->P), dim3(NT), lds, ctx->stream, ca);
     HIPCHK(hipGetLastError());
     return GRTE_OK;
 }
@@ -714,7 +923,10 @@ template <int M>
 int coop_blocks_per_cu()
 {
     int nb = 0;
-    const size_t lds = (size_t)(NT * M + 4 * NT) * sizeof(double);
+    const size_t lds = pred_lds_bytes<M>();
+    if (hipFuncSetAttribute((const void *)pred_kernel<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+        return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)pred_kernel<M>, NT, lds) != hipSuccess)
         return 0;
     return nb;
@@ -825,9 +1037,16 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
 
     const size_t N = ctx->N, P = ctx->P;
     grte_status st = GRTE_OK;
-    double **cells[] = {&ctx->T, &ctx->T2, &ctx->sigma0, &ctx->Ll, &ctx->Ld, &ctx->Lu, &ctx->Lam,
-                        &ctx->LmG, &ctx->G, &ctx->Bd, &ctx->beta, &ctx->Dl, &ctx->Dd, &ctx->Du,
-                        &ctx->rho_n, &ctx->res, &ctx->rho, &ctx->ustar, &ctx->Dv, &ctx->rho1};
+    double **cells[] = {&ctx->T, &ctx->T2, &ctx->sigma0, &ctx->Ll, &ctx->Lu, &ctx->Lam,
+                        &ctx->LmG, &ctx->Bd, &ctx->beta, &ctx->Dl, &ctx->Dd, &ctx->Du,
+                        &ctx->rho_n, &ctx->rho, &ctx->ustar, &ctx->Dv, &ctx->rho1};
+    const size_t NP = (size_t)NT * ctx->M;    // padded rows of the solvers
+    double **padded[] = {&ctx->Gt, &ctx->res};
+    for (double **q : padded)
+        if (st == GRTE_OK) st = alloc(ctx, q, NP);
+    double **padded_pairs[] = {&ctx->part, &ctx->estar_t};
+    for (double **q : padded_pairs)
+        if (st == GRTE_OK) st = alloc(ctx, q, NP * P);
     for (double **q : cells)
         if (st == GRTE_OK) st = alloc(ctx, q, N);
     double **nodes[] = {&ctx->Aw, &ctx->Bc};
@@ -836,12 +1055,15 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     double **pairs[] = {&ctx->mu, &ctx->omega, &ctx->bL, &ctx->bR};
     for (double **q : pairs)
         if (st == GRTE_OK) st = alloc(ctx, q, P);
-    double **cp[] = {&ctx->E, &ctx->E2, &ctx->r, &ctx->v, &ctx->estar, &ctx->enew, &ctx->estar_cm};
+    double **cp[] = {&ctx->E, &ctx->E2, &ctx->r, &ctx->estar};
     for (double **q : cp)
         if (st == GRTE_OK) st = alloc(ctx, q, N * P);
     double **np[] = {&ctx->O, &ctx->O2, &ctx->ostar};
     for (double **q : np)
         if (st == GRTE_OK) st = alloc(ctx, q, (N + 1) * P);
+    double *flagmem = nullptr;
+    if (st == GRTE_OK) st = alloc(ctx, &flagmem, (size_t)MAX_P * BAR_STRIDE);
+    ctx->flags = (unsigned long long *)flagmem;
     if (st == GRTE_OK && hipMalloc((void **)&ctx->stat, 8 * sizeof(int)) != hipSuccess) st = GRTE_E_NOMEM;
     if (st != GRTE_OK) { grte_destroy(ctx); return st; }
 
@@ -858,7 +1080,13 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
         grte_destroy(ctx);
         return GRTE_E_HIP;
     }
-    ctx->pred_grid = std::min(ctx->P, nb * ncu);
+    // one work-group per parity pair, all co-resident
+    if (nb * ncu < ctx->P) {
+        grte_destroy(ctx);
+        return GRTE_E_UNSUPPORTED;
+    }
+    ctx->pred_grid = ctx->P;
+    ctx->cpb = std::max(1, 256 / ctx->P);
 
     if (hipMemcpy(ctx->mu, mu, P * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ctx->omega, omega, P * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
@@ -873,6 +1101,12 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     hipLaunchKernelGGL(fill_kernel, dim3((N + b - 1) / b), dim3(b), 0, nullptr, ctx->sigma0, N, 1.0);
     hipLaunchKernelGGL(fill_kernel, dim3((P + b - 1) / b), dim3(b), 0, nullptr, ctx->bL, P, 0.0);
     hipLaunchKernelGGL(fill_kernel, dim3((P + b - 1) / b), dim3(b), 0, nullptr, ctx->bR, P, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3((MAX_P * BAR_STRIDE + b - 1) / b), dim3(b), 0, nullptr, flagmem,
+                       (size_t)MAX_P * BAR_STRIDE, 0.0);   // all-zero bits: generation 0
+    // padded rows of the position-ordered arrays stay zero
+    const size_t npad = (size_t)NT * ctx->M;
+    hipLaunchKernelGGL(fill_kernel, dim3((npad + b - 1) / b), dim3(b), 0, nullptr, ctx->Gt, npad, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3((npad + b - 1) / b), dim3(b), 0, nullptr, ctx->res, npad, 0.0);
     if (hipDeviceSynchronize() != hipSuccess) { grte_destroy(ctx); return GRTE_E_HIP; }
     *out = ctx;
     return GRTE_OK;
@@ -940,7 +1174,7 @@ grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device)
     if (!ctx || !out) return GRTE_E_INVAL;
     const size_t N = ctx->N, P = ctx->P;
     switch (stage) {
-    case GRTE_STAGE_ESTAR: return copy_out(ctx, out, ctx->estar_cm, N * P, on_device);
+    case GRTE_STAGE_ESTAR: return copy_out(ctx, out, ctx->estar, N * P, on_device);
     case GRTE_STAGE_OSTAR: return copy_out(ctx, out, ctx->ostar, (N + 1) * P, on_device);
     case GRTE_STAGE_USTAR: return copy_out(ctx, out, ctx->ustar, N, on_device);
     case GRTE_STAGE_D: return copy_out(ctx, out, ctx->Dv, N, on_device);
@@ -953,33 +1187,36 @@ grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info
 {
     if (!ctx || !(dt > 0) || !(eps > 0) || !std::isfinite(dt) || !std::isfinite(eps)) return GRTE_E_INVAL;
     const int N = ctx->N, P = ctx->P;
-    const unsigned b = 256;
     const double dx = ctx->L / N;
+    const unsigned ncb = (unsigned)((N + ctx->cpb - 1) / ctx->cpb);   // work-groups of the per-cell kernels
     int ev_step = -1, ev_pred = -1;
     grte_status st = prof_begin(ctx, GRTE_TIMING_STEP, &ev_step);
     if (st != GRTE_OK) return st;
-    hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, ctx->stream, ctx->stat, 8);
 
-    // ---- coefficients of the prediction (K from T^n)
+    // ---- coefficients of the prediction (K from T^n); also clears the step counters
     CoefArgs ca{};
-    ca.N = N; ca.P = P; ca.m = ctx->m; ca.mode = 0;
+    ca.N = N; ca.P = P; ca.m = ctx->m; ca.mode = 0; ca.cpb = ctx->cpb;
     ca.a = ctx->a; ca.c = ctx->c; ca.cv = ctx->cv; ca.eps = eps; ca.dt = dt; ca.dx = dx;
     ca.T = ctx->T; ca.Tn = ctx->T; ca.sigma0 = ctx->sigma0; ca.mu = ctx->mu; ca.omega = ctx->omega;
     ca.bL = ctx->bL; ca.bR = ctx->bR; ca.E = ctx->E; ca.O = ctx->O;
     ca.mu1 = ctx->mu1; ca.mu2 = ctx->mu2;
-    ca.Ll = ctx->Ll; ca.Ld = ctx->Ld; ca.Lu = ctx->Lu; ca.Lam = ctx->Lam; ca.LmG = ctx->LmG; ca.G = ctx->G;
+    ca.Ll = ctx->Ll; ca.Lu = ctx->Lu; ca.Lam = ctx->Lam; ca.LmG = ctx->LmG; ca.Gt = ctx->Gt; ca.M = ctx->M;
     ca.Bd = ctx->Bd; ca.Aw = ctx->Aw; ca.Bc = ctx->Bc; ca.beta = ctx->beta;
     ca.Dl = ctx->Dl; ca.Dd = ctx->Dd; ca.Du = ctx->Du; ca.rho_n = ctx->rho_n; ca.r = ctx->r;
-    hipLaunchKernelGGL(coef_kernel, dim3((N + 1 + b - 1) / b), dim3(b), 0, ctx->stream, ca);
+    ca.stat = ctx->stat;
+    hipLaunchKernelGGL(coef_kernel, dim3(ncb), dim3(256), 0, ctx->stream, ca);
     HIPCHK(hipGetLastError());
 
     // ---- prediction
     PredArgs pa{};
     pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
-    pa.Ll = ctx->Ll; pa.Ld = ctx->Ld; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.G = ctx->G;
-    pa.Bd = ctx->Bd; pa.Dl = ctx->Dl; pa.Dd = ctx->Dd; pa.Du = ctx->Du;
+    pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
+    pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
     pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
-    pa.v = ctx->v; pa.res = ctx->res; pa.estar = ctx->estar; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
+    pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->estar_t; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
+    pa.flags = ctx->flags;
+    pa.gen0 = ctx->bar_gen;
+    ctx->bar_gen += 2ull * (unsigned long long)ctx->pred_maxit + 4ull;   // never reused
     if ((st = prof_begin(ctx, GRTE_TIMING_PREDICT, &ev_pred)) != GRTE_OK) return st;
     switch (ctx->M) {
     case 2: st = launch_pred<2>(ctx, pa); break;
@@ -992,23 +1229,27 @@ grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info
 
     // ---- correction substep 1
     NewtonArgs na{};
-    na.N = N; na.P = P; na.m = ctx->m; na.maxit = ctx->newton_maxit; na.keep = ctx->keep;
+    na.N = N; na.P = P; na.m = ctx->m; na.maxit = ctx->newton_maxit; na.keep = ctx->keep; na.cpb = ctx->cpb;
+    na.M = ctx->M; na.estar_t = ctx->estar_t; na.Ecm = ctx->estar;
     na.a = ctx->a; na.c = ctx->c; na.cv = ctx->cv; na.eps = eps; na.dt = dt; na.dx = dx;
-    na.estar = ctx->estar; na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
+    na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
     na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;
     na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
     na.ostar = ctx->ostar; na.stat = ctx->stat;
-    hipLaunchKernelGGL(newton_kernel, dim3((N + b - 1) / b), dim3(b), 0, ctx->stream, na);
+    hipLaunchKernelGGL(gather_estar_kernel, dim3((unsigned)(((size_t)N * P + 255) / 256)), dim3(256), 0,
+                       ctx->stream, na);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(newton_kernel, dim3(ncb), dim3(256), 0, ctx->stream, na);
     HIPCHK(hipGetLastError());
 
-    // ---- correction substep 2 (K from T^{n+1})
+    // ---- correction substep 2 (K from T^{n+1}): E^{n+1} straight into the next state
     ca.mode = 1;
     ca.T = ctx->T2;
-    hipLaunchKernelGGL(coef_kernel, dim3((N + 1 + b - 1) / b), dim3(b), 0, ctx->stream, ca);
+    hipLaunchKernelGGL(coef_kernel, dim3(ncb), dim3(256), 0, ctx->stream, ca);
     HIPCHK(hipGetLastError());
     CorrArgs cc{};
-    cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Ld = ctx->Ld; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
-    cc.r = ctx->r; cc.mu = ctx->mu; cc.enew = ctx->enew;
+    cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
+    cc.r = ctx->r; cc.mu = ctx->mu; cc.Enew = ctx->E2;
     switch (ctx->M) {
     case 2: st = launch_corr<2>(ctx, cc); break;
     case 4: st = launch_corr<4>(ctx, cc); break;
@@ -1017,19 +1258,14 @@ grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info
     }
     if (st != GRTE_OK) return st;
 
-    // ---- projection
+    // ---- projection: O^{n+1} at the nodes, rho^{n+1}
     ProjArgs pj{};
-    pj.N = N; pj.P = P; pj.eps = eps; pj.enew = ctx->enew; pj.O = ctx->O; pj.Aw = ctx->Aw; pj.Bc = ctx->Bc;
-    pj.mu = ctx->mu; pj.omega = ctx->omega; pj.bL = ctx->bL; pj.bR = ctx->bR; pj.estar = ctx->estar;
-    pj.Eout = ctx->E2; pj.Oout = ctx->O2; pj.rho_out = ctx->rho1; pj.estar_cm = ctx->estar_cm; pj.keep = ctx->keep;
-    const size_t nt = (size_t)(N + 1) * P;
-    hipLaunchKernelGGL(project_kernel, dim3((unsigned)((nt + b - 1) / b)), dim3(b), 0, ctx->stream, pj);
+    pj.N = N; pj.P = P; pj.keep = ctx->keep; pj.cpb = ctx->cpb; pj.eps = eps;
+    pj.Enew = ctx->E2; pj.O = ctx->O; pj.Aw = ctx->Aw; pj.Bc = ctx->Bc;
+    pj.mu = ctx->mu; pj.omega = ctx->omega; pj.bL = ctx->bL; pj.bR = ctx->bR;
+    pj.Oout = ctx->O2; pj.rho_out = ctx->rho1;
+    hipLaunchKernelGGL(project_kernel, dim3(ncb), dim3(256), 0, ctx->stream, pj);
     HIPCHK(hipGetLastError());
-    if (ctx->keep) {
-        hipLaunchKernelGGL(rho_kernel, dim3((N + b - 1) / b), dim3(b), 0, ctx->stream, N, P, ctx->E2,
-                           ctx->omega, ctx->rho1);
-        HIPCHK(hipGetLastError());
-    }
     if ((st = prof_end(ctx, ev_step)) != GRTE_OK) return st;   // whole step
     std::swap(ctx->E, ctx->E2);
     std::swap(ctx->O, ctx->O2);
@@ -1045,6 +1281,8 @@ grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info
         info->newton_failed = h[3];
         info->kstar_clamped = h[4];
         info->negative_root = h[5];
+        info->sync_error = h[6];
+        if (h[6]) return GRTE_E_HIP;
         if (!h[1] || h[3]) return GRTE_E_NOCONV;
     }
     return GRTE_OK;
