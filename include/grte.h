@@ -147,6 +147,80 @@ grte_status grte_read_timing(grte_ctx *ctx, double *total_ms, int *count);
 /* Static text for a status code. */
 const char *grte_status_string(grte_status s);
 
+/* ------------------------------------------------------------------------
+ * Batched slabs: many independent 1-D problems of the kind above, each with
+ * its own N, P, opacity law, eps and dt, advanced together by one persistent
+ * kernel per step (one tile of 256 or 64 threads per instance, instances
+ * taken from a device work queue in longest-first order).  Each instance
+ * computes exactly the step of grte_step (Algorithm 2).
+ *
+ * Packed layouts: instances are concatenated in the order given at creation.
+ * For instance i with N_i cells and P_i pairs, its block starts at
+ *   cells:  sum_{k<i} N_k            (T, sigma0)
+ *   E:      sum_{k<i} N_k P_k        (E[j*P_i + p] inside the block)
+ *   O:      sum_{k<i} (N_k + 1) P_k  (O[i*P_i + p] inside the block)
+ *   pairs:  sum_{k<i} P_k            (mu, omega, inflow data)
+ * grte_batch_sizes returns the four totals.  Limits: 2 <= N_i <= 2048,
+ * 1 <= P_i <= 64.  The other conventions are those of the single context.
+ * ------------------------------------------------------------------------ */
+typedef struct grte_batch grte_batch;
+
+typedef struct grte_instance {
+    int nx;            /* cells N_i                                             */
+    int npairs;        /* parity pairs P_i                                      */
+    int opacity_law;   /* 0 or 3, as grte_problem.opacity_law                   */
+    double length, a, c, cv;
+    double dt, eps;    /* time step and eps of this instance (fixed)            */
+} grte_instance;
+
+typedef struct grte_batch_info {   /* per instance, as grte_step_info         */
+    int pred_iters, pred_converged, newton_max_iters, newton_failed;
+    int kstar_clamped, negative_root;
+} grte_batch_info;
+
+typedef struct grte_batch_tuning {
+    int wave_max_n;    /* instances with N <= wave_max_n (<= 256) run on one
+                          wavefront, the others on a 256-thread work-group    */
+    int grid;          /* work-groups of the persistent launch                 */
+    double step_ms;    /* filled by grte_batch_tune: time of one step          */
+} grte_batch_tuning;
+
+/* Create a batch of n instances; mu/omega are packed per-instance velocity
+ * grids (P_i entries each, mu > 0, omega > 0).  State zero, opacity one,
+ * inflow zero until set.  Returns GRTE_E_UNSUPPORTED beyond the limits. */
+grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu,
+                              const double *omega, grte_batch **out);
+grte_status grte_batch_destroy(grte_batch *b);
+/* Totals of the packed layouts (any pointer may be NULL). */
+grte_status grte_batch_sizes(const grte_batch *b, long long *cells, long long *e_len,
+                             long long *o_len, long long *pairs);
+grte_status grte_batch_set_stream(grte_batch *b, void *hip_stream);
+grte_status grte_batch_set_solver(grte_batch *b, double pred_tol, int pred_maxit, int newton_maxit);
+/* Packed sigma0[cells]; packed inflow b_left[pairs], b_right[pairs] (host). */
+grte_status grte_batch_set_opacity(grte_batch *b, const double *sigma0, int on_device);
+grte_status grte_batch_set_inflow(grte_batch *b, const double *b_left, const double *b_right);
+/* Packed state E[e_len], O[o_len], T[cells] in and out. */
+grte_status grte_batch_set_state(grte_batch *b, const double *E, const double *O,
+                                 const double *T, int on_device);
+grte_status grte_batch_get_state(grte_batch *b, double *E, double *O, double *T, int on_device);
+/* One step of every instance.  info == NULL: enqueue only; otherwise
+ * synchronise and fill info[n]; GRTE_E_NOCONV if any instance hit a cap. */
+grte_status grte_batch_step(grte_batch *b, grte_batch_info *info);
+/* Autotuner: times `trials` steps for each candidate (wavefront threshold
+ * 0/128/256 x grid of 1, 2, ... work-groups per compute unit) from the
+ * current state without changing it, orders the instances by the measured
+ * work (iterations x N x P, largest first) and keeps the fastest choice. */
+grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best);
+grte_status grte_batch_set_tuning(grte_batch *b, const grte_batch_tuning *t);
+grte_status grte_batch_get_tuning(const grte_batch *b, grte_batch_tuning *t);
+/* on != 0: every step replays a captured HIP graph (one per state-buffer
+ * parity, captured at first use and after any change of tuning or solver). */
+grte_status grte_batch_use_graph(grte_batch *b, int on);
+/* Event timing of whole steps on the batch stream (as grte_set_profiling /
+ * grte_read_timing, one stage). */
+grte_status grte_batch_set_profiling(grte_batch *b, int on);
+grte_status grte_batch_read_timing(grte_batch *b, double *total_ms, int *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,7 +3,8 @@ radiative transfer equation (Tang, Wang & Zhang, arXiv 1811.05579, Algorithm 2
 and Section 5).
 
 The Python layer only marshals arguments into the C ABI of include/grte.h;
-every stage of the step runs in the HIP kernels of csrc/grte.hip.  Arrays may
+every stage of the step runs in the HIP kernels of csrc/grte.hip (one
+slab) and csrc/batch.hip (many slabs in one persistent launch).  Arrays may
 be numpy arrays (host memory, copied by the library) or torch CUDA tensors
 (device memory, borrowed for the call).
 """
@@ -12,9 +13,9 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import GrteError, Problem, StepInfo, check, load
+from ._lib import BatchInfo, BatchTuning, GrteError, Instance, Problem, StepInfo, check, load
 
-__all__ = ["Grte", "GrteError", "gauss_legendre", "load"]
+__all__ = ["Grte", "GrteBatch", "GrteError", "gauss_legendre", "load"]
 
 
 def gauss_legendre(nv):
@@ -151,3 +152,130 @@ class Grte:
             return d
         check("grte_step", self._lib.grte_step(self._h, float(dt), float(eps), None))
         return None
+
+
+class GrteBatch:
+    """Many independent slabs advanced by one persistent launch per step.
+
+    `members` is a sequence of objects with attributes N, P, m, L, a, c, Cv,
+    dt, eps, mu, omega (e.g. workloads.Workload); arrays are exchanged in the
+    packed layout of include/grte.h (instances concatenated in order)."""
+
+    def __init__(self, members):
+        self._lib = load()
+        n = len(members)
+        arr = (Instance * n)()
+        for i, w in enumerate(members):
+            arr[i] = Instance(int(w.N), int(w.P), int(w.m), float(w.L), float(w.a), float(w.c),
+                              float(w.Cv), float(w.dt), float(w.eps))
+        mu = np.ascontiguousarray(np.concatenate([w.mu for w in members]), dtype=np.float64)
+        om = np.ascontiguousarray(np.concatenate([w.omega for w in members]), dtype=np.float64)
+        h = ctypes.c_void_p()
+        check("grte_batch_create", self._lib.grte_batch_create(n, arr, mu.ctypes.data, om.ctypes.data,
+                                                               ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self.Ns = [int(w.N) for w in members]
+        self.Ps = [int(w.P) for w in members]
+        tot = [ctypes.c_longlong() for _ in range(4)]
+        check("grte_batch_sizes", self._lib.grte_batch_sizes(self._h, *[ctypes.byref(t) for t in tot]))
+        self.n_cells, self.n_E, self.n_O, self.n_pairs = (int(t.value) for t in tot)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.grte_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        raw = getattr(stream, "cuda_stream", stream)
+        check("grte_batch_set_stream", self._lib.grte_batch_set_stream(self._h, ctypes.c_void_p(int(raw))))
+
+    def set_solver(self, pred_tol=1e-15, pred_maxit=200, newton_maxit=100):
+        check("grte_batch_set_solver", self._lib.grte_batch_set_solver(
+            self._h, float(pred_tol), int(pred_maxit), int(newton_maxit)))
+
+    def set_opacity(self, sigma0):
+        p, dev = _ptr(sigma0, self.n_cells, "sigma0")
+        check("grte_batch_set_opacity", self._lib.grte_batch_set_opacity(self._h, _addr(p), dev))
+
+    def set_inflow(self, b_left, b_right):
+        bl = np.ascontiguousarray(b_left, dtype=np.float64)
+        br = np.ascontiguousarray(b_right, dtype=np.float64)
+        if bl.size != self.n_pairs or br.size != self.n_pairs:
+            raise ValueError("inflow arrays need one entry per pair of every instance")
+        check("grte_batch_set_inflow", self._lib.grte_batch_set_inflow(self._h, bl.ctypes.data,
+                                                                       br.ctypes.data))
+
+    def set_state(self, E, O, T):
+        pe, d1 = _ptr(E, self.n_E, "E")
+        po, d2 = _ptr(O, self.n_O, "O")
+        pt, d3 = _ptr(T, self.n_cells, "T")
+        if not (d1 == d2 == d3):
+            raise ValueError("E, O, T must all be host arrays or all device tensors")
+        check("grte_batch_set_state", self._lib.grte_batch_set_state(self._h, _addr(pe), _addr(po),
+                                                                     _addr(pt), d1))
+
+    def get_state(self):
+        """Packed (E, O, T) as numpy arrays."""
+        E = np.empty(self.n_E)
+        O = np.empty(self.n_O)
+        T = np.empty(self.n_cells)
+        check("grte_batch_get_state", self._lib.grte_batch_get_state(self._h, E.ctypes.data, O.ctypes.data,
+                                                                     T.ctypes.data, 0))
+        return E, O, T
+
+    def split(self, E, O, T):
+        """Per-instance views (E (N,P), O (N+1,P), T (N,)) of packed arrays."""
+        out, oe, oo, ot = [], 0, 0, 0
+        for N, P in zip(self.Ns, self.Ps):
+            out.append((E[oe:oe + N * P].reshape(N, P), O[oo:oo + (N + 1) * P].reshape(N + 1, P),
+                        T[ot:ot + N]))
+            oe += N * P
+            oo += (N + 1) * P
+            ot += N
+        return out
+
+    def step(self, info=False):
+        """One step of every instance; with info=True synchronise and return
+        (status, list of per-instance dicts)."""
+        if not info:
+            check("grte_batch_step", self._lib.grte_batch_step(self._h, None))
+            return None
+        arr = (BatchInfo * self.n)()
+        st = self._lib.grte_batch_step(self._h, arr)
+        if st not in (0, -4):
+            check("grte_batch_step", st)
+        return st, [{k: getattr(a, k) for k, _ in BatchInfo._fields_} for a in arr]
+
+    def tune(self, trials=2):
+        t = BatchTuning()
+        check("grte_batch_tune", self._lib.grte_batch_tune(self._h, int(trials), ctypes.byref(t)))
+        return {"wave_max_n": t.wave_max_n, "grid": t.grid, "step_ms": t.step_ms}
+
+    def set_tuning(self, wave_max_n, grid):
+        t = BatchTuning(int(wave_max_n), int(grid), 0.0)
+        check("grte_batch_set_tuning", self._lib.grte_batch_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = BatchTuning()
+        check("grte_batch_get_tuning", self._lib.grte_batch_get_tuning(self._h, ctypes.byref(t)))
+        return {"wave_max_n": t.wave_max_n, "grid": t.grid}
+
+    def use_graph(self, on=True):
+        check("grte_batch_use_graph", self._lib.grte_batch_use_graph(self._h, int(bool(on))))
+
+    def set_profiling(self, on=True):
+        check("grte_batch_set_profiling", self._lib.grte_batch_set_profiling(self._h, int(bool(on))))
+
+    def read_timing(self):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int()
+        check("grte_batch_read_timing", self._lib.grte_batch_read_timing(self._h, ctypes.byref(ms),
+                                                                         ctypes.byref(cnt)))
+        return float(ms.value), int(cnt.value)

@@ -29,6 +29,23 @@ class StepInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("npairs", c_int), ("opacity_law", c_int), ("length", c_double),
+                ("a", c_double), ("c", c_double), ("cv", c_double), ("dt", c_double),
+                ("eps", c_double)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
+                ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("wave_max_n", c_int), ("grid", c_int), ("step_ms", c_double)]
+
+
+c_ll_p = ctypes.POINTER(ctypes.c_longlong)
+
 _SIGS = {
     "grte_gauss_legendre": (c_int, [c_int, c_void_p, c_void_p]),
     "grte_create": (c_int, [ctypes.POINTER(Problem), c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
@@ -44,6 +61,23 @@ _SIGS = {
     "grte_set_profiling": (c_int, [c_void_p, c_int]),
     "grte_read_timing": (c_int, [c_void_p, c_void_p, c_void_p]),
     "grte_status_string": (ctypes.c_char_p, [c_int]),
+    "grte_batch_create": (c_int, [c_int, ctypes.POINTER(Instance), c_void_p, c_void_p,
+                                  ctypes.POINTER(c_void_p)]),
+    "grte_batch_destroy": (c_int, [c_void_p]),
+    "grte_batch_sizes": (c_int, [c_void_p, c_ll_p, c_ll_p, c_ll_p, c_ll_p]),
+    "grte_batch_set_stream": (c_int, [c_void_p, c_void_p]),
+    "grte_batch_set_solver": (c_int, [c_void_p, c_double, c_int, c_int]),
+    "grte_batch_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
+    "grte_batch_set_inflow": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "grte_batch_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "grte_batch_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "grte_batch_step": (c_int, [c_void_p, ctypes.POINTER(BatchInfo)]),
+    "grte_batch_tune": (c_int, [c_void_p, c_int, ctypes.POINTER(BatchTuning)]),
+    "grte_batch_set_tuning": (c_int, [c_void_p, ctypes.POINTER(BatchTuning)]),
+    "grte_batch_get_tuning": (c_int, [c_void_p, ctypes.POINTER(BatchTuning)]),
+    "grte_batch_use_graph": (c_int, [c_void_p, c_int]),
+    "grte_batch_set_profiling": (c_int, [c_void_p, c_int]),
+    "grte_batch_read_timing": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
 }
 
 _lib = None

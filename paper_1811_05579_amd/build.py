@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "grte.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("grte.hip", "batch.hip")]
 OUT = os.path.join(HERE, "libgrte.so")
 
 HIPCC_FLAGS = [
@@ -15,10 +15,10 @@ HIPCC_FLAGS = [
 
 
 def build(verbose=False):
-    """Compile csrc/grte.hip into libgrte.so (always recompiles)."""
+    """Compile the HIP sources under csrc/ into libgrte.so (always recompiles)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = OUT + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp, SRC]
+    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + SRCS
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

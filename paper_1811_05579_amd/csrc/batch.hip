@@ -1,0 +1,1015 @@
+// batch.hip -- batched form of the AP step: many independent 1-D slabs of
+// different size, ordinate count, eps, dt and opacity advanced by one
+// persistent launch per step (the grte_batch_* calls of include/grte.h).
+//
+// Every instance is advanced by one "tile": a whole work-group (W = 256
+// threads) or, for small slabs, one wavefront (W = 64; four independent
+// instances per work-group).  Inside a tile the step is the algebra of the
+// single-instance path (Algorithm 2 and Section 5 of Tang, Wang & Zhang):
+// the per-pair tridiagonal operators T_p = Lam + mu_p^2 L + mu_p B with U*
+// eliminated through (4.5c), the angular coupling of the prediction solved by
+// Richardson iteration with diffusion-synthetic acceleration in residual form,
+// Newton on (4.13)/(5.5), the per-pair correction (4.11) and the projection
+// (4.14).  One tile owns all parity pairs of its instance, so the angular sum
+// is accumulated in registers and no grid-wide synchronisation exists.
+// Instances are taken from two work queues -- work-group tiles first, then
+// wavefront tiles -- in an order chosen by the host (longest expected work
+// first), so that work-groups that finish their large slabs early drain the
+// small ones.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/grte.h"
+#include "solver_common.hpp"
+
+namespace {
+
+constexpr int BNT = 256;              // threads per work-group
+constexpr int WAVE = 64;
+constexpr int BMAX_N = 2048;          // largest slab of the batched path (8 rows per thread)
+constexpr int BMAX_P = 64;
+constexpr int WAVE_MAX_N = 256;       // largest slab a wavefront tile can take (4 rows per lane)
+
+// per-instance cell scratch: NCA arrays of N+1 entries
+enum {
+    C_AW, C_BC, C_LL, C_LU, C_LAM, C_LMG, C_G, C_BD, C_DD, C_BETA, C_RHON, C_H, C_AWR, C_AWL,
+    C_SRC, C_KEPS, C_USTAR, C_D, C_TNEW, NCA
+};
+
+// LDS of one tile (doubles): rho, Ll, Lu in position order + 3 W scratch
+constexpr int LDS_WG = 3 * BMAX_N + 3 * BNT;
+constexpr int LDS_WAVE = 3 * WAVE_MAX_N + 3 * WAVE;
+static_assert(4 * LDS_WAVE <= LDS_WG, "four wavefront tiles fit in the work-group LDS");
+
+struct BInst {
+    int N, P, m, W, M;                 // tile of W threads, M rows each
+    int pad;
+    double dx, a, c, cv, eps, dt;
+    double one_minus_W, mu1, mu2;      // 1 - sum omega (exact), sum omega mu, sum omega mu^2
+    long long oE, oO, oT, oP;          // offsets of E (N P), O ((N+1) P), cells (N), pairs (P)
+    long long oC, oR, NPa;             // cell scratch, pair scratch (2 P NPa), padded rows allocated
+};
+
+struct BatchArgs {
+    int n_wg, n_wave;
+    const BInst *inst;
+    const int *order;                  // n_wg work-group instances, then n_wave wavefront instances
+    int *queue;                        // [0] work-group queue head, [1] wavefront queue head
+    const double *E, *O, *T, *sigma0;
+    double *E2, *O2, *T2;
+    const double *mu, *omega, *bL, *bR;
+    double *cells, *pairs;
+    int *istat;                        // 8 per instance
+    double tol;
+    int maxit, newton_maxit;
+};
+
+// make the tile's LDS and global writes visible to the whole tile
+template <int W>
+__device__ __forceinline__ void tsync()
+{
+    if constexpr (W == BNT) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
+__device__ __forceinline__ int bpos(int j, int W, int M) { return (j % M) * W + j / M; }
+
+// interior node i (1..N-1): harmonic-mean sigma, arithmetic-mean K
+__device__ __forceinline__ void b_node(const BInst &I, const double *Tk, const double *sg, int i,
+                                       double &aw, double &bc)
+{
+    const double Kn = 0.5 * (kpow(Tk[i - 1], I.m) + kpow(Tk[i], I.m));
+    const double sl = sg[i - 1], sr = sg[i];
+    const double ss = sl + sr;
+    const double sn = ss > 0.0 ? 2.0 * sl * sr / ss : 0.0;
+    const double den = Kn * I.eps * I.eps + sn * I.c * I.dt;
+    if (den > 0.0) {
+        aw = Kn * I.eps * I.eps / den;
+        bc = Kn * I.c * I.dt / (I.dx * den);
+    } else {
+        aw = 0.0;
+        bc = 0.0;
+    }
+}
+
+// per-cell coefficients of cell j; mode 0: prediction (K from T^n, with the
+// U* elimination of (4.5c)), mode 1: correction (K from T^{n+1})
+__device__ void b_cell(const BInst &I, int mode, const double *Tk, const double *Tn, const double *sg,
+                       int j, double *C, int N1)
+{
+    const int N = I.N;
+    const double eps = I.eps, c = I.c, dt = I.dt;
+    double awl = 0.0, bcl = 0.0, awr = 0.0, bcr = 0.0;
+    if (j >= 1) b_node(I, Tk, sg, j, awl, bcl);
+    if (j <= N - 2) b_node(I, Tk, sg, j + 1, awr, bcr);
+    C[C_AW * N1 + j] = awl;
+    C[C_BC * N1 + j] = bcl;
+    if (j == N - 1) {
+        C[C_AW * N1 + N] = 0.0;
+        C[C_BC * N1 + N] = 0.0;
+    }
+    const double Kc = kpow(Tk[j], I.m);
+    const double s0 = sg[j];
+    const double h = Kc * eps * eps * c * dt / I.dx;
+    const double fr = (j <= N - 2) ? h * bcr * (j == 0 ? 2.0 : 1.0) : 0.0;
+    const double fl = (j >= 1) ? h * bcl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+    const double bd = (j == 0 || j == N - 1) ? 2.0 * h / eps : 0.0;
+    C[C_LL * N1 + j] = -fl;
+    C[C_LU * N1 + j] = -fr;
+    C[C_BD * N1 + j] = bd;
+    C[C_LAM * N1 + j] = Kc * eps * eps + s0 * c * dt;
+    C[C_H * N1 + j] = h;
+    C[C_AWR * N1 + j] = (j <= N - 2) ? awr * (j == 0 ? 2.0 : 1.0) : 0.0;
+    C[C_AWL * N1 + j] = (j >= 1) ? awl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+    C[C_KEPS * N1 + j] = Kc * eps * eps;
+    const double ac = I.a * c;
+    if (mode == 0) {
+        const double t = Tn[j];
+        const double Un = t * t * t * t;
+        const double t3m = (I.m == 0) ? t * t * t : 1.0;
+        const double beta = 4.0 * s0 * dt * t3m / (eps * eps * I.cv);
+        const double opb = 1.0 + ac * beta;
+        const double lmg = Kc * eps * eps + s0 * c * dt / opb;
+        C[C_BETA * N1 + j] = beta;
+        C[C_LMG * N1 + j] = lmg;
+        C[C_G * N1 + j] = s0 * c * dt * (ac * beta) / opb;
+        C[C_DD * N1 + j] = lmg + I.mu2 * (fl + fr) + I.mu1 * bd;
+        C[C_SRC * N1 + j] = s0 * c * dt * ac * Un / opb;
+    } else {
+        const double t1 = Tk[j];
+        C[C_SRC * N1 + j] = s0 * c * dt * ac * (t1 * t1 * t1 * t1);
+    }
+}
+
+// right-hand sides of the per-pair systems into Rt (pair-major, position order)
+template <int W, int M>
+__device__ void b_rhs(const BInst &I, const double *C, int N1, const double *E, const double *O,
+                      const double *mu, const double *bL, const double *bR, double *Rt)
+{
+    constexpr int NP = W * M;
+    const int N = I.N, P = I.P;
+    const int k = tile_lane<W>();
+    for (int idx = k; idx < N * P; idx += W) {
+        const int j = idx / P, p = idx - (idx / P) * P;
+        const double h = C[C_H * N1 + j];
+        const double On_r = (j <= N - 2) ? O[(size_t)(j + 1) * P + p] : 0.0;
+        const double On_l = (j >= 1) ? O[(size_t)j * P + p] : 0.0;
+        double rv = C[C_KEPS * N1 + j] * E[idx] + C[C_SRC * N1 + j]
+                  - h * mu[p] * (C[C_AWR * N1 + j] * On_r - C[C_AWL * N1 + j] * On_l);
+        if (j == 0) rv += 2.0 * h * mu[p] * bL[p] / I.eps;
+        if (j == N - 1) rv += 2.0 * h * mu[p] * bR[p] / I.eps;
+        Rt[(size_t)p * NP + bpos(j, W, M)] = rv;
+    }
+}
+
+template <int W, int M>
+__device__ void run_instance(const BatchArgs &A, int i, double *sm)
+{
+    constexpr int NP = W * M;
+    const BInst I = A.inst[i];
+    const int N = I.N, P = I.P, N1 = N + 1;
+    const int k = tile_lane<W>();
+    const int j0 = k * M;
+    const double eps = I.eps;
+    const double *E = A.E + I.oE, *O = A.O + I.oO, *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
+    const double *mu = A.mu + I.oP, *om = A.omega + I.oP, *bL = A.bL + I.oP, *bR = A.bR + I.oP;
+    double *E2 = A.E2 + I.oE, *O2 = A.O2 + I.oO, *T2 = A.T2 + I.oT;
+    double *C = A.cells + I.oC;
+    double *Rt = A.pairs + I.oR;                  // right-hand sides, pair-major position order
+    double *Et = Rt + (size_t)P * I.NPa;          // E*, pair-major position order
+    int *st = A.istat + 8 * i;
+    double *rho = sm, *sLl = sm + NP, *sLu = sm + 2 * NP, *sh = sm + 3 * NP;
+
+    // ---------------- coefficients of the prediction (K from T^n) and rho^n
+    for (int j = k; j < N; j += W) {
+        b_cell(I, 0, Tn, Tn, sg, j, C, N1);
+        double rn = 0.0;
+        for (int p = 0; p < P; ++p) rn += om[p] * E[(size_t)j * P + p];
+        C[C_RHON * N1 + j] = rn;
+    }
+    tsync<W>();
+    b_rhs<W, M>(I, C, N1, E, O, mu, bL, bR, Rt);
+    for (int j = k; j < NP; j += W) {
+        const int t = bpos(j, W, M);
+        const bool in = j < N;
+        rho[t] = in ? C[C_RHON * N1 + j] : 0.0;
+        sLl[t] = in ? C[C_LL * N1 + j] : 0.0;
+        sLu[t] = in ? C[C_LU * N1 + j] : 0.0;
+    }
+    tsync<W>();
+    const double bd0 = C[C_BD * N1 + 0], bdN = C[C_BD * N1 + N - 1];
+
+    // ---------------- prediction: Richardson iteration with diffusion acceleration
+    double lam[M], lmg[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int j = j0 + r;
+        const bool in = j < N;
+        lam[r] = in ? C[C_LAM * N1 + j] : 1.0;
+        lmg[r] = in ? C[C_LMG * N1 + j] : 0.0;
+    }
+    int it = 0, converged = 0;
+    while (true) {
+        double acc[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[r] = 0.0;
+        for (int p = 0; p < P; ++p) {
+            // v_p = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho]
+            const double m1 = mu[p], m2 = m1 * m1, wp = om[p];
+            const double *rp = Rt + (size_t)p * NP;
+            double b[M], y[M], v[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const int j = j0 + r;
+                const int t = r * W + k;
+                if (j < N) {
+                    const double ll = sLl[t], lu = sLu[t];
+                    const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
+                    b[r] = lam[r] + m2 * (-(ll + lu)) + m1 * bdj;
+                    const double rj = rho[t];
+                    double rl = 0.0, rn = 0.0;
+                    if (j > 0) rl = (r > 0) ? rho[t - W] : rho[(M - 1) * W + k - 1];
+                    if (j < N - 1) rn = (r < M - 1) ? rho[t + W] : rho[k + 1];
+                    const double q = -(ll + lu) * rj + ll * rl + lu * rn;
+                    y[r] = rp[t] - lmg[r] * rj - m2 * q - m1 * bdj * rj;
+                } else {
+                    b[r] = 1.0;
+                    y[r] = 0.0;
+                }
+            }
+            TriFac<W, M> Ft;
+            tri_factor<W, M>(m2, sLl, sLu, b, Ft, sh);
+            tri_solve<W, M>(m2, sLl, sLu, Ft, y, v, sh);
+            double *ep = Et + (size_t)p * NP;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const int t = r * W + k;
+                acc[r] += wp * v[r];
+                ep[t] = rho[t] + v[r];          // E*_p of this sweep
+            }
+        }
+        // res = sum_p omega_p v_p - (1 - W) rho;  rho += res + D^{-1} (G res).
+        // The diffusion operator is factored again here rather than held in
+        // registers across the pair loop (one factorisation per P solves).
+        double rl[M], d[M], f[M];
+        {
+            double b[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const int j = j0 + r;
+                const bool in = j < N;
+                rl[r] = in ? acc[r] - I.one_minus_W * rho[r * W + k] : 0.0;
+                d[r] = in ? C[C_G * N1 + j] * rl[r] : 0.0;
+                b[r] = in ? C[C_DD * N1 + j] : 1.0;
+            }
+            TriFac<W, M> Fd;
+            tri_factor<W, M>(I.mu2, sLl, sLu, b, Fd, sh);
+            tri_solve<W, M>(I.mu2, sLl, sLu, Fd, d, f, sh);
+        }
+        double md = 0.0, mr = 0.0;
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            if (j0 + r < N) {
+                const int t = r * W + k;
+                const double delta = rl[r] + f[r];
+                const double nw = rho[t] + delta;
+                rho[t] = nw;
+                md = fmax(md, fabs(delta));
+                mr = fmax(mr, fabs(nw));
+            }
+        }
+        tile_max2<W>(md, mr, sh);
+        tsync<W>();                               // rho update and E* visible to the tile
+        ++it;
+        converged = (md <= A.tol * mr) ? 1 : 0;
+        if (converged || it >= A.maxit) break;
+    }
+    if (k == 0) {
+        st[0] = it;
+        st[1] = converged;
+    }
+
+    // ---------------- correction substep 1: moments, D, K*, Newton on (4.13)/(5.5)
+    int n_its = 0, n_fail = 0, n_clamp = 0, n_neg = 0;
+    for (int j = k; j < N; j += W) {
+        double rs = 0.0, D = 0.0;
+        for (int p = 0; p < P; ++p) {
+            const double *ep = Et + (size_t)p * NP;
+            const double m1 = mu[p];
+            const double ej = ep[bpos(j, W, M)];
+            // O* at nodes j and j+1 from the node relation and the inflow relations (4.7)
+            auto onode = [&](int ii) {
+                return C[C_AW * N1 + ii] * O[(size_t)ii * P + p]
+                     - C[C_BC * N1 + ii] * m1 * (ep[bpos(ii, W, M)] - ep[bpos(ii - 1, W, M)]);
+            };
+            double ol, orr;
+            if (j >= 1) ol = onode(j);
+            else ol = 2.0 / eps * (bL[p] - ej) - onode(1);
+            if (j <= N - 2) orr = onode(j + 1);
+            else orr = 2.0 / eps * (ej - bR[p]) - onode(N - 1);
+            rs += om[p] * ej;
+            D += om[p] * m1 * (orr - ol);
+        }
+        D /= I.dx;
+        const double ac = I.a * I.c;
+        const double t = Tn[j];
+        const double Un = t * t * t * t;
+        const double beta = C[C_BETA * N1 + j];
+        const double us = (Un + beta * rs) / (1.0 + ac * beta);
+        C[C_USTAR * N1 + j] = us;
+        C[C_D * N1 + j] = D;
+        double Ks = 1.0;
+        if (I.m == 3) {
+            if (us < 0.0) {
+                Ks = 0.0;
+                ++n_clamp;
+            } else {
+                Ks = pow(us, 0.75);
+            }
+        }
+        const double s0 = sg[j];
+        const double lin = I.cv * (eps * eps * Ks + I.c * s0 * I.dt);
+        const double q4 = ac * s0 * I.dt;
+        const double rhs = s0 * I.dt * (C[C_RHON * N1 + j] - I.c * I.dt * D);
+        double T = t;
+        int its = 0;
+        if (!(s0 == 0.0 && Ks == 0.0)) {
+            if (t + rhs / lin < 0.0) ++n_neg;
+            bool ok = false;
+            for (its = 0; its < A.newton_maxit;) {
+                const double T2v = T * T;
+                const double g = q4 * T2v * T2v + lin * (T - t) - rhs;
+                const double dg = 4.0 * q4 * T2v * T + lin;
+                const double step = g / dg;
+                T -= step;
+                ++its;
+                if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(t))) { ok = true; break; }
+            }
+            if (!ok) ++n_fail;
+        }
+        C[C_TNEW * N1 + j] = T;
+        T2[j] = T;
+        n_its = max(n_its, its);
+    }
+    // one atomic per wavefront for the step counters
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        n_its = max(n_its, __shfl_xor(n_its, o, 64));
+        n_fail += __shfl_xor(n_fail, o, 64);
+        n_clamp += __shfl_xor(n_clamp, o, 64);
+        n_neg += __shfl_xor(n_neg, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&st[2], n_its);
+        if (n_fail) atomicAdd(&st[3], n_fail);
+        if (n_clamp) atomicAdd(&st[4], n_clamp);
+        if (n_neg) atomicAdd(&st[5], n_neg);
+    }
+    tsync<W>();
+
+    // ---------------- correction substep 2 (K from T^{n+1}): E^{n+1} per pair
+    const double *Tnew = C + C_TNEW * N1;
+    for (int j = k; j < N; j += W) b_cell(I, 1, Tnew, Tn, sg, j, C, N1);
+    tsync<W>();
+    b_rhs<W, M>(I, C, N1, E, O, mu, bL, bR, Rt);
+    for (int j = k; j < NP; j += W) {
+        const int t = bpos(j, W, M);
+        const bool in = j < N;
+        sLl[t] = in ? C[C_LL * N1 + j] : 0.0;
+        sLu[t] = in ? C[C_LU * N1 + j] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) lam[r] = (j0 + r < N) ? C[C_LAM * N1 + j0 + r] : 1.0;
+    tsync<W>();
+    const double cb0 = C[C_BD * N1 + 0], cbN = C[C_BD * N1 + N - 1];
+    for (int p = 0; p < P; ++p) {
+        const double m1 = mu[p], m2 = m1 * m1;
+        const double *rp = Rt + (size_t)p * NP;
+        double b[M], d[M], x[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int j = j0 + r;
+            const int t = r * W + k;
+            if (j < N) {
+                const double bdj = (j == 0 ? cb0 : 0.0) + (j == N - 1 ? cbN : 0.0);
+                b[r] = lam[r] + m2 * (-(sLl[t] + sLu[t])) + m1 * bdj;
+                d[r] = rp[t];
+            } else {
+                b[r] = 1.0;
+                d[r] = 0.0;
+            }
+        }
+        TriFac<W, M> F;
+        tri_factor<W, M>(m2, sLl, sLu, b, F, sh);
+        tri_solve<W, M>(m2, sLl, sLu, F, d, x, sh);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            const int j = j0 + r;
+            if (j < N) E2[(size_t)j * P + p] = x[r];
+        }
+    }
+    tsync<W>();
+
+    // ---------------- projection (4.14): O^{n+1} from the node relation with K^{n+1}
+    const double *Aw = C + C_AW * N1, *Bc = C + C_BC * N1;
+    for (int idx = k; idx < (N + 1) * P; idx += W) {
+        const int ii = idx / P, p = idx - (idx / P) * P;
+        O2[idx] = node_any(E2, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, ii, p);
+    }
+    tsync<W>();
+}
+
+__global__ void __launch_bounds__(BNT) batch_kernel(BatchArgs A)
+{
+    extern __shared__ double smem[];
+    __shared__ int s_q;
+    // ---- work-group tiles, largest work first
+    while (true) {
+        if (threadIdx.x == 0) s_q = atomicAdd(&A.queue[0], 1);
+        __syncthreads();
+        const int q = __builtin_amdgcn_readfirstlane(s_q);   // uniform: instance data in SGPRs
+        __syncthreads();
+        if (q >= A.n_wg) break;
+        const int i = A.order[q];
+        switch (A.inst[i].M) {
+        case 2: run_instance<BNT, 2>(A, i, smem); break;
+        case 4: run_instance<BNT, 4>(A, i, smem); break;
+        default: run_instance<BNT, 8>(A, i, smem); break;
+        }
+    }
+    // ---- wavefront tiles: each wave takes instances on its own
+    double *wsm = smem + (threadIdx.x >> 6) * LDS_WAVE;
+    while (true) {
+        int q = 0;
+        if ((threadIdx.x & 63) == 0) q = atomicAdd(&A.queue[1], 1);
+        q = __builtin_amdgcn_readfirstlane(q);
+        if (q >= A.n_wave) break;
+        const int i = A.order[A.n_wg + q];
+        if (A.inst[i].M == 2) run_instance<WAVE, 2>(A, i, wsm);
+        else run_instance<WAVE, 4>(A, i, wsm);
+    }
+}
+
+// queue heads and per-instance counters cleared by a kernel (not a memset node)
+__global__ void batch_reset(int *queue, int *istat, int n8)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2) queue[t] = 0;
+    if (t < n8) istat[t] = 0;
+}
+
+__global__ void bfill(double *x, size_t n, double v)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = v;
+}
+
+int pow2_rows(int N, int W)
+{
+    int M = 2;
+    while (W * M < N) M *= 2;
+    return M;
+}
+
+}  // namespace
+
+// ===========================================================================
+// host side
+// ===========================================================================
+struct grte_batch {
+    int n = 0, dev = 0, ncu = 0;
+    int wave_max_n = 256, grid = 0, tuned = 0;
+    double tol = 1e-15;
+    int maxit = 200, newton_maxit = 100;
+    long long tot_cells = 0, tot_E = 0, tot_O = 0, tot_pairs = 0;
+    std::vector<BInst> h_inst;
+    std::vector<int> h_order;
+    std::vector<double> cost;                  // expected work per instance (scheduling)
+    int n_wg = 0, n_wave = 0;
+    hipStream_t stream = nullptr;
+    std::vector<void *> allocs;
+    BInst *d_inst = nullptr;
+    int *d_order = nullptr, *d_queue = nullptr, *d_istat = nullptr;
+    double *E[2] = {nullptr, nullptr}, *O[2] = {nullptr, nullptr}, *T[2] = {nullptr, nullptr};
+    int cur = 0;                               // state buffers in use: E[cur], O[cur], T[cur]
+    double *sigma0 = nullptr, *mu = nullptr, *omega = nullptr, *bL = nullptr, *bR = nullptr;
+    double *cells = nullptr, *pairs = nullptr;
+    // graphs, one per buffer parity; rebuilt when the launch changes
+    int use_graph = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipStream_t cap_stream = nullptr;
+    // timing
+    int profiling = 0;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+};
+
+namespace {
+
+grte_status bhip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return GRTE_OK;
+    fprintf(stderr, "grte_batch: %s failed: %s\n", what, hipGetErrorString(e));
+    return GRTE_E_HIP;
+}
+
+#define BCHK(x)                                                 \
+    do {                                                        \
+        grte_status _s = bhip((x), #x);                         \
+        if (_s != GRTE_OK) return _s;                           \
+    } while (0)
+
+template <class Tp>
+grte_status balloc(grte_batch *b, Tp **p, size_t n)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(Tp)) != hipSuccess) return GRTE_E_NOMEM;
+    b->allocs.push_back(q);
+    *p = (Tp *)q;
+    return GRTE_OK;
+}
+
+void drop_graphs(grte_batch *b)
+{
+    for (int q = 0; q < 2; ++q) {
+        if (b->gexec[q]) (void)hipGraphExecDestroy(b->gexec[q]);
+        b->gexec[q] = nullptr;
+    }
+}
+
+// tiles for the current wave_max_n; processing order: largest expected work first
+grte_status assign_tiles(grte_batch *b)
+{
+    std::vector<int> wg, wv;
+    for (int i = 0; i < b->n; ++i) {
+        BInst &I = b->h_inst[i];
+        if (I.N <= b->wave_max_n && I.N <= WAVE_MAX_N) {
+            I.W = WAVE;
+            wv.push_back(i);
+        } else {
+            I.W = BNT;
+            wg.push_back(i);
+        }
+        I.M = pow2_rows(I.N, I.W);
+    }
+    auto by_cost = [&](int x, int y) { return b->cost[x] > b->cost[y] || (b->cost[x] == b->cost[y] && x < y); };
+    std::sort(wg.begin(), wg.end(), by_cost);
+    std::sort(wv.begin(), wv.end(), by_cost);
+    b->h_order = wg;
+    b->h_order.insert(b->h_order.end(), wv.begin(), wv.end());
+    b->n_wg = (int)wg.size();
+    b->n_wave = (int)wv.size();
+    BCHK(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->n * sizeof(BInst), hipMemcpyHostToDevice, b->stream));
+    BCHK(hipMemcpyAsync(b->d_order, b->h_order.data(), b->n * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    return GRTE_OK;
+}
+
+BatchArgs make_args(const grte_batch *b, int src)
+{
+    BatchArgs A{};
+    A.n_wg = b->n_wg;
+    A.n_wave = b->n_wave;
+    A.inst = b->d_inst;
+    A.order = b->d_order;
+    A.queue = b->d_queue;
+    A.E = b->E[src]; A.O = b->O[src]; A.T = b->T[src];
+    A.E2 = b->E[1 - src]; A.O2 = b->O[1 - src]; A.T2 = b->T[1 - src];
+    A.sigma0 = b->sigma0; A.mu = b->mu; A.omega = b->omega; A.bL = b->bL; A.bR = b->bR;
+    A.cells = b->cells; A.pairs = b->pairs; A.istat = b->d_istat;
+    A.tol = b->tol; A.maxit = b->maxit; A.newton_maxit = b->newton_maxit;
+    return A;
+}
+
+constexpr size_t BATCH_LDS = (size_t)LDS_WG * sizeof(double);
+
+grte_status enqueue_step(grte_batch *b, hipStream_t s, int src)
+{
+    BatchArgs A = make_args(b, src);
+    const int n8 = 8 * b->n;
+    hipLaunchKernelGGL(batch_reset, dim3((unsigned)((std::max(n8, 2) + 255) / 256)), dim3(256), 0, s,
+                       b->d_queue, b->d_istat, n8);
+    BCHK(hipGetLastError());
+    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)b->grid), dim3(BNT), BATCH_LDS, s, A);
+    BCHK(hipGetLastError());
+    return GRTE_OK;
+}
+
+grte_status capture(grte_batch *b, int src)
+{
+    if (!b->cap_stream) BCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    BCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    grte_status st = enqueue_step(b, b->cap_stream, src);
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (st != GRTE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    BCHK(e);
+    e = hipGraphInstantiate(&b->gexec[src], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    BCHK(e);
+    return GRTE_OK;
+}
+
+// one step from buffers `src` into 1 - src, as a graph replay or a direct launch
+grte_status run_step(grte_batch *b, int src)
+{
+    if (b->use_graph) {
+        if (!b->gexec[src]) {
+            grte_status st = capture(b, src);
+            if (st != GRTE_OK) return st;
+        }
+        BCHK(hipGraphLaunch(b->gexec[src], b->stream));
+        return GRTE_OK;
+    }
+    return enqueue_step(b, b->stream, src);
+}
+
+grte_status read_stats(grte_batch *b, std::vector<int> &h)
+{
+    h.resize((size_t)8 * b->n);
+    BCHK(hipMemcpyAsync(h.data(), b->d_istat, h.size() * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    return GRTE_OK;
+}
+
+// expected work of each instance from the iteration counts of a step
+void update_cost(grte_batch *b, const std::vector<int> &h)
+{
+    for (int i = 0; i < b->n; ++i) {
+        const BInst &I = b->h_inst[i];
+        b->cost[i] = (double)I.N * I.P * std::max(1, h[8 * i]);
+    }
+}
+
+grte_status copy_dev(grte_batch *b, void *dst, const void *src, size_t bytes, hipMemcpyKind kind)
+{
+    BCHK(hipMemcpyAsync(dst, src, bytes, kind, b->stream));
+    if (kind != hipMemcpyDeviceToDevice) BCHK(hipStreamSynchronize(b->stream));
+    return GRTE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+grte_status grte_batch_destroy(grte_batch *b)
+{
+    if (!b) return GRTE_OK;
+    drop_graphs(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    for (void *p : b->allocs) (void)hipFree(p);
+    delete b;
+    return GRTE_OK;
+}
+
+grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu, const double *omega,
+                              grte_batch **out)
+{
+    if (!out) return GRTE_E_INVAL;
+    *out = nullptr;
+    if (n < 1 || !inst || !mu || !omega) return GRTE_E_INVAL;
+    long long tp = 0;
+    for (int i = 0; i < n; ++i) {
+        const grte_instance &d = inst[i];
+        if (d.nx < 2 || d.npairs < 1 || !(d.length > 0) || !(d.a > 0) || !(d.c > 0) || !(d.cv > 0) ||
+            (d.opacity_law != 0 && d.opacity_law != 3) || !(d.dt > 0) || !(d.eps > 0) ||
+            !std::isfinite(d.dt) || !std::isfinite(d.eps) || !std::isfinite(d.length))
+            return GRTE_E_INVAL;
+        if (d.nx > BMAX_N || d.npairs > BMAX_P) return GRTE_E_UNSUPPORTED;
+        tp += d.npairs;
+    }
+    for (long long q = 0; q < tp; ++q)
+        if (!(mu[q] > 0) || !(omega[q] > 0) || !std::isfinite(mu[q]) || !std::isfinite(omega[q]))
+            return GRTE_E_INVAL;
+    grte_batch *b = new (std::nothrow) grte_batch();
+    if (!b) return GRTE_E_NOMEM;
+    b->n = n;
+    if (hipGetDevice(&b->dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->dev) != hipSuccess) {
+        delete b;
+        return GRTE_E_HIP;
+    }
+    b->h_inst.resize(n);
+    b->cost.resize(n);
+    long long oE = 0, oO = 0, oT = 0, oP = 0, oC = 0, oR = 0;
+    for (int i = 0; i < n; ++i) {
+        const grte_instance &d = inst[i];
+        BInst &I = b->h_inst[i];
+        I.N = d.nx; I.P = d.npairs; I.m = d.opacity_law;
+        I.dx = d.length / d.nx; I.a = d.a; I.c = d.c; I.cv = d.cv; I.eps = d.eps; I.dt = d.dt;
+        // 1 - sum(omega) exactly rounded (two-sum), first and second moments
+        double s = 0.0, e = 0.0, m1 = 0.0, m2 = 0.0;
+        for (int p = 0; p < I.P; ++p) {
+            const double x = omega[oP + p];
+            const double t = s + x;
+            const double bp = t - s;
+            e += (s - (t - bp)) + (x - bp);
+            s = t;
+            m1 += omega[oP + p] * mu[oP + p];
+            m2 += omega[oP + p] * mu[oP + p] * mu[oP + p];
+        }
+        I.one_minus_W = (1.0 - s) - e;
+        I.mu1 = m1;
+        I.mu2 = m2;
+        I.oE = oE; I.oO = oO; I.oT = oT; I.oP = oP; I.oC = oC; I.oR = oR;
+        I.NPa = (long long)BNT * pow2_rows(I.N, BNT);   // also covers every wavefront tile
+        oE += (long long)I.N * I.P;
+        oO += (long long)(I.N + 1) * I.P;
+        oT += I.N;
+        oP += I.P;
+        oC += (long long)NCA * (I.N + 1);
+        oR += 2LL * I.P * I.NPa;
+        b->cost[i] = (double)I.N * I.P;
+    }
+    b->tot_E = oE; b->tot_O = oO; b->tot_cells = oT; b->tot_pairs = oP;
+    grte_status st = GRTE_OK;
+    if (st == GRTE_OK) st = balloc(b, &b->d_inst, n);
+    if (st == GRTE_OK) st = balloc(b, &b->d_order, n);
+    if (st == GRTE_OK) st = balloc(b, &b->d_queue, 2);
+    if (st == GRTE_OK) st = balloc(b, &b->d_istat, (size_t)8 * n);
+    for (int q = 0; q < 2 && st == GRTE_OK; ++q) {
+        st = balloc(b, &b->E[q], oE);
+        if (st == GRTE_OK) st = balloc(b, &b->O[q], oO);
+        if (st == GRTE_OK) st = balloc(b, &b->T[q], oT);
+    }
+    if (st == GRTE_OK) st = balloc(b, &b->sigma0, oT);
+    if (st == GRTE_OK) st = balloc(b, &b->mu, oP);
+    if (st == GRTE_OK) st = balloc(b, &b->omega, oP);
+    if (st == GRTE_OK) st = balloc(b, &b->bL, oP);
+    if (st == GRTE_OK) st = balloc(b, &b->bR, oP);
+    if (st == GRTE_OK) st = balloc(b, &b->cells, oC);
+    if (st == GRTE_OK) st = balloc(b, &b->pairs, oR);
+    if (st != GRTE_OK) { grte_batch_destroy(b); return st; }
+    if (hipFuncSetAttribute((const void *)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)BATCH_LDS) != hipSuccess) {
+        grte_batch_destroy(b);
+        return GRTE_E_HIP;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel, BNT, BATCH_LDS) !=
+            hipSuccess || nb < 1) {
+        grte_batch_destroy(b);
+        return GRTE_E_HIP;
+    }
+    b->grid = nb * b->ncu;
+    if (hipMemcpy(b->mu, mu, oP * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->omega, omega, oP * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        grte_batch_destroy(b);
+        return GRTE_E_HIP;
+    }
+    // defaults: zero state and inflow, unit opacity
+    const unsigned t = 256;
+    auto fill = [&](double *x, long long cnt, double v) {
+        hipLaunchKernelGGL(bfill, dim3((unsigned)((cnt + t - 1) / t)), dim3(t), 0, nullptr, x, (size_t)cnt, v);
+    };
+    fill(b->E[0], oE, 0.0);
+    fill(b->O[0], oO, 0.0);
+    fill(b->T[0], oT, 0.0);
+    fill(b->sigma0, oT, 1.0);
+    fill(b->bL, oP, 0.0);
+    fill(b->bR, oP, 0.0);
+    if (hipDeviceSynchronize() != hipSuccess || assign_tiles(b) != GRTE_OK) {
+        grte_batch_destroy(b);
+        return GRTE_E_HIP;
+    }
+    *out = b;
+    return GRTE_OK;
+}
+
+grte_status grte_batch_sizes(const grte_batch *b, long long *cells, long long *e_len, long long *o_len,
+                             long long *pairs)
+{
+    if (!b) return GRTE_E_INVAL;
+    if (cells) *cells = b->tot_cells;
+    if (e_len) *e_len = b->tot_E;
+    if (o_len) *o_len = b->tot_O;
+    if (pairs) *pairs = b->tot_pairs;
+    return GRTE_OK;
+}
+
+grte_status grte_batch_set_stream(grte_batch *b, void *hip_stream)
+{
+    if (!b) return GRTE_E_INVAL;
+    b->stream = (hipStream_t)hip_stream;
+    return GRTE_OK;
+}
+
+grte_status grte_batch_set_solver(grte_batch *b, double pred_tol, int pred_maxit, int newton_maxit)
+{
+    if (!b || !(pred_tol > 0) || pred_maxit < 1 || newton_maxit < 1) return GRTE_E_INVAL;
+    b->tol = pred_tol;
+    b->maxit = pred_maxit;
+    b->newton_maxit = newton_maxit;
+    drop_graphs(b);
+    return GRTE_OK;
+}
+
+grte_status grte_batch_set_opacity(grte_batch *b, const double *sigma0, int on_device)
+{
+    if (!b || !sigma0) return GRTE_E_INVAL;
+    if (!on_device)
+        for (long long j = 0; j < b->tot_cells; ++j)
+            if (!(sigma0[j] >= 0) || !std::isfinite(sigma0[j])) return GRTE_E_INVAL;
+    return copy_dev(b, b->sigma0, sigma0, b->tot_cells * sizeof(double),
+                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+}
+
+grte_status grte_batch_set_inflow(grte_batch *b, const double *b_left, const double *b_right)
+{
+    if (!b || !b_left || !b_right) return GRTE_E_INVAL;
+    grte_status s = copy_dev(b, b->bL, b_left, b->tot_pairs * sizeof(double), hipMemcpyHostToDevice);
+    if (s != GRTE_OK) return s;
+    return copy_dev(b, b->bR, b_right, b->tot_pairs * sizeof(double), hipMemcpyHostToDevice);
+}
+
+grte_status grte_batch_set_state(grte_batch *b, const double *E, const double *O, const double *T, int on_device)
+{
+    if (!b || !E || !O || !T) return GRTE_E_INVAL;
+    if (!on_device)
+        for (long long j = 0; j < b->tot_cells; ++j)
+            if (!(T[j] >= 0) || !std::isfinite(T[j])) return GRTE_E_INVAL;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    grte_status s = copy_dev(b, b->E[b->cur], E, b->tot_E * sizeof(double), k);
+    if (s == GRTE_OK) s = copy_dev(b, b->O[b->cur], O, b->tot_O * sizeof(double), k);
+    if (s == GRTE_OK) s = copy_dev(b, b->T[b->cur], T, b->tot_cells * sizeof(double), k);
+    return s;
+}
+
+grte_status grte_batch_get_state(grte_batch *b, double *E, double *O, double *T, int on_device)
+{
+    if (!b) return GRTE_E_INVAL;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    grte_status s = GRTE_OK;
+    if (E) s = copy_dev(b, E, b->E[b->cur], b->tot_E * sizeof(double), k);
+    if (s == GRTE_OK && O) s = copy_dev(b, O, b->O[b->cur], b->tot_O * sizeof(double), k);
+    if (s == GRTE_OK && T) s = copy_dev(b, T, b->T[b->cur], b->tot_cells * sizeof(double), k);
+    return s;
+}
+
+grte_status grte_batch_set_tuning(grte_batch *b, const grte_batch_tuning *t)
+{
+    if (!b || !t) return GRTE_E_INVAL;
+    if (t->wave_max_n < 0 || t->grid < 1 || t->grid > 65535) return GRTE_E_INVAL;
+    b->wave_max_n = t->wave_max_n;
+    b->grid = t->grid;
+    return assign_tiles(b);
+}
+
+grte_status grte_batch_get_tuning(const grte_batch *b, grte_batch_tuning *t)
+{
+    if (!b || !t) return GRTE_E_INVAL;
+    t->wave_max_n = b->wave_max_n;
+    t->grid = b->grid;
+    t->step_ms = 0.0;
+    return GRTE_OK;
+}
+
+grte_status grte_batch_use_graph(grte_batch *b, int on)
+{
+    if (!b) return GRTE_E_INVAL;
+    b->use_graph = on ? 1 : 0;
+    return GRTE_OK;
+}
+
+grte_status grte_batch_step(grte_batch *b, grte_batch_info *info)
+{
+    if (!b) return GRTE_E_INVAL;
+    int k = -1;
+    if (b->profiling) {
+        if (b->ev_used * 2 + 2 > b->ev.size()) {
+            for (int q = 0; q < 2; ++q) {
+                hipEvent_t e;
+                BCHK(hipEventCreate(&e));
+                b->ev.push_back(e);
+            }
+        }
+        k = (int)b->ev_used++;
+        BCHK(hipEventRecord(b->ev[2 * k], b->stream));
+    }
+    grte_status st = run_step(b, b->cur);
+    if (st != GRTE_OK) return st;
+    if (k >= 0) BCHK(hipEventRecord(b->ev[2 * k + 1], b->stream));
+    b->cur = 1 - b->cur;
+    if (!info) return GRTE_OK;
+    std::vector<int> h;
+    if ((st = read_stats(b, h)) != GRTE_OK) return st;
+    int bad = 0;
+    for (int i = 0; i < b->n; ++i) {
+        grte_batch_info &f = info[i];
+        f.pred_iters = h[8 * i + 0];
+        f.pred_converged = h[8 * i + 1];
+        f.newton_max_iters = h[8 * i + 2];
+        f.newton_failed = h[8 * i + 3];
+        f.kstar_clamped = h[8 * i + 4];
+        f.negative_root = h[8 * i + 5];
+        if (!f.pred_converged || f.newton_failed) bad = 1;
+    }
+    return bad ? GRTE_E_NOCONV : GRTE_OK;
+}
+
+grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best)
+{
+    if (!b || trials < 1) return GRTE_E_INVAL;
+    // every candidate step starts from the current state and writes the other
+    // buffers, so the state is left unchanged
+    const int save_graph = b->use_graph;
+    b->use_graph = 0;
+    std::vector<int> h;
+    grte_status st = assign_tiles(b);
+    if (st == GRTE_OK) st = enqueue_step(b, b->stream, b->cur);
+    if (st == GRTE_OK) st = read_stats(b, h);
+    if (st != GRTE_OK) { b->use_graph = save_graph; return st; }
+    update_cost(b, h);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel, BNT, BATCH_LDS) != hipSuccess)
+        nb = 1;
+    const int waves[] = {0, 128, 256};
+    std::vector<int> grids;
+    for (int f = 1; f <= std::max(1, nb); f *= 2) grids.push_back(f * b->ncu);
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0));
+    BCHK(hipEventCreate(&e1));
+    double best_ms = 1e300;
+    int bw = b->wave_max_n, bg = b->grid;
+    for (int wv : waves) {
+        for (int g : grids) {
+            b->wave_max_n = wv;
+            b->grid = g;
+            if ((st = assign_tiles(b)) != GRTE_OK) break;
+            if ((st = enqueue_step(b, b->stream, b->cur)) != GRTE_OK) break;   // warm-up
+            if (hipEventRecord(e0, b->stream) != hipSuccess) { st = GRTE_E_HIP; break; }
+            for (int r = 0; r < trials && st == GRTE_OK; ++r) st = enqueue_step(b, b->stream, b->cur);
+            if (st != GRTE_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = GRTE_E_HIP;
+                break;
+            }
+            const double per = ms / trials;
+            if (per < best_ms) {
+                best_ms = per;
+                bw = wv;
+                bg = g;
+            }
+        }
+        if (st != GRTE_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->use_graph = save_graph;
+    if (st != GRTE_OK) return st;
+    b->wave_max_n = bw;
+    b->grid = bg;
+    b->tuned = 1;
+    if ((st = assign_tiles(b)) != GRTE_OK) return st;
+    if (best) {
+        best->wave_max_n = bw;
+        best->grid = bg;
+        best->step_ms = best_ms;
+    }
+    return GRTE_OK;
+}
+
+grte_status grte_batch_set_profiling(grte_batch *b, int on)
+{
+    if (!b) return GRTE_E_INVAL;
+    b->profiling = on ? 1 : 0;
+    b->ev_used = 0;
+    return GRTE_OK;
+}
+
+grte_status grte_batch_read_timing(grte_batch *b, double *total_ms, int *count)
+{
+    if (!b || !total_ms || !count) return GRTE_E_INVAL;
+    *total_ms = 0.0;
+    *count = 0;
+    BCHK(hipStreamSynchronize(b->stream));
+    for (size_t k = 0; k < b->ev_used; ++k) {
+        float ms = 0.0f;
+        BCHK(hipEventElapsedTime(&ms, b->ev[2 * k], b->ev[2 * k + 1]));
+        *total_ms += ms;
+        *count += 1;
+    }
+    b->ev_used = 0;
+    return GRTE_OK;
+}
+
+}  // extern "C"

@@ -66,247 +66,9 @@
 
 #include "../../include/grte.h"
 
+#include "solver_common.hpp"
+
 namespace {
-
-constexpr int NT = 256;          // threads per work-group of the tridiagonal solvers
-constexpr int LOGNT = 8;
-constexpr int MAX_M = 16;        // rows per thread -> N <= NT * MAX_M = 4096
-constexpr int MAX_N = NT * MAX_M;
-constexpr int MAX_P = 64;
-constexpr int BAR_STRIDE = 16;   // 64-bit barrier flags, one 128-byte line per work-group
-
-// -------------------------------------------------------------------------
-// work-group tridiagonal solver: factor once, solve for many right-hand sides
-// -------------------------------------------------------------------------
-// Row j is owned by thread k = j / M as its row r = j % M; all per-row data
-// live in "position" order t = r * NT + k (conflict-free LDS, coalesced global
-// traffic).  The systems solved here have off-diagonals that are a scalar
-// multiple of two LDS-resident arrays, a_j = s Lo[t], c_j = s Up[t] (zero where
-// a row has no neighbour, and in padding rows), and a per-row diagonal b_j.
-// Each chunk's interior rows 0..M-2 are eliminated by Thomas' algorithm; the
-// chunk's last rows z_k form a tridiagonal system of NT rows solved by
-// parallel cyclic reduction.  What does not depend on the right-hand side --
-// the interior pivots and the PCR multipliers -- is computed once by
-// tri_factor and kept in registers; tri_solve then costs four short FMA
-// recurrences and one PCR sweep on the right-hand side only.
-template <int M>
-struct TriFac {
-    double inv[M - 1];          // reciprocal pivots of the interior rows
-    double k1[LOGNT], k2[LOGNT];
-    double invB;
-};
-
-template <int M>
-__device__ __forceinline__ void tri_factor(double s, const double *Lo, const double *Up,
-                                           const double (&b)[M], TriFac<M> &F, double *sh)
-{
-    static_assert(M >= 2, "at least two rows per thread");
-    const int k = threadIdx.x;
-    double Q[M - 1], R[M - 1];   // responses of the interior to z_{k-1} (Q) and z_k (R)
-    double cprev;
-    {
-        const double a0 = s * Lo[k], c0 = s * Up[k];
-        const double inv = 1.0 / b[0];
-        F.inv[0] = inv;
-        cprev = (M > 2) ? c0 * inv : 0.0;
-        Q[0] = -a0 * inv;
-        R[0] = (M == 2) ? -c0 * inv : 0.0;
-    }
-#pragma unroll
-    for (int r = 1; r < M - 1; ++r) {
-        const double ar = s * Lo[r * NT + k], cr = s * Up[r * NT + k];
-        const double inv = 1.0 / (b[r] - ar * cprev);
-        F.inv[r] = inv;
-        Q[r] = -ar * Q[r - 1] * inv;
-        R[r] = ((r == M - 2 ? -cr : 0.0) - ar * R[r - 1]) * inv;
-        cprev = (r < M - 2) ? cr * inv : 0.0;
-    }
-#pragma unroll
-    for (int r = M - 3; r >= 0; --r) {
-        const double cp = s * Up[r * NT + k] * F.inv[r];
-        Q[r] -= cp * Q[r + 1];
-        R[r] -= cp * R[r + 1];
-    }
-    const double ae = s * Lo[(M - 1) * NT + k], ce = s * Up[(M - 1) * NT + k];
-    sh[k] = Q[0];
-    sh[NT + k] = R[0];
-    __syncthreads();
-    const double Qn = (k + 1 < NT) ? sh[k + 1] : 0.0;
-    const double Rn = (k + 1 < NT) ? sh[NT + k + 1] : 0.0;
-    __syncthreads();
-    double Aa = ae * Q[M - 2];
-    double Bb = ae * R[M - 2] + b[M - 1] + ce * Qn;
-    double Cc = ce * Rn;
-    double *sA = sh, *sB = sh + NT, *sC = sh + 2 * NT;
-#pragma unroll
-    for (int l = 0; l < LOGNT; ++l) {
-        const int st = 1 << l;
-        sA[k] = Aa;
-        sB[k] = Bb;
-        sC[k] = Cc;
-        __syncthreads();
-        double Am = 0.0, Bm = 1.0, Cm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0;
-        if (k >= st) { Am = sA[k - st]; Bm = sB[k - st]; Cm = sC[k - st]; }
-        if (k + st < NT) { Ap = sA[k + st]; Bp = sB[k + st]; Cp = sC[k + st]; }
-        __syncthreads();
-        const double k1 = Aa / Bm, k2 = Cc / Bp;
-        F.k1[l] = k1;
-        F.k2[l] = k2;
-        Aa = -Am * k1;
-        Cc = -Cp * k2;
-        Bb = Bb - Cm * k1 - Ap * k2;
-    }
-    F.invB = 1.0 / Bb;
-}
-
-// forward elimination + back substitution over the interior rows 0..M-2
-template <int M>
-__device__ __forceinline__ void tri_interior(double s, const double *Lo, const double *Up, const TriFac<M> &F,
-                                             double (&y)[M - 1])
-{
-    const int k = threadIdx.x;
-    y[0] = y[0] * F.inv[0];
-#pragma unroll
-    for (int r = 1; r < M - 1; ++r) y[r] = (y[r] - s * Lo[r * NT + k] * y[r - 1]) * F.inv[r];
-#pragma unroll
-    for (int r = M - 3; r >= 0; --r) y[r] -= s * Up[r * NT + k] * F.inv[r] * y[r + 1];
-}
-
-template <int M>
-__device__ __forceinline__ void tri_solve(double s, const double *Lo, const double *Up, const TriFac<M> &F,
-                                          const double (&d)[M], double (&x)[M], double *sh)
-{
-    const int k = threadIdx.x;
-    // interior particular solution with z_{k-1} = z_k = 0
-    double y[M - 1];
-#pragma unroll
-    for (int r = 0; r < M - 1; ++r) y[r] = d[r];
-    tri_interior<M>(s, Lo, Up, F, y);
-    // forward value of the last interior row (needed before back substitution)
-    // equals its final value, so ylast is read after the sweep
-    const double ylast = y[M - 2];
-    sh[k] = y[0];
-    __syncthreads();
-    const double yn = (k + 1 < NT) ? sh[k + 1] : 0.0;
-    double D = d[M - 1] - s * Lo[(M - 1) * NT + k] * ylast - s * Up[(M - 1) * NT + k] * yn;
-    // PCR on the right-hand side, two buffers so one barrier per level suffices
-#pragma unroll
-    for (int l = 0; l < LOGNT; ++l) {
-        const int st = 1 << l;
-        double *bf = sh + NT * (1 + (l & 1));
-        bf[k] = D;
-        __syncthreads();
-        const double Dm = (k >= st) ? bf[k - st] : 0.0;
-        const double Dp = (k + st < NT) ? bf[k + st] : 0.0;
-        D = D - F.k1[l] * Dm - F.k2[l] * Dp;
-    }
-    const double z = D * F.invB;
-    sh[k] = z;
-    __syncthreads();
-    const double zl = (k > 0) ? sh[k - 1] : 0.0;
-    __syncthreads();
-    // interior again, now with the neighbouring chunk values folded in
-#pragma unroll
-    for (int r = 0; r < M - 1; ++r) y[r] = d[r];
-    y[0] -= s * Lo[k] * zl;
-    y[M - 2] -= s * Up[(M - 2) * NT + k] * z;
-    tri_interior<M>(s, Lo, Up, F, y);
-#pragma unroll
-    for (int r = 0; r < M - 1; ++r) x[r] = y[r];
-    x[M - 1] = z;
-}
-
-// block-wide max of two values at once: wave shuffles, then one LDS step
-// (fixed order; the result is the same in every thread)
-__device__ __forceinline__ void block_max2(double &a, double &b, double *sh)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a = fmax(a, __shfl_xor(a, o, 64));
-        b = fmax(b, __shfl_xor(b, o, 64));
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sh[w] = a;
-        sh[8 + w] = b;
-    }
-    __syncthreads();
-    a = sh[0];
-    b = sh[8];
-#pragma unroll
-    for (int q = 1; q < NT / 64; ++q) {
-        a = fmax(a, sh[q]);
-        b = fmax(b, sh[8 + q]);
-    }
-    __syncthreads();
-}
-
-// block-wide max of a non-negative value (fixed order; result in every thread)
-__device__ __forceinline__ double block_max(double v, double *sh)
-{
-    const int k = threadIdx.x;
-    sh[k] = v;
-    __syncthreads();
-#pragma unroll 1
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (k < s) sh[k] = fmax(sh[k], sh[k + s]);
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-// -------------------------------------------------------------------------
-// grid barrier for a cooperative launch (all work-groups co-resident)
-// -------------------------------------------------------------------------
-// Every work-group publishes the generation number in its own flag (no
-// contended counter); lanes of wave 0 watch one flag each.  Each thread makes
-// its own global writes visible at agent scope before the work-group
-// barrier, and the flag store is a release, so the writes are visible on every
-// XCD to a work-group that has observed the flag and executed the acquire.
-// The wait is bounded: on a timeout, or when another work-group has already
-// reported one, the error flag is raised and false is returned so that every
-// work-group leaves the iteration instead of hanging the device.
-__device__ __forceinline__ bool grid_barrier(unsigned long long *flags, unsigned long long gen, int *err)
-{
-    __shared__ int s_fail;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s_fail = 0;
-        __hip_atomic_store(&flags[(size_t)blockIdx.x * BAR_STRIDE], gen, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (threadIdx.x < 64) {
-        bool fail = false;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&flags[(size_t)b * BAR_STRIDE], __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT) < gen) {
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                    ++spins > (1u << 20)) {
-                    fail = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        if (fail) {
-            atomicOr(err, 1);
-            s_fail = 1;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    return s_fail == 0;
-}
-
-__device__ __forceinline__ double kpow(double T, int m) { return m == 0 ? 1.0 : T * T * T; }
-
-// position of row j in the per-thread-chunk ("position") order used by the
-// tridiagonal solvers: t = (j % M) * NT + j / M
-__device__ __forceinline__ int row_pos(int j, int M) { return (j % M) * NT + j / M; }
 
 // -------------------------------------------------------------------------
 // coefficients: one work-group per group of cells, all pairs of those cells
@@ -476,7 +238,7 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
     const int p = blockIdx.x;            // one parity pair per work-group
     const double mu = A.mu[p], mu2 = mu * mu, wp = A.omega[p];
 
-    TriFac<M> Ft, Fd;
+    TriFac<NT, M> Ft, Fd;
     double rr[M], gg[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) gg[r] = A.Gt[r * NT + k];
@@ -495,13 +257,13 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
                 rr[r] = 0.0;
             }
         }
-        tri_factor<M>(mu2, sLl, sLu, b, Ft, sh);
+        tri_factor<NT, M>(mu2, sLl, sLu, b, Ft, sh);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int j = j0 + r;
             b[r] = (j < N) ? A.Dd[j] : 1.0;
         }
-        tri_factor<M>(A.mu2avg, sLl, sLu, b, Fd, sh);
+        tri_factor<NT, M>(A.mu2avg, sLl, sLu, b, Fd, sh);
     }
 
     // positions whose angular sum this work-group forms
@@ -532,7 +294,7 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
                 y[r] = 0.0;
             }
         }
-        tri_solve<M>(mu2, sLl, sLu, Ft, y, v, sh);
+        tri_solve<NT, M>(mu2, sLl, sLu, Ft, y, v, sh);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int t = r * NT + k;          // padded rows give v = 0
@@ -563,7 +325,7 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
             rl[r] = A.res[t];
             d[r] = gg[r] * rl[r];
         }
-        tri_solve<M>(A.mu2avg, sLl, sLu, Fd, d, f, sh);
+        tri_solve<NT, M>(A.mu2avg, sLl, sLu, Fd, d, f, sh);
         double md = 0.0, mr = 0.0;
 #pragma unroll
         for (int r = 0; r < M; ++r) {
@@ -576,7 +338,7 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
                 mr = fmax(mr, fabs(nw));
             }
         }
-        block_max2(md, mr, sh);   // its barriers also publish the rho update
+        tile_max2<NT>(md, mr, sh);   // its barriers also publish the rho update
         ++it;
         converged = (md <= A.tol * mr) ? 1 : 0;
         if (converged || it >= A.maxit) break;
@@ -611,24 +373,6 @@ __global__ void __launch_bounds__(256) gather_estar_kernel(NewtonArgs A)
     if (t >= N * P) return;
     const int j = t / P, p = t - (t / P) * P;
     A.Ecm[t] = A.estar_t[(size_t)p * NT * A.M + row_pos(j, A.M)];
-}
-
-__device__ __forceinline__ double node_flux(const double *Eall, const double *O, const double *Aw,
-                                            const double *Bc, double mu, int N, int P, int i, int p)
-{
-    // interior node i (1..N-1): O_i = Aw_i O^n_i - Bc_i mu (E_i - E_{i-1})
-    return Aw[i] * O[(size_t)i * P + p] - Bc[i] * mu * (Eall[(size_t)i * P + p] - Eall[(size_t)(i - 1) * P + p]);
-}
-
-__device__ __forceinline__ double node_any(const double *Eall, const double *O, const double *Aw,
-                                           const double *Bc, double mu, double bl, double br, double eps,
-                                           int N, int P, int i, int p)
-{
-    if (i >= 1 && i <= N - 1) return node_flux(Eall, O, Aw, Bc, mu, N, P, i, p);
-    if (i == 0)   // inflow relation (4.7) at x = 0
-        return 2.0 / eps * (bl - Eall[p]) - node_flux(Eall, O, Aw, Bc, mu, N, P, 1, p);
-    // i == N, (4.7) at x = L
-    return 2.0 / eps * (Eall[(size_t)(N - 1) * P + p] - br) - node_flux(Eall, O, Aw, Bc, mu, N, P, N - 1, p);
 }
 
 __global__ void __launch_bounds__(256) newton_kernel(NewtonArgs A)
@@ -738,9 +482,9 @@ __global__ void __launch_bounds__(NT) corr_kernel(CorrArgs A)
             d[r] = 0.0;
         }
     }
-    TriFac<M> F;
-    tri_factor<M>(mu2, sLl, sLu, b, F, sh);
-    tri_solve<M>(mu2, sLl, sLu, F, d, x, sh);
+    TriFac<NT, M> F;
+    tri_factor<NT, M>(mu2, sLl, sLu, b, F, sh);
+    tri_solve<NT, M>(mu2, sLl, sLu, F, d, x, sh);
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int j = j0 + r;

@@ -13,6 +13,11 @@ seed (numpy PCG64, seed 18110000 + configuration number).
             i.i.d. per cell, eps in {1, 1e-2, 1e-4}, same initial and inflow
             data, dt = 0.5 dx, 2000 steps.
 
+  config 4  batched ensemble: 4096 independent slabs with N ~ U{64..2048},
+            N_v uniform in {8, 16, 32, 64}, eps = 10^U[-5, 0], one sigma0 =
+            10^U[-1, 2] per slab with sigma = sigma0 T^-3, the initial and inflow
+            data of config 1, dt = 0.5 / N.
+
 The velocity grid (Gauss-Legendre pairs: positive nodes by increasing mu,
 weight of +mu on [-1, 1], so the weights sum to one) is part of the input:
 both the oracle and the GPU library receive these exact binary64 values.
@@ -117,3 +122,40 @@ def random_state(N, nv, seed, m=3, eps=1e-2, T_lo=0.05, T_hi=1.0, anisotropy=0.2
     return Workload(name=f"random(N={N},nv={nv},seed={seed})", N=N, nv=nv, m=m, eps=eps,
                     dt=0.5 / N, steps=1, mu=mu, omega=om, sigma0=sigma0, T=T, E=E, O=O,
                     bL=bL, bR=bR)
+
+
+@dataclass
+class Ensemble:
+    """Independent slabs advanced together (packed in instance order)."""
+    name: str
+    members: list
+
+    def __len__(self):
+        return len(self.members)
+
+    def cell_angle_updates(self):
+        return sum(w.cell_angle_updates() for w in self.members)
+
+    def packed(self):
+        """Concatenated arrays in the packed layout of the batched library."""
+        cat = np.concatenate
+        return dict(
+            mu=cat([w.mu for w in self.members]), omega=cat([w.omega for w in self.members]),
+            sigma0=cat([w.sigma0 for w in self.members]), T=cat([w.T for w in self.members]),
+            E=cat([w.E.ravel() for w in self.members]), O=cat([w.O.ravel() for w in self.members]),
+            bL=cat([w.bL for w in self.members]), bR=cat([w.bR for w in self.members]))
+
+
+def config4(n=4096, N_lo=64, N_hi=2048, nvs=(8, 16, 32, 64), seed=SEED_BASE + 4):
+    """Batched ensemble: n slabs of uneven size, ordinate count, eps and opacity."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.integers(N_lo, N_hi + 1, n)
+    nv = rng.choice(np.asarray(nvs), n)
+    eps = 10.0 ** rng.uniform(-5.0, 0.0, n)
+    s0 = 10.0 ** rng.uniform(-1.0, 2.0, n)
+    members = []
+    for i in range(n):
+        N = int(Ns[i])
+        members.append(_slab(f"config4[{i}]", N, int(nv[i]), 3, float(eps[i]), 100,
+                             np.full(N, s0[i])))
+    return Ensemble(name=f"config4(n={n})", members=members)

@@ -89,3 +89,28 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.grte_destroy(None) == 0
     for s in (0, -1, -2, -3, -4, -5):
         assert lib.grte_status_string(s)
+
+
+def test_batch_invalid_arguments_rejected_before_device_work(lib):
+    from paper_1811_05579_amd._lib import Instance
+    mu = np.array([0.5, 0.5])
+    om = np.array([1.0, 1.0])
+    h = ctypes.c_void_p()
+
+    def create(*insts):
+        arr = (Instance * len(insts))(*insts)
+        return lib.grte_batch_create(len(insts), arr, mu.ctypes.data, om.ctypes.data, ctypes.byref(h))
+
+    good = Instance(8, 1, 0, 1.0, 1.0, 1.0, 1.0, 0.01, 1.0)
+    assert create(good, Instance(1, 1, 0, 1.0, 1.0, 1.0, 1.0, 0.01, 1.0)) == -1     # N < 2
+    assert create(good, Instance(8, 1, 2, 1.0, 1.0, 1.0, 1.0, 0.01, 1.0)) == -1     # opacity law
+    assert create(good, Instance(8, 1, 0, 1.0, 1.0, 1.0, 1.0, 0.0, 1.0)) == -1      # dt
+    assert create(good, Instance(8, 1, 0, 1.0, 1.0, 1.0, 1.0, 0.01, -1.0)) == -1    # eps
+    assert create(good, Instance(4096, 1, 0, 1.0, 1.0, 1.0, 1.0, 0.01, 1.0)) == -5  # N > 2048
+    assert lib.grte_batch_create(0, None, mu.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
+    bad = np.array([0.5, -0.5])
+    arr = (Instance * 2)(good, good)
+    assert lib.grte_batch_create(2, arr, bad.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
+    assert lib.grte_batch_step(None, None) == -1
+    assert lib.grte_batch_tune(None, 1, None) == -1
+    assert lib.grte_batch_destroy(None) == 0

@@ -1,0 +1,165 @@
+"""Batched slabs (one persistent launch per step) against the single-slab
+path and the CPU oracle.
+
+Every instance of a batch computes the step of Algorithm 2 on its own data,
+so the batch must reproduce (i) the single-instance library step of the same
+instance to rounding (different tile partitions of the tridiagonal solves:
+FP64 bar 1e-12, or 1e-11 above a stiffness a c beta of 1e6) and (ii) the
+oracle to the same bar.  The batch is built from instances that cover both
+tile kinds (one wavefront: N <= 256; one work-group: 2, 4, 8 rows per
+thread), ragged sizes, 1 to 64 pairs, both opacity laws and eps from 1 to
+1e-5, with the generic seeded states of the parity tests.
+"""
+import numpy as np
+import pytest
+
+from oracle.ap1d import Physics, ap_step
+from paper_1811_05579_amd import Grte, GrteBatch
+from paper_1811_05579_amd.workloads import Ensemble, config4, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(x, y):
+    den = np.max(np.abs(y))
+    return float(np.max(np.abs(x - y)) / den) if den > 0 else float(np.max(np.abs(x)))
+
+
+def _stiff(w):
+    beta = 4 * w.sigma0 * w.dt * np.asarray(w.T) ** (3 - w.m) / (w.eps ** 2 * w.Cv)
+    return float(np.max(w.a * w.c * beta))
+
+
+def _tol(w):
+    return 1e-12 if _stiff(w) <= 1e6 else 1e-11
+
+
+# (N, nv, m, eps): wavefront tiles (N <= 256) and work-group tiles (M = 2, 4, 8)
+MIX = [(2, 2, 0, 1.0), (37, 16, 3, 1e-2), (64, 8, 0, 1e-4), (129, 32, 3, 1.0), (256, 64, 3, 1e-3),
+       (257, 16, 0, 1e-2), (511, 8, 3, 1e-5), (512, 32, 0, 1.0), (700, 64, 3, 1e-2),
+       (1024, 4, 3, 1e-4), (1500, 16, 0, 1e-1), (2048, 32, 3, 1e-2), (97, 128, 3, 1e-3)]
+
+
+def _mix(seed0=0):
+    ms = []
+    for q, (N, nv, m, eps) in enumerate(MIX):
+        w = random_state(N, nv, seed=seed0 + q, m=m, eps=eps)
+        w.dt = 0.5 / N
+        ms.append(w)
+    return Ensemble("mix", ms)
+
+
+def _batch(ens):
+    b = GrteBatch(ens.members)
+    pk = ens.packed()
+    b.set_opacity(pk["sigma0"])
+    b.set_inflow(pk["bL"], pk["bR"])
+    b.set_state(pk["E"], pk["O"], pk["T"])
+    return b
+
+
+def _single(w):
+    g = Grte(w.N, w.mu, w.omega, length=w.L, a=w.a, c=w.c, cv=w.Cv, opacity_law=w.m)
+    g.set_opacity(w.sigma0)
+    g.set_inflow(w.bL, w.bR)
+    g.set_state(w.E, w.O, w.T)
+    info = g.step(w.dt, w.eps, info=True)
+    out = g.get_state()
+    g.close()
+    return out, info
+
+
+@pytest.mark.parametrize("wave_max_n", [0, 128, 256])
+def test_batch_matches_single_instance(wave_max_n):
+    ens = _mix()
+    b = _batch(ens)
+    b.set_tuning(wave_max_n=wave_max_n, grid=b.get_tuning()["grid"])
+    st, infos = b.step(info=True)
+    assert st == 0, infos
+    parts = b.split(*b.get_state())
+    for w, (E, O, T), inf in zip(ens.members, parts, infos):
+        (Es, Os, Ts), si = _single(w)
+        tol = _tol(w)
+        assert abs(inf["pred_iters"] - si["pred_iters"]) <= 1, (w.name, inf, si)
+        for name, x, y in (("T", T, Ts), ("E", E, Es), ("O", O, Os)):
+            assert _rel(x, y) <= tol, (w.name, name, _rel(x, y), tol)
+    b.close()
+
+
+def test_batch_matches_oracle():
+    ens = _mix(seed0=50)
+    b = _batch(ens)
+    st, infos = b.step(info=True)
+    assert st == 0
+    parts = b.split(*b.get_state())
+    for w, (E, O, T) in zip(ens.members, parts):
+        if w.N * w.P > 20000:
+            continue     # oracle time; the large tiles are covered against the single path
+        ph = Physics(a=w.a, c=w.c, Cv=w.Cv, eps=w.eps, dt=w.dt, L=w.L, m=w.m)
+        r = ap_step(w.E, w.O, w.T, w.sigma0, w.mu, w.omega, w.bL, w.bR, ph)
+        tol = _tol(w)
+        for name, x in (("T", T), ("E", E), ("O", O)):
+            assert _rel(x, r[name]) <= tol, (w.name, name, _rel(x, r[name]), tol)
+    b.close()
+
+
+def test_graph_replay_equals_direct_launch():
+    """Captured graphs (one per state-buffer parity) replayed over several
+    steps, with eager reads in between, give the direct launches' results
+    bitwise."""
+    ens = _mix(seed0=100)
+    a = _batch(ens)
+    g = _batch(ens)
+    g.use_graph(True)
+    for s in range(4):
+        a.step()
+        g.step()
+        Ea, Oa, Ta = a.get_state()
+        Eg, Og, Tg = g.get_state()
+        assert np.array_equal(Ea, Eg) and np.array_equal(Oa, Og) and np.array_equal(Ta, Tg), s
+    a.close()
+    g.close()
+
+
+def test_tune_keeps_state_and_result():
+    ens = _mix(seed0=200)
+    ref = _batch(ens)
+    ref.step()
+    Er, Or, Tr = ref.get_state()
+    b = _batch(ens)
+    E0, O0, T0 = b.get_state()
+    t = b.tune(trials=1)
+    assert t["wave_max_n"] in (0, 128, 256) and t["grid"] >= 1 and t["step_ms"] > 0
+    E1, O1, T1 = b.get_state()
+    assert np.array_equal(E0, E1) and np.array_equal(O0, O1) and np.array_equal(T0, T1)
+    b.step()
+    E, O, T = b.get_state()
+    for w, p, q in zip(ens.members, b.split(E, O, T), b.split(Er, Or, Tr)):
+        for x, y in zip(p, q):
+            assert _rel(x, y) <= _tol(w)
+    ref.close()
+    b.close()
+
+
+def test_config4_full_batch_sampled_against_single_instance():
+    """The 4096-slab ensemble: one graph step of all instances converges, and
+    sampled instances (both tile kinds, largest and smallest) agree with the
+    single-instance path to the FP64 bar; the temperature agrees far inside the
+    1e-6 relative requirement for the batched form."""
+    ens = config4()
+    b = _batch(ens)
+    b.use_graph(True)
+    st, infos = b.step(info=True)
+    assert st == 0, [i for i in infos if not i["pred_converged"] or i["newton_failed"]][:3]
+    parts = b.split(*b.get_state())
+    Ns = np.array([w.N for w in ens.members])
+    pick = sorted(set([int(np.argmin(Ns)), int(np.argmax(Ns))] +
+                      list(np.random.default_rng(7).choice(len(ens), 10, replace=False))))
+    for i in pick:
+        w = ens.members[i]
+        (Es, Os, Ts), si = _single(w)
+        E, O, T = parts[i]
+        assert _rel(T, Ts) <= 1e-11, (i, _rel(T, Ts))
+        assert _rel(E, Es) <= 1e-11 and _rel(O, Os) <= 1e-11, (i, _rel(E, Es), _rel(O, Os))
+        assert np.max(np.abs(T - Ts) / Ts) < 1e-6
+    b.close()
