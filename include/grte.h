@@ -123,6 +123,18 @@ grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int o
  * cap. */
 grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info);
 
+/* One AP step of n independent contexts with one launch of each kernel
+ * (1 <= n <= 4; the contexts must be distinct, on one device and of the same
+ * tile shape, i.e. the same rows per thread: N in the same one of the ranges
+ * (0,512], (512,1024], (1024,2048], (2048,4096]).  Context g advances with
+ * dt[g], eps[g]; the results are those of n separate grte_step calls, bit for
+ * bit.  All work is ordered on the first context's stream (the caller orders
+ * the others' streams with it).  info (n entries) as for grte_step; the
+ * status is the worst over the contexts.  GRTE_E_UNSUPPORTED if the pairs of
+ * all contexts exceed the device's co-resident work-groups. */
+grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, const double *eps,
+                            grte_step_info *info);
+
 /* Copy a stage of the last step (GRTE_STAGE_*) into out (sizes above). */
 grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device);
 

@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import BatchInfo, BatchTuning, GrteError, Instance, Problem, StepInfo, check, load
 
-__all__ = ["Grte", "GrteBatch", "GrteError", "gauss_legendre", "load"]
+__all__ = ["Grte", "GrteBatch", "GrteError", "gauss_legendre", "load", "step_group"]
 
 
 def gauss_legendre(nv):
@@ -152,6 +152,29 @@ class Grte:
             return d
         check("grte_step", self._lib.grte_step(self._h, float(dt), float(eps), None))
         return None
+
+
+def step_group(ctxs, dts, epss, info=False):
+    """One AP step of several Grte contexts with one launch of each kernel
+    (grte_step_group); ordered on the first context's stream."""
+    n = len(ctxs)
+    lib = load()
+    hs = (ctypes.c_void_p * n)(*[c._h for c in ctxs])
+    dt = np.ascontiguousarray(dts, dtype=np.float64)
+    ep = np.ascontiguousarray(epss, dtype=np.float64)
+    if dt.size != n or ep.size != n:
+        raise ValueError("one dt and one eps per context")
+    if not info:
+        check("grte_step_group", lib.grte_step_group(hs, n, dt.ctypes.data, ep.ctypes.data, None))
+        return None
+    arr = (StepInfo * n)()
+    st = lib.grte_step_group(hs, n, dt.ctypes.data, ep.ctypes.data, arr)
+    if st not in (0, -4):
+        check("grte_step_group", st)
+    out = [a.as_dict() for a in arr]
+    for d in out:
+        d["status"] = st
+    return out
 
 
 class GrteBatch:

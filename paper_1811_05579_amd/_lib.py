@@ -56,6 +56,8 @@ _SIGS = {
     "grte_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     "grte_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     "grte_step": (c_int, [c_void_p, c_double, c_double, ctypes.POINTER(StepInfo)]),
+    "grte_step_group": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, c_void_p,
+                                ctypes.POINTER(StepInfo)]),
     "grte_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
     "grte_set_solver": (c_int, [c_void_p, c_double, c_int, c_int]),
     "grte_set_profiling": (c_int, [c_void_p, c_int]),

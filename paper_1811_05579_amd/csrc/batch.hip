@@ -43,9 +43,9 @@ enum {
     C_SRC, C_KEPS, C_USTAR, C_D, C_TNEW, NCA
 };
 
-// LDS of one tile (doubles): rho, Ll, Lu in position order + 3 W scratch
-constexpr int LDS_WG = 3 * BMAX_N + 3 * BNT;
-constexpr int LDS_WAVE = 3 * WAVE_MAX_N + 3 * WAVE;
+// LDS of one tile (doubles): rho, Ll, Lu in position order + the solver's scratch
+constexpr int LDS_WG = 3 * BMAX_N + tile_scratch<BNT>();
+constexpr int LDS_WAVE = 3 * WAVE_MAX_N + tile_scratch<WAVE>();
 static_assert(4 * LDS_WAVE <= LDS_WG, "four wavefront tiles fit in the work-group LDS");
 
 struct BInst {
@@ -220,7 +220,7 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
         lam[r] = in ? C[C_LAM * N1 + j] : 1.0;
         lmg[r] = in ? C[C_LMG * N1 + j] : 0.0;
     }
-    int it = 0, converged = 0;
+    int it = 0, converged = 0, ph = 0;
     while (true) {
         double acc[M];
 #pragma unroll
@@ -251,7 +251,7 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
             }
             TriFac<W, M> Ft;
             tri_factor<W, M>(m2, sLl, sLu, b, Ft, sh);
-            tri_solve<W, M>(m2, sLl, sLu, Ft, y, v, sh);
+            tri_solve<W, M>(m2, sLl, sLu, Ft, y, v, sh, ph);
             double *ep = Et + (size_t)p * NP;
 #pragma unroll
             for (int r = 0; r < M; ++r) {
@@ -276,7 +276,7 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
             }
             TriFac<W, M> Fd;
             tri_factor<W, M>(I.mu2, sLl, sLu, b, Fd, sh);
-            tri_solve<W, M>(I.mu2, sLl, sLu, Fd, d, f, sh);
+            tri_solve<W, M>(I.mu2, sLl, sLu, Fd, d, f, sh, ph);
         }
         double md = 0.0, mr = 0.0;
 #pragma unroll
@@ -413,7 +413,7 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
         }
         TriFac<W, M> F;
         tri_factor<W, M>(m2, sLl, sLu, b, F, sh);
-        tri_solve<W, M>(m2, sLl, sLu, F, d, x, sh);
+        tri_solve<W, M>(m2, sLl, sLu, F, d, x, sh, ph);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int j = j0 + r;

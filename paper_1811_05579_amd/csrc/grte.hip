@@ -70,6 +70,20 @@
 
 namespace {
 
+// Several contexts (independent slabs of the same tile shape) can be advanced
+// by one launch of each kernel: blockIdx.y selects the context of the
+// per-cell and per-pair kernels, and the cooperative prediction kernel maps
+// its work-groups to contexts through `first` (one work-group per pair of
+// every context, each context synchronising only its own work-groups).
+constexpr int GMAX = 4;
+
+template <class Args>
+struct Group {
+    int n;
+    int first[GMAX + 1];    // prediction: first work-group of each context
+    Args a[GMAX];
+};
+
 // -------------------------------------------------------------------------
 // coefficients: one work-group per group of cells, all pairs of those cells
 // -------------------------------------------------------------------------
@@ -85,7 +99,7 @@ struct CoefArgs {
     int M;                       // rows per thread of the prediction kernel (for Gt)
     double *Dl, *Dd, *Du;        // diffusion operator (prediction only)
     double *rho_n;               // sum_p omega_p E^n_p (prediction only)
-    double *r;                   // right-hand sides, cell-major [j*P + p]
+    double *r;                   // right-hand sides, pair-major position order [p*NT*M + row_pos(j)]
     int *stat;                   // cleared by the prediction pass
 };
 
@@ -106,7 +120,7 @@ __device__ __forceinline__ void node_coef(const CoefArgs &A, int i, double &aw, 
     }
 }
 
-__global__ void __launch_bounds__(256) coef_kernel(CoefArgs A)
+__device__ __forceinline__ void coef_body(const CoefArgs &A)
 {
     __shared__ double s_h[256], s_awr[256], s_awl[256], s_src[256], s_keps[256], s_w[256];
     const int N = A.N, P = A.P, cpb = A.cpb;
@@ -177,7 +191,7 @@ __global__ void __launch_bounds__(256) coef_kernel(CoefArgs A)
         double rv = s_keps[cl] * En + s_src[cl] - h * mu * (s_awr[cl] * On_r - s_awl[cl] * On_l);
         if (j == 0) rv += 2.0 * h * mu * A.bL[p] / A.eps;
         if (j == N - 1) rv += 2.0 * h * mu * A.bR[p] / A.eps;
-        A.r[(size_t)j * P + p] = rv;
+        A.r[(size_t)p * NT * A.M + (j % A.M) * NT + j / A.M] = rv;   // pair-major, position order
         if (A.mode == 0) s_w[t] = A.omega[p] * En;
     }
     if (A.mode == 0) {
@@ -188,6 +202,12 @@ __global__ void __launch_bounds__(256) coef_kernel(CoefArgs A)
             A.rho_n[c0 + t] = rho;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) coef_kernel(Group<CoefArgs> G)
+{
+    const CoefArgs A = G.a[blockIdx.y];
+    coef_body(A);
 }
 
 // -------------------------------------------------------------------------
@@ -213,7 +233,7 @@ struct PredArgs {
 };
 
 template <int M>
-__global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
+__device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, const int nblk)
 {
     extern __shared__ double smem[];
     constexpr int NP = NT * M;           // padded rows
@@ -221,7 +241,7 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
     double *sLl = smem + NP;             // operator coefficients (position order)
     double *sLu = smem + 2 * NP;
     double *sLmG = smem + 3 * NP;
-    double *sh = smem + 4 * NP;          // 3*NT scratch
+    double *sh = smem + 4 * NP;          // solver scratch (tile_scratch<NT>())
     const int k = threadIdx.x;
     const int N = A.N, P = A.P;
     const int j0 = k * M;
@@ -235,13 +255,11 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
     }
     const double bd0 = A.Bd[0], bdN = A.Bd[N - 1];
     __syncthreads();
-    const int p = blockIdx.x;            // one parity pair per work-group
+    const int p = bid;                   // one parity pair per work-group
     const double mu = A.mu[p], mu2 = mu * mu, wp = A.omega[p];
 
     TriFac<NT, M> Ft, Fd;
-    double rr[M], gg[M];
-#pragma unroll
-    for (int r = 0; r < M; ++r) gg[r] = A.Gt[r * NT + k];
+    const double *rp = A.r + (size_t)p * NP;   // right-hand sides of this pair (position order)
     {
         double b[M];
 #pragma unroll
@@ -251,10 +269,8 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
                 const double ll = sLl[r * NT + k], lu = sLu[r * NT + k];
                 const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
                 b[r] = A.Lam[j] + mu2 * (-(ll + lu)) + mu * bdj;
-                rr[r] = A.r[(size_t)j * P + p];
             } else {
                 b[r] = 1.0;
-                rr[r] = 0.0;
             }
         }
         tri_factor<NT, M>(mu2, sLl, sLu, b, Ft, sh);
@@ -263,17 +279,18 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
             const int j = j0 + r;
             b[r] = (j < N) ? A.Dd[j] : 1.0;
         }
+        __syncthreads();   // the two factorisations share their LDS exchange area
         tri_factor<NT, M>(A.mu2avg, sLl, sLu, b, Fd, sh);
     }
 
     // positions whose angular sum this work-group forms
-    const int chunk = (NP + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int tb = blockIdx.x * chunk;
+    const int chunk = (NP + nblk - 1) / nblk;
+    const int tb = bid * chunk;
     const int te = min(NP, tb + chunk);
     double *part_p = A.part + (size_t)p * NP;
     double *estar_p = A.estar + (size_t)p * NP;
     unsigned long long gen = A.gen0;
-    int it = 0, converged = 0;
+    int it = 0, converged = 0, ph = 0;
     while (true) {
         // ---- sweep: v_p = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho]
         double y[M], v[M];
@@ -289,19 +306,19 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
                 const double ll = sLl[t], lu = sLu[t];
                 const double q = -(ll + lu) * rj + ll * rl + lu * rn;
                 const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
-                y[r] = rr[r] - sLmG[t] * rj - mu2 * q - mu * bdj * rj;
+                y[r] = rp[t] - sLmG[t] * rj - mu2 * q - mu * bdj * rj;
             } else {
                 y[r] = 0.0;
             }
         }
-        tri_solve<NT, M>(mu2, sLl, sLu, Ft, y, v, sh);
+        tri_solve<NT, M>(mu2, sLl, sLu, Ft, y, v, sh, ph);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int t = r * NT + k;          // padded rows give v = 0
             part_p[t] = wp * v[r];
             estar_p[t] = rho[t] + v[r];        // E*_p of this sweep
         }
-        if (!grid_barrier(A.flags, ++gen, A.stat + 6)) break;
+        if (!grid_barrier(A.flags, ++gen, A.stat + 6, bid, nblk)) break;
         // ---- angular sum for my positions: res = sum_p omega_p v_p - (1 - W) rho
         for (int t = tb + k; t < te; t += NT) {
             double s = 0.0;
@@ -316,16 +333,16 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
             for (; q < P; ++q) s += A.part[(size_t)q * NP + t];
             A.res[t] = s - A.one_minus_W * rho[t];
         }
-        if (!grid_barrier(A.flags, ++gen, A.stat + 6)) break;
+        if (!grid_barrier(A.flags, ++gen, A.stat + 6, bid, nblk)) break;
         // ---- diffusion acceleration, identical in every work-group
         double rl[M], d[M], f[M];
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int t = r * NT + k;
             rl[r] = A.res[t];
-            d[r] = gg[r] * rl[r];
+            d[r] = A.Gt[t] * rl[r];
         }
-        tri_solve<NT, M>(A.mu2avg, sLl, sLu, Fd, d, f, sh);
+        tri_solve<NT, M>(A.mu2avg, sLl, sLu, Fd, d, f, sh, ph);
         double md = 0.0, mr = 0.0;
 #pragma unroll
         for (int r = 0; r < M; ++r) {
@@ -343,13 +360,22 @@ __global__ void __launch_bounds__(NT) pred_kernel(PredArgs A)
         converged = (md <= A.tol * mr) ? 1 : 0;
         if (converged || it >= A.maxit) break;
     }
-    if (blockIdx.x == 0) {
+    if (bid == 0) {
         for (int j = k; j < N; j += NT) A.rho_out[j] = rho[row_pos(j, M)];
         if (k == 0) {
             A.stat[0] = it;
             A.stat[1] = converged;
         }
     }
+}
+
+template <int M>
+__global__ void __launch_bounds__(NT) pred_kernel(Group<PredArgs> G)
+{
+    int g = 0;
+    while (g + 1 < G.n && (int)blockIdx.x >= G.first[g + 1]) ++g;
+    const PredArgs A = G.a[g];
+    pred_body<M>(A, (int)blockIdx.x - G.first[g], G.first[g + 1] - G.first[g]);
 }
 
 // -------------------------------------------------------------------------
@@ -366,8 +392,9 @@ struct NewtonArgs {
 };
 
 // E* from the position-ordered prediction output into the cell-major layout
-__global__ void __launch_bounds__(256) gather_estar_kernel(NewtonArgs A)
+__global__ void __launch_bounds__(256) gather_estar_kernel(Group<NewtonArgs> G)
 {
+    const NewtonArgs A = G.a[blockIdx.y];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int N = A.N, P = A.P;
     if (t >= N * P) return;
@@ -375,7 +402,7 @@ __global__ void __launch_bounds__(256) gather_estar_kernel(NewtonArgs A)
     A.Ecm[t] = A.estar_t[(size_t)p * NT * A.M + row_pos(j, A.M)];
 }
 
-__global__ void __launch_bounds__(256) newton_kernel(NewtonArgs A)
+__device__ __forceinline__ void newton_body(const NewtonArgs &A)
 {
     __shared__ double s_w[256], s_f[256];
     const int N = A.N, P = A.P, cpb = A.cpb;
@@ -444,6 +471,12 @@ __global__ void __launch_bounds__(256) newton_kernel(NewtonArgs A)
     atomicMax(&A.stat[2], its);
 }
 
+__global__ void __launch_bounds__(256) newton_kernel(Group<NewtonArgs> G)
+{
+    const NewtonArgs A = G.a[blockIdx.y];
+    newton_body(A);
+}
+
 // -------------------------------------------------------------------------
 // correction substep 2: E^{n+1} per pair (one work-group per pair)
 // -------------------------------------------------------------------------
@@ -454,12 +487,14 @@ struct CorrArgs {
 };
 
 template <int M>
-__global__ void __launch_bounds__(NT) corr_kernel(CorrArgs A)
+__global__ void __launch_bounds__(NT) corr_kernel(Group<CorrArgs> G)
 {
     extern __shared__ double smem[];
     constexpr int NP = NT * M;
+    const CorrArgs A = G.a[blockIdx.y];
     double *sLl = smem, *sLu = smem + NP, *sh = smem + 2 * NP;
     const int p = blockIdx.x;
+    if (p >= A.P) return;                // contexts of the group may have fewer pairs
     const int N = A.N, P = A.P, k = threadIdx.x;
     const int j0 = k * M;
     for (int j = k; j < NP; j += NT) {
@@ -476,7 +511,7 @@ __global__ void __launch_bounds__(NT) corr_kernel(CorrArgs A)
         if (j < N) {
             const double ll = sLl[r * NT + k], lu = sLu[r * NT + k];
             b[r] = A.Lam[j] + mu2 * (-(ll + lu)) + mu * A.Bd[j];
-            d[r] = A.r[(size_t)j * P + p];
+            d[r] = A.r[(size_t)p * NP + r * NT + k];
         } else {
             b[r] = 1.0;
             d[r] = 0.0;
@@ -484,7 +519,8 @@ __global__ void __launch_bounds__(NT) corr_kernel(CorrArgs A)
     }
     TriFac<NT, M> F;
     tri_factor<NT, M>(mu2, sLl, sLu, b, F, sh);
-    tri_solve<NT, M>(mu2, sLl, sLu, F, d, x, sh);
+    int ph = 0;
+    tri_solve<NT, M>(mu2, sLl, sLu, F, d, x, sh, ph);
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int j = j0 + r;
@@ -502,8 +538,9 @@ struct ProjArgs {
     double *Oout, *rho_out;
 };
 
-__global__ void __launch_bounds__(256) project_kernel(ProjArgs A)
+__global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
 {
+    const ProjArgs A = G.a[blockIdx.y];
     __shared__ double s_w[256];
     const int N = A.N, P = A.P, cpb = A.cpb;
     const int c0 = blockIdx.x * cpb, t = threadIdx.x;
@@ -542,7 +579,7 @@ struct grte_ctx {
     double one_minus_W = 0, mu1 = 0, mu2 = 0;
     double pred_tol = 1e-15;
     int pred_maxit = 200, newton_maxit = 100;
-    int pred_grid = 1;
+    int coop_capacity = 0;                 // co-resident prediction work-groups on the device
     int keep = 1;
     hipStream_t stream = nullptr;
     std::vector<double *> allocs;
@@ -635,23 +672,23 @@ grte_status prof_end(grte_ctx *ctx, int idx)
 template <int M>
 size_t pred_lds_bytes()
 {
-    return (size_t)(4 * NT * M + 3 * NT) * sizeof(double);
+    return (size_t)(4 * NT * M + tile_scratch<NT>()) * sizeof(double);
 }
 
 template <int M>
-grte_status launch_pred(grte_ctx *ctx, PredArgs &pa)
+grte_status launch_pred(hipStream_t stream, Group<PredArgs> &g, int grid)
 {
-    void *args[] = {&pa};
-    HIPCHK(hipLaunchCooperativeKernel((const void *)pred_kernel<M>, dim3(ctx->pred_grid), dim3(NT),
-                                      args, (unsigned)pred_lds_bytes<M>(), ctx->stream));
+    void *args[] = {&g};
+    HIPCHK(hipLaunchCooperativeKernel((const void *)pred_kernel<M>, dim3(grid), dim3(NT), args,
+                                      (unsigned)pred_lds_bytes<M>(), stream));
     return GRTE_OK;
 }
 
 template <int M>
-grte_status launch_corr(grte_ctx *ctx, CorrArgs &ca)
+grte_status launch_corr(hipStream_t stream, Group<CorrArgs> &g, int maxP)
 {
-    const size_t lds = (size_t)(2 * NT * M + 3 * NT) * sizeof(double);
-    hipLaunchKernelGGL(corr_kernel<M>, dim3(ctx->P), dim3(NT), lds, ctx->stream, ca);
+    const size_t lds = (size_t)(2 * NT * M + tile_scratch<NT>()) * sizeof(double);
+    hipLaunchKernelGGL(corr_kernel<M>, dim3(maxP, g.n), dim3(NT), lds, stream, g);
     HIPCHK(hipGetLastError());
     return GRTE_OK;
 }
@@ -788,7 +825,7 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     double **padded[] = {&ctx->Gt, &ctx->res};
     for (double **q : padded)
         if (st == GRTE_OK) st = alloc(ctx, q, NP);
-    double **padded_pairs[] = {&ctx->part, &ctx->estar_t};
+    double **padded_pairs[] = {&ctx->part, &ctx->estar_t, &ctx->r};
     for (double **q : padded_pairs)
         if (st == GRTE_OK) st = alloc(ctx, q, NP * P);
     for (double **q : cells)
@@ -799,7 +836,7 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     double **pairs[] = {&ctx->mu, &ctx->omega, &ctx->bL, &ctx->bR};
     for (double **q : pairs)
         if (st == GRTE_OK) st = alloc(ctx, q, P);
-    double **cp[] = {&ctx->E, &ctx->E2, &ctx->r, &ctx->estar};
+    double **cp[] = {&ctx->E, &ctx->E2, &ctx->estar};
     for (double **q : cp)
         if (st == GRTE_OK) st = alloc(ctx, q, N * P);
     double **np[] = {&ctx->O, &ctx->O2, &ctx->ostar};
@@ -829,7 +866,7 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
         grte_destroy(ctx);
         return GRTE_E_UNSUPPORTED;
     }
-    ctx->pred_grid = ctx->P;
+    ctx->coop_capacity = nb * ncu;
     ctx->cpb = std::max(1, 256 / ctx->P);
 
     if (hipMemcpy(ctx->mu, mu, P * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -927,109 +964,164 @@ grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device)
     return GRTE_E_INVAL;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One AP step of n contexts (n <= GMAX, same tile shape M) with one launch of
+// each kernel, ordered on the stream of the first context.
+grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const double *epss,
+                       grte_step_info *info)
+{
+    grte_ctx *c0 = ctxs[0];
+    hipStream_t stream = c0->stream;
+    const int M = c0->M;
+    Group<CoefArgs> gc{};
+    Group<PredArgs> gp{};
+    Group<NewtonArgs> gn{};
+    Group<CorrArgs> gr{};
+    Group<ProjArgs> gj{};
+    gc.n = gp.n = gn.n = gr.n = gj.n = n;
+    unsigned ncb_max = 1, np_max = 1, maxP = 1;
+    int grid = 0;
+    for (int g = 0; g < n; ++g) {
+        grte_ctx *ctx = ctxs[g];
+        const double dt = dts[g], eps = epss[g];
+        const int N = ctx->N, P = ctx->P;
+        const double dx = ctx->L / N;
+        ncb_max = std::max(ncb_max, (unsigned)((N + ctx->cpb - 1) / ctx->cpb));
+        np_max = std::max(np_max, (unsigned)(((size_t)N * P + 255) / 256));
+        maxP = std::max(maxP, (unsigned)P);
+        // coefficients of the prediction (K from T^n); also clears the step counters
+        CoefArgs &ca = gc.a[g];
+        ca.N = N; ca.P = P; ca.m = ctx->m; ca.mode = 0; ca.cpb = ctx->cpb;
+        ca.a = ctx->a; ca.c = ctx->c; ca.cv = ctx->cv; ca.eps = eps; ca.dt = dt; ca.dx = dx;
+        ca.T = ctx->T; ca.Tn = ctx->T; ca.sigma0 = ctx->sigma0; ca.mu = ctx->mu; ca.omega = ctx->omega;
+        ca.bL = ctx->bL; ca.bR = ctx->bR; ca.E = ctx->E; ca.O = ctx->O;
+        ca.mu1 = ctx->mu1; ca.mu2 = ctx->mu2;
+        ca.Ll = ctx->Ll; ca.Lu = ctx->Lu; ca.Lam = ctx->Lam; ca.LmG = ctx->LmG; ca.Gt = ctx->Gt; ca.M = ctx->M;
+        ca.Bd = ctx->Bd; ca.Aw = ctx->Aw; ca.Bc = ctx->Bc; ca.beta = ctx->beta;
+        ca.Dl = ctx->Dl; ca.Dd = ctx->Dd; ca.Du = ctx->Du; ca.rho_n = ctx->rho_n; ca.r = ctx->r;
+        ca.stat = ctx->stat;
+        // prediction: work-groups [grid, grid + P) belong to this context
+        PredArgs &pa = gp.a[g];
+        pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
+        pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
+        pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
+        pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
+        pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->estar_t; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
+        pa.flags = ctx->flags;
+        pa.gen0 = ctx->bar_gen;
+        ctx->bar_gen += 2ull * (unsigned long long)ctx->pred_maxit + 4ull;   // never reused
+        gp.first[g] = grid;
+        grid += P;
+        // correction substep 1
+        NewtonArgs &na = gn.a[g];
+        na.N = N; na.P = P; na.m = ctx->m; na.maxit = ctx->newton_maxit; na.keep = ctx->keep; na.cpb = ctx->cpb;
+        na.M = ctx->M; na.estar_t = ctx->estar_t; na.Ecm = ctx->estar;
+        na.a = ctx->a; na.c = ctx->c; na.cv = ctx->cv; na.eps = eps; na.dt = dt; na.dx = dx;
+        na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
+        na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;
+        na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
+        na.ostar = ctx->ostar; na.stat = ctx->stat;
+        // correction substep 2: E^{n+1} straight into the next state
+        CorrArgs &cc = gr.a[g];
+        cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
+        cc.r = ctx->r; cc.mu = ctx->mu; cc.Enew = ctx->E2;
+        // projection: O^{n+1} at the nodes, rho^{n+1}
+        ProjArgs &pj = gj.a[g];
+        pj.N = N; pj.P = P; pj.keep = ctx->keep; pj.cpb = ctx->cpb; pj.eps = eps;
+        pj.Enew = ctx->E2; pj.O = ctx->O; pj.Aw = ctx->Aw; pj.Bc = ctx->Bc;
+        pj.mu = ctx->mu; pj.omega = ctx->omega; pj.bL = ctx->bL; pj.bR = ctx->bR;
+        pj.Oout = ctx->O2; pj.rho_out = ctx->rho1;
+    }
+    gp.first[n] = grid;
+    if (grid > c0->coop_capacity) return GRTE_E_UNSUPPORTED;
+
+    int ev_step = -1, ev_pred = -1;
+    grte_status st = prof_begin(c0, GRTE_TIMING_STEP, &ev_step);
+    if (st != GRTE_OK) return st;
+    hipLaunchKernelGGL(coef_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gc);
+    HIPCHK(hipGetLastError());
+    if ((st = prof_begin(c0, GRTE_TIMING_PREDICT, &ev_pred)) != GRTE_OK) return st;
+    switch (M) {
+    case 2: st = launch_pred<2>(stream, gp, grid); break;
+    case 4: st = launch_pred<4>(stream, gp, grid); break;
+    case 8: st = launch_pred<8>(stream, gp, grid); break;
+    default: st = launch_pred<16>(stream, gp, grid); break;
+    }
+    if (st != GRTE_OK) return st;
+    if ((st = prof_end(c0, ev_pred)) != GRTE_OK) return st;
+    hipLaunchKernelGGL(gather_estar_kernel, dim3(np_max, n), dim3(256), 0, stream, gn);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(newton_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gn);
+    HIPCHK(hipGetLastError());
+    for (int g = 0; g < n; ++g) {     // coefficients of the correction: K from T^{n+1}
+        gc.a[g].mode = 1;
+        gc.a[g].T = ctxs[g]->T2;
+    }
+    hipLaunchKernelGGL(coef_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gc);
+    HIPCHK(hipGetLastError());
+    switch (M) {
+    case 2: st = launch_corr<2>(stream, gr, (int)maxP); break;
+    case 4: st = launch_corr<4>(stream, gr, (int)maxP); break;
+    case 8: st = launch_corr<8>(stream, gr, (int)maxP); break;
+    default: st = launch_corr<16>(stream, gr, (int)maxP); break;
+    }
+    if (st != GRTE_OK) return st;
+    hipLaunchKernelGGL(project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gj);
+    HIPCHK(hipGetLastError());
+    if ((st = prof_end(c0, ev_step)) != GRTE_OK) return st;   // whole step
+    for (int g = 0; g < n; ++g) {
+        grte_ctx *ctx = ctxs[g];
+        std::swap(ctx->E, ctx->E2);
+        std::swap(ctx->O, ctx->O2);
+        std::swap(ctx->T, ctx->T2);
+    }
+    if (!info) return GRTE_OK;
+    grte_status worst = GRTE_OK;
+    for (int g = 0; g < n; ++g) {
+        int h[8];
+        HIPCHK(hipMemcpyAsync(h, ctxs[g]->stat, sizeof(h), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        grte_step_info &f = info[g];
+        f.pred_iters = h[0];
+        f.pred_converged = h[1];
+        f.newton_max_iters = h[2];
+        f.newton_failed = h[3];
+        f.kstar_clamped = h[4];
+        f.negative_root = h[5];
+        f.sync_error = h[6];
+        if (h[6]) worst = GRTE_E_HIP;
+        else if ((!h[1] || h[3]) && worst == GRTE_OK) worst = GRTE_E_NOCONV;
+    }
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
 grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info)
 {
     if (!ctx || !(dt > 0) || !(eps > 0) || !std::isfinite(dt) || !std::isfinite(eps)) return GRTE_E_INVAL;
-    const int N = ctx->N, P = ctx->P;
-    const double dx = ctx->L / N;
-    const unsigned ncb = (unsigned)((N + ctx->cpb - 1) / ctx->cpb);   // work-groups of the per-cell kernels
-    int ev_step = -1, ev_pred = -1;
-    grte_status st = prof_begin(ctx, GRTE_TIMING_STEP, &ev_step);
-    if (st != GRTE_OK) return st;
+    grte_ctx *one[1] = {ctx};
+    return step_group(one, 1, &dt, &eps, info);
+}
 
-    // ---- coefficients of the prediction (K from T^n); also clears the step counters
-    CoefArgs ca{};
-    ca.N = N; ca.P = P; ca.m = ctx->m; ca.mode = 0; ca.cpb = ctx->cpb;
-    ca.a = ctx->a; ca.c = ctx->c; ca.cv = ctx->cv; ca.eps = eps; ca.dt = dt; ca.dx = dx;
-    ca.T = ctx->T; ca.Tn = ctx->T; ca.sigma0 = ctx->sigma0; ca.mu = ctx->mu; ca.omega = ctx->omega;
-    ca.bL = ctx->bL; ca.bR = ctx->bR; ca.E = ctx->E; ca.O = ctx->O;
-    ca.mu1 = ctx->mu1; ca.mu2 = ctx->mu2;
-    ca.Ll = ctx->Ll; ca.Lu = ctx->Lu; ca.Lam = ctx->Lam; ca.LmG = ctx->LmG; ca.Gt = ctx->Gt; ca.M = ctx->M;
-    ca.Bd = ctx->Bd; ca.Aw = ctx->Aw; ca.Bc = ctx->Bc; ca.beta = ctx->beta;
-    ca.Dl = ctx->Dl; ca.Dd = ctx->Dd; ca.Du = ctx->Du; ca.rho_n = ctx->rho_n; ca.r = ctx->r;
-    ca.stat = ctx->stat;
-    hipLaunchKernelGGL(coef_kernel, dim3(ncb), dim3(256), 0, ctx->stream, ca);
-    HIPCHK(hipGetLastError());
-
-    // ---- prediction
-    PredArgs pa{};
-    pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
-    pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
-    pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
-    pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
-    pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->estar_t; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
-    pa.flags = ctx->flags;
-    pa.gen0 = ctx->bar_gen;
-    ctx->bar_gen += 2ull * (unsigned long long)ctx->pred_maxit + 4ull;   // never reused
-    if ((st = prof_begin(ctx, GRTE_TIMING_PREDICT, &ev_pred)) != GRTE_OK) return st;
-    switch (ctx->M) {
-    case 2: st = launch_pred<2>(ctx, pa); break;
-    case 4: st = launch_pred<4>(ctx, pa); break;
-    case 8: st = launch_pred<8>(ctx, pa); break;
-    default: st = launch_pred<16>(ctx, pa); break;
+grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, const double *eps,
+                            grte_step_info *info)
+{
+    if (!ctxs || !dt || !eps || n < 1) return GRTE_E_INVAL;
+    if (n > GMAX) return GRTE_E_UNSUPPORTED;
+    for (int g = 0; g < n; ++g) {
+        if (!ctxs[g] || !(dt[g] > 0) || !(eps[g] > 0) || !std::isfinite(dt[g]) || !std::isfinite(eps[g]))
+            return GRTE_E_INVAL;
+        if (ctxs[g]->M != ctxs[0]->M || ctxs[g]->dev != ctxs[0]->dev) return GRTE_E_INVAL;
+        for (int h = 0; h < g; ++h)
+            if (ctxs[h] == ctxs[g]) return GRTE_E_INVAL;
     }
-    if (st != GRTE_OK) return st;
-    if ((st = prof_end(ctx, ev_pred)) != GRTE_OK) return st;
-
-    // ---- correction substep 1
-    NewtonArgs na{};
-    na.N = N; na.P = P; na.m = ctx->m; na.maxit = ctx->newton_maxit; na.keep = ctx->keep; na.cpb = ctx->cpb;
-    na.M = ctx->M; na.estar_t = ctx->estar_t; na.Ecm = ctx->estar;
-    na.a = ctx->a; na.c = ctx->c; na.cv = ctx->cv; na.eps = eps; na.dt = dt; na.dx = dx;
-    na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
-    na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;
-    na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
-    na.ostar = ctx->ostar; na.stat = ctx->stat;
-    hipLaunchKernelGGL(gather_estar_kernel, dim3((unsigned)(((size_t)N * P + 255) / 256)), dim3(256), 0,
-                       ctx->stream, na);
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(newton_kernel, dim3(ncb), dim3(256), 0, ctx->stream, na);
-    HIPCHK(hipGetLastError());
-
-    // ---- correction substep 2 (K from T^{n+1}): E^{n+1} straight into the next state
-    ca.mode = 1;
-    ca.T = ctx->T2;
-    hipLaunchKernelGGL(coef_kernel, dim3(ncb), dim3(256), 0, ctx->stream, ca);
-    HIPCHK(hipGetLastError());
-    CorrArgs cc{};
-    cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
-    cc.r = ctx->r; cc.mu = ctx->mu; cc.Enew = ctx->E2;
-    switch (ctx->M) {
-    case 2: st = launch_corr<2>(ctx, cc); break;
-    case 4: st = launch_corr<4>(ctx, cc); break;
-    case 8: st = launch_corr<8>(ctx, cc); break;
-    default: st = launch_corr<16>(ctx, cc); break;
-    }
-    if (st != GRTE_OK) return st;
-
-    // ---- projection: O^{n+1} at the nodes, rho^{n+1}
-    ProjArgs pj{};
-    pj.N = N; pj.P = P; pj.keep = ctx->keep; pj.cpb = ctx->cpb; pj.eps = eps;
-    pj.Enew = ctx->E2; pj.O = ctx->O; pj.Aw = ctx->Aw; pj.Bc = ctx->Bc;
-    pj.mu = ctx->mu; pj.omega = ctx->omega; pj.bL = ctx->bL; pj.bR = ctx->bR;
-    pj.Oout = ctx->O2; pj.rho_out = ctx->rho1;
-    hipLaunchKernelGGL(project_kernel, dim3(ncb), dim3(256), 0, ctx->stream, pj);
-    HIPCHK(hipGetLastError());
-    if ((st = prof_end(ctx, ev_step)) != GRTE_OK) return st;   // whole step
-    std::swap(ctx->E, ctx->E2);
-    std::swap(ctx->O, ctx->O2);
-    std::swap(ctx->T, ctx->T2);
-
-    if (info) {
-        int h[8];
-        HIPCHK(hipMemcpyAsync(h, ctx->stat, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
-        info->pred_iters = h[0];
-        info->pred_converged = h[1];
-        info->newton_max_iters = h[2];
-        info->newton_failed = h[3];
-        info->kstar_clamped = h[4];
-        info->negative_root = h[5];
-        info->sync_error = h[6];
-        if (h[6]) return GRTE_E_HIP;
-        if (!h[1] || h[3]) return GRTE_E_NOCONV;
-    }
-    return GRTE_OK;
+    return step_group(ctxs, n, dt, eps, info);
 }
 
 grte_status grte_set_profiling(grte_ctx *ctx, int on)

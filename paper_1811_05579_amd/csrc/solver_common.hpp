@@ -23,114 +23,50 @@ constexpr int BAR_STRIDE = 16;   // 64-bit barrier flags, one 128-byte line per 
 // traffic).  The systems solved here have off-diagonals that are a scalar
 // multiple of two LDS-resident arrays, a_j = s Lo[t], c_j = s Up[t] (zero where
 // a row has no neighbour, and in padding rows), and a per-row diagonal b_j.
-// Each chunk's interior rows 0..M-2 are eliminated by Thomas' algorithm; the
-// chunk's last rows z_k form a tridiagonal system of W rows solved by
-// parallel cyclic reduction (through LDS for W = 256, through wavefront
-// shuffles for W = 64).  What does not depend on the right-hand side -- the
-// interior pivots and the PCR multipliers -- is computed once by tri_factor and
-// kept in registers; tri_solve then costs four short FMA recurrences and one
-// PCR sweep on the right-hand side only.
-template <int W>
-struct TileLog;
-template <>
-struct TileLog<64> { static constexpr int v = 6; };
-template <>
-struct TileLog<256> { static constexpr int v = 8; };
+//
+// Partitioned elimination: each thread eliminates the interior rows 0..M-2 of
+// its chunk (Thomas), which leaves one unknown per chunk -- its last row z_k --
+// in a "reduced" tridiagonal system of W rows.  In a wavefront tile the reduced
+// system has one row per lane and is solved by parallel cyclic reduction
+// through lane shuffles.  In a work-group tile the reduced rows are published
+// in LDS once (one barrier) and every wavefront then solves the whole
+// 256-row reduced system redundantly, as a wavefront tile with four rows per
+// lane, so that each wave obtains the z values it needs without a second
+// barrier.  What does not depend on the right-hand side (interior pivots,
+// reduced coefficients, PCR multipliers) is computed by tri_factor; tri_solve
+// costs two short FMA recurrences per thread, one LDS exchange with one
+// barrier (work-group tiles), and one shuffle PCR sweep.
 
 template <int W>
 __device__ __forceinline__ int tile_lane() { return (W == 64) ? (threadIdx.x & 63) : threadIdx.x; }
 
-template <int W>
-__device__ __forceinline__ void tile_sync()
+// value of lane l + o of this wavefront (o may be negative); `dflt` outside the wave
+__device__ __forceinline__ double wave_nb(double v, int o, double dflt)
 {
-    if constexpr (W == 256) __syncthreads();
+    const int l = threadIdx.x & 63;
+    const bool in = (l + o >= 0) && (l + o < 64);
+    const double r = __shfl(v, l + o, 64);
+    return in ? r : dflt;
 }
 
-// value of tile thread k + o (o may be negative); `dflt` outside the tile
+// LDS scratch (doubles) a tile's solver needs: factor exchange (5 W) + two
+// solve exchange buffers (2 x 2 W) for work-group tiles; none for wavefronts
 template <int W>
-__device__ __forceinline__ double tile_nb(double v, int o, double dflt, double *sh)
-{
-    const int k = tile_lane<W>();
-    const bool in = (k + o >= 0) && (k + o < W);
-    if constexpr (W == 64) {
-        const double r = __shfl(v, k + o, 64);
-        return in ? r : dflt;
-    } else {
-        sh[k] = v;
-        __syncthreads();
-        const double r = in ? sh[k + o] : dflt;
-        __syncthreads();
-        return r;
-    }
-}
+constexpr int tile_scratch() { return W == 256 ? 9 * W : 16; }
 
-template <int W, int M>
-struct TriFac {
-    double inv[M - 1];          // reciprocal pivots of the interior rows
-    double k1[TileLog<W>::v], k2[TileLog<W>::v];
+// parallel cyclic reduction of a 64-row tridiagonal (row l in lane l)
+struct WavePcr {
+    double k1[6], k2[6];
     double invB;
 };
 
-template <int W, int M>
-__device__ __forceinline__ void tri_factor(double s, const double *Lo, const double *Up,
-                                           const double (&b)[M], TriFac<W, M> &F, double *sh)
+__device__ __forceinline__ void wave_pcr_factor(double Aa, double Bb, double Cc, WavePcr &F)
 {
-    static_assert(M >= 2, "at least two rows per thread");
-    constexpr int L = TileLog<W>::v;
-    const int k = tile_lane<W>();
-    double Q[M - 1], R[M - 1];   // responses of the interior to z_{k-1} (Q) and z_k (R)
-    double cprev;
-    {
-        const double a0 = s * Lo[k], c0 = s * Up[k];
-        const double inv = 1.0 / b[0];
-        F.inv[0] = inv;
-        cprev = (M > 2) ? c0 * inv : 0.0;
-        Q[0] = -a0 * inv;
-        R[0] = (M == 2) ? -c0 * inv : 0.0;
-    }
 #pragma unroll
-    for (int r = 1; r < M - 1; ++r) {
-        const double ar = s * Lo[r * W + k], cr = s * Up[r * W + k];
-        const double inv = 1.0 / (b[r] - ar * cprev);
-        F.inv[r] = inv;
-        Q[r] = -ar * Q[r - 1] * inv;
-        R[r] = ((r == M - 2 ? -cr : 0.0) - ar * R[r - 1]) * inv;
-        cprev = (r < M - 2) ? cr * inv : 0.0;
-    }
-#pragma unroll
-    for (int r = M - 3; r >= 0; --r) {
-        const double cp = s * Up[r * W + k] * F.inv[r];
-        Q[r] -= cp * Q[r + 1];
-        R[r] -= cp * R[r + 1];
-    }
-    const double ae = s * Lo[(M - 1) * W + k], ce = s * Up[(M - 1) * W + k];
-    const double Qn = tile_nb<W>(Q[0], 1, 0.0, sh);
-    const double Rn = tile_nb<W>(R[0], 1, 0.0, sh);
-    double Aa = ae * Q[M - 2];
-    double Bb = ae * R[M - 2] + b[M - 1] + ce * Qn;
-    double Cc = ce * Rn;
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < 6; ++l) {
         const int st = 1 << l;
-        double Am, Bm, Cm, Ap, Bp, Cp;
-        if constexpr (W == 64) {
-            Am = tile_nb<W>(Aa, -st, 0.0, sh);
-            Bm = tile_nb<W>(Bb, -st, 1.0, sh);
-            Cm = tile_nb<W>(Cc, -st, 0.0, sh);
-            Ap = tile_nb<W>(Aa, st, 0.0, sh);
-            Bp = tile_nb<W>(Bb, st, 1.0, sh);
-            Cp = tile_nb<W>(Cc, st, 0.0, sh);
-        } else {
-            double *sA = sh, *sB = sh + W, *sC = sh + 2 * W;
-            sA[k] = Aa;
-            sB[k] = Bb;
-            sC[k] = Cc;
-            __syncthreads();
-            Am = 0.0; Bm = 1.0; Cm = 0.0; Ap = 0.0; Bp = 1.0; Cp = 0.0;
-            if (k >= st) { Am = sA[k - st]; Bm = sB[k - st]; Cm = sC[k - st]; }
-            if (k + st < W) { Ap = sA[k + st]; Bp = sB[k + st]; Cp = sC[k + st]; }
-            __syncthreads();
-        }
+        const double Am = wave_nb(Aa, -st, 0.0), Bm = wave_nb(Bb, -st, 1.0), Cm = wave_nb(Cc, -st, 0.0);
+        const double Ap = wave_nb(Aa, st, 0.0), Bp = wave_nb(Bb, st, 1.0), Cp = wave_nb(Cc, st, 0.0);
         const double k1 = Aa / Bm, k2 = Cc / Bp;
         F.k1[l] = k1;
         F.k2[l] = k2;
@@ -141,77 +77,203 @@ __device__ __forceinline__ void tri_factor(double s, const double *Lo, const dou
     F.invB = 1.0 / Bb;
 }
 
-// forward elimination + back substitution over the interior rows 0..M-2
-template <int W, int M>
-__device__ __forceinline__ void tri_interior(double s, const double *Lo, const double *Up,
-                                             const TriFac<W, M> &F, double (&y)[M - 1])
+__device__ __forceinline__ double wave_pcr_solve(double D, const WavePcr &F)
 {
-    const int k = tile_lane<W>();
-    y[0] = y[0] * F.inv[0];
 #pragma unroll
-    for (int r = 1; r < M - 1; ++r) y[r] = (y[r] - s * Lo[r * W + k] * y[r - 1]) * F.inv[r];
-#pragma unroll
-    for (int r = M - 3; r >= 0; --r) y[r] -= s * Up[r * W + k] * F.inv[r] * y[r + 1];
+    for (int l = 0; l < 6; ++l) {
+        const int st = 1 << l;
+        const double Dm = wave_nb(D, -st, 0.0), Dp = wave_nb(D, st, 0.0);
+        D = D - F.k1[l] * Dm - F.k2[l] * Dp;
+    }
+    return D * F.invB;
 }
 
-template <int W, int M>
-__device__ __forceinline__ void tri_solve(double s, const double *Lo, const double *Up, const TriFac<W, M> &F,
-                                          const double (&d)[M], double (&x)[M], double *sh)
+// interior rows 0..M-2 of one chunk with off-diagonals a[], c[] and diagonal
+// b[]: reciprocal pivots, and the responses of the interior to the previous
+// chunk's last unknown (Q) and to this chunk's last unknown (R)
+template <int M, class GetA, class GetC>
+__device__ __forceinline__ void chunk_factor(GetA a, GetC c, const double (&b)[M], double (&inv)[M - 1],
+                                             double (&Q)[M - 1], double (&R)[M - 1])
 {
-    constexpr int L = TileLog<W>::v;
-    const int k = tile_lane<W>();
-    // interior particular solution with z_{k-1} = z_k = 0
+    static_assert(M >= 2, "at least two rows per thread");
+    double cprev;
+    {
+        const double iv = 1.0 / b[0];
+        inv[0] = iv;
+        cprev = (M > 2) ? c(0) * iv : 0.0;
+        Q[0] = -a(0) * iv;
+        R[0] = (M == 2) ? -c(0) * iv : 0.0;
+    }
+#pragma unroll
+    for (int r = 1; r < M - 1; ++r) {
+        const double ar = a(r), cr = c(r);
+        const double iv = 1.0 / (b[r] - ar * cprev);
+        inv[r] = iv;
+        Q[r] = -ar * Q[r - 1] * iv;
+        R[r] = ((r == M - 2 ? -cr : 0.0) - ar * R[r - 1]) * iv;
+        cprev = (r < M - 2) ? cr * iv : 0.0;
+    }
+#pragma unroll
+    for (int r = M - 3; r >= 0; --r) {
+        const double cp = c(r) * inv[r];
+        Q[r] -= cp * Q[r + 1];
+        R[r] -= cp * R[r + 1];
+    }
+}
+
+// forward elimination + back substitution over the interior rows 0..M-2
+template <int M, class GetA, class GetC>
+__device__ __forceinline__ void chunk_interior(GetA a, GetC c, const double (&inv)[M - 1], double (&y)[M - 1])
+{
+    y[0] = y[0] * inv[0];
+#pragma unroll
+    for (int r = 1; r < M - 1; ++r) y[r] = (y[r] - a(r) * y[r - 1]) * inv[r];
+#pragma unroll
+    for (int r = M - 3; r >= 0; --r) y[r] -= c(r) * inv[r] * y[r + 1];
+}
+
+// ---- wavefront tile, off-diagonals given by accessors a(r), c(r) of the lane's rows
+template <int M>
+struct WaveFac {
+    double inv[M - 1];
+    WavePcr pcr;
+};
+
+template <int M, class GetA, class GetC>
+__device__ __forceinline__ void wave_factor(GetA a, GetC c, const double (&b)[M], WaveFac<M> &F)
+{
+    double Q[M - 1], R[M - 1];
+    chunk_factor<M>(a, c, b, F.inv, Q, R);
+    const double Qn = wave_nb(Q[0], 1, 0.0), Rn = wave_nb(R[0], 1, 0.0);
+    const double ae = a(M - 1), ce = c(M - 1);
+    wave_pcr_factor(ae * Q[M - 2], ae * R[M - 2] + b[M - 1] + ce * Qn, ce * Rn, F.pcr);
+}
+
+template <int M, class GetA, class GetC>
+__device__ __forceinline__ void wave_solve(GetA a, GetC c, const WaveFac<M> &F, const double (&d)[M],
+                                           double (&x)[M])
+{
     double y[M - 1];
 #pragma unroll
     for (int r = 0; r < M - 1; ++r) y[r] = d[r];
-    tri_interior<W, M>(s, Lo, Up, F, y);
-    // the last interior row is not changed by back substitution
-    const double ylast = y[M - 2];
-    double D, yn;
-    if constexpr (W == 64) {
-        yn = tile_nb<W>(y[0], 1, 0.0, sh);
-    } else {
-        sh[k] = y[0];
-        __syncthreads();
-        yn = (k + 1 < W) ? sh[k + 1] : 0.0;
-    }
-    D = d[M - 1] - s * Lo[(M - 1) * W + k] * ylast - s * Up[(M - 1) * W + k] * yn;
-    // PCR on the right-hand side (two LDS buffers: one barrier per level)
-#pragma unroll
-    for (int l = 0; l < L; ++l) {
-        const int st = 1 << l;
-        double Dm, Dp;
-        if constexpr (W == 64) {
-            Dm = tile_nb<W>(D, -st, 0.0, sh);
-            Dp = tile_nb<W>(D, st, 0.0, sh);
-        } else {
-            double *bf = sh + W * (1 + (l & 1));
-            bf[k] = D;
-            __syncthreads();
-            Dm = (k >= st) ? bf[k - st] : 0.0;
-            Dp = (k + st < W) ? bf[k + st] : 0.0;
-        }
-        D = D - F.k1[l] * Dm - F.k2[l] * Dp;
-    }
-    const double z = D * F.invB;
-    double zl;
-    if constexpr (W == 64) {
-        zl = tile_nb<W>(z, -1, 0.0, sh);
-    } else {
-        sh[k] = z;
-        __syncthreads();
-        zl = (k > 0) ? sh[k - 1] : 0.0;
-        __syncthreads();
-    }
-    // interior again, now with the neighbouring chunk values folded in
+    chunk_interior<M>(a, c, F.inv, y);
+    const double yn = wave_nb(y[0], 1, 0.0);
+    const double z = wave_pcr_solve(d[M - 1] - a(M - 1) * y[M - 2] - c(M - 1) * yn, F.pcr);
+    const double zl = wave_nb(z, -1, 0.0);
 #pragma unroll
     for (int r = 0; r < M - 1; ++r) y[r] = d[r];
-    y[0] -= s * Lo[k] * zl;
-    y[M - 2] -= s * Up[(M - 2) * W + k] * z;
-    tri_interior<W, M>(s, Lo, Up, F, y);
+    y[0] -= a(0) * zl;
+    y[M - 2] -= c(M - 2) * z;
+    chunk_interior<M>(a, c, F.inv, y);
 #pragma unroll
     for (int r = 0; r < M - 1; ++r) x[r] = y[r];
     x[M - 1] = z;
+}
+
+// ---- the tile solver used by the kernels
+template <int W, int M>
+struct TriFac;
+
+template <int M>
+struct TriFac<64, M> {
+    WaveFac<M> w;
+};
+
+template <int M>
+struct TriFac<256, M> {
+    double inv[M - 1];        // interior pivots of this thread's chunk
+    WaveFac<4> red;           // the 256-row reduced system, four rows per lane (same in every wave)
+    double ra[4], rc[4];      // its off-diagonals
+    double rce[4];            // last-row super-diagonal c_e of the chunks whose reduced rows this lane holds
+};
+
+// Factor.  LDS use (work-group tiles): sh[0, 5W).  The caller must separate two
+// factorisations by a barrier (the solve in between provides one).
+template <int W, int M>
+__device__ __forceinline__ void tri_factor(double s, const double *Lo, const double *Up, const double (&b)[M],
+                                           TriFac<W, M> &F, double *sh)
+{
+    const int k = tile_lane<W>();
+    auto a = [&](int r) { return s * Lo[r * W + k]; };
+    auto c = [&](int r) { return s * Up[r * W + k]; };
+    if constexpr (W == 64) {
+        wave_factor<M>(a, c, b, F.w);
+    } else {
+        double Q[M - 1], R[M - 1];
+        chunk_factor<M>(a, c, b, F.inv, Q, R);
+        double *fA = sh, *fB = sh + W, *fC = sh + 2 * W, *fQ = sh + 3 * W, *fR = sh + 4 * W;
+        const double ae = a(M - 1), ce = c(M - 1);
+        fA[k] = ae * Q[M - 2];
+        fB[k] = ae * R[M - 2] + b[M - 1];
+        fC[k] = ce;
+        fQ[k] = Q[0];
+        fR[k] = R[0];
+        __syncthreads();
+        // reduced row kk = 4 l + i couples z_{kk-1}, z_kk, z_{kk+1}
+        const int l = threadIdx.x & 63;
+        double rb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = 4 * l + i;
+            const double cek = fC[kk];
+            const double qn = (kk + 1 < W) ? fQ[kk + 1] : 0.0;
+            const double rn = (kk + 1 < W) ? fR[kk + 1] : 0.0;
+            F.ra[i] = fA[kk];
+            rb[i] = fB[kk] + cek * qn;
+            F.rc[i] = cek * rn;
+            F.rce[i] = cek;
+        }
+        wave_factor<4>([&](int r) { return F.ra[r]; }, [&](int r) { return F.rc[r]; }, rb, F.red);
+    }
+}
+
+// Solve T x = d.  LDS use (work-group tiles): sh[5W, 9W), alternating halves
+// selected by `ph` (flipped by every call), so that one barrier per solve
+// suffices.
+template <int W, int M>
+__device__ __forceinline__ void tri_solve(double s, const double *Lo, const double *Up, const TriFac<W, M> &F,
+                                          const double (&d)[M], double (&x)[M], double *sh, int &ph)
+{
+    const int k = tile_lane<W>();
+    auto a = [&](int r) { return s * Lo[r * W + k]; };
+    auto c = [&](int r) { return s * Up[r * W + k]; };
+    if constexpr (W == 64) {
+        wave_solve<M>(a, c, F.w, d, x);
+    } else {
+        double y[M - 1];
+#pragma unroll
+        for (int r = 0; r < M - 1; ++r) y[r] = d[r];
+        chunk_interior<M>(a, c, F.inv, y);
+        double *bf = sh + 5 * W + 2 * W * ph;
+        ph ^= 1;
+        bf[k] = d[M - 1] - a(M - 1) * y[M - 2];
+        bf[W + k] = y[0];
+        __syncthreads();
+        const int l = threadIdx.x & 63;
+        double Dr[4], zr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = 4 * l + i;
+            const double yn = (kk + 1 < W) ? bf[W + kk + 1] : 0.0;
+            Dr[i] = bf[kk] - F.rce[i] * yn;
+        }
+        wave_solve<4>([&](int r) { return F.ra[r]; }, [&](int r) { return F.rc[r]; }, F.red, Dr, zr);
+        // z_k and z_{k-1} from the lanes that hold them (the same lanes in every wave)
+        const int src = k >> 2, sub = k & 3;
+        const double z0 = __shfl(zr[0], src, 64), z1 = __shfl(zr[1], src, 64);
+        const double z2 = __shfl(zr[2], src, 64), z3 = __shfl(zr[3], src, 64);
+        const double zp = __shfl(zr[3], src > 0 ? src - 1 : 0, 64);
+        const double z = sub == 0 ? z0 : sub == 1 ? z1 : sub == 2 ? z2 : z3;
+        const double zl = sub == 0 ? (k > 0 ? zp : 0.0) : sub == 1 ? z0 : sub == 2 ? z1 : z2;
+#pragma unroll
+        for (int r = 0; r < M - 1; ++r) y[r] = d[r];
+        y[0] -= a(0) * zl;
+        y[M - 2] -= c(M - 2) * z;
+        chunk_interior<M>(a, c, F.inv, y);
+#pragma unroll
+        for (int r = 0; r < M - 1; ++r) x[r] = y[r];
+        x[M - 1] = z;
+    }
 }
 
 // max over the tile of two values at once (fixed order; same result in every tile thread)
@@ -258,29 +320,31 @@ __device__ __forceinline__ double block_max(double v, double *sh)
 }
 
 // -------------------------------------------------------------------------
-// grid barrier for a cooperative launch (all work-groups co-resident)
+// barrier over a set of co-resident work-groups of a cooperative launch
 // -------------------------------------------------------------------------
-// Every work-group publishes the generation number in its own flag (no
-// contended counter); lanes of wave 0 watch one flag each.  Each thread makes
+// The set is `nblk` work-groups whose member index is `bid` (0..nblk-1), with
+// their own flag array.  Every work-group publishes the generation number in
+// its own flag (no contended counter); lanes of wave 0 watch one flag each.  Each thread makes
 // its own global writes visible at agent scope before the work-group
 // barrier, and the flag store is a release, so the writes are visible on every
 // XCD to a work-group that has observed the flag and executed the acquire.
 // The wait is bounded: on a timeout, or when another work-group has already
 // reported one, the error flag is raised and false is returned so that every
 // work-group leaves the iteration instead of hanging the device.
-__device__ __forceinline__ bool grid_barrier(unsigned long long *flags, unsigned long long gen, int *err)
+__device__ __forceinline__ bool grid_barrier(unsigned long long *flags, unsigned long long gen, int *err,
+                                             int bid, int nblk)
 {
     __shared__ int s_fail;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         s_fail = 0;
-        __hip_atomic_store(&flags[(size_t)blockIdx.x * BAR_STRIDE], gen, __ATOMIC_RELEASE,
+        __hip_atomic_store(&flags[(size_t)bid * BAR_STRIDE], gen, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     if (threadIdx.x < 64) {
         bool fail = false;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) {
+        for (int b = threadIdx.x; b < nblk; b += 64) {
             unsigned spins = 0;
             while (__hip_atomic_load(&flags[(size_t)b * BAR_STRIDE], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT) < gen) {

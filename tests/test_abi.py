@@ -114,3 +114,16 @@ def test_batch_invalid_arguments_rejected_before_device_work(lib):
     assert lib.grte_batch_step(None, None) == -1
     assert lib.grte_batch_tune(None, 1, None) == -1
     assert lib.grte_batch_destroy(None) == 0
+
+
+def test_group_step_invalid_arguments(lib):
+    from paper_1811_05579_amd._lib import StepInfo
+    dt = np.array([0.1])
+    ep = np.array([1.0])
+    assert lib.grte_step_group(None, 1, dt.ctypes.data, ep.ctypes.data, None) == -1
+    hs = (ctypes.c_void_p * 1)(None)
+    assert lib.grte_step_group(hs, 1, dt.ctypes.data, ep.ctypes.data, None) == -1
+    assert lib.grte_step_group(hs, 0, dt.ctypes.data, ep.ctypes.data, None) == -1
+    hs5 = (ctypes.c_void_p * 5)()
+    d5 = np.full(5, 0.1)
+    assert lib.grte_step_group(hs5, 5, d5.ctypes.data, d5.ctypes.data, None) == -5

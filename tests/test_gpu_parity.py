@@ -202,3 +202,25 @@ def test_device_tensors_and_stream():
     assert _rel(E.cpu().numpy(), ref["E"]) <= TOL
     assert _rel(O.cpu().numpy(), ref["O"]) <= TOL
     g.close()
+
+
+def test_group_step_equals_separate_steps():
+    """Three slabs advanced by one grouped launch per kernel give, bit for bit,
+    what three separate steps give (the config-2 eps runs at a reduced size)."""
+    from paper_1811_05579_amd import step_group
+    ws = [config2(eps=e, N=600, nv=32) for e in (1.0, 1e-2, 1e-4)]
+    sep = [_ctx(w) for w in ws]
+    grp = [_ctx(w) for w in ws]
+    for w, a, b in zip(ws, sep, grp):
+        a.set_state(w.E, w.O, w.T)
+        b.set_state(w.E, w.O, w.T)
+    for s in range(5):
+        for w, a in zip(ws, sep):
+            assert a.step(w.dt, w.eps, info=True)["status"] == 0
+        infos = step_group(grp, [w.dt for w in ws], [w.eps for w in ws], info=True)
+        assert all(i["status"] == 0 for i in infos)
+        for a, b in zip(sep, grp):
+            for x, y in zip(a.get_state(), b.get_state()):
+                assert np.array_equal(x, y), s
+    for g in sep + grp:
+        g.close()
