@@ -68,6 +68,13 @@ typedef struct grte_step_info {
     int negative_root;    /* cells whose temperature equation has no root >= 0  */
     int sync_error;       /* 1 if a grid barrier of the prediction timed out
                              (the step's results are then invalid; GRTE_E_HIP) */
+    int guess_accepted;   /* cells whose learned starting value already met the
+                             residual bound (no Newton step taken)             */
+    int guess_rejected;   /* cells whose learned start was unusable, had a
+                             larger residual than T^n, or whose Newton from it
+                             hit the cap: solved from T^n                      */
+    int newton_total_iters; /* Newton iterations summed over the cells         */
+    int guess_started;    /* cells whose Newton started from the learned value */
 } grte_step_info;
 
 /* Stages readable after a step (grte_get_stage), for checking and diagnostics. */
@@ -155,6 +162,58 @@ grte_status grte_set_profiling(grte_ctx *ctx, int on);
  * elapsed milliseconds and the number of timed launches since profiling was
  * enabled or last read (arrays of GRTE_TIMING_NSTAGES entries); clears the log. */
 grte_status grte_read_timing(grte_ctx *ctx, double *total_ms, int *count);
+
+/* ------------------------------------------------------------------------
+ * Learned initial guess of the temperature solve (4.13)/(5.5).
+ *
+ * A multilayer perceptron 5 -> 64 -> 64 -> 1 with exact gelu activations maps
+ * f = log10(rho*, T^n, sigma0 (T^n)^-m, eps, dt), standardised with
+ * (mu_f, sd_f), to y; the starting value is T0 = T^n exp(mu_t + sd_t y).
+ * Inference uses the weights rounded to bfloat16 (nearest even) with binary32
+ * accumulation.  Every guess is judged by the normalised residual
+ * |alpha T0^4 + T0 - s| / max(|s|, tiny) of (4.13) (alpha T^4 + T - s = 0):
+ * at or below the acceptance bound it is the result; otherwise Newton starts
+ * from T0 if its residual is below that of T^n.  If T0 is not a positive
+ * finite number, is the worse start, or Newton from it hits its cap, plain
+ * Newton from T^n decides (grte_step_info counts each case).
+ *
+ * Parameters: 4609 binary32 values, W1 (64x5 row-major), b1 (64), W2 (64x64,
+ * row = output unit), b2 (64), W3 (64), b3 (1).  Normalisation: 12 values
+ * mu_f[5], sd_f[5], mu_t, sd_t.  Training rows: 6 binary32 values
+ * (f_0..f_4, log(T^{n+1}/T^n)), row-major, device memory.  Training is Adam
+ * (beta 0.9/0.999, eps 1e-8) on the mean squared error of the standardised
+ * target, binary32 master parameters, minibatches taken in row order
+ * (wrapping; shuffle the rows beforehand).
+ * ------------------------------------------------------------------------ */
+typedef struct grte_mlp grte_mlp;
+grte_status grte_mlp_create(grte_mlp **out);        /* zero parameters, unit normalisation */
+grte_status grte_mlp_destroy(grte_mlp *m);
+grte_status grte_mlp_set_stream(grte_mlp *m, void *hip_stream);
+/* Host parameters in (4609); resets the Adam moments and step count. */
+grte_status grte_mlp_set_params(grte_mlp *m, const float *theta);
+/* Host copies out: binary32 master values and/or their bfloat16 bit patterns
+ * (either pointer may be NULL). */
+grte_status grte_mlp_get_params(grte_mlp *m, float *theta, unsigned short *theta_bf16);
+grte_status grte_mlp_set_norm(grte_mlp *m, const float *norm);   /* 12 host values, sd > 0 */
+grte_status grte_mlp_get_norm(grte_mlp *m, float *norm);
+/* Normalisation from n >= 2 training rows (column means and standard deviations). */
+grte_status grte_mlp_fit_norm(grte_mlp *m, const float *dev_rows, long long n);
+/* Loss and gradient (host, 4609) of the mean squared error over n rows. */
+grte_status grte_mlp_grad(grte_mlp *m, const float *dev_rows, long long n, float *grad, float *loss);
+/* `steps` Adam steps with minibatches of `batch` rows and learning rate lr;
+ * loss_hist (host, may be NULL) receives the minibatch loss of each step. */
+grte_status grte_mlp_train(grte_mlp *m, const float *dev_rows, long long n, int steps, int batch,
+                           float lr, float *loss_hist);
+/* Network outputs y (device, n) for the feature columns of n rows. */
+grte_status grte_mlp_predict(grte_mlp *m, const float *dev_rows, long long n, float *dev_y);
+/* Use `model` (NULL: plain Newton from T^n) for the temperature solve of
+ * later steps of ctx, with acceptance bound accept_tol (e.g. 1e-10).  The
+ * model is borrowed: it must outlive its use and not be trained meanwhile. */
+grte_status grte_set_guess(grte_ctx *ctx, const grte_mlp *model, double accept_tol);
+/* Training rows of the last step (one per cell, N rows) into dev_rows
+ * (capacity cap_rows >= N); cells with sigma0 = 0 give a zero row.  Requires a
+ * step since the last grte_set_state.  Enqueued on the context's stream. */
+grte_status grte_log_pairs(grte_ctx *ctx, float *dev_rows, long long cap_rows, long long *n_rows);
 
 /* Static text for a status code. */
 const char *grte_status_string(grte_status s);

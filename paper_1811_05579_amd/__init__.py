@@ -15,7 +15,7 @@ import numpy as np
 from . import _lib
 from ._lib import BatchInfo, BatchTuning, GrteError, Instance, Problem, StepInfo, check, load
 
-__all__ = ["Grte", "GrteBatch", "GrteError", "gauss_legendre", "load", "step_group"]
+__all__ = ["Grte", "GrteBatch", "GrteError", "Mlp", "gauss_legendre", "load", "step_group"]
 
 
 def gauss_legendre(nv):
@@ -139,6 +139,20 @@ class Grte:
         check("grte_read_timing", self._lib.grte_read_timing(self._h, ms.ctypes.data, cnt.ctypes.data))
         return {k: (float(ms[v]), int(cnt[v])) for k, v in _lib.TIMING.items()}
 
+    def set_guess(self, model, accept_tol=1e-10):
+        """Learned initial guess for the temperature solve (None: Newton from T^n)."""
+        h = model._h if model is not None else None
+        check("grte_set_guess", self._lib.grte_set_guess(self._h, h, float(accept_tol)))
+
+    def log_pairs(self, rows):
+        """Write the last step's training rows into the float32 CUDA tensor
+        `rows` (shape (>= N, 6)); returns the number of rows written."""
+        _check_rows(rows, self.N)
+        n = ctypes.c_longlong()
+        check("grte_log_pairs", self._lib.grte_log_pairs(self._h, ctypes.c_void_p(rows.data_ptr()),
+                                                         rows.shape[0], ctypes.byref(n)))
+        return int(n.value)
+
     def step(self, dt, eps, info=False):
         """One AP step.  With info=True, synchronise and return the step
         diagnostics (dict, including 'status'); otherwise only enqueue."""
@@ -152,6 +166,96 @@ class Grte:
             return d
         check("grte_step", self._lib.grte_step(self._h, float(dt), float(eps), None))
         return None
+
+
+def _check_rows(rows, n_min=1):
+    import torch
+    if (not isinstance(rows, torch.Tensor) or rows.dtype != torch.float32 or not rows.is_cuda
+            or rows.dim() != 2 or rows.shape[1] != 6 or not rows.is_contiguous() or rows.shape[0] < n_min):
+        raise ValueError("rows: need a contiguous float32 CUDA tensor of shape (n, 6)")
+
+
+class Mlp:
+    """Learned Newton initial guess (5 -> 64 -> 64 -> 1, gelu); parameters and
+    training live on the GPU (grte_mlp_*)."""
+
+    N_PARAM = 4609
+    N_NORM = 12
+
+    def __init__(self):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        check("grte_mlp_create", self._lib.grte_mlp_create(ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.grte_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        raw = getattr(stream, "cuda_stream", stream)
+        check("grte_mlp_set_stream", self._lib.grte_mlp_set_stream(self._h, ctypes.c_void_p(int(raw))))
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != self.N_PARAM:
+            raise ValueError(f"need {self.N_PARAM} parameters")
+        check("grte_mlp_set_params", self._lib.grte_mlp_set_params(self._h, th.ctypes.data))
+
+    def get_params(self):
+        """(binary32 master parameters, their bfloat16 bit patterns as uint16)."""
+        th = np.empty(self.N_PARAM, dtype=np.float32)
+        bf = np.empty(self.N_PARAM, dtype=np.uint16)
+        check("grte_mlp_get_params", self._lib.grte_mlp_get_params(self._h, th.ctypes.data, bf.ctypes.data))
+        return th, bf
+
+    def set_norm(self, norm):
+        nm = np.ascontiguousarray(norm, dtype=np.float32)
+        check("grte_mlp_set_norm", self._lib.grte_mlp_set_norm(self._h, nm.ctypes.data))
+
+    def get_norm(self):
+        nm = np.empty(self.N_NORM, dtype=np.float32)
+        check("grte_mlp_get_norm", self._lib.grte_mlp_get_norm(self._h, nm.ctypes.data))
+        return nm
+
+    def fit_norm(self, rows):
+        _check_rows(rows, 2)
+        check("grte_mlp_fit_norm", self._lib.grte_mlp_fit_norm(self._h, ctypes.c_void_p(rows.data_ptr()),
+                                                               rows.shape[0]))
+
+    def grad(self, rows):
+        """(loss, gradient) of the mean squared error over all rows."""
+        _check_rows(rows)
+        g = np.empty(self.N_PARAM, dtype=np.float32)
+        loss = ctypes.c_float()
+        check("grte_mlp_grad", self._lib.grte_mlp_grad(self._h, ctypes.c_void_p(rows.data_ptr()), rows.shape[0],
+                                                       g.ctypes.data, ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def train(self, rows, steps, batch=4096, lr=1e-3):
+        """Adam steps on minibatches of consecutive rows; returns the loss history."""
+        _check_rows(rows)
+        hist = np.empty(int(steps), dtype=np.float32)
+        check("grte_mlp_train", self._lib.grte_mlp_train(self._h, ctypes.c_void_p(rows.data_ptr()), rows.shape[0],
+                                                         int(steps), int(batch), ctypes.c_float(lr),
+                                                         hist.ctypes.data))
+        return hist
+
+    def predict(self, rows):
+        """Network outputs y (float32 CUDA tensor) for the feature columns of rows."""
+        import torch
+        _check_rows(rows)
+        y = torch.empty(rows.shape[0], dtype=torch.float32, device=rows.device)
+        check("grte_mlp_predict", self._lib.grte_mlp_predict(self._h, ctypes.c_void_p(rows.data_ptr()),
+                                                             rows.shape[0], ctypes.c_void_p(y.data_ptr())))
+        return y
 
 
 def step_group(ctxs, dts, epss, info=False):

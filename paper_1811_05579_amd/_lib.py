@@ -23,7 +23,8 @@ class Problem(ctypes.Structure):
 class StepInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
                 ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int),
-                ("sync_error", c_int)]
+                ("sync_error", c_int), ("guess_accepted", c_int), ("guess_rejected", c_int),
+                ("newton_total_iters", c_int), ("guess_started", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -63,6 +64,20 @@ _SIGS = {
     "grte_set_profiling": (c_int, [c_void_p, c_int]),
     "grte_read_timing": (c_int, [c_void_p, c_void_p, c_void_p]),
     "grte_status_string": (ctypes.c_char_p, [c_int]),
+    "grte_mlp_create": (c_int, [ctypes.POINTER(c_void_p)]),
+    "grte_mlp_destroy": (c_int, [c_void_p]),
+    "grte_mlp_set_stream": (c_int, [c_void_p, c_void_p]),
+    "grte_mlp_set_params": (c_int, [c_void_p, c_void_p]),
+    "grte_mlp_get_params": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "grte_mlp_set_norm": (c_int, [c_void_p, c_void_p]),
+    "grte_mlp_get_norm": (c_int, [c_void_p, c_void_p]),
+    "grte_mlp_fit_norm": (c_int, [c_void_p, c_void_p, ctypes.c_longlong]),
+    "grte_mlp_grad": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_void_p, c_void_p]),
+    "grte_mlp_train": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, ctypes.c_float,
+                               c_void_p]),
+    "grte_mlp_predict": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_void_p]),
+    "grte_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
+    "grte_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
     "grte_batch_create": (c_int, [c_int, ctypes.POINTER(Instance), c_void_p, c_void_p,
                                   ctypes.POINTER(c_void_p)]),
     "grte_batch_destroy": (c_int, [c_void_p]),

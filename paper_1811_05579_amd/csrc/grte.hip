@@ -67,6 +67,7 @@
 #include "../../include/grte.h"
 
 #include "solver_common.hpp"
+#include "mlp_common.hpp"
 
 namespace {
 
@@ -76,6 +77,7 @@ namespace {
 // its work-groups to contexts through `first` (one work-group per pair of
 // every context, each context synchronising only its own work-groups).
 constexpr int GMAX = 4;
+constexpr int NSTAT = 16;    // per-step counters of a context
 
 template <class Args>
 struct Group {
@@ -126,7 +128,7 @@ __device__ __forceinline__ void coef_body(const CoefArgs &A)
     const int N = A.N, P = A.P, cpb = A.cpb;
     const int c0 = blockIdx.x * cpb;
     const int t = threadIdx.x;
-    if (A.mode == 0 && blockIdx.x == 0 && t < 8) A.stat[t] = 0;
+    if (A.mode == 0 && blockIdx.x == 0 && t < NSTAT) A.stat[t] = 0;
     // ---- per cell
     if (t < cpb && c0 + t < N) {
         const int j = c0 + t;
@@ -387,9 +389,31 @@ struct NewtonArgs {
     const double *estar_t;   // E*, pair-major, position order (prediction output)
     const double *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
     double *Ecm;             // E* copied to cell-major order (read by the node relations)
-    double *Tnew, *ustar, *Dv, *ostar;
-    int *stat;   // [2] max its, [3] failed, [4] K* clamped, [5] negative root
+    double *Tnew, *ustar, *Dv, *ostar, *rstar;
+    const uint16_t *gw;      // learned initial guess: bfloat16 weights (null: Newton from T^n)
+    const float *gnorm;      // and its normalisation
+    double gtol;             // residual below which the guess is taken as the root
+    int *stat;   // [2] max its, [3] failed, [4] K* clamped, [5] negative root,
+                 // [7] guesses accepted, [8] guesses not used (Newton from T^n), [9] sum of Newton its,
+                 // [10] Newton started from the guess
 };
+
+// Newton on g(T) = q4 T^4 + lin (T - Tn) - rhs from T0; false if the cap is hit
+__device__ __forceinline__ bool newton_quartic(double T0, double Tn, double q4, double lin, double rhs, int maxit,
+                                               double &T, int &its)
+{
+    T = T0;
+    for (int k = 0; k < maxit; ++k) {
+        const double T2 = T * T;
+        const double g = q4 * T2 * T2 + lin * (T - Tn) - rhs;
+        const double dg = 4.0 * q4 * T2 * T + lin;
+        const double step = g / dg;
+        T -= step;
+        ++its;
+        if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(Tn))) return true;
+    }
+    return false;
+}
 
 // E* from the position-ordered prediction output into the cell-major layout
 __global__ void __launch_bounds__(256) gather_estar_kernel(Group<NewtonArgs> G)
@@ -402,7 +426,7 @@ __global__ void __launch_bounds__(256) gather_estar_kernel(Group<NewtonArgs> G)
     A.Ecm[t] = A.estar_t[(size_t)p * NT * A.M + row_pos(j, A.M)];
 }
 
-__device__ __forceinline__ void newton_body(const NewtonArgs &A)
+__device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t *sW, const float *sN)
 {
     __shared__ double s_w[256], s_f[256];
     const int N = A.N, P = A.P, cpb = A.cpb;
@@ -451,30 +475,73 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A)
     const double lin = A.cv * (A.eps * A.eps * Ks + A.c * s0 * A.dt);
     const double q4 = ac * s0 * A.dt;
     const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
+    A.rstar[j] = rho;
     double T = Tn;
     int its = 0;
     if (!(s0 == 0.0 && Ks == 0.0)) {
         if (Tn + rhs / lin < 0.0) atomicAdd(&A.stat[5], 1);   // no root >= 0
-        bool ok = false;
-        for (its = 0; its < A.maxit;) {
-            const double T2 = T * T;
-            const double g = q4 * T2 * T2 + lin * (T - Tn) - rhs;
-            const double dg = 4.0 * q4 * T2 * T + lin;
-            const double step = g / dg;
-            T -= step;
-            ++its;
-            if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(Tn))) { ok = true; break; }
+        bool ok = false, done = false;
+        if (A.gw && s0 > 0.0 && Tn > 0.0) {
+            // learned starting value; judged by the normalised residual of (4.13)
+            float f[MLP_IN];
+            mlp_features(rho, Tn, s0, A.m, A.eps, A.dt, f);
+            const float y = mlp_eval(sW, sN, f);
+            const double Tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
+            if (isfinite(Tg) && Tg > 0.0) {
+                // normalised residuals of the guess and of T^n
+                const double T2 = Tg * Tg;
+                const double rg = fabs(q4 * T2 * T2 + lin * (Tg - Tn) - rhs) / lin;
+                const double Tn2 = Tn * Tn;
+                const double rn = fabs(q4 * Tn2 * Tn2 - rhs) / lin;
+                if (rg <= A.gtol * fmax(fabs(Tn + rhs / lin), 1e-300)) {
+                    T = Tg;
+                    ok = done = true;
+                    atomicAdd(&A.stat[7], 1);
+                } else if (rg < rn) {
+                    ok = done = newton_quartic(Tg, Tn, q4, lin, rhs, A.maxit, T, its);
+                    if (done) atomicAdd(&A.stat[10], 1);
+                }
+            }
+            if (!done) atomicAdd(&A.stat[8], 1);
         }
+        if (!done) ok = newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its);   // plain: from T^n
         if (!ok) atomicAdd(&A.stat[3], 1);
     }
     A.Tnew[j] = T;
     atomicMax(&A.stat[2], its);
+    atomicAdd(&A.stat[9], its);
 }
 
 __global__ void __launch_bounds__(256) newton_kernel(Group<NewtonArgs> G)
 {
+    __shared__ uint16_t sW[MLP_NPARAM + 3];
+    __shared__ float sN[MLP_NNORM];
     const NewtonArgs A = G.a[blockIdx.y];
-    newton_body(A);
+    if (A.gw) {
+        for (int e = threadIdx.x; e < MLP_NPARAM; e += 256) sW[e] = A.gw[e];
+        if (threadIdx.x < MLP_NNORM) sN[threadIdx.x] = A.gnorm[threadIdx.x];
+        __syncthreads();
+    }
+    newton_body(A, sW, sN);
+}
+
+// training rows (f_0..f_4, log(T^{n+1}/T^n)) of the last step, binary32;
+// cells without a defined input (sigma0 = 0 or T <= 0) give a zero row
+__global__ void log_pairs_kernel(int N, int m, double eps, double dt, const double *rstar, const double *Told,
+                                 const double *Tnew, const double *sigma0, float *out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const double t0 = Told[j], t1 = Tnew[j], s0 = sigma0[j];
+    float f[MLP_IN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float tg = 0.0f;
+    if (s0 > 0.0 && t0 > 0.0 && t1 > 0.0) {
+        mlp_features(rstar[j], t0, s0, m, eps, dt, f);
+        tg = (float)log(t1 / t0);
+    }
+#pragma unroll
+    for (int q = 0; q < MLP_IN; ++q) out[(size_t)j * 6 + q] = f[q];
+    out[(size_t)j * 6 + 5] = tg;
 }
 
 // -------------------------------------------------------------------------
@@ -588,7 +655,13 @@ struct grte_ctx {
     double *sigma0, *mu, *omega, *bL, *bR;
     double *Ll, *Lu, *Lam, *LmG, *Gt, *Bd, *Aw, *Bc, *beta, *Dl, *Dd, *Du, *rho_n;
     double *r, *part, *res, *estar_t, *estar, *rho;
-    double *ustar, *Dv, *ostar, *rho1;
+    double *ustar, *Dv, *ostar, *rho1, *rstar;
+    // learned initial guess of the temperature solve (borrowed from a grte_mlp)
+    const uint16_t *guess_w = nullptr;
+    const float *guess_norm = nullptr;
+    double guess_tol = 1e-10;
+    double last_dt = 0, last_eps = 0;      // of the last step (training-pair log)
+    int stepped = 0;
     unsigned long long *flags = nullptr;   // grid-barrier flags of the prediction kernel
     unsigned long long bar_gen = 0;        // generations used so far (strictly increasing)
     int cpb = 1;                           // cells per work-group of the per-cell kernels
@@ -820,7 +893,7 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     grte_status st = GRTE_OK;
     double **cells[] = {&ctx->T, &ctx->T2, &ctx->sigma0, &ctx->Ll, &ctx->Lu, &ctx->Lam,
                         &ctx->LmG, &ctx->Bd, &ctx->beta, &ctx->Dl, &ctx->Dd, &ctx->Du,
-                        &ctx->rho_n, &ctx->rho, &ctx->ustar, &ctx->Dv, &ctx->rho1};
+                        &ctx->rho_n, &ctx->rho, &ctx->ustar, &ctx->Dv, &ctx->rho1, &ctx->rstar};
     const size_t NP = (size_t)NT * ctx->M;    // padded rows of the solvers
     double **padded[] = {&ctx->Gt, &ctx->res};
     for (double **q : padded)
@@ -845,7 +918,7 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     double *flagmem = nullptr;
     if (st == GRTE_OK) st = alloc(ctx, &flagmem, (size_t)MAX_P * BAR_STRIDE);
     ctx->flags = (unsigned long long *)flagmem;
-    if (st == GRTE_OK && hipMalloc((void **)&ctx->stat, 8 * sizeof(int)) != hipSuccess) st = GRTE_E_NOMEM;
+    if (st == GRTE_OK && hipMalloc((void **)&ctx->stat, NSTAT * sizeof(int)) != hipSuccess) st = GRTE_E_NOMEM;
     if (st != GRTE_OK) { grte_destroy(ctx); return st; }
 
     // co-resident blocks for the cooperative prediction kernel
@@ -933,6 +1006,7 @@ grte_status grte_set_state(grte_ctx *ctx, const double *E, const double *O, cons
         for (int j = 0; j < ctx->N; ++j)
             if (!(T[j] >= 0) || !std::isfinite(T[j])) return GRTE_E_INVAL;
     const size_t N = ctx->N, P = ctx->P;
+    ctx->stepped = 0;                      // the pair log refers to a step from this state on
     grte_status s = copy_in(ctx, ctx->E, E, N * P, on_device);
     if (s == GRTE_OK) s = copy_in(ctx, ctx->O, O, (N + 1) * P, on_device);
     if (s == GRTE_OK) s = copy_in(ctx, ctx->T, T, N, on_device);
@@ -1023,7 +1097,11 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
         na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;
         na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
-        na.ostar = ctx->ostar; na.stat = ctx->stat;
+        na.ostar = ctx->ostar; na.stat = ctx->stat; na.rstar = ctx->rstar;
+        na.gw = ctx->guess_w; na.gnorm = ctx->guess_norm; na.gtol = ctx->guess_tol;
+        ctx->last_dt = dt;
+        ctx->last_eps = eps;
+        ctx->stepped = 1;
         // correction substep 2: E^{n+1} straight into the next state
         CorrArgs &cc = gr.a[g];
         cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
@@ -1081,7 +1159,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     if (!info) return GRTE_OK;
     grte_status worst = GRTE_OK;
     for (int g = 0; g < n; ++g) {
-        int h[8];
+        int h[NSTAT];
         HIPCHK(hipMemcpyAsync(h, ctxs[g]->stat, sizeof(h), hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         grte_step_info &f = info[g];
@@ -1092,6 +1170,10 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         f.kstar_clamped = h[4];
         f.negative_root = h[5];
         f.sync_error = h[6];
+        f.guess_accepted = h[7];
+        f.guess_rejected = h[8];
+        f.newton_total_iters = h[9];
+        f.guess_started = h[10];
         if (h[6]) worst = GRTE_E_HIP;
         else if ((!h[1] || h[3]) && worst == GRTE_OK) worst = GRTE_E_NOCONV;
     }
@@ -1122,6 +1204,30 @@ grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, cons
             if (ctxs[h] == ctxs[g]) return GRTE_E_INVAL;
     }
     return step_group(ctxs, n, dt, eps, info);
+}
+
+grte_status grte_set_guess(grte_ctx *ctx, const grte_mlp *model, double accept_tol)
+{
+    if (!ctx || !(accept_tol >= 0) || !std::isfinite(accept_tol)) return GRTE_E_INVAL;
+    ctx->guess_w = model ? model->wbf : nullptr;
+    ctx->guess_norm = model ? model->norm : nullptr;
+    ctx->guess_tol = accept_tol;
+    return GRTE_OK;
+}
+
+grte_status grte_log_pairs(grte_ctx *ctx, float *dev_rows, long long cap_rows, long long *n_rows)
+{
+    if (!ctx || !dev_rows || !n_rows) return GRTE_E_INVAL;
+    *n_rows = 0;
+    if (!ctx->stepped) return GRTE_E_INVAL;
+    if (cap_rows < ctx->N) return GRTE_E_INVAL;
+    // after the step the previous temperature sits in the second buffer
+    hipLaunchKernelGGL(log_pairs_kernel, dim3((unsigned)((ctx->N + 255) / 256)), dim3(256), 0, ctx->stream,
+                       ctx->N, ctx->m, ctx->last_eps, ctx->last_dt, ctx->rstar, ctx->T2, ctx->T, ctx->sigma0,
+                       dev_rows);
+    HIPCHK(hipGetLastError());
+    *n_rows = ctx->N;
+    return GRTE_OK;
 }
 
 grte_status grte_set_profiling(grte_ctx *ctx, int on)

@@ -18,6 +18,12 @@ seed (numpy PCG64, seed 18110000 + configuration number).
             10^U[-1, 2] per slab with sigma = sigma0 T^-3, the initial and inflow
             data of config 1, dt = 0.5 / N.
 
+  config 5  (one-dimensional analogue of the two-material learned-guess case)
+            N = 512, 64 ordinates, sigma in {1, 1000} (m = 0) piecewise
+            constant on the cells nearest to 64 seeded sites in [0, 1], each site
+            taking either value with probability 1/2, eps = 1e-4, the initial
+            and inflow data of config 1, dt = 0.5 dx.
+
 The velocity grid (Gauss-Legendre pairs: positive nodes by increasing mu,
 weight of +mu on [-1, 1], so the weights sum to one) is part of the input:
 both the oracle and the GPU library receive these exact binary64 values.
@@ -159,3 +165,24 @@ def config4(n=4096, N_lo=64, N_hi=2048, nvs=(8, 16, 32, 64), seed=SEED_BASE + 4)
         members.append(_slab(f"config4[{i}]", N, int(nv[i]), 3, float(eps[i]), 100,
                              np.full(N, s0[i])))
     return Ensemble(name=f"config4(n={n})", members=members)
+
+
+def config5_1d(N=512, nv=64, steps=200, seed=SEED_BASE + 5):
+    """Two-material slab: sigma in {1, 1000} on seeded nearest-site regions."""
+    rng = np.random.default_rng(seed)
+    sites = rng.uniform(0.0, 1.0, 64)
+    vals = np.where(rng.uniform(0.0, 1.0, 64) < 0.5, 1.0, 1000.0)
+    xc = (np.arange(N) + 0.5) / N
+    nearest = np.argmin(np.abs(xc[:, None] - sites[None, :]), axis=1)   # ties -> lower index
+    return _slab("config5_1d", N, nv, 0, 1e-4, steps, vals[nearest])
+
+
+def mlp_init(seed=SEED_BASE + 9, scale=1.0):
+    """Seeded initial parameters of the 5-64-64-1 guess network (uniform,
+    fan-in scaled), float32; biases zero."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.uniform(-1, 1, (64, 5)) * scale / np.sqrt(5)
+    w2 = rng.uniform(-1, 1, (64, 64)) * scale / np.sqrt(64)
+    w3 = rng.uniform(-1, 1, 64) * scale / np.sqrt(64)
+    th = np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, [0.0]])
+    return th.astype(np.float32)
