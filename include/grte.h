@@ -142,6 +142,16 @@ grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info
 grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, const double *eps,
                             grte_step_info *info);
 
+/* Storage of the intensity state: 0 = binary64 (default); 1 = binary32, with
+ * E kept per cell and pair as its binary32 deviation from a c T^4 (T stays
+ * binary64) and O in binary32.  The prediction, Newton and correction
+ * arithmetic, the angular sums (binary64 accumulation of the widened
+ * values) and T stay binary64; only the stored E and O are rounded, once per
+ * step.  The current state is converted; grte_set_state / grte_get_state keep
+ * exchanging binary64 arrays (get_state returns the values the binary32
+ * storage represents). */
+grte_status grte_set_storage(grte_ctx *ctx, int fp32);
+
 /* Copy a stage of the last step (GRTE_STAGE_*) into out (sizes above). */
 grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device);
 

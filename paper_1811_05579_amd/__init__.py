@@ -139,6 +139,11 @@ class Grte:
         check("grte_read_timing", self._lib.grte_read_timing(self._h, ms.ctypes.data, cnt.ctypes.data))
         return {k: (float(ms[v]), int(cnt[v])) for k, v in _lib.TIMING.items()}
 
+    def set_storage(self, fp32):
+        """Store E (as its deviation from a c T^4) and O in binary32 (True) or
+        binary64 (False); arithmetic stays binary64."""
+        check("grte_set_storage", self._lib.grte_set_storage(self._h, int(bool(fp32))))
+
     def set_guess(self, model, accept_tol=1e-10):
         """Learned initial guess for the temperature solve (None: Newton from T^n)."""
         h = model._h if model is not None else None

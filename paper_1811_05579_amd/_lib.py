@@ -77,6 +77,7 @@ _SIGS = {
                                c_void_p]),
     "grte_mlp_predict": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_void_p]),
     "grte_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
+    "grte_set_storage": (c_int, [c_void_p, c_int]),
     "grte_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
     "grte_batch_create": (c_int, [c_int, ctypes.POINTER(Instance), c_void_p, c_void_p,
                                   ctypes.POINTER(c_void_p)]),

@@ -95,7 +95,9 @@ struct CoefArgs {
     const double *T;             // temperature defining K (T^n or T^{n+1})
     const double *Tn;            // T^n (U^n and beta)
     const double *sigma0, *mu, *omega, *bL, *bR;
-    const double *E, *O;         // E^n, O^n, cell-major
+    const double *E, *O;         // E^n, O^n, cell-major (binary64 storage)
+    const float *E32, *O32;      // binary32 storage: E^n = a c (T^n)^4 + E32, O^n = O32
+    int f32;
     double mu1, mu2;             // sum omega mu, sum omega mu^2 (diffusion operator)
     double *Ll, *Lu, *Lam, *LmG, *Gt, *Bd, *Aw, *Bc, *beta;   // Gt: position order (row_pos)
     int M;                       // rows per thread of the prediction kernel (for Gt)
@@ -187,9 +189,17 @@ __device__ __forceinline__ void coef_body(const CoefArgs &A)
     if (cl < cpb && j < N) {
         const double mu = A.mu[p];
         const double h = s_h[cl];
-        const double On_r = (j <= N - 2) ? A.O[(size_t)(j + 1) * P + p] : 0.0;
-        const double On_l = (j >= 1) ? A.O[(size_t)j * P + p] : 0.0;
-        const double En = A.E[(size_t)j * P + p];
+        double On_r = 0.0, On_l = 0.0, En;
+        if (A.f32) {
+            if (j <= N - 2) On_r = (double)A.O32[(size_t)(j + 1) * P + p];
+            if (j >= 1) On_l = (double)A.O32[(size_t)j * P + p];
+            const double tn = A.Tn[j];
+            En = A.a * A.c * (tn * tn) * (tn * tn) + (double)A.E32[(size_t)j * P + p];
+        } else {
+            if (j <= N - 2) On_r = A.O[(size_t)(j + 1) * P + p];
+            if (j >= 1) On_l = A.O[(size_t)j * P + p];
+            En = A.E[(size_t)j * P + p];
+        }
         double rv = s_keps[cl] * En + s_src[cl] - h * mu * (s_awr[cl] * On_r - s_awl[cl] * On_l);
         if (j == 0) rv += 2.0 * h * mu * A.bL[p] / A.eps;
         if (j == N - 1) rv += 2.0 * h * mu * A.bR[p] / A.eps;
@@ -390,6 +400,8 @@ struct NewtonArgs {
     const double *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
     double *Ecm;             // E* copied to cell-major order (read by the node relations)
     double *Tnew, *ustar, *Dv, *ostar, *rstar;
+    const float *O32;        // binary32 storage of O^n (f32 != 0)
+    int f32;
     const uint16_t *gw;      // learned initial guess: bfloat16 weights (null: Newton from T^n)
     const float *gnorm;      // and its normalisation
     double gtol;             // residual below which the guess is taken as the root
@@ -435,8 +447,14 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t 
     const int jj = c0 + cl;
     if (cl < cpb && jj < N) {
         const double mu = A.mu[p], w = A.omega[p];
-        const double ol = node_any(A.Ecm, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj, p);
-        const double orr = node_any(A.Ecm, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj + 1, p);
+        double ol, orr;
+        if (A.f32) {
+            ol = node_any(A.Ecm, A.O32, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj, p);
+            orr = node_any(A.Ecm, A.O32, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj + 1, p);
+        } else {
+            ol = node_any(A.Ecm, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj, p);
+            orr = node_any(A.Ecm, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, jj + 1, p);
+        }
         s_w[t] = w * A.Ecm[(size_t)jj * P + p];
         s_f[t] = w * mu * (orr - ol);
         if (A.keep) {
@@ -550,7 +568,11 @@ __global__ void log_pairs_kernel(int N, int m, double eps, double dt, const doub
 struct CorrArgs {
     int N, P;
     const double *Ll, *Lu, *Lam, *Bd, *r, *mu;
-    double *Enew;   // cell-major E^{n+1}
+    double *Enew;   // cell-major E^{n+1} (binary64)
+    float *E32new;  // binary32 storage: E^{n+1} - a c (T^{n+1})^4 (f32 != 0)
+    const double *Tnew;
+    double ac;
+    int f32;
 };
 
 template <int M>
@@ -591,7 +613,13 @@ __global__ void __launch_bounds__(NT) corr_kernel(Group<CorrArgs> G)
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int j = j0 + r;
-        if (j < N) A.Enew[(size_t)j * P + p] = x[r];
+        if (j < N) {
+            A.Enew[(size_t)j * P + p] = x[r];
+            if (A.f32) {
+                const double t1 = A.Tnew[j];
+                A.E32new[(size_t)j * P + p] = (float)(x[r] - A.ac * (t1 * t1) * (t1 * t1));
+            }
+        }
     }
 }
 
@@ -603,6 +631,9 @@ struct ProjArgs {
     double eps;
     const double *Enew, *O, *Aw, *Bc, *mu, *omega, *bL, *bR;
     double *Oout, *rho_out;
+    const float *O32;       // binary32 storage (f32 != 0): O^n in, O^{n+1} out
+    float *O32out;
+    int f32;
 };
 
 __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
@@ -615,9 +646,18 @@ __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
     const int j = c0 + cl;
     if (cl < cpb && j < N) {
         const double mu = A.mu[p];
-        A.Oout[(size_t)j * P + p] = node_any(A.Enew, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, j, p);
-        if (j == N - 1)
-            A.Oout[(size_t)N * P + p] = node_any(A.Enew, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, N, p);
+        if (A.f32) {
+            A.O32out[(size_t)j * P + p] =
+                (float)node_any(A.Enew, A.O32, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, j, p);
+            if (j == N - 1)
+                A.O32out[(size_t)N * P + p] =
+                    (float)node_any(A.Enew, A.O32, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, N, p);
+        } else {
+            A.Oout[(size_t)j * P + p] = node_any(A.Enew, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, j, p);
+            if (j == N - 1)
+                A.Oout[(size_t)N * P + p] =
+                    node_any(A.Enew, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, N, p);
+        }
         if (A.keep) s_w[t] = A.omega[p] * A.Enew[(size_t)j * P + p];
     }
     if (!A.keep) return;
@@ -626,6 +666,24 @@ __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
         double s = 0.0;
         for (int q = 0; q < P; ++q) s += s_w[t * P + q];
         A.rho_out[c0 + t] = s;
+    }
+}
+
+// between binary64 state arrays and binary32 storage (E as the deviation from a c T^4)
+__global__ void convert_state_kernel(int N, int P, double ac, const double *T, double *E, double *O, float *E32,
+                                     float *O32, int to32)
+{
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t ne = (size_t)N * P, no = (size_t)(N + 1) * P;
+    if (t < ne) {
+        const double tj = T[t / P];
+        const double base = ac * (tj * tj) * (tj * tj);
+        if (to32) E32[t] = (float)(E[t] - base);
+        else E[t] = base + (double)E32[t];
+    }
+    if (t < no) {
+        if (to32) O32[t] = (float)O[t];
+        else O[t] = (double)O32[t];
     }
 }
 
@@ -656,6 +714,10 @@ struct grte_ctx {
     double *Ll, *Lu, *Lam, *LmG, *Gt, *Bd, *Aw, *Bc, *beta, *Dl, *Dd, *Du, *rho_n;
     double *r, *part, *res, *estar_t, *estar, *rho;
     double *ustar, *Dv, *ostar, *rho1, *rstar;
+    // binary32 storage of the intensity state (f32 != 0): E as E - a c T^4, and O;
+    // the binary64 E, O buffers then serve as scratch
+    int f32 = 0;
+    float *E32 = nullptr, *E32b = nullptr, *O32 = nullptr, *O32b = nullptr;
     // learned initial guess of the temperature solve (borrowed from a grte_mlp)
     const uint16_t *guess_w = nullptr;
     const float *guess_norm = nullptr;
@@ -771,6 +833,16 @@ int rows_per_thread(int N)
     int M = 2;
     while (NT * M < N) M *= 2;
     return M;
+}
+
+// binary64 state buffers <-> binary32 storage, on the context stream
+grte_status convert_state(grte_ctx *ctx, int to32)
+{
+    const size_t no = (size_t)(ctx->N + 1) * ctx->P;
+    hipLaunchKernelGGL(convert_state_kernel, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, ctx->stream, ctx->N,
+                       ctx->P, ctx->a * ctx->c, ctx->T, ctx->E, ctx->O, ctx->E32, ctx->O32, to32);
+    HIPCHK(hipGetLastError());
+    return GRTE_OK;
 }
 
 template <int M>
@@ -1010,6 +1082,7 @@ grte_status grte_set_state(grte_ctx *ctx, const double *E, const double *O, cons
     grte_status s = copy_in(ctx, ctx->E, E, N * P, on_device);
     if (s == GRTE_OK) s = copy_in(ctx, ctx->O, O, (N + 1) * P, on_device);
     if (s == GRTE_OK) s = copy_in(ctx, ctx->T, T, N, on_device);
+    if (s == GRTE_OK && ctx->f32) s = convert_state(ctx, 1);
     return s;
 }
 
@@ -1018,7 +1091,8 @@ grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int o
     if (!ctx) return GRTE_E_INVAL;
     const size_t N = ctx->N, P = ctx->P;
     grte_status s = GRTE_OK;
-    if (E) s = copy_out(ctx, E, ctx->E, N * P, on_device);
+    if (ctx->f32) s = convert_state(ctx, 0);   // binary64 values of the stored state
+    if (s == GRTE_OK && E) s = copy_out(ctx, E, ctx->E, N * P, on_device);
     if (s == GRTE_OK && O) s = copy_out(ctx, O, ctx->O, (N + 1) * P, on_device);
     if (s == GRTE_OK && T) s = copy_out(ctx, T, ctx->T, N, on_device);
     return s;
@@ -1077,6 +1151,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         ca.Bd = ctx->Bd; ca.Aw = ctx->Aw; ca.Bc = ctx->Bc; ca.beta = ctx->beta;
         ca.Dl = ctx->Dl; ca.Dd = ctx->Dd; ca.Du = ctx->Du; ca.rho_n = ctx->rho_n; ca.r = ctx->r;
         ca.stat = ctx->stat;
+        ca.E32 = ctx->E32; ca.O32 = ctx->O32; ca.f32 = ctx->f32;
         // prediction: work-groups [grid, grid + P) belong to this context
         PredArgs &pa = gp.a[g];
         pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
@@ -1099,6 +1174,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
         na.ostar = ctx->ostar; na.stat = ctx->stat; na.rstar = ctx->rstar;
         na.gw = ctx->guess_w; na.gnorm = ctx->guess_norm; na.gtol = ctx->guess_tol;
+        na.O32 = ctx->O32; na.f32 = ctx->f32;
         ctx->last_dt = dt;
         ctx->last_eps = eps;
         ctx->stepped = 1;
@@ -1106,12 +1182,14 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         CorrArgs &cc = gr.a[g];
         cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
         cc.r = ctx->r; cc.mu = ctx->mu; cc.Enew = ctx->E2;
+        cc.E32new = ctx->E32b; cc.Tnew = ctx->T2; cc.ac = ctx->a * ctx->c; cc.f32 = ctx->f32;
         // projection: O^{n+1} at the nodes, rho^{n+1}
         ProjArgs &pj = gj.a[g];
         pj.N = N; pj.P = P; pj.keep = ctx->keep; pj.cpb = ctx->cpb; pj.eps = eps;
         pj.Enew = ctx->E2; pj.O = ctx->O; pj.Aw = ctx->Aw; pj.Bc = ctx->Bc;
         pj.mu = ctx->mu; pj.omega = ctx->omega; pj.bL = ctx->bL; pj.bR = ctx->bR;
         pj.Oout = ctx->O2; pj.rho_out = ctx->rho1;
+        pj.O32 = ctx->O32; pj.O32out = ctx->O32b; pj.f32 = ctx->f32;
     }
     gp.first[n] = grid;
     if (grid > c0->coop_capacity) return GRTE_E_UNSUPPORTED;
@@ -1155,6 +1233,8 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         std::swap(ctx->E, ctx->E2);
         std::swap(ctx->O, ctx->O2);
         std::swap(ctx->T, ctx->T2);
+        std::swap(ctx->E32, ctx->E32b);
+        std::swap(ctx->O32, ctx->O32b);
     }
     if (!info) return GRTE_OK;
     grte_status worst = GRTE_OK;
@@ -1204,6 +1284,28 @@ grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, cons
             if (ctxs[h] == ctxs[g]) return GRTE_E_INVAL;
     }
     return step_group(ctxs, n, dt, eps, info);
+}
+
+grte_status grte_set_storage(grte_ctx *ctx, int fp32)
+{
+    if (!ctx || (fp32 != 0 && fp32 != 1)) return GRTE_E_INVAL;
+    if (fp32 == ctx->f32) return GRTE_OK;
+    if (fp32 && !ctx->E32) {
+        const size_t ne = (size_t)ctx->N * ctx->P, no = (size_t)(ctx->N + 1) * ctx->P;
+        float **bufs[] = {&ctx->E32, &ctx->E32b, &ctx->O32, &ctx->O32b};
+        const size_t sizes[] = {ne, ne, no, no};
+        for (int q = 0; q < 4; ++q) {
+            void *p = nullptr;
+            if (hipMalloc(&p, sizes[q] * sizeof(float)) != hipSuccess) return GRTE_E_NOMEM;
+            ctx->allocs.push_back((double *)p);
+            *bufs[q] = (float *)p;
+        }
+    }
+    grte_status s = convert_state(ctx, fp32);
+    if (s != GRTE_OK) return s;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->f32 = fp32;
+    return GRTE_OK;
 }
 
 grte_status grte_set_guess(grte_ctx *ctx, const grte_mlp *model, double accept_tol)

@@ -372,14 +372,18 @@ __device__ __forceinline__ double kpow(double T, int m) { return m == 0 ? 1.0 : 
 // tridiagonal solvers: t = (j % M) * NT + j / M
 __device__ __forceinline__ int row_pos(int j, int M) { return (j % M) * NT + j / M; }
 
-__device__ __forceinline__ double node_flux(const double *Eall, const double *O, const double *Aw,
+// O^n may be stored in binary64 or binary32 (OT); arithmetic is binary64
+template <class OT>
+__device__ __forceinline__ double node_flux(const double *Eall, const OT *O, const double *Aw,
                                             const double *Bc, double mu, int N, int P, int i, int p)
 {
     // interior node i (1..N-1): O_i = Aw_i O^n_i - Bc_i mu (E_i - E_{i-1})
-    return Aw[i] * O[(size_t)i * P + p] - Bc[i] * mu * (Eall[(size_t)i * P + p] - Eall[(size_t)(i - 1) * P + p]);
+    return Aw[i] * (double)O[(size_t)i * P + p] -
+           Bc[i] * mu * (Eall[(size_t)i * P + p] - Eall[(size_t)(i - 1) * P + p]);
 }
 
-__device__ __forceinline__ double node_any(const double *Eall, const double *O, const double *Aw,
+template <class OT>
+__device__ __forceinline__ double node_any(const double *Eall, const OT *O, const double *Aw,
                                            const double *Bc, double mu, double bl, double br, double eps,
                                            int N, int P, int i, int p)
 {

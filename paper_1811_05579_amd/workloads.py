@@ -24,6 +24,13 @@ seed (numpy PCG64, seed 18110000 + configuration number).
             taking either value with probability 1/2, eps = 1e-4, the initial
             and inflow data of config 1, dt = 0.5 dx.
 
+  marshak   dimensional Marshak wave of the paper's last example: eps = 1,
+            c = 29.98 cm/ns, a = 0.01372 GJ/(cm^3 keV^4), Cv = 0.3 GJ/(cm^3 keV),
+            sigma = 300 / T^3 cm^-1, x in [0, 0.02] cm, T(x, 0) =
+            (1 - tanh((x - 0.0024) 1000)) / 2 keV in equilibrium (I = a c T^4),
+            T = 1 keV at x = 0 imposed as the isotropic inflow a c 1^4, the
+            right-end inflow a c T(0.02, 0)^4; dt in ns (1.6e-12 s = 1.6e-3 ns).
+
 The velocity grid (Gauss-Legendre pairs: positive nodes by increasing mu,
 weight of +mu on [-1, 1], so the weights sum to one) is part of the input:
 both the oracle and the GPU library receive these exact binary64 values.
@@ -186,3 +193,18 @@ def mlp_init(seed=SEED_BASE + 9, scale=1.0):
     w3 = rng.uniform(-1, 1, 64) * scale / np.sqrt(64)
     th = np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, [0.0]])
     return th.astype(np.float32)
+
+
+def marshak(N=100, nv=16, dt=1.6e-3, steps=100):
+    """Dimensional Marshak wave (eps = 1, units cm, ns, keV, GJ)."""
+    a, c, Cv, L = 0.01372, 29.98, 0.3, 0.02
+    mu, om = gauss_legendre_pairs(nv)
+    P = nv // 2
+    xc = (np.arange(N) + 0.5) * (L / N)
+    T = 0.5 * (1.0 - np.tanh((xc - 0.0024) * 1000.0))
+    E = np.repeat((a * c * T ** 4)[:, None], P, axis=1)
+    O = np.zeros((N + 1, P))
+    TR = 0.5 * (1.0 - np.tanh((L - 0.0024) * 1000.0))
+    return Workload(name=f"marshak(N={N},dt={dt:g}ns)", N=N, nv=nv, m=3, eps=1.0, dt=dt, steps=steps,
+                    a=a, c=c, Cv=Cv, L=L, mu=mu, omega=om, sigma0=np.full(N, 300.0), T=T, E=E, O=O,
+                    bL=np.full(P, a * c * 1.0), bR=np.full(P, a * c * TR ** 4))
