@@ -13,6 +13,11 @@ Printed: one JSON line with the aggregate cell-angle updates per second
 (sum of N * N_v over the runs and steps / elapsed time), the roofline entry of
 the dominant kernel (the prediction solve, timed live with HIP events on its
 stream) and the CPU oracle timed on a bounded sample of the same workload.
+
+--workload config4 instead measures the batched form: 4096 uneven slabs
+(N ~ U{64..2048}, N_v in {8,16,32,64}, eps = 10^U[-5,0], sigma0 = 10^U[-1,2],
+sigma0/T^3, dt = 0.5/N) advanced by one persistent kernel per step, replayed
+as a captured HIP graph after the autotuner has chosen the tiles and grid.
 """
 import argparse
 import json
@@ -26,6 +31,13 @@ if ROOT not in sys.path:
 
 EPS_RUNS = (1.0, 1e-2, 1e-4)
 HBM_PEAK_GBS = 8000.0
+# Measured HBM bytes per launch of the dominant kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs, scaled by a plain-copy calibration; commands and raw values in
+# the named profiles/ files).  Set to None when the kernel changes.
+TRAFFIC = {
+    "config2": (1.0560e8, "profiles/pred_kernel_config2_hbm_traffic.txt"),
+    "config4": (1.8798e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
+}
 
 
 def pred_algorithmic_bytes(N, P):
@@ -60,17 +72,140 @@ def cpu_baseline(sample_steps=2):
                       f"initial state, {el:.1f} s, extended-precision sparse direct solves"}
 
 
+def batch_state_bytes(ens):
+    """Bytes of the binary64 state (E, O) of every slab: the algorithmic traffic
+    of one step is reading it twice (prediction and correction right-hand
+    sides) and writing it once."""
+    return 8 * sum(w.N * w.P + (w.N + 1) * w.P for w in ens.members)
+
+
+def cpu_baseline_batch(ens, budget_s=15.0):
+    """Oracle (as it stands) on whole slabs of the ensemble, in order, until
+    the time budget is spent; scaled per cell-angle update."""
+    from oracle.ap1d import Physics, ap_step
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)
+    except Exception:   # pragma: no cover
+        limit = None
+    t0 = time.perf_counter()
+    upd = 0
+    n = 0
+    for w in ens.members:
+        ph = Physics(a=w.a, c=w.c, Cv=w.Cv, eps=w.eps, dt=w.dt, L=w.L, m=w.m)
+        ap_step(w.E, w.O, w.T, w.sigma0, w.mu, w.omega, w.bL, w.bR, ph)
+        upd += w.cell_angle_updates()
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    if limit is not None and hasattr(limit, "unregister"):
+        limit.unregister()
+    return {"value": upd / el, "unit": "cell·angle updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one AP step of the first {n} slabs of the ensemble ({upd} cell-angle updates), "
+                      f"{el:.1f} s"}
+
+
+def main_batch(args):
+    import torch
+    from paper_1811_05579_amd import GrteBatch
+    from paper_1811_05579_amd.workloads import config4
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    ens = config4()
+    b = GrteBatch(ens.members)
+    stream = torch.cuda.Stream()
+    b.set_stream(stream)
+    pk = ens.packed()
+    b.set_opacity(pk["sigma0"])
+    b.set_inflow(pk["bL"], pk["bR"])
+    b.set_state(pk["E"], pk["O"], pk["T"])
+    tuning = b.tune(trials=1)
+    b.use_graph(True)
+    for _ in range(args.warmup):
+        b.step()
+    torch.cuda.synchronize()
+    b.set_profiling(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    main = torch.cuda.current_stream()
+    start.record(main)
+    stream.wait_event(start)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.step()
+    done = torch.cuda.Event()
+    done.record(stream)
+    main.wait_event(done)
+    stop.record(main)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    elapsed_ms = start.elapsed_time(stop)
+    ms, cnt = b.read_timing()
+    st, infos = b.step(info=True)
+    its = [i["pred_iters"] for i in infos]
+    updates = ens.cell_angle_updates() * args.steps
+    value = updates / (elapsed_ms / 1e3)
+    sbytes = batch_state_bytes(ens)
+    launch_s = ms / cnt / 1e3
+    achieved = 3 * sbytes / launch_s / 1e9
+    line = {
+        "metric": "cell_angle_updates_per_s",
+        "value": value,
+        "unit": "cell·angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded ensemble of slabs, analytic cold-start/hot-inflow data)",
+        "config": {
+            "workload": "batched ensemble: 4096 1D slabs, N~U{64..2048}, N_v in {8,16,32,64}, "
+                        "eps=10^U[-5,0], sigma0=10^U[-1,2], sigma=sigma0*T^-3, dt=0.5/N, FP64, "
+                        "one persistent graph launch per step",
+            "slabs": len(ens), "cell_angle_updates_per_step": ens.cell_angle_updates(),
+            "parallelism": "single GPU; one tile (work-group or wavefront) per slab",
+            "tuning": tuning, "pred_iters_mean": sum(its) / len(its), "pred_iters_max": max(its),
+            "status_last": st, "host_wall_s": wall,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "batch_kernel (whole step of every slab, one launch)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": TRAFFIC["config4"][0],
+            "traffic_source": TRAFFIC["config4"][1],
+            "bytes_per_launch": 3 * sbytes,
+            "avg_launch_us": launch_s * 1e6,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(ens)
+    b.close()
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["config2", "config4"], default="config2")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the single-GPU step; multi-GPU "
               "sharding is described, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "config4":
+        main_batch(args)
+        return
 
     import torch
     from paper_1811_05579_amd import Grte, step_group
@@ -152,7 +287,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": TRAFFIC["config2"][0],
+            "traffic_source": TRAFFIC["config2"][1],
             "bytes_per_launch": pred_bytes,
             "avg_launch_us": pred_avg_s * 1e6,
             "share_of_step": pred_ms / step_ms if step_ms > 0 else None,

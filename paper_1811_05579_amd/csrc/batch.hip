@@ -153,7 +153,21 @@ __device__ void b_cell(const BInst &I, int mode, const double *Tk, const double 
     }
 }
 
-// right-hand sides of the per-pair systems into Rt (pair-major, position order)
+// O at node i of pair p from cell values ec[] of that pair (cell order): the
+// node relation at interior nodes, the inflow relations (4.7) at the two ends
+template <class OT>
+__device__ __forceinline__ double node_pc(const double *ec, const OT *O, const double *Aw, const double *Bc,
+                                          double mu, double bl, double br, double eps, int N, int P, int i, int p)
+{
+    auto inner = [&](int ii) {
+        return Aw[ii] * (double)O[(size_t)ii * P + p] - Bc[ii] * mu * (ec[ii] - ec[ii - 1]);
+    };
+    if (i >= 1 && i <= N - 1) return inner(i);
+    if (i == 0) return 2.0 / eps * (bl - ec[0]) - inner(1);
+    return 2.0 / eps * (ec[N - 1] - br) - inner(N - 1);
+}
+
+// right-hand sides of the per-pair systems into Rt (pair-major, cell order)
 template <int W, int M>
 __device__ void b_rhs(const BInst &I, const double *C, int N1, const double *E, const double *O,
                       const double *mu, const double *bL, const double *bR, double *Rt)
@@ -170,7 +184,7 @@ __device__ void b_rhs(const BInst &I, const double *C, int N1, const double *E, 
                   - h * mu[p] * (C[C_AWR * N1 + j] * On_r - C[C_AWL * N1 + j] * On_l);
         if (j == 0) rv += 2.0 * h * mu[p] * bL[p] / I.eps;
         if (j == N - 1) rv += 2.0 * h * mu[p] * bR[p] / I.eps;
-        Rt[(size_t)p * NP + bpos(j, W, M)] = rv;
+        Rt[(size_t)p * NP + j] = rv;
     }
 }
 
@@ -187,8 +201,11 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
     const double *mu = A.mu + I.oP, *om = A.omega + I.oP, *bL = A.bL + I.oP, *bR = A.bR + I.oP;
     double *E2 = A.E2 + I.oE, *O2 = A.O2 + I.oO, *T2 = A.T2 + I.oT;
     double *C = A.cells + I.oC;
-    double *Rt = A.pairs + I.oR;                  // right-hand sides, pair-major position order
-    double *Et = Rt + (size_t)P * I.NPa;          // E*, pair-major position order
+    // Per-pair global arrays are pair-major in cell order: thread k's rows
+    // j0 .. j0+M-1 are contiguous, so its loads and stores are wide and the
+    // later per-cell phases read along cells.
+    double *Rt = A.pairs + I.oR;                  // right-hand sides
+    double *Et = Rt + (size_t)P * I.NPa;          // E* (prediction), then E^{n+1} (correction)
     int *st = A.istat + 8 * i;
     double *rho = sm, *sLl = sm + NP, *sLu = sm + 2 * NP, *sh = sm + 3 * NP;
 
@@ -222,13 +239,21 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
     }
     int it = 0, converged = 0, ph = 0;
     while (true) {
-        double acc[M];
+        double acc[M], rnext[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) acc[r] = 0.0;
+        for (int r = 0; r < M; ++r) {
+            acc[r] = 0.0;
+            rnext[r] = Rt[j0 + r];              // right-hand side of pair 0
+        }
         for (int p = 0; p < P; ++p) {
             // v_p = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho]
             const double m1 = mu[p], m2 = m1 * m1, wp = om[p];
-            const double *rp = Rt + (size_t)p * NP;
+            double rcur[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) {       // this pair's right-hand side; fetch the next one
+                rcur[r] = rnext[r];
+                if (p + 1 < P) rnext[r] = Rt[(size_t)(p + 1) * NP + j0 + r];
+            }
             double b[M], y[M], v[M];
 #pragma unroll
             for (int r = 0; r < M; ++r) {
@@ -243,26 +268,24 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
                     if (j > 0) rl = (r > 0) ? rho[t - W] : rho[(M - 1) * W + k - 1];
                     if (j < N - 1) rn = (r < M - 1) ? rho[t + W] : rho[k + 1];
                     const double q = -(ll + lu) * rj + ll * rl + lu * rn;
-                    y[r] = rp[t] - lmg[r] * rj - m2 * q - m1 * bdj * rj;
+                    y[r] = rcur[r] - lmg[r] * rj - m2 * q - m1 * bdj * rj;
                 } else {
                     b[r] = 1.0;
                     y[r] = 0.0;
                 }
             }
-            TriFac<W, M> Ft;
-            tri_factor<W, M>(m2, sLl, sLu, b, Ft, sh);
-            tri_solve<W, M>(m2, sLl, sLu, Ft, y, v, sh, ph);
+            tri_factor_solve<W, M>(m2, sLl, sLu, b, y, v, sh, ph);
             double *ep = Et + (size_t)p * NP;
 #pragma unroll
             for (int r = 0; r < M; ++r) {
-                const int t = r * W + k;
                 acc[r] += wp * v[r];
-                ep[t] = rho[t] + v[r];          // E*_p of this sweep
+                ep[j0 + r] = rho[r * W + k] + v[r];   // E*_p of this sweep
             }
         }
         // res = sum_p omega_p v_p - (1 - W) rho;  rho += res + D^{-1} (G res).
-        // The diffusion operator is factored again here rather than held in
-        // registers across the pair loop (one factorisation per P solves).
+        // Every operator is factored and solved in one call (one barrier); the
+        // diffusion operator is factored again each iteration rather than held
+        // in registers across the pair loop (one factorisation per P solves).
         double rl[M], d[M], f[M];
         {
             double b[M];
@@ -274,9 +297,7 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
                 d[r] = in ? C[C_G * N1 + j] * rl[r] : 0.0;
                 b[r] = in ? C[C_DD * N1 + j] : 1.0;
             }
-            TriFac<W, M> Fd;
-            tri_factor<W, M>(I.mu2, sLl, sLu, b, Fd, sh);
-            tri_solve<W, M>(I.mu2, sLl, sLu, Fd, d, f, sh, ph);
+            tri_factor_solve<W, M>(I.mu2, sLl, sLu, b, d, f, sh, ph);
         }
         double md = 0.0, mr = 0.0;
 #pragma unroll
@@ -308,17 +329,10 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
         for (int p = 0; p < P; ++p) {
             const double *ep = Et + (size_t)p * NP;
             const double m1 = mu[p];
-            const double ej = ep[bpos(j, W, M)];
+            const double ej = ep[j];
             // O* at nodes j and j+1 from the node relation and the inflow relations (4.7)
-            auto onode = [&](int ii) {
-                return C[C_AW * N1 + ii] * O[(size_t)ii * P + p]
-                     - C[C_BC * N1 + ii] * m1 * (ep[bpos(ii, W, M)] - ep[bpos(ii - 1, W, M)]);
-            };
-            double ol, orr;
-            if (j >= 1) ol = onode(j);
-            else ol = 2.0 / eps * (bL[p] - ej) - onode(1);
-            if (j <= N - 2) orr = onode(j + 1);
-            else orr = 2.0 / eps * (ej - bR[p]) - onode(N - 1);
+            const double ol = node_pc(ep, O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
+            const double orr = node_pc(ep, O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
             rs += om[p] * ej;
             D += om[p] * m1 * (orr - ol);
         }
@@ -405,28 +419,30 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
             if (j < N) {
                 const double bdj = (j == 0 ? cb0 : 0.0) + (j == N - 1 ? cbN : 0.0);
                 b[r] = lam[r] + m2 * (-(sLl[t] + sLu[t])) + m1 * bdj;
-                d[r] = rp[t];
+                d[r] = rp[j];
             } else {
                 b[r] = 1.0;
                 d[r] = 0.0;
             }
         }
-        TriFac<W, M> F;
-        tri_factor<W, M>(m2, sLl, sLu, b, F, sh);
-        tri_solve<W, M>(m2, sLl, sLu, F, d, x, sh, ph);
+        tri_factor_solve<W, M>(m2, sLl, sLu, b, d, x, sh, ph);
+        double *ep = Et + (size_t)p * NP;   // E*, no longer needed, takes E^{n+1}
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const int j = j0 + r;
-            if (j < N) E2[(size_t)j * P + p] = x[r];
-        }
+        for (int r = 0; r < M; ++r) ep[j0 + r] = x[r];
     }
     tsync<W>();
 
-    // ---------------- projection (4.14): O^{n+1} from the node relation with K^{n+1}
+    // ---------------- projection (4.14): E^{n+1} and O^{n+1} (node relation with K^{n+1})
+    // into the cell-major state; a thread takes cells, its lanes read along cells
     const double *Aw = C + C_AW * N1, *Bc = C + C_BC * N1;
-    for (int idx = k; idx < (N + 1) * P; idx += W) {
-        const int ii = idx / P, p = idx - (idx / P) * P;
-        O2[idx] = node_any(E2, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, ii, p);
+    for (int j = k; j < N; j += W) {
+        for (int p = 0; p < P; ++p) {
+            const double *ep = Et + (size_t)p * NP;
+            E2[(size_t)j * P + p] = ep[j];
+            O2[(size_t)j * P + p] = node_pc(ep, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
+            if (j == N - 1)
+                O2[(size_t)N * P + p] = node_pc(ep, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+        }
     }
     tsync<W>();
 }

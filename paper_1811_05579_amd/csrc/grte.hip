@@ -249,11 +249,16 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
 {
     extern __shared__ double smem[];
     constexpr int NP = NT * M;           // padded rows
+    // Everything an iteration reads besides the other work-groups' partial sums
+    // stays in LDS or registers: the grid barrier's device-scope release and
+    // acquire write back and invalidate the L2, so global data would be
+    // fetched again from memory in every iteration.
     double *rho = smem;                  // current iterate (position order)
     double *sLl = smem + NP;             // operator coefficients (position order)
     double *sLu = smem + 2 * NP;
-    double *sLmG = smem + 3 * NP;
-    double *sh = smem + 4 * NP;          // solver scratch (tile_scratch<NT>())
+    double *sh = smem + 3 * NP;          // solver scratch (tile_scratch<NT>())
+    double *redT = sh + tile_scratch<NT>();   // reduced systems of the two factorisations
+    double *redD = redT + red_doubles();
     const int k = threadIdx.x;
     const int N = A.N, P = A.P;
     const int j0 = k * M;
@@ -263,7 +268,6 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
         rho[t] = in ? A.rho0[j] : 0.0;
         sLl[t] = in ? A.Ll[j] : 0.0;
         sLu[t] = in ? A.Lu[j] : 0.0;
-        sLmG[t] = in ? A.LmG[j] : 0.0;
     }
     const double bd0 = A.Bd[0], bdN = A.Bd[N - 1];
     __syncthreads();
@@ -271,7 +275,14 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
     const double mu = A.mu[p], mu2 = mu * mu, wp = A.omega[p];
 
     TriFac<NT, M> Ft, Fd;
-    const double *rp = A.r + (size_t)p * NP;   // right-hand sides of this pair (position order)
+    double rr[M], gg[M], lmg[M];         // r_p, G and Lam - G of this thread's rows
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int j = j0 + r;
+        rr[r] = A.r[(size_t)p * NP + r * NT + k];
+        gg[r] = A.Gt[r * NT + k];
+        lmg[r] = (j < N) ? A.LmG[j] : 0.0;
+    }
     {
         double b[M];
 #pragma unroll
@@ -285,14 +296,14 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
                 b[r] = 1.0;
             }
         }
-        tri_factor<NT, M>(mu2, sLl, sLu, b, Ft, sh);
+        tri_factor<NT, M>(mu2, sLl, sLu, b, Ft, sh, redT);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             const int j = j0 + r;
             b[r] = (j < N) ? A.Dd[j] : 1.0;
         }
         __syncthreads();   // the two factorisations share their LDS exchange area
-        tri_factor<NT, M>(A.mu2avg, sLl, sLu, b, Fd, sh);
+        tri_factor<NT, M>(A.mu2avg, sLl, sLu, b, Fd, sh, redD);
     }
 
     // positions whose angular sum this work-group forms
@@ -318,7 +329,7 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
                 const double ll = sLl[t], lu = sLu[t];
                 const double q = -(ll + lu) * rj + ll * rl + lu * rn;
                 const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
-                y[r] = rp[t] - sLmG[t] * rj - mu2 * q - mu * bdj * rj;
+                y[r] = rr[r] - lmg[r] * rj - mu2 * q - mu * bdj * rj;
             } else {
                 y[r] = 0.0;
             }
@@ -352,7 +363,7 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
         for (int r = 0; r < M; ++r) {
             const int t = r * NT + k;
             rl[r] = A.res[t];
-            d[r] = A.Gt[t] * rl[r];
+            d[r] = gg[r] * rl[r];
         }
         tri_solve<NT, M>(A.mu2avg, sLl, sLu, Fd, d, f, sh, ph);
         double md = 0.0, mr = 0.0;
@@ -438,6 +449,7 @@ __global__ void __launch_bounds__(256) gather_estar_kernel(Group<NewtonArgs> G)
     A.Ecm[t] = A.estar_t[(size_t)p * NT * A.M + row_pos(j, A.M)];
 }
 
+template <bool GUESS>
 __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t *sW, const float *sN)
 {
     __shared__ double s_w[256], s_f[256];
@@ -499,7 +511,7 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t 
     if (!(s0 == 0.0 && Ks == 0.0)) {
         if (Tn + rhs / lin < 0.0) atomicAdd(&A.stat[5], 1);   // no root >= 0
         bool ok = false, done = false;
-        if (A.gw && s0 > 0.0 && Tn > 0.0) {
+        if (GUESS && s0 > 0.0 && Tn > 0.0) {
             // learned starting value; judged by the normalised residual of (4.13)
             float f[MLP_IN];
             mlp_features(rho, Tn, s0, A.m, A.eps, A.dt, f);
@@ -530,17 +542,24 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t 
     atomicAdd(&A.stat[9], its);
 }
 
+// GUESS: some context of the launch carries a learned guess (its weights are
+// staged in LDS); the plain kernel pays for none of it
+template <bool GUESS>
 __global__ void __launch_bounds__(256) newton_kernel(Group<NewtonArgs> G)
 {
-    __shared__ uint16_t sW[MLP_NPARAM + 3];
-    __shared__ float sN[MLP_NNORM];
     const NewtonArgs A = G.a[blockIdx.y];
-    if (A.gw) {
-        for (int e = threadIdx.x; e < MLP_NPARAM; e += 256) sW[e] = A.gw[e];
-        if (threadIdx.x < MLP_NNORM) sN[threadIdx.x] = A.gnorm[threadIdx.x];
-        __syncthreads();
+    if constexpr (GUESS) {
+        __shared__ uint16_t sW[MLP_NPARAM + 3];
+        __shared__ float sN[MLP_NNORM];
+        if (A.gw) {
+            for (int e = threadIdx.x; e < MLP_NPARAM; e += 256) sW[e] = A.gw[e];
+            if (threadIdx.x < MLP_NNORM) sN[threadIdx.x] = A.gnorm[threadIdx.x];
+            __syncthreads();
+            newton_body<true>(A, sW, sN);
+            return;
+        }
     }
-    newton_body(A, sW, sN);
+    newton_body<false>(A, nullptr, nullptr);
 }
 
 // training rows (f_0..f_4, log(T^{n+1}/T^n)) of the last step, binary32;
@@ -606,10 +625,8 @@ __global__ void __launch_bounds__(NT) corr_kernel(Group<CorrArgs> G)
             d[r] = 0.0;
         }
     }
-    TriFac<NT, M> F;
-    tri_factor<NT, M>(mu2, sLl, sLu, b, F, sh);
     int ph = 0;
-    tri_solve<NT, M>(mu2, sLl, sLu, F, d, x, sh, ph);
+    tri_factor_solve<NT, M>(mu2, sLl, sLu, b, d, x, sh, ph);
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const int j = j0 + r;
@@ -807,7 +824,7 @@ grte_status prof_end(grte_ctx *ctx, int idx)
 template <int M>
 size_t pred_lds_bytes()
 {
-    return (size_t)(4 * NT * M + tile_scratch<NT>()) * sizeof(double);
+    return (size_t)(3 * NT * M + tile_scratch<NT>() + 2 * red_doubles()) * sizeof(double);
 }
 
 template <int M>
@@ -1210,7 +1227,10 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     if ((st = prof_end(c0, ev_pred)) != GRTE_OK) return st;
     hipLaunchKernelGGL(gather_estar_kernel, dim3(np_max, n), dim3(256), 0, stream, gn);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(newton_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gn);
+    bool any_guess = false;
+    for (int g = 0; g < n; ++g) any_guess = any_guess || gn.a[g].gw != nullptr;
+    if (any_guess) hipLaunchKernelGGL(newton_kernel<true>, dim3(ncb_max, n), dim3(256), 0, stream, gn);
+    else hipLaunchKernelGGL(newton_kernel<false>, dim3(ncb_max, n), dim3(256), 0, stream, gn);
     HIPCHK(hipGetLastError());
     for (int g = 0; g < n; ++g) {     // coefficients of the correction: K from T^{n+1}
         gc.a[g].mode = 1;

@@ -49,10 +49,20 @@ __device__ __forceinline__ double wave_nb(double v, int o, double dflt)
     return in ? r : dflt;
 }
 
-// LDS scratch (doubles) a tile's solver needs: factor exchange (5 W) + two
-// solve exchange buffers (2 x 2 W) for work-group tiles; none for wavefronts
+// LDS scratch (doubles) of a work-group tile's solver, sh[0, 14 W + 16):
+//   tri_factor        sh[0, 5W)            reduced-row exchange
+//   tri_solve         sh[5W + 2W ph, +2W)  right-hand-side exchange, two buffers
+//   tri_factor_solve  sh[7W ph, +7W)       both at once, two buffers
+//   tile_max2         sh[14W, 14W + 16)
+// (the `ph` buffers alternate so that one barrier per call suffices; a kernel
+// uses either tri_factor/tri_solve or tri_factor_solve on one scratch area).
+// Wavefront tiles need no scratch.  A work-group factorisation also keeps its
+// reduced-system data in LDS (red_doubles(), one region per live
+// factorisation, passed to tri_factor).
 template <int W>
-constexpr int tile_scratch() { return W == 256 ? 9 * W : 16; }
+constexpr int tile_scratch() { return W == 256 ? 14 * W + 16 : 16; }
+constexpr int RED_FIELDS = 28;                 // per lane: ra, rc, rce (4 each), inv (3), k1, k2 (6 each), invB
+constexpr int red_doubles() { return RED_FIELDS * 64; }
 
 // parallel cyclic reduction of a 64-row tridiagonal (row l in lane l)
 struct WavePcr {
@@ -182,16 +192,70 @@ struct TriFac<64, M> {
 template <int M>
 struct TriFac<256, M> {
     double inv[M - 1];        // interior pivots of this thread's chunk
-    WaveFac<4> red;           // the 256-row reduced system, four rows per lane (same in every wave)
-    double ra[4], rc[4];      // its off-diagonals
-    double rce[4];            // last-row super-diagonal c_e of the chunks whose reduced rows this lane holds
+    double *red;              // LDS: the 256-row reduced system, four rows per lane (identical in every
+                              // wave): field f of lane l at red[64 f + l]
 };
 
-// Factor.  LDS use (work-group tiles): sh[0, 5W).  The caller must separate two
-// factorisations by a barrier (the solve in between provides one).
+// reduced-system data of one lane, kept in registers while it is used
+struct RedFac {
+    double ra[4], rc[4];      // off-diagonals of the lane's four reduced rows
+    double rce[4];            // last-row super-diagonal c_e of the chunks of those rows
+    WaveFac<4> w;             // their wavefront factorisation
+};
+
+__device__ __forceinline__ void red_store(const RedFac &R, double *red)
+{
+    const int l = threadIdx.x & 63;
+    double v[RED_FIELDS];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        v[i] = R.ra[i];
+        v[4 + i] = R.rc[i];
+        v[8 + i] = R.rce[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[12 + i] = R.w.inv[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        v[15 + i] = R.w.pcr.k1[i];
+        v[21 + i] = R.w.pcr.k2[i];
+    }
+    v[27] = R.w.pcr.invB;
+#pragma unroll
+    for (int f = 0; f < RED_FIELDS; ++f) red[64 * f + l] = v[f];
+}
+
+__device__ __forceinline__ void red_load(const double *red, RedFac &R)
+{
+    const int l = threadIdx.x & 63;
+    double v[RED_FIELDS];
+#pragma unroll
+    for (int f = 0; f < RED_FIELDS; ++f) v[f] = red[64 * f + l];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        R.ra[i] = v[i];
+        R.rc[i] = v[4 + i];
+        R.rce[i] = v[8 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) R.w.inv[i] = v[12 + i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        R.w.pcr.k1[i] = v[15 + i];
+        R.w.pcr.k2[i] = v[21 + i];
+    }
+    R.w.pcr.invB = v[27];
+}
+
+// Factor.  LDS use (work-group tiles): sh[0, 5W) and the reduced-system region
+// `red` (red_doubles()), which must stay untouched while the factorisation is
+// used.  Every wave writes the same values to `red` and reads back its own
+// writes, so no barrier is needed after it.  The caller must separate two
+// factorisations that share sh (or red) by a barrier (a solve in between
+// provides one).
 template <int W, int M>
 __device__ __forceinline__ void tri_factor(double s, const double *Lo, const double *Up, const double (&b)[M],
-                                           TriFac<W, M> &F, double *sh)
+                                           TriFac<W, M> &F, double *sh, double *red = nullptr)
 {
     const int k = tile_lane<W>();
     auto a = [&](int r) { return s * Lo[r * W + k]; };
@@ -211,6 +275,7 @@ __device__ __forceinline__ void tri_factor(double s, const double *Lo, const dou
         __syncthreads();
         // reduced row kk = 4 l + i couples z_{kk-1}, z_kk, z_{kk+1}
         const int l = threadIdx.x & 63;
+        RedFac RF;
         double rb[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -218,12 +283,14 @@ __device__ __forceinline__ void tri_factor(double s, const double *Lo, const dou
             const double cek = fC[kk];
             const double qn = (kk + 1 < W) ? fQ[kk + 1] : 0.0;
             const double rn = (kk + 1 < W) ? fR[kk + 1] : 0.0;
-            F.ra[i] = fA[kk];
+            RF.ra[i] = fA[kk];
             rb[i] = fB[kk] + cek * qn;
-            F.rc[i] = cek * rn;
-            F.rce[i] = cek;
+            RF.rc[i] = cek * rn;
+            RF.rce[i] = cek;
         }
-        wave_factor<4>([&](int r) { return F.ra[r]; }, [&](int r) { return F.rc[r]; }, rb, F.red);
+        wave_factor<4>([&](int r) { return RF.ra[r]; }, [&](int r) { return RF.rc[r]; }, rb, RF.w);
+        red_store(RF, red);
+        F.red = red;
     }
 }
 
@@ -250,14 +317,16 @@ __device__ __forceinline__ void tri_solve(double s, const double *Lo, const doub
         bf[W + k] = y[0];
         __syncthreads();
         const int l = threadIdx.x & 63;
+        RedFac RF;
+        red_load(F.red, RF);
         double Dr[4], zr[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int kk = 4 * l + i;
             const double yn = (kk + 1 < W) ? bf[W + kk + 1] : 0.0;
-            Dr[i] = bf[kk] - F.rce[i] * yn;
+            Dr[i] = bf[kk] - RF.rce[i] * yn;
         }
-        wave_solve<4>([&](int r) { return F.ra[r]; }, [&](int r) { return F.rc[r]; }, F.red, Dr, zr);
+        wave_solve<4>([&](int r) { return RF.ra[r]; }, [&](int r) { return RF.rc[r]; }, RF.w, Dr, zr);
         // z_k and z_{k-1} from the lanes that hold them (the same lanes in every wave)
         const int src = k >> 2, sub = k & 3;
         const double z0 = __shfl(zr[0], src, 64), z1 = __shfl(zr[1], src, 64);
@@ -276,6 +345,72 @@ __device__ __forceinline__ void tri_solve(double s, const double *Lo, const doub
     }
 }
 
+// Factor and solve at once, for an operator used with one right-hand side
+// (nothing is kept): the reduced coefficients and the reduced right-hand side
+// are published together, so a work-group tile needs a single barrier.  LDS
+// use (work-group tiles): the solve buffers sh[5W, 9W) selected by `ph`.
+template <int W, int M>
+__device__ __forceinline__ void tri_factor_solve(double s, const double *Lo, const double *Up,
+                                                 const double (&b)[M], const double (&d)[M], double (&x)[M],
+                                                 double *sh, int &ph)
+{
+    const int k = tile_lane<W>();
+    auto a = [&](int r) { return s * Lo[r * W + k]; };
+    auto c = [&](int r) { return s * Up[r * W + k]; };
+    if constexpr (W == 64) {
+        WaveFac<M> F;
+        wave_factor<M>(a, c, b, F);
+        wave_solve<M>(a, c, F, d, x);
+    } else {
+        double inv[M - 1], Q[M - 1], R[M - 1], y[M - 1];
+        chunk_factor<M>(a, c, b, inv, Q, R);
+#pragma unroll
+        for (int r = 0; r < M - 1; ++r) y[r] = d[r];
+        chunk_interior<M>(a, c, inv, y);
+        // one exchange: A, B-part, c_e, Q[0], R[0], D-part, y[0] of every chunk
+        double *rg = sh + 7 * W * ph;
+        ph ^= 1;
+        const double ae = a(M - 1), ce = c(M - 1);
+        rg[k] = ae * Q[M - 2];
+        rg[W + k] = ae * R[M - 2] + b[M - 1];
+        rg[2 * W + k] = ce;
+        rg[3 * W + k] = Q[0];
+        rg[4 * W + k] = R[0];
+        rg[5 * W + k] = d[M - 1] - ae * y[M - 2];
+        rg[6 * W + k] = y[0];
+        __syncthreads();
+        const int l = threadIdx.x & 63;
+        double ra[4], rb[4], rc[4], Dr[4], zr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = 4 * l + i;
+            const bool nx = kk + 1 < W;
+            const double cek = rg[2 * W + kk];
+            ra[i] = rg[kk];
+            rb[i] = rg[W + kk] + cek * (nx ? rg[3 * W + kk + 1] : 0.0);
+            rc[i] = cek * (nx ? rg[4 * W + kk + 1] : 0.0);
+            Dr[i] = rg[5 * W + kk] - cek * (nx ? rg[6 * W + kk + 1] : 0.0);
+        }
+        WaveFac<4> RF;
+        wave_factor<4>([&](int r) { return ra[r]; }, [&](int r) { return rc[r]; }, rb, RF);
+        wave_solve<4>([&](int r) { return ra[r]; }, [&](int r) { return rc[r]; }, RF, Dr, zr);
+        const int src = k >> 2, sub = k & 3;
+        const double z0 = __shfl(zr[0], src, 64), z1 = __shfl(zr[1], src, 64);
+        const double z2 = __shfl(zr[2], src, 64), z3 = __shfl(zr[3], src, 64);
+        const double zp = __shfl(zr[3], src > 0 ? src - 1 : 0, 64);
+        const double z = sub == 0 ? z0 : sub == 1 ? z1 : sub == 2 ? z2 : z3;
+        const double zl = sub == 0 ? (k > 0 ? zp : 0.0) : sub == 1 ? z0 : sub == 2 ? z1 : z2;
+#pragma unroll
+        for (int r = 0; r < M - 1; ++r) y[r] = d[r];
+        y[0] -= a(0) * zl;
+        y[M - 2] -= c(M - 2) * z;
+        chunk_interior<M>(a, c, inv, y);
+#pragma unroll
+        for (int r = 0; r < M - 1; ++r) x[r] = y[r];
+        x[M - 1] = z;
+    }
+}
+
 // max over the tile of two values at once (fixed order; same result in every tile thread)
 template <int W>
 __device__ __forceinline__ void tile_max2(double &a, double &b, double *sh)
@@ -286,18 +421,19 @@ __device__ __forceinline__ void tile_max2(double &a, double &b, double *sh)
         b = fmax(b, __shfl_xor(b, o, 64));
     }
     if constexpr (W == 256) {
+        double *m2 = sh + 14 * W;
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
-            sh[w] = a;
-            sh[8 + w] = b;
+            m2[w] = a;
+            m2[8 + w] = b;
         }
         __syncthreads();
-        a = sh[0];
-        b = sh[8];
+        a = m2[0];
+        b = m2[8];
 #pragma unroll
         for (int q = 1; q < W / 64; ++q) {
-            a = fmax(a, sh[q]);
-            b = fmax(b, sh[8 + q]);
+            a = fmax(a, m2[q]);
+            b = fmax(b, m2[8 + q]);
         }
         __syncthreads();
     }
