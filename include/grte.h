@@ -225,6 +225,38 @@ grte_status grte_set_guess(grte_ctx *ctx, const grte_mlp *model, double accept_t
  * step since the last grte_set_state.  Enqueued on the context's stream. */
 grte_status grte_log_pairs(grte_ctx *ctx, float *dev_rows, long long cap_rows, long long *n_rows);
 
+/* ------------------------------------------------------------------------
+ * The discrete nonlinear diffusion limit on the GPU: the three-stage scheme
+ * (2.7) (sigma independent of T) and its sigma0/T^3 form (2.9), and the
+ * two-stage scheme (2.8).  State T per cell (N <= 4096) on the cell-centred
+ * grid of the AP step; face coefficients a c K/(3 sigma) with the harmonic
+ * mean of sigma0 and the mean of K = T^m of the two cells.  Boundaries:
+ * 0 = zero flux, 1 = ghost temperatures one cell outside each end (the
+ * boundary cell's coefficient on the boundary face).
+ * ------------------------------------------------------------------------ */
+typedef struct grte_diff grte_diff;
+typedef struct grte_diff_problem {
+    int nx;                   /* cells, 2 <= N <= 4096                            */
+    double length, a, c, cv;
+    int opacity_law;          /* 0: sigma = sigma0; 3: sigma = sigma0 / T^3       */
+    int boundary;             /* 0: zero flux; 1: ghost temperatures              */
+    double ghost_left, ghost_right;
+} grte_diff_problem;
+enum { GRTE_DIFF_THREE_STAGE = 0, GRTE_DIFF_TWO_STAGE = 1 };
+grte_status grte_diff_create(const grte_diff_problem *pb, grte_diff **out);
+grte_status grte_diff_destroy(grte_diff *d);
+grte_status grte_diff_set_stream(grte_diff *d, void *hip_stream);
+grte_status grte_diff_set_opacity(grte_diff *d, const double *sigma0, int on_device);  /* > 0 */
+grte_status grte_diff_set_state(grte_diff *d, const double *T, int on_device);         /* T >= 0 */
+/* T^{n} after the last step and U* of its prediction (either may be NULL). */
+grte_status grte_diff_get_state(grte_diff *d, double *T, double *Ustar, int on_device);
+/* One step.  scheme: GRTE_DIFF_*; corr_K (sigma0/T^3 only): 0 = the correction
+ * flux with K^n (the limit of the AP step), 1 = with (U*)^{3/4} as printed in
+ * (2.9); a_time < 0: a, otherwise a_time replaces a in the time-derivative
+ * terms (a_time = 0 gives a porous-medium equation).  newton_its (may be NULL;
+ * then the call only enqueues): largest Newton count; GRTE_E_NOCONV at the cap. */
+grte_status grte_diff_step(grte_diff *d, double dt, int scheme, int corr_K, double a_time, int *newton_its);
+
 /* Static text for a status code. */
 const char *grte_status_string(grte_status s);
 

@@ -13,9 +13,9 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import BatchInfo, BatchTuning, GrteError, Instance, Problem, StepInfo, check, load
+from ._lib import BatchInfo, BatchTuning, DiffProblem, GrteError, Instance, Problem, StepInfo, check, load
 
-__all__ = ["Grte", "GrteBatch", "GrteError", "Mlp", "gauss_legendre", "load", "step_group"]
+__all__ = ["Grte", "GrteBatch", "GrteDiff", "GrteError", "Mlp", "gauss_legendre", "load", "step_group"]
 
 
 def gauss_legendre(nv):
@@ -411,3 +411,59 @@ class GrteBatch:
         check("grte_batch_read_timing", self._lib.grte_batch_read_timing(self._h, ctypes.byref(ms),
                                                                          ctypes.byref(cnt)))
         return float(ms.value), int(cnt.value)
+
+
+class GrteDiff:
+    """Discrete nonlinear diffusion limit: three-stage (2.7)/(2.9) or two-stage
+    (2.8) scheme on the GPU (grte_diff_*)."""
+
+    THREE_STAGE, TWO_STAGE = 0, 1
+
+    def __init__(self, nx, length=1.0, a=1.0, c=1.0, cv=1.0, opacity_law=0, boundary="neumann",
+                 ghost=(0.0, 0.0)):
+        self._lib = load()
+        bc = {"neumann": 0, "dirichlet": 1}[boundary]
+        pb = DiffProblem(int(nx), float(length), float(a), float(c), float(cv), int(opacity_law), bc,
+                         float(ghost[0]), float(ghost[1]))
+        h = ctypes.c_void_p()
+        check("grte_diff_create", self._lib.grte_diff_create(ctypes.byref(pb), ctypes.byref(h)))
+        self._h = h
+        self.N = int(nx)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.grte_diff_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_opacity(self, sigma0):
+        p, dev = _ptr(sigma0, self.N, "sigma0")
+        check("grte_diff_set_opacity", self._lib.grte_diff_set_opacity(self._h, _addr(p), dev))
+
+    def set_state(self, T):
+        p, dev = _ptr(T, self.N, "T")
+        check("grte_diff_set_state", self._lib.grte_diff_set_state(self._h, _addr(p), dev))
+
+    def get_state(self):
+        """(T, U* of the last prediction) as numpy arrays."""
+        T = np.empty(self.N)
+        U = np.empty(self.N)
+        check("grte_diff_get_state", self._lib.grte_diff_get_state(self._h, T.ctypes.data, U.ctypes.data, 0))
+        return T, U
+
+    def step(self, dt, scheme=0, corr_K="old", a_time=None, info=False):
+        ck = {"old": 0, "predicted": 1}[corr_K]
+        at = -1.0 if a_time is None else float(a_time)
+        if not info:
+            check("grte_diff_step", self._lib.grte_diff_step(self._h, float(dt), int(scheme), ck, at, None))
+            return None
+        its = ctypes.c_int()
+        st = self._lib.grte_diff_step(self._h, float(dt), int(scheme), ck, at, ctypes.byref(its))
+        if st not in (0, -4):
+            check("grte_diff_step", st)
+        return {"status": st, "newton_max_iters": int(its.value)}

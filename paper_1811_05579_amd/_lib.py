@@ -36,6 +36,12 @@ class Instance(ctypes.Structure):
                 ("eps", c_double)]
 
 
+class DiffProblem(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("length", c_double), ("a", c_double), ("c", c_double), ("cv", c_double),
+                ("opacity_law", c_int), ("boundary", c_int), ("ghost_left", c_double),
+                ("ghost_right", c_double)]
+
+
 class BatchInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
                 ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int)]
@@ -79,6 +85,13 @@ _SIGS = {
     "grte_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
     "grte_set_storage": (c_int, [c_void_p, c_int]),
     "grte_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
+    "grte_diff_create": (c_int, [ctypes.POINTER(DiffProblem), ctypes.POINTER(c_void_p)]),
+    "grte_diff_destroy": (c_int, [c_void_p]),
+    "grte_diff_set_stream": (c_int, [c_void_p, c_void_p]),
+    "grte_diff_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
+    "grte_diff_set_state": (c_int, [c_void_p, c_void_p, c_int]),
+    "grte_diff_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    "grte_diff_step": (c_int, [c_void_p, c_double, c_int, c_int, c_double, ctypes.POINTER(c_int)]),
     "grte_batch_create": (c_int, [c_int, ctypes.POINTER(Instance), c_void_p, c_void_p,
                                   ctypes.POINTER(c_void_p)]),
     "grte_batch_destroy": (c_int, [c_void_p]),

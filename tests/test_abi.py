@@ -127,3 +127,17 @@ def test_group_step_invalid_arguments(lib):
     hs5 = (ctypes.c_void_p * 5)()
     d5 = np.full(5, 0.1)
     assert lib.grte_step_group(hs5, 5, d5.ctypes.data, d5.ctypes.data, None) == -5
+
+
+def test_diffusion_invalid_arguments(lib):
+    from paper_1811_05579_amd._lib import DiffProblem
+    h = ctypes.c_void_p()
+    for pb in (DiffProblem(1, 1.0, 1.0, 1.0, 1.0, 0, 0, 0.0, 0.0),     # N < 2
+               DiffProblem(8, 1.0, 1.0, 1.0, 1.0, 1, 0, 0.0, 0.0),     # opacity law
+               DiffProblem(8, 1.0, 1.0, 1.0, 1.0, 0, 2, 0.0, 0.0),     # boundary kind
+               DiffProblem(8, 1.0, 1.0, 1.0, 1.0, 0, 1, -1.0, 0.0)):   # ghost T < 0
+        assert lib.grte_diff_create(ctypes.byref(pb), ctypes.byref(h)) == -1
+    big = DiffProblem(5000, 1.0, 1.0, 1.0, 1.0, 0, 0, 0.0, 0.0)
+    assert lib.grte_diff_create(ctypes.byref(big), ctypes.byref(h)) == -5
+    assert lib.grte_diff_step(None, 0.1, 0, 0, -1.0, None) == -1
+    assert lib.grte_diff_destroy(None) == 0
