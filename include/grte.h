@@ -142,6 +142,21 @@ grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info
 grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, const double *eps,
                             grte_step_info *info);
 
+/* The iterative implicit reference solver of the paper's nonlinear-opacity
+ * examples, (6.6): backward Euler in I and U with the opacity sigma0/T^3
+ * frozen at the previous iterate T^(k) = (U^(k))^(1/4), iterated from
+ * T^(0) = T^n until max|T^(k+1) - T^(k)| <= tol max T^(k+1) (at most maxit
+ * times).  On the parity grid one iteration is the prediction system (5.2)
+ * with K from T^(k); at the fixed point E^{n+1} = E*, O^{n+1} = O*,
+ * U^{n+1} = U*.  Replaces the state like grte_step; synchronises.
+ * GRTE_E_NOCONV if the iteration (or a prediction solve) hit its cap;
+ * GRTE_E_UNSUPPORTED with binary32 storage. */
+typedef struct grte_reference_info {
+    int picard_iters, converged, pred_max_iters, pred_failed, sync_error;
+} grte_reference_info;
+grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol, int maxit,
+                                grte_reference_info *info);
+
 /* Storage of the intensity state: 0 = binary64 (default); 1 = binary32, with
  * E kept per cell and pair as its binary32 deviation from a c T^4 (T stays
  * binary64) and O in binary32.  The prediction, Newton and correction

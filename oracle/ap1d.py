@@ -98,20 +98,22 @@ def _index(N, P):
 # --------------------------------------------------------------------------
 # Prediction: (4.5a)-(4.5c), inflow relations (4.6); sigma/T^3 form (5.2)
 # --------------------------------------------------------------------------
-def predict(E, O, T, sigma0, mu, omega, bL, bR, ph):
+def predict(E, O, T, sigma0, mu, omega, bL, bR, ph, T_K=None):
     """Solve the prediction system for E*, O*, U* (extended precision).
 
     Following the recipe after (4.5): U* is written in terms of E* with
     (4.5c), substituted into (4.5b), and (4.5a)+(4.5b)+(4.6) is solved as one
     linear system in (E*, O*).  Rows of (4.5a) and (4.5b) are multiplied by
-    eps^2 c dt (a row scaling; the solution is unchanged).
+    eps^2 c dt (a row scaling; the solution is unchanged).  `T_K` (default T)
+    is the temperature that defines K = T^m of the sigma/T^3 form (5.2); U^n
+    and beta always come from T.
     """
     N, P = E.shape
     a, c, Cv, eps, dt, L = ph.ext()
     m = ph.m
     dx = L / N
     U = T ** 4
-    Kc = cell_K(T, m)
+    Kc = cell_K(T if T_K is None else T_K, m)
     Kn = node_K(Kc)
     sn = node_sigma(sigma0)
     # (4.5c): Cv (U* - U^n)/dt = 4 sigma0 (T^n)^(3-m) (rho* - ac U*) / eps^2
@@ -359,6 +361,35 @@ def ap_step(E, O, T, sigma0, mu, omega, bL, bR, ph, newton_maxit=200):
                 K_star=f64(Kstar), E_J=f64(EJ), O_J=f64(OJ),
                 rho=f64(moment(Enew, omx)),
                 newton_its=its, newton_converged=conv)
+
+
+def implicit_reference_step(E, O, T, sigma0, mu, omega, bL, bR, ph, tol=1e-14, maxit=500):
+    """The iterative implicit reference solver of the paper's nonlinear-opacity
+    examples, (6.6): backward Euler in I and U with the opacity sigma0/T^3
+    evaluated at the previous iterate T^(k) = (U^(k))^(1/4), iterated from
+    T^(0) = T^n until T stops changing (max |T^(k+1) - T^(k)| <= tol max T).
+    On the parity grid one iteration is the prediction system (5.2) with K
+    from T^(k) (U^n and the material coupling from T^n); at the fixed point
+    E^{n+1} = E*, O^{n+1} = O*, U^{n+1} = U*.  Returns a dict with E, O, T, U,
+    the iteration count and whether it converged."""
+    E = np.asarray(E, dtype=np.float64)
+    O = np.asarray(O, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    Ex, Ox, Tx, sx = (np.asarray(x, dtype=XP) for x in (E, O, T, np.asarray(sigma0, dtype=np.float64)))
+    mux, omx = np.asarray(mu, dtype=XP), np.asarray(omega, dtype=XP)
+    bLx, bRx = np.asarray(bL, dtype=XP), np.asarray(bR, dtype=XP)
+    Tk = Tx.copy()
+    conv = False
+    for k in range(1, maxit + 1):
+        Es, Os, Us = predict(Ex, Ox, Tx, sx, mux, omx, bLx, bRx, ph, T_K=Tk)
+        Tn1 = np.maximum(Us, 0) ** XP(0.25)
+        done = np.max(np.abs(Tn1 - Tk)) <= tol * np.max(np.abs(Tn1))
+        Tk = Tn1
+        if done:
+            conv = True
+            break
+    f64 = lambda x: np.asarray(x, dtype=np.float64)
+    return dict(E=f64(Es), O=f64(Os), T=f64(Tk), U=f64(Us), iterations=k, converged=conv)
 
 
 def intensity(E, O, eps):

@@ -139,6 +139,18 @@ class Grte:
         check("grte_read_timing", self._lib.grte_read_timing(self._h, ms.ctypes.data, cnt.ctypes.data))
         return {k: (float(ms[v]), int(cnt[v])) for k, v in _lib.TIMING.items()}
 
+    def reference_step(self, dt, eps, tol=1e-14, maxit=500):
+        """One step of the iterative implicit reference solver (6.6); returns
+        its diagnostics (dict with 'status')."""
+        inf = _lib.ReferenceInfo()
+        st = self._lib.grte_reference_step(self._h, float(dt), float(eps), float(tol), int(maxit),
+                                           ctypes.byref(inf))
+        if st not in (0, -4):
+            check("grte_reference_step", st)
+        d = {k: getattr(inf, k) for k, _ in _lib.ReferenceInfo._fields_}
+        d["status"] = st
+        return d
+
     def set_storage(self, fp32):
         """Store E (as its deviation from a c T^4) and O in binary32 (True) or
         binary64 (False); arithmetic stays binary64."""

@@ -42,6 +42,11 @@ class DiffProblem(ctypes.Structure):
                 ("ghost_right", c_double)]
 
 
+class ReferenceInfo(ctypes.Structure):
+    _fields_ = [("picard_iters", c_int), ("converged", c_int), ("pred_max_iters", c_int),
+                ("pred_failed", c_int), ("sync_error", c_int)]
+
+
 class BatchInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
                 ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int)]
@@ -84,6 +89,8 @@ _SIGS = {
     "grte_mlp_predict": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_void_p]),
     "grte_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
     "grte_set_storage": (c_int, [c_void_p, c_int]),
+    "grte_reference_step": (c_int, [c_void_p, c_double, c_double, c_double, c_int,
+                                    ctypes.POINTER(ReferenceInfo)]),
     "grte_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
     "grte_diff_create": (c_int, [ctypes.POINTER(DiffProblem), ctypes.POINTER(c_void_p)]),
     "grte_diff_destroy": (c_int, [c_void_p]),

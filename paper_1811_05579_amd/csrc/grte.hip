@@ -686,6 +686,57 @@ __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
     }
 }
 
+// ---- iterative implicit reference (6.6): Picard update of the opacity temperature
+// U* = (U^n + beta rho*)/(1 + ac beta), T^(k+1) = max(U*, 0)^(1/4); the largest
+// change and the largest T^(k+1) (non-negative doubles: their bit patterns
+// order like unsigned integers) are reduced with one atomic per work-group
+__global__ void __launch_bounds__(256) picard_update_kernel(int N, double ac, const double *Tn, const double *beta,
+                                                            const double *rho_star, const double *Tk, double *Tk1,
+                                                            double *ustar, unsigned long long *dmax)
+{
+    __shared__ double s_d[256], s_t[256];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    double d = 0.0, tv = 0.0;
+    if (j < N) {
+        const double t = Tn[j];
+        const double us = ((t * t) * (t * t) + beta[j] * rho_star[j]) / (1.0 + ac * beta[j]);
+        const double t1 = pow(fmax(us, 0.0), 0.25);
+        ustar[j] = us;
+        Tk1[j] = t1;
+        d = fabs(t1 - Tk[j]);
+        tv = t1;
+    }
+    s_d[threadIdx.x] = d;
+    s_t[threadIdx.x] = tv;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s_d[threadIdx.x] = fmax(s_d[threadIdx.x], s_d[threadIdx.x + o]);
+            s_t[threadIdx.x] = fmax(s_t[threadIdx.x], s_t[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&dmax[0], (unsigned long long)__double_as_longlong(s_d[0]));
+        atomicMax(&dmax[1], (unsigned long long)__double_as_longlong(s_t[0]));
+    }
+}
+
+__global__ void clear_u64(unsigned long long *x, int n)
+{
+    if ((int)threadIdx.x < n) x[threadIdx.x] = 0ull;
+}
+
+// O at every node from cell values E (cell-major) through the node relation
+__global__ void node_all_kernel(int N, int P, double eps, const double *E, const double *O, const double *Aw,
+                                const double *Bc, const double *mu, const double *bL, const double *bR, double *Oout)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (N + 1) * P) return;
+    const int i = t / P, p = t - (t / P) * P;
+    Oout[t] = node_any(E, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, i, p);
+}
+
 // between binary64 state arrays and binary32 storage (E as the deviation from a c T^4)
 __global__ void convert_state_kernel(int N, int P, double ac, const double *T, double *E, double *O, float *E32,
                                      float *O32, int to32)
@@ -1304,6 +1355,108 @@ grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, cons
             if (ctxs[h] == ctxs[g]) return GRTE_E_INVAL;
     }
     return step_group(ctxs, n, dt, eps, info);
+}
+
+grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol, int maxit,
+                                grte_reference_info *info)
+{
+    if (!ctx || !(dt > 0) || !(eps > 0) || !std::isfinite(dt) || !std::isfinite(eps) || !(tol > 0) || maxit < 1)
+        return GRTE_E_INVAL;
+    if (ctx->f32) return GRTE_E_UNSUPPORTED;
+    const int N = ctx->N, P = ctx->P, M = ctx->M;
+    const double dx = ctx->L / N;
+    hipStream_t stream = ctx->stream;
+    double *Tk = ctx->T2, *Tk1 = ctx->rstar;   // Picard iterates (scratch of the normal step)
+    HIPCHK(hipMemcpyAsync(Tk, ctx->T, N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    unsigned long long *dmax = ctx->flags + (size_t)(MAX_P - 1) * BAR_STRIDE + 8;   // spare words of the last flag line
+    Group<CoefArgs> gc{};
+    gc.n = 1;
+    CoefArgs &ca = gc.a[0];
+    ca.N = N; ca.P = P; ca.m = ctx->m; ca.mode = 0; ca.cpb = ctx->cpb;
+    ca.a = ctx->a; ca.c = ctx->c; ca.cv = ctx->cv; ca.eps = eps; ca.dt = dt; ca.dx = dx;
+    ca.Tn = ctx->T; ca.sigma0 = ctx->sigma0; ca.mu = ctx->mu; ca.omega = ctx->omega;
+    ca.bL = ctx->bL; ca.bR = ctx->bR; ca.E = ctx->E; ca.O = ctx->O;
+    ca.mu1 = ctx->mu1; ca.mu2 = ctx->mu2;
+    ca.Ll = ctx->Ll; ca.Lu = ctx->Lu; ca.Lam = ctx->Lam; ca.LmG = ctx->LmG; ca.Gt = ctx->Gt; ca.M = M;
+    ca.Bd = ctx->Bd; ca.Aw = ctx->Aw; ca.Bc = ctx->Bc; ca.beta = ctx->beta;
+    ca.Dl = ctx->Dl; ca.Dd = ctx->Dd; ca.Du = ctx->Du; ca.rho_n = ctx->rho_n; ca.r = ctx->r;
+    ca.stat = ctx->stat;
+    Group<PredArgs> gp{};
+    gp.n = 1;
+    gp.first[0] = 0;
+    gp.first[1] = P;
+    PredArgs &pa = gp.a[0];
+    pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
+    pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
+    pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
+    pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
+    pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->estar_t; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
+    pa.flags = ctx->flags;
+    const unsigned ncb = (unsigned)((N + ctx->cpb - 1) / ctx->cpb);
+    const double ac = ctx->a * ctx->c;
+    int k = 0, converged = 0, worst_pred = 0, pred_fail = 0, sync_err = 0;
+    grte_status st = GRTE_OK;
+    for (k = 1; k <= maxit; ++k) {
+        ca.T = Tk;                                    // K from the current opacity temperature
+        hipLaunchKernelGGL(coef_kernel, dim3(ncb, 1), dim3(256), 0, stream, gc);
+        HIPCHK(hipGetLastError());
+        pa.gen0 = ctx->bar_gen;
+        ctx->bar_gen += 2ull * (unsigned long long)ctx->pred_maxit + 4ull;
+        switch (M) {
+        case 2: st = launch_pred<2>(stream, gp, P); break;
+        case 4: st = launch_pred<4>(stream, gp, P); break;
+        case 8: st = launch_pred<8>(stream, gp, P); break;
+        default: st = launch_pred<16>(stream, gp, P); break;
+        }
+        if (st != GRTE_OK) return st;
+        hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, stream, dmax, 2);
+        hipLaunchKernelGGL(picard_update_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, N, ac,
+                           ctx->T, ctx->beta, ctx->rho, Tk, Tk1, ctx->ustar, dmax);
+        HIPCHK(hipGetLastError());
+        unsigned long long h[2];
+        int hs[8];
+        HIPCHK(hipMemcpyAsync(h, dmax, sizeof(h), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(hs, ctx->stat, sizeof(hs), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        worst_pred = std::max(worst_pred, hs[0]);
+        if (!hs[1]) pred_fail = 1;
+        if (hs[6]) { sync_err = 1; break; }
+        double d, tmax;
+        std::memcpy(&d, &h[0], sizeof(d));
+        std::memcpy(&tmax, &h[1], sizeof(tmax));
+        std::swap(Tk, Tk1);                           // Tk holds T^(k+1)
+        if (d <= tol * tmax) { converged = 1; break; }
+    }
+    if (k > maxit) k = maxit;
+    ctx->T2 = Tk;
+    ctx->rstar = Tk1;
+    if (!sync_err) {
+        // E^{n+1} = E* and O^{n+1} = O* of the last prediction (K from the last T^(k))
+        Group<NewtonArgs> gn{};
+        gn.n = 1;
+        NewtonArgs &na = gn.a[0];
+        na.N = N; na.P = P; na.M = M; na.estar_t = ctx->estar_t; na.Ecm = ctx->E2;
+        hipLaunchKernelGGL(gather_estar_kernel, dim3((unsigned)(((size_t)N * P + 255) / 256), 1), dim3(256), 0,
+                           stream, gn);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(node_all_kernel, dim3((unsigned)(((size_t)(N + 1) * P + 255) / 256)), dim3(256), 0,
+                           stream, N, P, eps, ctx->E2, ctx->O, ctx->Aw, ctx->Bc, ctx->mu, ctx->bL, ctx->bR, ctx->O2);
+        HIPCHK(hipGetLastError());
+        std::swap(ctx->E, ctx->E2);
+        std::swap(ctx->O, ctx->O2);
+        std::swap(ctx->T, ctx->T2);
+        ctx->stepped = 0;
+        HIPCHK(hipStreamSynchronize(stream));
+    }
+    if (info) {
+        info->picard_iters = k;
+        info->converged = converged;
+        info->pred_max_iters = worst_pred;
+        info->pred_failed = pred_fail;
+        info->sync_error = sync_err;
+    }
+    if (sync_err) return GRTE_E_HIP;
+    return (converged && !pred_fail) ? GRTE_OK : GRTE_E_NOCONV;
 }
 
 grte_status grte_set_storage(grte_ctx *ctx, int fp32)
