@@ -75,6 +75,8 @@ typedef struct grte_step_info {
                              hit the cap: solved from T^n                      */
     int newton_total_iters; /* Newton iterations summed over the cells         */
     int guess_started;    /* cells whose Newton started from the learned value */
+    int pred_floor_stop;  /* 1 if the prediction stopped at the rounding level
+                             (counted in pred_converged; see grte_set_solver) */
 } grte_step_info;
 
 /* Stages readable after a step (grte_get_stage), for checking and diagnostics. */
@@ -167,12 +169,46 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
  * storage represents). */
 grte_status grte_set_storage(grte_ctx *ctx, int fp32);
 
+/* Convergence history of the last prediction solve of ctx (of a grte_step,
+ * grte_step_group or the last Picard sweep of grte_reference_step): entry k is
+ * max|z| / max|rho| of update k + 1, the quantity the stopping test compares
+ * with pred_tol.  The first GRTE_HIST_CAP updates are kept.  Copies
+ * min(cap, updates kept) values to the host array out, sets *n to that count
+ * and synchronises the context's stream.  GRTE_E_INVAL for a null ctx or n,
+ * a negative cap, or a null out with cap > 0. */
+enum { GRTE_HIST_CAP = 1024 };
+grte_status grte_get_pred_history(grte_ctx *ctx, double *out, int cap, int *n);
+
 /* Copy a stage of the last step (GRTE_STAGE_*) into out (sizes above). */
 grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device);
 
 /* Solver controls: relative tolerance of the prediction update (default
- * 1e-15), its iteration cap (default 200) and the Newton cap (default 100). */
+ * 1e-15), its iteration cap (default 200) and the Newton cap (default 100).
+ * The prediction stops when max|z| <= pred_tol max|rho| for its update z, or,
+ * as a safeguard, when max|z| <= 16 pred_tol max|rho| and max|z| / max|rho|
+ * has not decreased over the last two updates: the update norm has then
+ * reached the rounding level of the residual evaluation (about 1e-16 relative
+ * on optically thick slabs, e.g. N = 4096, 64 ordinates, eps = 1e-4), where it
+ * only fluctuates.  Both count as converged (info pred_converged); the second
+ * also sets pred_floor_stop. */
 grte_status grte_set_solver(grte_ctx *ctx, double pred_tol, int pred_maxit, int newton_maxit);
+
+/* Acceleration of the prediction iteration (default GRTE_ACCEL_CHEBYSHEV).
+ * Both modes iterate the same DSA-preconditioned update z = res + D^-1 (G res)
+ * and stop on the same test max|z| <= pred_tol max|rho|; they differ only in
+ * how z is applied:
+ *   GRTE_ACCEL_RICHARDSON  rho += z;
+ *   GRTE_ACCEL_CHEBYSHEV   plain updates until the contraction ratio r of
+ *     the update norms has settled (two consecutive ratios within 15%, r <= 0.5,
+ *     update norm above 100 pred_tol max|rho|), then the Chebyshev
+ *     semi-iteration for an iteration-matrix spectrum in [0, 1.2 r]; plain
+ *     updates for the rest of the solve if, 4 or more steps in, the update norm
+ *     is above what plain updates at ratio r would have reached, or above the
+ *     norm at which the recurrence began.  No inner products are formed.
+ * The converged rho agrees between the modes to the tolerance; iteration
+ * counts differ.  GRTE_E_INVAL for another mode. */
+enum { GRTE_ACCEL_RICHARDSON = 0, GRTE_ACCEL_CHEBYSHEV = 1 };
+grte_status grte_set_acceleration(grte_ctx *ctx, int mode);
 
 /* Stage timing with HIP events recorded on the context's stream around each
  * timed stage of every grte_step (off by default; enabling resets the log). */
@@ -304,6 +340,7 @@ typedef struct grte_instance {
 typedef struct grte_batch_info {   /* per instance, as grte_step_info         */
     int pred_iters, pred_converged, newton_max_iters, newton_failed;
     int kstar_clamped, negative_root;
+    int pred_floor_stop;
 } grte_batch_info;
 
 typedef struct grte_batch_tuning {
@@ -324,6 +361,10 @@ grte_status grte_batch_sizes(const grte_batch *b, long long *cells, long long *e
                              long long *o_len, long long *pairs);
 grte_status grte_batch_set_stream(grte_batch *b, void *hip_stream);
 grte_status grte_batch_set_solver(grte_batch *b, double pred_tol, int pred_maxit, int newton_maxit);
+/* Acceleration of the prediction iteration of every instance (GRTE_ACCEL_*,
+ * as grte_set_acceleration; default GRTE_ACCEL_CHEBYSHEV).  Takes effect at
+ * the next step (a captured step graph is rebuilt). */
+grte_status grte_batch_set_acceleration(grte_batch *b, int mode);
 /* Packed sigma0[cells]; packed inflow b_left[pairs], b_right[pairs] (host). */
 grte_status grte_batch_set_opacity(grte_batch *b, const double *sigma0, int on_device);
 grte_status grte_batch_set_inflow(grte_batch *b, const double *b_left, const double *b_right);

@@ -82,6 +82,21 @@ class Grte:
         check("grte_set_solver", self._lib.grte_set_solver(self._h, float(pred_tol), int(pred_maxit),
                                                            int(newton_maxit)))
 
+    def set_acceleration(self, mode):
+        """'chebyshev' (default) or 'richardson' for the prediction iteration."""
+        modes = {"richardson": 0, "chebyshev": 1}
+        if mode not in modes:
+            raise ValueError(f"acceleration must be one of {sorted(modes)}")
+        check("grte_set_acceleration", self._lib.grte_set_acceleration(self._h, modes[mode]))
+
+    def pred_history(self):
+        """max|z| / max|rho| of each update of the last prediction solve."""
+        out = np.zeros(1024)
+        n = ctypes.c_int(0)
+        check("grte_get_pred_history", self._lib.grte_get_pred_history(
+            self._h, out.ctypes.data, out.size, ctypes.byref(n)))
+        return out[:n.value].copy()
+
     def set_opacity(self, sigma0):
         p, dev = _ptr(sigma0, self.N, "sigma0")
         check("grte_set_opacity", self._lib.grte_set_opacity(self._h, _addr(p), dev))
@@ -343,6 +358,13 @@ class GrteBatch:
     def set_solver(self, pred_tol=1e-15, pred_maxit=200, newton_maxit=100):
         check("grte_batch_set_solver", self._lib.grte_batch_set_solver(
             self._h, float(pred_tol), int(pred_maxit), int(newton_maxit)))
+
+    def set_acceleration(self, mode):
+        """'chebyshev' (default) or 'richardson' for every instance's prediction."""
+        modes = {"richardson": 0, "chebyshev": 1}
+        if mode not in modes:
+            raise ValueError(f"acceleration must be one of {sorted(modes)}")
+        check("grte_batch_set_acceleration", self._lib.grte_batch_set_acceleration(self._h, modes[mode]))
 
     def set_opacity(self, sigma0):
         p, dev = _ptr(sigma0, self.n_cells, "sigma0")

@@ -24,7 +24,7 @@ class StepInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
                 ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int),
                 ("sync_error", c_int), ("guess_accepted", c_int), ("guess_rejected", c_int),
-                ("newton_total_iters", c_int), ("guess_started", c_int)]
+                ("newton_total_iters", c_int), ("guess_started", c_int), ("pred_floor_stop", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -49,7 +49,8 @@ class ReferenceInfo(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
-                ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int)]
+                ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int),
+                ("pred_floor_stop", c_int)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -72,6 +73,8 @@ _SIGS = {
                                 ctypes.POINTER(StepInfo)]),
     "grte_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
     "grte_set_solver": (c_int, [c_void_p, c_double, c_int, c_int]),
+    "grte_set_acceleration": (c_int, [c_void_p, c_int]),
+    "grte_get_pred_history": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     "grte_set_profiling": (c_int, [c_void_p, c_int]),
     "grte_read_timing": (c_int, [c_void_p, c_void_p, c_void_p]),
     "grte_status_string": (ctypes.c_char_p, [c_int]),
@@ -105,6 +108,7 @@ _SIGS = {
     "grte_batch_sizes": (c_int, [c_void_p, c_ll_p, c_ll_p, c_ll_p, c_ll_p]),
     "grte_batch_set_stream": (c_int, [c_void_p, c_void_p]),
     "grte_batch_set_solver": (c_int, [c_void_p, c_double, c_int, c_int]),
+    "grte_batch_set_acceleration": (c_int, [c_void_p, c_int]),
     "grte_batch_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
     "grte_batch_set_inflow": (c_int, [c_void_p, c_void_p, c_void_p]),
     "grte_batch_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),

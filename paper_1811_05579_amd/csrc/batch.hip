@@ -69,6 +69,7 @@ struct BatchArgs {
     int *istat;                        // 8 per instance
     double tol;
     int maxit, newton_maxit;
+    int accel;                  // prediction acceleration (GRTE_ACCEL_*)
 };
 
 // make the tile's LDS and global writes visible to the whole tile
@@ -189,7 +190,7 @@ __device__ void b_rhs(const BInst &I, const double *C, int N1, const double *E, 
 }
 
 template <int W, int M>
-__device__ void run_instance(const BatchArgs &A, int i, double *sm)
+__device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *sm)
 {
     constexpr int NP = W * M;
     const BInst I = A.inst[i];
@@ -238,6 +239,10 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
         lmg[r] = in ? C[C_LMG * N1 + j] : 0.0;
     }
     int it = 0, converged = 0, ph = 0;
+    ChebState Cs;
+    float dch[M];                             // previous update (steers the next one only)
+#pragma unroll
+    for (int r = 0; r < M; ++r) dch[r] = 0.0f;
     while (true) {
         double acc[M], rnext[M];
 #pragma unroll
@@ -264,10 +269,10 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
                     const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
                     b[r] = lam[r] + m2 * (-(ll + lu)) + m1 * bdj;
                     const double rj = rho[t];
-                    double rl = 0.0, rn = 0.0;
+                    double rl = rj, rn = rj;   // boundary rows: ll or lu is 0
                     if (j > 0) rl = (r > 0) ? rho[t - W] : rho[(M - 1) * W + k - 1];
                     if (j < N - 1) rn = (r < M - 1) ? rho[t + W] : rho[k + 1];
-                    const double q = -(ll + lu) * rj + ll * rl + lu * rn;
+                    const double q = ll * (rl - rj) + lu * (rn - rj);   // difference form (low rounding floor)
                     y[r] = rcur[r] - lmg[r] * rj - m2 * q - m1 * bdj * rj;
                 } else {
                     b[r] = 1.0;
@@ -299,22 +304,29 @@ __device__ void run_instance(const BatchArgs &A, int i, double *sm)
             }
             tri_factor_solve<W, M>(I.mu2, sLl, sLu, b, d, f, sh, ph);
         }
+        double alpha, beta;
+        cheb_coeffs(Cs, A.accel, A.tol, alpha, beta);
         double md = 0.0, mr = 0.0;
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             if (j0 + r < N) {
                 const int t = r * W + k;
-                const double delta = rl[r] + f[r];
-                const double nw = rho[t] + delta;
+                const double z = rl[r] + f[r];
+                const double upd = alpha * (double)dch[r] + beta * z;
+                dch[r] = (float)upd;
+                const double nw = rho[t] + upd;
                 rho[t] = nw;
-                md = fmax(md, fabs(delta));
+                md = fmax(md, fabs(z));
                 mr = fmax(mr, fabs(nw));
             }
         }
         tile_max2<W>(md, mr, sh);
         tsync<W>();                               // rho update and E* visible to the tile
         ++it;
-        converged = (md <= A.tol * mr) ? 1 : 0;
+        const float qprev = Cs.q1, qprev2 = Cs.q2;
+        const float q = (float)(mr > 0.0 ? md / mr : md);
+        cheb_record(Cs, q);
+        converged = pred_stop(md, mr, q, qprev, qprev2, it, A.tol);
         if (converged || it >= A.maxit) break;
     }
     if (k == 0) {
@@ -509,6 +521,7 @@ struct grte_batch {
     int wave_max_n = 256, grid = 0, tuned = 0;
     double tol = 1e-15;
     int maxit = 200, newton_maxit = 100;
+    int accel = GRTE_ACCEL_CHEBYSHEV;
     long long tot_cells = 0, tot_E = 0, tot_O = 0, tot_pairs = 0;
     std::vector<BInst> h_inst;
     std::vector<int> h_order;
@@ -606,7 +619,7 @@ BatchArgs make_args(const grte_batch *b, int src)
     A.E2 = b->E[1 - src]; A.O2 = b->O[1 - src]; A.T2 = b->T[1 - src];
     A.sigma0 = b->sigma0; A.mu = b->mu; A.omega = b->omega; A.bL = b->bL; A.bR = b->bR;
     A.cells = b->cells; A.pairs = b->pairs; A.istat = b->d_istat;
-    A.tol = b->tol; A.maxit = b->maxit; A.newton_maxit = b->newton_maxit;
+    A.tol = b->tol; A.maxit = b->maxit; A.newton_maxit = b->newton_maxit; A.accel = b->accel;
     return A;
 }
 
@@ -837,6 +850,14 @@ grte_status grte_batch_set_solver(grte_batch *b, double pred_tol, int pred_maxit
     return GRTE_OK;
 }
 
+grte_status grte_batch_set_acceleration(grte_batch *b, int mode)
+{
+    if (!b || (mode != GRTE_ACCEL_RICHARDSON && mode != GRTE_ACCEL_CHEBYSHEV)) return GRTE_E_INVAL;
+    b->accel = mode;
+    drop_graphs(b);
+    return GRTE_OK;
+}
+
 grte_status grte_batch_set_opacity(grte_batch *b, const double *sigma0, int on_device)
 {
     if (!b || !sigma0) return GRTE_E_INVAL;
@@ -930,7 +951,8 @@ grte_status grte_batch_step(grte_batch *b, grte_batch_info *info)
     for (int i = 0; i < b->n; ++i) {
         grte_batch_info &f = info[i];
         f.pred_iters = h[8 * i + 0];
-        f.pred_converged = h[8 * i + 1];
+        f.pred_converged = h[8 * i + 1] ? 1 : 0;
+        f.pred_floor_stop = h[8 * i + 1] == 2 ? 1 : 0;
         f.newton_max_iters = h[8 * i + 2];
         f.newton_failed = h[8 * i + 3];
         f.kstar_clamped = h[8 * i + 4];

@@ -231,6 +231,7 @@ __global__ void __launch_bounds__(256) coef_kernel(Group<CoefArgs> G)
 // bank conflicts, coalesced global traffic).
 struct PredArgs {
     int N, P, maxit;
+    int accel;                         // 0 Richardson, 1 adaptive Chebyshev (see cheb_coeffs)
     double tol, one_minus_W, mu2avg;   // mu2avg = sum_p omega_p mu_p^2 (diffusion operator)
     const double *Ll, *Lu, *Lam, *LmG, *Bd, *Dd;   // cell order; diffusion off-diagonals are mu2avg * L
     const double *Gt;                  // G in position order (padded entries zero)
@@ -240,9 +241,12 @@ struct PredArgs {
     double *estar;                     // E*, pair-major, position order [p*NP + t]
     double *rho_out;                   // cell order
     int *stat;                         // [0] iterations, [1] converged, [6] barrier error
+    double *hist;                      // max|z| / max|rho| of each update (first HIST_CAP)
     unsigned long long *flags;
     unsigned long long gen0;
 };
+
+constexpr int HIST_CAP = GRTE_HIST_CAP;
 
 template <int M>
 __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, const int nblk)
@@ -314,6 +318,13 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
     double *estar_p = A.estar + (size_t)p * NP;
     unsigned long long gen = A.gen0;
     int it = 0, converged = 0, ph = 0;
+    ChebState C;
+    // previous update of this thread's rows, kept in binary32: it only steers
+    // the next update (the residual is formed from rho in full precision), and
+    // near convergence it is below tol relative to rho
+    float dch[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) dch[r] = 0.0f;
     while (true) {
         // ---- sweep: v_p = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho]
         double y[M], v[M];
@@ -323,11 +334,15 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
             if (j < N) {
                 const int t = r * NT + k;
                 const double rj = rho[t];
-                double rl = 0.0, rn = 0.0;
+                double rl = rj, rn = rj;   // boundary rows have no coupling (ll or lu is 0)
                 if (j > 0) rl = (r > 0) ? rho[t - NT] : rho[(M - 1) * NT + k - 1];
                 if (j < N - 1) rn = (r < M - 1) ? rho[t + NT] : rho[k + 1];
                 const double ll = sLl[t], lu = sLu[t];
-                const double q = -(ll + lu) * rj + ll * rl + lu * rn;
+                // L rho from neighbour differences: near convergence the
+                // products ll rho_j and ll rho_{j-1} nearly cancel, and the
+                // rounding of that form sets a floor of ~1e-14 on the relative
+                // update; the differences are formed almost exactly
+                const double q = ll * (rl - rj) + lu * (rn - rj);
                 const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
                 y[r] = rr[r] - lmg[r] * rj - mu2 * q - mu * bdj * rj;
             } else {
@@ -366,21 +381,29 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
             d[r] = gg[r] * rl[r];
         }
         tri_solve<NT, M>(A.mu2avg, sLl, sLu, Fd, d, f, sh, ph);
+        double alpha, beta;
+        cheb_coeffs(C, A.accel, A.tol, alpha, beta);
         double md = 0.0, mr = 0.0;
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             if (j0 + r < N) {
                 const int t = r * NT + k;
-                const double delta = rl[r] + f[r];
-                const double nw = rho[t] + delta;
+                const double z = rl[r] + f[r];
+                const double upd = alpha * (double)dch[r] + beta * z;
+                dch[r] = (float)upd;
+                const double nw = rho[t] + upd;
                 rho[t] = nw;
-                md = fmax(md, fabs(delta));
+                md = fmax(md, fabs(z));
                 mr = fmax(mr, fabs(nw));
             }
         }
         tile_max2<NT>(md, mr, sh);   // its barriers also publish the rho update
         ++it;
-        converged = (md <= A.tol * mr) ? 1 : 0;
+        if (bid == 0 && k == 0 && it <= HIST_CAP) A.hist[it - 1] = mr > 0.0 ? md / mr : md;
+        const float qprev = C.q1, qprev2 = C.q2;
+        const float q = (float)(mr > 0.0 ? md / mr : md);
+        cheb_record(C, q);
+        converged = pred_stop(md, mr, q, qprev, qprev2, it, A.tol);
         if (converged || it >= A.maxit) break;
     }
     if (bid == 0) {
@@ -772,6 +795,8 @@ struct grte_ctx {
     double one_minus_W = 0, mu1 = 0, mu2 = 0;
     double pred_tol = 1e-15;
     int pred_maxit = 200, newton_maxit = 100;
+    int pred_accel = GRTE_ACCEL_CHEBYSHEV;
+    double *hist = nullptr;       // convergence history of the last prediction solve
     int coop_capacity = 0;                 // co-resident prediction work-groups on the device
     int keep = 1;
     hipStream_t stream = nullptr;
@@ -1055,6 +1080,7 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     double **np[] = {&ctx->O, &ctx->O2, &ctx->ostar};
     for (double **q : np)
         if (st == GRTE_OK) st = alloc(ctx, q, (N + 1) * P);
+    if (st == GRTE_OK) st = alloc(ctx, &ctx->hist, HIST_CAP);
     double *flagmem = nullptr;
     if (st == GRTE_OK) st = alloc(ctx, &flagmem, (size_t)MAX_P * BAR_STRIDE);
     ctx->flags = (unsigned long long *)flagmem;
@@ -1122,6 +1148,13 @@ grte_status grte_set_solver(grte_ctx *ctx, double pred_tol, int pred_maxit, int 
     return GRTE_OK;
 }
 
+grte_status grte_set_acceleration(grte_ctx *ctx, int mode)
+{
+    if (!ctx || (mode != GRTE_ACCEL_RICHARDSON && mode != GRTE_ACCEL_CHEBYSHEV)) return GRTE_E_INVAL;
+    ctx->pred_accel = mode;
+    return GRTE_OK;
+}
+
 grte_status grte_set_opacity(grte_ctx *ctx, const double *sigma0, int on_device)
 {
     if (!ctx || !sigma0) return GRTE_E_INVAL;
@@ -1164,6 +1197,18 @@ grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int o
     if (s == GRTE_OK && O) s = copy_out(ctx, O, ctx->O, (N + 1) * P, on_device);
     if (s == GRTE_OK && T) s = copy_out(ctx, T, ctx->T, N, on_device);
     return s;
+}
+
+grte_status grte_get_pred_history(grte_ctx *ctx, double *out, int cap, int *n)
+{
+    if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return GRTE_E_INVAL;
+    int its = 0;
+    HIPCHK(hipMemcpyAsync(&its, ctx->stat, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int k = std::min(std::min(its, cap), HIST_CAP);
+    *n = k;
+    if (k > 0) return copy_out(ctx, out, ctx->hist, (size_t)k, 0);
+    return GRTE_OK;
 }
 
 grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device)
@@ -1223,6 +1268,8 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         // prediction: work-groups [grid, grid + P) belong to this context
         PredArgs &pa = gp.a[g];
         pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
+        pa.accel = ctx->pred_accel;
+        pa.hist = ctx->hist;
         pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
         pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
         pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
@@ -1315,7 +1362,8 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         HIPCHK(hipStreamSynchronize(stream));
         grte_step_info &f = info[g];
         f.pred_iters = h[0];
-        f.pred_converged = h[1];
+        f.pred_converged = h[1] ? 1 : 0;
+        f.pred_floor_stop = h[1] == 2 ? 1 : 0;
         f.newton_max_iters = h[2];
         f.newton_failed = h[3];
         f.kstar_clamped = h[4];
@@ -1387,6 +1435,8 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
     gp.first[1] = P;
     PredArgs &pa = gp.a[0];
     pa.N = N; pa.P = P; pa.maxit = ctx->pred_maxit; pa.tol = ctx->pred_tol; pa.one_minus_W = ctx->one_minus_W;
+        pa.accel = ctx->pred_accel;
+        pa.hist = ctx->hist;
     pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
     pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
     pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;

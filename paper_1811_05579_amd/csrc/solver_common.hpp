@@ -530,4 +530,102 @@ __device__ __forceinline__ double node_any(const double *Eall, const OT *O, cons
     return 2.0 / eps * (Eall[(size_t)(N - 1) * P + p] - br) - node_flux(Eall, O, Aw, Bc, mu, N, P, N - 1, p);
 }
 
+// -------------------------------------------------------------------------
+// prediction iteration: acceleration and stopping test
+// -------------------------------------------------------------------------
+// Adaptive Chebyshev semi-iteration on top of the preconditioned Richardson
+// update z = res + D^-1 (G res).  The iteration matrix I - (I + D^-1 G) S has a
+// real spectrum in [0, b] with b < 1 (b ~ 0.1-0.3 on optically thick slabs), so
+// the three-term Chebyshev recurrence for that interval needs no inner
+// products; it replaces the plain updates by d_k = alpha_k d_{k-1} + beta_k z_k
+// once the plain contraction ratio r = |z_k| / |z_{k-1}| (max norms relative
+// to max|rho|) has settled: two consecutive ratios within CHEB_STAB of each
+// other, r <= CHEB_RMAX (larger ratios belong to the transient of the first
+// updates from a poor start, not to the spectrum), and the update norm still
+// above CHEB_MARGIN times the tolerance (close to it the norms approach the
+// rounding level).  The interval is [0, CHEB_KAPPA r].  The solve falls back to
+// plain updates for good if, CHEB_PROG or more recurrence steps in, the update
+// norm is above what plain updates at ratio r would have reached, or at any
+// point above the norm at which the recurrence began.  The state is a function
+// of the reduced norms only, so every thread of a tile, and every work-group of
+// a cooperative solve, takes the same decisions.  Convergence is tested on
+// max|z| as for the plain iteration.
+struct ChebState {
+    int nr = 0;                 // plain updates taken
+    int on = 0;                 // recurrence running
+    int off = 0;                // fell back to plain updates
+    int j = 0;                  // recurrence steps taken
+    // relative update norms max|z| / max|rho|, newest first (binary32: they
+    // only steer the recurrence and the decisions around it)
+    float q1 = 0.0f, q2 = 0.0f, q3 = 0.0f;
+    float q0 = 0.0f, r0 = 0.0f, rj = 1.0f;   // at the start: norm, ratio; r0^j
+    float s1 = 0.0f, rp = 0.0f, de = 1.0f;   // recurrence parameters
+};
+constexpr int CHEB_K0 = 3, CHEB_PROG = 4;
+constexpr float CHEB_KAPPA = 1.2f, CHEB_STAB = 0.15f, CHEB_RMAX = 0.5f, CHEB_BMIN = 0.02f, CHEB_MARGIN = 100.0f;
+
+// coefficients (alpha, beta) of this update
+__device__ __forceinline__ void cheb_coeffs(ChebState &C, int accel, double tol, double &alpha, double &beta)
+{
+    alpha = 0.0;
+    beta = 1.0;
+    if (!accel || C.off || C.nr < CHEB_K0) return;
+    if (!C.on) {
+        if (!(C.q1 > CHEB_MARGIN * (float)tol) || !(C.q2 > 0.0f) || !(C.q3 > 0.0f)) return;
+        const float r = C.q1 / C.q2, r2 = C.q2 / C.q3;
+        if (!(r <= CHEB_RMAX) || !(fabsf(r - r2) <= CHEB_STAB * r)) return;
+        const float b = fmaxf(CHEB_BMIN, CHEB_KAPPA * r);
+        const float th = 1.0f - 0.5f * b;
+        C.de = 0.5f * b;
+        C.s1 = th / C.de;
+        C.rp = 1.0f / C.s1;
+        C.q0 = C.q1;
+        C.r0 = r;
+        C.rj = 1.0f;
+        C.j = 0;
+        C.on = 1;
+        beta = 1.0 / (double)th;
+        return;
+    }
+    const float rn = 1.0f / (2.0f * C.s1 - C.rp);
+    alpha = (double)(rn * C.rp);
+    beta = (double)(2.0f * rn / C.de);
+    C.rp = rn;
+}
+
+// record this update's relative norm q
+__device__ __forceinline__ void cheb_record(ChebState &C, float q)
+{
+    if (C.on) {
+        ++C.j;
+        C.rj *= C.r0;
+        if (q > C.q0 || (C.j >= CHEB_PROG && q > C.q0 * C.rj)) {
+            C.on = 0;
+            C.off = 1;
+        }
+    } else {
+        ++C.nr;
+    }
+    C.q3 = C.q2;
+    C.q2 = C.q1;
+    C.q1 = q;
+}
+
+// Stopping test of the prediction iteration for update norm md and iterate
+// norm mr, with the relative update norms q = md / mr of this update and
+// qprev, qprev2 of the two before: 1 if md <= tol mr; 2 (a safeguard) if
+// md <= PRED_FLOOR tol mr and the relative update norm has not decreased over
+// the last two updates -- the updates have then reached the rounding level of
+// the residual, where they only fluctuate and further updates do not improve
+// the iterate; 0 otherwise.
+constexpr double PRED_FLOOR = 16.0;
+__device__ __forceinline__ int pred_stop(double md, double mr, float q, float qprev, float qprev2, int it,
+                                         double tol)
+{
+    if (md <= tol * mr) return 1;
+    if (it > 2 && md <= PRED_FLOOR * tol * mr && q >= qprev && qprev >= qprev2) return 2;
+    return 0;
+}
+
+
 }  // namespace

@@ -86,6 +86,8 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.grte_create(ctypes.byref(ok), bad_mu.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
     assert lib.grte_gauss_legendre(7, mu.ctypes.data, om.ctypes.data) == -1
     assert lib.grte_step(None, 1.0, 1.0, None) == -1
+    assert lib.grte_set_acceleration(None, 1) == -1
+    assert lib.grte_get_pred_history(None, None, 0, None) == -1
     assert lib.grte_destroy(None) == 0
     for s in (0, -1, -2, -3, -4, -5):
         assert lib.grte_status_string(s)
@@ -112,6 +114,7 @@ def test_batch_invalid_arguments_rejected_before_device_work(lib):
     arr = (Instance * 2)(good, good)
     assert lib.grte_batch_create(2, arr, bad.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
     assert lib.grte_batch_step(None, None) == -1
+    assert lib.grte_batch_set_acceleration(None, 0) == -1
     assert lib.grte_batch_tune(None, 1, None) == -1
     assert lib.grte_batch_destroy(None) == 0
 

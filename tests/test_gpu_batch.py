@@ -4,8 +4,8 @@ path and the CPU oracle.
 Every instance of a batch computes the step of Algorithm 2 on its own data,
 so the batch must reproduce (i) the single-instance library step of the same
 instance to rounding (different tile partitions of the tridiagonal solves:
-FP64 bar 1e-12, or 1e-11 above a stiffness a c beta of 1e6) and (ii) the
-oracle to the same bar.  The batch is built from instances that cover both
+FP64 bar 1e-12, growing above a stiffness a c beta of 1e6 as fp64_bar.py
+states) and (ii) the oracle to the same bar.  The batch is built from instances that cover both
 tile kinds (one wavefront: N <= 256; one work-group: 2, 4, 8 rows per
 thread), ragged sizes, 1 to 64 pairs, both opacity laws and eps from 1 to
 1e-5, with the generic seeded states of the parity tests.
@@ -13,6 +13,7 @@ thread), ragged sizes, 1 to 64 pairs, both opacity laws and eps from 1 to
 import numpy as np
 import pytest
 
+from fp64_bar import fp64_bar
 from oracle.ap1d import Physics, ap_step
 from paper_1811_05579_amd import Grte, GrteBatch
 from paper_1811_05579_amd.workloads import Ensemble, config4, random_state
@@ -25,13 +26,8 @@ def _rel(x, y):
     return float(np.max(np.abs(x - y)) / den) if den > 0 else float(np.max(np.abs(x)))
 
 
-def _stiff(w):
-    beta = 4 * w.sigma0 * w.dt * np.asarray(w.T) ** (3 - w.m) / (w.eps ** 2 * w.Cv)
-    return float(np.max(w.a * w.c * beta))
-
-
 def _tol(w):
-    return 1e-12 if _stiff(w) <= 1e6 else 1e-11
+    return fp64_bar(w, w.T)
 
 
 # (N, nv, m, eps): wavefront tiles (N <= 256) and work-group tiles (M = 2, 4, 8)
@@ -162,4 +158,32 @@ def test_config4_full_batch_sampled_against_single_instance():
         assert _rel(T, Ts) <= 1e-11, (i, _rel(T, Ts))
         assert _rel(E, Es) <= 1e-11 and _rel(O, Os) <= 1e-11, (i, _rel(E, Es), _rel(O, Os))
         assert np.max(np.abs(T - Ts) / Ts) < 1e-6
+    b.close()
+
+
+def test_stiffest_ensemble_members_against_oracle():
+    """The six stiffest small slabs of the 4096-slab ensemble (a c beta of
+    2e9 to 7e9: cold T = 0.01 starts with sigma0 up to 100 and eps ~ 1e-5),
+    four batched steps, each against the oracle's step from the same state.
+    The bar is that of fp64_bar.py, 2e-9 to 7e-9 here (errors measured: up
+    to ~2e-11 in E and T, ~1e-9 in O)."""
+    full = config4(n=4096)
+    idx = [1276, 1053, 2171, 3750, 1545, 3779]
+    sub = Ensemble("stiffest", [full.members[i] for i in idx])
+    b = _batch(sub)
+    states = [(w.E, w.O, w.T) for w in sub.members]
+    for _ in range(4):
+        refs, bars = [], []
+        for w, (E, O, T) in zip(sub.members, states):
+            ph = Physics(a=w.a, c=w.c, Cv=w.Cv, eps=w.eps, dt=w.dt, L=w.L, m=w.m)
+            refs.append(ap_step(E, O, T, w.sigma0, w.mu, w.omega, w.bL, w.bR, ph))
+            bars.append(fp64_bar(w, T))
+        st, infos = b.step(info=True)
+        assert st == 0
+        for w, r, bar, (E, O, T) in zip(sub.members, refs, bars, b.split(*b.get_state())):
+            for name, x in (("T", T), ("E", E), ("O", O)):
+                assert _rel(x, r[name]) <= bar, (w.name, name, _rel(x, r[name]), bar)
+        states = [(r["E"], r["O"], r["T"]) for r in refs]
+        b.set_state(np.concatenate([s_[0].ravel() for s_ in states]), np.concatenate([s_[1].ravel() for s_ in states]),
+                    np.concatenate([s_[2] for s_ in states]))
     b.close()

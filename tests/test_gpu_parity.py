@@ -3,12 +3,13 @@
 Every case feeds the same seeded state to one GPU step and one oracle step
 and compares, element by element, T, E, O and the intermediate stages
 (E*, O*, U*, D, rho).  FP64 bar: max |gpu - oracle| / max |oracle| <= 1e-12
-per array where the stiffness a c beta of (4.5c) stays below 1e6 (every
-named workload; the oracle itself is accurate to ~1e-14 there), 1e-11 above.
+per array where the stiffness a c beta of (4.5c) stays below 1e6 (the oracle
+itself is accurate to ~1e-14 there); above, the bar of fp64_bar.py.
 """
 import numpy as np
 import pytest
 
+from fp64_bar import fp64_bar
 from oracle.ap1d import Physics, ap_step
 from paper_1811_05579_amd import Grte
 from paper_1811_05579_amd.workloads import config1, config2, random_state
@@ -47,21 +48,11 @@ def gpu_step(w, E, O, T, eps=None, dt=None, g=None):
     return out, info
 
 
-def stiffness(w, T, eps=None, dt=None):
-    """max a c beta of (4.5c): the ratio between the material coupling and the
-    net isotropic absorption of an optically thick cell."""
-    eps = w.eps if eps is None else eps
-    dt = w.dt if dt is None else dt
-    beta = 4 * w.sigma0 * dt * np.asarray(T) ** (3 - w.m) / (eps ** 2 * w.Cv)
-    return float(np.max(w.a * w.c * beta))
-
-
 def compare(w, E, O, T, eps=None, dt=None, tol=None, label=""):
-    # FP64 bar: 1e-12; above a stiffness a c beta of 1e6 (beyond every named
-    # workload) FP64 rounding of E* is amplified through the second difference
-    # that forms D, and the bar is 1e-11.
+    # FP64 bar: 1e-12 up to a stiffness a c beta of 1e6, growing above it
+    # (fp64_bar.py gives the rule and its reason)
     if tol is None:
-        tol = TOL if stiffness(w, T, eps, dt) <= 1e6 else 1e-11
+        tol = fp64_bar(w, T, eps, dt)
     print(f"[parity] {w.name} {label} N={w.N} P={w.P} m={w.m} eps={eps or w.eps}", flush=True)
     out, info = gpu_step(w, E, O, T, eps, dt)
     assert info["status"] == 0 and info["pred_converged"] == 1, info
