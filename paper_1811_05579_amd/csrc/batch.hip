@@ -243,15 +243,17 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     float dch[M];                             // previous update (steers the next one only)
 #pragma unroll
     for (int r = 0; r < M; ++r) dch[r] = 0.0f;
-    while (true) {
-        double acc[M], rnext[M];
+    // One sweep over the pairs from the current rho, v_p = T_p^{-1} [r_p -
+    // (Lam - G + mu^2 L + mu B) rho]: accumulates sum_p omega_p v_p into acc,
+    // or (final) writes E*_p = rho + v_p of the final iterate.
+    auto sweep = [&](double (&acc)[M], bool final_sweep) {
+        double rnext[M];
 #pragma unroll
         for (int r = 0; r < M; ++r) {
             acc[r] = 0.0;
             rnext[r] = Rt[j0 + r];              // right-hand side of pair 0
         }
         for (int p = 0; p < P; ++p) {
-            // v_p = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho]
             const double m1 = mu[p], m2 = m1 * m1, wp = om[p];
             double rcur[M];
 #pragma unroll
@@ -280,13 +282,19 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
                 }
             }
             tri_factor_solve<W, M>(m2, sLl, sLu, b, y, v, sh, ph);
-            double *ep = Et + (size_t)p * NP;
+            if (final_sweep) {
+                double *ep = Et + (size_t)p * NP;
 #pragma unroll
-            for (int r = 0; r < M; ++r) {
-                acc[r] += wp * v[r];
-                ep[j0 + r] = rho[r * W + k] + v[r];   // E*_p of this sweep
+                for (int r = 0; r < M; ++r) ep[j0 + r] = rho[r * W + k] + v[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < M; ++r) acc[r] += wp * v[r];
             }
         }
+    };
+    while (true) {
+        double acc[M];
+        sweep(acc, false);
         // res = sum_p omega_p v_p - (1 - W) rho;  rho += res + D^{-1} (G res).
         // Every operator is factored and solved in one call (one barrier); the
         // diffusion operator is factored again each iteration rather than held
@@ -321,7 +329,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
             }
         }
         tile_max2<W>(md, mr, sh);
-        tsync<W>();                               // rho update and E* visible to the tile
+        tsync<W>();                               // rho update visible to the tile
         ++it;
         const float qprev = Cs.q1, qprev2 = Cs.q2;
         const float q = (float)(mr > 0.0 ? md / mr : md);
@@ -329,6 +337,11 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         converged = pred_stop(md, mr, q, qprev, qprev2, it, A.tol);
         if (converged || it >= A.maxit) break;
     }
+    {
+        double acc[M];
+        sweep(acc, true);                         // E* of the final iterate
+    }
+    tsync<W>();                                   // E* visible to the tile
     if (k == 0) {
         st[0] = it;
         st[1] = converged;

@@ -238,7 +238,7 @@ struct PredArgs {
     const double *r, *mu, *omega, *rho0;
     double *part;                      // omega_p v_p, pair-major, position order [p*NP + t]
     double *res;                       // position order
-    double *estar;                     // E*, pair-major, position order [p*NP + t]
+    double *estar;                     // E* of the final iterate, pair-major, position order [p*NP + t]
     double *rho_out;                   // cell order
     int *stat;                         // [0] iterations, [1] converged, [6] barrier error
     double *hist;                      // max|z| / max|rho| of each update (first HIST_CAP)
@@ -247,6 +247,40 @@ struct PredArgs {
 };
 
 constexpr int HIST_CAP = GRTE_HIST_CAP;
+
+// One sweep of a pair from the iterate rho (position order, LDS):
+// v = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho] for this thread's rows.
+template <int M>
+__device__ __forceinline__ void pred_sweep(const double *rho, const double *sLl, const double *sLu,
+                                           const double (&rr)[M], const double (&lmg)[M], double mu, double mu2,
+                                           double bd0, double bdN, int N, const TriFac<NT, M> &Ft, double (&v)[M],
+                                           double *sh, int &ph)
+{
+    const int k = threadIdx.x, j0 = k * M;
+    double y[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const int j = j0 + r;
+        if (j < N) {
+            const int t = r * NT + k;
+            const double rj = rho[t];
+            double rl = rj, rn = rj;   // boundary rows have no coupling (ll or lu is 0)
+            if (j > 0) rl = (r > 0) ? rho[t - NT] : rho[(M - 1) * NT + k - 1];
+            if (j < N - 1) rn = (r < M - 1) ? rho[t + NT] : rho[k + 1];
+            const double ll = sLl[t], lu = sLu[t];
+            // L rho from neighbour differences: near convergence the products
+            // ll rho_j and ll rho_{j-1} nearly cancel, and the rounding of that
+            // form sets a floor of ~1e-14 on the relative update; the
+            // differences are formed almost exactly
+            const double q = ll * (rl - rj) + lu * (rn - rj);
+            const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
+            y[r] = rr[r] - lmg[r] * rj - mu2 * q - mu * bdj * rj;
+        } else {
+            y[r] = 0.0;
+        }
+    }
+    tri_solve<NT, M>(mu2, sLl, sLu, Ft, y, v, sh, ph);
+}
 
 template <int M>
 __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, const int nblk)
@@ -327,49 +361,32 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
     for (int r = 0; r < M; ++r) dch[r] = 0.0f;
     while (true) {
         // ---- sweep: v_p = T_p^{-1} [r_p - (Lam - G + mu^2 L + mu B) rho]
-        double y[M], v[M];
+        double v[M];
+        pred_sweep<M>(rho, sLl, sLu, rr, lmg, mu, mu2, bd0, bdN, N, Ft, v, sh, ph);
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const int j = j0 + r;
-            if (j < N) {
-                const int t = r * NT + k;
-                const double rj = rho[t];
-                double rl = rj, rn = rj;   // boundary rows have no coupling (ll or lu is 0)
-                if (j > 0) rl = (r > 0) ? rho[t - NT] : rho[(M - 1) * NT + k - 1];
-                if (j < N - 1) rn = (r < M - 1) ? rho[t + NT] : rho[k + 1];
-                const double ll = sLl[t], lu = sLu[t];
-                // L rho from neighbour differences: near convergence the
-                // products ll rho_j and ll rho_{j-1} nearly cancel, and the
-                // rounding of that form sets a floor of ~1e-14 on the relative
-                // update; the differences are formed almost exactly
-                const double q = ll * (rl - rj) + lu * (rn - rj);
-                const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
-                y[r] = rr[r] - lmg[r] * rj - mu2 * q - mu * bdj * rj;
-            } else {
-                y[r] = 0.0;
-            }
-        }
-        tri_solve<NT, M>(mu2, sLl, sLu, Ft, y, v, sh, ph);
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const int t = r * NT + k;          // padded rows give v = 0
-            part_p[t] = wp * v[r];
-            estar_p[t] = rho[t] + v[r];        // E*_p of this sweep
-        }
+        for (int r = 0; r < M; ++r) part_p[r * NT + k] = wp * v[r];   // padded rows give v = 0
         if (!grid_barrier(A.flags, ++gen, A.stat + 6, bid, nblk)) break;
-        // ---- angular sum for my positions: res = sum_p omega_p v_p - (1 - W) rho
-        for (int t = tb + k; t < te; t += NT) {
-            double s = 0.0;
-            int q = 0;
-            for (; q + 8 <= P; q += 8) {
-                double t8[8];
+        // ---- angular sum for my positions: res = sum_p omega_p v_p - (1 - W) rho.
+        // Two adjacent lanes share a position, each summing half of the pairs
+        // (half the dependent load round trips), combined in a fixed order.
+        {
+            const int h = k & 1, Ph = (P + 1) >> 1;
+            const int q0 = h ? Ph : 0, q1 = h ? P : Ph;
+            // lanes k and k^1 have the same position, so they iterate together
+            for (int t = tb + (k >> 1); t < te; t += NT / 2) {
+                double s = 0.0;
+                int q = q0;
+                for (; q + 8 <= q1; q += 8) {
+                    double t8[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) t8[u] = A.part[(size_t)(q + u) * NP + t];
+                    for (int u = 0; u < 8; ++u) t8[u] = A.part[(size_t)(q + u) * NP + t];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) s += t8[u];
+                    for (int u = 0; u < 8; ++u) s += t8[u];
+                }
+                for (; q < q1; ++q) s += A.part[(size_t)q * NP + t];
+                const double other = __shfl_xor(s, 1);
+                if (h == 0) A.res[t] = (s + other) - A.one_minus_W * rho[t];
             }
-            for (; q < P; ++q) s += A.part[(size_t)q * NP + t];
-            A.res[t] = s - A.one_minus_W * rho[t];
         }
         if (!grid_barrier(A.flags, ++gen, A.stat + 6, bid, nblk)) break;
         // ---- diffusion acceleration, identical in every work-group
@@ -405,6 +422,14 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
         cheb_record(C, q);
         converged = pred_stop(md, mr, q, qprev, qprev2, it, A.tol);
         if (converged || it >= A.maxit) break;
+    }
+    {
+        // E*_p = rho + T_p^{-1} [r_p - (T_p - G) rho] from the final iterate
+        // (no grid barrier: each work-group sweeps its own pair once more)
+        double v[M];
+        pred_sweep<M>(rho, sLl, sLu, rr, lmg, mu, mu2, bd0, bdN, N, Ft, v, sh, ph);
+#pragma unroll
+        for (int r = 0; r < M; ++r) estar_p[r * NT + k] = rho[r * NT + k] + v[r];
     }
     if (bid == 0) {
         for (int j = k; j < N; j += NT) A.rho_out[j] = rho[row_pos(j, M)];

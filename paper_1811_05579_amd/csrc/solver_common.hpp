@@ -471,7 +471,9 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *flags, unsigned
                                              int bid, int nblk)
 {
     __shared__ int s_fail;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // The work-group barrier orders every wave's prior stores before thread 0's
+    // agent-scope release, whose write-back covers the work-group's data (one
+    // write-back per work-group rather than one per wave).
     __syncthreads();
     if (threadIdx.x == 0) {
         s_fail = 0;
