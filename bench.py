@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs, scaled by a plain-copy calibration; commands and raw values in
 # the named profiles/ files).  Set to None when the kernel changes.
 TRAFFIC = {
-    "config2": (None, None),
-    "config4": (None, None),
+    "config2": (9.0504e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
+    "config4": (1.6937e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
 }
 
 

@@ -1,5 +1,14 @@
-"""Summarise a rocprofv3 kernel-trace database (run_results.db) as text:
-per-kernel call count, total and average duration (the --stats view)."""
+"""Summarise rocprofv3 output as text.
+
+  python3 profile_summary.py RUN_results.db
+      kernel-trace database: per-kernel call count, total, average, min and
+      max duration in microseconds (the --stats view).
+  python3 profile_summary.py --pmc COUNTER_CSV KERNEL_SUBSTRING
+      counter-collection CSV of one --pmc run: per-dispatch values of the
+      counter (KiB for FETCH_SIZE / WRITE_SIZE) for the kernels whose name
+      contains KERNEL_SUBSTRING: count, mean, min, max.
+"""
+import csv
 import sqlite3
 import sys
 
@@ -17,5 +26,32 @@ def summarise(db_path):
     return "\n".join(out)
 
 
+def counter_values(csv_path, kernel_substring):
+    """{counter name: [value per dispatch]} for the matching kernels (rows of
+    one dispatch are summed: some counters come per shader engine or XCD)."""
+    per = {}
+    with open(csv_path, newline="") as f:
+        for row in csv.DictReader(f):
+            if kernel_substring not in row["Kernel_Name"]:
+                continue
+            key = (row["Counter_Name"], row["Dispatch_Id"])
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (name, _), v in sorted(per.items(), key=lambda kv: int(kv[0][1])):
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def summarise_pmc(csv_path, kernel_substring):
+    lines = []
+    for name, vals in counter_values(csv_path, kernel_substring).items():
+        lines.append(f"{name} over {len(vals)} dispatches of '{kernel_substring}': mean {sum(vals) / len(vals):.1f} "
+                     f"min {min(vals):.1f} max {max(vals):.1f}")
+    return "\n".join(lines) if lines else f"no '{kernel_substring}' dispatches in {csv_path}"
+
+
 if __name__ == "__main__":
-    print(summarise(sys.argv[1]))
+    if len(sys.argv) >= 2 and sys.argv[1] == "--pmc":
+        print(summarise_pmc(sys.argv[2], sys.argv[3]))
+    else:
+        print(summarise(sys.argv[1]))
