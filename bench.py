@@ -35,8 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs, scaled by a plain-copy calibration; commands and raw values in
 # the named profiles/ files).  Set to None when the kernel changes.
 TRAFFIC = {
-    "config2": (9.0504e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
-    "config4": (1.6937e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
+    ("config2", "fp64"): (9.0504e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
+    ("config2", "fp32"): (None, None),
+    ("config4", "fp64"): (1.6937e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
+    ("config4", "fp32"): (None, None),
 }
 
 
@@ -72,11 +74,11 @@ def cpu_baseline(sample_steps=2):
                       f"initial state, {el:.1f} s, extended-precision sparse direct solves"}
 
 
-def batch_state_bytes(ens):
-    """Bytes of the binary64 state (E, O) of every slab: the algorithmic traffic
-    of one step is reading it twice (prediction and correction right-hand
-    sides) and writing it once."""
-    return 8 * sum(w.N * w.P + (w.N + 1) * w.P for w in ens.members)
+def batch_state_bytes(ens, value_bytes=8):
+    """Bytes of the stored state (E, O; binary64 or binary32) of every slab:
+    the algorithmic traffic of one step is reading it twice (prediction and
+    correction right-hand sides) and writing it once."""
+    return value_bytes * sum(w.N * w.P + (w.N + 1) * w.P for w in ens.members)
 
 
 def cpu_baseline_batch(ens, budget_s=15.0):
@@ -120,6 +122,8 @@ def main_batch(args):
     pk = ens.packed()
     b.set_opacity(pk["sigma0"])
     b.set_inflow(pk["bL"], pk["bR"])
+    storage = args.storage or "fp32"       # the ensemble is defined with binary32 intensities
+    b.set_storage(storage == "fp32")
     b.set_state(pk["E"], pk["O"], pk["T"])
     tuning = b.tune(trials=1)
     b.use_graph(True)
@@ -147,7 +151,7 @@ def main_batch(args):
     its = [i["pred_iters"] for i in infos]
     updates = ens.cell_angle_updates() * args.steps
     value = updates / (elapsed_ms / 1e3)
-    sbytes = batch_state_bytes(ens)
+    sbytes = batch_state_bytes(ens, 4 if storage == "fp32" else 8)
     launch_s = ms / cnt / 1e3
     achieved = 3 * sbytes / launch_s / 1e9
     line = {
@@ -165,8 +169,10 @@ def main_batch(args):
         "data": "synthetic (seeded ensemble of slabs, analytic cold-start/hot-inflow data)",
         "config": {
             "workload": "batched ensemble: 4096 1D slabs, N~U{64..2048}, N_v in {8,16,32,64}, "
-                        "eps=10^U[-5,0], sigma0=10^U[-1,2], sigma=sigma0*T^-3, dt=0.5/N, FP64, "
-                        "one persistent graph launch per step",
+                        "eps=10^U[-5,0], sigma0=10^U[-1,2], sigma=sigma0*T^-3, dt=0.5/N, "
+                        f"{'binary32' if storage == 'fp32' else 'binary64'} intensities, FP64 arithmetic "
+                        "and Newton, one persistent graph launch per step",
+            "storage": storage,
             "slabs": len(ens), "cell_angle_updates_per_step": ens.cell_angle_updates(),
             "parallelism": "single GPU; one tile (work-group or wavefront) per slab",
             "tuning": tuning, "pred_iters_mean": sum(its) / len(its), "pred_iters_max": max(its),
@@ -179,8 +185,8 @@ def main_batch(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": TRAFFIC["config4"][0],
-            "traffic_source": TRAFFIC["config4"][1],
+            "traffic": TRAFFIC[("config4", storage)][0],
+            "traffic_source": TRAFFIC[("config4", storage)][1],
             "bytes_per_launch": 3 * sbytes,
             "avg_launch_us": launch_s * 1e6,
         },
@@ -198,6 +204,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["config2", "config4"], default="config2")
+    ap.add_argument("--storage", choices=["fp64", "fp32"], default=None,
+                    help="intensity storage (default: fp64 for config2, fp32 for config4, "
+                         "as each workload is defined)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the single-GPU step; multi-GPU "
@@ -217,6 +226,7 @@ def main():
     # the three runs are independent problems advanced by one grouped launch of
     # each kernel (one cooperative prediction launch holds all their pairs)
     stream = torch.cuda.Stream()
+    storage = args.storage or "fp64"
     runs = []
     for eps in EPS_RUNS:
         w = config2(eps=eps)
@@ -225,6 +235,7 @@ def main():
         g.set_opacity(w.sigma0)
         g.set_inflow(w.bL, w.bR)
         g.set_state(w.E, w.O, w.T)
+        g.set_storage(storage == "fp32")
         runs.append((w, g))
     ctxs = [g for _, g in runs]
     dts = [w.dt for w, _ in runs]
@@ -274,7 +285,9 @@ def main():
         "data": "synthetic (seeded sigma0 field, analytic cold-start/hot-inflow data)",
         "config": {
             "workload": "1D slab N=4096, 64 Gauss-Legendre ordinates, sigma=sigma0*T^-3 "
-                        "(sigma0~U[0.5,2]), eps in {1,1e-2,1e-4} advanced together, dt=0.5dx, FP64",
+                        "(sigma0~U[0.5,2]), eps in {1,1e-2,1e-4} advanced together, dt=0.5dx, "
+                        f"{'binary32' if storage == 'fp32' else 'binary64'} intensities, FP64 arithmetic",
+            "storage": storage,
             "cells": w0.N, "ordinates": w0.nv, "eps_runs": list(EPS_RUNS),
             "parallelism": "single GPU; the three independent eps runs as one grouped launch per kernel",
             "pred_iters_last": [i["pred_iters"] for i in infos],
@@ -287,8 +300,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": TRAFFIC["config2"][0],
-            "traffic_source": TRAFFIC["config2"][1],
+            "traffic": TRAFFIC[("config2", storage)][0],
+            "traffic_source": TRAFFIC[("config2", storage)][1],
             "bytes_per_launch": pred_bytes,
             "avg_launch_us": pred_avg_s * 1e6,
             "share_of_step": pred_ms / step_ms if step_ms > 0 else None,

@@ -361,6 +361,15 @@ grte_status grte_batch_sizes(const grte_batch *b, long long *cells, long long *e
                              long long *o_len, long long *pairs);
 grte_status grte_batch_set_stream(grte_batch *b, void *hip_stream);
 grte_status grte_batch_set_solver(grte_batch *b, double pred_tol, int pred_maxit, int newton_maxit);
+/* Binary32 storage of every instance's intensity state, as grte_set_storage
+ * for one slab: with fp32 = 1 the stored E is fl32(E - a c T^4) (T of the same
+ * state) and O is fl32(O); every step computes in binary64 from the stored
+ * values and rounds its result once.  The current state is converted;
+ * grte_batch_set_state / grte_batch_get_state keep exchanging binary64 packed
+ * arrays (get_state returns the values the binary32 storage represents).  A
+ * captured step graph is rebuilt.  GRTE_E_INVAL for fp32 other than 0 or 1,
+ * GRTE_E_NOMEM if the binary32 buffers cannot be allocated. */
+grte_status grte_batch_set_storage(grte_batch *b, int fp32);
 /* Acceleration of the prediction iteration of every instance (GRTE_ACCEL_*,
  * as grte_set_acceleration; default GRTE_ACCEL_CHEBYSHEV).  Takes effect at
  * the next step (a captured step graph is rebuilt). */

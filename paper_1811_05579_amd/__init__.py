@@ -359,6 +359,10 @@ class GrteBatch:
         check("grte_batch_set_solver", self._lib.grte_batch_set_solver(
             self._h, float(pred_tol), int(pred_maxit), int(newton_maxit)))
 
+    def set_storage(self, fp32):
+        """Binary32 intensity storage (True) or binary64 (False) for every instance."""
+        check("grte_batch_set_storage", self._lib.grte_batch_set_storage(self._h, 1 if fp32 else 0))
+
     def set_acceleration(self, mode):
         """'chebyshev' (default) or 'richardson' for every instance's prediction."""
         modes = {"richardson": 0, "chebyshev": 1}

@@ -109,6 +109,7 @@ _SIGS = {
     "grte_batch_set_stream": (c_int, [c_void_p, c_void_p]),
     "grte_batch_set_solver": (c_int, [c_void_p, c_double, c_int, c_int]),
     "grte_batch_set_acceleration": (c_int, [c_void_p, c_int]),
+    "grte_batch_set_storage": (c_int, [c_void_p, c_int]),
     "grte_batch_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
     "grte_batch_set_inflow": (c_int, [c_void_p, c_void_p, c_void_p]),
     "grte_batch_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int]),

@@ -64,6 +64,11 @@ struct BatchArgs {
     int *queue;                        // [0] work-group queue head, [1] wavefront queue head
     const double *E, *O, *T, *sigma0;
     double *E2, *O2, *T2;
+    // binary32 storage (f32 != 0): E^n = a c (T^n)^4 + E32, O^n = O32 in;
+    // E32o = E^{n+1} - a c (T^{n+1})^4, O32o = O^{n+1} out (E, O, E2, O2 unused)
+    const float *E32, *O32;
+    float *E32o, *O32o;
+    int f32;                    // (the kernel variant is chosen by the host)
     const double *mu, *omega, *bL, *bR;
     double *cells, *pairs;
     int *istat;                        // 8 per instance
@@ -168,9 +173,31 @@ __device__ __forceinline__ double node_pc(const double *ec, const OT *O, const d
     return 2.0 / eps * (ec[N - 1] - br) - inner(N - 1);
 }
 
+// The state E^n, O^n of one instance: binary64 arrays, or the binary32
+// storage E32 = E^n - a c (T^n)^4, O32 = O^n (f32 != 0).
+template <bool F32>
+struct BState {
+    static constexpr bool f32 = F32;
+    const double *E, *O, *Tn;
+    const float *E32, *O32;
+    double ac;
+    int P;
+    __device__ __forceinline__ double e(int j, int idx) const
+    {
+        if constexpr (!F32) return E[idx];
+        const double t = Tn[j];
+        return ac * (t * t) * (t * t) + (double)E32[idx];
+    }
+    __device__ __forceinline__ double o(size_t idx) const
+    {
+        if constexpr (F32) return (double)O32[idx];
+        else return O[idx];
+    }
+};
+
 // right-hand sides of the per-pair systems into Rt (pair-major, cell order)
-template <int W, int M>
-__device__ void b_rhs(const BInst &I, const double *C, int N1, const double *E, const double *O,
+template <int W, int M, bool F32>
+__device__ void b_rhs(const BInst &I, const double *C, int N1, const BState<F32> &S,
                       const double *mu, const double *bL, const double *bR, double *Rt)
 {
     constexpr int NP = W * M;
@@ -179,9 +206,9 @@ __device__ void b_rhs(const BInst &I, const double *C, int N1, const double *E, 
     for (int idx = k; idx < N * P; idx += W) {
         const int j = idx / P, p = idx - (idx / P) * P;
         const double h = C[C_H * N1 + j];
-        const double On_r = (j <= N - 2) ? O[(size_t)(j + 1) * P + p] : 0.0;
-        const double On_l = (j >= 1) ? O[(size_t)j * P + p] : 0.0;
-        double rv = C[C_KEPS * N1 + j] * E[idx] + C[C_SRC * N1 + j]
+        const double On_r = (j <= N - 2) ? S.o((size_t)(j + 1) * P + p) : 0.0;
+        const double On_l = (j >= 1) ? S.o((size_t)j * P + p) : 0.0;
+        double rv = C[C_KEPS * N1 + j] * S.e(j, idx) + C[C_SRC * N1 + j]
                   - h * mu[p] * (C[C_AWR * N1 + j] * On_r - C[C_AWL * N1 + j] * On_l);
         if (j == 0) rv += 2.0 * h * mu[p] * bL[p] / I.eps;
         if (j == N - 1) rv += 2.0 * h * mu[p] * bR[p] / I.eps;
@@ -189,7 +216,7 @@ __device__ void b_rhs(const BInst &I, const double *C, int N1, const double *E, 
     }
 }
 
-template <int W, int M>
+template <int W, int M, bool F32>
 __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *sm)
 {
     constexpr int NP = W * M;
@@ -198,9 +225,17 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     const int k = tile_lane<W>();
     const int j0 = k * M;
     const double eps = I.eps;
-    const double *E = A.E + I.oE, *O = A.O + I.oO, *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
+    const double *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
+    BState<F32> S;
+    S.P = I.P;
+    S.ac = I.a * I.c;
+    S.Tn = Tn;
+    S.E = F32 ? nullptr : A.E + I.oE;
+    S.O = F32 ? nullptr : A.O + I.oO;
+    S.E32 = F32 ? A.E32 + I.oE : nullptr;
+    S.O32 = F32 ? A.O32 + I.oO : nullptr;
     const double *mu = A.mu + I.oP, *om = A.omega + I.oP, *bL = A.bL + I.oP, *bR = A.bR + I.oP;
-    double *E2 = A.E2 + I.oE, *O2 = A.O2 + I.oO, *T2 = A.T2 + I.oT;
+    double *T2 = A.T2 + I.oT;
     double *C = A.cells + I.oC;
     // Per-pair global arrays are pair-major in cell order: thread k's rows
     // j0 .. j0+M-1 are contiguous, so its loads and stores are wide and the
@@ -214,11 +249,11 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     for (int j = k; j < N; j += W) {
         b_cell(I, 0, Tn, Tn, sg, j, C, N1);
         double rn = 0.0;
-        for (int p = 0; p < P; ++p) rn += om[p] * E[(size_t)j * P + p];
+        for (int p = 0; p < P; ++p) rn += om[p] * S.e(j, j * P + p);
         C[C_RHON * N1 + j] = rn;
     }
     tsync<W>();
-    b_rhs<W, M>(I, C, N1, E, O, mu, bL, bR, Rt);
+    b_rhs<W, M, F32>(I, C, N1, S, mu, bL, bR, Rt);
     for (int j = k; j < NP; j += W) {
         const int t = bpos(j, W, M);
         const bool in = j < N;
@@ -356,8 +391,14 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
             const double m1 = mu[p];
             const double ej = ep[j];
             // O* at nodes j and j+1 from the node relation and the inflow relations (4.7)
-            const double ol = node_pc(ep, O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
-            const double orr = node_pc(ep, O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
+            double ol, orr;
+            if constexpr (F32) {
+                ol = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
+                orr = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
+            } else {
+                ol = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
+                orr = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
+            }
             rs += om[p] * ej;
             D += om[p] * m1 * (orr - ol);
         }
@@ -422,7 +463,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     const double *Tnew = C + C_TNEW * N1;
     for (int j = k; j < N; j += W) b_cell(I, 1, Tnew, Tn, sg, j, C, N1);
     tsync<W>();
-    b_rhs<W, M>(I, C, N1, E, O, mu, bL, bR, Rt);
+    b_rhs<W, M, F32>(I, C, N1, S, mu, bL, bR, Rt);
     for (int j = k; j < NP; j += W) {
         const int t = bpos(j, W, M);
         const bool in = j < N;
@@ -460,18 +501,56 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     // ---------------- projection (4.14): E^{n+1} and O^{n+1} (node relation with K^{n+1})
     // into the cell-major state; a thread takes cells, its lanes read along cells
     const double *Aw = C + C_AW * N1, *Bc = C + C_BC * N1;
-    for (int j = k; j < N; j += W) {
-        for (int p = 0; p < P; ++p) {
-            const double *ep = Et + (size_t)p * NP;
-            E2[(size_t)j * P + p] = ep[j];
-            O2[(size_t)j * P + p] = node_pc(ep, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
-            if (j == N - 1)
-                O2[(size_t)N * P + p] = node_pc(ep, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+    if constexpr (F32) {
+        float *E32o = A.E32o + I.oE, *O32o = A.O32o + I.oO;
+        for (int j = k; j < N; j += W) {
+            const double t1 = T2[j];
+            const double base = S.ac * (t1 * t1) * (t1 * t1);
+            for (int p = 0; p < P; ++p) {
+                const double *ep = Et + (size_t)p * NP;
+                E32o[(size_t)j * P + p] = (float)(ep[j] - base);
+                O32o[(size_t)j * P + p] = (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
+                if (j == N - 1)
+                    O32o[(size_t)N * P + p] =
+                        (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+            }
+        }
+    } else {
+        double *E2 = A.E2 + I.oE, *O2 = A.O2 + I.oO;
+        for (int j = k; j < N; j += W) {
+            for (int p = 0; p < P; ++p) {
+                const double *ep = Et + (size_t)p * NP;
+                E2[(size_t)j * P + p] = ep[j];
+                O2[(size_t)j * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
+                if (j == N - 1)
+                    O2[(size_t)N * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+            }
         }
     }
     tsync<W>();
 }
 
+// binary64 state <-> binary32 storage of every instance (one block per
+// instance): E32 = E - a c T^4, O32 = O (to32), or back
+__global__ void __launch_bounds__(256) batch_convert(const BInst *inst, const double *T, double *E, double *O,
+                                                    float *E32, float *O32, int to32)
+{
+    const BInst I = inst[blockIdx.x];
+    const long long ne = (long long)I.N * I.P, no = (long long)(I.N + 1) * I.P;
+    const double ac = I.a * I.c;
+    for (long long t = threadIdx.x; t < ne; t += blockDim.x) {
+        const double tj = T[I.oT + t / I.P];
+        const double base = ac * (tj * tj) * (tj * tj);
+        if (to32) E32[I.oE + t] = (float)(E[I.oE + t] - base);
+        else E[I.oE + t] = base + (double)E32[I.oE + t];
+    }
+    for (long long t = threadIdx.x; t < no; t += blockDim.x) {
+        if (to32) O32[I.oO + t] = (float)O[I.oO + t];
+        else O[I.oO + t] = (double)O32[I.oO + t];
+    }
+}
+
+template <bool F32>
 __global__ void __launch_bounds__(BNT) batch_kernel(BatchArgs A)
 {
     extern __shared__ double smem[];
@@ -485,9 +564,9 @@ __global__ void __launch_bounds__(BNT) batch_kernel(BatchArgs A)
         if (q >= A.n_wg) break;
         const int i = A.order[q];
         switch (A.inst[i].M) {
-        case 2: run_instance<BNT, 2>(A, i, smem); break;
-        case 4: run_instance<BNT, 4>(A, i, smem); break;
-        default: run_instance<BNT, 8>(A, i, smem); break;
+        case 2: run_instance<BNT, 2, F32>(A, i, smem); break;
+        case 4: run_instance<BNT, 4, F32>(A, i, smem); break;
+        default: run_instance<BNT, 8, F32>(A, i, smem); break;
         }
     }
     // ---- wavefront tiles: each wave takes instances on its own
@@ -498,8 +577,8 @@ __global__ void __launch_bounds__(BNT) batch_kernel(BatchArgs A)
         q = __builtin_amdgcn_readfirstlane(q);
         if (q >= A.n_wave) break;
         const int i = A.order[A.n_wg + q];
-        if (A.inst[i].M == 2) run_instance<WAVE, 2>(A, i, wsm);
-        else run_instance<WAVE, 4>(A, i, wsm);
+        if (A.inst[i].M == 2) run_instance<WAVE, 2, F32>(A, i, wsm);
+        else run_instance<WAVE, 4, F32>(A, i, wsm);
     }
 }
 
@@ -546,6 +625,10 @@ struct grte_batch {
     int *d_order = nullptr, *d_queue = nullptr, *d_istat = nullptr;
     double *E[2] = {nullptr, nullptr}, *O[2] = {nullptr, nullptr}, *T[2] = {nullptr, nullptr};
     int cur = 0;                               // state buffers in use: E[cur], O[cur], T[cur]
+    // binary32 storage (f32 != 0): the state is E32[cur], O32[cur] with T[cur];
+    // E[cur], O[cur] then only stage set_state / get_state
+    float *E32[2] = {nullptr, nullptr}, *O32[2] = {nullptr, nullptr};
+    int f32 = 0;
     double *sigma0 = nullptr, *mu = nullptr, *omega = nullptr, *bL = nullptr, *bR = nullptr;
     double *cells = nullptr, *pairs = nullptr;
     // graphs, one per buffer parity; rebuilt when the launch changes
@@ -633,6 +716,9 @@ BatchArgs make_args(const grte_batch *b, int src)
     A.sigma0 = b->sigma0; A.mu = b->mu; A.omega = b->omega; A.bL = b->bL; A.bR = b->bR;
     A.cells = b->cells; A.pairs = b->pairs; A.istat = b->d_istat;
     A.tol = b->tol; A.maxit = b->maxit; A.newton_maxit = b->newton_maxit; A.accel = b->accel;
+    A.f32 = b->f32;
+    A.E32 = b->E32[src]; A.O32 = b->O32[src];
+    A.E32o = b->E32[1 - src]; A.O32o = b->O32[1 - src];
     return A;
 }
 
@@ -645,7 +731,10 @@ grte_status enqueue_step(grte_batch *b, hipStream_t s, int src)
     hipLaunchKernelGGL(batch_reset, dim3((unsigned)((std::max(n8, 2) + 255) / 256)), dim3(256), 0, s,
                        b->d_queue, b->d_istat, n8);
     BCHK(hipGetLastError());
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)b->grid), dim3(BNT), BATCH_LDS, s, A);
+    if (b->f32)
+        hipLaunchKernelGGL(batch_kernel<true>, dim3((unsigned)b->grid), dim3(BNT), BATCH_LDS, s, A);
+    else
+        hipLaunchKernelGGL(batch_kernel<false>, dim3((unsigned)b->grid), dim3(BNT), BATCH_LDS, s, A);
     BCHK(hipGetLastError());
     return GRTE_OK;
 }
@@ -799,18 +888,22 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
     if (st == GRTE_OK) st = balloc(b, &b->cells, oC);
     if (st == GRTE_OK) st = balloc(b, &b->pairs, oR);
     if (st != GRTE_OK) { grte_batch_destroy(b); return st; }
-    if (hipFuncSetAttribute((const void *)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    if (hipFuncSetAttribute((const void *)batch_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)BATCH_LDS) != hipSuccess ||
+        hipFuncSetAttribute((const void *)batch_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)BATCH_LDS) != hipSuccess) {
         grte_batch_destroy(b);
         return GRTE_E_HIP;
     }
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel, BNT, BATCH_LDS) !=
-            hipSuccess || nb < 1) {
+    int nb = 0, nb32 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel<false>, BNT, BATCH_LDS) !=
+            hipSuccess || nb < 1 ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb32, (const void *)batch_kernel<true>, BNT, BATCH_LDS) !=
+            hipSuccess || nb32 < 1) {
         grte_batch_destroy(b);
         return GRTE_E_HIP;
     }
-    b->grid = nb * b->ncu;
+    b->grid = std::min(nb, nb32) * b->ncu;
     if (hipMemcpy(b->mu, mu, oP * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->omega, omega, oP * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         grte_batch_destroy(b);
@@ -889,6 +982,39 @@ grte_status grte_batch_set_inflow(grte_batch *b, const double *b_left, const dou
     return copy_dev(b, b->bR, b_right, b->tot_pairs * sizeof(double), hipMemcpyHostToDevice);
 }
 
+namespace {
+grte_status convert_state(grte_batch *b, int to32)
+{
+    hipLaunchKernelGGL(batch_convert, dim3((unsigned)b->n), dim3(256), 0, b->stream, b->d_inst, b->T[b->cur],
+                       b->E[b->cur], b->O[b->cur], b->E32[b->cur], b->O32[b->cur], to32);
+    BCHK(hipGetLastError());
+    return GRTE_OK;
+}
+}  // namespace
+
+grte_status grte_batch_set_storage(grte_batch *b, int fp32)
+{
+    if (!b || (fp32 != 0 && fp32 != 1)) return GRTE_E_INVAL;
+    if (fp32 == b->f32) return GRTE_OK;
+    if (fp32 && !b->E32[0]) {
+        for (int q = 0; q < 2; ++q) {
+            void *pe = nullptr, *po = nullptr;
+            if (hipMalloc(&pe, std::max<long long>(b->tot_E, 1) * sizeof(float)) != hipSuccess) return GRTE_E_NOMEM;
+            b->allocs.push_back(pe);
+            if (hipMalloc(&po, std::max<long long>(b->tot_O, 1) * sizeof(float)) != hipSuccess) return GRTE_E_NOMEM;
+            b->allocs.push_back(po);
+            b->E32[q] = (float *)pe;
+            b->O32[q] = (float *)po;
+        }
+    }
+    grte_status s = convert_state(b, fp32);
+    if (s != GRTE_OK) return s;
+    BCHK(hipStreamSynchronize(b->stream));
+    b->f32 = fp32;
+    drop_graphs(b);
+    return GRTE_OK;
+}
+
 grte_status grte_batch_set_state(grte_batch *b, const double *E, const double *O, const double *T, int on_device)
 {
     if (!b || !E || !O || !T) return GRTE_E_INVAL;
@@ -899,6 +1025,7 @@ grte_status grte_batch_set_state(grte_batch *b, const double *E, const double *O
     grte_status s = copy_dev(b, b->E[b->cur], E, b->tot_E * sizeof(double), k);
     if (s == GRTE_OK) s = copy_dev(b, b->O[b->cur], O, b->tot_O * sizeof(double), k);
     if (s == GRTE_OK) s = copy_dev(b, b->T[b->cur], T, b->tot_cells * sizeof(double), k);
+    if (s == GRTE_OK && b->f32) s = convert_state(b, 1);
     return s;
 }
 
@@ -907,7 +1034,8 @@ grte_status grte_batch_get_state(grte_batch *b, double *E, double *O, double *T,
     if (!b) return GRTE_E_INVAL;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     grte_status s = GRTE_OK;
-    if (E) s = copy_dev(b, E, b->E[b->cur], b->tot_E * sizeof(double), k);
+    if (b->f32 && (E || O)) s = convert_state(b, 0);   // binary64 values of the stored state
+    if (s == GRTE_OK && E) s = copy_dev(b, E, b->E[b->cur], b->tot_E * sizeof(double), k);
     if (s == GRTE_OK && O) s = copy_dev(b, O, b->O[b->cur], b->tot_O * sizeof(double), k);
     if (s == GRTE_OK && T) s = copy_dev(b, T, b->T[b->cur], b->tot_cells * sizeof(double), k);
     return s;
@@ -989,8 +1117,8 @@ grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best)
     if (st != GRTE_OK) { b->use_graph = save_graph; return st; }
     update_cost(b, h);
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel, BNT, BATCH_LDS) != hipSuccess)
-        nb = 1;
+    const void *kfn = b->f32 ? (const void *)batch_kernel<true> : (const void *)batch_kernel<false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kfn, BNT, BATCH_LDS) != hipSuccess) nb = 1;
     const int waves[] = {0, 128, 256};
     std::vector<int> grids;
     for (int f = 1; f <= std::max(1, nb); f *= 2) grids.push_back(f * b->ncu);

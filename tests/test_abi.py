@@ -115,6 +115,7 @@ def test_batch_invalid_arguments_rejected_before_device_work(lib):
     assert lib.grte_batch_create(2, arr, bad.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
     assert lib.grte_batch_step(None, None) == -1
     assert lib.grte_batch_set_acceleration(None, 0) == -1
+    assert lib.grte_batch_set_storage(None, 1) == -1
     assert lib.grte_batch_tune(None, 1, None) == -1
     assert lib.grte_batch_destroy(None) == 0
 
