@@ -129,7 +129,11 @@ grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int o
  * replaced by (E^{n+1}, O^{n+1}, T^{n+1}).  With info == NULL the call only
  * enqueues work; otherwise it synchronises and fills *info.  Returns
  * GRTE_E_NOCONV (state still advanced) if info != NULL and a solve hit its
- * cap. */
+ * cap.  The prediction's iteration starts from rho^n = sum_p omega_p E^n_p,
+ * or, when the current state is the one the previous grte_step /
+ * grte_step_group of ctx produced, from that step's converged rho* (fewer
+ * iterations; the converged result is the same to the solver tolerance).
+ * grte_set_state, grte_set_storage and grte_reference_step return to rho^n. */
 grte_status grte_step(grte_ctx *ctx, double dt, double eps, grte_step_info *info);
 
 /* One AP step of n independent contexts with one launch of each kernel
@@ -382,7 +386,10 @@ grte_status grte_batch_set_state(grte_batch *b, const double *E, const double *O
                                  const double *T, int on_device);
 grte_status grte_batch_get_state(grte_batch *b, double *E, double *O, double *T, int on_device);
 /* One step of every instance.  info == NULL: enqueue only; otherwise
- * synchronise and fill info[n]; GRTE_E_NOCONV if any instance hit a cap. */
+ * synchronise and fill info[n]; GRTE_E_NOCONV if any instance hit a cap.
+ * As for grte_step, each prediction starts from the instance's rho* of the
+ * previous step when the current state is the one that step produced
+ * (grte_batch_set_state and grte_batch_set_storage return to rho^n). */
 grte_status grte_batch_step(grte_batch *b, grte_batch_info *info);
 /* Autotuner: times `trials` steps for each candidate (wavefront threshold
  * 0/128/256 x grid of 1, 2, ... work-groups per compute unit) from the

@@ -75,6 +75,8 @@ struct BatchArgs {
     double tol;
     int maxit, newton_maxit;
     int accel;                  // prediction acceleration (GRTE_ACCEL_*)
+    double *rprev;              // per cell: the last prediction's rho* (written every step)
+    int warm;                   // start the prediction from rprev instead of rho^n
 };
 
 // make the tile's LDS and global writes visible to the whole tile
@@ -254,10 +256,11 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     }
     tsync<W>();
     b_rhs<W, M, F32>(I, C, N1, S, mu, bL, bR, Rt);
+    double *rp = A.rprev + I.oT;
     for (int j = k; j < NP; j += W) {
         const int t = bpos(j, W, M);
         const bool in = j < N;
-        rho[t] = in ? C[C_RHON * N1 + j] : 0.0;
+        rho[t] = in ? (A.warm ? rp[j] : C[C_RHON * N1 + j]) : 0.0;
         sLl[t] = in ? C[C_LL * N1 + j] : 0.0;
         sLu[t] = in ? C[C_LU * N1 + j] : 0.0;
     }
@@ -376,6 +379,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         double acc[M];
         sweep(acc, true);                         // E* of the final iterate
     }
+    for (int j = k; j < N; j += W) rp[j] = rho[bpos(j, W, M)];   // next step's starting iterate
     tsync<W>();                                   // E* visible to the tile
     if (k == 0) {
         st[0] = it;
@@ -631,6 +635,8 @@ struct grte_batch {
     int f32 = 0;
     double *sigma0 = nullptr, *mu = nullptr, *omega = nullptr, *bL = nullptr, *bR = nullptr;
     double *cells = nullptr, *pairs = nullptr;
+    double *rprev = nullptr;                   // per cell: the last prediction's rho*
+    int warm = 0;                              // rprev belongs to the step that produced the state
     // graphs, one per buffer parity; rebuilt when the launch changes
     int use_graph = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -717,6 +723,8 @@ BatchArgs make_args(const grte_batch *b, int src)
     A.cells = b->cells; A.pairs = b->pairs; A.istat = b->d_istat;
     A.tol = b->tol; A.maxit = b->maxit; A.newton_maxit = b->newton_maxit; A.accel = b->accel;
     A.f32 = b->f32;
+    A.rprev = b->rprev;
+    A.warm = b->warm;
     A.E32 = b->E32[src]; A.O32 = b->O32[src];
     A.E32o = b->E32[1 - src]; A.O32o = b->O32[1 - src];
     return A;
@@ -887,6 +895,7 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
     if (st == GRTE_OK) st = balloc(b, &b->bR, oP);
     if (st == GRTE_OK) st = balloc(b, &b->cells, oC);
     if (st == GRTE_OK) st = balloc(b, &b->pairs, oR);
+    if (st == GRTE_OK) st = balloc(b, &b->rprev, oT);
     if (st != GRTE_OK) { grte_batch_destroy(b); return st; }
     if (hipFuncSetAttribute((const void *)batch_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)BATCH_LDS) != hipSuccess ||
@@ -1011,6 +1020,7 @@ grte_status grte_batch_set_storage(grte_batch *b, int fp32)
     if (s != GRTE_OK) return s;
     BCHK(hipStreamSynchronize(b->stream));
     b->f32 = fp32;
+    b->warm = 0;
     drop_graphs(b);
     return GRTE_OK;
 }
@@ -1022,6 +1032,10 @@ grte_status grte_batch_set_state(grte_batch *b, const double *E, const double *O
         for (long long j = 0; j < b->tot_cells; ++j)
             if (!(T[j] >= 0) || !std::isfinite(T[j])) return GRTE_E_INVAL;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (b->warm) {           // the next prediction starts from rho^n again
+        b->warm = 0;
+        drop_graphs(b);
+    }
     grte_status s = copy_dev(b, b->E[b->cur], E, b->tot_E * sizeof(double), k);
     if (s == GRTE_OK) s = copy_dev(b, b->O[b->cur], O, b->tot_O * sizeof(double), k);
     if (s == GRTE_OK) s = copy_dev(b, b->T[b->cur], T, b->tot_cells * sizeof(double), k);
@@ -1085,6 +1099,10 @@ grte_status grte_batch_step(grte_batch *b, grte_batch_info *info)
     if (st != GRTE_OK) return st;
     if (k >= 0) BCHK(hipEventRecord(b->ev[2 * k + 1], b->stream));
     b->cur = 1 - b->cur;
+    if (!b->warm) {          // rprev now belongs to the current state; the launch changes
+        b->warm = 1;
+        drop_graphs(b);
+    }
     if (!info) return GRTE_OK;
     std::vector<int> h;
     if ((st = read_stats(b, h)) != GRTE_OK) return st;

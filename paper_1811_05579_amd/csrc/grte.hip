@@ -238,7 +238,7 @@ struct PredArgs {
     const double *r, *mu, *omega, *rho0;
     double *part;                      // omega_p v_p, pair-major, position order [p*NP + t]
     double *res;                       // position order
-    double *estar;                     // E* of the final iterate, pair-major, position order [p*NP + t]
+    double *estar;                     // E* of the final iterate, cell-major [j*P + p]
     double *rho_out;                   // cell order
     int *stat;                         // [0] iterations, [1] converged, [6] barrier error
     double *hist;                      // max|z| / max|rho| of each update (first HIST_CAP)
@@ -349,7 +349,6 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
     const int tb = bid * chunk;
     const int te = min(NP, tb + chunk);
     double *part_p = A.part + (size_t)p * NP;
-    double *estar_p = A.estar + (size_t)p * NP;
     unsigned long long gen = A.gen0;
     int it = 0, converged = 0, ph = 0;
     ChebState C;
@@ -429,7 +428,8 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
         double v[M];
         pred_sweep<M>(rho, sLl, sLu, rr, lmg, mu, mu2, bd0, bdN, N, Ft, v, sh, ph);
 #pragma unroll
-        for (int r = 0; r < M; ++r) estar_p[r * NT + k] = rho[r * NT + k] + v[r];
+        for (int r = 0; r < M; ++r)
+            if (j0 + r < N) A.estar[(size_t)(j0 + r) * P + p] = rho[r * NT + k] + v[r];
     }
     if (bid == 0) {
         for (int j = k; j < N; j += NT) A.rho_out[j] = rho[row_pos(j, M)];
@@ -455,7 +455,6 @@ __global__ void __launch_bounds__(NT) pred_kernel(Group<PredArgs> G)
 struct NewtonArgs {
     int N, P, m, maxit, keep, cpb, M;
     double a, c, cv, eps, dt, dx;
-    const double *estar_t;   // E*, pair-major, position order (prediction output)
     const double *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
     double *Ecm;             // E* copied to cell-major order (read by the node relations)
     double *Tnew, *ustar, *Dv, *ostar, *rstar;
@@ -486,17 +485,6 @@ __device__ __forceinline__ bool newton_quartic(double T0, double Tn, double q4, 
     return false;
 }
 
-// E* from the position-ordered prediction output into the cell-major layout
-__global__ void __launch_bounds__(256) gather_estar_kernel(Group<NewtonArgs> G)
-{
-    const NewtonArgs A = G.a[blockIdx.y];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int N = A.N, P = A.P;
-    if (t >= N * P) return;
-    const int j = t / P, p = t - (t / P) * P;
-    A.Ecm[t] = A.estar_t[(size_t)p * NT * A.M + row_pos(j, A.M)];
-}
-
 template <bool GUESS>
 __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t *sW, const float *sN)
 {
@@ -523,71 +511,92 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t 
         }
     }
     __syncthreads();
-    if (t >= cpb || c0 + t >= N) return;
-    const int j = c0 + t;
-    double rho = 0.0, D = 0.0;
-    for (int q = 0; q < P; ++q) {
-        rho += s_w[t * P + q];
-        D += s_f[t * P + q];
-    }
-    D /= A.dx;
-    const double ac = A.a * A.c;
-    const double Tn = A.Tn[j];
-    const double Un = Tn * Tn * Tn * Tn;
-    const double beta = A.beta[j];
-    const double us = (Un + beta * rho) / (1.0 + ac * beta);
-    A.ustar[j] = us;
-    A.Dv[j] = D;
-    double Ks = 1.0;
-    if (A.m == 3) {
-        if (us < 0.0) {
-            Ks = 0.0;
-            atomicAdd(&A.stat[4], 1);
-        } else {
-            Ks = pow(us, 0.75);
+    // per-cell counters, summed over the wavefront before one atomic each:
+    // [0] Newton its, [1] K* clamped, [2] no root, [3] guess accepted,
+    // [4] guess not used, [5] started from the guess, [6] Newton failed
+    int its = 0, cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (t < cpb && c0 + t < N) {
+        const int j = c0 + t;
+        double rho = 0.0, D = 0.0;
+        for (int q = 0; q < P; ++q) {
+            rho += s_w[t * P + q];
+            D += s_f[t * P + q];
         }
-    }
-    // (4.13) times c sigma0 dt^2:
-    //   a c sigma0 dt T^4 + Cv (eps^2 K* + c sigma0 dt)(T - T^n) - sigma0 dt (rho^n - c dt D) = 0
-    const double s0 = A.sigma0[j];
-    const double lin = A.cv * (A.eps * A.eps * Ks + A.c * s0 * A.dt);
-    const double q4 = ac * s0 * A.dt;
-    const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
-    A.rstar[j] = rho;
-    double T = Tn;
-    int its = 0;
-    if (!(s0 == 0.0 && Ks == 0.0)) {
-        if (Tn + rhs / lin < 0.0) atomicAdd(&A.stat[5], 1);   // no root >= 0
-        bool ok = false, done = false;
-        if (GUESS && s0 > 0.0 && Tn > 0.0) {
-            // learned starting value; judged by the normalised residual of (4.13)
-            float f[MLP_IN];
-            mlp_features(rho, Tn, s0, A.m, A.eps, A.dt, f);
-            const float y = mlp_eval(sW, sN, f);
-            const double Tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
-            if (isfinite(Tg) && Tg > 0.0) {
-                // normalised residuals of the guess and of T^n
-                const double T2 = Tg * Tg;
-                const double rg = fabs(q4 * T2 * T2 + lin * (Tg - Tn) - rhs) / lin;
-                const double Tn2 = Tn * Tn;
-                const double rn = fabs(q4 * Tn2 * Tn2 - rhs) / lin;
-                if (rg <= A.gtol * fmax(fabs(Tn + rhs / lin), 1e-300)) {
-                    T = Tg;
-                    ok = done = true;
-                    atomicAdd(&A.stat[7], 1);
-                } else if (rg < rn) {
-                    ok = done = newton_quartic(Tg, Tn, q4, lin, rhs, A.maxit, T, its);
-                    if (done) atomicAdd(&A.stat[10], 1);
-                }
+        D /= A.dx;
+        const double ac = A.a * A.c;
+        const double Tn = A.Tn[j];
+        const double Un = Tn * Tn * Tn * Tn;
+        const double beta = A.beta[j];
+        const double us = (Un + beta * rho) / (1.0 + ac * beta);
+        A.ustar[j] = us;
+        A.Dv[j] = D;
+        double Ks = 1.0;
+        if (A.m == 3) {
+            if (us < 0.0) {
+                Ks = 0.0;
+                cnt[1] = 1;
+            } else {
+                Ks = pow(us, 0.75);
             }
-            if (!done) atomicAdd(&A.stat[8], 1);
         }
-        if (!done) ok = newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its);   // plain: from T^n
-        if (!ok) atomicAdd(&A.stat[3], 1);
+        // (4.13) times c sigma0 dt^2:
+        //   a c sigma0 dt T^4 + Cv (eps^2 K* + c sigma0 dt)(T - T^n) - sigma0 dt (rho^n - c dt D) = 0
+        const double s0 = A.sigma0[j];
+        const double lin = A.cv * (A.eps * A.eps * Ks + A.c * s0 * A.dt);
+        const double q4 = ac * s0 * A.dt;
+        const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
+        A.rstar[j] = rho;
+        double T = Tn;
+        if (!(s0 == 0.0 && Ks == 0.0)) {
+            if (Tn + rhs / lin < 0.0) cnt[2] = 1;   // no root >= 0
+            bool ok = false, done = false;
+            if (GUESS && s0 > 0.0 && Tn > 0.0) {
+                // learned starting value; judged by the normalised residual of (4.13)
+                float f[MLP_IN];
+                mlp_features(rho, Tn, s0, A.m, A.eps, A.dt, f);
+                const float y = mlp_eval(sW, sN, f);
+                const double Tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
+                if (isfinite(Tg) && Tg > 0.0) {
+                    // normalised residuals of the guess and of T^n
+                    const double T2 = Tg * Tg;
+                    const double rg = fabs(q4 * T2 * T2 + lin * (Tg - Tn) - rhs) / lin;
+                    const double Tn2 = Tn * Tn;
+                    const double rn = fabs(q4 * Tn2 * Tn2 - rhs) / lin;
+                    if (rg <= A.gtol * fmax(fabs(Tn + rhs / lin), 1e-300)) {
+                        T = Tg;
+                        ok = done = true;
+                        cnt[3] = 1;
+                    } else if (rg < rn) {
+                        ok = done = newton_quartic(Tg, Tn, q4, lin, rhs, A.maxit, T, its);
+                        if (done) cnt[5] = 1;
+                    }
+                }
+                if (!done) cnt[4] = 1;
+            }
+            if (!done) ok = newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its);   // plain: from T^n
+            if (!ok) cnt[6] = 1;
+        }
+        A.Tnew[j] = T;
     }
-    A.Tnew[j] = T;
-    atomicMax(&A.stat[2], its);
-    atomicAdd(&A.stat[9], its);
+    // step counters: the same words are the target of every cell of the
+    // context, so each wavefront sums its cells first
+    int mx = its;
+    cnt[0] = its;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, __shfl_xor(mx, o, 64));
+#pragma unroll
+        for (int q = 0; q < 7; ++q) cnt[q] += __shfl_xor(cnt[q], o, 64);
+    }
+    if ((t & 63) == 0) {
+        // stat: [2] max its, [3] failed, [4] K* clamped, [5] no root, [7] accepted,
+        // [8] not used, [9] sum of its, [10] started from the guess
+        const int slot[7] = {9, 4, 5, 7, 8, 10, 3};
+        if (mx > 0) atomicMax(&A.stat[2], mx);
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            if (cnt[q]) atomicAdd(&A.stat[slot[q]], cnt[q]);
+    }
 }
 
 // GUESS: some context of the launch carries a learned guess (its weights are
@@ -830,7 +839,7 @@ struct grte_ctx {
     double *E2 = nullptr, *O2 = nullptr, *T2 = nullptr;    // next state
     double *sigma0, *mu, *omega, *bL, *bR;
     double *Ll, *Lu, *Lam, *LmG, *Gt, *Bd, *Aw, *Bc, *beta, *Dl, *Dd, *Du, *rho_n;
-    double *r, *part, *res, *estar_t, *estar, *rho;
+    double *r, *part, *res, *estar, *rho;
     double *ustar, *Dv, *ostar, *rho1, *rstar;
     // binary32 storage of the intensity state (f32 != 0): E as E - a c T^4, and O;
     // the binary64 E, O buffers then serve as scratch
@@ -842,6 +851,11 @@ struct grte_ctx {
     double guess_tol = 1e-10;
     double last_dt = 0, last_eps = 0;      // of the last step (training-pair log)
     int stepped = 0;
+    // warm start: rho (the last prediction's converged rho*, of the step that
+    // produced the current state) is the next prediction's starting iterate;
+    // cleared whenever the state is set or replaced otherwise
+    int warm = 0;
+    double *rho_b = nullptr;      // the prediction's output buffer (swapped with rho)
     unsigned long long *flags = nullptr;   // grid-barrier flags of the prediction kernel
     unsigned long long bar_gen = 0;        // generations used so far (strictly increasing)
     int cpb = 1;                           // cells per work-group of the per-cell kernels
@@ -1083,12 +1097,12 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     grte_status st = GRTE_OK;
     double **cells[] = {&ctx->T, &ctx->T2, &ctx->sigma0, &ctx->Ll, &ctx->Lu, &ctx->Lam,
                         &ctx->LmG, &ctx->Bd, &ctx->beta, &ctx->Dl, &ctx->Dd, &ctx->Du,
-                        &ctx->rho_n, &ctx->rho, &ctx->ustar, &ctx->Dv, &ctx->rho1, &ctx->rstar};
+                        &ctx->rho_n, &ctx->rho, &ctx->rho_b, &ctx->ustar, &ctx->Dv, &ctx->rho1, &ctx->rstar};
     const size_t NP = (size_t)NT * ctx->M;    // padded rows of the solvers
     double **padded[] = {&ctx->Gt, &ctx->res};
     for (double **q : padded)
         if (st == GRTE_OK) st = alloc(ctx, q, NP);
-    double **padded_pairs[] = {&ctx->part, &ctx->estar_t, &ctx->r};
+    double **padded_pairs[] = {&ctx->part, &ctx->r};
     for (double **q : padded_pairs)
         if (st == GRTE_OK) st = alloc(ctx, q, NP * P);
     for (double **q : cells)
@@ -1205,6 +1219,7 @@ grte_status grte_set_state(grte_ctx *ctx, const double *E, const double *O, cons
             if (!(T[j] >= 0) || !std::isfinite(T[j])) return GRTE_E_INVAL;
     const size_t N = ctx->N, P = ctx->P;
     ctx->stepped = 0;                      // the pair log refers to a step from this state on
+    ctx->warm = 0;
     grte_status s = copy_in(ctx, ctx->E, E, N * P, on_device);
     if (s == GRTE_OK) s = copy_in(ctx, ctx->O, O, (N + 1) * P, on_device);
     if (s == GRTE_OK) s = copy_in(ctx, ctx->T, T, N, on_device);
@@ -1268,7 +1283,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     Group<CorrArgs> gr{};
     Group<ProjArgs> gj{};
     gc.n = gp.n = gn.n = gr.n = gj.n = n;
-    unsigned ncb_max = 1, np_max = 1, maxP = 1;
+    unsigned ncb_max = 1, maxP = 1;
     int grid = 0;
     for (int g = 0; g < n; ++g) {
         grte_ctx *ctx = ctxs[g];
@@ -1276,7 +1291,6 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         const int N = ctx->N, P = ctx->P;
         const double dx = ctx->L / N;
         ncb_max = std::max(ncb_max, (unsigned)((N + ctx->cpb - 1) / ctx->cpb));
-        np_max = std::max(np_max, (unsigned)(((size_t)N * P + 255) / 256));
         maxP = std::max(maxP, (unsigned)P);
         // coefficients of the prediction (K from T^n); also clears the step counters
         CoefArgs &ca = gc.a[g];
@@ -1297,8 +1311,8 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         pa.hist = ctx->hist;
         pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
         pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
-        pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
-        pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->estar_t; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
+        pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->warm ? ctx->rho : ctx->rho_n;
+        pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->estar; pa.rho_out = ctx->rho_b; pa.stat = ctx->stat;
         pa.flags = ctx->flags;
         pa.gen0 = ctx->bar_gen;
         ctx->bar_gen += 2ull * (unsigned long long)ctx->pred_maxit + 4ull;   // never reused
@@ -1307,7 +1321,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         // correction substep 1
         NewtonArgs &na = gn.a[g];
         na.N = N; na.P = P; na.m = ctx->m; na.maxit = ctx->newton_maxit; na.keep = ctx->keep; na.cpb = ctx->cpb;
-        na.M = ctx->M; na.estar_t = ctx->estar_t; na.Ecm = ctx->estar;
+        na.M = ctx->M; na.Ecm = ctx->estar;
         na.a = ctx->a; na.c = ctx->c; na.cv = ctx->cv; na.eps = eps; na.dt = dt; na.dx = dx;
         na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
         na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;
@@ -1348,8 +1362,6 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     }
     if (st != GRTE_OK) return st;
     if ((st = prof_end(c0, ev_pred)) != GRTE_OK) return st;
-    hipLaunchKernelGGL(gather_estar_kernel, dim3(np_max, n), dim3(256), 0, stream, gn);
-    HIPCHK(hipGetLastError());
     bool any_guess = false;
     for (int g = 0; g < n; ++g) any_guess = any_guess || gn.a[g].gw != nullptr;
     if (any_guess) hipLaunchKernelGGL(newton_kernel<true>, dim3(ncb_max, n), dim3(256), 0, stream, gn);
@@ -1378,6 +1390,8 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         std::swap(ctx->T, ctx->T2);
         std::swap(ctx->E32, ctx->E32b);
         std::swap(ctx->O32, ctx->O32b);
+        std::swap(ctx->rho, ctx->rho_b);   // rho*: the next step's starting iterate
+        ctx->warm = 1;
     }
     if (!info) return GRTE_OK;
     grte_status worst = GRTE_OK;
@@ -1433,6 +1447,7 @@ grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, cons
 grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol, int maxit,
                                 grte_reference_info *info)
 {
+    if (ctx) ctx->warm = 0;   // the Picard loop reuses the rho* buffer
     if (!ctx || !(dt > 0) || !(eps > 0) || !std::isfinite(dt) || !std::isfinite(eps) || !(tol > 0) || maxit < 1)
         return GRTE_E_INVAL;
     if (ctx->f32) return GRTE_E_UNSUPPORTED;
@@ -1465,7 +1480,7 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
     pa.Ll = ctx->Ll; pa.Lu = ctx->Lu; pa.Lam = ctx->Lam; pa.LmG = ctx->LmG; pa.Gt = ctx->Gt;
     pa.Bd = ctx->Bd; pa.Dd = ctx->Dd; pa.mu2avg = ctx->mu2;
     pa.r = ctx->r; pa.mu = ctx->mu; pa.omega = ctx->omega; pa.rho0 = ctx->rho_n;
-    pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->estar_t; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
+    pa.part = ctx->part; pa.res = ctx->res; pa.estar = ctx->E2; pa.rho_out = ctx->rho; pa.stat = ctx->stat;
     pa.flags = ctx->flags;
     const unsigned ncb = (unsigned)((N + ctx->cpb - 1) / ctx->cpb);
     const double ac = ctx->a * ctx->c;
@@ -1506,14 +1521,8 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
     ctx->T2 = Tk;
     ctx->rstar = Tk1;
     if (!sync_err) {
-        // E^{n+1} = E* and O^{n+1} = O* of the last prediction (K from the last T^(k))
-        Group<NewtonArgs> gn{};
-        gn.n = 1;
-        NewtonArgs &na = gn.a[0];
-        na.N = N; na.P = P; na.M = M; na.estar_t = ctx->estar_t; na.Ecm = ctx->E2;
-        hipLaunchKernelGGL(gather_estar_kernel, dim3((unsigned)(((size_t)N * P + 255) / 256), 1), dim3(256), 0,
-                           stream, gn);
-        HIPCHK(hipGetLastError());
+        // E^{n+1} = E* (the last prediction wrote it into E2) and O^{n+1} = O*
+        // of the last prediction (K from the last T^(k))
         hipLaunchKernelGGL(node_all_kernel, dim3((unsigned)(((size_t)(N + 1) * P + 255) / 256)), dim3(256), 0,
                            stream, N, P, eps, ctx->E2, ctx->O, ctx->Aw, ctx->Bc, ctx->mu, ctx->bL, ctx->bR, ctx->O2);
         HIPCHK(hipGetLastError());
@@ -1521,6 +1530,7 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
         std::swap(ctx->O, ctx->O2);
         std::swap(ctx->T, ctx->T2);
         ctx->stepped = 0;
+        ctx->warm = 0;
         HIPCHK(hipStreamSynchronize(stream));
     }
     if (info) {
@@ -1553,6 +1563,7 @@ grte_status grte_set_storage(grte_ctx *ctx, int fp32)
     if (s != GRTE_OK) return s;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->f32 = fp32;
+    ctx->warm = 0;
     return GRTE_OK;
 }
 

@@ -42,7 +42,9 @@ def test_modes_agree_and_chebyshev_saves_updates(eps):
     its_a = its_b = 0
     worst = 0.0
     for _ in range(30):
-        b.set_state(*a.get_state())
+        state = a.get_state()
+        a.set_state(*state)      # both start from rho^n (no warm start), so the
+        b.set_state(*state)      # update counts compare the two iterations alone
         ia = a.step(w.dt, w.eps, info=True)
         ib = b.step(w.dt, w.eps, info=True)
         assert c.step(w.dt, w.eps, info=True)["status"] == 0
@@ -147,3 +149,28 @@ def test_developed_state_against_oracle(eps):
         for x, y in zip(g.get_state(), (ref["E"], ref["O"], ref["T"])):
             assert _rel(x, y) <= 1e-12, (mode, _rel(x, y))
         g.close()
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_warm_start(eps):
+    """A context stepping its own state starts each prediction from the
+    previous step's rho*; one reset to its state before every step starts from
+    rho^n.  Same results to the one-step bar, fewer updates warm."""
+    w = config2(eps=eps)
+    warm, cold = _ctx(w, "chebyshev"), _ctx(w, "chebyshev")
+    its_w = its_c = 0
+    for k in range(30):
+        state = warm.get_state()
+        cold.set_state(*state)
+        iw = warm.step(w.dt, w.eps, info=True)
+        ic = cold.step(w.dt, w.eps, info=True)
+        assert iw["status"] == 0 and ic["status"] == 0
+        if k >= 3:
+            its_w += iw["pred_iters"]
+            its_c += ic["pred_iters"]
+        for x, y in zip(warm.get_state(), cold.get_state()):
+            assert _rel(x, y) <= 1e-12
+    print(f"eps={eps:g}: prediction updates, steps 4-30: cold {its_c} warm {its_w}")
+    assert its_w < its_c
+    warm.close()
+    cold.close()
