@@ -511,92 +511,71 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t 
         }
     }
     __syncthreads();
-    // per-cell counters, summed over the wavefront before one atomic each:
-    // [0] Newton its, [1] K* clamped, [2] no root, [3] guess accepted,
-    // [4] guess not used, [5] started from the guess, [6] Newton failed
-    int its = 0, cnt[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (t < cpb && c0 + t < N) {
-        const int j = c0 + t;
-        double rho = 0.0, D = 0.0;
-        for (int q = 0; q < P; ++q) {
-            rho += s_w[t * P + q];
-            D += s_f[t * P + q];
+    if (t >= cpb || c0 + t >= N) return;
+    const int j = c0 + t;
+    double rho = 0.0, D = 0.0;
+    for (int q = 0; q < P; ++q) {
+        rho += s_w[t * P + q];
+        D += s_f[t * P + q];
+    }
+    D /= A.dx;
+    const double ac = A.a * A.c;
+    const double Tn = A.Tn[j];
+    const double Un = Tn * Tn * Tn * Tn;
+    const double beta = A.beta[j];
+    const double us = (Un + beta * rho) / (1.0 + ac * beta);
+    A.ustar[j] = us;
+    A.Dv[j] = D;
+    double Ks = 1.0;
+    if (A.m == 3) {
+        if (us < 0.0) {
+            Ks = 0.0;
+            atomicAdd(&A.stat[4], 1);
+        } else {
+            Ks = pow(us, 0.75);
         }
-        D /= A.dx;
-        const double ac = A.a * A.c;
-        const double Tn = A.Tn[j];
-        const double Un = Tn * Tn * Tn * Tn;
-        const double beta = A.beta[j];
-        const double us = (Un + beta * rho) / (1.0 + ac * beta);
-        A.ustar[j] = us;
-        A.Dv[j] = D;
-        double Ks = 1.0;
-        if (A.m == 3) {
-            if (us < 0.0) {
-                Ks = 0.0;
-                cnt[1] = 1;
-            } else {
-                Ks = pow(us, 0.75);
-            }
-        }
-        // (4.13) times c sigma0 dt^2:
-        //   a c sigma0 dt T^4 + Cv (eps^2 K* + c sigma0 dt)(T - T^n) - sigma0 dt (rho^n - c dt D) = 0
-        const double s0 = A.sigma0[j];
-        const double lin = A.cv * (A.eps * A.eps * Ks + A.c * s0 * A.dt);
-        const double q4 = ac * s0 * A.dt;
-        const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
-        A.rstar[j] = rho;
-        double T = Tn;
-        if (!(s0 == 0.0 && Ks == 0.0)) {
-            if (Tn + rhs / lin < 0.0) cnt[2] = 1;   // no root >= 0
-            bool ok = false, done = false;
-            if (GUESS && s0 > 0.0 && Tn > 0.0) {
-                // learned starting value; judged by the normalised residual of (4.13)
-                float f[MLP_IN];
-                mlp_features(rho, Tn, s0, A.m, A.eps, A.dt, f);
-                const float y = mlp_eval(sW, sN, f);
-                const double Tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
-                if (isfinite(Tg) && Tg > 0.0) {
-                    // normalised residuals of the guess and of T^n
-                    const double T2 = Tg * Tg;
-                    const double rg = fabs(q4 * T2 * T2 + lin * (Tg - Tn) - rhs) / lin;
-                    const double Tn2 = Tn * Tn;
-                    const double rn = fabs(q4 * Tn2 * Tn2 - rhs) / lin;
-                    if (rg <= A.gtol * fmax(fabs(Tn + rhs / lin), 1e-300)) {
-                        T = Tg;
-                        ok = done = true;
-                        cnt[3] = 1;
-                    } else if (rg < rn) {
-                        ok = done = newton_quartic(Tg, Tn, q4, lin, rhs, A.maxit, T, its);
-                        if (done) cnt[5] = 1;
-                    }
+    }
+    // (4.13) times c sigma0 dt^2:
+    //   a c sigma0 dt T^4 + Cv (eps^2 K* + c sigma0 dt)(T - T^n) - sigma0 dt (rho^n - c dt D) = 0
+    const double s0 = A.sigma0[j];
+    const double lin = A.cv * (A.eps * A.eps * Ks + A.c * s0 * A.dt);
+    const double q4 = ac * s0 * A.dt;
+    const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
+    A.rstar[j] = rho;
+    double T = Tn;
+    int its = 0;
+    if (!(s0 == 0.0 && Ks == 0.0)) {
+        if (Tn + rhs / lin < 0.0) atomicAdd(&A.stat[5], 1);   // no root >= 0
+        bool ok = false, done = false;
+        if (GUESS && s0 > 0.0 && Tn > 0.0) {
+            // learned starting value; judged by the normalised residual of (4.13)
+            float f[MLP_IN];
+            mlp_features(rho, Tn, s0, A.m, A.eps, A.dt, f);
+            const float y = mlp_eval(sW, sN, f);
+            const double Tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
+            if (isfinite(Tg) && Tg > 0.0) {
+                // normalised residuals of the guess and of T^n
+                const double T2 = Tg * Tg;
+                const double rg = fabs(q4 * T2 * T2 + lin * (Tg - Tn) - rhs) / lin;
+                const double Tn2 = Tn * Tn;
+                const double rn = fabs(q4 * Tn2 * Tn2 - rhs) / lin;
+                if (rg <= A.gtol * fmax(fabs(Tn + rhs / lin), 1e-300)) {
+                    T = Tg;
+                    ok = done = true;
+                    atomicAdd(&A.stat[7], 1);
+                } else if (rg < rn) {
+                    ok = done = newton_quartic(Tg, Tn, q4, lin, rhs, A.maxit, T, its);
+                    if (done) atomicAdd(&A.stat[10], 1);
                 }
-                if (!done) cnt[4] = 1;
             }
-            if (!done) ok = newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its);   // plain: from T^n
-            if (!ok) cnt[6] = 1;
+            if (!done) atomicAdd(&A.stat[8], 1);
         }
-        A.Tnew[j] = T;
+        if (!done) ok = newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its);   // plain: from T^n
+        if (!ok) atomicAdd(&A.stat[3], 1);
     }
-    // step counters: the same words are the target of every cell of the
-    // context, so each wavefront sums its cells first
-    int mx = its;
-    cnt[0] = its;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        mx = max(mx, __shfl_xor(mx, o, 64));
-#pragma unroll
-        for (int q = 0; q < 7; ++q) cnt[q] += __shfl_xor(cnt[q], o, 64);
-    }
-    if ((t & 63) == 0) {
-        // stat: [2] max its, [3] failed, [4] K* clamped, [5] no root, [7] accepted,
-        // [8] not used, [9] sum of its, [10] started from the guess
-        const int slot[7] = {9, 4, 5, 7, 8, 10, 3};
-        if (mx > 0) atomicMax(&A.stat[2], mx);
-#pragma unroll
-        for (int q = 0; q < 7; ++q)
-            if (cnt[q]) atomicAdd(&A.stat[slot[q]], cnt[q]);
-    }
+    A.Tnew[j] = T;
+    atomicMax(&A.stat[2], its);
+    atomicAdd(&A.stat[9], its);
 }
 
 // GUESS: some context of the launch carries a learned guess (its weights are
