@@ -35,10 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE runs, scaled by a plain-copy calibration; commands and raw values in
 # the named profiles/ files).  Set to None when the kernel changes.
 TRAFFIC = {
-    ("config2", "fp64"): (9.0504e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
+    ("config2", "fp64"): (9.2663e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
     ("config2", "fp32"): (None, None),
-    ("config4", "fp64"): (1.6937e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
-    ("config4", "fp32"): (None, None),
+    ("config4", "fp64"): (None, None),
+    ("config4", "fp32"): (1.4142e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
 }
 
 
