@@ -8,7 +8,8 @@
 // single-instance path (Algorithm 2 and Section 5 of Tang, Wang & Zhang):
 // the per-pair tridiagonal operators T_p = Lam + mu_p^2 L + mu_p B with U*
 // eliminated through (4.5c), the angular coupling of the prediction solved by
-// Richardson iteration with diffusion-synthetic acceleration in residual form,
+// the DSA-preconditioned residual-form iteration with adaptive Chebyshev
+// updates (warm-started from the previous step's rho*),
 // Newton on (4.13)/(5.5), the per-pair correction (4.11) and the projection
 // (4.14).  One tile owns all parity pairs of its instance, so the angular sum
 // is accumulated in registers and no grid-wide synchronisation exists.
@@ -113,7 +114,7 @@ __device__ __forceinline__ void b_node(const BInst &I, const double *Tk, const d
 }
 
 // per-cell coefficients of cell j; mode 0: prediction (K from T^n, with the
-// U* elimination of (4.5c)), mode 1: correction (K from T^{n+1})
+// U* elimination of (4.5c)), 1: correction (K from T^{n+1})
 __device__ void b_cell(const BInst &I, int mode, const double *Tk, const double *Tn, const double *sg,
                        int j, double *C, int N1)
 {
@@ -267,7 +268,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     tsync<W>();
     const double bd0 = C[C_BD * N1 + 0], bdN = C[C_BD * N1 + N - 1];
 
-    // ---------------- prediction: Richardson iteration with diffusion acceleration
+    // ---------------- prediction: DSA-preconditioned iteration (plain or Chebyshev updates)
     double lam[M], lmg[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {

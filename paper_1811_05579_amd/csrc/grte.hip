@@ -24,12 +24,15 @@
 //     S rho = s ,  S x = (1 - W) x + sum_p omega_p T_p^{-1} [(Lam - G) x + mu_p^2 L x + mu_p B x],
 // where Lam - G = K eps^2 + sigma0 c dt/(1 + ac beta) is formed directly, so
 // the small isotropic coefficient of optically thick cells carries no
-// cancellation.  It is solved by Richardson iteration preconditioned with
-// the diffusion operator D = (Lam - G) + <mu^2> L + <mu> B (a consistent
-// diffusion-synthetic acceleration):
+// cancellation.  The update is preconditioned with the diffusion operator
+// D = (Lam - G) + <mu^2> L + <mu> B (a consistent diffusion-synthetic
+// acceleration):
 //     res = s - S rho^k = sum_p omega_p T_p^{-1}[r_p - (T_p - G) rho^k] - (1 - W) rho^k,
-//     rho^{k+1} = rho^k + res + D^{-1}(G res),
-// and E*_p = rho^k + T_p^{-1}[r_p - (T_p - G) rho^k] from the last sweep.
+//     z^k = res + D^{-1}(G res),
+// applied as rho^{k+1} = rho^k + z^k (plain) or through an adaptive Chebyshev
+// recurrence (solver_common.hpp), starting from the previous step's rho* when
+// the state is the one that step produced; E*_p = rho + T_p^{-1}[r_p - (T_p - G) rho]
+// from a final sweep of the converged iterate.
 // One cooperative kernel runs the whole iteration: one work-group per
 // parity pair solves its tridiagonal system in registers/LDS, a grid barrier
 // separates the angular reduction, and every work-group then performs the
@@ -47,9 +50,9 @@
 //
 // Tridiagonal systems are solved inside one work-group by a partitioned
 // method: each thread owns M consecutive rows, eliminates its interior rows
-// (Thomas with three right-hand sides), the chunk-boundary rows form a
-// tridiagonal system of size NT solved by parallel cyclic reduction in LDS,
-// and each thread back-substitutes.  All systems are M-matrices (diagonally
+// (Thomas), the chunk-boundary rows form a tridiagonal system of size NT that
+// every wavefront solves redundantly (published once in LDS; parallel cyclic
+// reduction across the lanes), and each thread back-substitutes.  All systems are M-matrices (diagonally
 // dominant), so no pivoting is needed.  All reductions have a fixed order:
 // results are bitwise reproducible.
 
@@ -223,7 +226,7 @@ __global__ void __launch_bounds__(256) coef_kernel(Group<CoefArgs> G)
 }
 
 // -------------------------------------------------------------------------
-// prediction: cooperative Richardson iteration with diffusion acceleration
+// prediction: cooperative DSA-preconditioned iteration (plain or Chebyshev updates)
 // -------------------------------------------------------------------------
 // Row j of a system is owned by thread k = j / M as its row r = j % M.  Every
 // per-row array the iteration touches is kept in "position" order
