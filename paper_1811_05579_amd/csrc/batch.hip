@@ -433,12 +433,18 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         if (!(s0 == 0.0 && Ks == 0.0)) {
             if (t + rhs / lin < 0.0) ++n_neg;
             bool ok = false;
+            // Newton from T^n, iterates clamped to the upper bound of the root
+            // (the smaller single-term root of q4 T^4 + lin T = rhs + lin T^n)
+            const double Cq = rhs + lin * t;
+            const double cap = (Cq > 0.0 && q4 > 0.0)
+                                   ? fmin(sqrt(sqrt(Cq / q4)), Cq / lin) * (1.0 + 0x1p-50) : INFINITY;
             for (its = 0; its < A.newton_maxit;) {
                 const double T2v = T * T;
                 const double g = q4 * T2v * T2v + lin * (T - t) - rhs;
                 const double dg = 4.0 * q4 * T2v * T + lin;
-                const double step = g / dg;
-                T -= step;
+                const double Tp = T;
+                T = fmin(T - g / dg, cap);
+                const double step = Tp - T;
                 ++its;
                 if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(t))) { ok = true; break; }
             }
