@@ -215,7 +215,11 @@ enum { GRTE_ACCEL_RICHARDSON = 0, GRTE_ACCEL_CHEBYSHEV = 1 };
 grte_status grte_set_acceleration(grte_ctx *ctx, int mode);
 
 /* Stage timing with HIP events recorded on the context's stream around each
- * timed stage of every grte_step (off by default; enabling resets the log). */
+ * timed stage of a step (grte_step, or grte_step_group through its first
+ * context).  on = 0: off (default); on = k >= 1: every k-th step from now is
+ * timed (each event record costs the stream a few microseconds, so sampling
+ * keeps the timed run close to an untimed one).  Setting resets the log;
+ * GRTE_E_INVAL for on < 0. */
 enum {
     GRTE_TIMING_STEP = 0,     /* the whole step, first to last kernel          */
     GRTE_TIMING_PREDICT = 1,  /* the prediction solve kernel (4.5)/(5.2)       */

@@ -144,7 +144,9 @@ class Grte:
         return out
 
     def set_profiling(self, on=True):
-        check("grte_set_profiling", self._lib.grte_set_profiling(self._h, int(bool(on))))
+        """True or 1: time every step; k >= 2: every k-th step; False or 0: off."""
+        k = int(on) if not isinstance(on, bool) else int(on)
+        check("grte_set_profiling", self._lib.grte_set_profiling(self._h, k))
 
     def read_timing(self):
         """{stage: (total_ms, launches)} from the library's HIP events."""

@@ -861,7 +861,8 @@ struct grte_ctx {
     size_t pred_lds = 0;
     int *stat = nullptr;
     // optional stage timing: event pairs recorded on the context stream
-    int profiling = 0;
+    int profiling = 0;            // 0 off, k: time every k-th step
+    long long prof_count = 0;     // steps since profiling was set
     std::vector<hipEvent_t> ev_pool;      // created on demand, reused
     std::vector<int> ev_stage;            // stage index of each recorded pair
     size_t ev_used = 0;                   // pairs recorded since the last read
@@ -1348,11 +1349,14 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     if (grid > c0->coop_capacity) return GRTE_E_UNSUPPORTED;
 
     int ev_step = -1, ev_pred = -1;
-    grte_status st = prof_begin(c0, GRTE_TIMING_STEP, &ev_step);
+    // profiling samples every c0->profiling-th step (event records cost the
+    // stream a few microseconds each)
+    const bool sample = c0->profiling > 0 && (c0->prof_count++ % c0->profiling) == 0;
+    grte_status st = sample ? prof_begin(c0, GRTE_TIMING_STEP, &ev_step) : GRTE_OK;
     if (st != GRTE_OK) return st;
     hipLaunchKernelGGL(coef_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gc);
     HIPCHK(hipGetLastError());
-    if ((st = prof_begin(c0, GRTE_TIMING_PREDICT, &ev_pred)) != GRTE_OK) return st;
+    if (sample && (st = prof_begin(c0, GRTE_TIMING_PREDICT, &ev_pred)) != GRTE_OK) return st;
     switch (M) {
     case 2: st = launch_pred<2>(stream, gp, grid); break;
     case 4: st = launch_pred<4>(stream, gp, grid); break;
@@ -1592,8 +1596,9 @@ grte_status grte_log_pairs(grte_ctx *ctx, float *dev_rows, long long cap_rows, l
 
 grte_status grte_set_profiling(grte_ctx *ctx, int on)
 {
-    if (!ctx) return GRTE_E_INVAL;
-    ctx->profiling = on ? 1 : 0;
+    if (!ctx || on < 0) return GRTE_E_INVAL;
+    ctx->profiling = on;
+    ctx->prof_count = 0;
     ctx->ev_used = 0;
     return GRTE_OK;
 }

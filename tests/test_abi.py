@@ -87,6 +87,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.grte_gauss_legendre(7, mu.ctypes.data, om.ctypes.data) == -1
     assert lib.grte_step(None, 1.0, 1.0, None) == -1
     assert lib.grte_set_acceleration(None, 1) == -1
+    assert lib.grte_set_profiling(None, 1) == -1
     assert lib.grte_get_pred_history(None, None, 0, None) == -1
     assert lib.grte_destroy(None) == 0
     for s in (0, -1, -2, -3, -4, -5):

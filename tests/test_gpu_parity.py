@@ -215,3 +215,23 @@ def test_group_step_equals_separate_steps():
                 assert np.array_equal(x, y), s
     for g in sep + grp:
         g.close()
+
+
+def test_profiling_samples_every_kth_step():
+    """grte_set_profiling(ctx, k) times every k-th step (k = 1: every step)."""
+    w = config1()
+    g = _ctx(w)
+    g.set_state(w.E, w.O, w.T)
+    g.set_profiling(3)
+    for _ in range(9):
+        g.step(w.dt, w.eps)
+    t = g.read_timing()
+    assert t["predict"][1] == 3 and t["step"][1] == 3
+    assert 0 < t["predict"][0] <= t["step"][0]
+    g.set_profiling(True)
+    for _ in range(4):
+        g.step(w.dt, w.eps)
+    assert g.read_timing()["step"][1] == 4
+    with pytest.raises(Exception):
+        g.set_profiling(-1)
+    g.close()
