@@ -39,7 +39,7 @@ TRAFFIC = {
     ("config2", "fp64"): (9.2663e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
     ("config2", "fp32"): (None, None),
     ("config4", "fp64"): (None, None),
-    ("config4", "fp32"): (None, None),
+    ("config4", "fp32"): (1.4162e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
 }
 
 

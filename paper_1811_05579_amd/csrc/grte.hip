@@ -456,10 +456,10 @@ __global__ void __launch_bounds__(NT) pred_kernel(Group<PredArgs> G)
 // correction substep 1: moments, D, K*, scalar Newton
 // -------------------------------------------------------------------------
 struct NewtonArgs {
-    int N, P, m, maxit, keep, cpb, M;
+    int N, P, m, maxit, keep, cpb;
     double a, c, cv, eps, dt, dx;
     const double *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
-    double *Ecm;             // E* copied to cell-major order (read by the node relations)
+    double *Ecm;             // E* in cell-major order, as the prediction writes it
     double *Tnew, *ustar, *Dv, *ostar, *rstar;
     const float *O32;        // binary32 storage of O^n (f32 != 0)
     int f32;
@@ -1321,7 +1321,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         // correction substep 1
         NewtonArgs &na = gn.a[g];
         na.N = N; na.P = P; na.m = ctx->m; na.maxit = ctx->newton_maxit; na.keep = ctx->keep; na.cpb = ctx->cpb;
-        na.M = ctx->M; na.Ecm = ctx->estar;
+        na.Ecm = ctx->estar;
         na.a = ctx->a; na.c = ctx->c; na.cv = ctx->cv; na.eps = eps; na.dt = dt; na.dx = dx;
         na.O = ctx->O; na.Aw = ctx->Aw; na.Bc = ctx->Bc; na.beta = ctx->beta;
         na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;

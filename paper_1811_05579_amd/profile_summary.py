@@ -7,6 +7,10 @@
       counter-collection CSV of one --pmc run: per-dispatch values of the
       counter (KiB for FETCH_SIZE / WRITE_SIZE) for the kernels whose name
       contains KERNEL_SUBSTRING: count, mean, min, max.
+  python3 profile_summary.py --window RUN_results.db KERNEL_SUBSTRING FIRST COUNT
+      durations of COUNT launches of the matching kernel, in launch order,
+      starting at launch FIRST (negative: counted from the last launch), e.g.
+      the timed steps of a run that ends with one extra step: -51 50.
 """
 import csv
 import sqlite3
@@ -24,6 +28,18 @@ def summarise(db_path):
         out.append(f"{name[:70]:70s} {n:6d} {tot / 1e3:11.1f} {avg / 1e3:9.2f} {mn / 1e3:9.2f} "
                    f"{mx / 1e3:9.2f} {100 * tot / total:6.1f}")
     return "\n".join(out)
+
+
+def summarise_window(db_path, kernel_substring, first, count):
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, duration from kernels order by start").fetchall()
+    d = [dur for name, dur in rows if kernel_substring in name]
+    sel = d[first:first + count] if first + count != 0 else d[first:]
+    if len(sel) != count:
+        return f"only {len(sel)} of {count} '{kernel_substring}' launches from {first} ({len(d)} in all)"
+    mean = sum(sel) / count
+    return (f"'{kernel_substring}' launches {first}..{first + count - 1} of {len(d)} (launch order): "
+            f"mean {mean / 1e3:.2f} us  min {min(sel) / 1e3:.2f}  max {max(sel) / 1e3:.2f}")
 
 
 def counter_values(csv_path, kernel_substring):
@@ -51,7 +67,9 @@ def summarise_pmc(csv_path, kernel_substring):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 2 and sys.argv[1] == "--pmc":
+    if len(sys.argv) >= 2 and sys.argv[1] == "--window":
+        print(summarise_window(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5])))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "--pmc":
         print(summarise_pmc(sys.argv[2], sys.argv[3]))
     else:
         print(summarise(sys.argv[1]))
