@@ -11,10 +11,13 @@ the method's arithmetic.
 
 Modules
 -------
-quadrature   Gauss-Legendre parity pairs (reading of the velocity grid).
+quadrature   Gauss-Legendre parity pairs (reading of the velocity grid) and
+             the equally spaced circle directions of the 2-D workloads.
 ap1d         One fully discrete AP step in 1-D, Algorithm 2 (Section 4) and its
              temperature-dependent-opacity variant (Section 5), solved with
              direct sparse linear algebra.
+ap2d         The same step on a 2-D rectangle (staggered parity reading:
+             E in cells, O on the faces), direct sparse linear algebra.
 diffusion1d  The three-stage diffusion scheme (2.7) / its sigma/T^3 form, the
              two-stage counter-example (2.8), and the fully implicit
              reference solvers (6.1) and (6.7).
