@@ -410,6 +410,116 @@ grte_status grte_batch_use_graph(grte_batch *b, int on);
 grte_status grte_batch_set_profiling(grte_batch *b, int on);
 grte_status grte_batch_read_timing(grte_batch *b, double *total_ms, int *count);
 
+/* ===========================================================================
+ * The AP step on a 2-D rectangle [0, lx] x [0, ly] (nx x ny cells).
+ *
+ * The paper's scheme is one-dimensional; this is its extension on a staggered
+ * parity grid: E_p in the cells, the odd parity O_p on the faces (O^x on the
+ * x-faces, O^y on the y-faces), the O-equation of (4.3) at every interior face
+ * with Omega_p . grad E discretised as the compact difference across the face
+ * plus the mean of the two adjacent cells' centred differences along the face
+ * (one-sided at a wall), the E-equation in every cell with the discrete
+ * divergence, and the inflow relation (4.6) at the centre of every edge cell
+ * through the cell's two faces normal to the edge.  Each step is Algorithm 2:
+ * prediction (4.5)/(5.2), the scalar equation (4.13) per cell, correction
+ * (4.11)-(4.12), projection (4.14).  Both linear systems are solved by a
+ * preconditioned Krylov method to a relative residual (grte2d_set_solver).
+ *
+ * Layouts (binary64, cell-major, pair index fastest; device or host):
+ *   E[(iy*nx + ix)*P + p]        cells, ix along x, iy along y
+ *   Ox[(iy*(nx+1) + fx)*P + p]   x-faces fx = 0..nx (face fx between cells fx-1, fx)
+ *   Oy[(fy*nx + ix)*P + p]       y-faces fy = 0..ny
+ *   T[iy*nx + ix], sigma0[iy*nx + ix]
+ * Direction pair p: Omega_p = (mu_p, eta_p) with eta_p > 0 and mu_p != 0 (no
+ * direction parallel to an edge), and -Omega_p; omega_p the pair weight,
+ * rho = sum_p omega_p E_p.
+ * ======================================================================== */
+typedef struct grte2d_ctx grte2d_ctx;
+
+typedef struct grte2d_problem {
+    int nx, ny;        /* cells along x and y, each >= 2; nx*ny <= 2^28          */
+    int npairs;        /* P: a power of two, 1 <= P <= 64                        */
+    double lx, ly;     /* rectangle sides > 0                                    */
+    double a, c, cv;   /* radiation constant, speed of light, heat capacity > 0  */
+    int opacity_law;   /* m: 0 -> sigma = sigma0; 3 -> sigma = sigma0 / T^3      */
+} grte2d_problem;
+
+typedef struct grte2d_step_info {
+    int pred_iters;          /* Krylov iterations of the prediction               */
+    int pred_converged;      /* 1 if its true relative residual met the tolerance */
+    double pred_residual;    /* that residual, ||b - A x||_2 / ||b||_2             */
+    int corr_iters;          /* the same for the correction                        */
+    int corr_converged;
+    double corr_residual;
+    int newton_max_iters;    /* largest Newton iteration count over the cells     */
+    int newton_failed;       /* cells whose Newton solve hit the cap               */
+    int kstar_clamped;       /* sigma/T^3: cells with U* < 0 (K* taken as 0)       */
+    int negative_root;       /* cells whose (4.13) has no root >= 0                */
+    int newton_total_iters;  /* Newton iterations summed over the cells            */
+    int pred_floor_stop;     /* 1 if a solve was accepted at the rounding level of */
+    int corr_floor_stop;     /* its residual: restarting no longer reduced it and
+                                it was within 64 x max(tol, that level), the level
+                                being 2^-53 || |A| |x| + |b| ||_2 / ||b||_2 (the
+                                normwise backward-error floor of a binary64
+                                iterate; counted in *_converged)                   */
+} grte2d_step_info;
+
+enum {
+    GRTE2D_STAGE_ESTAR = 0,  /* E* of the prediction, nx*ny*P                     */
+    GRTE2D_STAGE_USTAR = 1,  /* U* from (4.5c), nx*ny                              */
+    GRTE2D_STAGE_D = 2,      /* flux divergence D of (4.13), nx*ny                 */
+    GRTE2D_STAGE_RHON = 3    /* rho^n = sum_p omega_p E^n_p, nx*ny                 */
+};
+
+/* nv equally spaced directions theta_k = 2 pi (k + 1/2)/nv on the unit circle
+ * (host, no device work): the nv/2 pairs k < nv/2 with mu = cos, eta = sin,
+ * omega = 2/nv.  nv a multiple of 4, 4 <= nv <= 128; arrays of nv/2 doubles. */
+grte_status grte2d_circle_directions(int nv, double *mu, double *eta, double *omega);
+
+/* Create a context: copies the problem and the pairs (host arrays of P doubles)
+ * and allocates device memory (about 16 binary64 arrays of nx*ny*P).  State
+ * zero, opacity one, inflow zero until set.  GRTE_E_UNSUPPORTED for sizes or P
+ * outside the limits above, GRTE_E_INVAL for bad values, GRTE_E_NOMEM. */
+grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const double *eta,
+                          const double *omega, grte2d_ctx **out);
+
+/* Free the context (NULL accepted). */
+grte_status grte2d_destroy(grte2d_ctx *ctx);
+
+/* Order the context's work on `hip_stream` (NULL = the null stream). */
+grte_status grte2d_set_stream(grte2d_ctx *ctx, void *hip_stream);
+
+/* Krylov tolerance on the relative 2-norm residual (default 1e-14) and the
+ * iteration cap per solve (default 2000).  The residual is recomputed from the
+ * equations (in a form whose rounding stays near the residual's own size)
+ * after each pass of iterations, and the solve restarted from it, up to six
+ * times; an iterate whose residual no longer drops by half from one pass to
+ * the next is accepted when within 64 x max(tol, the residual's rounding
+ * level) -- stiff problems (a c beta of (4.5c) above ~1e7) cannot reach
+ * 1e-14. */
+grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
+
+/* Opacity coefficient per cell, sigma0[nx*ny] >= 0. */
+grte_status grte2d_set_opacity(grte2d_ctx *ctx, const double *sigma0, int on_device);
+
+/* Inflow b[4*P] (host): b[e*P + p] is the intensity of whichever of +-Omega_p
+ * enters through edge e = 0 (x = 0), 1 (x = lx), 2 (y = 0), 3 (y = ly). */
+grte_status grte2d_set_inflow(grte2d_ctx *ctx, const double *b);
+
+/* State (E^n, O^x, O^y, T^n) in the layouts above. */
+grte_status grte2d_set_state(grte2d_ctx *ctx, const double *E, const double *Ox, const double *Oy,
+                             const double *T, int on_device);
+grte_status grte2d_get_state(grte2d_ctx *ctx, double *E, double *Ox, double *Oy, double *T,
+                             int on_device);
+
+/* One AP step (dt > 0, eps > 0).  Synchronises the stream (the Krylov loop
+ * reads its convergence flag); fills *info when non-NULL.  GRTE_E_NOCONV (state
+ * still advanced) if a solve missed its tolerance or a Newton solve its cap. */
+grte_status grte2d_step(grte2d_ctx *ctx, double dt, double eps, grte2d_step_info *info);
+
+/* A stage of the last step (GRTE2D_STAGE_*). */
+grte_status grte2d_get_stage(grte2d_ctx *ctx, int which, double *out, int on_device);
+
 #ifdef __cplusplus
 }
 #endif

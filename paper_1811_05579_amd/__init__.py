@@ -1,10 +1,11 @@
-"""MI355X (gfx950) library for the asymptotic-preserving step of the 1-D gray
+"""MI355X (gfx950) library for the asymptotic-preserving step of the gray
 radiative transfer equation (Tang, Wang & Zhang, arXiv 1811.05579, Algorithm 2
 and Section 5).
 
 The Python layer only marshals arguments into the C ABI of include/grte.h;
 every stage of the step runs in the HIP kernels of csrc/grte.hip (one
-slab) and csrc/batch.hip (many slabs in one persistent launch).  Arrays may
+slab), csrc/batch.hip (many slabs in one persistent launch) and csrc/ap2d.hip
+(a 2-D rectangle).  Arrays may
 be numpy arrays (host memory, copied by the library) or torch CUDA tensors
 (device memory, borrowed for the call).
 """
@@ -13,9 +14,11 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import BatchInfo, BatchTuning, DiffProblem, GrteError, Instance, Problem, StepInfo, check, load
+from ._lib import (BatchInfo, BatchTuning, DiffProblem, GrteError, Instance, Problem, Problem2D, StepInfo,
+                   StepInfo2D, check, load)
 
-__all__ = ["Grte", "GrteBatch", "GrteDiff", "GrteError", "Mlp", "gauss_legendre", "load", "step_group"]
+__all__ = ["Grte", "Grte2D", "GrteBatch", "GrteDiff", "GrteError", "Mlp", "circle_directions",
+           "gauss_legendre", "load", "step_group"]
 
 
 def gauss_legendre(nv):
@@ -507,3 +510,108 @@ class GrteDiff:
         if st not in (0, -4):
             check("grte_diff_step", st)
         return {"status": st, "newton_max_iters": int(its.value)}
+
+
+def circle_directions(nv):
+    """The nv/2 direction pairs of nv equally spaced circle directions, computed
+    by the library (host routine): (mu, eta, omega)."""
+    lib = load()
+    P = nv // 2
+    mu, eta, om = np.zeros(P), np.zeros(P), np.zeros(P)
+    check("grte2d_circle_directions", lib.grte2d_circle_directions(int(nv), mu.ctypes.data, eta.ctypes.data,
+                                                                   om.ctypes.data))
+    return mu, eta, om
+
+
+class Grte2D:
+    """AP solver context on a 2-D rectangle (staggered parity: E in the cells,
+    O on the x- and y-faces).  Arrays: E (ny, nx, P), Ox (ny, nx+1, P),
+    Oy (ny+1, nx, P), T and sigma0 (ny, nx), inflow b (4, P) for the edges
+    x = 0, x = lx, y = 0, y = ly."""
+
+    def __init__(self, nx, ny, mu, eta, omega, lx=1.0, ly=1.0, a=1.0, c=1.0, cv=1.0, opacity_law=0):
+        self._lib = load()
+        mu, eta, omega = (np.ascontiguousarray(x, dtype=np.float64) for x in (mu, eta, omega))
+        if not (mu.shape == eta.shape == omega.shape) or mu.ndim != 1:
+            raise ValueError("mu, eta and omega must be 1-D arrays of equal length")
+        self.nx, self.ny, self.P = int(nx), int(ny), int(mu.size)
+        self.N = self.nx * self.ny
+        pb = Problem2D(self.nx, self.ny, self.P, float(lx), float(ly), float(a), float(c), float(cv),
+                       int(opacity_law))
+        h = ctypes.c_void_p()
+        check("grte2d_create", self._lib.grte2d_create(ctypes.byref(pb), mu.ctypes.data, eta.ctypes.data,
+                                                       omega.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.grte2d_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self):
+        return (self.N * self.P, self.ny * (self.nx + 1) * self.P, (self.ny + 1) * self.nx * self.P, self.N)
+
+    def set_stream(self, stream):
+        raw = getattr(stream, "cuda_stream", stream)
+        check("grte2d_set_stream", self._lib.grte2d_set_stream(self._h, ctypes.c_void_p(int(raw))))
+
+    def set_solver(self, tol=1e-14, maxit=2000):
+        check("grte2d_set_solver", self._lib.grte2d_set_solver(self._h, float(tol), int(maxit)))
+
+    def set_opacity(self, sigma0):
+        p, dev = _ptr(sigma0, self.N, "sigma0")
+        check("grte2d_set_opacity", self._lib.grte2d_set_opacity(self._h, _addr(p), dev))
+
+    def set_inflow(self, b):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        if b.size != 4 * self.P:
+            raise ValueError("inflow: need 4 * P values (edges x=0, x=lx, y=0, y=ly)")
+        check("grte2d_set_inflow", self._lib.grte2d_set_inflow(self._h, b.ctypes.data))
+
+    def set_state(self, E, Ox, Oy, T):
+        nE, nX, nY, nT = self.sizes()
+        pe, d1 = _ptr(E, nE, "E")
+        px, d2 = _ptr(Ox, nX, "Ox")
+        py, d3 = _ptr(Oy, nY, "Oy")
+        pt, d4 = _ptr(T, nT, "T")
+        if not (d1 == d2 == d3 == d4):
+            raise ValueError("E, Ox, Oy, T must all be host arrays or all device tensors")
+        check("grte2d_set_state", self._lib.grte2d_set_state(self._h, _addr(pe), _addr(px), _addr(py),
+                                                             _addr(pt), d1))
+
+    def get_state(self):
+        """(E, Ox, Oy, T) as numpy arrays."""
+        E = np.empty((self.ny, self.nx, self.P))
+        Ox = np.empty((self.ny, self.nx + 1, self.P))
+        Oy = np.empty((self.ny + 1, self.nx, self.P))
+        T = np.empty((self.ny, self.nx))
+        check("grte2d_get_state", self._lib.grte2d_get_state(self._h, E.ctypes.data, Ox.ctypes.data,
+                                                             Oy.ctypes.data, T.ctypes.data, 0))
+        return E, Ox, Oy, T
+
+    def get_stage(self, name):
+        shape = (self.ny, self.nx, self.P) if name == "E_star" else (self.ny, self.nx)
+        out = np.empty(shape)
+        check("grte2d_get_stage", self._lib.grte2d_get_stage(self._h, _lib.STAGES2D[name], out.ctypes.data, 0))
+        return out
+
+    def step(self, dt, eps, info=False):
+        """One AP step; returns the diagnostics (dict with 'status') when info=True.
+        The step synchronises its stream either way (convergence checks)."""
+        si = StepInfo2D()
+        st = self._lib.grte2d_step(self._h, float(dt), float(eps), ctypes.byref(si))
+        if st not in (0, -4):
+            check("grte2d_step", st)
+        if not info:
+            if st != 0:
+                check("grte2d_step", st)
+            return None
+        d = si.as_dict()
+        d["status"] = st
+        return d

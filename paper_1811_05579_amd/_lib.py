@@ -57,6 +57,24 @@ class BatchTuning(ctypes.Structure):
     _fields_ = [("wave_max_n", c_int), ("grid", c_int), ("step_ms", c_double)]
 
 
+class Problem2D(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("npairs", c_int), ("lx", c_double), ("ly", c_double),
+                ("a", c_double), ("c", c_double), ("cv", c_double), ("opacity_law", c_int)]
+
+
+class StepInfo2D(ctypes.Structure):
+    _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("pred_residual", c_double),
+                ("corr_iters", c_int), ("corr_converged", c_int), ("corr_residual", c_double),
+                ("newton_max_iters", c_int), ("newton_failed", c_int), ("kstar_clamped", c_int),
+                ("negative_root", c_int), ("newton_total_iters", c_int), ("pred_floor_stop", c_int),
+                ("corr_floor_stop", c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+STAGES2D = {"E_star": 0, "U_star": 1, "D": 2, "rho_n": 3}
+
 c_ll_p = ctypes.POINTER(ctypes.c_longlong)
 
 _SIGS = {
@@ -121,6 +139,18 @@ _SIGS = {
     "grte_batch_use_graph": (c_int, [c_void_p, c_int]),
     "grte_batch_set_profiling": (c_int, [c_void_p, c_int]),
     "grte_batch_read_timing": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
+    "grte2d_circle_directions": (c_int, [c_int, c_void_p, c_void_p, c_void_p]),
+    "grte2d_create": (c_int, [ctypes.POINTER(Problem2D), c_void_p, c_void_p, c_void_p,
+                              ctypes.POINTER(c_void_p)]),
+    "grte2d_destroy": (c_int, [c_void_p]),
+    "grte2d_set_stream": (c_int, [c_void_p, c_void_p]),
+    "grte2d_set_solver": (c_int, [c_void_p, c_double, c_int]),
+    "grte2d_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
+    "grte2d_set_inflow": (c_int, [c_void_p, c_void_p]),
+    "grte2d_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "grte2d_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "grte2d_step": (c_int, [c_void_p, c_double, c_double, ctypes.POINTER(StepInfo2D)]),
+    "grte2d_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
 }
 
 _lib = None

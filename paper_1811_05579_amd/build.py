@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("grte.hip", "batch.hip", "mlp.hip", "diffusion.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("grte.hip", "batch.hip", "mlp.hip", "diffusion.hip", "ap2d.hip")]
 OUT = os.path.join(HERE, "libgrte.so")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,1169 @@
+// ap2d.hip -- the AP step of Algorithm 2 on a 2-D rectangle, staggered parity:
+// E_p in the cells, the odd parity O_p on the faces (x-faces and y-faces), the
+// O-equation (second equation of (4.3)) at every interior face, the E-equation
+// in every cell, the inflow relation (4.6) at the centre of every edge cell.
+//
+// Both linear systems of the step -- the prediction (4.5)/(5.2) in (E*, O*) and
+// the correction (4.11) in (E_J, O_J) -- have the same structure once the face
+// unknowns are eliminated (each face value is an explicit function of its
+// neighbouring cell values):
+//
+//   A X = d_c X_p - g_c sum_q omega_q X_q + k_c div_p O(X)  =  rhs,
+//
+//   O(X) at an interior face = alpha_f O^n_f - gamma_f (Omega_p . grad X)_f  [+ known part],
+//   O(X) at an edge face     = (2 s / eps)(b - fe X_cell) - O(X) at the opposite face,
+//
+// where the discrete Omega_p . grad at an x-face is the compact x-difference
+// plus the mean of the two cells' centred y-differences (one-sided at a wall),
+// and the y-faces likewise.  g_c (the angular coupling of (4.5c)) is zero in the
+// correction.  The system is solved matrix-free by BiCGStab with a cell-block
+// Jacobi preconditioner (the P x P block of a cell -- diagonal plus the rank-one
+// coupling -- inverted exactly by the Sherman-Morrison formula), all in binary64.
+//
+// Data layout (device, binary64): cell-major, pair index fastest:
+//   E[(iy*nx + ix)*P + p], Ox[(iy*(nx+1) + fx)*P + p], Oy[(fy*nx + ix)*P + p].
+// A thread owns one (cell, pair); the P threads of a cell are adjacent lanes of
+// one wavefront (P a power of two <= 64), so angular sums are lane shuffles and
+// the stencil reads of a neighbouring cell are one contiguous P*8-byte run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/grte.h"
+#include "solver_common.hpp"
+
+namespace {
+
+constexpr int B2 = 256;        // threads per block of the (cell, pair) kernels
+constexpr int MAXB = 2048;     // blocks of the grid-stride kernels = partial sums per dot product
+constexpr int CHUNK = 8;       // BiCGStab iterations enqueued between convergence checks
+constexpr int KRY_RESTARTS = 6;      // restarts from the true residual per solve
+constexpr double KRY_FLOOR = 64.0;   // floor stop: true residual within this factor of its rounding level
+
+// scalars of the Krylov solve, in device memory
+enum { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_RV, S_TS, S_TT, S_MM, S_NS };
+enum { F_STATE = 0, F_ITS, F_NF };          // F_STATE: 0 running, 1 converged, 2 breakdown
+
+struct Sys {
+    int nx, ny, P, corr;
+    double dx, dy, eps, fe, W1;
+    const double *mu, *eta, *om, *b;     // pairs and inflow b[4*P]
+    const double *E0, *Ox0, *Oy0;        // E^n, O^n
+    const double *ax, *gx, *ay, *gy;     // face alpha, gamma (gamma includes fe)
+    const double *lam, *dmg, *cg, *kco;  // cell: Lambda, Lambda - g W1, g, K co c dt
+    const double *rb1, *rb0, *acU;       // rhs = rb1 E^n_p + rb0; acU (correction's known part)
+    const double *sab, *ue;              // residual in difference form (see residual_at)
+};
+
+__device__ __forceinline__ double group_sum(double v, int P)
+{
+    for (int o = P >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double group_lane0(double v, int P)
+{
+    const int lane = __lane_id();
+    return __shfl(v, lane & ~(P - 1), 64);
+}
+
+// 3 x 3 neighbourhood of a cell field (indices clamped at the walls)
+struct Nb {
+    double v[3][3];
+};
+
+__device__ __forceinline__ Nb load_nb(const double *x, int nx, int ny, int iy, int ix, int P, int p)
+{
+    Nb n;
+    const int r[3] = {max(iy - 1, 0), iy, min(iy + 1, ny - 1)};
+    const int c[3] = {max(ix - 1, 0), ix, min(ix + 1, nx - 1)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) n.v[a][k] = x[((size_t)r[a] * nx + c[k]) * P + p];
+    return n;
+}
+
+// Omega . grad of a neighbourhood at the cell's four faces (left, right, bottom, top)
+struct Grad {
+    double l, r, b, t;
+};
+
+__device__ __forceinline__ Grad face_grad(const Nb &n, double mu, double eta, const Sys &S, int iy, int ix)
+{
+    // centred differences, one-sided next to a wall (the clamped neighbourhood
+    // turns the centred formula into the one-sided one with the weight 1/h)
+    const double wy = (iy == 0 || iy == S.ny - 1) ? 1.0 / S.dy : 0.5 / S.dy;
+    const double wx = (ix == 0 || ix == S.nx - 1) ? 1.0 / S.dx : 0.5 / S.dx;
+    double dy[3], dx[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dy[k] = (n.v[2][k] - n.v[0][k]) * wy;
+        dx[k] = (n.v[k][2] - n.v[k][0]) * wx;
+    }
+    Grad g;
+    g.l = mu * (n.v[1][1] - n.v[1][0]) / S.dx + eta * 0.5 * (dy[0] + dy[1]);
+    g.r = mu * (n.v[1][2] - n.v[1][1]) / S.dx + eta * 0.5 * (dy[1] + dy[2]);
+    g.b = eta * (n.v[1][1] - n.v[0][1]) / S.dy + mu * 0.5 * (dx[0] + dx[1]);
+    g.t = eta * (n.v[2][1] - n.v[1][1]) / S.dy + mu * 0.5 * (dx[1] + dx[2]);
+    return g;
+}
+
+// Face values of O at the cell's four faces.  KNOWN: the part independent of X
+// (O^n, the inflow data and, in the correction, a c U^{n+1}); LIN: the part linear
+// in X (a neighbourhood of X for this pair).
+template <bool KNOWN, bool LIN>
+__device__ __forceinline__ void faces(const Sys &S, int iy, int ix, int p, const Nb *X, Grad &O)
+{
+    const int nx = S.nx, ny = S.ny, P = S.P;
+    const double mu = S.mu[p], eta = S.eta[p];
+    const size_t fl = (size_t)iy * (nx + 1) + ix, fb = (size_t)iy * nx + ix;
+    const size_t fr = fl + 1, ft = fb + nx;
+    O.l = O.r = O.b = O.t = 0.0;
+    if (LIN) {
+        const Grad g = face_grad(*X, mu, eta, S, iy, ix);
+        O.l = -S.gx[fl] * g.l;
+        O.r = -S.gx[fr] * g.r;
+        O.b = -S.gy[fb] * g.b;
+        O.t = -S.gy[ft] * g.t;
+    }
+    double uc = 0.0;
+    if (KNOWN) {
+        O.l += S.ax[fl] * S.Ox0[fl * P + p];
+        O.r += S.ax[fr] * S.Ox0[fr * P + p];
+        O.b += S.ay[fb] * S.Oy0[fb * P + p];
+        O.t += S.ay[ft] * S.Oy0[ft * P + p];
+        if (S.corr) {
+            const Nb U = load_nb(S.acU, nx, ny, iy, ix, 1, 0);
+            const Grad g = face_grad(U, mu, eta, S, iy, ix);
+            const double ife = 1.0 / S.fe;
+            O.l -= S.gx[fl] * ife * g.l;
+            O.r -= S.gx[fr] * ife * g.r;
+            O.b -= S.gy[fb] * ife * g.b;
+            O.t -= S.gy[ft] * ife * g.t;
+            uc = U.v[1][1];
+        }
+    }
+    // inflow relations: E_cell + s (eps/2)(O_edge + O_opposite) = b, s = +1 when
+    // +Omega_p enters through that edge
+    const double xc = LIN ? X->v[1][1] : 0.0;
+    const double k2 = 2.0 / S.eps;
+    // (the difference inflow - cell value is formed first: both terms carry 2/eps)
+    auto edge = [&](int e, double s) {
+        double d = 0.0;
+        if (KNOWN && LIN) d = (S.b[e * P + p] - uc) - S.fe * xc;
+        else if (KNOWN) d = S.b[e * P + p] - uc;
+        else d = -S.fe * xc;
+        return s * k2 * d;
+    };
+    const double sx = mu > 0.0 ? 1.0 : -1.0, sy = eta > 0.0 ? 1.0 : -1.0;
+    if (ix == 0) O.l = edge(0, sx) - O.r;
+    if (ix == nx - 1) O.r = edge(1, -sx) - O.l;
+    if (iy == 0) O.b = edge(2, sy) - O.t;
+    if (iy == ny - 1) O.t = edge(3, -sy) - O.b;
+}
+
+__device__ __forceinline__ double divergence(const Sys &S, const Grad &O, int p)
+{
+    return S.mu[p] * (O.r - O.l) / S.dx + S.eta[p] * (O.t - O.b) / S.dy;
+}
+
+// ---------------------------------------------------------------------------
+// per-step coefficients
+// ---------------------------------------------------------------------------
+struct CoefArgs {
+    int nx, ny, m, corr;
+    double a, c, cv, eps, dt, fe, W1;
+    const double *T, *sigma0;
+    double *ax, *gx, *ay, *gy, *lam, *dmg, *cg, *kco, *rb0, *acU, *beta, *sab, *ue;
+};
+
+
+__device__ __forceinline__ double harm(double a, double b)
+{
+    const double s = a + b;
+    return s > 0.0 ? 2.0 * a * b / s : 0.0;
+}
+
+__global__ void __launch_bounds__(B2) coef2d_kernel(CoefArgs A)
+{
+    const int n = A.nx * A.ny;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        const int iy = j / A.nx, ix = j - iy * A.nx;
+        const double T = A.T[j], s0 = A.sigma0[j];
+        const double K = kpow(T, A.m);
+        const double e2 = A.eps * A.eps, cdt = A.c * A.dt, ac = A.a * A.c;
+        const double U = T * T * T * T;
+        const double lam = K * e2 + s0 * cdt;
+        A.lam[j] = lam;
+        if (!A.corr) {
+            // (4.5c): U* = (U^n + beta rho*)/(1 + ac beta), substituted into (4.5b)
+            const double beta = 4.0 * s0 * A.dt * (A.m == 0 ? T * T * T : 1.0) / (e2 * A.cv);
+            const double g = s0 * cdt * ac * beta / (1.0 + ac * beta);
+            A.beta[j] = beta;
+            A.cg[j] = g;
+            // Lambda - g W1 formed directly: K eps^2 + sigma0 c dt / (1 + ac beta) + g (1 - W1)
+            A.dmg[j] = K * e2 + s0 * cdt / (1.0 + ac * beta) + g * (1.0 - A.W1);
+            A.kco[j] = K * e2 * cdt;
+            A.rb0[j] = s0 * cdt * ac * U / (1.0 + ac * beta);
+            A.sab[j] = s0 * cdt / (1.0 + ac * beta);
+            A.ue[j] = ac * U;
+        } else {
+            A.cg[j] = 0.0;
+            A.dmg[j] = lam;
+            A.kco[j] = K * A.eps * cdt;
+            A.rb0[j] = -K * A.eps * ac * U;
+            A.acU[j] = ac * U;
+            A.sab[j] = s0 * cdt;
+            A.ue[j] = ac * U;
+        }
+        // faces owned by this cell: its left x-face and bottom y-face (interior ones)
+        auto face = [&](int jn, double &alpha, double &gamma) {
+            const double Kf = 0.5 * (K + kpow(A.T[jn], A.m));
+            const double sf = harm(s0, A.sigma0[jn]);
+            const double den = Kf * e2 + sf * cdt;
+            alpha = Kf * e2 / den;
+            gamma = Kf * cdt * A.fe / den;
+        };
+        const size_t fl = (size_t)iy * (A.nx + 1) + ix, fb = (size_t)iy * A.nx + ix;
+        double al = 0.0, gl = 0.0, ab = 0.0, gb = 0.0;
+        if (ix > 0) face(j - 1, al, gl);
+        if (iy > 0) face(j - A.nx, ab, gb);
+        A.ax[fl] = al;
+        A.gx[fl] = gl;
+        A.ay[fb] = ab;
+        A.gy[fb] = gb;
+        if (ix == A.nx - 1) A.ax[fl + 1] = A.gx[fl + 1] = 0.0;
+        if (iy == A.ny - 1) A.ay[fb + A.nx] = A.gy[fb + A.nx] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side, residual, operator
+// ---------------------------------------------------------------------------
+struct VecArgs {
+    Sys S;
+    size_t n;                  // N * P
+    const double *En;          // E^n (rhs)
+    double *bv, *x, *r, *r0, *p, *ph, *v, *s, *sh, *t;
+    double *part;              // [k * MAXB + block]
+    double *sc;                // scalars
+    int *fl;                   // flags
+    double tol;
+    int maxit;
+};
+
+__device__ __forceinline__ void block_sums(double *vals, int k, double *part)
+{
+    __shared__ double red[4][B2 / 64];
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    for (int q = 0; q < k; ++q) {
+        double v = vals[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[q][w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double v = 0.0;
+        for (int i = 0; i < B2 / 64; ++i) v += red[threadIdx.x][i];
+        part[threadIdx.x * MAXB + blockIdx.x] = v;
+    }
+}
+
+// rhs: rb1 E^n_p + rb0 - k div O(known)   (rb1 = K eps^2 prediction, K eps correction)
+__global__ void __launch_bounds__(B2) rhs2d_kernel(VecArgs A)
+{
+    const Sys &S = A.S;
+    const int P = S.P;
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
+        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+        const int iy = j / S.nx, ix = j - iy * S.nx;
+        Grad O;
+        faces<true, false>(S, iy, ix, p, nullptr, O);
+        A.bv[t] = S.rb1[j] * A.En[t] + S.rb0[j] - S.kco[j] * divergence(S, O, p);
+    }
+}
+
+// y = A x for the (cell, pair) of thread t
+__device__ __forceinline__ double apply_at(const Sys &S, const double *x, size_t t, int j, int p)
+{
+    const int P = S.P;
+    const int iy = j / S.nx, ix = j - iy * S.nx;
+    const Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
+    Grad O;
+    faces<false, true>(S, iy, ix, p, &X, O);
+    const double xp = X.v[1][1];
+    // W1 x_p - sum_q omega_q x_q, referred to the cell's first pair to keep it
+    // exact for a nearly isotropic x
+    const double xr = group_lane0(xp, P);
+    const double w = S.om[p];
+    const double cpl = S.W1 * (xp - xr) - group_sum(w * (xp - xr), P);
+    return S.dmg[j] * xp + S.cg[j] * cpl + S.kco[j] * divergence(S, O, p);
+}
+
+// b - A x evaluated from the full face values and differences of nearly equal
+// quantities (E^n - x, a c U - x), so that its rounding stays at the level of the
+// residual itself rather than of the large terms that cancel in it (the inflow
+// relations carry 2/eps times the inflow and the cell value):
+//   prediction  K eps^2 (E^n_p - x_p) + s (a c U^n - x_p) - g (1 - W1) x_p
+//               - g (W1 x_p - sum_q omega_q x_q) - k div O(x),   s = sigma0 c dt / (1 + ac beta)
+//   correction  K eps (E^n_p - a c U - eps x_p) - sigma0 c dt x_p - k div O(x)
+__device__ __forceinline__ double residual_at(const Sys &S, const double *En, const double *x, size_t t, int j,
+                                              int p, double &mag)
+{
+    const int P = S.P;
+    const int iy = j / S.nx, ix = j - iy * S.nx;
+    const Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
+    Grad O;
+    faces<true, true>(S, iy, ix, p, &X, O);
+    const double xp = X.v[1][1];
+    const double mu = S.mu[p], eta = S.eta[p];
+    const double k = S.kco[j];
+    const double div = k * divergence(S, O, p);
+    // mag: an upper estimate of (|A| |x| + |b|) for this row -- the scale of the
+    // rounding a binary64 iterate and its residual cannot avoid (normwise
+    // backward error): the face terms bounded by the largest |x| of the
+    // neighbourhood, the inflow and O^n terms by their magnitudes
+    double xm = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xm = fmax(xm, fabs(X.v[a][c]));
+    const size_t fl = (size_t)iy * (S.nx + 1) + ix, fb = (size_t)iy * S.nx + ix;
+    const double gsum = S.gx[fl] + S.gx[fl + 1] + S.gy[fb] + S.gy[fb + S.nx];
+    const double grad_bound = 2.0 * (fabs(mu) / S.dx + fabs(eta) / S.dy) * xm;
+    const double k2 = 2.0 / S.eps;
+    const double edge_bound = ((ix == 0 || ix == S.nx - 1) + (iy == 0 || iy == S.ny - 1)) * k2 *
+                              (4.0 * S.fe * xm + fabs(S.ue[j]));
+    const double dmag = fabs(k) * (fabs(mu) / S.dx + fabs(eta) / S.dy) *
+                        (fabs(O.l) + fabs(O.r) + fabs(O.b) + fabs(O.t) + gsum * grad_bound + edge_bound);
+    if (S.corr) {
+        const double a1 = S.rb1[j] * ((En[t] - S.ue[j]) - S.eps * xp), a2 = S.sab[j] * xp;
+        mag = fabs(S.rb1[j]) * (fabs(En[t]) + fabs(S.ue[j]) + S.eps * fabs(xp)) + fabs(a2) + dmag;
+        return a1 - a2 - div;
+    }
+    const double xr = group_lane0(xp, P);
+    const double w = S.om[p];
+    const double cpl = S.W1 * (xp - xr) - group_sum(w * (xp - xr), P);
+    const double g = S.cg[j];
+    mag = fabs(S.rb1[j]) * (fabs(En[t]) + fabs(xp)) + S.sab[j] * (fabs(S.ue[j]) + fabs(xp)) +
+          fabs(g) * (S.W1 * fabs(xp) + group_sum(w * fabs(xp), P)) + dmag;
+    return S.rb1[j] * (En[t] - xp) + S.sab[j] * (S.ue[j] - xp) - g * (1.0 - S.W1) * xp - g * cpl - div;
+}
+
+// mode 0: r = b - A x, r0 = r, partial (r, r) and (b, b)
+// mode 1: v = A ph, partial (r0, v)
+// mode 2: t = A sh, partial (t, s), (t, t)
+template <int MODE>
+__global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
+{
+    if (A.fl[F_STATE] != 0 && MODE != 0) return;
+    const Sys &S = A.S;
+    const int P = S.P;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
+        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+        if (MODE == 0) {
+            double mag;
+            const double rr = residual_at(S, A.En, A.x, t, j, p, mag);
+            A.r[t] = rr;
+            A.r0[t] = rr;
+            acc[0] += rr * rr;
+            acc[1] += A.bv[t] * A.bv[t];
+            acc[2] += mag * mag;
+        } else if (MODE == 1) {
+            const double y = apply_at(S, A.ph, t, j, p);
+            A.v[t] = y;
+            acc[0] += A.r0[t] * y;
+        } else {
+            const double y = apply_at(S, A.sh, t, j, p);
+            A.t[t] = y;
+            const double sv = A.s[t];
+            acc[0] += y * sv;
+            acc[1] += y * y;
+        }
+    }
+    block_sums(acc, MODE == 0 ? 3 : (MODE == 1 ? 1 : 2), A.part);
+}
+
+// cell-block Jacobi: z = B^{-1} y, B = diag(d_p) - g 1 omega^T (Sherman-Morrison)
+__device__ __forceinline__ double precond_at(const Sys &S, double y, int j, int p)
+{
+    const int P = S.P;
+    const int iy = j / S.nx, ix = j - iy * S.nx;
+    const double mu = S.mu[p], eta = S.eta[p];
+    const double mx = mu * mu / (S.dx * S.dx), my = eta * eta / (S.dy * S.dy);
+    const size_t fl = (size_t)iy * (S.nx + 1) + ix, fb = (size_t)iy * S.nx + ix;
+    const double gl = S.gx[fl], gr = S.gx[fl + 1], gb = S.gy[fb], gt = S.gy[fb + S.nx];
+    // diagonal of k div O(X) with respect to X_cell (the compact terms; an edge
+    // face doubles the opposite face and adds the inflow term 2|Omega_n| fe/(eps h))
+    double tr = 0.0;
+    const double k2 = 2.0 * S.fe / S.eps;
+    if (ix == 0) tr += 2.0 * gr * mx + k2 * fabs(mu) / S.dx;
+    else if (ix == S.nx - 1) tr += 2.0 * gl * mx + k2 * fabs(mu) / S.dx;
+    else tr += (gl + gr) * mx;
+    if (iy == 0) tr += 2.0 * gt * my + k2 * fabs(eta) / S.dy;
+    else if (iy == S.ny - 1) tr += 2.0 * gb * my + k2 * fabs(eta) / S.dy;
+    else tr += (gb + gt) * my;
+    const double d = S.lam[j] + S.kco[j] * tr;
+    const double w = S.om[p];
+    const double u = y / d;
+    const double s1 = group_sum(w * u, P);
+    const double s2 = group_sum(w / d, P);
+    const double g = S.cg[j];
+    return u + (g * s1 / (1.0 - g * s2)) / d;
+}
+
+// p = r + beta (p - omega v); ph = B^{-1} p
+__global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
+{
+    if (A.fl[F_STATE] != 0) return;
+    const double beta = A.sc[S_BETA], omega = A.sc[S_OMEGA];
+    const int P = A.S.P;
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
+        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+        const double pv = A.r[t] + beta * (A.p[t] - omega * A.v[t]);
+        A.p[t] = pv;
+        A.ph[t] = precond_at(A.S, pv, j, p);
+    }
+}
+
+// s = r - alpha v; sh = B^{-1} s; x += alpha ph
+__global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
+{
+    if (A.fl[F_STATE] != 0) return;
+    const double alpha = A.sc[S_ALPHA];
+    const int P = A.S.P;
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
+        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+        const double sv = A.r[t] - alpha * A.v[t];
+        A.s[t] = sv;
+        A.sh[t] = precond_at(A.S, sv, j, p);
+        A.x[t] += alpha * A.ph[t];
+    }
+}
+
+// x += omega sh; r = s - omega t; partial (r0, r), (r, r)
+__global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
+{
+    if (A.fl[F_STATE] != 0) return;
+    const double omega = A.sc[S_OMEGA];
+    double acc[2] = {0.0, 0.0};
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
+        A.x[t] += omega * A.sh[t];
+        const double rv = A.s[t] - omega * A.t[t];
+        A.r[t] = rv;
+        acc[0] += A.r0[t] * rv;
+        acc[1] += rv * rv;
+    }
+    block_sums(acc, 2, A.part);
+}
+
+// sum of the partials of dot k over nb blocks, in a fixed order (one block of B2 threads)
+__device__ __forceinline__ double fin_sum(const double *part, int k, int nb)
+{
+    __shared__ double red[B2];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += B2) v += part[k * MAXB + i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = B2 / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// which: 0 = start (rho = rr = (r, r), bb, test), 1 = alpha, 2 = omega, 3 = rho/beta/test
+__global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
+{
+    if (which != 0 && A.fl[F_STATE] != 0) return;
+    double *sc = A.sc;
+    if (which == 0) {
+        const double rr = fin_sum(A.part, 0, nb), bb = fin_sum(A.part, 1, nb), mm = fin_sum(A.part, 2, nb);
+        if (threadIdx.x == 0) {
+            sc[S_RHO] = rr;
+            sc[S_RR] = rr;
+            sc[S_BB] = bb;
+            sc[S_MM] = mm;
+            sc[S_ALPHA] = sc[S_OMEGA] = 1.0;
+            sc[S_BETA] = 0.0;
+            A.fl[F_STATE] = (rr <= A.tol * A.tol * bb) ? 1 : 0;
+        }
+    } else if (which == 1) {
+        const double rv = fin_sum(A.part, 0, nb);
+        if (threadIdx.x == 0) {
+            sc[S_RV] = rv;
+            if (rv == 0.0 || !isfinite(rv)) A.fl[F_STATE] = 2;
+            else sc[S_ALPHA] = sc[S_RHO] / rv;
+        }
+    } else if (which == 2) {
+        const double ts = fin_sum(A.part, 0, nb), tt = fin_sum(A.part, 1, nb);
+        if (threadIdx.x == 0) {
+            sc[S_TS] = ts;
+            sc[S_TT] = tt;
+            if (tt == 0.0 || !isfinite(tt)) A.fl[F_STATE] = 2;
+            else sc[S_OMEGA] = ts / tt;
+        }
+    } else {
+        const double rho = fin_sum(A.part, 0, nb), rr = fin_sum(A.part, 1, nb);
+        if (threadIdx.x == 0) {
+            const int its = A.fl[F_ITS] + 1;
+            A.fl[F_ITS] = its;
+            sc[S_RR] = rr;
+            if (!(rr <= A.tol * A.tol * sc[S_BB]) && its >= A.maxit) {
+                A.fl[F_STATE] = 3;
+            } else if (rr <= A.tol * A.tol * sc[S_BB]) {
+                A.fl[F_STATE] = 1;
+            } else if (sc[S_OMEGA] == 0.0 || rho == 0.0 || !isfinite(rho)) {
+                A.fl[F_STATE] = 2;
+            } else {
+                sc[S_BETA] = (rho / sc[S_RHO]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+                sc[S_RHO] = rho;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(B2) zero2_kernel(double *a, double *b, size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2) a[t] = b[t] = 0.0;
+}
+
+__global__ void reset_flags_kernel(int *fl)
+{
+    if (threadIdx.x < F_NF) fl[threadIdx.x] = 0;
+}
+
+// x0 of the correction: E_J = (E* - a c U^{n+1}) / eps
+__global__ void __launch_bounds__(B2) xcorr0_kernel(double *x, const double *Es, const double *acU, int P,
+                                                    double ieps, size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2)
+        x[t] = (Es[t] - acU[t / P]) * ieps;
+}
+
+// ---------------------------------------------------------------------------
+// correction substep 1: moments, D, U*, K*, scalar Newton per cell
+// ---------------------------------------------------------------------------
+struct NewtArgs {
+    Sys S;                       // the prediction's system (its faces give O*)
+    const double *Es, *En, *Tn, *sigma0, *beta;
+    double a, c, cv, dt;
+    int m, maxit;
+    double *Tnew, *ustar, *Dv, *rhon;
+    int *stat;                   // [0] max its, [1] failed, [2] K* clamped, [3] negative root, [4] sum its
+};
+
+__global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
+{
+    const Sys &S = A.S;
+    const int P = S.P;
+    const size_t n = (size_t)S.nx * S.ny * P;
+    int mx = 0, sum = 0, failed = 0, clamped = 0, neg = 0;
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2) {
+        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+        const int iy = j / S.nx, ix = j - iy * S.nx;
+        const Nb X = load_nb(A.Es, S.nx, S.ny, iy, ix, P, p);
+        Grad O;
+        faces<true, true>(S, iy, ix, p, &X, O);
+        const double w = S.om[p];
+        const double D = group_sum(w * divergence(S, O, p), P);
+        const double rhs_s = group_sum(w * X.v[1][1], P);
+        const double rn = group_sum(w * A.En[t], P);
+        if (p != 0) continue;
+        const double ac = A.a * A.c;
+        const double Tn = A.Tn[j];
+        const double Un = Tn * Tn * Tn * Tn;
+        const double beta = A.beta[j];
+        const double us = (Un + beta * rhs_s) / (1.0 + ac * beta);
+        A.ustar[j] = us;
+        A.Dv[j] = D;
+        A.rhon[j] = rn;
+        double Ks = 1.0;
+        if (A.m == 3) {
+            if (us < 0.0) {
+                Ks = 0.0;
+                ++clamped;
+            } else {
+                Ks = pow(us, 0.75);
+            }
+        }
+        // (4.13) times c sigma0 dt^2:
+        //   a c sigma0 dt T^4 + Cv (eps^2 K* + c sigma0 dt)(T - T^n) - sigma0 dt (rho^n - c dt D) = 0
+        const double s0 = A.sigma0[j];
+        const double lin = A.cv * (S.eps * S.eps * Ks + A.c * s0 * A.dt);
+        const double q4 = ac * s0 * A.dt;
+        const double rhs = s0 * A.dt * (rn - A.c * A.dt * D);
+        double T = Tn;
+        int its = 0;
+        if (!(s0 == 0.0 && Ks == 0.0)) {
+            if (Tn + rhs / lin < 0.0) ++neg;
+            if (!newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its)) ++failed;
+        }
+        A.Tnew[j] = T;
+        mx = max(mx, its);
+        sum += its;
+    }
+    // one atomic per wavefront and counter
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = max(mx, __shfl_xor(mx, o, 64));
+        sum += __shfl_xor(sum, o, 64);
+        failed += __shfl_xor(failed, o, 64);
+        clamped += __shfl_xor(clamped, o, 64);
+        neg += __shfl_xor(neg, o, 64);
+    }
+    if (__lane_id() == 0) {
+        if (mx) atomicMax(&A.stat[0], mx);
+        if (failed) atomicAdd(&A.stat[1], failed);
+        if (clamped) atomicAdd(&A.stat[2], clamped);
+        if (neg) atomicAdd(&A.stat[3], neg);
+        if (sum) atomicAdd(&A.stat[4], sum);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// projection (4.14): E^{n+1} = a c U^{n+1} + eps E_J, O^{n+1} = O_J
+// ---------------------------------------------------------------------------
+struct ProjArgs {
+    Sys S;                    // the correction's system
+    const double *EJ;
+    double *E1, *Ox1, *Oy1;
+};
+
+__global__ void __launch_bounds__(B2) project2d_kernel(ProjArgs A)
+{
+    const Sys &S = A.S;
+    const int P = S.P;
+    const size_t n = (size_t)S.nx * S.ny * P;
+    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2) {
+        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+        const int iy = j / S.nx, ix = j - iy * S.nx;
+        const Nb X = load_nb(A.EJ, S.nx, S.ny, iy, ix, P, p);
+        Grad O;
+        faces<true, true>(S, iy, ix, p, &X, O);
+        A.E1[t] = S.acU[j] + S.eps * X.v[1][1];
+        const size_t fl = (size_t)iy * (S.nx + 1) + ix, fb = (size_t)iy * S.nx + ix;
+        A.Ox1[fl * P + p] = O.l;
+        if (ix == S.nx - 1) A.Ox1[(fl + 1) * P + p] = O.r;
+        A.Oy1[fb * P + p] = O.b;
+        if (iy == S.ny - 1) A.Oy1[(fb + S.nx) * P + p] = O.t;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// host side
+// ===========================================================================
+struct grte2d_ctx {
+    int nx, ny, P, m;
+    double lx, ly, a, c, cv, W1;
+    size_t N, nE, nOx, nOy;
+    hipStream_t stream = nullptr;
+    double tol = 1e-14;
+    int maxit = 2000;
+    // pairs, inflow
+    double *mu = nullptr, *eta = nullptr, *om = nullptr, *b = nullptr;
+    // state
+    double *E = nullptr, *Ox = nullptr, *Oy = nullptr, *T = nullptr, *sigma0 = nullptr;
+    double *E1 = nullptr, *Ox1 = nullptr, *Oy1 = nullptr, *T1 = nullptr;
+    // coefficients
+    double *ax = nullptr, *gx = nullptr, *ay = nullptr, *gy = nullptr;
+    double *lam = nullptr, *dmg = nullptr, *cg = nullptr, *kco = nullptr, *rb0 = nullptr, *rb1 = nullptr;
+    double *acU = nullptr, *beta = nullptr, *ustar = nullptr, *Dv = nullptr, *rhon = nullptr;
+    double *sab = nullptr, *ue = nullptr;
+    // Krylov
+    double *bv = nullptr, *x = nullptr, *r = nullptr, *r0 = nullptr, *p = nullptr, *ph = nullptr;
+    double *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr, *Es = nullptr;
+    double *part = nullptr, *sc = nullptr;
+    int *fl = nullptr, *stat = nullptr;
+    int *h_fl = nullptr;      // pinned
+    double *h_sc = nullptr;   // pinned
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+grte_status hip_ok(hipError_t e) { return e == hipSuccess ? GRTE_OK : GRTE_E_HIP; }
+
+template <class T>
+bool dalloc(grte2d_ctx *c, T *&p, size_t n)
+{
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return false;
+    c->allocs.push_back(q);
+    p = (T *)q;
+    return true;
+}
+
+int nblocks(size_t n)
+{
+    const size_t b = (n + B2 - 1) / B2;
+    return (int)std::max<size_t>(1, std::min<size_t>(b, MAXB));
+}
+
+Sys make_sys(grte2d_ctx *c, int corr, double eps)
+{
+    Sys S;
+    S.nx = c->nx;
+    S.ny = c->ny;
+    S.P = c->P;
+    S.corr = corr;
+    S.dx = c->lx / c->nx;
+    S.dy = c->ly / c->ny;
+    S.eps = eps;
+    S.fe = corr ? eps : 1.0;
+    S.W1 = c->W1;
+    S.mu = c->mu;
+    S.eta = c->eta;
+    S.om = c->om;
+    S.b = c->b;
+    S.E0 = c->E;
+    S.Ox0 = c->Ox;
+    S.Oy0 = c->Oy;
+    S.ax = c->ax;
+    S.gx = c->gx;
+    S.ay = c->ay;
+    S.gy = c->gy;
+    S.lam = c->lam;
+    S.dmg = c->dmg;
+    S.cg = c->cg;
+    S.kco = c->kco;
+    S.rb1 = c->rb1;
+    S.rb0 = c->rb0;
+    S.acU = c->acU;
+    S.sab = c->sab;
+    S.ue = c->ue;
+    return S;
+}
+
+__global__ void rb1_kernel(double *rb1, const double *T, int m, double f, int n)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) rb1[j] = (m == 0 ? 1.0 : T[j] * T[j] * T[j]) * f;
+}
+
+// BiCGStab on the system currently described by the coefficient arrays; x holds
+// the start and receives the solution.  Returns iterations, state and the
+// final true relative residual.
+grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, double &res_out, int &floor_out)
+{
+    int floor = 0;
+    VecArgs A;
+    A.S = S;
+    A.n = c->nE;
+    A.En = c->E;
+    A.bv = c->bv;
+    A.x = c->x;
+    A.r = c->r;
+    A.r0 = c->r0;
+    A.p = c->p;
+    A.ph = c->ph;
+    A.v = c->v;
+    A.s = c->s;
+    A.sh = c->sh;
+    A.t = c->t;
+    A.part = c->part;
+    A.sc = c->sc;
+    A.fl = c->fl;
+    A.tol = c->tol;
+    A.maxit = c->maxit;
+    const int nb = nblocks(c->nE);
+    hipStream_t st = c->stream;
+    int its_total = 0, state = 0;
+    double res = INFINITY;
+    for (int restart = 0; restart <= KRY_RESTARTS; ++restart) {
+        hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
+        hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
+        hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 0, nb);
+        hipLaunchKernelGGL(zero2_kernel, dim3(nb), dim3(B2), 0, st, c->p, c->v, c->nE);
+        if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+            return GRTE_E_HIP;
+        if (hipMemcpyAsync(c->h_sc, c->sc, S_NS * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+            return GRTE_E_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
+        const double prev = res;
+        res = c->h_sc[S_BB] > 0 ? sqrt(c->h_sc[S_RR] / c->h_sc[S_BB]) : 0.0;
+        // accept the iterate when its true residual meets the tolerance, or when
+        // a pass of iterations no longer reduces it and it lies within KRY_FLOOR
+        // units of binary64 rounding of || |A| |x| + |b| || / ||b|| (the
+        // normwise backward-error floor) or of the tolerance, whichever is larger
+        if (c->h_fl[F_STATE] == 1 || c->h_sc[S_BB] == 0.0) {
+            state = 1;
+            break;
+        }
+        const double lvl = c->h_sc[S_BB] > 0 ? 0x1p-53 * sqrt(c->h_sc[S_MM] / c->h_sc[S_BB]) : 0.0;
+        if (restart > 0 && res > 0.5 * prev && res <= KRY_FLOOR * fmax(c->tol, lvl)) {
+            state = 1;
+            floor = 1;
+            break;
+        }
+        if (restart == KRY_RESTARTS || its_total >= c->maxit) break;
+        while (true) {
+            for (int k = 0; k < CHUNK; ++k) {
+                hipLaunchKernelGGL(pupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(apply2d_kernel<1>, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 1, nb);
+                hipLaunchKernelGGL(supd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(apply2d_kernel<2>, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 2, nb);
+                hipLaunchKernelGGL(xupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 3, nb);
+            }
+            if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
+            if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+                return GRTE_E_HIP;
+            if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
+            if (c->h_fl[F_STATE] != 0) break;
+        }
+        its_total += c->h_fl[F_ITS];
+        // the recursion's residual has met the tolerance (or broken down): the
+        // next pass recomputes the true residual and restarts from it if needed
+        if (c->h_fl[F_STATE] == 3 && its_total >= c->maxit) {
+            // one more true residual for the report
+            hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
+            hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
+            hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 0, nb);
+            if (hipMemcpyAsync(c->h_sc, c->sc, S_NS * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+                return GRTE_E_HIP;
+            if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
+            res = c->h_sc[S_BB] > 0 ? sqrt(c->h_sc[S_RR] / c->h_sc[S_BB]) : 0.0;
+            state = 0;
+            break;
+        }
+    }
+    its_out = its_total;
+    state_out = state;
+    res_out = res;
+    floor_out = floor;
+    return GRTE_OK;
+}
+
+grte_status check_ctx(const grte2d_ctx *c) { return c ? GRTE_OK : GRTE_E_INVAL; }
+
+}  // namespace
+
+extern "C" {
+
+grte_status grte2d_circle_directions(int nv, double *mu, double *eta, double *omega)
+{
+    if (!mu || !eta || !omega || nv < 4 || nv % 4 || nv > 128) return GRTE_E_INVAL;
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < nv / 2; ++k) {
+        const double th = 2.0 * pi * (k + 0.5) / nv;
+        mu[k] = cos(th);
+        eta[k] = sin(th);
+        omega[k] = 2.0 / nv;
+    }
+    return GRTE_OK;
+}
+
+grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const double *eta, const double *omega,
+                          grte2d_ctx **out)
+{
+    if (!pb || !mu || !eta || !omega || !out) return GRTE_E_INVAL;
+    *out = nullptr;
+    const int P = pb->npairs;
+    if (pb->nx < 2 || pb->ny < 2 || P < 1 || P > 64 || (P & (P - 1))) return GRTE_E_UNSUPPORTED;
+    if (!(pb->lx > 0) || !(pb->ly > 0) || !(pb->a > 0) || !(pb->c > 0) || !(pb->cv > 0)) return GRTE_E_INVAL;
+    if (pb->opacity_law != 0 && pb->opacity_law != 3) return GRTE_E_INVAL;
+    if ((size_t)pb->nx * pb->ny > (size_t)1 << 28) return GRTE_E_UNSUPPORTED;
+    for (int p = 0; p < P; ++p)
+        if (!(eta[p] > 0.0) || mu[p] == 0.0 || !(omega[p] > 0.0)) return GRTE_E_INVAL;
+    grte2d_ctx *c = new (std::nothrow) grte2d_ctx();
+    if (!c) return GRTE_E_NOMEM;
+    c->nx = pb->nx;
+    c->ny = pb->ny;
+    c->P = P;
+    c->m = pb->opacity_law;
+    c->lx = pb->lx;
+    c->ly = pb->ly;
+    c->a = pb->a;
+    c->c = pb->c;
+    c->cv = pb->cv;
+    c->W1 = 0.0;
+    for (int p = 0; p < P; ++p) c->W1 += omega[p];
+    c->N = (size_t)c->nx * c->ny;
+    c->nE = c->N * P;
+    c->nOx = (size_t)c->ny * (c->nx + 1) * P;
+    c->nOy = (size_t)(c->ny + 1) * c->nx * P;
+    const size_t nfx = (size_t)c->ny * (c->nx + 1), nfy = (size_t)(c->ny + 1) * c->nx;
+    bool ok = dalloc(c, c->mu, P) && dalloc(c, c->eta, P) && dalloc(c, c->om, P) && dalloc(c, c->b, 4 * P) &&
+              dalloc(c, c->E, c->nE) && dalloc(c, c->Ox, c->nOx) && dalloc(c, c->Oy, c->nOy) &&
+              dalloc(c, c->T, c->N) && dalloc(c, c->sigma0, c->N) && dalloc(c, c->E1, c->nE) &&
+              dalloc(c, c->Ox1, c->nOx) && dalloc(c, c->Oy1, c->nOy) && dalloc(c, c->T1, c->N) &&
+              dalloc(c, c->ax, nfx) && dalloc(c, c->gx, nfx) && dalloc(c, c->ay, nfy) && dalloc(c, c->gy, nfy) &&
+              dalloc(c, c->lam, c->N) && dalloc(c, c->dmg, c->N) && dalloc(c, c->cg, c->N) &&
+              dalloc(c, c->kco, c->N) && dalloc(c, c->rb0, c->N) && dalloc(c, c->rb1, c->N) &&
+              dalloc(c, c->acU, c->N) && dalloc(c, c->beta, c->N) && dalloc(c, c->ustar, c->N) &&
+              dalloc(c, c->Dv, c->N) && dalloc(c, c->rhon, c->N) && dalloc(c, c->bv, c->nE) &&
+              dalloc(c, c->sab, c->N) && dalloc(c, c->ue, c->N) &&
+              dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
+              dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
+              dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
+              dalloc(c, c->Es, c->nE) && dalloc(c, c->part, 3 * MAXB) && dalloc(c, c->sc, S_NS) &&
+              dalloc(c, c->fl, F_NF) && dalloc(c, c->stat, 8);
+    if (ok) ok = hipHostMalloc((void **)&c->h_fl, F_NF * sizeof(int)) == hipSuccess;
+    if (ok) ok = hipHostMalloc((void **)&c->h_sc, S_NS * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        grte2d_destroy(c);
+        return GRTE_E_NOMEM;
+    }
+    bool hok = hipMemcpy(c->mu, mu, P * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+               hipMemcpy(c->eta, eta, P * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+               hipMemcpy(c->om, omega, P * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+               hipMemset(c->b, 0, 4 * P * sizeof(double)) == hipSuccess &&
+               hipMemset(c->E, 0, c->nE * sizeof(double)) == hipSuccess &&
+               hipMemset(c->Ox, 0, c->nOx * sizeof(double)) == hipSuccess &&
+               hipMemset(c->Oy, 0, c->nOy * sizeof(double)) == hipSuccess &&
+               hipMemset(c->T, 0, c->N * sizeof(double)) == hipSuccess;
+    if (hok) {
+        std::vector<double> one(c->N, 1.0);
+        hok = hipMemcpy(c->sigma0, one.data(), c->N * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!hok) {
+        grte2d_destroy(c);
+        return GRTE_E_HIP;
+    }
+    *out = c;
+    return GRTE_OK;
+}
+
+grte_status grte2d_destroy(grte2d_ctx *c)
+{
+    if (!c) return GRTE_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (void *q : c->allocs) (void)hipFree(q);
+    if (c->h_fl) (void)hipHostFree(c->h_fl);
+    if (c->h_sc) (void)hipHostFree(c->h_sc);
+    delete c;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_stream(grte2d_ctx *c, void *stream)
+{
+    if (!c) return GRTE_E_INVAL;
+    c->stream = (hipStream_t)stream;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_solver(grte2d_ctx *c, double tol, int maxit)
+{
+    if (!c || !(tol > 0.0) || maxit < 1) return GRTE_E_INVAL;
+    c->tol = tol;
+    c->maxit = maxit;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_opacity(grte2d_ctx *c, const double *sigma0, int on_device)
+{
+    if (!c || !sigma0) return GRTE_E_INVAL;
+    if (!on_device) {
+        for (size_t j = 0; j < c->N; ++j)
+            if (!(sigma0[j] >= 0.0) || !std::isfinite(sigma0[j])) return GRTE_E_INVAL;
+    }
+    if (hipMemcpyAsync(c->sigma0, sigma0, c->N * sizeof(double),
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return GRTE_E_HIP;
+    return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+grte_status grte2d_set_inflow(grte2d_ctx *c, const double *b)
+{
+    if (!c || !b) return GRTE_E_INVAL;
+    if (hipMemcpyAsync(c->b, b, 4 * c->P * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return GRTE_E_HIP;
+    return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+grte_status grte2d_set_state(grte2d_ctx *c, const double *E, const double *Ox, const double *Oy, const double *T,
+                             int on_device)
+{
+    if (!c || !E || !Ox || !Oy || !T) return GRTE_E_INVAL;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipStream_t st = c->stream;
+    if (hipMemcpyAsync(c->E, E, c->nE * sizeof(double), k, st) != hipSuccess ||
+        hipMemcpyAsync(c->Ox, Ox, c->nOx * sizeof(double), k, st) != hipSuccess ||
+        hipMemcpyAsync(c->Oy, Oy, c->nOy * sizeof(double), k, st) != hipSuccess ||
+        hipMemcpyAsync(c->T, T, c->N * sizeof(double), k, st) != hipSuccess)
+        return GRTE_E_HIP;
+    return hip_ok(hipStreamSynchronize(st));
+}
+
+grte_status grte2d_get_state(grte2d_ctx *c, double *E, double *Ox, double *Oy, double *T, int on_device)
+{
+    if (!c) return GRTE_E_INVAL;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hipStream_t st = c->stream;
+    if ((E && hipMemcpyAsync(E, c->E, c->nE * sizeof(double), k, st) != hipSuccess) ||
+        (Ox && hipMemcpyAsync(Ox, c->Ox, c->nOx * sizeof(double), k, st) != hipSuccess) ||
+        (Oy && hipMemcpyAsync(Oy, c->Oy, c->nOy * sizeof(double), k, st) != hipSuccess) ||
+        (T && hipMemcpyAsync(T, c->T, c->N * sizeof(double), k, st) != hipSuccess))
+        return GRTE_E_HIP;
+    return hip_ok(hipStreamSynchronize(st));
+}
+
+grte_status grte2d_get_stage(grte2d_ctx *c, int which, double *out, int on_device)
+{
+    if (!c || !out) return GRTE_E_INVAL;
+    const double *src = nullptr;
+    size_t n = c->N;
+    switch (which) {
+        case GRTE2D_STAGE_ESTAR: src = c->Es; n = c->nE; break;
+        case GRTE2D_STAGE_USTAR: src = c->ustar; break;
+        case GRTE2D_STAGE_D: src = c->Dv; break;
+        case GRTE2D_STAGE_RHON: src = c->rhon; break;
+        default: return GRTE_E_INVAL;
+    }
+    if (hipMemcpyAsync(out, src, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       c->stream) != hipSuccess)
+        return GRTE_E_HIP;
+    return hip_ok(hipStreamSynchronize(c->stream));
+}
+
+grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *info)
+{
+    if (!c || !(dt > 0.0) || !(eps > 0.0) || !std::isfinite(dt) || !std::isfinite(eps)) return GRTE_E_INVAL;
+    hipStream_t st = c->stream;
+    const int nbc = nblocks(c->N), nb = nblocks(c->nE);
+    grte2d_step_info inf;
+    memset(&inf, 0, sizeof(inf));
+    if (hipMemsetAsync(c->stat, 0, 8 * sizeof(int), st) != hipSuccess) return GRTE_E_HIP;
+
+    // ---- prediction (4.5)/(5.2)
+    CoefArgs ca;
+    ca.nx = c->nx;
+    ca.ny = c->ny;
+    ca.m = c->m;
+    ca.corr = 0;
+    ca.a = c->a;
+    ca.c = c->c;
+    ca.cv = c->cv;
+    ca.eps = eps;
+    ca.dt = dt;
+    ca.fe = 1.0;
+    ca.W1 = c->W1;
+    ca.T = c->T;
+    ca.sigma0 = c->sigma0;
+    ca.ax = c->ax;
+    ca.gx = c->gx;
+    ca.ay = c->ay;
+    ca.gy = c->gy;
+    ca.lam = c->lam;
+    ca.dmg = c->dmg;
+    ca.cg = c->cg;
+    ca.kco = c->kco;
+    ca.rb0 = c->rb0;
+    ca.acU = c->acU;
+    ca.beta = c->beta;
+    ca.sab = c->sab;
+    ca.ue = c->ue;
+    hipLaunchKernelGGL(coef2d_kernel, dim3(nbc), dim3(B2), 0, st, ca);
+    hipLaunchKernelGGL(rb1_kernel, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, st, c->rb1, c->T, c->m,
+                       eps * eps, (int)c->N);
+    Sys Sp = make_sys(c, 0, eps);
+    {
+        VecArgs A;
+        A.S = Sp;
+        A.n = c->nE;
+        A.En = c->E;
+        A.bv = c->bv;
+        hipLaunchKernelGGL(rhs2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+    }
+    if (hipMemcpyAsync(c->x, c->E, c->nE * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return GRTE_E_HIP;
+    if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
+    int its, state;
+    double res;
+    int floor;
+    grte_status s = krylov(c, Sp, its, state, res, floor);
+    if (s != GRTE_OK) return s;
+    inf.pred_iters = its;
+    inf.pred_converged = state == 1;
+    inf.pred_residual = res;
+    inf.pred_floor_stop = floor;
+    if (hipMemcpyAsync(c->Es, c->x, c->nE * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return GRTE_E_HIP;
+
+    // ---- correction, substep 1: Newton per cell
+    NewtArgs na;
+    na.S = Sp;
+    na.Es = c->Es;
+    na.En = c->E;
+    na.Tn = c->T;
+    na.sigma0 = c->sigma0;
+    na.beta = c->beta;
+    na.a = c->a;
+    na.c = c->c;
+    na.cv = c->cv;
+    na.dt = dt;
+    na.m = c->m;
+    na.maxit = 60;
+    na.Tnew = c->T1;
+    na.ustar = c->ustar;
+    na.Dv = c->Dv;
+    na.rhon = c->rhon;
+    na.stat = c->stat;
+    hipLaunchKernelGGL(newton2d_kernel, dim3(nb), dim3(B2), 0, st, na);
+
+    // ---- correction, substep 2 (4.11) with K^{n+1}, U^{n+1}
+    ca.corr = 1;
+    ca.fe = eps;
+    ca.T = c->T1;
+    hipLaunchKernelGGL(coef2d_kernel, dim3(nbc), dim3(B2), 0, st, ca);
+    hipLaunchKernelGGL(rb1_kernel, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, st, c->rb1, c->T1, c->m,
+                       eps, (int)c->N);
+    Sys Sc = make_sys(c, 1, eps);
+    {
+        VecArgs A;
+        A.S = Sc;
+        A.n = c->nE;
+        A.En = c->E;
+        A.bv = c->bv;
+        hipLaunchKernelGGL(rhs2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+    }
+    hipLaunchKernelGGL(xcorr0_kernel, dim3(nb), dim3(B2), 0, st, c->x, c->Es, c->acU, c->P, 1.0 / eps, c->nE);
+    if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
+    s = krylov(c, Sc, its, state, res, floor);
+    if (s != GRTE_OK) return s;
+    inf.corr_iters = its;
+    inf.corr_converged = state == 1;
+    inf.corr_residual = res;
+    inf.corr_floor_stop = floor;
+
+    // ---- projection (4.14)
+    ProjArgs pa;
+    pa.S = Sc;
+    pa.EJ = c->x;
+    pa.E1 = c->E1;
+    pa.Ox1 = c->Ox1;
+    pa.Oy1 = c->Oy1;
+    hipLaunchKernelGGL(project2d_kernel, dim3(nb), dim3(B2), 0, st, pa);
+    if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
+    std::swap(c->E, c->E1);
+    std::swap(c->Ox, c->Ox1);
+    std::swap(c->Oy, c->Oy1);
+    std::swap(c->T, c->T1);
+    int stat[8];
+    if (hipMemcpyAsync(stat, c->stat, 8 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return GRTE_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
+    inf.newton_max_iters = stat[0];
+    inf.newton_failed = stat[1];
+    inf.kstar_clamped = stat[2];
+    inf.negative_root = stat[3];
+    inf.newton_total_iters = stat[4];
+    if (info) *info = inf;
+    const bool bad = !inf.pred_converged || !inf.corr_converged || inf.newton_failed;
+    return bad ? GRTE_E_NOCONV : GRTE_OK;
+}
+
+}  // extern "C"

@@ -630,4 +630,40 @@ __device__ __forceinline__ int pred_stop(double md, double mr, float q, float qp
 }
 
 
+// -------------------------------------------------------------------------
+// scalar temperature equation (4.13): Newton with an upper bound of the root
+// -------------------------------------------------------------------------
+// g is convex and increasing for T >= 0, and its root lies below both
+// single-term roots (C/q4)^{1/4} and C/lin, C = rhs + lin Tn (each term alone
+// is non-negative), and above half the smaller of them; iterates are clamped to
+// that bound, so a start far below the root (a cold cell heated by the inflow)
+// does not overshoot by orders of magnitude and then creep back by 3/4 per
+// step.  The root and the stopping test are those of the plain iteration.
+__device__ __forceinline__ double newton_cap(double q4, double lin, double rhs, double Tn)
+{
+    const double C = rhs + lin * Tn;
+    // no positive root, or a linear equation (Newton exact in one step): no bound
+    if (!(C > 0.0) || !(q4 > 0.0)) return INFINITY;
+    // widened by 2^-50 so that rounding never puts the bound below the root
+    return fmin(sqrt(sqrt(C / q4)), C / lin) * (1.0 + 0x1p-50);
+}
+
+__device__ __forceinline__ bool newton_quartic(double T0, double Tn, double q4, double lin, double rhs, int maxit,
+                                               double &T, int &its)
+{
+    const double cap = newton_cap(q4, lin, rhs, Tn);
+    T = T0;
+    for (int k = 0; k < maxit; ++k) {
+        const double T2 = T * T;
+        const double g = q4 * T2 * T2 + lin * (T - Tn) - rhs;
+        const double dg = 4.0 * q4 * T2 * T + lin;
+        const double Tp = T;
+        T = fmin(T - g / dg, cap);
+        const double step = Tp - T;
+        ++its;
+        if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(Tn))) return true;
+    }
+    return false;
+}
+
 }  // namespace

@@ -24,12 +24,24 @@ seed (numpy PCG64, seed 18110000 + configuration number).
             taking either value with probability 1/2, eps = 1e-4, the initial
             and inflow data of config 1, dt = 0.5 dx.
 
+  config 3  2-D square [0,1]^2, 1024 x 1024 cells, 32 equally spaced circle
+            directions, two-material opacity: the cell takes the value of the
+            nearest of 64 seeded sites (Voronoi), each site sigma in {1, 100}
+            with probability 1/2, m = 0, eps = 1e-3, T = 1e-2 and I = ac T^4
+            initially, isotropic inflow ac on the edge x = 0, vacuum elsewhere,
+            dt = 0.5 dx.
+  config 5  the same set-up on 512 x 512 cells, 64 directions, sigma in
+            {1, 1000}, eps = 1e-4 (the learned-guess case).
+
   marshak   dimensional Marshak wave of the paper's last example: eps = 1,
             c = 29.98 cm/ns, a = 0.01372 GJ/(cm^3 keV^4), Cv = 0.3 GJ/(cm^3 keV),
             sigma = 300 / T^3 cm^-1, x in [0, 0.02] cm, T(x, 0) =
             (1 - tanh((x - 0.0024) 1000)) / 2 keV in equilibrium (I = a c T^4),
             T = 1 keV at x = 0 imposed as the isotropic inflow a c 1^4, the
             right-end inflow a c T(0.02, 0)^4; dt in ns (1.6e-12 s = 1.6e-3 ns).
+
+The 2-D direction set is theta_k = 2 pi (k + 1/2)/N_v; the pairs are k < N_v/2
+(eta > 0), each with weight 2/N_v.
 
 The velocity grid (Gauss-Legendre pairs: positive nodes by increasing mu,
 weight of +mu on [-1, 1], so the weights sum to one) is part of the input:
@@ -208,3 +220,103 @@ def marshak(N=100, nv=16, dt=1.6e-3, steps=100):
     return Workload(name=f"marshak(N={N},dt={dt:g}ns)", N=N, nv=nv, m=3, eps=1.0, dt=dt, steps=steps,
                     a=a, c=c, Cv=Cv, L=L, mu=mu, omega=om, sigma0=np.full(N, 300.0), T=T, E=E, O=O,
                     bL=np.full(P, a * c * 1.0), bR=np.full(P, a * c * TR ** 4))
+
+
+# ---------------------------------------------------------------------------
+# 2-D
+# ---------------------------------------------------------------------------
+def circle_pairs(nv):
+    """(mu, eta, omega) of the nv/2 pairs of nv equally spaced directions."""
+    k = np.arange(int(nv) // 2)
+    th = 2.0 * np.pi * (k + 0.5) / int(nv)
+    return np.cos(th), np.sin(th), np.full(k.size, 2.0 / int(nv))
+
+
+@dataclass
+class Workload2D:
+    name: str
+    nx: int
+    ny: int
+    nv: int
+    m: int
+    eps: float
+    dt: float
+    steps: int
+    a: float = 1.0
+    c: float = 1.0
+    Cv: float = 1.0
+    Lx: float = 1.0
+    Ly: float = 1.0
+    mu: np.ndarray = field(default=None, repr=False)
+    eta: np.ndarray = field(default=None, repr=False)
+    omega: np.ndarray = field(default=None, repr=False)
+    sigma0: np.ndarray = field(default=None, repr=False)   # (ny, nx)
+    T: np.ndarray = field(default=None, repr=False)        # (ny, nx)
+    E: np.ndarray = field(default=None, repr=False)        # (ny, nx, P)
+    Ox: np.ndarray = field(default=None, repr=False)       # (ny, nx+1, P)
+    Oy: np.ndarray = field(default=None, repr=False)       # (ny+1, nx, P)
+    b: np.ndarray = field(default=None, repr=False)        # (4, P)
+
+    @property
+    def P(self):
+        return self.nv // 2
+
+    def cell_angle_updates(self):
+        return self.nx * self.ny * self.nv
+
+
+def voronoi_two_material(nx, ny, values, seed, sites=64):
+    """Cell field taking, per cell, the value of the nearest of `sites` seeded
+    points in [0,1]^2; each site holds values[0] or values[1] with probability 1/2."""
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, 1.0, (sites, 2))
+    val = np.where(rng.uniform(0.0, 1.0, sites) < 0.5, values[0], values[1])
+    xc = (np.arange(nx) + 0.5) / nx
+    out = np.empty((ny, nx))
+    for iy in range(ny):
+        yc = (iy + 0.5) / ny
+        d2 = (xc[:, None] - pts[None, :, 0]) ** 2 + (yc - pts[None, :, 1]) ** 2
+        out[iy] = val[np.argmin(d2, axis=1)]
+    return out
+
+
+def _square(name, n, nv, m, eps, steps, sigma0, T_in=1e-2, b_hot=1.0, a=1.0, c=1.0, Cv=1.0, cfl=0.5):
+    mu, eta, om = circle_pairs(nv)
+    P = nv // 2
+    acT = a * c * T_in ** 4
+    b = np.zeros((4, P))
+    b[0] = a * c * b_hot ** 4
+    return Workload2D(name=name, nx=n, ny=n, nv=nv, m=m, eps=eps, dt=cfl / n, steps=steps, a=a, c=c, Cv=Cv,
+                      mu=mu, eta=eta, omega=om, sigma0=np.asarray(sigma0, dtype=np.float64),
+                      T=np.full((n, n), T_in), E=np.full((n, n, P), acT),
+                      Ox=np.zeros((n, n + 1, P)), Oy=np.zeros((n + 1, n, P)), b=b)
+
+
+def config3(n=1024, nv=32, steps=500):
+    """2-D, 1024^2 cells, 32 directions, Voronoi sigma in {1, 100}, eps = 1e-3."""
+    sig = voronoi_two_material(n, n, (1.0, 100.0), SEED_BASE + 3)
+    return _square(f"config3(n={n})", n, nv, 0, 1e-3, steps, sig)
+
+
+def config5(n=512, nv=64, steps=200):
+    """2-D, 512^2 cells, 64 directions, Voronoi sigma in {1, 1000}, eps = 1e-4."""
+    sig = voronoi_two_material(n, n, (1.0, 1000.0), SEED_BASE + 5)
+    return _square(f"config5(n={n})", n, nv, 0, 1e-4, steps, sig)
+
+
+def random_state_2d(nx, ny, nv, seed, m=3, eps=1e-2, T_lo=0.1, T_hi=1.0, anisotropy=0.2, sigma=(0.5, 2.0)):
+    """A generic 2-D state with seeded temperature, opacity and inflow (not one
+    of the named configurations); E deviates from a T^4 by anisotropy*min(1, eps)."""
+    rng = np.random.default_rng(SEED_BASE + 2000 + seed)
+    mu, eta, om = circle_pairs(nv)
+    P = nv // 2
+    T = rng.uniform(T_lo, T_hi, (ny, nx))
+    dev = anisotropy * min(1.0, eps)
+    E = (T ** 4)[:, :, None] * (1.0 + dev * rng.uniform(-1, 1, (ny, nx, P)))
+    osc = (T ** 4).max() * dev / max(eps, 1e-300) * min(1.0, eps)
+    Ox = osc * rng.uniform(-1, 1, (ny, nx + 1, P))
+    Oy = osc * rng.uniform(-1, 1, (ny + 1, nx, P))
+    sig = rng.uniform(sigma[0], sigma[1], (ny, nx))
+    b = rng.uniform(0.0, 1.0, (4, P))
+    return Workload2D(name=f"random2d({seed})", nx=nx, ny=ny, nv=nv, m=m, eps=eps, dt=0.5 / max(nx, ny),
+                      steps=1, mu=mu, eta=eta, omega=om, sigma0=sig, T=T, E=E, Ox=Ox, Oy=Oy, b=b)

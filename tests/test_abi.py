@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "grte.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(grte_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(grte(?:2d)?_[a-z_0-9]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -146,3 +146,45 @@ def test_diffusion_invalid_arguments(lib):
     assert lib.grte_diff_create(ctypes.byref(big), ctypes.byref(h)) == -5
     assert lib.grte_diff_step(None, 0.1, 0, 0, -1.0, None) == -1
     assert lib.grte_diff_destroy(None) == 0
+
+
+def test_2d_host_checks(lib):
+    """grte2d_* argument checks that return before any device work."""
+    from paper_1811_05579_amd._lib import Problem2D
+    mu, eta, om = (np.zeros(4) for _ in range(3))
+    assert lib.grte2d_circle_directions(8, mu.ctypes.data, eta.ctypes.data, om.ctypes.data) == 0
+    for bad in (2, 6, 130):
+        assert lib.grte2d_circle_directions(bad, mu.ctypes.data, eta.ctypes.data, om.ctypes.data) == -1
+    h = ctypes.c_void_p()
+    for nx, ny, P in ((1, 4, 4), (4, 1, 4), (4, 4, 3), (4, 4, 128), (4, 4, 0)):
+        pb = Problem2D(nx, ny, P, 1.0, 1.0, 1.0, 1.0, 1.0, 0)
+        assert lib.grte2d_create(ctypes.byref(pb), mu.ctypes.data, eta.ctypes.data, om.ctypes.data,
+                                 ctypes.byref(h)) == -5
+    pb = Problem2D(4, 4, 4, 1.0, 1.0, 1.0, 1.0, 1.0, 2)
+    assert lib.grte2d_create(ctypes.byref(pb), mu.ctypes.data, eta.ctypes.data, om.ctypes.data,
+                             ctypes.byref(h)) == -1
+    # a direction parallel to an edge (eta = 0) or a zero weight is rejected
+    pb = Problem2D(4, 4, 4, 1.0, 1.0, 1.0, 1.0, 1.0, 0)
+    mu[:], eta[:], om[:] = 0.5, 0.0, 0.25
+    assert lib.grte2d_create(ctypes.byref(pb), mu.ctypes.data, eta.ctypes.data, om.ctypes.data,
+                             ctypes.byref(h)) == -1
+    assert lib.grte2d_create(None, mu.ctypes.data, eta.ctypes.data, om.ctypes.data, ctypes.byref(h)) == -1
+    for f in ("grte2d_step",):
+        assert getattr(lib, f)(None, 0.1, 0.1, None) == -1
+    assert lib.grte2d_set_solver(None, 1e-14, 10) == -1
+    assert lib.grte2d_set_inflow(None, None) == -1
+    assert lib.grte2d_set_opacity(None, None, 0) == -1
+    assert lib.grte2d_get_stage(None, 0, None, 0) == -1
+    assert lib.grte2d_destroy(None) == 0
+
+
+def test_2d_directions_match_numpy(lib):
+    from oracle.quadrature import circle_pairs
+    for nv in (4, 8, 32, 64, 128):
+        P = nv // 2
+        mu, eta, om = np.zeros(P), np.zeros(P), np.zeros(P)
+        assert lib.grte2d_circle_directions(nv, mu.ctypes.data, eta.ctypes.data, om.ctypes.data) == 0
+        m2, e2, o2 = circle_pairs(nv)
+        np.testing.assert_allclose(mu, m2, rtol=0, atol=2.3e-16)
+        np.testing.assert_allclose(eta, e2, rtol=0, atol=2.3e-16)
+        assert np.array_equal(om, o2)
