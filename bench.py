@@ -18,6 +18,12 @@ stream) and the CPU oracle timed on a bounded sample of the same workload.
 (N ~ U{64..2048}, N_v in {8,16,32,64}, eps = 10^U[-5,0], sigma0 = 10^U[-1,2],
 sigma0/T^3, dt = 0.5/N) advanced by one persistent kernel per step, replayed
 as a captured HIP graph after the autotuner has chosen the tiles and grid.
+
+--workload config3 (config5) measures the 2-D step: 1024^2 cells and 32
+directions, two-material Voronoi opacity sigma in {1, 100}, eps = 1e-3
+(512^2, 64 directions, {1, 1000}, 1e-4), cold start with a hot inflow on the
+edge x = 0, dt = 0.5 dx, FP64; the step's two Krylov solves run on the GPU,
+the roofline entry is their matrix-free operator kernel.
 """
 import argparse
 import json
@@ -209,13 +215,131 @@ def main_batch(args):
     print(json.dumps(line))
 
 
+def op2d_algorithmic_bytes(N, P):
+    """Bytes the 2-D operator kernel must move at least once per launch: read
+    the search direction and the shadow residual, write the product (N*P each,
+    FP64), and read five N-sized cell and face coefficient arrays."""
+    return 8 * (3 * N * P + 5 * N)
+
+
+def cpu_baseline_2d(w, budget_s=20.0, n=32):
+    """Oracle (as it stands, one thread) on an n x n grid with the workload's
+    directions, opacity law and values (its own seeded Voronoi field), eps and
+    CFL, from the cold start, stepped until the time budget is spent."""
+    from oracle.ap1d import Physics
+    from oracle import ap2d
+    from paper_1811_05579_amd.workloads import voronoi_two_material, _square
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)
+    except Exception:   # pragma: no cover
+        limit = None
+    vals = (1.0, float(w.sigma0.max()))
+    sw = _square("sample", n, w.nv, w.m, w.eps, 1, voronoi_two_material(n, n, vals, 18110000 + 3))
+    g = ap2d.Grid2D(n, n)
+    ph = Physics(a=sw.a, c=sw.c, Cv=sw.Cv, eps=sw.eps, dt=sw.dt, m=sw.m)
+    E, Ox, Oy, T = sw.E, sw.Ox, sw.Oy, sw.T
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        r = ap2d.ap_step(g, E, Ox, Oy, T, sw.sigma0, sw.mu, sw.eta, sw.omega, sw.b, ph)
+        E, Ox, Oy, T = r["E"], r["Ox"], r["Oy"], r["T"]
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    if limit is not None and hasattr(limit, "unregister"):
+        limit.unregister()
+    upd = k * sw.cell_angle_updates()
+    return {"value": upd / el, "unit": "cell·angle updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} oracle steps of a {n}x{n}-cell grid with the workload's {w.nv} directions, "
+                      f"opacity values, eps and CFL from the cold start ({upd} cell-angle updates), {el:.1f} s"}
+
+
+def main_2d(args):
+    import torch
+    from paper_1811_05579_amd import Grte2D
+    from paper_1811_05579_amd.workloads import config3, config5
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = config3() if args.workload == "config3" else config5()
+    g = Grte2D(w.nx, w.ny, w.mu, w.eta, w.omega, lx=w.Lx, ly=w.Ly, a=w.a, c=w.c, cv=w.Cv, opacity_law=w.m)
+    stream = torch.cuda.Stream()
+    g.set_stream(stream)
+    g.set_opacity(w.sigma0)
+    g.set_inflow(w.b)
+    g.set_state(w.E, w.Ox, w.Oy, w.T)
+    for _ in range(args.warmup):
+        g.step(w.dt, w.eps)
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    t0 = time.perf_counter()
+    its = []
+    for _ in range(args.steps):
+        d = g.step(w.dt, w.eps, info=True)
+        its.append((d["pred_iters"], d["corr_iters"], d["status"]))
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    elapsed_ms = start.elapsed_time(stop)
+    ms, cnt = g.read_timing()
+    N, P = w.nx * w.ny, w.P
+    launch_s = ms / max(cnt, 1) / 1e3
+    achieved = op2d_algorithmic_bytes(N, P) / launch_s / 1e9
+    value = w.cell_angle_updates() * args.steps / (elapsed_ms / 1e3)
+    line = {
+        "metric": "cell_angle_updates_per_s",
+        "value": value,
+        "unit": "cell·angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Voronoi opacity, analytic cold-start/hot-inflow data)",
+        "config": {
+            "workload": (f"2D square {w.nx}x{w.ny} cells, {w.nv} equally spaced directions, two-material "
+                         f"Voronoi sigma in {{1, {w.sigma0.max():g}}} (64 sites), eps={w.eps:g}, T0=1e-2, hot "
+                         "inflow on x=0, dt=0.5dx, FP64 storage and arithmetic, staggered parity grid"),
+            "steps_from_cold_start": [args.warmup, args.warmup + args.steps],
+            "pred_iters_mean": sum(i[0] for i in its) / len(its), "pred_iters_max": max(i[0] for i in its),
+            "corr_iters_mean": sum(i[1] for i in its) / len(its), "status_worst": min(i[2] for i in its),
+            "host_wall_s": wall,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "apply2d_kernel<1> (matrix-free operator product of the Krylov iteration)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": TRAFFIC.get((args.workload, "fp64"), (None, None))[0],
+            "traffic_source": TRAFFIC.get((args.workload, "fp64"), (None, None))[1],
+            "bytes_per_launch": op2d_algorithmic_bytes(N, P),
+            "avg_launch_us": launch_s * 1e6,
+            "timed_launches": cnt,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_2d(w)
+    g.close()
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["config2", "config4"], default="config2")
+    ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5"], default="config2")
     ap.add_argument("--storage", choices=["fp64", "fp32"], default=None,
                     help="intensity storage (default: fp64 for config2, fp32 for config4, "
                          "as each workload is defined)")
@@ -226,6 +350,9 @@ def main():
         sys.exit(2)
     if args.workload == "config4":
         main_batch(args)
+        return
+    if args.workload in ("config3", "config5"):
+        main_2d(args)
         return
 
     import torch

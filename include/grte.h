@@ -437,7 +437,8 @@ grte_status grte_batch_read_timing(grte_batch *b, double *total_ms, int *count);
 typedef struct grte2d_ctx grte2d_ctx;
 
 typedef struct grte2d_problem {
-    int nx, ny;        /* cells along x and y, each >= 2; nx*ny <= 2^28          */
+    int nx, ny;        /* cells along x and y, each >= 2; nx*ny <= 2^28 and      
+                          (nx+1)*(ny+1)*npairs < 2^31 (32-bit indexing)        */
     int npairs;        /* P: a power of two, 1 <= P <= 64                        */
     double lx, ly;     /* rectangle sides > 0                                    */
     double a, c, cv;   /* radiation constant, speed of light, heat capacity > 0  */
@@ -499,6 +500,16 @@ grte_status grte2d_set_stream(grte2d_ctx *ctx, void *hip_stream);
  * 1e-14. */
 grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
 
+/* The Krylov preconditioner inverts each cell's P x P block (the direction-
+ * diagonal part plus the rank-one angular coupling of (4.5c)) and, in the
+ * prediction, adds an isotropic correction: `steps` Chebyshev steps (default
+ * 10; 0 = none, at most 64) on the operator's angular average over isotropic
+ * fields, a 5-point diffusion operator -- the mode that the angular coupling
+ * leaves nearly undamped in optically thick cells (the diffusion limit of
+ * Section 3).  The correction's systems have no angular coupling and use the
+ * block inverse alone. */
+grte_status grte2d_set_isotropic_correction(grte2d_ctx *ctx, int steps);
+
 /* Opacity coefficient per cell, sigma0[nx*ny] >= 0. */
 grte_status grte2d_set_opacity(grte2d_ctx *ctx, const double *sigma0, int on_device);
 
@@ -516,6 +527,14 @@ grte_status grte2d_get_state(grte2d_ctx *ctx, double *E, double *Ox, double *Oy,
  * reads its convergence flag); fills *info when non-NULL.  GRTE_E_NOCONV (state
  * still advanced) if a solve missed its tolerance or a Newton solve its cap. */
 grte_status grte2d_step(grte2d_ctx *ctx, double dt, double eps, grte2d_step_info *info);
+
+/* Timing of the operator kernel (the matrix-free product inside the Krylov
+ * iterations, the step's dominant kernel): with on != 0, HIP events on the
+ * context's stream bracket the first product of every batch of eight
+ * iterations; grte2d_read_timing returns the summed milliseconds and the
+ * number of timed launches since the last grte2d_set_profiling call. */
+grte_status grte2d_set_profiling(grte2d_ctx *ctx, int on);
+grte_status grte2d_read_timing(grte2d_ctx *ctx, double *ms, int *count);
 
 /* A stage of the last step (GRTE2D_STAGE_*). */
 grte_status grte2d_get_stage(grte2d_ctx *ctx, int which, double *out, int on_device);

@@ -595,6 +595,19 @@ class Grte2D:
                                                              Oy.ctypes.data, T.ctypes.data, 0))
         return E, Ox, Oy, T
 
+    def set_isotropic_correction(self, steps=10):
+        """Chebyshev steps of the preconditioner's isotropic (diffusion) correction; 0 = off."""
+        check("grte2d_set_isotropic_correction", self._lib.grte2d_set_isotropic_correction(self._h, int(steps)))
+
+    def set_profiling(self, on=True):
+        check("grte2d_set_profiling", self._lib.grte2d_set_profiling(self._h, int(bool(on))))
+
+    def read_timing(self):
+        """(total ms, launches) of the timed operator-kernel launches."""
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        check("grte2d_read_timing", self._lib.grte2d_read_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def get_stage(self, name):
         shape = (self.ny, self.nx, self.P) if name == "E_star" else (self.ny, self.nx)
         out = np.empty(shape)

@@ -151,6 +151,9 @@ _SIGS = {
     "grte2d_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     "grte2d_step": (c_int, [c_void_p, c_double, c_double, ctypes.POINTER(StepInfo2D)]),
     "grte2d_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
+    "grte2d_set_profiling": (c_int, [c_void_p, c_int]),
+    "grte2d_set_isotropic_correction": (c_int, [c_void_p, c_int]),
+    "grte2d_read_timing": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
 }
 
 _lib = None

@@ -43,6 +43,7 @@ constexpr int B2 = 256;        // threads per block of the (cell, pair) kernels
 constexpr int MAXB = 2048;     // blocks of the grid-stride kernels = partial sums per dot product
 constexpr int CHUNK = 8;       // BiCGStab iterations enqueued between convergence checks
 constexpr int KRY_RESTARTS = 6;      // restarts from the true residual per solve
+constexpr double CHEB2_A = 0.02, CHEB2_B = 2.0;   // eigenvalue interval of the Jacobi-scaled isotropic operator
 constexpr double KRY_FLOOR = 64.0;   // floor stop: true residual within this factor of its rounding level
 
 // scalars of the Krylov solve, in device memory
@@ -50,8 +51,9 @@ enum { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_RV, S_TS, S_TT, S_MM, 
 enum { F_STATE = 0, F_ITS, F_NF };          // F_STATE: 0 running, 1 converged, 2 breakdown
 
 struct Sys {
-    int nx, ny, P, corr;
+    int nx, ny, P, lgP, corr;
     double dx, dy, eps, fe, W1;
+    double idx, idy, inx, k2;            // 1/dx, 1/dy, 1/nx, 2/eps
     const double *mu, *eta, *om, *b;     // pairs and inflow b[4*P]
     const double *E0, *Ox0, *Oy0;        // E^n, O^n
     const double *ax, *gx, *ay, *gy;     // face alpha, gamma (gamma includes fe)
@@ -59,6 +61,21 @@ struct Sys {
     const double *rb1, *rb0, *acU;       // rhs = rb1 E^n_p + rb0; acU (correction's known part)
     const double *sab, *ue;              // residual in difference form (see residual_at)
 };
+
+// (iy, ix) of cell j without an integer division: the binary64 product is off
+// by at most one for j < 2^31
+__device__ __forceinline__ void cell_yx(const Sys &S, int j, int &iy, int &ix)
+{
+    iy = (int)((double)j * S.inx);
+    ix = j - iy * S.nx;
+    if (ix < 0) {
+        --iy;
+        ix += S.nx;
+    } else if (ix >= S.nx) {
+        ++iy;
+        ix -= S.nx;
+    }
+}
 
 __device__ __forceinline__ double group_sum(double v, int P)
 {
@@ -85,7 +102,7 @@ __device__ __forceinline__ Nb load_nb(const double *x, int nx, int ny, int iy, i
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) n.v[a][k] = x[((size_t)r[a] * nx + c[k]) * P + p];
+        for (int k = 0; k < 3; ++k) n.v[a][k] = x[(r[a] * nx + c[k]) * P + p];
     return n;
 }
 
@@ -98,8 +115,8 @@ __device__ __forceinline__ Grad face_grad(const Nb &n, double mu, double eta, co
 {
     // centred differences, one-sided next to a wall (the clamped neighbourhood
     // turns the centred formula into the one-sided one with the weight 1/h)
-    const double wy = (iy == 0 || iy == S.ny - 1) ? 1.0 / S.dy : 0.5 / S.dy;
-    const double wx = (ix == 0 || ix == S.nx - 1) ? 1.0 / S.dx : 0.5 / S.dx;
+    const double wy = (iy == 0 || iy == S.ny - 1) ? S.idy : 0.5 * S.idy;
+    const double wx = (ix == 0 || ix == S.nx - 1) ? S.idx : 0.5 * S.idx;
     double dy[3], dx[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -107,10 +124,10 @@ __device__ __forceinline__ Grad face_grad(const Nb &n, double mu, double eta, co
         dx[k] = (n.v[k][2] - n.v[k][0]) * wx;
     }
     Grad g;
-    g.l = mu * (n.v[1][1] - n.v[1][0]) / S.dx + eta * 0.5 * (dy[0] + dy[1]);
-    g.r = mu * (n.v[1][2] - n.v[1][1]) / S.dx + eta * 0.5 * (dy[1] + dy[2]);
-    g.b = eta * (n.v[1][1] - n.v[0][1]) / S.dy + mu * 0.5 * (dx[0] + dx[1]);
-    g.t = eta * (n.v[2][1] - n.v[1][1]) / S.dy + mu * 0.5 * (dx[1] + dx[2]);
+    g.l = mu * (n.v[1][1] - n.v[1][0]) * S.idx + eta * 0.5 * (dy[0] + dy[1]);
+    g.r = mu * (n.v[1][2] - n.v[1][1]) * S.idx + eta * 0.5 * (dy[1] + dy[2]);
+    g.b = eta * (n.v[1][1] - n.v[0][1]) * S.idy + mu * 0.5 * (dx[0] + dx[1]);
+    g.t = eta * (n.v[2][1] - n.v[1][1]) * S.idy + mu * 0.5 * (dx[1] + dx[2]);
     return g;
 }
 
@@ -122,8 +139,8 @@ __device__ __forceinline__ void faces(const Sys &S, int iy, int ix, int p, const
 {
     const int nx = S.nx, ny = S.ny, P = S.P;
     const double mu = S.mu[p], eta = S.eta[p];
-    const size_t fl = (size_t)iy * (nx + 1) + ix, fb = (size_t)iy * nx + ix;
-    const size_t fr = fl + 1, ft = fb + nx;
+    const int fl = iy * (nx + 1) + ix, fb = iy * nx + ix;
+    const int fr = fl + 1, ft = fb + nx;
     O.l = O.r = O.b = O.t = 0.0;
     if (LIN) {
         const Grad g = face_grad(*X, mu, eta, S, iy, ix);
@@ -152,7 +169,7 @@ __device__ __forceinline__ void faces(const Sys &S, int iy, int ix, int p, const
     // inflow relations: E_cell + s (eps/2)(O_edge + O_opposite) = b, s = +1 when
     // +Omega_p enters through that edge
     const double xc = LIN ? X->v[1][1] : 0.0;
-    const double k2 = 2.0 / S.eps;
+    const double k2 = S.k2;
     // (the difference inflow - cell value is formed first: both terms carry 2/eps)
     auto edge = [&](int e, double s) {
         double d = 0.0;
@@ -170,7 +187,7 @@ __device__ __forceinline__ void faces(const Sys &S, int iy, int ix, int p, const
 
 __device__ __forceinline__ double divergence(const Sys &S, const Grad &O, int p)
 {
-    return S.mu[p] * (O.r - O.l) / S.dx + S.eta[p] * (O.t - O.b) / S.dy;
+    return S.mu[p] * (O.r - O.l) * S.idx + S.eta[p] * (O.t - O.b) * S.idy;
 }
 
 // ---------------------------------------------------------------------------
@@ -256,6 +273,11 @@ struct VecArgs {
     int *fl;                   // flags
     double tol;
     int maxit;
+    // isotropic (diffusion) correction of the preconditioner: the preconditioned
+    // vectors are ph + dP[cell] and sh + dS[cell]; yP, yS receive sum_p omega_p p_p,
+    // sum_p omega_p s_p (null: no correction)
+    const double *dP, *dS;
+    double *yP, *yS;
 };
 
 __device__ __forceinline__ void block_sums(double *vals, int k, double *part)
@@ -280,30 +302,40 @@ __global__ void __launch_bounds__(B2) rhs2d_kernel(VecArgs A)
 {
     const Sys &S = A.S;
     const int P = S.P;
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
-        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
-        const int iy = j / S.nx, ix = j - iy * S.nx;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
+        const int j = t >> S.lgP, p = t & (P - 1);
+        int iy, ix;
+        cell_yx(S, j, iy, ix);
         Grad O;
         faces<true, false>(S, iy, ix, p, nullptr, O);
         A.bv[t] = S.rb1[j] * A.En[t] + S.rb0[j] - S.kco[j] * divergence(S, O, p);
     }
 }
 
-// y = A x for the (cell, pair) of thread t
-__device__ __forceinline__ double apply_at(const Sys &S, const double *x, size_t t, int j, int p)
+// y = A (x + 1 d) for the (cell, pair) of thread t; d (null: none) is a per-cell
+// isotropic shift, which the angular coupling does not see
+__device__ __forceinline__ double apply_at(const Sys &S, const double *x, const double *d, int t, int j, int p)
 {
     const int P = S.P;
-    const int iy = j / S.nx, ix = j - iy * S.nx;
-    const Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
+    int iy, ix;
+    cell_yx(S, j, iy, ix);
+    Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
+    const double xp = X.v[1][1];
+    if (d) {
+        const Nb D = load_nb(d, S.nx, S.ny, iy, ix, 1, 0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) X.v[a][c] += D.v[a][c];
+    }
     Grad O;
     faces<false, true>(S, iy, ix, p, &X, O);
-    const double xp = X.v[1][1];
     // W1 x_p - sum_q omega_q x_q, referred to the cell's first pair to keep it
     // exact for a nearly isotropic x
     const double xr = group_lane0(xp, P);
     const double w = S.om[p];
     const double cpl = S.W1 * (xp - xr) - group_sum(w * (xp - xr), P);
-    return S.dmg[j] * xp + S.cg[j] * cpl + S.kco[j] * divergence(S, O, p);
+    return S.dmg[j] * X.v[1][1] + S.cg[j] * cpl + S.kco[j] * divergence(S, O, p);
 }
 
 // b - A x evaluated from the full face values and differences of nearly equal
@@ -313,11 +345,12 @@ __device__ __forceinline__ double apply_at(const Sys &S, const double *x, size_t
 //   prediction  K eps^2 (E^n_p - x_p) + s (a c U^n - x_p) - g (1 - W1) x_p
 //               - g (W1 x_p - sum_q omega_q x_q) - k div O(x),   s = sigma0 c dt / (1 + ac beta)
 //   correction  K eps (E^n_p - a c U - eps x_p) - sigma0 c dt x_p - k div O(x)
-__device__ __forceinline__ double residual_at(const Sys &S, const double *En, const double *x, size_t t, int j,
+__device__ __forceinline__ double residual_at(const Sys &S, const double *En, const double *x, int t, int j,
                                               int p, double &mag)
 {
     const int P = S.P;
-    const int iy = j / S.nx, ix = j - iy * S.nx;
+    int iy, ix;
+    cell_yx(S, j, iy, ix);
     const Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
     Grad O;
     faces<true, true>(S, iy, ix, p, &X, O);
@@ -334,13 +367,13 @@ __device__ __forceinline__ double residual_at(const Sys &S, const double *En, co
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) xm = fmax(xm, fabs(X.v[a][c]));
-    const size_t fl = (size_t)iy * (S.nx + 1) + ix, fb = (size_t)iy * S.nx + ix;
+    const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
     const double gsum = S.gx[fl] + S.gx[fl + 1] + S.gy[fb] + S.gy[fb + S.nx];
-    const double grad_bound = 2.0 * (fabs(mu) / S.dx + fabs(eta) / S.dy) * xm;
-    const double k2 = 2.0 / S.eps;
+    const double grad_bound = 2.0 * (fabs(mu) * S.idx + fabs(eta) * S.idy) * xm;
+    const double k2 = S.k2;
     const double edge_bound = ((ix == 0 || ix == S.nx - 1) + (iy == 0 || iy == S.ny - 1)) * k2 *
                               (4.0 * S.fe * xm + fabs(S.ue[j]));
-    const double dmag = fabs(k) * (fabs(mu) / S.dx + fabs(eta) / S.dy) *
+    const double dmag = fabs(k) * (fabs(mu) * S.idx + fabs(eta) * S.idy) *
                         (fabs(O.l) + fabs(O.r) + fabs(O.b) + fabs(O.t) + gsum * grad_bound + edge_bound);
     if (S.corr) {
         const double a1 = S.rb1[j] * ((En[t] - S.ue[j]) - S.eps * xp), a2 = S.sab[j] * xp;
@@ -366,8 +399,8 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
     const Sys &S = A.S;
     const int P = S.P;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
-        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
+        const int j = t >> A.S.lgP, p = t & (P - 1);
         if (MODE == 0) {
             double mag;
             const double rr = residual_at(S, A.En, A.x, t, j, p, mag);
@@ -377,11 +410,11 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
             acc[1] += A.bv[t] * A.bv[t];
             acc[2] += mag * mag;
         } else if (MODE == 1) {
-            const double y = apply_at(S, A.ph, t, j, p);
+            const double y = apply_at(S, A.ph, A.dP, t, j, p);
             A.v[t] = y;
             acc[0] += A.r0[t] * y;
         } else {
-            const double y = apply_at(S, A.sh, t, j, p);
+            const double y = apply_at(S, A.sh, A.dS, t, j, p);
             A.t[t] = y;
             const double sv = A.s[t];
             acc[0] += y * sv;
@@ -395,28 +428,29 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
 __device__ __forceinline__ double precond_at(const Sys &S, double y, int j, int p)
 {
     const int P = S.P;
-    const int iy = j / S.nx, ix = j - iy * S.nx;
+    int iy, ix;
+    cell_yx(S, j, iy, ix);
     const double mu = S.mu[p], eta = S.eta[p];
-    const double mx = mu * mu / (S.dx * S.dx), my = eta * eta / (S.dy * S.dy);
-    const size_t fl = (size_t)iy * (S.nx + 1) + ix, fb = (size_t)iy * S.nx + ix;
+    const double mx = mu * mu * S.idx * S.idx, my = eta * eta * S.idy * S.idy;
+    const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
     const double gl = S.gx[fl], gr = S.gx[fl + 1], gb = S.gy[fb], gt = S.gy[fb + S.nx];
     // diagonal of k div O(X) with respect to X_cell (the compact terms; an edge
     // face doubles the opposite face and adds the inflow term 2|Omega_n| fe/(eps h))
     double tr = 0.0;
-    const double k2 = 2.0 * S.fe / S.eps;
-    if (ix == 0) tr += 2.0 * gr * mx + k2 * fabs(mu) / S.dx;
-    else if (ix == S.nx - 1) tr += 2.0 * gl * mx + k2 * fabs(mu) / S.dx;
+    const double k2 = S.k2 * S.fe;
+    if (ix == 0) tr += 2.0 * gr * mx + k2 * fabs(mu) * S.idx;
+    else if (ix == S.nx - 1) tr += 2.0 * gl * mx + k2 * fabs(mu) * S.idx;
     else tr += (gl + gr) * mx;
-    if (iy == 0) tr += 2.0 * gt * my + k2 * fabs(eta) / S.dy;
-    else if (iy == S.ny - 1) tr += 2.0 * gb * my + k2 * fabs(eta) / S.dy;
+    if (iy == 0) tr += 2.0 * gt * my + k2 * fabs(eta) * S.idy;
+    else if (iy == S.ny - 1) tr += 2.0 * gb * my + k2 * fabs(eta) * S.idy;
     else tr += (gb + gt) * my;
-    const double d = S.lam[j] + S.kco[j] * tr;
+    const double id = 1.0 / (S.lam[j] + S.kco[j] * tr);
     const double w = S.om[p];
-    const double u = y / d;
+    const double u = y * id;
     const double s1 = group_sum(w * u, P);
-    const double s2 = group_sum(w / d, P);
+    const double s2 = group_sum(w * id, P);
     const double g = S.cg[j];
-    return u + (g * s1 / (1.0 - g * s2)) / d;
+    return u + g * s1 / (1.0 - g * s2) * id;
 }
 
 // p = r + beta (p - omega v); ph = B^{-1} p
@@ -425,11 +459,15 @@ __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
     if (A.fl[F_STATE] != 0) return;
     const double beta = A.sc[S_BETA], omega = A.sc[S_OMEGA];
     const int P = A.S.P;
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
-        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
+        const int j = t >> A.S.lgP, p = t & (P - 1);
         const double pv = A.r[t] + beta * (A.p[t] - omega * A.v[t]);
         A.p[t] = pv;
         A.ph[t] = precond_at(A.S, pv, j, p);
+        if (A.yP) {
+            const double y = group_sum(A.S.om[p] * pv, P);
+            if (p == 0) A.yP[j] = y;
+        }
     }
 }
 
@@ -439,12 +477,16 @@ __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
     if (A.fl[F_STATE] != 0) return;
     const double alpha = A.sc[S_ALPHA];
     const int P = A.S.P;
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
-        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
+        const int j = t >> A.S.lgP, p = t & (P - 1);
         const double sv = A.r[t] - alpha * A.v[t];
         A.s[t] = sv;
         A.sh[t] = precond_at(A.S, sv, j, p);
-        A.x[t] += alpha * A.ph[t];
+        A.x[t] += alpha * (A.ph[t] + (A.dP ? A.dP[j] : 0.0));
+        if (A.yS) {
+            const double y = group_sum(A.S.om[p] * sv, P);
+            if (p == 0) A.yS[j] = y;
+        }
     }
 }
 
@@ -453,15 +495,90 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double omega = A.sc[S_OMEGA];
+    const int P = A.S.P;
     double acc[2] = {0.0, 0.0};
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < A.n; t += (size_t)gridDim.x * B2) {
-        A.x[t] += omega * A.sh[t];
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
+        A.x[t] += omega * (A.sh[t] + (A.dS ? A.dS[t >> A.S.lgP] : 0.0));
         const double rv = A.s[t] - omega * A.t[t];
         A.r[t] = rv;
         acc[0] += A.r0[t] * rv;
         acc[1] += rv * rv;
     }
     block_sums(acc, 2, A.part);
+}
+
+// ---------------------------------------------------------------------------
+// isotropic correction of the preconditioner: D z = y with D the operator's
+// angular average on isotropic fields (sum_p omega_p A_p applied to 1 z; the
+// angular coupling cancels on them), a 5-point diffusion operator
+//   D z_c = W1 (Lambda - g W1)_c z_c + k_c [ sum_faces M h^-2 gamma_f (z_c - z_nb) (x2 next to an edge)
+//                                           + edge cells: 2 fe S / (eps h) z_c ],
+// M = sum_p omega_p mu_p^2 (x-faces) or eta_p^2 (y-faces), S = sum_p omega_p |mu_p| or |eta_p|
+// (the mixed moment sum_p omega_p mu_p eta_p vanishes for direction sets symmetric
+// under x -> -x, as the equally spaced one is, and is not carried).  Solved
+// approximately by a fixed number of Chebyshev steps on the Jacobi-scaled
+// operator over the eigenvalue interval [CHEB2_A, CHEB2_B]: a fixed linear map,
+// as the Krylov method requires of its preconditioner.
+// ---------------------------------------------------------------------------
+struct IsoArgs {
+    Sys S;
+    double Mxx, Myy, Sx, Sy;
+    const double *y;
+    const double *xin;
+    double *xout, *d;
+    double c1, c2, th;
+    const int *fl;
+};
+
+__device__ __forceinline__ void iso_row(const IsoArgs &A, int j, const double *x, double &Dx, double &diag)
+{
+    const Sys &S = A.S;
+    int iy, ix;
+    cell_yx(S, j, iy, ix);
+    const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
+    const double k = S.kco[j];
+    const double cx = A.Mxx * S.idx * S.idx, cy = A.Myy * S.idy * S.idy;
+    double gl = S.gx[fl], gr = S.gx[fl + 1], gb = S.gy[fb], gt = S.gy[fb + S.nx];
+    double ed = 0.0;
+    const double e2 = S.k2 * S.fe;
+    if (ix == 0) { gr *= 2.0; gl = 0.0; ed += e2 * A.Sx * S.idx; }
+    else if (ix == S.nx - 1) { gl *= 2.0; gr = 0.0; ed += e2 * A.Sx * S.idx; }
+    if (iy == 0) { gt *= 2.0; gb = 0.0; ed += e2 * A.Sy * S.idy; }
+    else if (iy == S.ny - 1) { gb *= 2.0; gt = 0.0; ed += e2 * A.Sy * S.idy; }
+    const double xc = x[j];
+    const double xl = ix > 0 ? x[j - 1] : 0.0, xr = ix < S.nx - 1 ? x[j + 1] : 0.0;
+    const double xb = iy > 0 ? x[j - S.nx] : 0.0, xt = iy < S.ny - 1 ? x[j + S.nx] : 0.0;
+    diag = S.W1 * S.dmg[j] + k * (cx * (gl + gr) + cy * (gb + gt) + ed);
+    Dx = diag * xc - k * (cx * (gl * xl + gr * xr) + cy * (gb * xb + gt * xt));
+}
+
+// first step: x1 = d0 = (y / diag) / theta
+__global__ void __launch_bounds__(B2) iso_first_kernel(IsoArgs A)
+{
+    if (A.fl[F_STATE] != 0) return;
+    const int n = A.S.nx * A.S.ny;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        double Dx, diag;
+        iso_row(A, j, A.y, Dx, diag);       // only the diagonal is used here
+        const double d0 = A.y[j] / (diag * A.th);
+        A.d[j] = d0;
+        A.xout[j] = d0;
+    }
+}
+
+// later steps: r = (y - D x)/diag; d = c1 d + c2 r; x_out = x + d
+__global__ void __launch_bounds__(B2) iso_step_kernel(IsoArgs A)
+{
+    if (A.fl[F_STATE] != 0) return;
+    const int n = A.S.nx * A.S.ny;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        double Dx, diag;
+        iso_row(A, j, A.xin, Dx, diag);
+        const double r = (A.y[j] - Dx) / diag;
+        const double dn = A.c1 * A.d[j] + A.c2 * r;
+        A.d[j] = dn;
+        A.xout[j] = A.xin[j] + dn;
+    }
 }
 
 // sum of the partials of dot k over nb blocks, in a fixed order (one block of B2 threads)
@@ -534,7 +651,7 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
 
 __global__ void __launch_bounds__(B2) zero2_kernel(double *a, double *b, size_t n)
 {
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2) a[t] = b[t] = 0.0;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) a[t] = b[t] = 0.0;
 }
 
 __global__ void reset_flags_kernel(int *fl)
@@ -546,7 +663,7 @@ __global__ void reset_flags_kernel(int *fl)
 __global__ void __launch_bounds__(B2) xcorr0_kernel(double *x, const double *Es, const double *acU, int P,
                                                     double ieps, size_t n)
 {
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2)
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2)
         x[t] = (Es[t] - acU[t / P]) * ieps;
 }
 
@@ -568,9 +685,10 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
     const int P = S.P;
     const size_t n = (size_t)S.nx * S.ny * P;
     int mx = 0, sum = 0, failed = 0, clamped = 0, neg = 0;
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2) {
-        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
-        const int iy = j / S.nx, ix = j - iy * S.nx;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) {
+        const int j = t >> S.lgP, p = t & (P - 1);
+        int iy, ix;
+        cell_yx(S, j, iy, ix);
         const Nb X = load_nb(A.Es, S.nx, S.ny, iy, ix, P, p);
         Grad O;
         faces<true, true>(S, iy, ix, p, &X, O);
@@ -643,14 +761,15 @@ __global__ void __launch_bounds__(B2) project2d_kernel(ProjArgs A)
     const Sys &S = A.S;
     const int P = S.P;
     const size_t n = (size_t)S.nx * S.ny * P;
-    for (size_t t = (size_t)blockIdx.x * B2 + threadIdx.x; t < n; t += (size_t)gridDim.x * B2) {
-        const int j = (int)(t / P), p = (int)(t - (size_t)j * P);
-        const int iy = j / S.nx, ix = j - iy * S.nx;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) {
+        const int j = t >> S.lgP, p = t & (P - 1);
+        int iy, ix;
+        cell_yx(S, j, iy, ix);
         const Nb X = load_nb(A.EJ, S.nx, S.ny, iy, ix, P, p);
         Grad O;
         faces<true, true>(S, iy, ix, p, &X, O);
         A.E1[t] = S.acU[j] + S.eps * X.v[1][1];
-        const size_t fl = (size_t)iy * (S.nx + 1) + ix, fb = (size_t)iy * S.nx + ix;
+        const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
         A.Ox1[fl * P + p] = O.l;
         if (ix == S.nx - 1) A.Ox1[(fl + 1) * P + p] = O.r;
         A.Oy1[fb * P + p] = O.b;
@@ -688,6 +807,15 @@ struct grte2d_ctx {
     int *h_fl = nullptr;      // pinned
     double *h_sc = nullptr;   // pinned
     std::vector<void *> allocs;
+    // isotropic correction of the preconditioner
+    int iso_k = 10;                      // Chebyshev steps (0: off)
+    double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
+    double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
+    // sampled timing of the operator kernel (first iteration of every chunk)
+    int profiling = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double prof_ms = 0.0;
+    int prof_n = 0;
 };
 
 namespace {
@@ -719,6 +847,12 @@ Sys make_sys(grte2d_ctx *c, int corr, double eps)
     S.corr = corr;
     S.dx = c->lx / c->nx;
     S.dy = c->ly / c->ny;
+    S.idx = 1.0 / S.dx;
+    S.idy = 1.0 / S.dy;
+    S.inx = 1.0 / c->nx;
+    S.k2 = 2.0 / eps;
+    S.lgP = 0;
+    while ((1 << S.lgP) < c->P) ++S.lgP;
     S.eps = eps;
     S.fe = corr ? eps : 1.0;
     S.W1 = c->W1;
@@ -751,6 +885,39 @@ __global__ void rb1_kernel(double *rb1, const double *T, int m, double f, int n)
     if (j < n) rb1[j] = (m == 0 ? 1.0 : T[j] * T[j] * T[j]) * f;
 }
 
+// K Chebyshev steps for D z = y; the result lands in out (tmp is scratch)
+void iso_solve(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStream_t st)
+{
+    const int K = c->iso_k;
+    const int nbc = nblocks(c->N);
+    IsoArgs I;
+    I.S = S;
+    I.Mxx = c->Mxx;
+    I.Myy = c->Myy;
+    I.Sx = c->Sx;
+    I.Sy = c->Sy;
+    I.y = y;
+    I.d = c->idir;
+    I.fl = c->fl;
+    const double th = 0.5 * (CHEB2_B + CHEB2_A), de = 0.5 * (CHEB2_B - CHEB2_A), sg = th / de;
+    I.th = th;
+    auto buf = [&](int k) { return ((K - k) % 2 == 0) ? out : c->itmp; };   // iterate k lands in buf(k)
+    I.xin = nullptr;
+    I.xout = buf(1);
+    I.c1 = I.c2 = 0.0;
+    hipLaunchKernelGGL(iso_first_kernel, dim3(nbc), dim3(B2), 0, st, I);
+    double rho = 1.0 / sg;
+    for (int k = 1; k < K; ++k) {
+        const double rn = 1.0 / (2.0 * sg - rho);
+        I.c1 = rn * rho;
+        I.c2 = 2.0 * rn / de;
+        rho = rn;
+        I.xin = buf(k);
+        I.xout = buf(k + 1);
+        hipLaunchKernelGGL(iso_step_kernel, dim3(nbc), dim3(B2), 0, st, I);
+    }
+}
+
 // BiCGStab on the system currently described by the coefficient arrays; x holds
 // the start and receives the solution.  Returns iterations, state and the
 // final true relative residual.
@@ -776,6 +943,13 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.fl = c->fl;
     A.tol = c->tol;
     A.maxit = c->maxit;
+    // the isotropic correction targets the angular coupling of the prediction;
+    // the correction's systems have none
+    const bool iso = c->iso_k > 0 && !S.corr;
+    A.dP = iso ? c->dP : nullptr;
+    A.dS = iso ? c->dS : nullptr;
+    A.yP = iso ? c->yP : nullptr;
+    A.yS = iso ? c->yS : nullptr;
     const int nb = nblocks(c->nE);
     hipStream_t st = c->stream;
     int its_total = 0, state = 0;
@@ -808,11 +982,16 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
         }
         if (restart == KRY_RESTARTS || its_total >= c->maxit) break;
         while (true) {
+            const bool timed = c->profiling != 0;
             for (int k = 0; k < CHUNK; ++k) {
                 hipLaunchKernelGGL(pupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+                if (iso) iso_solve(c, S, c->yP, c->dP, st);
+                if (timed && k == 0) (void)hipEventRecord(c->ev0, st);
                 hipLaunchKernelGGL(apply2d_kernel<1>, dim3(nb), dim3(B2), 0, st, A);
+                if (timed && k == 0) (void)hipEventRecord(c->ev1, st);
                 hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 1, nb);
                 hipLaunchKernelGGL(supd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+                if (iso) iso_solve(c, S, c->yS, c->dS, st);
                 hipLaunchKernelGGL(apply2d_kernel<2>, dim3(nb), dim3(B2), 0, st, A);
                 hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 2, nb);
                 hipLaunchKernelGGL(xupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
@@ -822,6 +1001,13 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GRTE_E_HIP;
             if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
+            if (timed) {
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
+                    c->prof_ms += ms;
+                    ++c->prof_n;
+                }
+            }
             if (c->h_fl[F_STATE] != 0) break;
         }
         its_total += c->h_fl[F_ITS];
@@ -876,6 +1062,8 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
     if (!(pb->lx > 0) || !(pb->ly > 0) || !(pb->a > 0) || !(pb->c > 0) || !(pb->cv > 0)) return GRTE_E_INVAL;
     if (pb->opacity_law != 0 && pb->opacity_law != 3) return GRTE_E_INVAL;
     if ((size_t)pb->nx * pb->ny > (size_t)1 << 28) return GRTE_E_UNSUPPORTED;
+    // 32-bit indexing of the face arrays of every pair
+    if ((size_t)(pb->nx + 1) * (pb->ny + 1) * P >= ((size_t)1 << 31)) return GRTE_E_UNSUPPORTED;
     for (int p = 0; p < P; ++p)
         if (!(eta[p] > 0.0) || mu[p] == 0.0 || !(omega[p] > 0.0)) return GRTE_E_INVAL;
     grte2d_ctx *c = new (std::nothrow) grte2d_ctx();
@@ -890,7 +1078,13 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
     c->c = pb->c;
     c->cv = pb->cv;
     c->W1 = 0.0;
-    for (int p = 0; p < P; ++p) c->W1 += omega[p];
+    for (int p = 0; p < P; ++p) {
+        c->W1 += omega[p];
+        c->Mxx += omega[p] * mu[p] * mu[p];
+        c->Myy += omega[p] * eta[p] * eta[p];
+        c->Sx += omega[p] * fabs(mu[p]);
+        c->Sy += omega[p] * fabs(eta[p]);
+    }
     c->N = (size_t)c->nx * c->ny;
     c->nE = c->N * P;
     c->nOx = (size_t)c->ny * (c->nx + 1) * P;
@@ -906,6 +1100,8 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
               dalloc(c, c->acU, c->N) && dalloc(c, c->beta, c->N) && dalloc(c, c->ustar, c->N) &&
               dalloc(c, c->Dv, c->N) && dalloc(c, c->rhon, c->N) && dalloc(c, c->bv, c->nE) &&
               dalloc(c, c->sab, c->N) && dalloc(c, c->ue, c->N) &&
+              dalloc(c, c->yP, c->N) && dalloc(c, c->yS, c->N) && dalloc(c, c->dP, c->N) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
@@ -945,6 +1141,8 @@ grte_status grte2d_destroy(grte2d_ctx *c)
     for (void *q : c->allocs) (void)hipFree(q);
     if (c->h_fl) (void)hipHostFree(c->h_fl);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
     return GRTE_OK;
 }
@@ -953,6 +1151,33 @@ grte_status grte2d_set_stream(grte2d_ctx *c, void *stream)
 {
     if (!c) return GRTE_E_INVAL;
     c->stream = (hipStream_t)stream;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_isotropic_correction(grte2d_ctx *c, int steps)
+{
+    if (!c || steps < 0 || steps > 64) return GRTE_E_INVAL;
+    c->iso_k = steps;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_profiling(grte2d_ctx *c, int on)
+{
+    if (!c) return GRTE_E_INVAL;
+    if (on && !c->ev0) {
+        if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) return GRTE_E_HIP;
+    }
+    c->profiling = on != 0;
+    c->prof_ms = 0.0;
+    c->prof_n = 0;
+    return GRTE_OK;
+}
+
+grte_status grte2d_read_timing(grte2d_ctx *c, double *ms, int *count)
+{
+    if (!c || !ms || !count) return GRTE_E_INVAL;
+    *ms = c->prof_ms;
+    *count = c->prof_n;
     return GRTE_OK;
 }
 
