@@ -46,6 +46,8 @@ TRAFFIC = {
     ("config2", "fp32"): (None, None),
     ("config4", "fp64"): (None, None),
     ("config4", "fp32"): (1.4162e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
+    ("config3", "fp64"): (5.470e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config5", "fp64"): (None, None),
 }
 
 

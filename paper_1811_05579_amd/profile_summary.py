@@ -7,6 +7,12 @@
       counter-collection CSV of one --pmc run: per-dispatch values of the
       counter (KiB for FETCH_SIZE / WRITE_SIZE) for the kernels whose name
       contains KERNEL_SUBSTRING: count, mean, min, max.
+  python3 profile_summary.py --pmc COUNTER_CSV KERNEL_SUBSTRING MIN
+      the same over the dispatches whose value is at least MIN (e.g. to leave
+      out launches that returned at once because a solve had converged).
+  python3 profile_summary.py --launches RUN_results.db KERNEL_SUBSTRING MIN_US
+      count, mean, min, max duration of the matching kernel's launches that
+      took at least MIN_US microseconds.
   python3 profile_summary.py --window RUN_results.db KERNEL_SUBSTRING FIRST COUNT
       durations of COUNT launches of the matching kernel, in launch order,
       starting at launch FIRST (negative: counted from the last launch), e.g.
@@ -42,6 +48,17 @@ def summarise_window(db_path, kernel_substring, first, count):
             f"mean {mean / 1e3:.2f} us  min {min(sel) / 1e3:.2f}  max {max(sel) / 1e3:.2f}")
 
 
+def summarise_launches(db_path, kernel_substring, min_us):
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, duration from kernels order by start").fetchall()
+    d = [dur / 1e3 for name, dur in rows if kernel_substring in name]
+    sel = [x for x in d if x >= min_us]
+    if not sel:
+        return f"no '{kernel_substring}' launch of at least {min_us} us ({len(d)} in all)"
+    return (f"'{kernel_substring}' launches >= {min_us} us: {len(sel)} of {len(d)}, mean {sum(sel) / len(sel):.2f} us  "
+            f"min {min(sel):.2f}  max {max(sel):.2f}")
+
+
 def counter_values(csv_path, kernel_substring):
     """{counter name: [value per dispatch]} for the matching kernels (rows of
     one dispatch are summed: some counters come per shader engine or XCD)."""
@@ -58,9 +75,13 @@ def counter_values(csv_path, kernel_substring):
     return out
 
 
-def summarise_pmc(csv_path, kernel_substring):
+def summarise_pmc(csv_path, kernel_substring, vmin=None):
     lines = []
     for name, vals in counter_values(csv_path, kernel_substring).items():
+        if vmin is not None:
+            vals = [v for v in vals if v >= vmin]
+            if not vals:
+                continue
         lines.append(f"{name} over {len(vals)} dispatches of '{kernel_substring}': mean {sum(vals) / len(vals):.1f} "
                      f"min {min(vals):.1f} max {max(vals):.1f}")
     return "\n".join(lines) if lines else f"no '{kernel_substring}' dispatches in {csv_path}"
@@ -69,7 +90,9 @@ def summarise_pmc(csv_path, kernel_substring):
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "--window":
         print(summarise_window(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5])))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "--launches":
+        print(summarise_launches(sys.argv[2], sys.argv[3], float(sys.argv[4])))
     elif len(sys.argv) >= 2 and sys.argv[1] == "--pmc":
-        print(summarise_pmc(sys.argv[2], sys.argv[3]))
+        print(summarise_pmc(sys.argv[2], sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else None))
     else:
         print(summarise(sys.argv[1]))
