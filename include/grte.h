@@ -457,6 +457,11 @@ typedef struct grte2d_step_info {
     int kstar_clamped;       /* sigma/T^3: cells with U* < 0 (K* taken as 0)       */
     int negative_root;       /* cells whose (4.13) has no root >= 0                */
     int newton_total_iters;  /* Newton iterations summed over the cells            */
+    int guess_accepted;      /* learned guess (grte2d_set_guess): cells whose guess
+                                met the residual bound (no Newton step)            */
+    int guess_rejected;      /* cells whose guess was unusable, no better than T^n
+                                by residual, or whose Newton from it hit the cap  */
+    int guess_started;       /* cells whose Newton started from the guess          */
     int pred_floor_stop;     /* 1 if a solve was accepted at the rounding level of */
     int corr_floor_stop;     /* its residual: restarting no longer reduced it and
                                 it was within 64 x max(tol, that level), the level
@@ -509,6 +514,20 @@ grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
  * Section 3).  The correction's systems have no angular coupling and use the
  * block inverse alone. */
 grte_status grte2d_set_isotropic_correction(grte2d_ctx *ctx, int steps);
+
+/* Learned initial guess of the per-cell temperature solve (4.13), as for the
+ * 1-D context (grte_set_guess): the model's bfloat16 weights and normalisation
+ * are read at every step (the model must outlive its use; NULL = Newton from
+ * T^n).  A guess whose normalised residual is at most accept_tol is taken as
+ * the root; otherwise Newton starts from it if its residual is below that of
+ * T^n, else from T^n. */
+grte_status grte2d_set_guess(grte2d_ctx *ctx, const grte_mlp *model, double accept_tol);
+
+/* Training rows of the last step: for every cell six binary32 values, the
+ * five standardisable features of (rho*, T^n, sigma0 (T^n)^-m, eps, dt) and the
+ * target log(T^{n+1}/T^n), into the device buffer dev_rows (cap_rows >= nx*ny
+ * rows).  Enqueued on the context's stream.  GRTE_E_INVAL before a step. */
+grte_status grte2d_log_pairs(grte2d_ctx *ctx, float *dev_rows, long long cap_rows, long long *n_rows);
 
 /* Opacity coefficient per cell, sigma0[nx*ny] >= 0. */
 grte_status grte2d_set_opacity(grte2d_ctx *ctx, const double *sigma0, int on_device);

@@ -595,6 +595,20 @@ class Grte2D:
                                                              Oy.ctypes.data, T.ctypes.data, 0))
         return E, Ox, Oy, T
 
+    def set_guess(self, model, accept_tol=1e-10):
+        """Learned initial guess for the temperature solve (None: Newton from T^n)."""
+        h = model._h if model is not None else None
+        check("grte2d_set_guess", self._lib.grte2d_set_guess(self._h, h, float(accept_tol)))
+
+    def log_pairs(self, rows):
+        """Write the last step's training rows into the float32 CUDA tensor `rows`
+        (shape (>= nx*ny, 6)); returns the number of rows written."""
+        _check_rows(rows, self.N)
+        n = ctypes.c_longlong()
+        check("grte2d_log_pairs", self._lib.grte2d_log_pairs(self._h, ctypes.c_void_p(rows.data_ptr()),
+                                                             rows.shape[0], ctypes.byref(n)))
+        return int(n.value)
+
     def set_isotropic_correction(self, steps=10):
         """Chebyshev steps of the preconditioner's isotropic (diffusion) correction; 0 = off."""
         check("grte2d_set_isotropic_correction", self._lib.grte2d_set_isotropic_correction(self._h, int(steps)))

@@ -66,7 +66,8 @@ class StepInfo2D(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("pred_residual", c_double),
                 ("corr_iters", c_int), ("corr_converged", c_int), ("corr_residual", c_double),
                 ("newton_max_iters", c_int), ("newton_failed", c_int), ("kstar_clamped", c_int),
-                ("negative_root", c_int), ("newton_total_iters", c_int), ("pred_floor_stop", c_int),
+                ("negative_root", c_int), ("newton_total_iters", c_int), ("guess_accepted", c_int),
+                ("guess_rejected", c_int), ("guess_started", c_int), ("pred_floor_stop", c_int),
                 ("corr_floor_stop", c_int)]
 
     def as_dict(self):
@@ -153,6 +154,8 @@ _SIGS = {
     "grte2d_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
     "grte2d_set_profiling": (c_int, [c_void_p, c_int]),
     "grte2d_set_isotropic_correction": (c_int, [c_void_p, c_int]),
+    "grte2d_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
+    "grte2d_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
     "grte2d_read_timing": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
 }
 

@@ -35,6 +35,7 @@
 #include <vector>
 
 #include "../../include/grte.h"
+#include "mlp_common.hpp"
 #include "solver_common.hpp"
 
 namespace {
@@ -675,12 +676,25 @@ struct NewtArgs {
     const double *Es, *En, *Tn, *sigma0, *beta;
     double a, c, cv, dt;
     int m, maxit;
-    double *Tnew, *ustar, *Dv, *rhon;
-    int *stat;                   // [0] max its, [1] failed, [2] K* clamped, [3] negative root, [4] sum its
+    double *Tnew, *ustar, *Dv, *rhon, *rstar;
+    int *stat;                   // [0] max its, [1] failed, [2] K* clamped, [3] negative root, [4] sum its,
+                                 // [5] guesses accepted, [6] guesses not used, [7] Newton started from a guess
+    const uint16_t *gw;          // learned initial guess: bfloat16 weights (null: Newton from T^n)
+    const float *gnorm;          // and its normalisation
+    double gtol;                 // residual below which the guess is taken as the root
 };
 
+template <bool GUESS>
 __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
 {
+    __shared__ uint16_t sW[GUESS ? MLP_NPARAM + 3 : 1];
+    __shared__ float sN[GUESS ? MLP_NNORM : 1];
+    if constexpr (GUESS) {
+        for (int e = threadIdx.x; e < MLP_NPARAM; e += B2) sW[e] = A.gw[e];
+        if (threadIdx.x < MLP_NNORM) sN[threadIdx.x] = A.gnorm[threadIdx.x];
+        __syncthreads();
+    }
+    int acc = 0, unused = 0, started = 0;
     const Sys &S = A.S;
     const int P = S.P;
     const size_t n = (size_t)S.nx * S.ny * P;
@@ -705,6 +719,7 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
         A.ustar[j] = us;
         A.Dv[j] = D;
         A.rhon[j] = rn;
+        A.rstar[j] = rhs_s;
         double Ks = 1.0;
         if (A.m == 3) {
             if (us < 0.0) {
@@ -724,7 +739,33 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
         int its = 0;
         if (!(s0 == 0.0 && Ks == 0.0)) {
             if (Tn + rhs / lin < 0.0) ++neg;
-            if (!newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its)) ++failed;
+            bool ok = false, done = false;
+            if (GUESS && s0 > 0.0 && Tn > 0.0) {
+                // learned starting value, judged by the normalised residual of (4.13):
+                // taken as the root below gtol, used as Newton's start if its residual
+                // is below that of T^n, otherwise Newton starts from T^n
+                float f[MLP_IN];
+                mlp_features(rhs_s, Tn, s0, A.m, S.eps, A.dt, f);
+                const float y = mlp_eval(sW, sN, f);
+                const double Tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
+                if (isfinite(Tg) && Tg > 0.0) {
+                    const double T2 = Tg * Tg;
+                    const double rg = fabs(q4 * T2 * T2 + lin * (Tg - Tn) - rhs) / lin;
+                    const double Tn2 = Tn * Tn;
+                    const double rr = fabs(q4 * Tn2 * Tn2 - rhs) / lin;
+                    if (rg <= A.gtol * fmax(fabs(Tn + rhs / lin), 1e-300)) {
+                        T = Tg;
+                        ok = done = true;
+                        ++acc;
+                    } else if (rg < rr) {
+                        ok = done = newton_quartic(Tg, Tn, q4, lin, rhs, A.maxit, T, its);
+                        if (done) ++started;
+                    }
+                }
+                if (!done) ++unused;
+            }
+            if (!done) ok = newton_quartic(Tn, Tn, q4, lin, rhs, A.maxit, T, its);
+            if (!ok) ++failed;
         }
         A.Tnew[j] = T;
         mx = max(mx, its);
@@ -737,6 +778,9 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
         failed += __shfl_xor(failed, o, 64);
         clamped += __shfl_xor(clamped, o, 64);
         neg += __shfl_xor(neg, o, 64);
+        acc += __shfl_xor(acc, o, 64);
+        unused += __shfl_xor(unused, o, 64);
+        started += __shfl_xor(started, o, 64);
     }
     if (__lane_id() == 0) {
         if (mx) atomicMax(&A.stat[0], mx);
@@ -744,7 +788,30 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
         if (clamped) atomicAdd(&A.stat[2], clamped);
         if (neg) atomicAdd(&A.stat[3], neg);
         if (sum) atomicAdd(&A.stat[4], sum);
+        if (acc) atomicAdd(&A.stat[5], acc);
+        if (unused) atomicAdd(&A.stat[6], unused);
+        if (started) atomicAdd(&A.stat[7], started);
     }
+}
+
+// training rows of the learned guess for the last step: features of (rho*, T^n,
+// sigma0, eps, dt) and the target log(T^{n+1}/T^n), six binary32 values per cell
+__global__ void __launch_bounds__(B2) log2d_kernel(int n, int m, double eps, double dt, const double *rstar,
+                                                   const double *Told, const double *Tnew, const double *sigma0,
+                                                   float *out)
+{
+    const int j = blockIdx.x * B2 + threadIdx.x;
+    if (j >= n) return;
+    const double t0 = Told[j], t1 = Tnew[j], s0 = sigma0[j];
+    float f[MLP_IN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float tg = 0.0f;
+    if (s0 > 0.0 && t0 > 0.0 && t1 > 0.0) {
+        mlp_features(rstar[j], t0, s0, m, eps, dt, f);
+        tg = (float)log(t1 / t0);
+    }
+#pragma unroll
+    for (int q = 0; q < MLP_IN; ++q) out[(size_t)j * 6 + q] = f[q];
+    out[(size_t)j * 6 + 5] = tg;
 }
 
 // ---------------------------------------------------------------------------
@@ -807,6 +874,13 @@ struct grte2d_ctx {
     int *h_fl = nullptr;      // pinned
     double *h_sc = nullptr;   // pinned
     std::vector<void *> allocs;
+    // learned initial guess of the temperature solve
+    const uint16_t *guess_w = nullptr;
+    const float *guess_norm = nullptr;
+    double guess_tol = 1e-10;
+    double *rstar = nullptr;
+    int stepped = 0;
+    double last_eps = 0, last_dt = 0;
     // isotropic correction of the preconditioner
     int iso_k = 10;                      // Chebyshev steps (0: off)
     double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
@@ -1101,6 +1175,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
               dalloc(c, c->Dv, c->N) && dalloc(c, c->rhon, c->N) && dalloc(c, c->bv, c->nE) &&
               dalloc(c, c->sab, c->N) && dalloc(c, c->ue, c->N) &&
               dalloc(c, c->yP, c->N) && dalloc(c, c->yS, c->N) && dalloc(c, c->dP, c->N) &&
+              dalloc(c, c->rstar, c->N) &&
               dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
@@ -1151,6 +1226,28 @@ grte_status grte2d_set_stream(grte2d_ctx *c, void *stream)
 {
     if (!c) return GRTE_E_INVAL;
     c->stream = (hipStream_t)stream;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_guess(grte2d_ctx *c, const grte_mlp *model, double accept_tol)
+{
+    if (!c || !(accept_tol >= 0) || !std::isfinite(accept_tol)) return GRTE_E_INVAL;
+    c->guess_w = model ? model->wbf : nullptr;
+    c->guess_norm = model ? model->norm : nullptr;
+    c->guess_tol = accept_tol;
+    return GRTE_OK;
+}
+
+grte_status grte2d_log_pairs(grte2d_ctx *c, float *dev_rows, long long cap_rows, long long *n_rows)
+{
+    if (!c || !dev_rows || !n_rows) return GRTE_E_INVAL;
+    *n_rows = 0;
+    if (!c->stepped || cap_rows < (long long)c->N) return GRTE_E_INVAL;
+    // after the step T holds T^{n+1} and the second buffer T^n
+    hipLaunchKernelGGL(log2d_kernel, dim3((unsigned)((c->N + B2 - 1) / B2)), dim3(B2), 0, c->stream, (int)c->N,
+                       c->m, c->last_eps, c->last_dt, c->rstar, c->T1, c->T, c->sigma0, dev_rows);
+    if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
+    *n_rows = (long long)c->N;
     return GRTE_OK;
 }
 
@@ -1216,6 +1313,7 @@ grte_status grte2d_set_state(grte2d_ctx *c, const double *E, const double *Ox, c
     if (!c || !E || !Ox || !Oy || !T) return GRTE_E_INVAL;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     hipStream_t st = c->stream;
+    c->stepped = 0;
     if (hipMemcpyAsync(c->E, E, c->nE * sizeof(double), k, st) != hipSuccess ||
         hipMemcpyAsync(c->Ox, Ox, c->nOx * sizeof(double), k, st) != hipSuccess ||
         hipMemcpyAsync(c->Oy, Oy, c->nOy * sizeof(double), k, st) != hipSuccess ||
@@ -1338,7 +1436,12 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     na.Dv = c->Dv;
     na.rhon = c->rhon;
     na.stat = c->stat;
-    hipLaunchKernelGGL(newton2d_kernel, dim3(nb), dim3(B2), 0, st, na);
+    na.rstar = c->rstar;
+    na.gw = c->guess_w;
+    na.gnorm = c->guess_norm;
+    na.gtol = c->guess_tol;
+    if (c->guess_w) hipLaunchKernelGGL(newton2d_kernel<true>, dim3(nb), dim3(B2), 0, st, na);
+    else hipLaunchKernelGGL(newton2d_kernel<false>, dim3(nb), dim3(B2), 0, st, na);
 
     // ---- correction, substep 2 (4.11) with K^{n+1}, U^{n+1}
     ca.corr = 1;
@@ -1386,6 +1489,12 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     inf.kstar_clamped = stat[2];
     inf.negative_root = stat[3];
     inf.newton_total_iters = stat[4];
+    inf.guess_accepted = stat[5];
+    inf.guess_rejected = stat[6];
+    inf.guess_started = stat[7];
+    c->stepped = 1;
+    c->last_eps = eps;
+    c->last_dt = dt;
     if (info) *info = inf;
     const bool bad = !inf.pred_converged || !inf.corr_converged || inf.newton_failed;
     return bad ? GRTE_E_NOCONV : GRTE_OK;
