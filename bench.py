@@ -47,6 +47,7 @@ TRAFFIC = {
     ("config4", "fp64"): (None, None),
     ("config4", "fp32"): (1.4162e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
     ("config3", "fp64"): (5.470e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config3", "fp32"): (5.470e8, "profiles/apply2d_config3_hbm_traffic.txt"),   # Krylov vectors are binary64 either way
     ("config5", "fp64"): (None, None),
 }
 
@@ -271,6 +272,9 @@ def main_2d(args):
     g.set_stream(stream)
     g.set_opacity(w.sigma0)
     g.set_inflow(w.b)
+    # config 3 is defined with binary32 intensities (FP64 arithmetic and Newton)
+    storage = args.storage or ("fp32" if args.workload == "config3" else "fp64")
+    g.set_storage(storage == "fp32")
     g.set_state(w.E, w.Ox, w.Oy, w.T)
     for _ in range(args.warmup):
         g.step(w.dt, w.eps)
@@ -309,7 +313,9 @@ def main_2d(args):
         "config": {
             "workload": (f"2D square {w.nx}x{w.ny} cells, {w.nv} equally spaced directions, two-material "
                          f"Voronoi sigma in {{1, {w.sigma0.max():g}}} (64 sites), eps={w.eps:g}, T0=1e-2, hot "
-                         "inflow on x=0, dt=0.5dx, FP64 storage and arithmetic, staggered parity grid"),
+                         f"inflow on x=0, dt=0.5dx, {'binary32' if storage == 'fp32' else 'binary64'} intensity "
+                         "storage, FP64 arithmetic and Newton, staggered parity grid"),
+            "storage": storage,
             "steps_from_cold_start": [args.warmup, args.warmup + args.steps],
             "pred_iters_mean": sum(i[0] for i in its) / len(its), "pred_iters_max": max(i[0] for i in its),
             "corr_iters_mean": sum(i[1] for i in its) / len(its), "status_worst": min(i[2] for i in its),
@@ -322,8 +328,8 @@ def main_2d(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": TRAFFIC.get((args.workload, "fp64"), (None, None))[0],
-            "traffic_source": TRAFFIC.get((args.workload, "fp64"), (None, None))[1],
+            "traffic": TRAFFIC.get((args.workload, storage), (None, None))[0],
+            "traffic_source": TRAFFIC.get((args.workload, storage), (None, None))[1],
             "bytes_per_launch": op2d_algorithmic_bytes(N, P),
             "avg_launch_us": launch_s * 1e6,
             "timed_launches": cnt,
@@ -343,8 +349,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5"], default="config2")
     ap.add_argument("--storage", choices=["fp64", "fp32"], default=None,
-                    help="intensity storage (default: fp64 for config2, fp32 for config4, "
-                         "as each workload is defined)")
+                    help="intensity storage (default: fp64 for config2 and config5, fp32 for config3 and "
+                         "config4, as each workload is defined)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the single-GPU step; multi-GPU "

@@ -515,6 +515,15 @@ grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
  * block inverse alone. */
 grte_status grte2d_set_isotropic_correction(grte2d_ctx *ctx, int steps);
 
+/* Storage of the state between steps: fp32 = 1 keeps E (as its deviation from
+ * a c T^4) and O^x, O^y in binary32 -- each step reads the stored values widened
+ * to binary64 and all arithmetic, the temperature and the Newton solve stay
+ * binary64; fp32 = 0 (default) keeps binary64.  Switching on rounds the current
+ * state.  get/set_state keep their binary64 layouts (set_state rounds, get_state
+ * returns the stored values).  GRTE_E_NOMEM if the binary32 arrays cannot be
+ * allocated. */
+grte_status grte2d_set_storage(grte2d_ctx *ctx, int fp32);
+
 /* Learned initial guess of the per-cell temperature solve (4.13), as for the
  * 1-D context (grte_set_guess): the model's bfloat16 weights and normalisation
  * are read at every step (the model must outlive its use; NULL = Newton from

@@ -595,6 +595,11 @@ class Grte2D:
                                                              Oy.ctypes.data, T.ctypes.data, 0))
         return E, Ox, Oy, T
 
+    def set_storage(self, fp32):
+        """Store E (as its deviation from a c T^4), O^x and O^y in binary32 (True) or
+        binary64 (False) between steps; arithmetic stays binary64."""
+        check("grte2d_set_storage", self._lib.grte2d_set_storage(self._h, int(bool(fp32))))
+
     def set_guess(self, model, accept_tol=1e-10):
         """Learned initial guess for the temperature solve (None: Newton from T^n)."""
         h = model._h if model is not None else None

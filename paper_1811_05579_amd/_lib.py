@@ -155,6 +155,7 @@ _SIGS = {
     "grte2d_set_profiling": (c_int, [c_void_p, c_int]),
     "grte2d_set_isotropic_correction": (c_int, [c_void_p, c_int]),
     "grte2d_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
+    "grte2d_set_storage": (c_int, [c_void_p, c_int]),
     "grte2d_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),
     "grte2d_read_timing": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
 }

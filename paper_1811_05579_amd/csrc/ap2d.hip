@@ -668,6 +668,31 @@ __global__ void __launch_bounds__(B2) xcorr0_kernel(double *x, const double *Es,
         x[t] = (Es[t] - acU[t / P]) * ieps;
 }
 
+// between the binary64 state and its binary32 storage (E stored as its deviation
+// from a c T^4, O as is)
+__global__ void __launch_bounds__(B2) conv2d_kernel(int nE, int nOx, int nOy, int lgP, double ac, const double *T,
+                                                    double *E, double *Ox, double *Oy, float *E32, float *Ox32,
+                                                    float *Oy32, int to32)
+{
+    const int n = max(nE, max(nOx, nOy));
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < n; t += gridDim.x * B2) {
+        if (t < nE) {
+            const double tj = T[t >> lgP];
+            const double base = ac * (tj * tj) * (tj * tj);
+            if (to32) E32[t] = (float)(E[t] - base);
+            else E[t] = base + (double)E32[t];
+        }
+        if (t < nOx) {
+            if (to32) Ox32[t] = (float)Ox[t];
+            else Ox[t] = (double)Ox32[t];
+        }
+        if (t < nOy) {
+            if (to32) Oy32[t] = (float)Oy[t];
+            else Oy[t] = (double)Oy32[t];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // correction substep 1: moments, D, U*, K*, scalar Newton per cell
 // ---------------------------------------------------------------------------
@@ -874,6 +899,9 @@ struct grte2d_ctx {
     int *h_fl = nullptr;      // pinned
     double *h_sc = nullptr;   // pinned
     std::vector<void *> allocs;
+    // binary32 storage of the state between steps (0: binary64)
+    int f32 = 0;
+    float *E32 = nullptr, *Ox32 = nullptr, *Oy32 = nullptr;
     // learned initial guess of the temperature solve
     const uint16_t *guess_w = nullptr;
     const float *guess_norm = nullptr;
@@ -957,6 +985,17 @@ __global__ void rb1_kernel(double *rb1, const double *T, int m, double f, int n)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n) rb1[j] = (m == 0 ? 1.0 : T[j] * T[j] * T[j]) * f;
+}
+
+// widen (to32 = 0) or round (to32 = 1) the state held in E, Ox, Oy with temperature T
+grte_status convert2d(grte2d_ctx *c, int to32)
+{
+    int lgP = 0;
+    while ((1 << lgP) < c->P) ++lgP;
+    const size_t n = std::max(c->nE, std::max(c->nOx, c->nOy));
+    hipLaunchKernelGGL(conv2d_kernel, dim3(nblocks(n)), dim3(B2), 0, c->stream, (int)c->nE, (int)c->nOx, (int)c->nOy,
+                       lgP, c->a * c->c, c->T, c->E, c->Ox, c->Oy, c->E32, c->Ox32, c->Oy32, to32);
+    return hipGetLastError() == hipSuccess ? GRTE_OK : GRTE_E_HIP;
 }
 
 // K Chebyshev steps for D z = y; the result lands in out (tmp is scratch)
@@ -1229,6 +1268,22 @@ grte_status grte2d_set_stream(grte2d_ctx *c, void *stream)
     return GRTE_OK;
 }
 
+grte_status grte2d_set_storage(grte2d_ctx *c, int fp32)
+{
+    if (!c || (fp32 != 0 && fp32 != 1)) return GRTE_E_INVAL;
+    if (fp32 == c->f32) return GRTE_OK;
+    if (fp32 && !c->E32) {
+        if (!dalloc(c, c->E32, c->nE) || !dalloc(c, c->Ox32, c->nOx) || !dalloc(c, c->Oy32, c->nOy))
+            return GRTE_E_NOMEM;
+    }
+    // switching on rounds the current state; switching off keeps the stored values
+    grte_status s = convert2d(c, fp32 ? 1 : 0);
+    if (s != GRTE_OK) return s;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return GRTE_E_HIP;
+    c->f32 = fp32;
+    return GRTE_OK;
+}
+
 grte_status grte2d_set_guess(grte2d_ctx *c, const grte_mlp *model, double accept_tol)
 {
     if (!c || !(accept_tol >= 0) || !std::isfinite(accept_tol)) return GRTE_E_INVAL;
@@ -1319,6 +1374,10 @@ grte_status grte2d_set_state(grte2d_ctx *c, const double *E, const double *Ox, c
         hipMemcpyAsync(c->Oy, Oy, c->nOy * sizeof(double), k, st) != hipSuccess ||
         hipMemcpyAsync(c->T, T, c->N * sizeof(double), k, st) != hipSuccess)
         return GRTE_E_HIP;
+    if (c->f32) {
+        grte_status s = convert2d(c, 1);
+        if (s != GRTE_OK) return s;
+    }
     return hip_ok(hipStreamSynchronize(st));
 }
 
@@ -1327,6 +1386,10 @@ grte_status grte2d_get_state(grte2d_ctx *c, double *E, double *Ox, double *Oy, d
     if (!c) return GRTE_E_INVAL;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     hipStream_t st = c->stream;
+    if (c->f32) {   // the stored state: widen the binary32 arrays
+        grte_status s = convert2d(c, 0);
+        if (s != GRTE_OK) return s;
+    }
     if ((E && hipMemcpyAsync(E, c->E, c->nE * sizeof(double), k, st) != hipSuccess) ||
         (Ox && hipMemcpyAsync(Ox, c->Ox, c->nOx * sizeof(double), k, st) != hipSuccess) ||
         (Oy && hipMemcpyAsync(Oy, c->Oy, c->nOy * sizeof(double), k, st) != hipSuccess) ||
@@ -1361,6 +1424,10 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     grte2d_step_info inf;
     memset(&inf, 0, sizeof(inf));
     if (hipMemsetAsync(c->stat, 0, 8 * sizeof(int), st) != hipSuccess) return GRTE_E_HIP;
+    if (c->f32) {   // the step reads the stored (binary32) state, widened to binary64
+        grte_status s = convert2d(c, 0);
+        if (s != GRTE_OK) return s;
+    }
 
     // ---- prediction (4.5)/(5.2)
     CoefArgs ca;
@@ -1481,6 +1548,10 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     std::swap(c->Ox, c->Ox1);
     std::swap(c->Oy, c->Oy1);
     std::swap(c->T, c->T1);
+    if (c->f32) {   // store the new state in binary32
+        grte_status s2 = convert2d(c, 1);
+        if (s2 != GRTE_OK) return s2;
+    }
     int stat[8];
     if (hipMemcpyAsync(stat, c->stat, 8 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return GRTE_E_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;

@@ -176,3 +176,58 @@ def test_full_size_step_properties():
         assert np.all(r["T"] > 0)
         E, Ox, Oy, T = r["E"], r["Ox"], r["Oy"], r["T"]
     g.close()
+
+
+U32 = 2.0 ** -24
+
+
+def test_fp32_storage_round_trip_and_step_against_oracle():
+    """Binary32 storage: the stored state is E = a c T^4 + fl32(E - a c T^4) and
+    fl32(O); one step from that state equals the oracle's step from it (T at the
+    FP64 bar: the arithmetic is binary64), with E and O rounded once more on
+    storing (<= 2 u32 of the array's largest deviation)."""
+    w = random_state_2d(16, 11, 16, 2, m=3, eps=1e-2)
+    g = _ctx(w)
+    g.set_storage(True)
+    g.set_state(w.E, w.Ox, w.Oy, w.T)
+    E, Ox, Oy, T = g.get_state()
+    # the library forms a c T^4 as (a c T^2) T^2
+    T2 = w.T * w.T
+    base = ((w.a * w.c) * T2 * T2)[:, :, None]
+    assert np.array_equal(E, base + (w.E - base).astype(np.float32).astype(np.float64))
+    assert np.array_equal(Ox, w.Ox.astype(np.float32).astype(np.float64))
+    assert np.array_equal(Oy, w.Oy.astype(np.float32).astype(np.float64))
+    assert np.array_equal(T, w.T)
+    info = g.step(w.dt, w.eps, info=True)
+    assert info["status"] == 0, info
+    E1, Ox1, Oy1, T1 = g.get_state()
+    g.close()
+    o = oracle_step(w, E, Ox, Oy, T)
+    assert _rel(T1, o["T"]) <= fp64_bar(w, T)
+    dev = o["E"] - w.a * w.c * (o["T"] ** 4)[:, :, None]
+    assert np.max(np.abs(E1 - o["E"])) <= 2 * U32 * np.max(np.abs(dev)) + 1e-12 * np.max(np.abs(o["E"]))
+    for k, x in (("Ox", Ox1), ("Oy", Oy1)):
+        assert np.max(np.abs(x - o[k])) <= 2 * U32 * np.max(np.abs(o[k])), k
+
+
+def test_fp32_storage_full_size_against_fp64_storage():
+    """Five steps of the 1024 x 1024 workload from its cold start with binary32
+    and with binary64 storage: the trajectories stay close (the error the
+    stored rounding adds, reported per output)."""
+    w = config3()
+    res = []
+    for f32 in (False, True):
+        g = _ctx(w)
+        g.set_storage(f32)
+        g.set_state(w.E, w.Ox, w.Oy, w.T)
+        for _ in range(5):
+            info = g.step(w.dt, w.eps, info=True)
+            assert info["status"] == 0, info
+        res.append(g.get_state())
+        g.close()
+    (E0, X0, Y0, T0), (E1, X1, Y1, T1) = res
+    errs = {"T": _rel(T1, T0), "E": _rel(E1, E0), "Ox": _rel(X1, X0), "Oy": _rel(Y1, Y0),
+            "rho": _rel(E1 @ w.omega, E0 @ w.omega)}
+    print("config3, 5 steps, binary32 vs binary64 storage:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert errs["T"] < 1e-6 and errs["rho"] < 1e-6
+    assert errs["E"] < 1e-5 and errs["Ox"] < 1e-5 and errs["Oy"] < 1e-5
