@@ -69,6 +69,8 @@ CASES = [  # nx, ny, nv, m, eps, seed
     (20, 14, 32, 0, 1e-3, 4),
     (7, 6, 64, 0, 1e-4, 5),
     (9, 17, 4, 3, 1.0, 6),
+    (5, 4, 128, 3, 1e-2, 7),      # 64 pairs: one cell per wavefront
+    (37, 29, 8, 0, 1e-2, 8),      # 1073 cells x 4 pairs: 17 tiles, ragged
 ]
 
 
