@@ -507,13 +507,17 @@ grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
 
 /* The Krylov preconditioner inverts each cell's P x P block (the direction-
  * diagonal part plus the rank-one angular coupling of (4.5c)) and, in the
- * prediction, adds an isotropic correction: `steps` Chebyshev steps (default
- * 10; 0 = none, at most 64) on the operator's angular average over isotropic
- * fields, a 5-point diffusion operator -- the mode that the angular coupling
- * leaves nearly undamped in optically thick cells (the diffusion limit of
- * Section 3).  The correction's systems have no angular coupling and use the
- * block inverse alone. */
-grte_status grte2d_set_isotropic_correction(grte2d_ctx *ctx, int steps);
+ * prediction, adds an isotropic correction: an approximate inverse of the
+ * operator's angular average over isotropic fields, a 5-point diffusion
+ * operator -- the mode that the angular coupling leaves nearly undamped in
+ * optically thick cells (the diffusion limit of Section 3).  kind 0: none;
+ * kind 1 (default): `steps` Chebyshev steps (default 10) on the Jacobi-scaled
+ * operator; kind 2: one multigrid V-cycle (2 x 2 cell aggregates, coarse rows
+ * with the children's row sums and half their couplings across each side,
+ * `steps` weighted-Jacobi sweeps before and after each coarse correction).
+ * 1 <= steps <= 64.  The correction's systems have no
+ * angular coupling and use the block inverse alone. */
+grte_status grte2d_set_isotropic_correction(grte2d_ctx *ctx, int kind, int steps);
 
 /* Storage of the state between steps: fp32 = 1 keeps E (as its deviation from
  * a c T^4) and O^x, O^y in binary32 -- each step reads the stored values widened

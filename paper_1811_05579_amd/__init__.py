@@ -614,9 +614,17 @@ class Grte2D:
                                                              rows.shape[0], ctypes.byref(n)))
         return int(n.value)
 
-    def set_isotropic_correction(self, steps=10):
-        """Chebyshev steps of the preconditioner's isotropic (diffusion) correction; 0 = off."""
-        check("grte2d_set_isotropic_correction", self._lib.grte2d_set_isotropic_correction(self._h, int(steps)))
+    def set_isotropic_correction(self, kind="chebyshev", steps=None):
+        """The prediction preconditioner's isotropic (diffusion) correction:
+        'none', 'chebyshev' (steps: Chebyshev steps, default 10) or 'multigrid'
+        (steps: Jacobi sweeps before and after each coarse correction, default 2)."""
+        kinds = {"none": 0, "chebyshev": 1, "multigrid": 2}
+        if kind not in kinds:
+            raise ValueError(f"kind must be one of {sorted(kinds)}")
+        if steps is None:
+            steps = 10 if kind == "chebyshev" else 2
+        check("grte2d_set_isotropic_correction",
+              self._lib.grte2d_set_isotropic_correction(self._h, kinds[kind], int(steps)))
 
     def set_profiling(self, on=True):
         check("grte2d_set_profiling", self._lib.grte2d_set_profiling(self._h, int(bool(on))))

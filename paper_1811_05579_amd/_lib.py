@@ -153,7 +153,7 @@ _SIGS = {
     "grte2d_step": (c_int, [c_void_p, c_double, c_double, ctypes.POINTER(StepInfo2D)]),
     "grte2d_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
     "grte2d_set_profiling": (c_int, [c_void_p, c_int]),
-    "grte2d_set_isotropic_correction": (c_int, [c_void_p, c_int]),
+    "grte2d_set_isotropic_correction": (c_int, [c_void_p, c_int, c_int]),
     "grte2d_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
     "grte2d_set_storage": (c_int, [c_void_p, c_int]),
     "grte2d_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),

@@ -582,6 +582,139 @@ __global__ void __launch_bounds__(B2) iso_step_kernel(IsoArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// the isotropic operator by multigrid: Galerkin coarse operators of 2 x 2 cell
+// aggregates (piecewise-constant prolongation, summing restriction), weighted
+// Jacobi smoothing, one V-cycle per application -- again a fixed linear map.
+// Each level stores its 5-point rows: diagonal d and the couplings wl, wr, wb, wt
+// to the left, right, bottom and top neighbours (zero at a wall).
+// ---------------------------------------------------------------------------
+struct MgRows {
+    int nx, ny;
+    double *d, *wl, *wr, *wb, *wt;
+};
+
+constexpr double MG_COUPLE = 0.5;   // coarse coupling = this x the summed fine couplings across a side
+
+__global__ void __launch_bounds__(B2) mg_fine_kernel(IsoArgs A, MgRows L)
+{
+    const Sys &S = A.S;
+    const int n = S.nx * S.ny;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        int iy, ix;
+        cell_yx(S, j, iy, ix);
+        const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
+        const double k = S.kco[j];
+        const double cx = A.Mxx * S.idx * S.idx, cy = A.Myy * S.idy * S.idy;
+        double gl = S.gx[fl], gr = S.gx[fl + 1], gb = S.gy[fb], gt = S.gy[fb + S.nx];
+        double ed = 0.0;
+        const double e2 = S.k2 * S.fe;
+        if (ix == 0) { gr *= 2.0; gl = 0.0; ed += e2 * A.Sx * S.idx; }
+        else if (ix == S.nx - 1) { gl *= 2.0; gr = 0.0; ed += e2 * A.Sx * S.idx; }
+        if (iy == 0) { gt *= 2.0; gb = 0.0; ed += e2 * A.Sy * S.idy; }
+        else if (iy == S.ny - 1) { gb *= 2.0; gt = 0.0; ed += e2 * A.Sy * S.idy; }
+        L.d[j] = S.W1 * S.dmg[j] + k * (cx * (gl + gr) + cy * (gb + gt) + ed);
+        L.wl[j] = -k * cx * gl;
+        L.wr[j] = -k * cx * gr;
+        L.wb[j] = -k * cy * gb;
+        L.wt[j] = -k * cy * gt;
+    }
+}
+
+// coarse rows: the children's row sums (absorption and inflow terms) add up; a
+// coupling to a neighbouring aggregate is half the sum of the children's
+// couplings across that side (the rediscretised coarse operator: two fine faces
+// of unchanged face/distance ratio make one coarse face); the diagonal closes the
+// row with the same row sum
+__global__ void __launch_bounds__(B2) mg_coarsen_kernel(MgRows F, MgRows C)
+{
+    const int n = C.nx * C.ny;
+    for (int J = blockIdx.x * B2 + threadIdx.x; J < n; J += gridDim.x * B2) {
+        const int cy = J / C.nx, cx = J - cy * C.nx;
+        const int x0 = 2 * cx, x1 = min(2 * cx + 1, F.nx - 1), y0 = 2 * cy, y1 = min(2 * cy + 1, F.ny - 1);
+        double rs = 0.0, wl = 0.0, wr = 0.0, wb = 0.0, wt = 0.0;
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const int c = y * F.nx + x;
+                rs += F.d[c] + F.wl[c] + F.wr[c] + F.wb[c] + F.wt[c];
+                if (x - 1 < x0) wl += F.wl[c];
+                if (x + 1 > x1) wr += F.wr[c];
+                if (y - 1 < y0) wb += F.wb[c];
+                if (y + 1 > y1) wt += F.wt[c];
+            }
+        wl *= MG_COUPLE;
+        wr *= MG_COUPLE;
+        wb *= MG_COUPLE;
+        wt *= MG_COUPLE;
+        C.d[J] = rs - (wl + wr + wb + wt);
+        C.wl[J] = wl;
+        C.wr[J] = wr;
+        C.wb[J] = wb;
+        C.wt[J] = wt;
+    }
+}
+
+__device__ __forceinline__ double mg_Az(const MgRows &L, const double *z, int j, int x, int y)
+{
+    double a = L.d[j] * z[j];
+    if (x > 0) a += L.wl[j] * z[j - 1];
+    if (x < L.nx - 1) a += L.wr[j] * z[j + 1];
+    if (y > 0) a += L.wb[j] * z[j - L.nx];
+    if (y < L.ny - 1) a += L.wt[j] * z[j + L.nx];
+    return a;
+}
+
+// one weighted Jacobi sweep: zout = zin + om (b - A zin) / d  (zin = null: zero)
+__global__ void __launch_bounds__(B2) mg_jacobi_kernel(MgRows L, const double *b, const double *zin, double *zout,
+                                                       double om, const int *fl)
+{
+    if (fl[F_STATE] != 0) return;
+    const int n = L.nx * L.ny;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        const int y = j / L.nx, x = j - y * L.nx;
+        const double z = zin ? zin[j] : 0.0;
+        const double az = zin ? mg_Az(L, zin, j, x, y) : 0.0;
+        zout[j] = z + om * (b[j] - az) / L.d[j];
+    }
+}
+
+// coarse right-hand side: the sum of the children's residuals b - A z
+__global__ void __launch_bounds__(B2) mg_restrict_kernel(MgRows F, const double *b, const double *z, MgRows C,
+                                                         double *bc, const int *fl)
+{
+    if (fl[F_STATE] != 0) return;
+    const int n = C.nx * C.ny;
+    for (int J = blockIdx.x * B2 + threadIdx.x; J < n; J += gridDim.x * B2) {
+        const int cy = J / C.nx, cx = J - cy * C.nx;
+        const int x0 = 2 * cx, x1 = min(2 * cx + 1, F.nx - 1), y0 = 2 * cy, y1 = min(2 * cy + 1, F.ny - 1);
+        double r = 0.0;
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const int c = y * F.nx + x;
+                r += b[c] - mg_Az(F, z, c, x, y);
+            }
+        bc[J] = r;
+    }
+}
+
+// z += (coarse correction of the parent aggregate)
+__global__ void __launch_bounds__(B2) mg_prolong_kernel(MgRows F, double *z, MgRows C, const double *zc,
+                                                        const int *fl)
+{
+    if (fl[F_STATE] != 0) return;
+    const int n = F.nx * F.ny;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        const int y = j / F.nx, x = j - y * F.nx;
+        z[j] += zc[(y >> 1) * C.nx + (x >> 1)];
+    }
+}
+
+__global__ void __launch_bounds__(B2) copy_kernel(double *dst, const double *src, int n, const int *fl)
+{
+    if (fl[F_STATE] != 0) return;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) dst[j] = src[j];
+}
+
 // sum of the partials of dot k over nb blocks, in a fixed order (one block of B2 threads)
 __device__ __forceinline__ double fin_sum(const double *part, int k, int nb)
 {
@@ -910,7 +1043,14 @@ struct grte2d_ctx {
     int stepped = 0;
     double last_eps = 0, last_dt = 0;
     // isotropic correction of the preconditioner
-    int iso_k = 10;                      // Chebyshev steps (0: off)
+    int iso_kind = 1;                    // 0 none, 1 Chebyshev, 2 multigrid V-cycle
+    int iso_k = 10;                      // Chebyshev steps
+    int mg_nu = 2;                       // multigrid: Jacobi sweeps before and after the coarse correction
+    struct Lv {
+        MgRows R;
+        double *b, *z0, *z1;
+    };
+    std::vector<Lv> mg;
     double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
     double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
     // sampled timing of the operator kernel (first iteration of every chunk)
@@ -998,8 +1138,73 @@ grte_status convert2d(grte2d_ctx *c, int to32)
     return hipGetLastError() == hipSuccess ? GRTE_OK : GRTE_E_HIP;
 }
 
+IsoArgs iso_args(grte2d_ctx *c, const Sys &S)
+{
+    IsoArgs I;
+    I.S = S;
+    I.Mxx = c->Mxx;
+    I.Myy = c->Myy;
+    I.Sx = c->Sx;
+    I.Sy = c->Sy;
+    I.fl = c->fl;
+    I.y = nullptr;
+    I.xin = nullptr;
+    I.xout = nullptr;
+    I.d = c->idir;
+    I.c1 = I.c2 = I.th = 0.0;
+    return I;
+}
+
+// rows of every multigrid level for the current prediction system
+void mg_setup(grte2d_ctx *c, const Sys &S, hipStream_t st)
+{
+    hipLaunchKernelGGL(mg_fine_kernel, dim3(nblocks(c->N)), dim3(B2), 0, st, iso_args(c, S), c->mg[0].R);
+    for (size_t l = 1; l < c->mg.size(); ++l) {
+        const MgRows &C = c->mg[l].R;
+        hipLaunchKernelGGL(mg_coarsen_kernel, dim3(nblocks((size_t)C.nx * C.ny)), dim3(B2), 0, st, c->mg[l - 1].R,
+                           C);
+    }
+}
+
+constexpr double MG_OMEGA = 0.8;       // Jacobi damping
+constexpr int MG_COARSE_SWEEPS = 40;   // on the coarsest level (at most 4 x 4 cells on a side)
+
+// k Jacobi sweeps on level L for right-hand side b, from z = 0 (zero) or from the
+// values in L.z0; the result is left in L.z0
+void mg_sweeps(grte2d_ctx *c, grte2d_ctx::Lv &L, const double *b, int k, bool zero, hipStream_t st)
+{
+    const int nb = nblocks((size_t)L.R.nx * L.R.ny);
+    double *cur = zero ? nullptr : L.z0;
+    for (int i = 0; i < k; ++i) {
+        double *dst = (cur == L.z0) ? L.z1 : L.z0;
+        hipLaunchKernelGGL(mg_jacobi_kernel, dim3(nb), dim3(B2), 0, st, L.R, b, (const double *)cur, dst, MG_OMEGA,
+                           (const int *)c->fl);
+        cur = dst;
+    }
+    if (cur == L.z1)
+        hipLaunchKernelGGL(copy_kernel, dim3(nb), dim3(B2), 0, st, L.z0, (const double *)L.z1,
+                           L.R.nx * L.R.ny, (const int *)c->fl);
+}
+
+void mg_vcycle(grte2d_ctx *c, size_t l, const double *b, hipStream_t st)
+{
+    grte2d_ctx::Lv &L = c->mg[l];
+    if (l + 1 == c->mg.size()) {
+        mg_sweeps(c, L, b, MG_COARSE_SWEEPS, true, st);
+        return;
+    }
+    mg_sweeps(c, L, b, c->mg_nu, true, st);
+    grte2d_ctx::Lv &C = c->mg[l + 1];
+    hipLaunchKernelGGL(mg_restrict_kernel, dim3(nblocks((size_t)C.R.nx * C.R.ny)), dim3(B2), 0, st, L.R, b,
+                       (const double *)L.z0, C.R, C.b, (const int *)c->fl);
+    mg_vcycle(c, l + 1, C.b, st);
+    hipLaunchKernelGGL(mg_prolong_kernel, dim3(nblocks((size_t)L.R.nx * L.R.ny)), dim3(B2), 0, st, L.R, L.z0, C.R,
+                       (const double *)C.z0, (const int *)c->fl);
+    mg_sweeps(c, L, b, c->mg_nu, false, st);
+}
+
 // K Chebyshev steps for D z = y; the result lands in out (tmp is scratch)
-void iso_solve(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStream_t st)
+void iso_cheb(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStream_t st)
 {
     const int K = c->iso_k;
     const int nbc = nblocks(c->N);
@@ -1031,6 +1236,20 @@ void iso_solve(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStr
     }
 }
 
+void iso_solve(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStream_t st)
+{
+    if (c->iso_kind == 1) {
+        iso_cheb(c, S, y, out, st);
+        return;
+    }
+    // one V-cycle; level 0's result buffer is `out`
+    grte2d_ctx::Lv &L0 = c->mg[0];
+    double *keep = L0.z0;
+    L0.z0 = out;
+    mg_vcycle(c, 0, y, st);
+    L0.z0 = keep;
+}
+
 // BiCGStab on the system currently described by the coefficient arrays; x holds
 // the start and receives the solution.  Returns iterations, state and the
 // final true relative residual.
@@ -1058,7 +1277,8 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.maxit = c->maxit;
     // the isotropic correction targets the angular coupling of the prediction;
     // the correction's systems have none
-    const bool iso = c->iso_k > 0 && !S.corr;
+    const bool iso = c->iso_kind != 0 && !S.corr;
+    if (iso && c->iso_kind == 2) mg_setup(c, S, c->stream);
     A.dP = iso ? c->dP : nullptr;
     A.dS = iso ? c->dS : nullptr;
     A.yP = iso ? c->yP : nullptr;
@@ -1200,6 +1420,21 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
     }
     c->N = (size_t)c->nx * c->ny;
     c->nE = c->N * P;
+    // multigrid levels of the isotropic correction: halve while both sides exceed 4
+    {
+        int lx = c->nx, ly = c->ny;
+        while (true) {
+            grte2d_ctx::Lv L;
+            L.R.nx = lx;
+            L.R.ny = ly;
+            L.R.d = L.R.wl = L.R.wr = L.R.wb = L.R.wt = nullptr;
+            L.b = L.z0 = L.z1 = nullptr;
+            c->mg.push_back(L);
+            if (lx <= 4 || ly <= 4 || c->mg.size() >= 16) break;
+            lx = (lx + 1) / 2;
+            ly = (ly + 1) / 2;
+        }
+    }
     c->nOx = (size_t)c->ny * (c->nx + 1) * P;
     c->nOy = (size_t)(c->ny + 1) * c->nx * P;
     const size_t nfx = (size_t)c->ny * (c->nx + 1), nfy = (size_t)(c->ny + 1) * c->nx;
@@ -1215,6 +1450,16 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
               dalloc(c, c->sab, c->N) && dalloc(c, c->ue, c->N) &&
               dalloc(c, c->yP, c->N) && dalloc(c, c->yS, c->N) && dalloc(c, c->dP, c->N) &&
               dalloc(c, c->rstar, c->N) &&
+              [&] {
+                  for (auto &L : c->mg) {
+                      const size_t m = (size_t)L.R.nx * L.R.ny;
+                      if (!(dalloc(c, L.R.d, m) && dalloc(c, L.R.wl, m) && dalloc(c, L.R.wr, m) &&
+                            dalloc(c, L.R.wb, m) && dalloc(c, L.R.wt, m) && dalloc(c, L.b, m) &&
+                            dalloc(c, L.z0, m) && dalloc(c, L.z1, m)))
+                          return false;
+                  }
+                  return true;
+              }() &&
               dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
@@ -1306,10 +1551,12 @@ grte_status grte2d_log_pairs(grte2d_ctx *c, float *dev_rows, long long cap_rows,
     return GRTE_OK;
 }
 
-grte_status grte2d_set_isotropic_correction(grte2d_ctx *c, int steps)
+grte_status grte2d_set_isotropic_correction(grte2d_ctx *c, int kind, int steps)
 {
-    if (!c || steps < 0 || steps > 64) return GRTE_E_INVAL;
-    c->iso_k = steps;
+    if (!c || kind < 0 || kind > 2 || steps < 1 || steps > 64) return GRTE_E_INVAL;
+    c->iso_kind = kind;
+    if (kind == 1) c->iso_k = steps;
+    if (kind == 2) c->mg_nu = steps;
     return GRTE_OK;
 }
 
