@@ -56,7 +56,7 @@ struct Sys {
     double dx, dy, eps, fe, W1;
     double idx, idy, inx, k2;            // 1/dx, 1/dy, 1/nx, 2/eps
     const double *mu, *eta, *om, *b;     // pairs and inflow b[4*P]
-    const double *E0, *Ox0, *Oy0;        // E^n, O^n
+    const double *Ox0, *Oy0;             // O^n
     const double *ax, *gx, *ay, *gy;     // face alpha, gamma (gamma includes fe)
     const double *lam, *dmg, *cg, *kco;  // cell: Lambda, Lambda - g W1, g, K co c dt
     const double *rb1, *rb0, *acU;       // rhs = rb1 E^n_p + rb0; acU (correction's known part)
@@ -198,7 +198,7 @@ struct CoefArgs {
     int nx, ny, m, corr;
     double a, c, cv, eps, dt, fe, W1;
     const double *T, *sigma0;
-    double *ax, *gx, *ay, *gy, *lam, *dmg, *cg, *kco, *rb0, *acU, *beta, *sab, *ue;
+    double *ax, *gx, *ay, *gy, *lam, *dmg, *cg, *kco, *rb0, *rb1, *acU, *beta, *sab, *ue;
 };
 
 
@@ -228,6 +228,7 @@ __global__ void __launch_bounds__(B2) coef2d_kernel(CoefArgs A)
             // Lambda - g W1 formed directly: K eps^2 + sigma0 c dt / (1 + ac beta) + g (1 - W1)
             A.dmg[j] = K * e2 + s0 * cdt / (1.0 + ac * beta) + g * (1.0 - A.W1);
             A.kco[j] = K * e2 * cdt;
+            A.rb1[j] = K * e2;
             A.rb0[j] = s0 * cdt * ac * U / (1.0 + ac * beta);
             A.sab[j] = s0 * cdt / (1.0 + ac * beta);
             A.ue[j] = ac * U;
@@ -235,6 +236,7 @@ __global__ void __launch_bounds__(B2) coef2d_kernel(CoefArgs A)
             A.cg[j] = 0.0;
             A.dmg[j] = lam;
             A.kco[j] = K * A.eps * cdt;
+            A.rb1[j] = K * A.eps;
             A.rb0[j] = -K * A.eps * ac * U;
             A.acU[j] = ac * U;
             A.sab[j] = s0 * cdt;
@@ -1102,7 +1104,6 @@ Sys make_sys(grte2d_ctx *c, int corr, double eps)
     S.eta = c->eta;
     S.om = c->om;
     S.b = c->b;
-    S.E0 = c->E;
     S.Ox0 = c->Ox;
     S.Oy0 = c->Oy;
     S.ax = c->ax;
@@ -1119,12 +1120,6 @@ Sys make_sys(grte2d_ctx *c, int corr, double eps)
     S.sab = c->sab;
     S.ue = c->ue;
     return S;
-}
-
-__global__ void rb1_kernel(double *rb1, const double *T, int m, double f, int n)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) rb1[j] = (m == 0 ? 1.0 : T[j] * T[j] * T[j]) * f;
 }
 
 // widen (to32 = 0) or round (to32 = 1) the state held in E, Ox, Oy with temperature T
@@ -1704,9 +1699,8 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     ca.beta = c->beta;
     ca.sab = c->sab;
     ca.ue = c->ue;
+    ca.rb1 = c->rb1;
     hipLaunchKernelGGL(coef2d_kernel, dim3(nbc), dim3(B2), 0, st, ca);
-    hipLaunchKernelGGL(rb1_kernel, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, st, c->rb1, c->T, c->m,
-                       eps * eps, (int)c->N);
     Sys Sp = make_sys(c, 0, eps);
     {
         VecArgs A;
@@ -1762,8 +1756,6 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     ca.fe = eps;
     ca.T = c->T1;
     hipLaunchKernelGGL(coef2d_kernel, dim3(nbc), dim3(B2), 0, st, ca);
-    hipLaunchKernelGGL(rb1_kernel, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, st, c->rb1, c->T1, c->m,
-                       eps, (int)c->N);
     Sys Sc = make_sys(c, 1, eps);
     {
         VecArgs A;
