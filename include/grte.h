@@ -125,6 +125,14 @@ grte_status grte_set_state(grte_ctx *ctx, const double *E, const double *O,
  * three pointers may be NULL to skip it. */
 grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int on_device);
 
+/* Cell-centre intensities of the current state: I[j*2P + p] = I(+mu_p) and
+ * I[j*2P + P + p] = I(-mu_p), i.e. E_{j,p} + eps (O_{j,p} + O_{j+1,p})/2 and
+ * E_{j,p} - eps (O_{j,p} + O_{j+1,p})/2: the parities (4.2) with O interpolated to
+ * the cell centre as in the inflow relations (4.6); eps > 0 the scaling of the
+ * state.  I holds 2 N P doubles
+ * (host or device).  With binary32 storage, of the stored state. */
+grte_status grte_get_intensity(grte_ctx *ctx, double eps, double *I, int on_device);
+
 /* One AP step of Algorithm 2 with time step dt > 0 and eps > 0.  The state is
  * replaced by (E^{n+1}, O^{n+1}, T^{n+1}).  With info == NULL the call only
  * enqueues work; otherwise it synchronises and fills *info.  Returns
@@ -567,6 +575,12 @@ grte_status grte2d_step(grte2d_ctx *ctx, double dt, double eps, grte2d_step_info
  * number of timed launches since the last grte2d_set_profiling call. */
 grte_status grte2d_set_profiling(grte2d_ctx *ctx, int on);
 grte_status grte2d_read_timing(grte2d_ctx *ctx, double *ms, int *count);
+
+/* Cell-centre intensities of the current state: I[c*2P + p] = I(+Omega_p) and
+ * I[c*2P + P + p] = I(-Omega_p) for cell c = iy*nx + ix, E_p +- eps O_p with O at
+ * the cell centre the mean of the cell's four face values; eps > 0 the scaling
+ * of the state.  I holds 2 nx ny P doubles (host or device). */
+grte_status grte2d_get_intensity(grte2d_ctx *ctx, double eps, double *I, int on_device);
 
 /* A stage of the last step (GRTE2D_STAGE_*). */
 grte_status grte2d_get_stage(grte2d_ctx *ctx, int which, double *out, int on_device);

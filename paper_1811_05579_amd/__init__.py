@@ -146,6 +146,12 @@ class Grte:
             return out.reshape(self.N + 1, self.P)
         return out
 
+    def get_intensity(self, eps):
+        """Cell-centre intensities (N, 2P): columns p = I(+mu_p), P + p = I(-mu_p)."""
+        out = np.empty((self.N, 2 * self.P))
+        check("grte_get_intensity", self._lib.grte_get_intensity(self._h, float(eps), out.ctypes.data, 0))
+        return out
+
     def set_profiling(self, on=True):
         """True or 1: time every step; k >= 2: every k-th step; False or 0: off."""
         k = int(on) if not isinstance(on, bool) else int(on)
@@ -634,6 +640,12 @@ class Grte2D:
         ms, n = ctypes.c_double(), ctypes.c_int()
         check("grte2d_read_timing", self._lib.grte2d_read_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def get_intensity(self, eps):
+        """Cell-centre intensities (ny, nx, 2P): [..., p] = I(+Omega_p), [..., P + p] = I(-Omega_p)."""
+        out = np.empty((self.ny, self.nx, 2 * self.P))
+        check("grte2d_get_intensity", self._lib.grte2d_get_intensity(self._h, float(eps), out.ctypes.data, 0))
+        return out
 
     def get_stage(self, name):
         shape = (self.ny, self.nx, self.P) if name == "E_star" else (self.ny, self.nx)

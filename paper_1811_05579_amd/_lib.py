@@ -91,6 +91,7 @@ _SIGS = {
     "grte_step_group": (c_int, [ctypes.POINTER(c_void_p), c_int, c_void_p, c_void_p,
                                 ctypes.POINTER(StepInfo)]),
     "grte_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
+    "grte_get_intensity": (c_int, [c_void_p, c_double, c_void_p, c_int]),
     "grte_set_solver": (c_int, [c_void_p, c_double, c_int, c_int]),
     "grte_set_acceleration": (c_int, [c_void_p, c_int]),
     "grte_get_pred_history": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
@@ -152,6 +153,7 @@ _SIGS = {
     "grte2d_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     "grte2d_step": (c_int, [c_void_p, c_double, c_double, ctypes.POINTER(StepInfo2D)]),
     "grte2d_get_stage": (c_int, [c_void_p, c_int, c_void_p, c_int]),
+    "grte2d_get_intensity": (c_int, [c_void_p, c_double, c_void_p, c_int]),
     "grte2d_set_profiling": (c_int, [c_void_p, c_int]),
     "grte2d_set_isotropic_correction": (c_int, [c_void_p, c_int, c_int]),
     "grte2d_set_guess": (c_int, [c_void_p, c_void_p, c_double]),

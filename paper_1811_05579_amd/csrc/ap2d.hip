@@ -828,6 +828,23 @@ __global__ void __launch_bounds__(B2) conv2d_kernel(int nE, int nOx, int nOy, in
     }
 }
 
+// cell-centre intensities I(+-Omega_p) = E_p +- eps O_p, O at the cell centre the
+// mean of its four faces; out[c*2P + p] = I(+Omega_p), out[c*2P + P + p] = I(-Omega_p)
+__global__ void __launch_bounds__(B2) intensity2d_kernel(int nx, int ny, int lgP, double eps, const double *E,
+                                                         const double *Ox, const double *Oy, double *out)
+{
+    const int P = 1 << lgP;
+    const int n = nx * ny * P;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < n; t += gridDim.x * B2) {
+        const int j = t >> lgP, p = t & (P - 1);
+        const int iy = j / nx, ix = j - iy * nx;
+        const int fl = iy * (nx + 1) + ix, fb = iy * nx + ix;
+        const double oc = 0.25 * (Ox[fl * P + p] + Ox[(fl + 1) * P + p] + Oy[fb * P + p] + Oy[(fb + nx) * P + p]);
+        out[j * 2 * P + p] = E[t] + eps * oc;
+        out[j * 2 * P + P + p] = E[t] - eps * oc;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // correction substep 1: moments, D, U*, K*, scalar Newton per cell
 // ---------------------------------------------------------------------------
@@ -1034,6 +1051,7 @@ struct grte2d_ctx {
     int *h_fl = nullptr;      // pinned
     double *h_sc = nullptr;   // pinned
     std::vector<void *> allocs;
+    double *ibuf = nullptr;              // intensity readout for host destinations
     // binary32 storage of the state between steps (0: binary64)
     int f32 = 0;
     float *E32 = nullptr, *Ox32 = nullptr, *Oy32 = nullptr;
@@ -1638,6 +1656,28 @@ grte_status grte2d_get_state(grte2d_ctx *c, double *E, double *Ox, double *Oy, d
         (T && hipMemcpyAsync(T, c->T, c->N * sizeof(double), k, st) != hipSuccess))
         return GRTE_E_HIP;
     return hip_ok(hipStreamSynchronize(st));
+}
+
+grte_status grte2d_get_intensity(grte2d_ctx *c, double eps, double *I, int on_device)
+{
+    if (!c || !I || !(eps > 0.0) || !std::isfinite(eps)) return GRTE_E_INVAL;
+    if (c->f32) {   // the stored state
+        grte_status s = convert2d(c, 0);
+        if (s != GRTE_OK) return s;
+    }
+    int lgP = 0;
+    while ((1 << lgP) < c->P) ++lgP;
+    // a host destination is filled from a device buffer of 2 N P doubles,
+    // allocated on first use
+    if (!on_device && !c->ibuf && !dalloc(c, c->ibuf, 2 * c->nE)) return GRTE_E_NOMEM;
+    double *dst = on_device ? I : c->ibuf;
+    hipLaunchKernelGGL(intensity2d_kernel, dim3(nblocks(2 * c->nE)), dim3(B2), 0, c->stream, c->nx, c->ny, lgP, eps,
+                       (const double *)c->E, (const double *)c->Ox, (const double *)c->Oy, dst);
+    if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
+    if (!on_device &&
+        hipMemcpyAsync(I, dst, 2 * c->nE * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return GRTE_E_HIP;
+    return hip_ok(hipStreamSynchronize(c->stream));
 }
 
 grte_status grte2d_get_stage(grte2d_ctx *c, int which, double *out, int on_device)

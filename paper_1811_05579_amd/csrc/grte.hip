@@ -760,6 +760,20 @@ __global__ void node_all_kernel(int N, int P, double eps, const double *E, const
     Oout[t] = node_any(E, O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, i, p);
 }
 
+// cell-centre intensities from the parities (4.2): I(+-mu_p) = E_p +- eps O_p, O
+// interpolated to the cell centre as the mean of the cell's two nodes (the
+// interpolation of the inflow relations (4.6)); out[j*2P + p] = I(+mu_p),
+// out[j*2P + P + p] = I(-mu_p)
+__global__ void intensity_kernel(int N, int P, double eps, const double *E, const double *O, double *out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * P) return;
+    const int j = t / P, p = t - j * P;
+    const double oc = 0.5 * (O[(size_t)j * P + p] + O[(size_t)(j + 1) * P + p]);
+    out[(size_t)j * 2 * P + p] = E[t] + eps * oc;
+    out[(size_t)j * 2 * P + P + p] = E[t] - eps * oc;
+}
+
 // between binary64 state arrays and binary32 storage (E as the deviation from a c T^4)
 __global__ void convert_state_kernel(int N, int P, double ac, const double *T, double *E, double *O, float *E32,
                                      float *O32, int to32)
@@ -811,6 +825,7 @@ struct grte_ctx {
     // the binary64 E, O buffers then serve as scratch
     int f32 = 0;
     float *E32 = nullptr, *E32b = nullptr, *O32 = nullptr, *O32b = nullptr;
+    double *ibuf = nullptr;                // intensity readout (2 N P), allocated on first use
     // learned initial guess of the temperature solve (borrowed from a grte_mlp)
     const uint16_t *guess_w = nullptr;
     const float *guess_norm = nullptr;
@@ -1204,6 +1219,32 @@ grte_status grte_get_state(grte_ctx *ctx, double *E, double *O, double *T, int o
     if (s == GRTE_OK && O) s = copy_out(ctx, O, ctx->O, (N + 1) * P, on_device);
     if (s == GRTE_OK && T) s = copy_out(ctx, T, ctx->T, N, on_device);
     return s;
+}
+
+grte_status grte_get_intensity(grte_ctx *ctx, double eps, double *I, int on_device)
+{
+    if (!ctx || !I || !(eps > 0.0) || !std::isfinite(eps)) return GRTE_E_INVAL;
+    const size_t N = ctx->N, P = ctx->P;
+    if (ctx->f32) {
+        grte_status s = convert_state(ctx, 0);   // binary64 values of the stored state
+        if (s != GRTE_OK) return s;
+    }
+    double *dst = I;
+    if (!on_device) {
+        if (!ctx->ibuf) {
+            void *q = nullptr;
+            if (hipMalloc(&q, 2 * N * P * sizeof(double)) != hipSuccess) return GRTE_E_NOMEM;
+            ctx->allocs.push_back((double *)q);
+            ctx->ibuf = (double *)q;
+        }
+        dst = ctx->ibuf;
+    }
+    hipLaunchKernelGGL(intensity_kernel, dim3((unsigned)((N * P + 255) / 256)), dim3(256), 0, ctx->stream, (int)N,
+                       (int)P, eps, ctx->E, ctx->O, dst);
+    HIPCHK(hipGetLastError());
+    if (!on_device) return copy_out(ctx, I, dst, 2 * N * P, 0);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return GRTE_OK;
 }
 
 grte_status grte_get_pred_history(grte_ctx *ctx, double *out, int cap, int *n)

@@ -253,3 +253,22 @@ def test_isotropic_correction_variants_agree(kind, steps):
         g.close()
     for a, b in zip(out[0], out[1]):
         assert _rel(b, a) < 1e-10
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_intensity_readout_2d(fp32):
+    """I(+-Omega_p) at the cell centres from the library equals the oracle's
+    readout (E +- eps times the mean of the four face values of O)."""
+    w = _two_material(20, 16, (1.0, 100.0), 1e-2, 18110000 + 3)
+    g = _ctx(w)
+    g.set_storage(fp32)
+    g.set_state(w.E, w.Ox, w.Oy, w.T)
+    for _ in range(3):
+        g.step(w.dt, w.eps)
+    E, Ox, Oy, T = g.get_state()
+    I = g.get_intensity(w.eps)
+    g.close()
+    ip, im = ap2d.intensity(E, Ox, Oy, w.eps)
+    scale = np.max(np.abs(ip))
+    assert np.max(np.abs(I[:, :, :w.P] - ip)) <= 4e-16 * scale
+    assert np.max(np.abs(I[:, :, w.P:] - im)) <= 4e-16 * scale

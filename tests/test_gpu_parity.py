@@ -235,3 +235,23 @@ def test_profiling_samples_every_kth_step():
     with pytest.raises(Exception):
         g.set_profiling(-1)
     g.close()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_intensity_readout(fp32):
+    """I(+-mu_p) at the cell centres from the library equals the oracle's readout
+    (4.2) of the same state, for binary64 and binary32 storage."""
+    from oracle.ap1d import intensity
+    w = config1()
+    g = _ctx(w)
+    g.set_storage(fp32)
+    g.set_state(w.E, w.O, w.T)
+    for _ in range(3):
+        g.step(w.dt, w.eps)
+    E, O, T = g.get_state()
+    I = g.get_intensity(w.eps)
+    g.close()
+    ip, im = intensity(E, O, w.eps)
+    scale = np.max(np.abs(ip))
+    assert np.max(np.abs(I[:, :w.P] - ip)) <= 4e-16 * scale
+    assert np.max(np.abs(I[:, w.P:] - im)) <= 4e-16 * scale
