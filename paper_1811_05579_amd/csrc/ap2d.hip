@@ -1788,8 +1788,10 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     na.gw = c->guess_w;
     na.gnorm = c->guess_norm;
     na.gtol = c->guess_tol;
-    if (c->guess_w) hipLaunchKernelGGL(newton2d_kernel<true>, dim3(nb), dim3(B2), 0, st, na);
-    else hipLaunchKernelGGL(newton2d_kernel<false>, dim3(nb), dim3(B2), 0, st, na);
+    // (fewer, longer-lived blocks: one atomic per wavefront and counter)
+    const int nbn = std::min(nb, 2048);
+    if (c->guess_w) hipLaunchKernelGGL(newton2d_kernel<true>, dim3(nbn), dim3(B2), 0, st, na);
+    else hipLaunchKernelGGL(newton2d_kernel<false>, dim3(nbn), dim3(B2), 0, st, na);
 
     // ---- correction, substep 2 (4.11) with K^{n+1}, U^{n+1}
     ca.corr = 1;
