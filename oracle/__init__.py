@@ -21,5 +21,7 @@ ap2d         The same step on a 2-D rectangle (staggered parity reading:
 diffusion1d  The three-stage diffusion scheme (2.7) / its sigma/T^3 form, the
              two-stage counter-example (2.8), and the fully implicit
              reference solvers (6.1) and (6.7).
+diffusion2d  The three-stage scheme (2.7)/(2.9) on a 2-D rectangle (the eps -> 0
+             reference of ap2d).
 energy       Energy bookkeeping used by the conservation pins, (3.12)-(3.13).
 """

@@ -13,7 +13,10 @@
   (which fixes the cross-derivative terms the two pins above cannot see);
 * the per-cell conservation identity of the full step (the 2-D form of (3.13))
   and the telescoping of the flux divergence into the boundary outflow;
-* every cell's temperature is the root of (4.13) (bisection on [0, s]).
+* every cell's temperature is the root of (4.13) (bisection on [0, s]);
+* the thick limit: as eps -> 0 the step tends, at the rate eps^2, to the 2-D
+  three-stage scheme (2.7)/(2.9) whose diffusion coefficient carries the
+  dimension factor <mu^2> = 1/2 (not 1/3).
 """
 import numpy as np
 import pytest
@@ -232,3 +235,37 @@ def test_temperature_is_the_root_of_4_13():
     Tb, _ = bisect_temperature(T.ravel(), r["rho_n"].ravel(), r["D"].ravel(), r["K_star"].ravel(),
                                sig.ravel(), ph)
     np.testing.assert_allclose(r["T"].ravel(), np.asarray(Tb, dtype=np.float64), rtol=4e-16 * 4, atol=0)
+
+
+@pytest.mark.parametrize("m", [0, 3])
+def test_eps_to_zero_reaches_2d_diffusion_limit(m):
+    """A compact bump (IC (6.3)'s shape in 2-D), sigma = 1, zero inflow, dt = 0.1 dx:
+    as eps -> 0 the 2-D AP step tends to the three-stage scheme (2.7)/(2.9) with
+    the 2-D diffusion coefficient ac K <mu^2>/sigma, <mu^2> = 1/2 -- the dimension
+    factor D_d = 2 of the limit -- at the rate eps^2, as the 1-D step does."""
+    from oracle.diffusion2d import three_stage_step
+    n, nv = 14, 8
+    g = ap2d.Grid2D(n, n)
+    mu, eta, om = circle_pairs(nv)
+    P = mu.size
+    xc = (np.arange(n) + 0.5) / n
+    T0 = np.maximum(1 - 40 * ((xc[None, :] - 0.5) ** 2 + (xc[:, None] - 0.5) ** 2), 0.0)
+    b = np.zeros((4, P))
+    diffs, wrong = [], []
+    for eps in (1e-2, 1e-3, 1e-4):
+        ph = Physics(eps=eps, dt=0.1 / n, m=m)
+        T = T0.copy()
+        E = np.repeat((T ** 4)[:, :, None], P, 2)
+        Ox, Oy = np.zeros((n, n + 1, P)), np.zeros((n + 1, n, P))
+        Td, Tw = T0.copy(), T0.copy()
+        for _ in range(6):
+            r = ap2d.ap_step(g, E, Ox, Oy, T, np.ones((n, n)), mu, eta, om, b, ph)
+            E, Ox, Oy, T = r["E"], r["Ox"], r["Oy"], r["T"]
+            Td, _ = three_stage_step(Td, np.ones((n, n)), ph.dt, m=m, mu2=0.5)
+            Tw, _ = three_stage_step(Tw, np.ones((n, n)), ph.dt, m=m, mu2=1.0 / 3.0)
+        diffs.append(np.max(np.abs(T - Td)))
+        wrong.append(np.max(np.abs(T - Tw)))
+    assert diffs[2] < 1e-5, diffs
+    assert diffs[0] / diffs[1] > 50 and diffs[1] / diffs[2] > 50, diffs
+    # the 1-D coefficient (<mu^2> = 1/3) is a different limit
+    assert min(wrong) > 100 * diffs[2], (wrong, diffs)
