@@ -272,3 +272,36 @@ def test_intensity_readout_2d(fp32):
     scale = np.max(np.abs(ip))
     assert np.max(np.abs(I[:, :, :w.P] - ip)) <= 4e-16 * scale
     assert np.max(np.abs(I[:, :, w.P:] - im)) <= 4e-16 * scale
+
+
+@pytest.mark.parametrize("m", [0, 3])
+def test_gpu_step_reaches_the_diffusion_limit(m):
+    """The asymptotic-preserving property on the GPU path, at a grid the
+    transport oracle cannot reach: a compact bump on 48 x 48 cells with 16
+    directions, sigma = 1, zero inflow, dt = 0.1 dx; after six steps the GPU
+    solution tends to the 2-D three-stage scheme (2.7)/(2.9) (<mu^2> = 1/2) at
+    the rate eps^2."""
+    from oracle.diffusion2d import three_stage_step
+    n, nv = 48, 16
+    mu, eta, om = circle_pairs(nv)
+    P = nv // 2
+    xc = (np.arange(n) + 0.5) / n
+    T0 = np.maximum(1 - 40 * ((xc[None, :] - 0.5) ** 2 + (xc[:, None] - 0.5) ** 2), 0.0)
+    diffs = []
+    for eps in (1e-2, 1e-3, 1e-4):
+        w = Workload2D(name=f"bump({eps:g})", nx=n, ny=n, nv=nv, m=m, eps=eps, dt=0.1 / n, steps=6, mu=mu, eta=eta,
+                       omega=om, sigma0=np.ones((n, n)), T=T0.copy(), E=np.repeat((T0 ** 4)[:, :, None], P, 2),
+                       Ox=np.zeros((n, n + 1, P)), Oy=np.zeros((n + 1, n, P)), b=np.zeros((4, P)))
+        g = _ctx(w)
+        g.set_state(w.E, w.Ox, w.Oy, w.T)
+        Td = T0.copy()
+        for _ in range(6):
+            info = g.step(w.dt, eps, info=True)
+            assert info["status"] == 0, info
+            Td, _ = three_stage_step(Td, np.ones((n, n)), w.dt, m=m, mu2=0.5)
+        T = g.get_state()[3]
+        g.close()
+        diffs.append(float(np.max(np.abs(T - Td))))
+    print("max |T_gpu - T_(2.7)|:", diffs, flush=True)
+    assert diffs[2] < 1e-5, diffs
+    assert diffs[0] / diffs[1] > 50 and diffs[1] / diffs[2] > 50, diffs
