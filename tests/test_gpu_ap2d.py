@@ -305,3 +305,29 @@ def test_gpu_step_reaches_the_diffusion_limit(m):
     print("max |T_gpu - T_(2.7)|:", diffs, flush=True)
     assert diffs[2] < 1e-5, diffs
     assert diffs[0] / diffs[1] > 50 and diffs[1] / diffs[2] > 50, diffs
+
+
+@pytest.mark.parametrize("nx,ny,pairs", [
+    (2, 2, ([0.6], [0.8], [1.0])),                      # smallest grid, one pair
+    (3, 2, ([-0.28, 0.8], [0.96, 0.6], [0.5, 0.5])),    # two user pairs, one with mu < 0
+    (2, 5, ([0.6], [0.8], [1.0])),
+])
+def test_degenerate_sizes_match_oracle(nx, ny, pairs):
+    """The smallest grids (every cell an edge cell, corner cells on both kinds of
+    edge) and user-supplied direction pairs, P = 1 and 2."""
+    mu, eta, om = (np.asarray(x, dtype=np.float64) for x in pairs)
+    P = mu.size
+    rng = np.random.default_rng(nx * 10 + ny)
+    T = rng.uniform(0.3, 1.0, (ny, nx))
+    E = (T ** 4)[:, :, None] * rng.uniform(0.9, 1.1, (ny, nx, P))
+    Ox = rng.uniform(-0.1, 0.1, (ny, nx + 1, P))
+    Oy = rng.uniform(-0.1, 0.1, (ny + 1, nx, P))
+    w = Workload2D(name=f"tiny({nx}x{ny}, P={P})", nx=nx, ny=ny, nv=2 * P, m=3, eps=1e-2, dt=0.1, steps=1, mu=mu,
+                   eta=eta, omega=om, sigma0=rng.uniform(0.5, 2.0, (ny, nx)), T=T, E=E, Ox=Ox, Oy=Oy,
+                   b=rng.uniform(0.0, 1.0, (4, P)))
+    g = _ctx(w)
+    r, info = gpu_step(g, w, E, Ox, Oy, T)
+    g.close()
+    assert info["status"] == 0, info
+    o = oracle_step(w, E, Ox, Oy, T)
+    _compare(w, r, o, T)
