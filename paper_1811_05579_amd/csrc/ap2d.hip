@@ -16,9 +16,15 @@
 // where the discrete Omega_p . grad at an x-face is the compact x-difference
 // plus the mean of the two cells' centred y-differences (one-sided at a wall),
 // and the y-faces likewise.  g_c (the angular coupling of (4.5c)) is zero in the
-// correction.  The system is solved matrix-free by BiCGStab with a cell-block
-// Jacobi preconditioner (the P x P block of a cell -- diagonal plus the rank-one
-// coupling -- inverted exactly by the Sherman-Morrison formula), all in binary64.
+// correction.  The system is solved matrix-free by BiCGStab in binary64 with a
+// right preconditioner: the exact inverse of each cell's P x P block (diagonal
+// plus the rank-one coupling, by the Sherman-Morrison formula) and, in the
+// prediction, an isotropic correction -- an approximate inverse of the operator's
+// angular average over isotropic fields (a 5-point diffusion operator) by fixed
+// Chebyshev steps or one multigrid V-cycle.  The true residual is recomputed
+// from the equations after every pass of iterations and the solve restarted from
+// it.  The state between steps may be stored in binary32 (E as its deviation
+// from a c T^4); the arithmetic is binary64 throughout.
 //
 // Data layout (device, binary64): cell-major, pair index fastest:
 //   E[(iy*nx + ix)*P + p], Ox[(iy*(nx+1) + fx)*P + p], Oy[(fy*nx + ix)*P + p].
@@ -1327,6 +1333,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             break;
         }
         if (restart == KRY_RESTARTS || its_total >= c->maxit) break;
+        A.maxit = c->maxit - its_total;    // the cap holds for the whole solve
         while (true) {
             const bool timed = c->profiling != 0;
             for (int k = 0; k < CHUNK; ++k) {
@@ -1378,8 +1385,6 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     floor_out = floor;
     return GRTE_OK;
 }
-
-grte_status check_ctx(const grte2d_ctx *c) { return c ? GRTE_OK : GRTE_E_INVAL; }
 
 }  // namespace
 

@@ -331,3 +331,18 @@ def test_degenerate_sizes_match_oracle(nx, ny, pairs):
     assert info["status"] == 0, info
     o = oracle_step(w, E, Ox, Oy, T)
     _compare(w, r, o, T)
+
+
+def test_iteration_cap_holds_for_the_whole_solve():
+    """With a cap of 5 Krylov iterations the stiff cold-start step stops at the cap
+    (over all restarts) and reports that it did not converge."""
+    w = _two_material(24, 32, (1.0, 100.0), 1e-3, 18110000 + 3)
+    g = _ctx(w)
+    g.set_solver(1e-14, 5)
+    g.set_state(w.E, w.Ox, w.Oy, w.T)
+    first = g.step(w.dt, w.eps, info=True)
+    assert first["pred_iters"] <= 5 and first["corr_iters"] <= 5, first
+    info = g.step(w.dt, w.eps, info=True)  # the spike step (R15) needs the most iterations
+    g.close()
+    assert info["pred_iters"] <= 5 and info["corr_iters"] <= 5, info
+    assert info["status"] == -4 and not info["pred_converged"], info
