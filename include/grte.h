@@ -294,8 +294,8 @@ grte_status grte_log_pairs(grte_ctx *ctx, float *dev_rows, long long cap_rows, l
 
 /* ------------------------------------------------------------------------
  * The discrete nonlinear diffusion limit on the GPU: the three-stage scheme
- * (2.7) (sigma independent of T) and its sigma0/T^3 form (2.9), and the
- * two-stage scheme (2.8).  State T per cell (N <= 4096) on the cell-centred
+ * (2.7) (sigma independent of T) and its sigma0/T^3 form (2.9), the two-stage
+ * scheme (2.8) and the limit of the alternative correction (3.14).  State T per cell (N <= 4096) on the cell-centred
  * grid of the AP step; face coefficients a c K/(3 sigma) with the harmonic
  * mean of sigma0 and the mean of K = T^m of the two cells.  Boundaries:
  * 0 = zero flux, 1 = ghost temperatures one cell outside each end (the
@@ -309,7 +309,11 @@ typedef struct grte_diff_problem {
     int boundary;             /* 0: zero flux; 1: ghost temperatures              */
     double ghost_left, ghost_right;
 } grte_diff_problem;
-enum { GRTE_DIFF_THREE_STAGE = 0, GRTE_DIFF_TWO_STAGE = 1 };
+/* GRTE_DIFF_SEMI_COR: the diffusion limit printed for the alternative correction
+ * (3.14) (remark closing Section 3): the prediction of (2.7)/(2.9), then the
+ * linear update a (U* - U^n)/dt + Cv (T^{n+1} - T^n)/dt = div(F^n grad U*) --
+ * no Newton solve, not energy-conservative, only conditionally stable. */
+enum { GRTE_DIFF_THREE_STAGE = 0, GRTE_DIFF_TWO_STAGE = 1, GRTE_DIFF_SEMI_COR = 2 };
 grte_status grte_diff_create(const grte_diff_problem *pb, grte_diff **out);
 grte_status grte_diff_destroy(grte_diff *d);
 grte_status grte_diff_set_stream(grte_diff *d, void *hip_stream);

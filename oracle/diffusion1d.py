@@ -8,7 +8,13 @@ The AP step must reduce, as eps -> 0, to a discretisation of
                     sigma/T^3 form (2.9) (fully discrete version after (2.9));
   two_stage_step    the counter-example (2.8) (prediction + projection only);
   implicit_step     the fully implicit reference solvers (6.1) (q = 4) and
-                    (6.7) (q = 7), solved by a global Newton iteration.
+                    (6.7) (q = 7), solved by a global Newton iteration;
+  semi_cor_step     the diffusion limit of the alternative correction (3.14)
+                    that the remark closing Section 3 gives: the prediction of
+                    (2.7)/(2.9), then the linear update
+                      a (U* - U^n)/dt + Cv (T - T^n)/dt = div(F^n grad U*)
+                    (no nonlinear solve; the paper reports that it fails for a
+                    T-dependent sigma and is not energy-conservative).
 
 All live on the AP step's cell-centred grid (cells j = 0..N-1 on [0, L],
 interior faces i = 1..N-1 between cells i-1 and i).  A face coefficient at an
@@ -127,6 +133,31 @@ def three_stage_step(T, sigma0, dt, L=1.0, a=1.0, c=1.0, Cv=1.0, m=0,
         _, Fbc = _bc_data(bc, ghost_T, sigma0, Ks, a, c)
     rhs_T = dt * _div_flux(Fc, Us, dx, bc, ghost_U, Fbc) + at * U + Cv * T
     Tn1 = _scalar_quartic(at, Cv, rhs_T, T, maxit)
+    return Tn1, Us
+
+
+def semi_cor_step(T, sigma0, dt, L=1.0, a=1.0, c=1.0, Cv=1.0, m=0, a_time=None, bc="neumann",
+                  ghost_T=(0.0, 0.0)):
+    """One step of the diffusion limit of (3.14): stage 1 of (2.7)/(2.9), then
+        T^{n+1} = T^n + [dt div(F^n grad U*) - a (U* - U^n)] / Cv,
+    the limit equation printed in the remark after (3.13).  Returns (T^{n+1}, U*)."""
+    T = np.asarray(T, dtype=np.float64)
+    sigma0 = np.asarray(sigma0, dtype=np.float64)
+    at = a if a_time is None else a_time
+    N = T.size
+    dx = L / N
+    U = T ** 4
+    Kn = np.ones(N) if m == 0 else T ** m
+    Fint = _face_coeff(Kn, sigma0, m, a, c, from_K=True)
+    ghost_U, Fb = _bc_data(bc, ghost_T, sigma0, Kn, a, c)
+    pref = 4.0 * T ** 3 / (4.0 * at * T ** 3 + Cv)
+    lo, di, up = _diffusion_matrix(Fint, N, dx, bc, Fb)
+    rhs = U.copy()
+    if bc == "dirichlet":
+        rhs[0] += dt * pref[0] * Fb[0] * ghost_U[0] / dx ** 2
+        rhs[-1] += dt * pref[-1] * Fb[1] * ghost_U[1] / dx ** 2
+    Us = _solve_tri(dt * pref * lo, 1.0 + dt * pref * di, dt * pref * up, rhs)
+    Tn1 = T + (dt * _div_flux(Fint, Us, dx, bc, ghost_U, Fb) - at * (Us - U)) / Cv
     return Tn1, Us
 
 

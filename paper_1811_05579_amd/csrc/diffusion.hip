@@ -11,7 +11,10 @@
 //   stage 2   a (T^4 - U^n)/dt + Cv (T - T^n)/dt = the same flux difference of U*, one
 //             scalar Newton per cell (F from K^n, or from (U*)^{3/4} for the printed (2.9));
 //   stage 3   U^{n+1} = (T^{n+1})^4 (the state is T).
-// The two-stage scheme replaces stages 2-3 by T^{n+1} = max(U*, 0)^{1/4}.
+// The two-stage scheme replaces stages 2-3 by T^{n+1} = max(U*, 0)^{1/4}; the
+// limit of the alternative correction (3.14) (the remark closing Section 3)
+// replaces stage 2 by the linear update
+//   a (U* - U^n)/dt + Cv (T^{n+1} - T^n)/dt = the flux difference of U* (F from K^n).
 // Boundaries: zero flux, or ghost temperatures one cell outside the slab with
 // the boundary cell's coefficient on the boundary face.
 
@@ -126,7 +129,10 @@ __global__ void __launch_bounds__(NT) diff_kernel(DiffArgs A)
             if (j <= N - 2) fluxr = fr * (Uat(j + 1) - us) / A.dx;
             else if (A.bc == 1) fluxr = fr * (A.gUR - us) / A.dx;
             const double rhs = A.dt * (fluxr - fluxl) / A.dx + A.at * (Tj * Tj) * (Tj * Tj) + A.cv * Tj;
-            if (A.at == 0.0) {
+            if (A.scheme == 2) {
+                // (3.14): no nonlinear solve, U* in the time derivative
+                Tn1 = Tj + (A.dt * (fluxr - fluxl) / A.dx - A.at * (us - (Tj * Tj) * (Tj * Tj))) / A.cv;
+            } else if (A.at == 0.0) {
                 Tn1 = rhs / A.cv;
             } else {
                 // a_t T^4 + Cv T = rhs: convex and increasing for T >= 0; Newton from a start
@@ -294,7 +300,7 @@ grte_status grte_diff_get_state(grte_diff *dd, double *T, double *Ustar, int on_
 
 grte_status grte_diff_step(grte_diff *dd, double dt, int scheme, int corr_K, double a_time, int *newton_its)
 {
-    if (!dd || !(dt > 0) || !std::isfinite(dt) || (scheme != 0 && scheme != 1) || (corr_K != 0 && corr_K != 1) ||
+    if (!dd || !(dt > 0) || !std::isfinite(dt) || scheme < 0 || scheme > 2 || (corr_K != 0 && corr_K != 1) ||
         !std::isfinite(a_time))
         return GRTE_E_INVAL;
     DiffArgs A{};

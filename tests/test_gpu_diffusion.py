@@ -9,12 +9,17 @@ and the two-stage counter-example (2.8).
   * the front: from compactly supported data the three-stage scheme spreads the
     support, the two-stage scheme leaves it where it was (remark after (2.8));
   * porous-medium limit (a_time = 0): the GPU scheme converges to the
-    Barenblatt closed form under refinement.
+    Barenblatt closed form under refinement;
+  * the limit of the alternative correction (3.14): one step against the
+    oracle, and its properties -- total energy sum(a T^4 + Cv T) drifts where the
+    three-stage scheme keeps it to rounding; on the cold-start front with a hot
+    boundary it blows up at the hyperbolic time step (conditional stability)
+    where the three-stage scheme stays positive.
 """
 import numpy as np
 import pytest
 
-from oracle.diffusion1d import barenblatt, three_stage_step, two_stage_step
+from oracle.diffusion1d import barenblatt, semi_cor_step, three_stage_step, two_stage_step
 from paper_1811_05579_amd import GrteDiff
 
 pytestmark = pytest.mark.gpu
@@ -43,6 +48,7 @@ CASES = [  # (N, m, bc, corr_K, a_time, scheme)
     (1000, 3, "neumann", "predicted", None, 0), (513, 0, "neumann", "old", 0.0, 0),
     (700, 3, "dirichlet", "old", 0.0, 0), (4096, 3, "dirichlet", "old", None, 0),
     (300, 0, "dirichlet", "old", None, 1), (129, 3, "neumann", "old", None, 1),
+    (333, 0, "dirichlet", "old", None, 2), (2048, 3, "neumann", "old", None, 2),
 ]
 
 
@@ -60,8 +66,11 @@ def test_one_step_matches_oracle(N, m, bc, ck, at, scheme):
     if scheme == 0:
         To, Uo = three_stage_step(T, sigma0, dt, m=m, a_time=at, bc=bc, ghost_T=ghost, corr_K=ck)
         assert _rel(Ug, Uo) <= 1e-12
-    else:
+    elif scheme == 1:
         To = two_stage_step(T, sigma0, dt, m=m, bc=bc, ghost_T=ghost)
+    else:
+        To, Uo = semi_cor_step(T, sigma0, dt, m=m, bc=bc, ghost_T=ghost)
+        assert _rel(Ug, Uo) <= 1e-12
     assert _rel(Tg, To) <= 1e-12
     g.close()
 
@@ -114,3 +123,48 @@ def test_porous_medium_limit_converges_to_barenblatt():
         errs.append(np.sum(np.abs(T - barenblatt(x, t0 + steps * dt, q, D, Cb))) / N)
         g.close()
     assert errs[0] > errs[1] > errs[2] and errs[2] < 5e-3
+
+
+
+@pytest.mark.parametrize("m", [0, 3])
+def test_semi_cor_limit_is_not_energy_conservative(m):
+    """Closed ends: sum(a T^4 + Cv T) is kept to rounding by the three-stage
+    scheme and drifts with the (3.14) limit (its update conserves the sum with
+    U* in place of (T^{n+1})^4), as the paper states."""
+    N = 400
+    T, sigma0 = _state(N, 40 + m)
+    dt = 0.5 / N
+    res = {}
+    for scheme in (0, 2):
+        g = GrteDiff(N, opacity_law=m, boundary="neumann")
+        g.set_opacity(sigma0)
+        g.set_state(T)
+        for _ in range(20):
+            g.step(dt, scheme=scheme)
+        Tg = g.get_state()[0]
+        g.close()
+        res[scheme] = abs(np.sum(Tg ** 4 + Tg) - np.sum(T ** 4 + T)) / np.sum(T ** 4 + T)
+    assert res[0] < 1e-13 and res[2] > 1e-6, res
+
+
+def test_semi_cor_limit_blows_up_on_the_front_at_the_hyperbolic_step():
+    """Cold start (T = 0.01), hot boundary (ghost T = 1), sigma = 1, dt = 0.5 dx:
+    the (3.14) limit loses positivity and overflows within a few steps (its T
+    update is explicit in the flux of U*), the three-stage scheme does not."""
+    N = 100
+    dt = 0.5 / N
+    out = {}
+    for scheme in (0, 2):
+        g = GrteDiff(N, opacity_law=0, boundary="dirichlet", ghost=(1.0, 0.01))
+        g.set_opacity(np.ones(N))
+        g.set_state(np.full(N, 0.01))
+        ok = True
+        for _ in range(20):
+            g.step(dt, scheme=scheme)
+            Tg = g.get_state()[0]
+            if not np.all(np.isfinite(Tg)) or Tg.min() < 0:
+                ok = False
+                break
+        g.close()
+        out[scheme] = ok
+    assert out[0] and not out[2], out

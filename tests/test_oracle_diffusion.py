@@ -134,3 +134,37 @@ def test_stability_tables_at_dx_1_100(table, eps):
     assert _max_T(100, C, eps, m) <= 1.0
     if eps < 1:
         assert _max_T(100, 3 * C, eps, m) > 1.0
+
+
+@pytest.mark.parametrize("m", [0, 3])
+def test_semi_cor_limit_conserves_its_own_sum(m):
+    """The (3.14) limit update a (U* - U^n) + Cv (T^{n+1} - T^n) = dt div(F grad U*)
+    telescopes with closed ends: sum(a U* + Cv T^{n+1}) = sum(a U^n + Cv T^n) to
+    rounding -- while the energy with U^{n+1} = (T^{n+1})^4 does not balance."""
+    from oracle.diffusion1d import semi_cor_step
+    N = 80
+    x = (np.arange(N) + 0.5) / N
+    T = 0.5 + 0.3 * np.cos(2 * np.pi * x) + 0.1 * np.sin(6 * np.pi * x)
+    sig = 0.5 + np.random.default_rng(3).uniform(0, 1.5, N)
+    T1, Us = semi_cor_step(T, sig, 0.5 / N, m=m)
+    before = np.sum(T ** 4 + T)
+    assert abs(np.sum(Us + T1) - before) < 1e-13 * before
+    assert abs(np.sum(T1 ** 4 + T1) - before) > 1e-8 * before
+
+
+def test_semi_cor_limit_first_order_on_smooth_data():
+    """sigma independent of T, smooth data, closed ends: the (3.14) limit
+    converges at first order to the implicit reference (6.1) under refinement
+    (the case the paper reports as behaving well)."""
+    from oracle.diffusion1d import semi_cor_step
+    errs = []
+    for N in (50, 100, 200):
+        x = (np.arange(N) + 0.5) / N
+        T = 0.5 + 0.4 * np.cos(2 * np.pi * x)
+        Tr = T.copy()
+        dt = 0.5 / N
+        for _ in range(int(round(0.05 / dt))):
+            T, _ = semi_cor_step(T, np.ones(N), dt, m=0)
+            Tr = implicit_step(Tr, np.ones(N - 1), dt, q=4)
+        errs.append(np.mean(np.abs(T - Tr)))
+    assert errs[0] / errs[1] > 1.7 and errs[1] / errs[2] > 1.7, errs
