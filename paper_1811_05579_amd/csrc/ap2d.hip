@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
     }
 }
 
-// s = r - alpha v; sh = B^{-1} s; x += alpha ph
+// s = r - alpha v; sh = B^{-1} s
 __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
@@ -491,7 +491,6 @@ __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
         const double sv = A.r[t] - alpha * A.v[t];
         A.s[t] = sv;
         A.sh[t] = precond_at(A.S, sv, j, p);
-        A.x[t] += alpha * (A.ph[t] + (A.dP ? A.dP[j] : 0.0));
         if (A.yS) {
             const double y = group_sum(A.S.om[p] * sv, P);
             if (p == 0) A.yS[j] = y;
@@ -499,15 +498,15 @@ __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
     }
 }
 
-// x += omega sh; r = s - omega t; partial (r0, r), (r, r)
+// x += alpha ph + omega sh (one pass over x); r = s - omega t; partial (r0, r), (r, r)
 __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
-    const double omega = A.sc[S_OMEGA];
-    const int P = A.S.P;
+    const double alpha = A.sc[S_ALPHA], omega = A.sc[S_OMEGA];
     double acc[2] = {0.0, 0.0};
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
-        A.x[t] += omega * (A.sh[t] + (A.dS ? A.dS[t >> A.S.lgP] : 0.0));
+        const int j = t >> A.S.lgP;
+        A.x[t] += alpha * (A.ph[t] + (A.dP ? A.dP[j] : 0.0)) + omega * (A.sh[t] + (A.dS ? A.dS[j] : 0.0));
         const double rv = A.s[t] - omega * A.t[t];
         A.r[t] = rv;
         acc[0] += A.r0[t] * rv;
@@ -768,8 +767,10 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
         if (threadIdx.x == 0) {
             sc[S_TS] = ts;
             sc[S_TT] = tt;
-            if (tt == 0.0 || !isfinite(tt)) A.fl[F_STATE] = 2;
-            else sc[S_OMEGA] = ts / tt;
+            // t = A sh vanishes only with s: omega = 0 lets the last update still
+            // take x += alpha ph, and the test after it stops on r = s
+            if (!isfinite(tt) || !isfinite(ts)) A.fl[F_STATE] = 2;
+            else sc[S_OMEGA] = tt == 0.0 ? 0.0 : ts / tt;
         }
     } else {
         const double rho = fin_sum(A.part, 0, nb), rr = fin_sum(A.part, 1, nb);
