@@ -23,8 +23,13 @@ import sqlite3
 import sys
 
 
+def _open(db_path):
+    # read-only: a mistyped path fails instead of creating an empty database
+    return sqlite3.connect(f"file:{db_path}?mode=ro", uri=True)
+
+
 def summarise(db_path):
-    con = sqlite3.connect(db_path)
+    con = _open(db_path)
     rows = con.execute(
         "select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
         "from kernels group by name order by sum(duration) desc").fetchall()
@@ -37,7 +42,7 @@ def summarise(db_path):
 
 
 def summarise_window(db_path, kernel_substring, first, count):
-    con = sqlite3.connect(db_path)
+    con = _open(db_path)
     rows = con.execute("select name, duration from kernels order by start").fetchall()
     d = [dur for name, dur in rows if kernel_substring in name]
     sel = d[first:first + count] if first + count != 0 else d[first:]
@@ -49,7 +54,7 @@ def summarise_window(db_path, kernel_substring, first, count):
 
 
 def summarise_launches(db_path, kernel_substring, min_us):
-    con = sqlite3.connect(db_path)
+    con = _open(db_path)
     rows = con.execute("select name, duration from kernels order by start").fetchall()
     d = [dur / 1e3 for name, dur in rows if kernel_substring in name]
     sel = [x for x in d if x >= min_us]
@@ -88,7 +93,9 @@ def summarise_pmc(csv_path, kernel_substring, vmin=None):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 2 and sys.argv[1] == "--window":
+    if len(sys.argv) < 2 or sys.argv[1] in ("-h", "--help"):
+        print(__doc__)
+    elif sys.argv[1] == "--window":
         print(summarise_window(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5])))
     elif len(sys.argv) >= 2 and sys.argv[1] == "--launches":
         print(summarise_launches(sys.argv[2], sys.argv[3], float(sys.argv[4])))
