@@ -524,9 +524,12 @@ grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
  * operator -- the mode that the angular coupling leaves nearly undamped in
  * optically thick cells (the diffusion limit of Section 3).  kind 0: none;
  * kind 1 (default): `steps` Chebyshev steps (default 10) on the Jacobi-scaled
- * operator; kind 2: one multigrid V-cycle (2 x 2 cell aggregates, coarse rows
- * with the children's row sums and half their couplings across each side,
- * `steps` weighted-Jacobi sweeps before and after each coarse correction).
+ * operator, all in one launch of 32 x 32-cell tiles with a halo of steps - 1
+ * cells when steps <= 10, one launch per step beyond; kind 2: one multigrid
+ * V-cycle (2 x 2 cell aggregates, coarse rows with the children's row sums and
+ * half their couplings across each side, `steps` weighted-Jacobi sweeps before
+ * and after each coarse correction); kind 3: kind 1's map with one launch per
+ * Chebyshev step whatever `steps` (the same result to the bit).
  * 1 <= steps <= 64.  The correction's systems have no
  * angular coupling and use the block inverse alone. */
 grte_status grte2d_set_isotropic_correction(grte2d_ctx *ctx, int kind, int steps);

@@ -538,26 +538,56 @@ struct IsoArgs {
     const int *fl;
 };
 
+// the four face values around a cell (left, right, bottom, top)
+struct Faces {
+    double l, r, b, t;
+};
+
+// a cell's faces in the isotropic operator's form: at a wall the face on the
+// far side counts twice and the wall face drops out
+__device__ __forceinline__ Faces iso_walls(const Sys &S, int iy, int ix, Faces g)
+{
+    if (ix == 0) { g.r *= 2.0; g.l = 0.0; }
+    else if (ix == S.nx - 1) { g.l *= 2.0; g.r = 0.0; }
+    if (iy == 0) { g.t *= 2.0; g.b = 0.0; }
+    else if (iy == S.ny - 1) { g.b *= 2.0; g.t = 0.0; }
+    return g;
+}
+
+// the diagonal of a cell's row (wall-form faces g; a wall adds the inflow term)
+__device__ __forceinline__ double iso_diag(const IsoArgs &A, int iy, int ix, int j, const Faces &g)
+{
+    const Sys &S = A.S;
+    const double k = S.kco[j];
+    const double cx = A.Mxx * S.idx * S.idx, cy = A.Myy * S.idy * S.idy;
+    double ed = 0.0;
+    const double e2 = S.k2 * S.fe;
+    if (ix == 0 || ix == S.nx - 1) ed += e2 * A.Sx * S.idx;
+    if (iy == 0 || iy == S.ny - 1) ed += e2 * A.Sy * S.idy;
+    return S.W1 * S.dmg[j] + k * (cx * (g.l + g.r) + cy * (g.b + g.t) + ed);
+}
+
+// (D x)_cell from the cell's value and its neighbours' (0 beyond a wall)
+__device__ __forceinline__ double iso_Dx(const IsoArgs &A, double k, double diag, const Faces &g, double xc,
+                                         double xl, double xr, double xb, double xt)
+{
+    const Sys &S = A.S;
+    const double cx = A.Mxx * S.idx * S.idx, cy = A.Myy * S.idy * S.idy;
+    return diag * xc - k * (cx * (g.l * xl + g.r * xr) + cy * (g.b * xb + g.t * xt));
+}
+
 __device__ __forceinline__ void iso_row(const IsoArgs &A, int j, const double *x, double &Dx, double &diag)
 {
     const Sys &S = A.S;
     int iy, ix;
     cell_yx(S, j, iy, ix);
     const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
-    const double k = S.kco[j];
-    const double cx = A.Mxx * S.idx * S.idx, cy = A.Myy * S.idy * S.idy;
-    double gl = S.gx[fl], gr = S.gx[fl + 1], gb = S.gy[fb], gt = S.gy[fb + S.nx];
-    double ed = 0.0;
-    const double e2 = S.k2 * S.fe;
-    if (ix == 0) { gr *= 2.0; gl = 0.0; ed += e2 * A.Sx * S.idx; }
-    else if (ix == S.nx - 1) { gl *= 2.0; gr = 0.0; ed += e2 * A.Sx * S.idx; }
-    if (iy == 0) { gt *= 2.0; gb = 0.0; ed += e2 * A.Sy * S.idy; }
-    else if (iy == S.ny - 1) { gb *= 2.0; gt = 0.0; ed += e2 * A.Sy * S.idy; }
+    const Faces g = iso_walls(S, iy, ix, Faces{S.gx[fl], S.gx[fl + 1], S.gy[fb], S.gy[fb + S.nx]});
+    diag = iso_diag(A, iy, ix, j, g);
     const double xc = x[j];
     const double xl = ix > 0 ? x[j - 1] : 0.0, xr = ix < S.nx - 1 ? x[j + 1] : 0.0;
     const double xb = iy > 0 ? x[j - S.nx] : 0.0, xt = iy < S.ny - 1 ? x[j + S.nx] : 0.0;
-    diag = S.W1 * S.dmg[j] + k * (cx * (gl + gr) + cy * (gb + gt) + ed);
-    Dx = diag * xc - k * (cx * (gl * xl + gr * xr) + cy * (gb * xb + gt * xt));
+    Dx = iso_Dx(A, S.kco[j], diag, g, xc, xl, xr, xb, xt);
 }
 
 // first step: x1 = d0 = (y / diag) / theta
@@ -586,6 +616,115 @@ __global__ void __launch_bounds__(B2) iso_step_kernel(IsoArgs A)
         const double dn = A.c1 * A.d[j] + A.c2 * r;
         A.d[j] = dn;
         A.xout[j] = A.xin[j] + dn;
+    }
+}
+
+// All K steps of the Chebyshev map in one launch (K - 1 <= ISO_HALO stencil
+// steps after the local first step).  A block owns a tile of ISO_T x ISO_T
+// cells and works on the tile plus a halo of K - 1 cells: the iterate and the
+// face values sit in LDS, each cell's own values (y, diagonal, k, the
+// Chebyshev direction) in registers.  Stencil step s updates the region cells
+// at least s + 1 cells inside its border (their neighbours hold step-s
+// values), so after K - 1 steps the tile's cells are exact; cells outside the
+// grid are never read (their neighbours' weights are zero and their values
+// taken as 0, as in the per-step form).  The arithmetic is the per-step
+// kernels' own, term for term, so the result is the same to the bit.
+constexpr int ISO_T = 32, ISO_HALO = 9, ISO_RMAX = ISO_T + 2 * ISO_HALO, ISO_TB = 512;
+constexpr int ISO_CPT = (ISO_RMAX * ISO_RMAX + ISO_TB - 1) / ISO_TB;
+
+struct IsoFused {
+    IsoArgs A;
+    int nsteps;                 // stencil steps after the first, 0 .. ISO_HALO
+    double c1[ISO_HALO], c2[ISO_HALO];
+};
+
+__global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
+{
+    const IsoArgs &A = F.A;
+    if (A.fl[F_STATE] != 0) return;
+    const Sys &S = A.S;
+    const int h = F.nsteps, R = ISO_T + 2 * h;
+    const int ox = blockIdx.x * ISO_T - h, oy = blockIdx.y * ISO_T - h;   // grid position of region cell (0, 0)
+    __shared__ double X[ISO_RMAX * ISO_RMAX];
+    __shared__ double GX[ISO_RMAX * (ISO_RMAX + 1)];     // x-faces: row ry, face fx = left face of region cell fx
+    __shared__ double GY[(ISO_RMAX + 1) * ISO_RMAX];     // y-faces: face row fy = bottom face of region row fy
+    const int t = threadIdx.x;
+    for (int f = t; f < R * (R + 1); f += ISO_TB) {
+        const int ry = f / (R + 1), fx = f - ry * (R + 1);
+        const int iy = oy + ry, ix = ox + fx;
+        GX[f] = (iy >= 0 && iy < S.ny && ix >= 0 && ix <= S.nx) ? S.gx[iy * (S.nx + 1) + ix] : 0.0;
+    }
+    for (int f = t; f < (R + 1) * R; f += ISO_TB) {
+        const int fy = f / R, rx = f - fy * R;
+        const int iy = oy + fy, ix = ox + rx;
+        GY[f] = (iy >= 0 && iy <= S.ny && ix >= 0 && ix < S.nx) ? S.gy[iy * S.nx + ix] : 0.0;
+    }
+    __syncthreads();
+    double y[ISO_CPT], dg[ISO_CPT], kc[ISO_CPT], d[ISO_CPT], xn[ISO_CPT];
+#pragma unroll
+    for (int i = 0; i < ISO_CPT; ++i) {
+        const int c = t + i * ISO_TB;
+        y[i] = dg[i] = kc[i] = d[i] = xn[i] = 0.0;
+        if (c >= R * R) continue;
+        const int ry = c / R, rx = c - ry * R;
+        const int iy = oy + ry, ix = ox + rx;
+        if (iy < 0 || iy >= S.ny || ix < 0 || ix >= S.nx) continue;
+        const int j = iy * S.nx + ix;
+        const Faces g = iso_walls(S, iy, ix, Faces{GX[ry * (R + 1) + rx], GX[ry * (R + 1) + rx + 1],
+                                                    GY[ry * R + rx], GY[(ry + 1) * R + rx]});
+        dg[i] = iso_diag(A, iy, ix, j, g);
+        kc[i] = S.kco[j];
+        y[i] = A.y[j];
+        d[i] = y[i] / (dg[i] * A.th);       // the first step: x1 = d0
+        xn[i] = d[i];
+    }
+#pragma unroll
+    for (int i = 0; i < ISO_CPT; ++i) {
+        const int c = t + i * ISO_TB;
+        if (c < R * R) X[c] = xn[i];
+    }
+    __syncthreads();
+    for (int s = 0; s < h; ++s) {
+        const double c1 = F.c1[s], c2 = F.c2[s];
+#pragma unroll
+        for (int i = 0; i < ISO_CPT; ++i) {
+            const int c = t + i * ISO_TB;
+            if (c >= R * R) continue;
+            const int ry = c / R, rx = c - ry * R;
+            if (rx <= s || rx >= R - 1 - s || ry <= s || ry >= R - 1 - s) continue;
+            const int iy = oy + ry, ix = ox + rx;
+            if (iy < 0 || iy >= S.ny || ix < 0 || ix >= S.nx) continue;
+            const Faces g = iso_walls(S, iy, ix, Faces{GX[ry * (R + 1) + rx], GX[ry * (R + 1) + rx + 1],
+                                                        GY[ry * R + rx], GY[(ry + 1) * R + rx]});
+            const double xc = X[c];
+            const double xl = ix > 0 ? X[c - 1] : 0.0, xr = ix < S.nx - 1 ? X[c + 1] : 0.0;
+            const double xb = iy > 0 ? X[c - R] : 0.0, xt = iy < S.ny - 1 ? X[c + R] : 0.0;
+            const double Dx = iso_Dx(A, kc[i], dg[i], g, xc, xl, xr, xb, xt);
+            const double r = (y[i] - Dx) / dg[i];
+            const double dn = c1 * d[i] + c2 * r;
+            d[i] = dn;
+            xn[i] = xc + dn;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ISO_CPT; ++i) {
+            const int c = t + i * ISO_TB;
+            if (c >= R * R) continue;
+            const int ry = c / R, rx = c - ry * R;
+            if (rx <= s || rx >= R - 1 - s || ry <= s || ry >= R - 1 - s) continue;
+            X[c] = xn[i];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < ISO_CPT; ++i) {
+        const int c = t + i * ISO_TB;
+        if (c >= R * R) continue;
+        const int ry = c / R, rx = c - ry * R;
+        if (rx < h || rx >= h + ISO_T || ry < h || ry >= h + ISO_T) continue;
+        const int iy = oy + ry, ix = ox + rx;
+        if (iy >= S.ny || ix >= S.nx) continue;
+        A.xout[iy * S.nx + ix] = X[c];
     }
 }
 
@@ -1070,7 +1209,7 @@ struct grte2d_ctx {
     int stepped = 0;
     double last_eps = 0, last_dt = 0;
     // isotropic correction of the preconditioner
-    int iso_kind = 1;                    // 0 none, 1 Chebyshev, 2 multigrid V-cycle
+    int iso_kind = 1;                    // 0 none, 1 Chebyshev (tiled), 2 multigrid V-cycle, 3 Chebyshev per step
     int iso_k = 10;                      // Chebyshev steps
     int mg_nu = 2;                       // multigrid: Jacobi sweeps before and after the coarse correction
     struct Lv {
@@ -1239,6 +1378,24 @@ void iso_cheb(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStre
     I.fl = c->fl;
     const double th = 0.5 * (CHEB2_B + CHEB2_A), de = 0.5 * (CHEB2_B - CHEB2_A), sg = th / de;
     I.th = th;
+    if (c->iso_kind == 1 && K - 1 <= ISO_HALO) {
+        // all steps in one tiled launch
+        IsoFused F;
+        F.A = I;
+        F.A.xin = nullptr;
+        F.A.xout = out;
+        F.nsteps = K - 1;
+        double rho = 1.0 / sg;
+        for (int k = 1; k < K; ++k) {
+            const double rn = 1.0 / (2.0 * sg - rho);
+            F.c1[k - 1] = rn * rho;
+            F.c2[k - 1] = 2.0 * rn / de;
+            rho = rn;
+        }
+        const dim3 grid((S.nx + ISO_T - 1) / ISO_T, (S.ny + ISO_T - 1) / ISO_T);
+        hipLaunchKernelGGL(iso_fused_kernel, grid, dim3(ISO_TB), 0, st, F);
+        return;
+    }
     auto buf = [&](int k) { return ((K - k) % 2 == 0) ? out : c->itmp; };   // iterate k lands in buf(k)
     I.xin = nullptr;
     I.xout = buf(1);
@@ -1258,7 +1415,7 @@ void iso_cheb(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStre
 
 void iso_solve(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStream_t st)
 {
-    if (c->iso_kind == 1) {
+    if (c->iso_kind == 1 || c->iso_kind == 3) {
         iso_cheb(c, S, y, out, st);
         return;
     }
@@ -1572,9 +1729,9 @@ grte_status grte2d_log_pairs(grte2d_ctx *c, float *dev_rows, long long cap_rows,
 
 grte_status grte2d_set_isotropic_correction(grte2d_ctx *c, int kind, int steps)
 {
-    if (!c || kind < 0 || kind > 2 || steps < 1 || steps > 64) return GRTE_E_INVAL;
+    if (!c || kind < 0 || kind > 3 || steps < 1 || steps > 64) return GRTE_E_INVAL;
     c->iso_kind = kind;
-    if (kind == 1) c->iso_k = steps;
+    if (kind == 1 || kind == 3) c->iso_k = steps;
     if (kind == 2) c->mg_nu = steps;
     return GRTE_OK;
 }

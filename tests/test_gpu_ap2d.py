@@ -255,6 +255,31 @@ def test_isotropic_correction_variants_agree(kind, steps):
         assert _rel(b, a) < 1e-10
 
 
+@pytest.mark.parametrize("nx,ny,steps", [(75, 41, 10), (75, 41, 5), (33, 70, 2), (33, 70, 1), (64, 32, 10)])
+def test_tiled_chebyshev_equals_per_step(nx, ny, steps):
+    """The isotropic correction's Chebyshev steps in one tiled launch (32 x 32
+    cells per block plus a halo of steps - 1) give the per-step launches' map
+    to the bit: two steps of an optically thick state on grids of whole and
+    ragged tiles leave identical states and iteration counts."""
+    w = random_state_2d(nx, ny, 16, 40 + steps, m=0, eps=1e-3, sigma=(1.0, 100.0))
+    out = []
+    for kind in ("chebyshev", "chebyshev-per-step"):
+        g = _ctx(w)
+        g.set_isotropic_correction(kind, steps)
+        g.set_state(w.E, w.Ox, w.Oy, w.T)
+        its = []
+        for _ in range(2):
+            info = g.step(w.dt, w.eps, info=True)
+            assert info["status"] == 0, info
+            its.append((info["pred_iters"], info["corr_iters"]))
+        out.append((g.get_state(), its))
+        g.close()
+    print(w.name, steps, "iterations", out[0][1], out[1][1], flush=True)
+    assert out[0][1] == out[1][1]
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("fp32", [False, True])
 def test_intensity_readout_2d(fp32):
     """I(+-Omega_p) at the cell centres from the library equals the oracle's
