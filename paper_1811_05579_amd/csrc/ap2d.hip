@@ -67,6 +67,7 @@ struct Sys {
     const double *lam, *dmg, *cg, *kco;  // cell: Lambda, Lambda - g W1, g, K co c dt
     const double *rb1, *rb0, *acU;       // rhs = rb1 E^n_p + rb0; acU (correction's known part)
     const double *sab, *ue;              // residual in difference form (see residual_at)
+    const double *pgc;                   // cell: g / (1 - g sum_p omega_p / d_p) of the block inverse
 };
 
 // (iy, ix) of cell j without an integer division: the binary64 product is off
@@ -433,10 +434,9 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
     block_sums(acc, MODE == 0 ? 3 : (MODE == 1 ? 1 : 2), A.part);
 }
 
-// cell-block Jacobi: z = B^{-1} y, B = diag(d_p) - g 1 omega^T (Sherman-Morrison)
-__device__ __forceinline__ double precond_at(const Sys &S, double y, int j, int p)
+// 1 / d_p: the inverse of the direction-diagonal part of a cell's block
+__device__ __forceinline__ double block_idiag(const Sys &S, int j, int p)
 {
-    const int P = S.P;
     int iy, ix;
     cell_yx(S, j, iy, ix);
     const double mu = S.mu[p], eta = S.eta[p];
@@ -453,13 +453,31 @@ __device__ __forceinline__ double precond_at(const Sys &S, double y, int j, int 
     if (iy == 0) tr += 2.0 * gt * my + k2 * fabs(eta) * S.idy;
     else if (iy == S.ny - 1) tr += 2.0 * gb * my + k2 * fabs(eta) * S.idy;
     else tr += (gb + gt) * my;
-    const double id = 1.0 / (S.lam[j] + S.kco[j] * tr);
-    const double w = S.om[p];
+    return 1.0 / (S.lam[j] + S.kco[j] * tr);
+}
+
+// the system-dependent scalar of each cell's Sherman-Morrison inverse,
+// g / (1 - g sum_p omega_p / d_p), once per prediction solve
+__global__ void __launch_bounds__(B2) pgc2d_kernel(Sys S, double *pgc, size_t n)
+{
+    const int P = S.P;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) {
+        const int j = t >> S.lgP, p = t & (P - 1);
+        const double s2 = group_sum(S.om[p] * block_idiag(S, j, p), P);
+        const double g = S.cg[j];
+        if (p == 0) pgc[j] = g / (1.0 - g * s2);
+    }
+}
+
+// cell-block Jacobi: z = B^{-1} y, B = diag(d_p) - g 1 omega^T (Sherman-Morrison);
+// the correction's blocks have g = 0 and are diagonal
+__device__ __forceinline__ double precond_at(const Sys &S, double y, int j, int p)
+{
+    const double id = block_idiag(S, j, p);
     const double u = y * id;
-    const double s1 = group_sum(w * u, P);
-    const double s2 = group_sum(w * id, P);
-    const double g = S.cg[j];
-    return u + g * s1 / (1.0 - g * s2) * id;
+    if (S.corr) return u;
+    const double s1 = group_sum(S.om[p] * u, S.P);
+    return u + S.pgc[j] * s1 * id;
 }
 
 // p = r + beta (p - omega v); ph = B^{-1} p
@@ -1219,6 +1237,7 @@ struct grte2d_ctx {
     std::vector<Lv> mg;
     double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
     double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
+    double *pgc = nullptr;               // per-cell scalar of the block inverse
     // sampled timing of the operator kernel (first iteration of every chunk)
     int profiling = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1283,6 +1302,7 @@ Sys make_sys(grte2d_ctx *c, int corr, double eps)
     S.acU = c->acU;
     S.sab = c->sab;
     S.ue = c->ue;
+    S.pgc = c->pgc;
     return S;
 }
 
@@ -1455,6 +1475,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     // the isotropic correction targets the angular coupling of the prediction;
     // the correction's systems have none
     const bool iso = c->iso_kind != 0 && !S.corr;
+    if (!S.corr) hipLaunchKernelGGL(pgc2d_kernel, dim3(nblocks(c->nE)), dim3(B2), 0, c->stream, S, c->pgc, c->nE);
     if (iso && c->iso_kind == 2) mg_setup(c, S, c->stream);
     A.dP = iso ? c->dP : nullptr;
     A.dS = iso ? c->dS : nullptr;
@@ -1636,7 +1657,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   }
                   return true;
               }() &&
-              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->pgc, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
