@@ -17,7 +17,7 @@ import pytest
 from fp64_bar import fp64_bar
 from oracle import ap2d
 from oracle.ap1d import Physics
-from paper_1811_05579_amd import Grte2D
+from paper_1811_05579_amd import Grte2D, GrteError
 from paper_1811_05579_amd.workloads import (Workload2D, circle_pairs, config3, random_state_2d,
                                             voronoi_two_material, _square)
 
@@ -255,12 +255,14 @@ def test_isotropic_correction_variants_agree(kind, steps):
         assert _rel(b, a) < 1e-10
 
 
-@pytest.mark.parametrize("nx,ny,steps", [(75, 41, 10), (75, 41, 5), (33, 70, 2), (33, 70, 1), (64, 32, 10)])
+@pytest.mark.parametrize("nx,ny,steps", [(75, 41, 10), (75, 41, 5), (33, 70, 2), (33, 70, 1), (64, 32, 10),
+                                         (33, 70, 12)])
 def test_tiled_chebyshev_equals_per_step(nx, ny, steps):
     """The isotropic correction's Chebyshev steps in one tiled launch (32 x 32
     cells per block plus a halo of steps - 1) give the per-step launches' map
     to the bit: two steps of an optically thick state on grids of whole and
-    ragged tiles leave identical states and iteration counts."""
+    ragged tiles leave identical states and iteration counts.  (Beyond 10
+    steps both kinds take the per-step launches.)"""
     w = random_state_2d(nx, ny, 16, 40 + steps, m=0, eps=1e-3, sigma=(1.0, 100.0))
     out = []
     for kind in ("chebyshev", "chebyshev-per-step"):
@@ -278,6 +280,18 @@ def test_tiled_chebyshev_equals_per_step(nx, ny, steps):
     assert out[0][1] == out[1][1]
     for a, b in zip(out[0][0], out[1][0]):
         assert np.array_equal(a, b)
+
+
+def test_isotropic_correction_arguments():
+    """Step counts outside 1..64 and unknown kinds are rejected."""
+    w = random_state_2d(8, 8, 8, 1)
+    g = _ctx(w)
+    for steps in (0, 65):
+        with pytest.raises(GrteError):
+            g.set_isotropic_correction("chebyshev", steps)
+    with pytest.raises(ValueError):
+        g.set_isotropic_correction("jacobi", 4)
+    g.close()
 
 
 @pytest.mark.parametrize("fp32", [False, True])
