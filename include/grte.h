@@ -523,9 +523,10 @@ grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
  * operator's angular average over isotropic fields, a 5-point diffusion
  * operator -- the mode that the angular coupling leaves nearly undamped in
  * optically thick cells (the diffusion limit of Section 3).  kind 0: none;
- * kind 1 (default): `steps` Chebyshev steps (default 10) on the Jacobi-scaled
- * operator, all in one launch of 32 x 32-cell tiles with a halo of steps - 1
- * cells when steps <= 10, one launch per step beyond; kind 2: one multigrid
+ * kind 1 (default): `steps` Chebyshev steps (default 19) on the Jacobi-scaled
+ * operator, in launches over 32 x 32-cell tiles that take up to 9 stencil
+ * steps each with a halo of as many cells (one launch up to 10 steps, two up
+ * to 19); kind 2: one multigrid
  * V-cycle (2 x 2 cell aggregates, coarse rows with the children's row sums and
  * half their couplings across each side, `steps` weighted-Jacobi sweeps before
  * and after each coarse correction); kind 3: kind 1's map with one launch per

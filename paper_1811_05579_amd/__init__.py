@@ -622,14 +622,14 @@ class Grte2D:
 
     def set_isotropic_correction(self, kind="chebyshev", steps=None):
         """The prediction preconditioner's isotropic (diffusion) correction:
-        'none', 'chebyshev' (steps: Chebyshev steps, default 10), 'multigrid'
+        'none', 'chebyshev' (steps: Chebyshev steps, default 19), 'multigrid'
         (steps: Jacobi sweeps before and after each coarse correction, default 2)
         or 'chebyshev-per-step' (the same map as 'chebyshev', one launch per step)."""
         kinds = {"none": 0, "chebyshev": 1, "multigrid": 2, "chebyshev-per-step": 3}
         if kind not in kinds:
             raise ValueError(f"kind must be one of {sorted(kinds)}")
         if steps is None:
-            steps = 2 if kind == "multigrid" else 10
+            steps = 2 if kind == "multigrid" else 19
         check("grte2d_set_isotropic_correction",
               self._lib.grte2d_set_isotropic_correction(self._h, kinds[kind], int(steps)))
 

@@ -637,22 +637,26 @@ __global__ void __launch_bounds__(B2) iso_step_kernel(IsoArgs A)
     }
 }
 
-// All K steps of the Chebyshev map in one launch (K - 1 <= ISO_HALO stencil
-// steps after the local first step).  A block owns a tile of ISO_T x ISO_T
-// cells and works on the tile plus a halo of K - 1 cells: the iterate and the
+// Up to ISO_HALO stencil steps of the Chebyshev map in one launch, preceded
+// by the local first step (first = 1) or continuing from a stored iterate and
+// direction.  A block owns a tile of ISO_T x ISO_T cells and works on the tile
+// plus a halo of as many cells as it takes stencil steps: the iterate and the
 // face values sit in LDS, each cell's own values (y, diagonal, k, the
 // Chebyshev direction) in registers.  Stencil step s updates the region cells
 // at least s + 1 cells inside its border (their neighbours hold step-s
-// values), so after K - 1 steps the tile's cells are exact; cells outside the
-// grid are never read (their neighbours' weights are zero and their values
-// taken as 0, as in the per-step form).  The arithmetic is the per-step
-// kernels' own, term for term, so the result is the same to the bit.
+// values), so after the launch's steps the tile's cells are exact; cells
+// outside the grid are never read (their neighbours' weights are zero and
+// their values taken as 0, as in the per-step form).  The arithmetic is the
+// per-step kernels' own, term for term, so the result is the same to the bit.
 constexpr int ISO_T = 32, ISO_HALO = 9, ISO_RMAX = ISO_T + 2 * ISO_HALO, ISO_TB = 512;
 constexpr int ISO_CPT = (ISO_RMAX * ISO_RMAX + ISO_TB - 1) / ISO_TB;
 
 struct IsoFused {
-    IsoArgs A;
-    int nsteps;                 // stencil steps after the first, 0 .. ISO_HALO
+    IsoArgs A;                  // A.xin: the iterate to continue from (first = 0); A.xout: the result
+    int first;                  // 1: start with the local first step from A.y
+    int nsteps;                 // stencil steps of this launch, 0 .. ISO_HALO
+    const double *din;          // the direction to continue from (first = 0)
+    double *dout;               // the direction after the launch (null: not kept)
     double c1[ISO_HALO], c2[ISO_HALO];
 };
 
@@ -693,8 +697,13 @@ __global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
         dg[i] = iso_diag(A, iy, ix, j, g);
         kc[i] = S.kco[j];
         y[i] = A.y[j];
-        d[i] = y[i] / (dg[i] * A.th);       // the first step: x1 = d0
-        xn[i] = d[i];
+        if (F.first) {
+            d[i] = y[i] / (dg[i] * A.th);   // the first step: x1 = d0
+            xn[i] = d[i];
+        } else {
+            d[i] = F.din[j];
+            xn[i] = A.xin[j];
+        }
     }
 #pragma unroll
     for (int i = 0; i < ISO_CPT; ++i) {
@@ -743,6 +752,7 @@ __global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
         const int iy = oy + ry, ix = ox + rx;
         if (iy >= S.ny || ix >= S.nx) continue;
         A.xout[iy * S.nx + ix] = X[c];
+        if (F.dout) F.dout[iy * S.nx + ix] = d[i];
     }
 }
 
@@ -1228,7 +1238,7 @@ struct grte2d_ctx {
     double last_eps = 0, last_dt = 0;
     // isotropic correction of the preconditioner
     int iso_kind = 1;                    // 0 none, 1 Chebyshev (tiled), 2 multigrid V-cycle, 3 Chebyshev per step
-    int iso_k = 10;                      // Chebyshev steps
+    int iso_k = 19;                      // Chebyshev steps (two tiled launches)
     int mg_nu = 2;                       // multigrid: Jacobi sweeps before and after the coarse correction
     struct Lv {
         MgRows R;
@@ -1238,6 +1248,7 @@ struct grte2d_ctx {
     double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
     double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
     double *pgc = nullptr;               // per-cell scalar of the block inverse
+    double *idir2 = nullptr;             // second Chebyshev direction buffer of the tiled launches
     // sampled timing of the operator kernel (first iteration of every chunk)
     int profiling = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1398,22 +1409,32 @@ void iso_cheb(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStre
     I.fl = c->fl;
     const double th = 0.5 * (CHEB2_B + CHEB2_A), de = 0.5 * (CHEB2_B - CHEB2_A), sg = th / de;
     I.th = th;
-    if (c->iso_kind == 1 && K - 1 <= ISO_HALO) {
-        // all steps in one tiled launch
-        IsoFused F;
-        F.A = I;
-        F.A.xin = nullptr;
-        F.A.xout = out;
-        F.nsteps = K - 1;
-        double rho = 1.0 / sg;
-        for (int k = 1; k < K; ++k) {
-            const double rn = 1.0 / (2.0 * sg - rho);
-            F.c1[k - 1] = rn * rho;
-            F.c2[k - 1] = 2.0 * rn / de;
-            rho = rn;
-        }
+    if (c->iso_kind == 1) {
+        // tiled launches of up to ISO_HALO stencil steps each (the first also
+        // takes the local first step); the iterate alternates between itmp and
+        // out so that the last launch writes out, the direction between idir
+        // and idir2
+        const int nl = K - 1 <= ISO_HALO ? 1 : 1 + (K - 1 - ISO_HALO + ISO_HALO - 1) / ISO_HALO;
         const dim3 grid((S.nx + ISO_T - 1) / ISO_T, (S.ny + ISO_T - 1) / ISO_T);
-        hipLaunchKernelGGL(iso_fused_kernel, grid, dim3(ISO_TB), 0, st, F);
+        double rho = 1.0 / sg;
+        int k = 1;                          // global index of the next stencil step
+        for (int l = 0; l < nl; ++l) {
+            IsoFused F;
+            F.A = I;
+            F.first = l == 0;
+            F.nsteps = std::min(ISO_HALO, K - k);
+            F.A.xin = l == 0 ? nullptr : (((nl - l) % 2 == 0) ? out : c->itmp);
+            F.A.xout = ((nl - 1 - l) % 2 == 0) ? out : c->itmp;
+            F.din = l == 0 ? nullptr : ((l % 2 == 1) ? c->idir : c->idir2);
+            F.dout = l == nl - 1 ? nullptr : ((l % 2 == 0) ? c->idir : c->idir2);
+            for (int s = 0; s < F.nsteps; ++s, ++k) {
+                const double rn = 1.0 / (2.0 * sg - rho);
+                F.c1[s] = rn * rho;
+                F.c2[s] = 2.0 * rn / de;
+                rho = rn;
+            }
+            hipLaunchKernelGGL(iso_fused_kernel, grid, dim3(ISO_TB), 0, st, F);
+        }
         return;
     }
     auto buf = [&](int k) { return ((K - k) % 2 == 0) ? out : c->itmp; };   // iterate k lands in buf(k)
@@ -1657,7 +1678,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   }
                   return true;
               }() &&
-              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->pgc, c->N) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&

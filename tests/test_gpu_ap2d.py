@@ -242,7 +242,7 @@ def test_isotropic_correction_variants_agree(kind, steps):
     variant (within the solver tolerance's effect) and match the oracle."""
     w = _two_material(40, 32, (1.0, 100.0), 1e-3, 18110000 + 3)
     out = []
-    for k, st in (("chebyshev", 10), (kind, steps)):
+    for k, st in (("chebyshev", 19), (kind, steps)):
         g = _ctx(w)
         g.set_isotropic_correction(k, st)
         g.set_state(w.E, w.Ox, w.Oy, w.T)
@@ -256,13 +256,14 @@ def test_isotropic_correction_variants_agree(kind, steps):
 
 
 @pytest.mark.parametrize("nx,ny,steps", [(75, 41, 10), (75, 41, 5), (33, 70, 2), (33, 70, 1), (64, 32, 10),
-                                         (33, 70, 12)])
+                                         (33, 70, 12), (75, 41, 19), (64, 32, 20), (33, 70, 28)])
 def test_tiled_chebyshev_equals_per_step(nx, ny, steps):
-    """The isotropic correction's Chebyshev steps in one tiled launch (32 x 32
-    cells per block plus a halo of steps - 1) give the per-step launches' map
-    to the bit: two steps of an optically thick state on grids of whole and
-    ragged tiles leave identical states and iteration counts.  (Beyond 10
-    steps both kinds take the per-step launches.)"""
+    """The isotropic correction's Chebyshev steps in tiled launches (32 x 32
+    cells per block plus a halo of the launch's stencil steps, at most 9 per
+    launch, chained through the stored iterate and direction) give the
+    per-step launches' map to the bit: two steps of an optically thick state
+    on grids of whole and ragged tiles leave identical states and iteration
+    counts, for one launch (up to 10 steps) and two or three (12 to 28)."""
     w = random_state_2d(nx, ny, 16, 40 + steps, m=0, eps=1e-3, sigma=(1.0, 100.0))
     out = []
     for kind in ("chebyshev", "chebyshev-per-step"):
