@@ -50,7 +50,7 @@ constexpr int B2 = 256;        // threads per block of the (cell, pair) kernels
 constexpr int MAXB = 2048;     // blocks of the grid-stride kernels = partial sums per dot product
 constexpr int CHUNK = 8;       // BiCGStab iterations enqueued between convergence checks
 constexpr int KRY_RESTARTS = 6;      // restarts from the true residual per solve
-constexpr double CHEB2_A = 0.02, CHEB2_B = 2.0;   // eigenvalue interval of the Jacobi-scaled isotropic operator
+constexpr double CHEB2_A = 0.01, CHEB2_B = 2.0;   // eigenvalue interval of the Jacobi-scaled isotropic operator
 constexpr double KRY_FLOOR = 64.0;   // floor stop: true residual within this factor of its rounding level
 
 // scalars of the Krylov solve, in device memory
