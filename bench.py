@@ -46,9 +46,9 @@ TRAFFIC = {
     ("config2", "fp32"): (None, None),
     ("config4", "fp64"): (None, None),
     ("config4", "fp32"): (1.4162e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
-    ("config3", "fp64"): (5.434e8, "profiles/apply2d_config3_hbm_traffic.txt"),
-    ("config3", "fp32"): (5.434e8, "profiles/apply2d_config3_hbm_traffic.txt"),   # Krylov vectors are binary64 either way
-    ("config5", "fp64"): (2.658e8, "profiles/apply2d_config5_hbm_traffic.txt"),
+    ("config3", "fp64"): (4.853e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config3", "fp32"): (4.853e8, "profiles/apply2d_config3_hbm_traffic.txt"),   # Krylov vectors are binary64 either way
+    ("config5", "fp64"): (2.484e8, "profiles/apply2d_config5_hbm_traffic.txt"),
 }
 
 

@@ -47,7 +47,11 @@
 namespace {
 
 constexpr int B2 = 256;        // threads per block of the (cell, pair) kernels
-constexpr int MAXB = 2048;     // blocks of the grid-stride kernels = partial sums per dot product
+constexpr int MAXB = 2048;     // blocks of the grid-stride kernels outside the Krylov loop
+// the Krylov kernels over the N*P items run KRY_ITEMS items per thread (up to
+// KRYB blocks); their per-block partial sums are reduced in two levels (RED_B
+// partials per block of the first level, then one block over at most RED_MAX)
+constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = 2048, RED_MAX = KRYB / RED_B;
 constexpr int CHUNK = 8;       // BiCGStab iterations enqueued between convergence checks
 constexpr int KRY_RESTARTS = 6;      // restarts from the true residual per solve
 constexpr double CHEB2_A = 0.01, CHEB2_B = 2.0;   // eigenvalue interval of the Jacobi-scaled isotropic operator
@@ -278,7 +282,8 @@ struct VecArgs {
     size_t n;                  // N * P
     const double *En;          // E^n (rhs)
     double *bv, *x, *r, *r0, *p, *ph, *v, *s, *sh, *t;
-    double *part;              // [k * MAXB + block]
+    double *part;              // [k * KRYB + block]
+    double *part2;             // [k * RED_MAX + block] (first reduction level)
     double *sc;                // scalars
     int *fl;                   // flags
     double tol;
@@ -303,7 +308,7 @@ __device__ __forceinline__ void block_sums(double *vals, int k, double *part)
     if (threadIdx.x < k) {
         double v = 0.0;
         for (int i = 0; i < B2 / 64; ++i) v += red[threadIdx.x][i];
-        part[threadIdx.x * MAXB + blockIdx.x] = v;
+        part[threadIdx.x * KRYB + blockIdx.x] = v;
     }
 }
 
@@ -890,11 +895,9 @@ __global__ void __launch_bounds__(B2) copy_kernel(double *dst, const double *src
 }
 
 // sum of the partials of dot k over nb blocks, in a fixed order (one block of B2 threads)
-__device__ __forceinline__ double fin_sum(const double *part, int k, int nb)
+__device__ __forceinline__ double block_reduce(double v)
 {
     __shared__ double red[B2];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += B2) v += part[k * MAXB + i];
     red[threadIdx.x] = v;
     __syncthreads();
     for (int o = B2 / 2; o > 0; o >>= 1) {
@@ -906,13 +909,37 @@ __device__ __forceinline__ double fin_sum(const double *part, int k, int nb)
     return r;
 }
 
+// first reduction level: block b sums partials b*RED_B .. of each of k sums
+__global__ void __launch_bounds__(B2) red2d_kernel(VecArgs A, int which, int k, int nb)
+{
+    if (which != 0 && A.fl[F_STATE] != 0) return;
+    const int base = blockIdx.x * RED_B, cnt = min(RED_B, nb - base);
+    for (int q = 0; q < k; ++q) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < cnt; i += B2) v += A.part[q * KRYB + base + i];
+        v = block_reduce(v);
+        if (threadIdx.x == 0) A.part2[q * RED_MAX + blockIdx.x] = v;
+    }
+}
+
+// sum k of the nb partials (through the first level when nb > RED_B)
+__device__ __forceinline__ double fin_sum(const VecArgs &A, int k, int nb)
+{
+    const bool two = nb > RED_B;
+    const double *part = two ? A.part2 : A.part;
+    const int stride = two ? RED_MAX : KRYB, cnt = two ? (nb + RED_B - 1) / RED_B : nb;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += B2) v += part[k * stride + i];
+    return block_reduce(v);
+}
+
 // which: 0 = start (rho = rr = (r, r), bb, test), 1 = alpha, 2 = omega, 3 = rho/beta/test
 __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
 {
     if (which != 0 && A.fl[F_STATE] != 0) return;
     double *sc = A.sc;
     if (which == 0) {
-        const double rr = fin_sum(A.part, 0, nb), bb = fin_sum(A.part, 1, nb), mm = fin_sum(A.part, 2, nb);
+        const double rr = fin_sum(A, 0, nb), bb = fin_sum(A, 1, nb), mm = fin_sum(A, 2, nb);
         if (threadIdx.x == 0) {
             sc[S_RHO] = rr;
             sc[S_RR] = rr;
@@ -923,14 +950,14 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
             A.fl[F_STATE] = (rr <= A.tol * A.tol * bb) ? 1 : 0;
         }
     } else if (which == 1) {
-        const double rv = fin_sum(A.part, 0, nb);
+        const double rv = fin_sum(A, 0, nb);
         if (threadIdx.x == 0) {
             sc[S_RV] = rv;
             if (rv == 0.0 || !isfinite(rv)) A.fl[F_STATE] = 2;
             else sc[S_ALPHA] = sc[S_RHO] / rv;
         }
     } else if (which == 2) {
-        const double ts = fin_sum(A.part, 0, nb), tt = fin_sum(A.part, 1, nb);
+        const double ts = fin_sum(A, 0, nb), tt = fin_sum(A, 1, nb);
         if (threadIdx.x == 0) {
             sc[S_TS] = ts;
             sc[S_TT] = tt;
@@ -940,7 +967,7 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
             else sc[S_OMEGA] = tt == 0.0 ? 0.0 : ts / tt;
         }
     } else {
-        const double rho = fin_sum(A.part, 0, nb), rr = fin_sum(A.part, 1, nb);
+        const double rho = fin_sum(A, 0, nb), rr = fin_sum(A, 1, nb);
         if (threadIdx.x == 0) {
             const int its = A.fl[F_ITS] + 1;
             A.fl[F_ITS] = its;
@@ -1220,7 +1247,7 @@ struct grte2d_ctx {
     // Krylov
     double *bv = nullptr, *x = nullptr, *r = nullptr, *r0 = nullptr, *p = nullptr, *ph = nullptr;
     double *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr, *Es = nullptr;
-    double *part = nullptr, *sc = nullptr;
+    double *part = nullptr, *part2 = nullptr, *sc = nullptr;
     int *fl = nullptr, *stat = nullptr;
     int *h_fl = nullptr;      // pinned
     double *h_sc = nullptr;   // pinned
@@ -1274,6 +1301,12 @@ int nblocks(size_t n)
 {
     const size_t b = (n + B2 - 1) / B2;
     return (int)std::max<size_t>(1, std::min<size_t>(b, MAXB));
+}
+
+int kblocks(size_t n)
+{
+    const size_t b = (n + (size_t)B2 * KRY_ITEMS - 1) / ((size_t)B2 * KRY_ITEMS);
+    return (int)std::max<size_t>(1, std::min<size_t>(b, KRYB));
 }
 
 Sys make_sys(grte2d_ctx *c, int corr, double eps)
@@ -1489,6 +1522,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.sh = c->sh;
     A.t = c->t;
     A.part = c->part;
+    A.part2 = c->part2;
     A.sc = c->sc;
     A.fl = c->fl;
     A.tol = c->tol;
@@ -1502,14 +1536,20 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.dS = iso ? c->dS : nullptr;
     A.yP = iso ? c->yP : nullptr;
     A.yS = iso ? c->yS : nullptr;
-    const int nb = nblocks(c->nE);
+    const int nb = kblocks(c->nE);
     hipStream_t st = c->stream;
+    // the scalar step `which` of the iteration after a kernel that left k partial sums per block
+    auto fin = [&](int which, int k) {
+        if (nb > RED_B)
+            hipLaunchKernelGGL(red2d_kernel, dim3((nb + RED_B - 1) / RED_B), dim3(B2), 0, st, A, which, k, nb);
+        hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, which, nb);
+    };
     int its_total = 0, state = 0;
     double res = INFINITY;
     for (int restart = 0; restart <= KRY_RESTARTS; ++restart) {
         hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
         hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
-        hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 0, nb);
+        fin(0, 3);
         hipLaunchKernelGGL(zero2_kernel, dim3(nb), dim3(B2), 0, st, c->p, c->v, c->nE);
         if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
             return GRTE_E_HIP;
@@ -1542,13 +1582,13 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
                 if (timed && k == 0) (void)hipEventRecord(c->ev0, st);
                 hipLaunchKernelGGL(apply2d_kernel<1>, dim3(nb), dim3(B2), 0, st, A);
                 if (timed && k == 0) (void)hipEventRecord(c->ev1, st);
-                hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 1, nb);
+                fin(1, 1);
                 hipLaunchKernelGGL(supd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
                 if (iso) iso_solve(c, S, c->yS, c->dS, st);
                 hipLaunchKernelGGL(apply2d_kernel<2>, dim3(nb), dim3(B2), 0, st, A);
-                hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 2, nb);
+                fin(2, 2);
                 hipLaunchKernelGGL(xupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
-                hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 3, nb);
+                fin(3, 2);
             }
             if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
             if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1570,7 +1610,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             // one more true residual for the report
             hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
             hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
-            hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, 0, nb);
+            fin(0, 3);
             if (hipMemcpyAsync(c->h_sc, c->sc, S_NS * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GRTE_E_HIP;
             if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
@@ -1682,7 +1722,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
-              dalloc(c, c->Es, c->nE) && dalloc(c, c->part, 3 * MAXB) && dalloc(c, c->sc, S_NS) &&
+              dalloc(c, c->Es, c->nE) && dalloc(c, c->part, 3 * KRYB) && dalloc(c, c->part2, 3 * RED_MAX) && dalloc(c, c->sc, S_NS) &&
               dalloc(c, c->fl, F_NF) && dalloc(c, c->stat, 8);
     if (ok) ok = hipHostMalloc((void **)&c->h_fl, F_NF * sizeof(int)) == hipSuccess;
     if (ok) ok = hipHostMalloc((void **)&c->h_sc, S_NS * sizeof(double)) == hipSuccess;
