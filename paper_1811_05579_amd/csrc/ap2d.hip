@@ -52,7 +52,7 @@ constexpr int MAXB = 2048;     // blocks of the grid-stride kernels outside the 
 // KRYB blocks); their per-block partial sums are reduced in two levels (RED_B
 // partials per block of the first level, then one block over at most RED_MAX)
 constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = 2048, RED_MAX = KRYB / RED_B;
-constexpr int CHUNK = 8;       // BiCGStab iterations enqueued between convergence checks
+constexpr int CHUNK = 8;       // most BiCGStab iterations enqueued between convergence checks
 constexpr int KRY_RESTARTS = 6;      // restarts from the true residual per solve
 constexpr double CHEB2_A = 0.01, CHEB2_B = 2.0;   // eigenvalue interval of the Jacobi-scaled isotropic operator
 constexpr double KRY_FLOOR = 64.0;   // floor stop: true residual within this factor of its rounding level
@@ -1266,6 +1266,7 @@ struct grte2d_ctx {
     // isotropic correction of the preconditioner
     int iso_kind = 1;                    // 0 none, 1 Chebyshev (tiled), 2 multigrid V-cycle, 3 Chebyshev per step
     int iso_k = 19;                      // Chebyshev steps (two tiled launches)
+    int last_its[2] = {-1, -1};          // iterations of the last prediction / correction solve (-1: none yet)
     int mg_nu = 2;                       // multigrid: Jacobi sweeps before and after the coarse correction
     struct Lv {
         MgRows R;
@@ -1545,6 +1546,10 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
         hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, which, nb);
     };
     int its_total = 0, state = 0;
+    // iterations are enqueued in batches between convergence checks; the
+    // batches are sized to end where the last solve of the same kind ended
+    // (iteration counts change slowly from step to step), and iterations
+    // enqueued past convergence return at once
     double res = INFINITY;
     for (int restart = 0; restart <= KRY_RESTARTS; ++restart) {
         hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
@@ -1574,9 +1579,13 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
         }
         if (restart == KRY_RESTARTS || its_total >= c->maxit) break;
         A.maxit = c->maxit - its_total;    // the cap holds for the whole solve
+        int inpass = 0;                    // iterations enqueued in this pass
         while (true) {
             const bool timed = c->profiling != 0;
-            for (int k = 0; k < CHUNK; ++k) {
+            const int last = c->last_its[S.corr], left = last - (its_total + inpass);
+            const int batch = last < 0 ? CHUNK : (left >= 1 ? std::min(CHUNK, left) : 2);
+            inpass += batch;
+            for (int k = 0; k < batch; ++k) {
                 hipLaunchKernelGGL(pupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
                 if (iso) iso_solve(c, S, c->yP, c->dP, st);
                 if (timed && k == 0) (void)hipEventRecord(c->ev0, st);
@@ -1619,6 +1628,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             break;
         }
     }
+    c->last_its[S.corr] = its_total;
     its_out = its_total;
     state_out = state;
     res_out = res;
