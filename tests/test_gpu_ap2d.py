@@ -283,6 +283,30 @@ def test_tiled_chebyshev_equals_per_step(nx, ny, steps):
         assert np.array_equal(a, b)
 
 
+def test_step_independent_of_convergence_check_batches():
+    """The host reads the convergence flag after batches of iterations sized
+    from the previous solve; iterations enqueued past convergence do nothing,
+    so a context with that history and a fresh one (batches of eight) take
+    the same step from the same state, to the bit."""
+    w = _two_material(40, 32, (1.0, 100.0), 1e-3, 18110000 + 3)
+    g = _ctx(w)
+    g.set_state(w.E, w.Ox, w.Oy, w.T)
+    for _ in range(3):
+        assert g.step(w.dt, w.eps, info=True)["status"] == 0
+    s1 = g.get_state()
+    i_hist = g.step(w.dt, w.eps, info=True)
+    s_hist = g.get_state()
+    g.close()
+    f = _ctx(w)
+    f.set_state(*s1)
+    i_fresh = f.step(w.dt, w.eps, info=True)
+    s_fresh = f.get_state()
+    f.close()
+    assert (i_hist["pred_iters"], i_hist["corr_iters"]) == (i_fresh["pred_iters"], i_fresh["corr_iters"])
+    for a, b in zip(s_hist, s_fresh):
+        assert np.array_equal(a, b)
+
+
 def test_isotropic_correction_arguments():
     """Step counts outside 1..64 and unknown kinds are rejected."""
     w = random_state_2d(8, 8, 8, 1)
