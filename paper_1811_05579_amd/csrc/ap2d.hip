@@ -635,7 +635,7 @@ __global__ void __launch_bounds__(B2) iso_step_kernel(IsoArgs A)
     for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
         double Dx, diag;
         iso_row(A, j, A.xin, Dx, diag);
-        const double r = (A.y[j] - Dx) / diag;
+        const double r = (A.y[j] - Dx) * (1.0 / diag);
         const double dn = A.c1 * A.d[j] + A.c2 * r;
         A.d[j] = dn;
         A.xout[j] = A.xin[j] + dn;
@@ -687,19 +687,28 @@ __global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
         GY[f] = (iy >= 0 && iy <= S.ny && ix >= 0 && ix < S.nx) ? S.gy[iy * S.nx + ix] : 0.0;
     }
     __syncthreads();
-    double y[ISO_CPT], dg[ISO_CPT], kc[ISO_CPT], d[ISO_CPT], xn[ISO_CPT];
+    // per cell: its own values in registers, and its region position packed as
+    // rx | ry << 8 | (depth + 1) << 16, depth = distance to the region's border
+    // (-1: outside the region or the grid), so that stencil step s updates the
+    // cells of depth > s and the tile is the cells of depth >= h
+    double y[ISO_CPT], dg[ISO_CPT], rdg[ISO_CPT], kc[ISO_CPT], d[ISO_CPT], xn[ISO_CPT];
+    int pk[ISO_CPT];
 #pragma unroll
     for (int i = 0; i < ISO_CPT; ++i) {
         const int c = t + i * ISO_TB;
-        y[i] = dg[i] = kc[i] = d[i] = xn[i] = 0.0;
+        y[i] = dg[i] = rdg[i] = kc[i] = d[i] = xn[i] = 0.0;
+        pk[i] = 0;
         if (c >= R * R) continue;
         const int ry = c / R, rx = c - ry * R;
         const int iy = oy + ry, ix = ox + rx;
         if (iy < 0 || iy >= S.ny || ix < 0 || ix >= S.nx) continue;
+        const int dep = min(min(rx, R - 1 - rx), min(ry, R - 1 - ry));
+        pk[i] = rx | (ry << 8) | ((dep + 1) << 16);
         const int j = iy * S.nx + ix;
         const Faces g = iso_walls(S, iy, ix, Faces{GX[ry * (R + 1) + rx], GX[ry * (R + 1) + rx + 1],
                                                     GY[ry * R + rx], GY[(ry + 1) * R + rx]});
         dg[i] = iso_diag(A, iy, ix, j, g);
+        rdg[i] = 1.0 / dg[i];
         kc[i] = S.kco[j];
         y[i] = A.y[j];
         if (F.first) {
@@ -720,44 +729,34 @@ __global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
         const double c1 = F.c1[s], c2 = F.c2[s];
 #pragma unroll
         for (int i = 0; i < ISO_CPT; ++i) {
+            if ((pk[i] >> 16) - 1 <= s) continue;
             const int c = t + i * ISO_TB;
-            if (c >= R * R) continue;
-            const int ry = c / R, rx = c - ry * R;
-            if (rx <= s || rx >= R - 1 - s || ry <= s || ry >= R - 1 - s) continue;
+            const int rx = pk[i] & 0xff, ry = (pk[i] >> 8) & 0xff;
             const int iy = oy + ry, ix = ox + rx;
-            if (iy < 0 || iy >= S.ny || ix < 0 || ix >= S.nx) continue;
             const Faces g = iso_walls(S, iy, ix, Faces{GX[ry * (R + 1) + rx], GX[ry * (R + 1) + rx + 1],
                                                         GY[ry * R + rx], GY[(ry + 1) * R + rx]});
             const double xc = X[c];
             const double xl = ix > 0 ? X[c - 1] : 0.0, xr = ix < S.nx - 1 ? X[c + 1] : 0.0;
             const double xb = iy > 0 ? X[c - R] : 0.0, xt = iy < S.ny - 1 ? X[c + R] : 0.0;
             const double Dx = iso_Dx(A, kc[i], dg[i], g, xc, xl, xr, xb, xt);
-            const double r = (y[i] - Dx) / dg[i];
+            const double r = (y[i] - Dx) * rdg[i];
             const double dn = c1 * d[i] + c2 * r;
             d[i] = dn;
             xn[i] = xc + dn;
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < ISO_CPT; ++i) {
-            const int c = t + i * ISO_TB;
-            if (c >= R * R) continue;
-            const int ry = c / R, rx = c - ry * R;
-            if (rx <= s || rx >= R - 1 - s || ry <= s || ry >= R - 1 - s) continue;
-            X[c] = xn[i];
-        }
+        for (int i = 0; i < ISO_CPT; ++i)
+            if ((pk[i] >> 16) - 1 > s) X[t + i * ISO_TB] = xn[i];
         __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < ISO_CPT; ++i) {
-        const int c = t + i * ISO_TB;
-        if (c >= R * R) continue;
-        const int ry = c / R, rx = c - ry * R;
-        if (rx < h || rx >= h + ISO_T || ry < h || ry >= h + ISO_T) continue;
-        const int iy = oy + ry, ix = ox + rx;
-        if (iy >= S.ny || ix >= S.nx) continue;
-        A.xout[iy * S.nx + ix] = X[c];
-        if (F.dout) F.dout[iy * S.nx + ix] = d[i];
+        if ((pk[i] >> 16) - 1 < h) continue;
+        const int rx = pk[i] & 0xff, ry = (pk[i] >> 8) & 0xff;
+        const int j = (oy + ry) * S.nx + ox + rx;
+        A.xout[j] = X[t + i * ISO_TB];
+        if (F.dout) F.dout[j] = d[i];
     }
 }
 
