@@ -72,6 +72,7 @@ struct Sys {
     const double *rb1, *rb0, *acU;       // rhs = rb1 E^n_p + rb0; acU (correction's known part)
     const double *sab, *ue;              // residual in difference form (see residual_at)
     const double *pgc;                   // cell: g / (1 - g sum_p omega_p / d_p) of the block inverse
+    const double *idg;                   // (cell, pair): 1 / d_p of the block inverse
 };
 
 // (iy, ix) of cell j without an integer division: the binary64 product is off
@@ -461,14 +462,18 @@ __device__ __forceinline__ double block_idiag(const Sys &S, int j, int p)
     return 1.0 / (S.lam[j] + S.kco[j] * tr);
 }
 
-// the system-dependent scalar of each cell's Sherman-Morrison inverse,
-// g / (1 - g sum_p omega_p / d_p), once per prediction solve
-__global__ void __launch_bounds__(B2) pgc2d_kernel(Sys S, double *pgc, size_t n)
+// the system-dependent parts of each cell's block inverse, once per solve:
+// 1 / d_p for every (cell, pair) and, with angular coupling (the prediction),
+// the Sherman-Morrison scalar g / (1 - g sum_p omega_p / d_p) of the cell
+__global__ void __launch_bounds__(B2) pgc2d_kernel(Sys S, double *idg, double *pgc, size_t n)
 {
     const int P = S.P;
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) {
         const int j = t >> S.lgP, p = t & (P - 1);
-        const double s2 = group_sum(S.om[p] * block_idiag(S, j, p), P);
+        const double id = block_idiag(S, j, p);
+        idg[t] = id;
+        if (S.corr) continue;
+        const double s2 = group_sum(S.om[p] * id, P);
         const double g = S.cg[j];
         if (p == 0) pgc[j] = g / (1.0 - g * s2);
     }
@@ -476,9 +481,9 @@ __global__ void __launch_bounds__(B2) pgc2d_kernel(Sys S, double *pgc, size_t n)
 
 // cell-block Jacobi: z = B^{-1} y, B = diag(d_p) - g 1 omega^T (Sherman-Morrison);
 // the correction's blocks have g = 0 and are diagonal
-__device__ __forceinline__ double precond_at(const Sys &S, double y, int j, int p)
+__device__ __forceinline__ double precond_at(const Sys &S, double y, int t, int j, int p)
 {
-    const double id = block_idiag(S, j, p);
+    const double id = S.idg[t];
     const double u = y * id;
     if (S.corr) return u;
     const double s1 = group_sum(S.om[p] * u, S.P);
@@ -495,7 +500,7 @@ __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
         const int j = t >> A.S.lgP, p = t & (P - 1);
         const double pv = A.r[t] + beta * (A.p[t] - omega * A.v[t]);
         A.p[t] = pv;
-        A.ph[t] = precond_at(A.S, pv, j, p);
+        A.ph[t] = precond_at(A.S, pv, t, j, p);
         if (A.yP) {
             const double y = group_sum(A.S.om[p] * pv, P);
             if (p == 0) A.yP[j] = y;
@@ -513,7 +518,7 @@ __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
         const int j = t >> A.S.lgP, p = t & (P - 1);
         const double sv = A.r[t] - alpha * A.v[t];
         A.s[t] = sv;
-        A.sh[t] = precond_at(A.S, sv, j, p);
+        A.sh[t] = precond_at(A.S, sv, t, j, p);
         if (A.yS) {
             const double y = group_sum(A.S.om[p] * sv, P);
             if (p == 0) A.yS[j] = y;
@@ -1275,6 +1280,7 @@ struct grte2d_ctx {
     double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
     double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
     double *pgc = nullptr;               // per-cell scalar of the block inverse
+    double *idg = nullptr;               // per-(cell, pair) inverse diagonal of the block inverse
     double *idir2 = nullptr;             // second Chebyshev direction buffer of the tiled launches
     // sampled timing of the operator kernel (first iteration of every chunk)
     int profiling = 0;
@@ -1347,6 +1353,7 @@ Sys make_sys(grte2d_ctx *c, int corr, double eps)
     S.sab = c->sab;
     S.ue = c->ue;
     S.pgc = c->pgc;
+    S.idg = c->idg;
     return S;
 }
 
@@ -1530,7 +1537,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     // the isotropic correction targets the angular coupling of the prediction;
     // the correction's systems have none
     const bool iso = c->iso_kind != 0 && !S.corr;
-    if (!S.corr) hipLaunchKernelGGL(pgc2d_kernel, dim3(nblocks(c->nE)), dim3(B2), 0, c->stream, S, c->pgc, c->nE);
+    hipLaunchKernelGGL(pgc2d_kernel, dim3(nblocks(c->nE)), dim3(B2), 0, c->stream, S, c->idg, c->pgc, c->nE);
     if (iso && c->iso_kind == 2) mg_setup(c, S, c->stream);
     A.dP = iso ? c->dP : nullptr;
     A.dS = iso ? c->dS : nullptr;
@@ -1727,7 +1734,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   }
                   return true;
               }() &&
-              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
