@@ -289,11 +289,15 @@ struct VecArgs {
     int *fl;                   // flags
     double tol;
     int maxit;
-    // isotropic (diffusion) correction of the preconditioner: the preconditioned
-    // vectors are ph + dP[cell] and sh + dS[cell]; yP, yS receive sum_p omega_p p_p,
-    // sum_p omega_p s_p (null: no correction)
+    // isotropic (diffusion) correction of the preconditioner (null: none): the
+    // preconditioned vectors are B^{-1} p + dP[cell] and B^{-1} s + dS[cell], dP and
+    // dS the correction applied to yP = sum_p omega_p p_p and yS = sum_p omega_p s_p.
+    // yP and yS are formed per cell from the moments mr = sum_p omega_p r_p and
+    // mv = sum_p omega_p v_p, which the kernels producing r and v also write
+    // (p = r + beta (p - omega v), s = r - alpha v are linear), so that the
+    // correction can be solved before the update that adds it
     const double *dP, *dS;
-    double *yP, *yS;
+    double *yP, *yS, *mr, *mv;
 };
 
 __device__ __forceinline__ void block_sums(double *vals, int k, double *part)
@@ -328,22 +332,14 @@ __global__ void __launch_bounds__(B2) rhs2d_kernel(VecArgs A)
     }
 }
 
-// y = A (x + 1 d) for the (cell, pair) of thread t; d (null: none) is a per-cell
-// isotropic shift, which the angular coupling does not see
-__device__ __forceinline__ double apply_at(const Sys &S, const double *x, const double *d, int t, int j, int p)
+// y = A x for the (cell, pair) of thread t
+__device__ __forceinline__ double apply_at(const Sys &S, const double *x, int t, int j, int p)
 {
     const int P = S.P;
     int iy, ix;
     cell_yx(S, j, iy, ix);
-    Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
+    const Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
     const double xp = X.v[1][1];
-    if (d) {
-        const Nb D = load_nb(d, S.nx, S.ny, iy, ix, 1, 0);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) X.v[a][c] += D.v[a][c];
-    }
     Grad O;
     faces<false, true>(S, iy, ix, p, &X, O);
     // W1 x_p - sum_q omega_q x_q, referred to the cell's first pair to keep it
@@ -422,15 +418,23 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
             const double rr = residual_at(S, A.En, A.x, t, j, p, mag);
             A.r[t] = rr;
             A.r0[t] = rr;
+            if (A.mr) {
+                const double m = group_sum(S.om[p] * rr, P);
+                if (p == 0) A.mr[j] = m;
+            }
             acc[0] += rr * rr;
             acc[1] += A.bv[t] * A.bv[t];
             acc[2] += mag * mag;
         } else if (MODE == 1) {
-            const double y = apply_at(S, A.ph, A.dP, t, j, p);
+            const double y = apply_at(S, A.ph, t, j, p);
             A.v[t] = y;
+            if (A.mv) {
+                const double m = group_sum(S.om[p] * y, P);
+                if (p == 0) A.mv[j] = m;
+            }
             acc[0] += A.r0[t] * y;
         } else {
-            const double y = apply_at(S, A.sh, A.dS, t, j, p);
+            const double y = apply_at(S, A.sh, t, j, p);
             A.t[t] = y;
             const double sv = A.s[t];
             acc[0] += y * sv;
@@ -490,7 +494,7 @@ __device__ __forceinline__ double precond_at(const Sys &S, double y, int t, int 
     return u + S.pgc[j] * s1 * id;
 }
 
-// p = r + beta (p - omega v); ph = B^{-1} p
+// p = r + beta (p - omega v); ph = B^{-1} p (+ dP)
 __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
@@ -500,15 +504,11 @@ __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
         const int j = t >> A.S.lgP, p = t & (P - 1);
         const double pv = A.r[t] + beta * (A.p[t] - omega * A.v[t]);
         A.p[t] = pv;
-        A.ph[t] = precond_at(A.S, pv, t, j, p);
-        if (A.yP) {
-            const double y = group_sum(A.S.om[p] * pv, P);
-            if (p == 0) A.yP[j] = y;
-        }
+        A.ph[t] = precond_at(A.S, pv, t, j, p) + (A.dP ? A.dP[j] : 0.0);
     }
 }
 
-// s = r - alpha v; sh = B^{-1} s
+// s = r - alpha v; sh = B^{-1} s (+ dS)
 __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
@@ -518,25 +518,40 @@ __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
         const int j = t >> A.S.lgP, p = t & (P - 1);
         const double sv = A.r[t] - alpha * A.v[t];
         A.s[t] = sv;
-        A.sh[t] = precond_at(A.S, sv, t, j, p);
-        if (A.yS) {
-            const double y = group_sum(A.S.om[p] * sv, P);
-            if (p == 0) A.yS[j] = y;
-        }
+        A.sh[t] = precond_at(A.S, sv, t, j, p) + (A.dS ? A.dS[j] : 0.0);
     }
 }
 
-// x += alpha ph + omega sh (one pass over x); r = s - omega t; partial (r0, r), (r, r)
+// the isotropic correction's inputs from the moments:
+// which 0: yP = mr + beta (yP - omega mv) (yP holds the last direction's moment);
+// which 1: yS = mr - alpha mv
+__global__ void __launch_bounds__(B2) ymom2d_kernel(VecArgs A, int which, int n)
+{
+    if (A.fl[F_STATE] != 0) return;
+    const double alpha = A.sc[S_ALPHA], beta = A.sc[S_BETA], omega = A.sc[S_OMEGA];
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        if (which == 0) A.yP[j] = A.mr[j] + beta * (A.yP[j] - omega * A.mv[j]);
+        else A.yS[j] = A.mr[j] - alpha * A.mv[j];
+    }
+}
+
+// x += alpha ph + omega sh (one pass over x); r = s - omega t (and its moment);
+// partial (r0, r), (r, r)
 __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double alpha = A.sc[S_ALPHA], omega = A.sc[S_OMEGA];
+    const int P = A.S.P;
     double acc[2] = {0.0, 0.0};
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
-        const int j = t >> A.S.lgP;
-        A.x[t] += alpha * (A.ph[t] + (A.dP ? A.dP[j] : 0.0)) + omega * (A.sh[t] + (A.dS ? A.dS[j] : 0.0));
+        const int j = t >> A.S.lgP, p = t & (P - 1);
+        A.x[t] += alpha * A.ph[t] + omega * A.sh[t];
         const double rv = A.s[t] - omega * A.t[t];
         A.r[t] = rv;
+        if (A.mr) {
+            const double m = group_sum(A.S.om[p] * rv, P);
+            if (p == 0) A.mr[j] = m;
+        }
         acc[0] += A.r0[t] * rv;
         acc[1] += rv * rv;
     }
@@ -1281,6 +1296,7 @@ struct grte2d_ctx {
     double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
     double *pgc = nullptr;               // per-cell scalar of the block inverse
     double *idg = nullptr;               // per-(cell, pair) inverse diagonal of the block inverse
+    double *mr = nullptr, *mv = nullptr;  // angular moments of r and v (isotropic correction)
     double *idir2 = nullptr;             // second Chebyshev direction buffer of the tiled launches
     // sampled timing of the operator kernel (first iteration of every chunk)
     int profiling = 0;
@@ -1543,6 +1559,9 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.dS = iso ? c->dS : nullptr;
     A.yP = iso ? c->yP : nullptr;
     A.yS = iso ? c->yS : nullptr;
+    A.mr = iso ? c->mr : nullptr;
+    A.mv = iso ? c->mv : nullptr;
+    const int nbc = nblocks(c->N);
     const int nb = kblocks(c->nE);
     hipStream_t st = c->stream;
     // the scalar step `which` of the iteration after a kernel that left k partial sums per block
@@ -1562,6 +1581,8 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
         hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
         fin(0, 3);
         hipLaunchKernelGGL(zero2_kernel, dim3(nb), dim3(B2), 0, st, c->p, c->v, c->nE);
+        // the moments of p and v start from zero with them
+        if (iso) hipLaunchKernelGGL(zero2_kernel, dim3(nbc), dim3(B2), 0, st, c->yP, c->mv, c->N);
         if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
             return GRTE_E_HIP;
         if (hipMemcpyAsync(c->h_sc, c->sc, S_NS * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1592,14 +1613,20 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             const int batch = last < 0 ? CHUNK : (left >= 1 ? std::min(CHUNK, left) : 2);
             inpass += batch;
             for (int k = 0; k < batch; ++k) {
+                if (iso) {
+                    hipLaunchKernelGGL(ymom2d_kernel, dim3(nbc), dim3(B2), 0, st, A, 0, (int)c->N);
+                    iso_solve(c, S, c->yP, c->dP, st);
+                }
                 hipLaunchKernelGGL(pupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
-                if (iso) iso_solve(c, S, c->yP, c->dP, st);
                 if (timed && k == 0) (void)hipEventRecord(c->ev0, st);
                 hipLaunchKernelGGL(apply2d_kernel<1>, dim3(nb), dim3(B2), 0, st, A);
                 if (timed && k == 0) (void)hipEventRecord(c->ev1, st);
                 fin(1, 1);
+                if (iso) {
+                    hipLaunchKernelGGL(ymom2d_kernel, dim3(nbc), dim3(B2), 0, st, A, 1, (int)c->N);
+                    iso_solve(c, S, c->yS, c->dS, st);
+                }
                 hipLaunchKernelGGL(supd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
-                if (iso) iso_solve(c, S, c->yS, c->dS, st);
                 hipLaunchKernelGGL(apply2d_kernel<2>, dim3(nb), dim3(B2), 0, st, A);
                 fin(2, 2);
                 hipLaunchKernelGGL(xupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
@@ -1734,7 +1761,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   }
                   return true;
               }() &&
-              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
