@@ -46,9 +46,9 @@ TRAFFIC = {
     ("config2", "fp32"): (None, None),
     ("config4", "fp64"): (None, None),
     ("config4", "fp32"): (1.4162e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
-    ("config3", "fp64"): (4.853e8, "profiles/apply2d_config3_hbm_traffic.txt"),
-    ("config3", "fp32"): (4.853e8, "profiles/apply2d_config3_hbm_traffic.txt"),   # Krylov vectors are binary64 either way
-    ("config5", "fp64"): (2.484e8, "profiles/apply2d_config5_hbm_traffic.txt"),
+    ("config3", "fp64"): (3.417e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config3", "fp32"): (3.417e8, "profiles/apply2d_config3_hbm_traffic.txt"),   # Krylov vectors are binary64 either way
+    ("config5", "fp64"): (1.767e8, "profiles/apply2d_config5_hbm_traffic.txt"),
 }
 
 
@@ -219,10 +219,12 @@ def main_batch(args):
 
 
 def op2d_algorithmic_bytes(N, P):
-    """Bytes the 2-D operator kernel must move at least once per launch: read
-    the search direction and the shadow residual, write the product (N*P each,
-    FP64), and read five N-sized cell and face coefficient arrays."""
-    return 8 * (3 * N * P + 5 * N)
+    """Bytes the 2-D operator kernel (v = A p-hat) must move at least once per
+    launch: read the preconditioned direction and write the product (N*P each,
+    FP64) and read five N-sized cell and face coefficient arrays (the
+    prediction's launches also write the product's angular moment, N values,
+    left out here)."""
+    return 8 * (2 * N * P + 5 * N)
 
 
 def cpu_baseline_2d(w, budget_s=20.0, n=32):

@@ -282,7 +282,7 @@ struct VecArgs {
     Sys S;
     size_t n;                  // N * P
     const double *En;          // E^n (rhs)
-    double *bv, *x, *r, *r0, *p, *ph, *v, *s, *sh, *t;
+    double *bv, *x, *r, *p, *ph, *v, *s, *sh, *t;
     double *part;              // [k * KRYB + block]
     double *part2;             // [k * RED_MAX + block] (first reduction level)
     double *sc;                // scalars
@@ -315,6 +315,17 @@ __device__ __forceinline__ void block_sums(double *vals, int k, double *part)
         for (int i = 0; i < B2 / 64; ++i) v += red[threadIdx.x][i];
         part[threadIdx.x * KRYB + blockIdx.x] = v;
     }
+}
+
+// the shadow vector of BiCGStab: a fixed pseudo-random value in [-1, 1) per
+// item (the splitmix64 output function of the item index), computed where used
+__device__ __forceinline__ double shadow(int t)
+{
+    unsigned long long z = (unsigned long long)(unsigned)t + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1p-52 - 1.0;
 }
 
 // rhs: rb1 E^n_p + rb0 - k div O(known)   (rb1 = K eps^2 prediction, K eps correction)
@@ -401,8 +412,8 @@ __device__ __forceinline__ double residual_at(const Sys &S, const double *En, co
     return S.rb1[j] * (En[t] - xp) + S.sab[j] * (S.ue[j] - xp) - g * (1.0 - S.W1) * xp - g * cpl - div;
 }
 
-// mode 0: r = b - A x, r0 = r, partial (r, r) and (b, b)
-// mode 1: v = A ph, partial (r0, v)
+// mode 0: r = b - A x, partial (r, r), (b, b), the backward-error scale and (h, r)
+// mode 1: v = A ph, partial (h, v)   (h: the shadow vector)
 // mode 2: t = A sh, partial (t, s), (t, t)
 template <int MODE>
 __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
@@ -410,14 +421,13 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
     if (A.fl[F_STATE] != 0 && MODE != 0) return;
     const Sys &S = A.S;
     const int P = S.P;
-    double acc[3] = {0.0, 0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
         const int j = t >> A.S.lgP, p = t & (P - 1);
         if (MODE == 0) {
             double mag;
             const double rr = residual_at(S, A.En, A.x, t, j, p, mag);
             A.r[t] = rr;
-            A.r0[t] = rr;
             if (A.mr) {
                 const double m = group_sum(S.om[p] * rr, P);
                 if (p == 0) A.mr[j] = m;
@@ -425,6 +435,7 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
             acc[0] += rr * rr;
             acc[1] += A.bv[t] * A.bv[t];
             acc[2] += mag * mag;
+            acc[3] += shadow(t) * rr;
         } else if (MODE == 1) {
             const double y = apply_at(S, A.ph, t, j, p);
             A.v[t] = y;
@@ -432,7 +443,7 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
                 const double m = group_sum(S.om[p] * y, P);
                 if (p == 0) A.mv[j] = m;
             }
-            acc[0] += A.r0[t] * y;
+            acc[0] += shadow(t) * y;
         } else {
             const double y = apply_at(S, A.sh, t, j, p);
             A.t[t] = y;
@@ -441,7 +452,7 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
             acc[1] += y * y;
         }
     }
-    block_sums(acc, MODE == 0 ? 3 : (MODE == 1 ? 1 : 2), A.part);
+    block_sums(acc, MODE == 0 ? 4 : (MODE == 1 ? 1 : 2), A.part);
 }
 
 // 1 / d_p: the inverse of the direction-diagonal part of a cell's block
@@ -536,7 +547,7 @@ __global__ void __launch_bounds__(B2) ymom2d_kernel(VecArgs A, int which, int n)
 }
 
 // x += alpha ph + omega sh (one pass over x); r = s - omega t (and its moment);
-// partial (r0, r), (r, r)
+// partial (h, r), (r, r)
 __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
@@ -552,7 +563,7 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
             const double m = group_sum(A.S.om[p] * rv, P);
             if (p == 0) A.mr[j] = m;
         }
-        acc[0] += A.r0[t] * rv;
+        acc[0] += shadow(t) * rv;
         acc[1] += rv * rv;
     }
     block_sums(acc, 2, A.part);
@@ -952,15 +963,16 @@ __device__ __forceinline__ double fin_sum(const VecArgs &A, int k, int nb)
     return block_reduce(v);
 }
 
-// which: 0 = start (rho = rr = (r, r), bb, test), 1 = alpha, 2 = omega, 3 = rho/beta/test
+// which: 0 = start (rho = (h, r), rr = (r, r), bb, test), 1 = alpha, 2 = omega, 3 = rho/beta/test
 __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
 {
     if (which != 0 && A.fl[F_STATE] != 0) return;
     double *sc = A.sc;
     if (which == 0) {
         const double rr = fin_sum(A, 0, nb), bb = fin_sum(A, 1, nb), mm = fin_sum(A, 2, nb);
+        const double hr = fin_sum(A, 3, nb);
         if (threadIdx.x == 0) {
-            sc[S_RHO] = rr;
+            sc[S_RHO] = hr;
             sc[S_RR] = rr;
             sc[S_BB] = bb;
             sc[S_MM] = mm;
@@ -1264,7 +1276,7 @@ struct grte2d_ctx {
     double *acU = nullptr, *beta = nullptr, *ustar = nullptr, *Dv = nullptr, *rhon = nullptr;
     double *sab = nullptr, *ue = nullptr;
     // Krylov
-    double *bv = nullptr, *x = nullptr, *r = nullptr, *r0 = nullptr, *p = nullptr, *ph = nullptr;
+    double *bv = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *ph = nullptr;
     double *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr, *Es = nullptr;
     double *part = nullptr, *part2 = nullptr, *sc = nullptr;
     int *fl = nullptr, *stat = nullptr;
@@ -1537,7 +1549,6 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.bv = c->bv;
     A.x = c->x;
     A.r = c->r;
-    A.r0 = c->r0;
     A.p = c->p;
     A.ph = c->ph;
     A.v = c->v;
@@ -1579,7 +1590,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     for (int restart = 0; restart <= KRY_RESTARTS; ++restart) {
         hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
         hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
-        fin(0, 3);
+        fin(0, 4);
         hipLaunchKernelGGL(zero2_kernel, dim3(nb), dim3(B2), 0, st, c->p, c->v, c->nE);
         // the moments of p and v start from zero with them
         if (iso) hipLaunchKernelGGL(zero2_kernel, dim3(nbc), dim3(B2), 0, st, c->yP, c->mv, c->N);
@@ -1652,7 +1663,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             // one more true residual for the report
             hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
             hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
-            fin(0, 3);
+            fin(0, 4);
             if (hipMemcpyAsync(c->h_sc, c->sc, S_NS * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GRTE_E_HIP;
             if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
@@ -1762,10 +1773,10 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   return true;
               }() &&
               dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
-              dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) && dalloc(c, c->r0, c->nE) &&
+              dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
-              dalloc(c, c->Es, c->nE) && dalloc(c, c->part, 3 * KRYB) && dalloc(c, c->part2, 3 * RED_MAX) && dalloc(c, c->sc, S_NS) &&
+              dalloc(c, c->Es, c->nE) && dalloc(c, c->part, 4 * KRYB) && dalloc(c, c->part2, 4 * RED_MAX) && dalloc(c, c->sc, S_NS) &&
               dalloc(c, c->fl, F_NF) && dalloc(c, c->stat, 8);
     if (ok) ok = hipHostMalloc((void **)&c->h_fl, F_NF * sizeof(int)) == hipSuccess;
     if (ok) ok = hipHostMalloc((void **)&c->h_sc, S_NS * sizeof(double)) == hipSuccess;
