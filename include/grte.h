@@ -171,6 +171,22 @@ typedef struct grte_reference_info {
 grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol, int maxit,
                                 grte_reference_info *info);
 
+/* How the prediction kernel is launched.  Its work-groups (one per parity
+ * pair, over all contexts of a grouped step) wait for each other at grid
+ * barriers inside the kernel, so all of them must be resident at once.
+ * cooperative = 1 (default): a cooperative launch, for which the runtime
+ * guarantees that.  cooperative = 0: an ordinary launch of the same grid,
+ * ~18 us faster per step on an MI355X; it relies on the grid fitting the
+ * device at once (checked at creation against the kernel's occupancy, as for
+ * the cooperative launch) and on no other work -- another stream, another
+ * process -- holding the device's compute units while the step runs.  For
+ * callers that own the device.  If the assumption fails, the barriers' bounded
+ * wait expires and the step reports sync_error (GRTE_E_HIP when info is
+ * requested) with invalid results; it never hangs.  The setting of the first
+ * context applies to a grouped step; the implicit reference step uses its
+ * context's.  GRTE_E_INVAL for a null ctx or a value other than 0 or 1. */
+grte_status grte_set_launch(grte_ctx *ctx, int cooperative);
+
 /* Storage of the intensity state: 0 = binary64 (default); 1 = binary32, with
  * E kept per cell and pair as its binary32 deviation from a c T^4 (T stays
  * binary64) and O in binary32.  The prediction, Newton and correction

@@ -177,6 +177,11 @@ class Grte:
         d["status"] = st
         return d
 
+    def set_launch(self, cooperative=True):
+        """Cooperative (default) or ordinary launch of the prediction kernel; the
+        ordinary one is faster but assumes no other work holds the device."""
+        check("grte_set_launch", self._lib.grte_set_launch(self._h, int(bool(cooperative))))
+
     def set_storage(self, fp32):
         """Store E (as its deviation from a c T^4) and O in binary32 (True) or
         binary64 (False); arithmetic stays binary64."""

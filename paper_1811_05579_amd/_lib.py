@@ -112,6 +112,7 @@ _SIGS = {
     "grte_mlp_predict": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_void_p]),
     "grte_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
     "grte_set_storage": (c_int, [c_void_p, c_int]),
+    "grte_set_launch": (c_int, [c_void_p, c_int]),
     "grte_reference_step": (c_int, [c_void_p, c_double, c_double, c_double, c_int,
                                     ctypes.POINTER(ReferenceInfo)]),
     "grte_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),

@@ -812,6 +812,7 @@ struct grte_ctx {
     int pred_accel = GRTE_ACCEL_CHEBYSHEV;
     double *hist = nullptr;       // convergence history of the last prediction solve
     int coop_capacity = 0;                 // co-resident prediction work-groups on the device
+    int coop_launch = 1;                   // 1: cooperative launch of the prediction; 0: ordinary launch
     int keep = 1;
     hipStream_t stream = nullptr;
     std::vector<double *> allocs;
@@ -924,9 +925,21 @@ size_t pred_lds_bytes()
     return (size_t)(3 * NT * M + tile_scratch<NT>() + 2 * red_doubles()) * sizeof(double);
 }
 
+// The prediction's work-groups wait for each other at grid barriers, so they
+// must all be resident at once.  The cooperative launch has the runtime
+// guarantee it; the ordinary launch (coop = false) relies on the grid fitting
+// the device at once (checked against the occupancy at creation) and on no
+// other work occupying it -- when that fails the bounded barrier times out and
+// the step reports a sync error (grte_step_info.sync_error, GRTE_E_HIP) instead
+// of waiting forever.
 template <int M>
-grte_status launch_pred(hipStream_t stream, Group<PredArgs> &g, int grid)
+grte_status launch_pred(hipStream_t stream, Group<PredArgs> &g, int grid, bool coop)
 {
+    if (!coop) {
+        hipLaunchKernelGGL(pred_kernel<M>, dim3(grid), dim3(NT), pred_lds_bytes<M>(), stream, g);
+        HIPCHK(hipGetLastError());
+        return GRTE_OK;
+    }
     void *args[] = {&g};
     HIPCHK(hipLaunchCooperativeKernel((const void *)pred_kernel<M>, dim3(grid), dim3(NT), args,
                                       (unsigned)pred_lds_bytes<M>(), stream));
@@ -1366,10 +1379,10 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     HIPCHK(hipGetLastError());
     if (sample && (st = prof_begin(c0, GRTE_TIMING_PREDICT, &ev_pred)) != GRTE_OK) return st;
     switch (M) {
-    case 2: st = launch_pred<2>(stream, gp, grid); break;
-    case 4: st = launch_pred<4>(stream, gp, grid); break;
-    case 8: st = launch_pred<8>(stream, gp, grid); break;
-    default: st = launch_pred<16>(stream, gp, grid); break;
+    case 2: st = launch_pred<2>(stream, gp, grid, c0->coop_launch != 0); break;
+    case 4: st = launch_pred<4>(stream, gp, grid, c0->coop_launch != 0); break;
+    case 8: st = launch_pred<8>(stream, gp, grid, c0->coop_launch != 0); break;
+    default: st = launch_pred<16>(stream, gp, grid, c0->coop_launch != 0); break;
     }
     if (st != GRTE_OK) return st;
     if ((st = prof_end(c0, ev_pred)) != GRTE_OK) return st;
@@ -1504,10 +1517,10 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
         pa.gen0 = ctx->bar_gen;
         ctx->bar_gen += 2ull * (unsigned long long)ctx->pred_maxit + 4ull;
         switch (M) {
-        case 2: st = launch_pred<2>(stream, gp, P); break;
-        case 4: st = launch_pred<4>(stream, gp, P); break;
-        case 8: st = launch_pred<8>(stream, gp, P); break;
-        default: st = launch_pred<16>(stream, gp, P); break;
+        case 2: st = launch_pred<2>(stream, gp, P, ctx->coop_launch != 0); break;
+        case 4: st = launch_pred<4>(stream, gp, P, ctx->coop_launch != 0); break;
+        case 8: st = launch_pred<8>(stream, gp, P, ctx->coop_launch != 0); break;
+        default: st = launch_pred<16>(stream, gp, P, ctx->coop_launch != 0); break;
         }
         if (st != GRTE_OK) return st;
         hipLaunchKernelGGL(clear_u64, dim3(1), dim3(64), 0, stream, dmax, 2);
@@ -1553,6 +1566,13 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
     }
     if (sync_err) return GRTE_E_HIP;
     return (converged && !pred_fail) ? GRTE_OK : GRTE_E_NOCONV;
+}
+
+grte_status grte_set_launch(grte_ctx *ctx, int cooperative)
+{
+    if (!ctx || (cooperative != 0 && cooperative != 1)) return GRTE_E_INVAL;
+    ctx->coop_launch = cooperative;
+    return GRTE_OK;
 }
 
 grte_status grte_set_storage(grte_ctx *ctx, int fp32)

@@ -179,6 +179,7 @@ def test_2d_host_checks(lib):
     assert lib.grte_get_intensity(None, 1.0, None, 0) == -1
     for kind in range(4):
         assert lib.grte2d_set_isotropic_correction(None, kind, 10) == -1
+    assert lib.grte_set_launch(None, 0) == -1
     assert lib.grte2d_destroy(None) == 0
 
 

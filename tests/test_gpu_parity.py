@@ -217,6 +217,43 @@ def test_group_step_equals_separate_steps():
         g.close()
 
 
+def test_ordinary_launch_equals_cooperative():
+    """The prediction under the ordinary launch (grte_set_launch(ctx, 0)) gives,
+    bit for bit, what the cooperative launch gives: five grouped steps of the
+    three config-2 eps runs at a reduced size, and five single-slab steps of the
+    full-size eps = 1e-4 run with sync_error 0 throughout."""
+    from paper_1811_05579_amd import step_group
+    ws = [config2(eps=e, N=600, nv=32) for e in (1.0, 1e-2, 1e-4)]
+    coop = [_ctx(w) for w in ws]
+    plain = [_ctx(w) for w in ws]
+    for w, a, b in zip(ws, coop, plain):
+        a.set_state(w.E, w.O, w.T)
+        b.set_state(w.E, w.O, w.T)
+        b.set_launch(cooperative=False)
+    for s in range(5):
+        ia = step_group(coop, [w.dt for w in ws], [w.eps for w in ws], info=True)
+        ib = step_group(plain, [w.dt for w in ws], [w.eps for w in ws], info=True)
+        assert all(i["status"] == 0 and i["sync_error"] == 0 for i in ia + ib)
+        for a, b in zip(coop, plain):
+            for x, y in zip(a.get_state(), b.get_state()):
+                assert np.array_equal(x, y), s
+    for g in coop + plain:
+        g.close()
+    w = config2(eps=1e-4)
+    a, b = _ctx(w), _ctx(w)
+    a.set_state(w.E, w.O, w.T)
+    b.set_state(w.E, w.O, w.T)
+    b.set_launch(cooperative=False)
+    for s in range(5):
+        assert a.step(w.dt, w.eps, info=True)["status"] == 0
+        ib = b.step(w.dt, w.eps, info=True)
+        assert ib["status"] == 0 and ib["sync_error"] == 0
+        for x, y in zip(a.get_state(), b.get_state()):
+            assert np.array_equal(x, y), s
+    a.close()
+    b.close()
+
+
 def test_profiling_samples_every_kth_step():
     """grte_set_profiling(ctx, k) times every k-th step (k = 1: every step)."""
     w = config1()
