@@ -358,7 +358,7 @@ def main():
                          "config4, as each workload is defined)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the single-GPU step; multi-GPU "
+        print("bench.py: runs on one GPU only (the single-GPU step; multi-GPU "
               "sharding is described, not built)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "config4":

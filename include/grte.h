@@ -41,7 +41,7 @@ typedef enum grte_status {
     GRTE_E_HIP = -3,         /* a HIP runtime call or kernel launch failed       */
     GRTE_E_NOCONV = -4,      /* step completed, but the prediction iteration or
                                 a Newton solve stopped at its cap (see info)    */
-    GRTE_E_UNSUPPORTED = -5  /* size beyond this build's limits (N > 4096 or
+    GRTE_E_UNSUPPORTED = -5  /* size beyond the library's limits (N > 4096 or
                                 P > 64)                                          */
 } grte_status;
 

@@ -21,7 +21,7 @@ Index conventions (0-based).  Cells j = 0..N-1 are the paper's i+1/2
 node i separates cell i-1 (left) from cell i (right).  Parity arrays are
 cell-major: E[j, p], O[i, p], p the parity pair (mu_p > 0).
 
-Readings of points the paper leaves open (listed in the design doc as well):
+Readings of points the paper leaves open:
   * sigma at an interior node: harmonic mean of the two adjacent cell values
     (the arithmetic mean of 1/sigma, the face rule of (6.7));
   * K at an interior node: arithmetic mean of the adjacent cell values, as

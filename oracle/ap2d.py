@@ -36,7 +36,7 @@ Layout (0-based):
 With periodic_y the faces fy and fy + ny coincide: Oy[ny] repeats Oy[0] and
 the edges 2, 3 carry no inflow.
 
-Readings of points this extension leaves open (listed in the design doc as well):
+Readings of points this extension leaves open:
   * sigma at a face: harmonic mean of the two cells, K: arithmetic mean (the
     1-D node rules);
   * the cell-centre odd parity used by the readout I = E +- eps O is the mean

@@ -997,7 +997,7 @@ const char *grte_status_string(grte_status s)
     case GRTE_E_NOMEM: return "device allocation failed";
     case GRTE_E_HIP: return "HIP runtime error";
     case GRTE_E_NOCONV: return "a solve stopped at its iteration cap";
-    case GRTE_E_UNSUPPORTED: return "size beyond the limits of this build";
+    case GRTE_E_UNSUPPORTED: return "size beyond the library's limits";
     }
     return "unknown status";
 }
