@@ -77,7 +77,28 @@ typedef struct grte_step_info {
     int guess_started;    /* cells whose Newton started from the learned value */
     int pred_floor_stop;  /* 1 if the prediction stopped at the rounding level
                              (counted in pred_converged; see grte_set_solver) */
+    /* Energy balance of the step, (3.12)-(3.13): binary64 sums in a fixed
+     * order (the same bits for the same state), formed by the projection
+     * kernel on every step. */
+    double energy_before;    /* E_tot^n = sum_j dx (rho^n_j / c + Cv T^n_j)        */
+    double energy_after;     /* E_tot^{n+1}, the same sum over the new state       */
+    double boundary_flux_dt; /* dt sum_p omega_p mu_p (O*_{N,p} - O*_{0,p}): the
+                                net outflow through the two ends, with the
+                                prediction's O* (the correction's moment
+                                equation (4.13) uses D from O*)                   */
+    double energy_defect;    /* energy_after - energy_before + boundary_flux_dt:
+                                the defect of (3.13), sum_j dx (rho^{n+1}_j -
+                                rho~_j) / c up to rounding; it vanishes with eps */
 } grte_step_info;
+
+/* Error flags of the steps since the last clear (grte_get_error_flags): the
+ * per-step counters of grte_step_info are reset by every step, these are not. */
+enum {
+    GRTE_ERRF_SYNC = 1,          /* a grid barrier of the prediction timed out  */
+    GRTE_ERRF_PRED_NOCONV = 2,   /* a prediction solve stopped at its cap       */
+    GRTE_ERRF_NEWTON = 4,        /* a Newton solve stopped at its cap           */
+    GRTE_ERRF_NEGATIVE_ROOT = 8  /* a cell's temperature equation had no root >= 0 */
+};
 
 /* Stages readable after a step (grte_get_stage), for checking and diagnostics. */
 enum {
@@ -186,6 +207,13 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
  * context applies to a grouped step; the implicit reference step uses its
  * context's.  GRTE_E_INVAL for a null ctx or a value other than 0 or 1. */
 grte_status grte_set_launch(grte_ctx *ctx, int cooperative);
+
+/* The GRTE_ERRF_* flags OR-ed over every step since the context was created
+ * or the flags were last cleared (clear != 0 clears them after reading).
+ * Lets a caller that enqueues many steps without `info` (no host
+ * synchronisation per step) check afterwards that none of them timed out at a
+ * grid barrier or stopped at an iteration cap.  Synchronises the stream. */
+grte_status grte_get_error_flags(grte_ctx *ctx, int *flags, int clear);
 
 /* Storage of the intensity state: 0 = binary64 (default); 1 = binary32, with
  * E kept per cell and pair as its binary32 deviation from a c T^4 (T stays
@@ -377,6 +405,9 @@ typedef struct grte_batch_info {   /* per instance, as grte_step_info         */
     int pred_iters, pred_converged, newton_max_iters, newton_failed;
     int kstar_clamped, negative_root;
     int pred_floor_stop;
+    /* energy balance of the instance's step, (3.12)-(3.13), as in
+     * grte_step_info (binary64, fixed summation order for a given tile) */
+    double energy_before, energy_after, boundary_flux_dt, energy_defect;
 } grte_batch_info;
 
 typedef struct grte_batch_tuning {
@@ -423,6 +454,11 @@ grte_status grte_batch_get_state(grte_batch *b, double *E, double *O, double *T,
  * previous step when the current state is the one that step produced
  * (grte_batch_set_state and grte_batch_set_storage return to rho^n). */
 grte_status grte_batch_step(grte_batch *b, grte_batch_info *info);
+/* GRTE_ERRF_* flags OR-ed over every step (of any instance) since creation or
+ * the last clear, as grte_get_error_flags: PRED_NOCONV, NEWTON and
+ * NEGATIVE_ROOT (the batched step has no grid barrier).  For callers that
+ * enqueue steps or graph replays without `info`.  Synchronises the stream. */
+grte_status grte_batch_get_error_flags(grte_batch *b, int *flags, int clear);
 /* Autotuner: times `trials` steps for each candidate (wavefront threshold
  * 0/128/256 x grid of 1, 2, ... work-groups per compute unit) from the
  * current state without changing it, orders the instances by the measured
@@ -496,6 +532,17 @@ typedef struct grte2d_step_info {
                                 being 2^-53 || |A| |x| + |b| ||_2 / ||b||_2 (the
                                 normwise backward-error floor of a binary64
                                 iterate; counted in *_converged)                   */
+    /* Energy balance of the step, (3.12)-(3.13) on the rectangle: binary64
+     * sums in a fixed order, formed on the device every step (values of the
+     * binary64 state, before a binary32 storage rounds it). */
+    double energy_before;    /* E_tot^n = sum_cells dx dy (rho^n / c + Cv T^n)    */
+    double energy_after;     /* E_tot^{n+1}                                       */
+    double boundary_flux_dt; /* dt x the net outflow through the four edges: dy
+                                sum_rows sum_p omega_p mu_p (O*x_right - O*x_left)
+                                + dx sum_cols sum_p omega_p eta_p (O*y_top -
+                                O*y_bottom), the prediction's edge face values    */
+    double energy_defect;    /* energy_after - energy_before + boundary_flux_dt:
+                                the defect of (3.13)                              */
 } grte2d_step_info;
 
 enum {

@@ -187,6 +187,13 @@ class Grte:
         binary64 (False); arithmetic stays binary64."""
         check("grte_set_storage", self._lib.grte_set_storage(self._h, int(bool(fp32))))
 
+    def error_flags(self, clear=False):
+        """Error flags OR-ed over the steps since the last clear (grte_get_error_flags):
+        a dict of booleans keyed by 'sync', 'pred_noconv', 'newton', 'negative_root'."""
+        f = ctypes.c_int()
+        check("grte_get_error_flags", self._lib.grte_get_error_flags(self._h, ctypes.byref(f), int(bool(clear))))
+        return {k: bool(f.value & b) for k, b in _lib.ERRF.items()}
+
     def set_guess(self, model, accept_tol=1e-10):
         """Learned initial guess for the temperature solve (None: Newton from T^n)."""
         h = model._h if model is not None else None
@@ -438,6 +445,13 @@ class GrteBatch:
         if st not in (0, -4):
             check("grte_batch_step", st)
         return st, [{k: getattr(a, k) for k, _ in BatchInfo._fields_} for a in arr]
+
+    def error_flags(self, clear=False):
+        """Error flags OR-ed over the steps since the last clear (grte_batch_get_error_flags)."""
+        f = ctypes.c_int()
+        check("grte_batch_get_error_flags",
+              self._lib.grte_batch_get_error_flags(self._h, ctypes.byref(f), int(bool(clear))))
+        return {k: bool(f.value & b) for k, b in _lib.ERRF.items()}
 
     def tune(self, trials=2):
         t = BatchTuning()

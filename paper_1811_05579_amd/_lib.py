@@ -24,10 +24,15 @@ class StepInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
                 ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int),
                 ("sync_error", c_int), ("guess_accepted", c_int), ("guess_rejected", c_int),
-                ("newton_total_iters", c_int), ("guess_started", c_int), ("pred_floor_stop", c_int)]
+                ("newton_total_iters", c_int), ("guess_started", c_int), ("pred_floor_stop", c_int),
+                ("energy_before", c_double), ("energy_after", c_double), ("boundary_flux_dt", c_double),
+                ("energy_defect", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ERRF = {"sync": 1, "pred_noconv": 2, "newton": 4, "negative_root": 8}
 
 
 class Instance(ctypes.Structure):
@@ -50,7 +55,8 @@ class ReferenceInfo(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("pred_iters", c_int), ("pred_converged", c_int), ("newton_max_iters", c_int),
                 ("newton_failed", c_int), ("kstar_clamped", c_int), ("negative_root", c_int),
-                ("pred_floor_stop", c_int)]
+                ("pred_floor_stop", c_int), ("energy_before", c_double), ("energy_after", c_double),
+                ("boundary_flux_dt", c_double), ("energy_defect", c_double)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -68,7 +74,8 @@ class StepInfo2D(ctypes.Structure):
                 ("newton_max_iters", c_int), ("newton_failed", c_int), ("kstar_clamped", c_int),
                 ("negative_root", c_int), ("newton_total_iters", c_int), ("guess_accepted", c_int),
                 ("guess_rejected", c_int), ("guess_started", c_int), ("pred_floor_stop", c_int),
-                ("corr_floor_stop", c_int)]
+                ("corr_floor_stop", c_int), ("energy_before", c_double), ("energy_after", c_double),
+                ("boundary_flux_dt", c_double), ("energy_defect", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -113,6 +120,8 @@ _SIGS = {
     "grte_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
     "grte_set_storage": (c_int, [c_void_p, c_int]),
     "grte_set_launch": (c_int, [c_void_p, c_int]),
+    "grte_get_error_flags": (c_int, [c_void_p, ctypes.POINTER(c_int), c_int]),
+    "grte_batch_get_error_flags": (c_int, [c_void_p, ctypes.POINTER(c_int), c_int]),
     "grte_reference_step": (c_int, [c_void_p, c_double, c_double, c_double, c_int,
                                     ctypes.POINTER(ReferenceInfo)]),
     "grte_log_pairs": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]),

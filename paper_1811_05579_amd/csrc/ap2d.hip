@@ -1086,6 +1086,7 @@ struct NewtArgs {
     double a, c, cv, dt;
     int m, maxit;
     double *Tnew, *ustar, *Dv, *rhon, *rstar;
+    double *bflux;               // edge cells: outflow through their edge faces, sum_p omega_p (...)
     int *stat;                   // [0] max its, [1] failed, [2] K* clamped, [3] negative root, [4] sum its,
                                  // [5] guesses accepted, [6] guesses not used, [7] Newton started from a guess
     const uint16_t *gw;          // learned initial guess: bfloat16 weights (null: Newton from T^n)
@@ -1119,7 +1120,16 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
         const double D = group_sum(w * divergence(S, O, p), P);
         const double rhs_s = group_sum(w * X.v[1][1], P);
         const double rn = group_sum(w * A.En[t], P);
+        // outflow through the domain's edge faces of this cell (the face values
+        // are those whose divergence is D; interior faces cancel in the sum of D)
+        double fo = 0.0;
+        if (ix == S.nx - 1) fo += S.mu[p] * O.r * S.dy;
+        if (ix == 0) fo -= S.mu[p] * O.l * S.dy;
+        if (iy == S.ny - 1) fo += S.eta[p] * O.t * S.dx;
+        if (iy == 0) fo -= S.eta[p] * O.b * S.dx;
+        const double fout = group_sum(w * fo, P);
         if (p != 0) continue;
+        if (ix == 0 || iy == 0 || ix == S.nx - 1 || iy == S.ny - 1) A.bflux[j] = fout;
         const double ac = A.a * A.c;
         const double Tn = A.Tn[j];
         const double Un = Tn * Tn * Tn * Tn;
@@ -1230,6 +1240,7 @@ struct ProjArgs {
     Sys S;                    // the correction's system
     const double *EJ;
     double *E1, *Ox1, *Oy1;
+    double *rho1;             // rho^{n+1} per cell (energy balance)
 };
 
 __global__ void __launch_bounds__(B2) project2d_kernel(ProjArgs A)
@@ -1244,12 +1255,94 @@ __global__ void __launch_bounds__(B2) project2d_kernel(ProjArgs A)
         const Nb X = load_nb(A.EJ, S.nx, S.ny, iy, ix, P, p);
         Grad O;
         faces<true, true>(S, iy, ix, p, &X, O);
-        A.E1[t] = S.acU[j] + S.eps * X.v[1][1];
+        const double e1 = S.acU[j] + S.eps * X.v[1][1];
+        A.E1[t] = e1;
+        const double r1 = group_sum(S.om[p] * e1, P);
+        if (p == 0) A.rho1[j] = r1;
         const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
         A.Ox1[fl * P + p] = O.l;
         if (ix == S.nx - 1) A.Ox1[(fl + 1) * P + p] = O.r;
         A.Oy1[fb * P + p] = O.b;
         if (iy == S.ny - 1) A.Oy1[(fb + S.nx) * P + p] = O.t;
+    }
+}
+
+// energy balance of the step ((3.12)-(3.13)): E_tot = sum dx dy (rho / c + Cv T)
+// before and after, and the outflow through the domain's edges of the
+// prediction's face values times dt.  Binary64 sums in a fixed order: each
+// thread takes cells j = t, t + G, ... (G threads in the grid) in order, a tree
+// over the block, per-block partials, and the last block to finish sums those
+// by index.
+struct EnergyArgs {
+    int n, nb;
+    double dxdy, c, cv, dt;
+    int nx, ny;
+    const double *rhon, *Tn, *rho1, *Tnew, *bflux;
+    double *epart;            // 3 per block
+    unsigned *ecnt;           // blocks done (reset to 0 by the last one)
+    double *energy;           // E_before, E_after, outflow dt, defect
+};
+
+__global__ void __launch_bounds__(B2) energy2d_kernel(EnergyArgs A)
+{
+    __shared__ double s0[B2], s1[B2], s2[B2];
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    double e0 = 0.0, e1 = 0.0, fo = 0.0;
+    for (int j = blockIdx.x * B2 + t; j < A.n; j += A.nb * B2) {
+        e0 += A.dxdy * (A.rhon[j] / A.c + A.cv * A.Tn[j]);
+        e1 += A.dxdy * (A.rho1[j] / A.c + A.cv * A.Tnew[j]);
+        const int iy = j / A.nx, ix = j - iy * A.nx;
+        if (ix == 0 || iy == 0 || ix == A.nx - 1 || iy == A.ny - 1) fo += A.bflux[j];
+    }
+    s0[t] = e0;
+    s1[t] = e1;
+    s2[t] = fo;
+    __syncthreads();
+    for (int o = B2 / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            s0[t] += s0[t + o];
+            s1[t] += s1[t + o];
+            s2[t] += s2[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        A.epart[3 * blockIdx.x] = s0[0];
+        A.epart[3 * blockIdx.x + 1] = s1[0];
+        A.epart[3 * blockIdx.x + 2] = s2[0];
+        __threadfence();                         // partials visible device-wide before the count
+        s_last = atomicAdd(A.ecnt, 1u) == (unsigned)(A.nb - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();                             // every block's partials are in memory
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int b = t; b < A.nb; b += B2) {
+        a0 += __hip_atomic_load(&A.epart[3 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a1 += __hip_atomic_load(&A.epart[3 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a2 += __hip_atomic_load(&A.epart[3 * b + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    s0[t] = a0;
+    s1[t] = a1;
+    s2[t] = a2;
+    __syncthreads();
+    for (int o = B2 / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            s0[t] += s0[t + o];
+            s1[t] += s1[t + o];
+            s2[t] += s2[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double eb = s0[0], ea = s1[0], fdt = A.dt * s2[0];
+        A.energy[0] = eb;
+        A.energy[1] = ea;
+        A.energy[2] = fdt;
+        A.energy[3] = (ea - eb) + fdt;
+        *A.ecnt = 0u;
     }
 }
 
@@ -1307,6 +1400,10 @@ struct grte2d_ctx {
     double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
     double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
     double *pgc = nullptr;               // per-cell scalar of the block inverse
+    // energy balance: edge outflow per edge cell, rho^{n+1}, block partials,
+    // the blocks-done counter and the four results
+    double *bflux = nullptr, *rho1 = nullptr, *epart = nullptr, *energy = nullptr;
+    unsigned *ecnt = nullptr;
     double *idg = nullptr;               // per-(cell, pair) inverse diagonal of the block inverse
     double *mr = nullptr, *mv = nullptr;  // angular moments of r and v (isotropic correction)
     double *idir2 = nullptr;             // second Chebyshev direction buffer of the tiled launches
@@ -1329,6 +1426,14 @@ bool dalloc(grte2d_ctx *c, T *&p, size_t n)
     c->allocs.push_back(q);
     p = (T *)q;
     return true;
+}
+
+constexpr int ENERGY_BLOCKS = 1024;    // most blocks of the energy reduction
+
+int energy_blocks(size_t n)
+{
+    const size_t b = (n + B2 - 1) / B2;
+    return (int)std::max<size_t>(1, std::min<size_t>(b, ENERGY_BLOCKS));
 }
 
 int nblocks(size_t n)
@@ -1761,7 +1866,8 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
               dalloc(c, c->Dv, c->N) && dalloc(c, c->rhon, c->N) && dalloc(c, c->bv, c->nE) &&
               dalloc(c, c->sab, c->N) && dalloc(c, c->ue, c->N) &&
               dalloc(c, c->yP, c->N) && dalloc(c, c->yS, c->N) && dalloc(c, c->dP, c->N) &&
-              dalloc(c, c->rstar, c->N) &&
+              dalloc(c, c->rstar, c->N) && dalloc(c, c->bflux, c->N) && dalloc(c, c->rho1, c->N) &&
+              dalloc(c, c->epart, 3 * ENERGY_BLOCKS) && dalloc(c, c->energy, 4) && dalloc(c, c->ecnt, 1) &&
               [&] {
                   for (auto &L : c->mg) {
                       const size_t m = (size_t)L.R.nx * L.R.ny;
@@ -1791,7 +1897,10 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                hipMemset(c->E, 0, c->nE * sizeof(double)) == hipSuccess &&
                hipMemset(c->Ox, 0, c->nOx * sizeof(double)) == hipSuccess &&
                hipMemset(c->Oy, 0, c->nOy * sizeof(double)) == hipSuccess &&
-               hipMemset(c->T, 0, c->N * sizeof(double)) == hipSuccess;
+               hipMemset(c->T, 0, c->N * sizeof(double)) == hipSuccess &&
+               hipMemset(c->bflux, 0, c->N * sizeof(double)) == hipSuccess &&
+               hipMemset(c->energy, 0, 4 * sizeof(double)) == hipSuccess &&
+               hipMemset(c->ecnt, 0, sizeof(unsigned)) == hipSuccess;
     if (hok) {
         std::vector<double> one(c->N, 1.0);
         hok = hipMemcpy(c->sigma0, one.data(), c->N * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
@@ -2084,6 +2193,7 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     na.rhon = c->rhon;
     na.stat = c->stat;
     na.rstar = c->rstar;
+    na.bflux = c->bflux;
     na.gw = c->guess_w;
     na.gnorm = c->guess_norm;
     na.gtol = c->guess_tol;
@@ -2122,7 +2232,28 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     pa.E1 = c->E1;
     pa.Ox1 = c->Ox1;
     pa.Oy1 = c->Oy1;
+    pa.rho1 = c->rho1;
     hipLaunchKernelGGL(project2d_kernel, dim3(nb), dim3(B2), 0, st, pa);
+    {
+        EnergyArgs ea;
+        ea.n = (int)c->N;
+        ea.nb = energy_blocks(c->N);
+        ea.dxdy = (c->lx / c->nx) * (c->ly / c->ny);
+        ea.c = c->c;
+        ea.cv = c->cv;
+        ea.dt = dt;
+        ea.nx = c->nx;
+        ea.ny = c->ny;
+        ea.rhon = c->rhon;
+        ea.Tn = c->T;
+        ea.rho1 = c->rho1;
+        ea.Tnew = c->T1;
+        ea.bflux = c->bflux;
+        ea.epart = c->epart;
+        ea.ecnt = c->ecnt;
+        ea.energy = c->energy;
+        hipLaunchKernelGGL(energy2d_kernel, dim3(ea.nb), dim3(B2), 0, st, ea);
+    }
     if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
     std::swap(c->E, c->E1);
     std::swap(c->Ox, c->Ox1);
@@ -2133,8 +2264,14 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
         if (s2 != GRTE_OK) return s2;
     }
     int stat[8];
+    double en[4];
     if (hipMemcpyAsync(stat, c->stat, 8 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) return GRTE_E_HIP;
+    if (hipMemcpyAsync(en, c->energy, sizeof(en), hipMemcpyDeviceToHost, st) != hipSuccess) return GRTE_E_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
+    inf.energy_before = en[0];
+    inf.energy_after = en[1];
+    inf.boundary_flux_dt = en[2];
+    inf.energy_defect = en[3];
     inf.newton_max_iters = stat[0];
     inf.newton_failed = stat[1];
     inf.kstar_clamped = stat[2];

@@ -41,7 +41,9 @@ constexpr int WAVE_MAX_N = 256;       // largest slab a wavefront tile can take 
 // per-instance cell scratch: NCA arrays of N+1 entries
 enum {
     C_AW, C_BC, C_LL, C_LU, C_LAM, C_LMG, C_G, C_BD, C_DD, C_BETA, C_RHON, C_H, C_AWR, C_AWL,
-    C_SRC, C_KEPS, C_USTAR, C_D, C_TNEW, NCA
+    C_SRC, C_KEPS, C_USTAR, C_D, C_TNEW,
+    C_FLUX,     // [0], [1]: sum_p omega_p mu_p O*_{0,p} and O*_{N,p} (energy balance)
+    NCA
 };
 
 // LDS of one tile (doubles): rho, Ll, Lu in position order + the solver's scratch
@@ -78,6 +80,8 @@ struct BatchArgs {
     int accel;                  // prediction acceleration (GRTE_ACCEL_*)
     double *rprev;              // per cell: the last prediction's rho* (written every step)
     int warm;                   // start the prediction from rprev instead of rho^n
+    double *ienergy;            // per instance: E_tot^n, E_tot^{n+1}, outflow dt, defect
+    int *sticky;                // error flags OR-ed over steps (GRTE_ERRF_*), not cleared by a step
 };
 
 // make the tile's LDS and global writes visible to the whole tile
@@ -390,7 +394,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     // ---------------- correction substep 1: moments, D, K*, Newton on (4.13)/(5.5)
     int n_its = 0, n_fail = 0, n_clamp = 0, n_neg = 0;
     for (int j = k; j < N; j += W) {
-        double rs = 0.0, D = 0.0;
+        double rs = 0.0, D = 0.0, f0 = 0.0, fN = 0.0;
         for (int p = 0; p < P; ++p) {
             const double *ep = Et + (size_t)p * NP;
             const double m1 = mu[p];
@@ -406,7 +410,11 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
             }
             rs += om[p] * ej;
             D += om[p] * m1 * (orr - ol);
+            f0 += om[p] * m1 * ol;
+            fN += om[p] * m1 * orr;
         }
+        if (j == 0) C[C_FLUX * N1] = f0;
+        if (j == N - 1) C[C_FLUX * N1 + 1] = fN;
         D /= I.dx;
         const double ac = I.a * I.c;
         const double t = Tn[j];
@@ -467,6 +475,9 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         if (n_fail) atomicAdd(&st[3], n_fail);
         if (n_clamp) atomicAdd(&st[4], n_clamp);
         if (n_neg) atomicAdd(&st[5], n_neg);
+        const int ef = (n_fail ? GRTE_ERRF_NEWTON : 0) | (n_neg ? GRTE_ERRF_NEGATIVE_ROOT : 0) |
+                       ((k == 0 && !converged) ? GRTE_ERRF_PRED_NOCONV : 0);
+        if (ef) atomicOr(A.sticky, ef);
     }
     tsync<W>();
 
@@ -510,33 +521,54 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     tsync<W>();
 
     // ---------------- projection (4.14): E^{n+1} and O^{n+1} (node relation with K^{n+1})
-    // into the cell-major state; a thread takes cells, its lanes read along cells
+    // into the cell-major state; a thread takes cells, its lanes read along cells.
+    // With it, the energy balance ((3.12)-(3.13)): E_tot = sum_j dx (rho_j / c +
+    // Cv T_j) before and after, in a fixed order (each thread's cells in order,
+    // then the tile sum).
     const double *Aw = C + C_AW * N1, *Bc = C + C_BC * N1;
+    double eb = 0.0, ea = 0.0;
     if constexpr (F32) {
         float *E32o = A.E32o + I.oE, *O32o = A.O32o + I.oO;
         for (int j = k; j < N; j += W) {
             const double t1 = T2[j];
             const double base = S.ac * (t1 * t1) * (t1 * t1);
+            double r1 = 0.0;
             for (int p = 0; p < P; ++p) {
                 const double *ep = Et + (size_t)p * NP;
+                r1 += om[p] * ep[j];
                 E32o[(size_t)j * P + p] = (float)(ep[j] - base);
                 O32o[(size_t)j * P + p] = (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
                 if (j == N - 1)
                     O32o[(size_t)N * P + p] =
                         (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
             }
+            eb += I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
+            ea += I.dx * (r1 / I.c + I.cv * t1);
         }
     } else {
         double *E2 = A.E2 + I.oE, *O2 = A.O2 + I.oO;
         for (int j = k; j < N; j += W) {
+            double r1 = 0.0;
             for (int p = 0; p < P; ++p) {
                 const double *ep = Et + (size_t)p * NP;
+                r1 += om[p] * ep[j];
                 E2[(size_t)j * P + p] = ep[j];
                 O2[(size_t)j * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
                 if (j == N - 1)
                     O2[(size_t)N * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
             }
+            eb += I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
+            ea += I.dx * (r1 / I.c + I.cv * T2[j]);
         }
+    }
+    tile_sum2<W>(eb, ea, sh);
+    if (k == 0) {
+        const double fdt = I.dt * (C[C_FLUX * N1 + 1] - C[C_FLUX * N1]);
+        double *en = A.ienergy + 4 * (size_t)i;
+        en[0] = eb;
+        en[1] = ea;
+        en[2] = fdt;
+        en[3] = (ea - eb) + fdt;
     }
     tsync<W>();
 }
@@ -601,6 +633,12 @@ __global__ void batch_reset(int *queue, int *istat, int n8)
     if (t < n8) istat[t] = 0;
 }
 
+// one int cleared (the sticky error flags)
+__global__ void iclear1(int *x)
+{
+    if (threadIdx.x == 0) x[0] = 0;
+}
+
 __global__ void bfill(double *x, size_t n, double v)
 {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -643,6 +681,8 @@ struct grte_batch {
     double *sigma0 = nullptr, *mu = nullptr, *omega = nullptr, *bL = nullptr, *bR = nullptr;
     double *cells = nullptr, *pairs = nullptr;
     double *rprev = nullptr;                   // per cell: the last prediction's rho*
+    double *d_energy = nullptr;                // per instance: energy balance of the last step (4)
+    int *d_sticky = nullptr;                   // error flags OR-ed over steps (GRTE_ERRF_*)
     int warm = 0;                              // rprev belongs to the step that produced the state
     // graphs, one per buffer parity; rebuilt when the launch changes
     int use_graph = 0;
@@ -734,6 +774,8 @@ BatchArgs make_args(const grte_batch *b, int src)
     A.warm = b->warm;
     A.E32 = b->E32[src]; A.O32 = b->O32[src];
     A.E32o = b->E32[1 - src]; A.O32o = b->O32[1 - src];
+    A.ienergy = b->d_energy;
+    A.sticky = b->d_sticky;
     return A;
 }
 
@@ -903,6 +945,11 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
     if (st == GRTE_OK) st = balloc(b, &b->cells, oC);
     if (st == GRTE_OK) st = balloc(b, &b->pairs, oR);
     if (st == GRTE_OK) st = balloc(b, &b->rprev, oT);
+    if (st == GRTE_OK) st = balloc(b, &b->d_energy, (size_t)4 * n);
+    if (st == GRTE_OK) st = balloc(b, &b->d_sticky, 1);
+    if (st == GRTE_OK && (hipMemset(b->d_sticky, 0, sizeof(int)) != hipSuccess ||
+                          hipMemset(b->d_energy, 0, (size_t)4 * n * sizeof(double)) != hipSuccess))
+        st = GRTE_E_HIP;
     if (st != GRTE_OK) { grte_batch_destroy(b); return st; }
     if (hipFuncSetAttribute((const void *)batch_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)BATCH_LDS) != hipSuccess ||
@@ -1112,10 +1159,16 @@ grte_status grte_batch_step(grte_batch *b, grte_batch_info *info)
     }
     if (!info) return GRTE_OK;
     std::vector<int> h;
-    if ((st = read_stats(b, h)) != GRTE_OK) return st;
+    std::vector<double> en((size_t)4 * b->n);
+    BCHK(hipMemcpyAsync(en.data(), b->d_energy, en.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    if ((st = read_stats(b, h)) != GRTE_OK) return st;   // (synchronises the stream)
     int bad = 0;
     for (int i = 0; i < b->n; ++i) {
         grte_batch_info &f = info[i];
+        f.energy_before = en[4 * i];
+        f.energy_after = en[4 * i + 1];
+        f.boundary_flux_dt = en[4 * i + 2];
+        f.energy_defect = en[4 * i + 3];
         f.pred_iters = h[8 * i + 0];
         f.pred_converged = h[8 * i + 1] ? 1 : 0;
         f.pred_floor_stop = h[8 * i + 1] == 2 ? 1 : 0;
@@ -1126,6 +1179,19 @@ grte_status grte_batch_step(grte_batch *b, grte_batch_info *info)
         if (!f.pred_converged || f.newton_failed) bad = 1;
     }
     return bad ? GRTE_E_NOCONV : GRTE_OK;
+}
+
+grte_status grte_batch_get_error_flags(grte_batch *b, int *flags, int clear)
+{
+    if (!b || !flags) return GRTE_E_INVAL;
+    BCHK(hipMemcpyAsync(flags, b->d_sticky, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    if (clear) {
+        hipLaunchKernelGGL(iclear1, dim3(1), dim3(64), 0, b->stream, b->d_sticky);
+        BCHK(hipGetLastError());
+        BCHK(hipStreamSynchronize(b->stream));
+    }
+    return GRTE_OK;
 }
 
 grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best)

@@ -81,6 +81,7 @@ namespace {
 // every context, each context synchronising only its own work-groups).
 constexpr int GMAX = 4;
 constexpr int NSTAT = 16;    // per-step counters of a context
+constexpr int STAT_STICKY = NSTAT - 1;   // error flags OR-ed over steps (GRTE_ERRF_*), cleared on request
 
 template <class Args>
 struct Group {
@@ -133,7 +134,7 @@ __device__ __forceinline__ void coef_body(const CoefArgs &A)
     const int N = A.N, P = A.P, cpb = A.cpb;
     const int c0 = blockIdx.x * cpb;
     const int t = threadIdx.x;
-    if (A.mode == 0 && blockIdx.x == 0 && t < NSTAT) A.stat[t] = 0;
+    if (A.mode == 0 && blockIdx.x == 0 && t < STAT_STICKY) A.stat[t] = 0;   // the sticky word survives
     // ---- per cell
     if (t < cpb && c0 + t < N) {
         const int j = c0 + t;
@@ -461,6 +462,7 @@ struct NewtonArgs {
     const double *O, *Aw, *Bc, *beta, *rho_n, *Tn, *sigma0, *mu, *omega, *bL, *bR;
     double *Ecm;             // E* in cell-major order, as the prediction writes it
     double *Tnew, *ustar, *Dv, *ostar, *rstar;
+    double *obnd;            // O* at the two end nodes, [p] (node 0) and [P + p] (node N)
     const float *O32;        // binary32 storage of O^n (f32 != 0)
     int f32;
     const uint16_t *gw;      // learned initial guess: bfloat16 weights (null: Newton from T^n)
@@ -496,6 +498,8 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t 
             A.ostar[(size_t)jj * P + p] = ol;
             if (jj == N - 1) A.ostar[(size_t)N * P + p] = orr;
         }
+        if (jj == 0) A.obnd[p] = ol;
+        if (jj == N - 1) A.obnd[P + p] = orr;
     }
     __syncthreads();
     if (t >= cpb || c0 + t >= N) return;
@@ -664,7 +668,14 @@ __global__ void __launch_bounds__(NT) corr_kernel(Group<CorrArgs> G)
 }
 
 // -------------------------------------------------------------------------
-// projection (4.14): O^{n+1} at the nodes (E^{n+1} is already in place), rho^{n+1}
+// projection (4.14): O^{n+1} at the nodes (E^{n+1} is already in place),
+// rho^{n+1}, and the energy balance of the step ((3.12)-(3.13)):
+//   E_tot = sum_j dx (rho_j / c + Cv T_j) before and after the step, the
+//   outflow dt sum_p omega_p mu_p (O*_{N,p} - O*_{0,p}) of the prediction's
+//   fluxes (the correction's moment equation uses D from O*), and the defect
+//   E_tot^{n+1} - E_tot^n + outflow.
+// Binary64 sums in a fixed order: a tree over each block's cells, per-block
+// partials, and the last block to finish sums the partials by index.
 // -------------------------------------------------------------------------
 struct ProjArgs {
     int N, P, keep, cpb;
@@ -674,16 +685,28 @@ struct ProjArgs {
     const float *O32;       // binary32 storage (f32 != 0): O^n in, O^{n+1} out
     float *O32out;
     int f32;
+    // energy balance
+    double dx, c, cv, dt;
+    const double *Tn, *Tnew, *rho_n, *obnd;
+    double *epart;          // 2 per block
+    unsigned *ecnt;         // blocks done (reset to 0 by the last one)
+    double *energy;         // E_before, E_after, outflow dt, defect
+    int *stat;              // per-step counters; the sticky word collects their error flags
 };
 
 __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
 {
     const ProjArgs A = G.a[blockIdx.y];
     __shared__ double s_w[256];
+    __shared__ double s_e0[256], s_e1[256];
+    __shared__ int s_last;
     const int N = A.N, P = A.P, cpb = A.cpb;
+    const int nb = (N + cpb - 1) / cpb;
+    if ((int)blockIdx.x >= nb) return;          // whole block: contexts of the group differ in size
     const int c0 = blockIdx.x * cpb, t = threadIdx.x;
     const int cl = t / P, p = t - (t / P) * P;
     const int j = c0 + cl;
+    double wE = 0.0;
     if (cl < cpb && j < N) {
         const double mu = A.mu[p];
         if (A.f32) {
@@ -698,14 +721,70 @@ __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
                 A.Oout[(size_t)N * P + p] =
                     node_any(A.Enew, A.O, A.Aw, A.Bc, mu, A.bL[p], A.bR[p], A.eps, N, P, N, p);
         }
-        if (A.keep) s_w[t] = A.omega[p] * A.Enew[(size_t)j * P + p];
+        wE = A.omega[p] * A.Enew[(size_t)j * P + p];
     }
-    if (!A.keep) return;
+    s_w[t] = wE;
     __syncthreads();
+    double e0 = 0.0, e1 = 0.0;
     if (t < cpb && c0 + t < N) {
+        const int jc = c0 + t;
         double s = 0.0;
         for (int q = 0; q < P; ++q) s += s_w[t * P + q];
-        A.rho_out[c0 + t] = s;
+        if (A.keep) A.rho_out[jc] = s;
+        e0 = A.dx * (A.rho_n[jc] / A.c + A.cv * A.Tn[jc]);
+        e1 = A.dx * (s / A.c + A.cv * A.Tnew[jc]);
+    }
+    s_e0[t] = e0;
+    s_e1[t] = e1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            s_e0[t] += s_e0[t + o];
+            s_e1[t] += s_e1[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        A.epart[2 * blockIdx.x] = s_e0[0];
+        A.epart[2 * blockIdx.x + 1] = s_e1[0];
+        __threadfence();                         // partial visible device-wide before the count
+        s_last = atomicAdd(A.ecnt, 1u) == (unsigned)(nb - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();                             // every block's partial is in memory
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = t; b < nb; b += 256) {
+        a0 += __hip_atomic_load(&A.epart[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a1 += __hip_atomic_load(&A.epart[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();                             // s_e0/s_e1 reused
+    s_e0[t] = a0;
+    s_e1[t] = a1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            s_e0[t] += s_e0[t + o];
+            s_e1[t] += s_e1[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double fl = 0.0;
+        for (int q = 0; q < P; ++q) fl += A.omega[q] * A.mu[q] * (A.obnd[P + q] - A.obnd[q]);
+        const double eb = s_e0[0], ea = s_e1[0], fdt = A.dt * fl;
+        A.energy[0] = eb;
+        A.energy[1] = ea;
+        A.energy[2] = fdt;
+        A.energy[3] = (ea - eb) + fdt;
+        *A.ecnt = 0u;
+        // error flags of this step, kept until read (the counters are cleared next step)
+        int f = 0;
+        if (A.stat[6]) f |= GRTE_ERRF_SYNC;
+        if (!A.stat[1]) f |= GRTE_ERRF_PRED_NOCONV;
+        if (A.stat[3]) f |= GRTE_ERRF_NEWTON;
+        if (A.stat[5]) f |= GRTE_ERRF_NEGATIVE_ROOT;
+        if (f) A.stat[STAT_STICKY] |= f;
     }
 }
 
@@ -792,6 +871,12 @@ __global__ void convert_state_kernel(int N, int P, double ac, const double *T, d
     }
 }
 
+__global__ void fill_int_kernel(int *x, int n, int v)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) x[t] = v;
+}
+
 __global__ void fill_kernel(double *x, size_t n, double v)
 {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -843,6 +928,10 @@ struct grte_ctx {
     int cpb = 1;                           // cells per work-group of the per-cell kernels
     size_t pred_lds = 0;
     int *stat = nullptr;
+    // energy balance of the last step (projection kernel): O* at the end nodes,
+    // per-block partial sums, the blocks-done counter, and the four results
+    double *obnd = nullptr, *epart = nullptr, *energy = nullptr;
+    unsigned *ecnt = nullptr;
     // optional stage timing: event pairs recorded on the context stream
     int profiling = 0;            // 0 off, k: time every k-th step
     long long prof_count = 0;     // steps since profiling was set
@@ -1119,6 +1208,12 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     if (st == GRTE_OK) st = alloc(ctx, &flagmem, (size_t)MAX_P * BAR_STRIDE);
     ctx->flags = (unsigned long long *)flagmem;
     if (st == GRTE_OK && hipMalloc((void **)&ctx->stat, NSTAT * sizeof(int)) != hipSuccess) st = GRTE_E_NOMEM;
+    if (st == GRTE_OK) st = alloc(ctx, &ctx->obnd, 2 * P);
+    if (st == GRTE_OK) st = alloc(ctx, &ctx->epart, 2 * N);   // 2 per cell block (at most N blocks)
+    if (st == GRTE_OK) st = alloc(ctx, &ctx->energy, 4);
+    double *cntmem = nullptr;
+    if (st == GRTE_OK) st = alloc(ctx, &cntmem, 1);
+    ctx->ecnt = (unsigned *)cntmem;
     if (st != GRTE_OK) { grte_destroy(ctx); return st; }
 
     // co-resident blocks for the cooperative prediction kernel
@@ -1157,6 +1252,9 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     hipLaunchKernelGGL(fill_kernel, dim3((P + b - 1) / b), dim3(b), 0, nullptr, ctx->bR, P, 0.0);
     hipLaunchKernelGGL(fill_kernel, dim3((MAX_P * BAR_STRIDE + b - 1) / b), dim3(b), 0, nullptr, flagmem,
                        (size_t)MAX_P * BAR_STRIDE, 0.0);   // all-zero bits: generation 0
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(b), 0, nullptr, cntmem, 1, 0.0);        // counter 0
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(b), 0, nullptr, ctx->energy, 4, 0.0);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, nullptr, ctx->stat, NSTAT, 0);
     // padded rows of the position-ordered arrays stay zero
     const size_t npad = (size_t)NT * ctx->M;
     hipLaunchKernelGGL(fill_kernel, dim3((npad + b - 1) / b), dim3(b), 0, nullptr, ctx->Gt, npad, 0.0);
@@ -1348,6 +1446,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         na.rho_n = ctx->rho_n; na.Tn = ctx->T; na.sigma0 = ctx->sigma0; na.mu = ctx->mu; na.omega = ctx->omega;
         na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
         na.ostar = ctx->ostar; na.stat = ctx->stat; na.rstar = ctx->rstar;
+        na.obnd = ctx->obnd;
         na.gw = ctx->guess_w; na.gnorm = ctx->guess_norm; na.gtol = ctx->guess_tol;
         na.O32 = ctx->O32; na.f32 = ctx->f32;
         ctx->last_dt = dt;
@@ -1365,6 +1464,9 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         pj.mu = ctx->mu; pj.omega = ctx->omega; pj.bL = ctx->bL; pj.bR = ctx->bR;
         pj.Oout = ctx->O2; pj.rho_out = ctx->rho1;
         pj.O32 = ctx->O32; pj.O32out = ctx->O32b; pj.f32 = ctx->f32;
+        pj.dx = dx; pj.c = ctx->c; pj.cv = ctx->cv; pj.dt = dt;
+        pj.Tn = ctx->T; pj.Tnew = ctx->T2; pj.rho_n = ctx->rho_n; pj.obnd = ctx->obnd;
+        pj.epart = ctx->epart; pj.ecnt = ctx->ecnt; pj.energy = ctx->energy; pj.stat = ctx->stat;
     }
     gp.first[n] = grid;
     if (grid > c0->coop_capacity) return GRTE_E_UNSUPPORTED;
@@ -1421,7 +1523,9 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     grte_status worst = GRTE_OK;
     for (int g = 0; g < n; ++g) {
         int h[NSTAT];
+        double en[4];
         HIPCHK(hipMemcpyAsync(h, ctxs[g]->stat, sizeof(h), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(en, ctxs[g]->energy, sizeof(en), hipMemcpyDeviceToHost, stream));
         HIPCHK(hipStreamSynchronize(stream));
         grte_step_info &f = info[g];
         f.pred_iters = h[0];
@@ -1436,6 +1540,10 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         f.guess_rejected = h[8];
         f.newton_total_iters = h[9];
         f.guess_started = h[10];
+        f.energy_before = en[0];
+        f.energy_after = en[1];
+        f.boundary_flux_dt = en[2];
+        f.energy_defect = en[3];
         if (h[6]) worst = GRTE_E_HIP;
         else if ((!h[1] || h[3]) && worst == GRTE_OK) worst = GRTE_E_NOCONV;
     }
@@ -1566,6 +1674,19 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
     }
     if (sync_err) return GRTE_E_HIP;
     return (converged && !pred_fail) ? GRTE_OK : GRTE_E_NOCONV;
+}
+
+grte_status grte_get_error_flags(grte_ctx *ctx, int *flags, int clear)
+{
+    if (!ctx || !flags) return GRTE_E_INVAL;
+    HIPCHK(hipMemcpyAsync(flags, ctx->stat + STAT_STICKY, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (clear) {
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->stat + STAT_STICKY, 1, 0);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return GRTE_OK;
 }
 
 grte_status grte_set_launch(grte_ctx *ctx, int cooperative)

@@ -439,6 +439,36 @@ __device__ __forceinline__ void tile_max2(double &a, double &b, double *sh)
     }
 }
 
+// sum over the tile of two values at once (fixed order: a butterfly within
+// each wavefront, then the wavefronts' sums in wave order; result in every
+// tile thread)
+template <int W>
+__device__ __forceinline__ void tile_sum2(double &a, double &b, double *sh)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if constexpr (W == 256) {
+        double *m2 = sh + 14 * W;
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            m2[w] = a;
+            m2[8 + w] = b;
+        }
+        __syncthreads();
+        a = m2[0];
+        b = m2[8];
+#pragma unroll
+        for (int q = 1; q < W / 64; ++q) {
+            a += m2[q];
+            b += m2[8 + q];
+        }
+        __syncthreads();
+    }
+}
+
 // block-wide max of a non-negative value (fixed order; result in every thread)
 __device__ __forceinline__ double block_max(double v, double *sh)
 {
