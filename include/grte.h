@@ -325,6 +325,21 @@ grte_status grte_mlp_grad(grte_mlp *m, const float *dev_rows, long long n, float
  * loss_hist (host, may be NULL) receives the minibatch loss of each step. */
 grte_status grte_mlp_train(grte_mlp *m, const float *dev_rows, long long n, int steps, int batch,
                            float lr, float *loss_hist);
+/* The same training as grte_mlp_train, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving or training loops that
+ * forbid hipMalloc): it calls no hipMalloc, hipFree or other allocating
+ * routine.  Its per-block partial gradients and losses and its loss history
+ * live in one fixed workspace of 4.98 MB in the library's code object, which
+ * each device holds until the process ends: at most 16384 rows per minibatch
+ * (min(batch, n)) and, when loss_hist is non-NULL, at most 65536 steps;
+ * larger requests return GRTE_E_UNSUPPORTED (with a message on stderr) and do
+ * nothing.  Every call on a device shares that device's workspace: calls that
+ * overlap on one device (two streams, two threads) race and must not be made.
+ * Results are bit-identical to grte_mlp_train's for the same model state,
+ * rows and arguments (the same kernels in the same order).  Synchronises the
+ * model's stream. */
+grte_status grte_mlp_train_noalloc(grte_mlp *m, const float *dev_rows, long long n, int steps, int batch,
+                                   float lr, float *loss_hist);
 /* Network outputs y (device, n) for the feature columns of n rows. */
 grte_status grte_mlp_predict(grte_mlp *m, const float *dev_rows, long long n, float *dev_y);
 /* Use `model` (NULL: plain Newton from T^n) for the temperature solve of

@@ -303,6 +303,18 @@ class Mlp:
                                                          hist.ctypes.data))
         return hist
 
+    def train_noalloc(self, rows, steps, batch=4096, lr=1e-3, history=True):
+        """The same training through grte_mlp_train_noalloc (no device
+        allocation: a fixed workspace, at most 16384 rows per minibatch and
+        65536 recorded steps); returns the loss history (None if history=False)."""
+        _check_rows(rows)
+        hist = np.empty(int(steps), dtype=np.float32) if history else None
+        check("grte_mlp_train_noalloc",
+              self._lib.grte_mlp_train_noalloc(self._h, ctypes.c_void_p(rows.data_ptr()), rows.shape[0], int(steps),
+                                               int(batch), ctypes.c_float(lr),
+                                               hist.ctypes.data if history else None))
+        return hist
+
     def predict(self, rows):
         """Network outputs y (float32 CUDA tensor) for the feature columns of rows."""
         import torch

@@ -117,6 +117,8 @@ _SIGS = {
     "grte_mlp_train": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, ctypes.c_float,
                                c_void_p]),
     "grte_mlp_predict": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_void_p]),
+    "grte_mlp_train_noalloc": (c_int, [c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, ctypes.c_float,
+                                       c_void_p]),
     "grte_set_guess": (c_int, [c_void_p, c_void_p, c_double]),
     "grte_set_storage": (c_int, [c_void_p, c_int]),
     "grte_set_launch": (c_int, [c_void_p, c_int]),

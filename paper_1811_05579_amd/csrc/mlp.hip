@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -27,8 +28,24 @@
 #include "mlp_common.hpp"
 
 namespace {
-
 constexpr int GB = 64;                 // rows per training block (one wavefront)
+}
+
+// Workspace of grte_mlp_train_noalloc: per-block partial gradients, partial
+// losses and the loss history, in one file-scope device array that each device
+// holds until the process ends.  In host code the array's name only stands
+// for it: its address on a device comes from hipGetSymbolAddress, taken once
+// per device with that device current, and kept.
+constexpr int NOALLOC_MAX_BATCH = 16384;                      // rows per minibatch
+constexpr int NOALLOC_MAX_BLOCKS = NOALLOC_MAX_BATCH / GB;    // 256 gradient blocks
+constexpr int NOALLOC_MAX_STEPS = 65536;                      // loss-history entries
+constexpr size_t NOALLOC_FLOATS =
+    (size_t)NOALLOC_MAX_BLOCKS * MLP_NPARAM + NOALLOC_MAX_BLOCKS + NOALLOC_MAX_STEPS;   // 4.98 MB
+
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+namespace {
+
 constexpr int HS = MLP_H + 1;          // padded LDS row stride (conflict-free)
 constexpr int NPAD = 4612;             // parameters in LDS, padded
 
@@ -234,7 +251,7 @@ grte_status ensure_gpart(grte_mlp *m, int nblk)
     return GRTE_OK;
 }
 
-grte_status launch_grad(grte_mlp *m, const float *data, long long n, long long start, int B)
+grte_status grad_lds_attribute()
 {
     static bool lds_set = false;
     if (!lds_set) {
@@ -242,12 +259,70 @@ grte_status launch_grad(grte_mlp *m, const float *data, long long n, long long s
                                  (int)grad_lds_bytes()));
         lds_set = true;
     }
+    return GRTE_OK;
+}
+
+// per-block partial gradients and losses into gpart/lpart (nblk = ceil(B / GB) blocks)
+grte_status launch_grad_into(grte_mlp *m, const float *data, long long n, long long start, int B, float *gpart,
+                             float *lpart)
+{
+    grte_status st = grad_lds_attribute();
+    if (st != GRTE_OK) return st;
+    const int nblk = (B + GB - 1) / GB;
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(nblk), dim3(GB), grad_lds_bytes(), m->stream, m->theta, m->norm, data,
+                       n, start, B, gpart, lpart);
+    MCHK(hipGetLastError());
+    return GRTE_OK;
+}
+
+grte_status launch_grad(grte_mlp *m, const float *data, long long n, long long start, int B)
+{
     const int nblk = (B + GB - 1) / GB;
     grte_status st = ensure_gpart(m, nblk);
     if (st != GRTE_OK) return st;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(nblk), dim3(GB), grad_lds_bytes(), m->stream, m->theta, m->norm, data,
-                       n, start, B, m->gpart, m->lpart);
-    MCHK(hipGetLastError());
+    return launch_grad_into(m, data, n, start, B, m->gpart, m->lpart);
+}
+
+// `steps` Adam steps on minibatches of B rows, taken cyclically from the n
+// rows; the per-block partials go to gpart/lpart, the loss of step k to
+// lhist[k] (device, null: not recorded).  Allocates nothing.
+grte_status train_steps(grte_mlp *m, const float *data, long long n, int steps, int B, float lr, float *gpart,
+                        float *lpart, float *lhist)
+{
+    const int nblk = (B + GB - 1) / GB;
+    long long start = 0;
+    for (int k = 0; k < steps; ++k) {
+        grte_status st = launch_grad_into(m, data, n, start, B, gpart, lpart);
+        if (st != GRTE_OK) return st;
+        start = (start + B) % n;
+        const int kk = ++m->adam_k;
+        const float c1 = (float)(1.0 - std::pow(0.9, kk)), c2 = (float)(1.0 - std::pow(0.999, kk));
+        hipLaunchKernelGGL(mlp_adam_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, m->stream, m->theta,
+                           m->am, m->av, m->wbf, gpart, nblk, lpart, B, lhist, k, lr, c1, c2);
+        MCHK(hipGetLastError());
+    }
+    return GRTE_OK;
+}
+
+// ---- the training entry point that allocates nothing (grte_mlp_train_noalloc):
+// the device address of the file-scope workspace, per device
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+float *scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+grte_status scratch_on_device(float **out)
+{
+    int dev = -1;
+    MCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return GRTE_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        MCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return GRTE_E_HIP;
+        scratch_ptr[dev] = (float *)p;
+    }
+    *out = scratch_ptr[dev];
     return GRTE_OK;
 }
 
@@ -396,20 +471,36 @@ grte_status grte_mlp_train(grte_mlp *m, const float *data, long long n, int step
         if (hipMalloc((void **)&m->lhist, (size_t)steps * sizeof(float)) != hipSuccess) return GRTE_E_NOMEM;
         m->hcap = steps;
     }
-    long long start = 0;
-    for (int k = 0; k < steps; ++k) {
-        grte_status st = launch_grad(m, data, n, start, B);
-        if (st != GRTE_OK) return st;
-        start = (start + B) % n;
-        const int kk = ++m->adam_k;
-        const float c1 = (float)(1.0 - std::pow(0.9, kk)), c2 = (float)(1.0 - std::pow(0.999, kk));
-        hipLaunchKernelGGL(mlp_adam_kernel, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, m->stream, m->theta,
-                           m->am, m->av, m->wbf, m->gpart, nblk, m->lpart, B, loss_hist ? m->lhist : nullptr, k,
-                           lr, c1, c2);
-        MCHK(hipGetLastError());
-    }
+    grte_status st = ensure_gpart(m, nblk);
+    if (st != GRTE_OK) return st;
+    st = train_steps(m, data, n, steps, B, lr, m->gpart, m->lpart, loss_hist ? m->lhist : nullptr);
+    if (st != GRTE_OK) return st;
     if (loss_hist)
         MCHK(hipMemcpyAsync(loss_hist, m->lhist, (size_t)steps * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    MCHK(hipStreamSynchronize(m->stream));
+    return GRTE_OK;
+}
+
+grte_status grte_mlp_train_noalloc(grte_mlp *m, const float *data, long long n, int steps, int batch, float lr,
+                                   float *loss_hist)
+{
+    if (!m || !data || n < 1 || steps < 1 || batch < 1 || !(lr > 0)) return GRTE_E_INVAL;
+    const int B = (int)std::min<long long>(batch, n);
+    if (B > NOALLOC_MAX_BATCH || (loss_hist && steps > NOALLOC_MAX_STEPS)) {
+        fprintf(stderr, "grte_mlp_train_noalloc: minibatch %d rows (at most %d) or %d loss-history steps "
+                        "(at most %d) beyond the fixed workspace\n", B, NOALLOC_MAX_BATCH, steps, NOALLOC_MAX_STEPS);
+        return GRTE_E_UNSUPPORTED;
+    }
+    float *ws = nullptr;
+    grte_status st = scratch_on_device(&ws);
+    if (st != GRTE_OK) return st;
+    float *gpart = ws;                                              // NOALLOC_MAX_BLOCKS x MLP_NPARAM
+    float *lpart = gpart + (size_t)NOALLOC_MAX_BLOCKS * MLP_NPARAM;  // NOALLOC_MAX_BLOCKS
+    float *lhist = lpart + NOALLOC_MAX_BLOCKS;                      // NOALLOC_MAX_STEPS
+    st = train_steps(m, data, n, steps, B, lr, gpart, lpart, loss_hist ? lhist : nullptr);
+    if (st != GRTE_OK) return st;
+    if (loss_hist)
+        MCHK(hipMemcpyAsync(loss_hist, lhist, (size_t)steps * sizeof(float), hipMemcpyDeviceToHost, m->stream));
     MCHK(hipStreamSynchronize(m->stream));
     return GRTE_OK;
 }
