@@ -208,6 +208,24 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
  * context's.  GRTE_E_INVAL for a null ctx or a value other than 0 or 1. */
 grte_status grte_set_launch(grte_ctx *ctx, int cooperative);
 
+/* Correction stage of the step.
+ * GRTE_CORRECTION_CONSERVATIVE (default): Algorithm 2's correction, (4.13)
+ *   by a scalar Newton per cell, then (4.11)+(4.12), projection (4.14).
+ * GRTE_CORRECTION_ALT: the alternative of the remark closing Section 3,
+ *   (3.14): the time derivative of the intensity taken from the prediction's
+ *   update and the emission at U*, which needs no nonlinear solve -- per
+ *   direction (4.11a,b) with U^{n+1} -> U* and the known time-derivative
+ *   terms (K = (T^n)^m), then T^{n+1} = T^n + dt sigma0 rho_J / (eps K Cv)
+ *   explicitly, then (4.14).  The remark reports it not energy conservative
+ *   (the step's energy_defect does not vanish with eps; boundary_flux_dt is
+ *   then formed with the correction's O_J) and failing for T-dependent
+ *   opacity; it is kept as the ablation the remark describes.  Needs
+ *   sigma0 > 0 in every cell (it divides by the node opacity) and binary64
+ *   storage (GRTE_E_UNSUPPORTED with binary32, either way round).  A grouped
+ *   step needs the same kind in every context (GRTE_E_INVAL otherwise). */
+enum { GRTE_CORRECTION_CONSERVATIVE = 0, GRTE_CORRECTION_ALT = 1 };
+grte_status grte_set_correction(grte_ctx *ctx, int kind);
+
 /* The GRTE_ERRF_* flags OR-ed over every step since the context was created
  * or the flags were last cleared (clear != 0 clears them after reading).
  * Lets a caller that enqueues many steps without `info` (no host
@@ -241,12 +259,15 @@ grte_status grte_get_stage(grte_ctx *ctx, int stage, double *out, int on_device)
 /* Solver controls: relative tolerance of the prediction update (default
  * 1e-15), its iteration cap (default 200) and the Newton cap (default 100).
  * The prediction stops when max|z| <= pred_tol max|rho| for its update z, or,
- * as a safeguard, when max|z| <= 16 pred_tol max|rho| and max|z| / max|rho|
- * has not decreased over the last two updates: the update norm has then
- * reached the rounding level of the residual evaluation (about 1e-16 relative
- * on optically thick slabs, e.g. N = 4096, 64 ordinates, eps = 1e-4), where it
- * only fluctuates.  Both count as converged (info pred_converged); the second
- * also sets pred_floor_stop. */
+ * as a safeguard, when the update norm has reached the rounding level of the
+ * residual evaluation, where it only fluctuates: max|z| <= 16 pred_tol
+ * max|rho| and max|z| / max|rho| has not decreased over the last two updates,
+ * or max|z| <= 64 pred_tol max|rho| and max|z| / max|rho| is above 0.9 of its
+ * value three updates earlier (that level is about 1e-16 relative on
+ * optically thick slabs, e.g. N = 4096, 64 ordinates, eps = 1e-4, and up to
+ * ~2.3e-14 on some binary32-stored states of the batched ensemble right after
+ * the cold start).  Both count as converged (info pred_converged); the second
+ * also sets pred_floor_stop (the batched path applies the same test). */
 grte_status grte_set_solver(grte_ctx *ctx, double pred_tol, int pred_maxit, int newton_maxit);
 
 /* Acceleration of the prediction iteration (default GRTE_ACCEL_CHEBYSHEV).
@@ -476,8 +497,11 @@ grte_status grte_batch_step(grte_batch *b, grte_batch_info *info);
 grte_status grte_batch_get_error_flags(grte_batch *b, int *flags, int clear);
 /* Autotuner: times `trials` steps for each candidate (wavefront threshold
  * 0/128/256 x grid of 1, 2, ... work-groups per compute unit) from the
- * current state without changing it, orders the instances by the measured
- * work (iterations x N x P, largest first) and keeps the fastest choice. */
+ * current state without changing it (each candidate step also starts its
+ * prediction from the same iterate as the next real step will), orders the
+ * instances by the measured work (iterations x N x P, largest first) and
+ * keeps the fastest choice.  Tune on a state like the ones to be stepped
+ * through: the cold start needs a fraction of a developed state's iterations. */
 grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best);
 grte_status grte_batch_set_tuning(grte_batch *b, const grte_batch_tuning *t);
 grte_status grte_batch_get_tuning(const grte_batch *b, grte_batch_tuning *t);
@@ -594,6 +618,16 @@ grte_status grte2d_set_stream(grte2d_ctx *ctx, void *hip_stream);
  * level) -- stiff problems (a c beta of (4.5c) above ~1e7) cannot reach
  * 1e-14. */
 grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
+
+/* Launch shape of the Krylov kernels: each thread takes `items_per_thread`
+ * (cell, pair) items (1..64, default 4; at most 16384 blocks of 256 threads),
+ * and the per-block partial sums of the inner products are reduced in two
+ * levels when there are more than `first_level` of them (1..16384, default
+ * 2048: blocks of that many partials, then one block), else in one.  The
+ * results differ only in the order of the binary64 sums.  A small shape makes
+ * a small grid run the many-block, two-level path of a large one (tests).
+ * GRTE_E_INVAL outside those ranges. */
+grte_status grte2d_set_launch_shape(grte2d_ctx *ctx, int items_per_thread, int first_level);
 
 /* The Krylov preconditioner inverts each cell's P x P block (the direction-
  * diagonal part plus the rank-one angular coupling of (4.5c)) and, in the

@@ -24,4 +24,7 @@ diffusion1d  The three-stage diffusion scheme (2.7) / its sigma/T^3 form, the
 diffusion2d  The three-stage scheme (2.7)/(2.9) on a 2-D rectangle (the eps -> 0
              reference of ap2d).
 energy       Energy bookkeeping used by the conservation pins, (3.12)-(3.13).
+alt314       The alternative correction of the remark closing Section 3,
+             (3.14): no nonlinear solve, T^{n+1} explicit, not energy
+             conservative.
 """

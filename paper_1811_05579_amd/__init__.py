@@ -187,6 +187,14 @@ class Grte:
         binary64 (False); arithmetic stays binary64."""
         check("grte_set_storage", self._lib.grte_set_storage(self._h, int(bool(fp32))))
 
+    def set_correction(self, kind="conservative"):
+        """Correction stage: 'conservative' (Algorithm 2) or 'alt' (the
+        remark's alternative (3.14), grte_set_correction)."""
+        kinds = {"conservative": 0, "alt": 1}
+        if kind not in kinds:
+            raise ValueError(f"correction kind: one of {sorted(kinds)}")
+        check("grte_set_correction", self._lib.grte_set_correction(self._h, kinds[kind]))
+
     def error_flags(self, clear=False):
         """Error flags OR-ed over the steps since the last clear (grte_get_error_flags):
         a dict of booleans keyed by 'sync', 'pred_noconv', 'newton', 'negative_root'."""
@@ -600,6 +608,12 @@ class Grte2D:
 
     def set_solver(self, tol=1e-14, maxit=2000):
         check("grte2d_set_solver", self._lib.grte2d_set_solver(self._h, float(tol), int(maxit)))
+
+    def set_launch_shape(self, items_per_thread=4, first_level=2048):
+        """Krylov kernels' items per thread and the two-level reduction threshold
+        (grte2d_set_launch_shape)."""
+        check("grte2d_set_launch_shape",
+              self._lib.grte2d_set_launch_shape(self._h, int(items_per_thread), int(first_level)))
 
     def set_opacity(self, sigma0):
         p, dev = _ptr(sigma0, self.N, "sigma0")

@@ -123,6 +123,7 @@ _SIGS = {
     "grte_set_storage": (c_int, [c_void_p, c_int]),
     "grte_set_launch": (c_int, [c_void_p, c_int]),
     "grte_get_error_flags": (c_int, [c_void_p, ctypes.POINTER(c_int), c_int]),
+    "grte_set_correction": (c_int, [c_void_p, c_int]),
     "grte_batch_get_error_flags": (c_int, [c_void_p, ctypes.POINTER(c_int), c_int]),
     "grte_reference_step": (c_int, [c_void_p, c_double, c_double, c_double, c_int,
                                     ctypes.POINTER(ReferenceInfo)]),
@@ -159,6 +160,7 @@ _SIGS = {
     "grte2d_destroy": (c_int, [c_void_p]),
     "grte2d_set_stream": (c_int, [c_void_p, c_void_p]),
     "grte2d_set_solver": (c_int, [c_void_p, c_double, c_int]),
+    "grte2d_set_launch_shape": (c_int, [c_void_p, c_int, c_int]),
     "grte2d_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
     "grte2d_set_inflow": (c_int, [c_void_p, c_void_p]),
     "grte2d_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),

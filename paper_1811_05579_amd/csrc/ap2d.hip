@@ -50,8 +50,9 @@ constexpr int B2 = 256;        // threads per block of the (cell, pair) kernels
 constexpr int MAXB = 2048;     // blocks of the grid-stride kernels outside the Krylov loop
 // the Krylov kernels over the N*P items run KRY_ITEMS items per thread (up to
 // KRYB blocks); their per-block partial sums are reduced in two levels (RED_B
-// partials per block of the first level, then one block over at most RED_MAX)
-constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = 2048, RED_MAX = KRYB / RED_B;
+// partials per block of the first level, then one block) when there are more
+// than RED_B of them (both figures can be set per context)
+constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = 2048;
 constexpr int CHUNK = 8;       // most BiCGStab iterations enqueued between convergence checks
 constexpr int KRY_RESTARTS = 6;      // restarts from the true residual per solve
 constexpr double CHEB2_A = 0.01, CHEB2_B = 2.0;   // eigenvalue interval of the Jacobi-scaled isotropic operator
@@ -284,7 +285,8 @@ struct VecArgs {
     const double *En;          // E^n (rhs)
     double *bv, *x, *r, *p, *ph, *v, *s, *sh, *t;
     double *part;              // [k * KRYB + block]
-    double *part2;             // [k * RED_MAX + block] (first reduction level)
+    double *part2;             // [k * KRYB + block] (first reduction level)
+    int red_b;                 // partials per block of the first reduction level
     double *sc;                // scalars
     int *fl;                   // flags
     double tol;
@@ -939,27 +941,27 @@ __device__ __forceinline__ double block_reduce(double v)
     return r;
 }
 
-// first reduction level: block b sums partials b*RED_B .. of each of k sums
+// first reduction level: block b sums partials b*red_b .. of each of k sums
 __global__ void __launch_bounds__(B2) red2d_kernel(VecArgs A, int which, int k, int nb)
 {
     if (which != 0 && A.fl[F_STATE] != 0) return;
-    const int base = blockIdx.x * RED_B, cnt = min(RED_B, nb - base);
+    const int base = blockIdx.x * A.red_b, cnt = min(A.red_b, nb - base);
     for (int q = 0; q < k; ++q) {
         double v = 0.0;
         for (int i = threadIdx.x; i < cnt; i += B2) v += A.part[q * KRYB + base + i];
         v = block_reduce(v);
-        if (threadIdx.x == 0) A.part2[q * RED_MAX + blockIdx.x] = v;
+        if (threadIdx.x == 0) A.part2[q * KRYB + blockIdx.x] = v;
     }
 }
 
-// sum k of the nb partials (through the first level when nb > RED_B)
+// sum k of the nb partials (through the first level when nb > red_b)
 __device__ __forceinline__ double fin_sum(const VecArgs &A, int k, int nb)
 {
-    const bool two = nb > RED_B;
+    const bool two = nb > A.red_b;
     const double *part = two ? A.part2 : A.part;
-    const int stride = two ? RED_MAX : KRYB, cnt = two ? (nb + RED_B - 1) / RED_B : nb;
+    const int cnt = two ? (nb + A.red_b - 1) / A.red_b : nb;
     double v = 0.0;
-    for (int i = threadIdx.x; i < cnt; i += B2) v += part[k * stride + i];
+    for (int i = threadIdx.x; i < cnt; i += B2) v += part[k * KRYB + i];
     return block_reduce(v);
 }
 
@@ -1400,6 +1402,8 @@ struct grte2d_ctx {
     double Mxx = 0, Myy = 0, Sx = 0, Sy = 0;
     double *yP = nullptr, *yS = nullptr, *dP = nullptr, *dS = nullptr, *itmp = nullptr, *idir = nullptr;
     double *pgc = nullptr;               // per-cell scalar of the block inverse
+    int kry_items = KRY_ITEMS;           // launch shape of the Krylov kernels (grte2d_set_launch_shape)
+    int red_b = RED_B;
     // energy balance: edge outflow per edge cell, rho^{n+1}, block partials,
     // the blocks-done counter and the four results
     double *bflux = nullptr, *rho1 = nullptr, *epart = nullptr, *energy = nullptr;
@@ -1442,9 +1446,9 @@ int nblocks(size_t n)
     return (int)std::max<size_t>(1, std::min<size_t>(b, MAXB));
 }
 
-int kblocks(size_t n)
+int kblocks(size_t n, int items)
 {
-    const size_t b = (n + (size_t)B2 * KRY_ITEMS - 1) / ((size_t)B2 * KRY_ITEMS);
+    const size_t b = (n + (size_t)B2 * items - 1) / ((size_t)B2 * items);
     return (int)std::max<size_t>(1, std::min<size_t>(b, KRYB));
 }
 
@@ -1678,12 +1682,13 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.mr = iso ? c->mr : nullptr;
     A.mv = iso ? c->mv : nullptr;
     const int nbc = nblocks(c->N);
-    const int nb = kblocks(c->nE);
+    const int nb = kblocks(c->nE, c->kry_items);
+    A.red_b = c->red_b;
     hipStream_t st = c->stream;
     // the scalar step `which` of the iteration after a kernel that left k partial sums per block
     auto fin = [&](int which, int k) {
-        if (nb > RED_B)
-            hipLaunchKernelGGL(red2d_kernel, dim3((nb + RED_B - 1) / RED_B), dim3(B2), 0, st, A, which, k, nb);
+        if (nb > c->red_b)
+            hipLaunchKernelGGL(red2d_kernel, dim3((nb + c->red_b - 1) / c->red_b), dim3(B2), 0, st, A, which, k, nb);
         hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, which, nb);
     };
     int its_total = 0, state = 0;
@@ -1882,7 +1887,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
-              dalloc(c, c->Es, c->nE) && dalloc(c, c->part, 4 * KRYB) && dalloc(c, c->part2, 4 * RED_MAX) && dalloc(c, c->sc, S_NS) &&
+              dalloc(c, c->Es, c->nE) && dalloc(c, c->part, 4 * KRYB) && dalloc(c, c->part2, 4 * KRYB) && dalloc(c, c->sc, S_NS) &&
               dalloc(c, c->fl, F_NF) && dalloc(c, c->stat, 8);
     if (ok) ok = hipHostMalloc((void **)&c->h_fl, F_NF * sizeof(int)) == hipSuccess;
     if (ok) ok = hipHostMalloc((void **)&c->h_sc, S_NS * sizeof(double)) == hipSuccess;
@@ -2006,6 +2011,15 @@ grte_status grte2d_set_solver(grte2d_ctx *c, double tol, int maxit)
     if (!c || !(tol > 0.0) || maxit < 1) return GRTE_E_INVAL;
     c->tol = tol;
     c->maxit = maxit;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_launch_shape(grte2d_ctx *c, int items_per_thread, int first_level)
+{
+    if (!c || items_per_thread < 1 || items_per_thread > 64 || first_level < 1 || first_level > KRYB)
+        return GRTE_E_INVAL;
+    c->kry_items = items_per_thread;
+    c->red_b = first_level;
     return GRTE_OK;
 }
 

@@ -374,10 +374,10 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         tile_max2<W>(md, mr, sh);
         tsync<W>();                               // rho update visible to the tile
         ++it;
-        const float qprev = Cs.q1, qprev2 = Cs.q2;
+        const float qprev = Cs.q1, qprev2 = Cs.q2, qprev3 = Cs.q3;
         const float q = (float)(mr > 0.0 ? md / mr : md);
         cheb_record(Cs, q);
-        converged = pred_stop(md, mr, q, qprev, qprev2, it, A.tol);
+        converged = pred_stop(md, mr, q, qprev, qprev2, qprev3, it, A.tol);
         if (converged || it >= A.maxit) break;
     }
     {
@@ -1201,11 +1201,38 @@ grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best)
     // buffers, so the state is left unchanged
     const int save_graph = b->use_graph;
     b->use_graph = 0;
+    // every candidate step also starts its prediction from the same iterate: the
+    // warm start (the previous step's rho*) is saved and put back before each,
+    // else all but the first would start from the answer of this very step
+    double *rsave = nullptr;
+    if (b->warm) {
+        if (hipMalloc((void **)&rsave, std::max<long long>(b->tot_cells, 1) * sizeof(double)) != hipSuccess) {
+            b->use_graph = save_graph;
+            return GRTE_E_NOMEM;
+        }
+        if (hipMemcpyAsync(rsave, b->rprev, b->tot_cells * sizeof(double), hipMemcpyDeviceToDevice, b->stream) !=
+            hipSuccess) {
+            (void)hipFree(rsave);
+            b->use_graph = save_graph;
+            return GRTE_E_HIP;
+        }
+    }
+    auto restore = [&]() -> grte_status {
+        if (rsave && hipMemcpyAsync(b->rprev, rsave, b->tot_cells * sizeof(double), hipMemcpyDeviceToDevice,
+                                    b->stream) != hipSuccess)
+            return GRTE_E_HIP;
+        return GRTE_OK;
+    };
     std::vector<int> h;
     grte_status st = assign_tiles(b);
+    if (st == GRTE_OK) st = restore();
     if (st == GRTE_OK) st = enqueue_step(b, b->stream, b->cur);
     if (st == GRTE_OK) st = read_stats(b, h);
-    if (st != GRTE_OK) { b->use_graph = save_graph; return st; }
+    if (st != GRTE_OK) {
+        if (rsave) (void)hipFree(rsave);
+        b->use_graph = save_graph;
+        return st;
+    }
     update_cost(b, h);
     int nb = 0;
     const void *kfn = b->f32 ? (const void *)batch_kernel<true> : (const void *)batch_kernel<false>;
@@ -1223,9 +1250,14 @@ grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best)
             b->wave_max_n = wv;
             b->grid = g;
             if ((st = assign_tiles(b)) != GRTE_OK) break;
+            if ((st = restore()) != GRTE_OK) break;
             if ((st = enqueue_step(b, b->stream, b->cur)) != GRTE_OK) break;   // warm-up
+            if ((st = restore()) != GRTE_OK) break;
             if (hipEventRecord(e0, b->stream) != hipSuccess) { st = GRTE_E_HIP; break; }
-            for (int r = 0; r < trials && st == GRTE_OK; ++r) st = enqueue_step(b, b->stream, b->cur);
+            for (int r = 0; r < trials && st == GRTE_OK; ++r) {
+                if (r > 0) st = restore();
+                if (st == GRTE_OK) st = enqueue_step(b, b->stream, b->cur);
+            }
             if (st != GRTE_OK) break;
             float ms = 0.0f;
             if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1244,6 +1276,11 @@ grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (st == GRTE_OK) st = restore();   // the next step starts as it would have without tuning
+    if (rsave) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess && st == GRTE_OK) st = GRTE_E_HIP;
+        (void)hipFree(rsave);
+    }
     b->use_graph = save_graph;
     if (st != GRTE_OK) return st;
     b->wave_max_n = bw;

@@ -420,10 +420,10 @@ __device__ __forceinline__ void pred_body(const PredArgs &A, const int bid, cons
         tile_max2<NT>(md, mr, sh);   // its barriers also publish the rho update
         ++it;
         if (bid == 0 && k == 0 && it <= HIST_CAP) A.hist[it - 1] = mr > 0.0 ? md / mr : md;
-        const float qprev = C.q1, qprev2 = C.q2;
+        const float qprev = C.q1, qprev2 = C.q2, qprev3 = C.q3;
         const float q = (float)(mr > 0.0 ? md / mr : md);
         cheb_record(C, q);
-        converged = pred_stop(md, mr, q, qprev, qprev2, it, A.tol);
+        converged = pred_stop(md, mr, q, qprev, qprev2, qprev3, it, A.tol);
         if (converged || it >= A.maxit) break;
     }
     {
@@ -463,6 +463,7 @@ struct NewtonArgs {
     double *Ecm;             // E* in cell-major order, as the prediction writes it
     double *Tnew, *ustar, *Dv, *ostar, *rstar;
     double *obnd;            // O* at the two end nodes, [p] (node 0) and [P + p] (node N)
+    int moments_only;        // 1: rho*, U*, D and O* only, T^{n+1} = T^n (the alternative correction)
     const float *O32;        // binary32 storage of O^n (f32 != 0)
     int f32;
     const uint16_t *gw;      // learned initial guess: bfloat16 weights (null: Newton from T^n)
@@ -533,6 +534,10 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &A, const uint16_t 
     const double q4 = ac * s0 * A.dt;
     const double rhs = s0 * A.dt * (A.rho_n[j] - A.c * A.dt * D);
     A.rstar[j] = rho;
+    if (A.moments_only) {
+        A.Tnew[j] = Tn;
+        return;
+    }
     double T = Tn;
     int its = 0;
     if (!(s0 == 0.0 && Ks == 0.0)) {
@@ -694,12 +699,61 @@ struct ProjArgs {
     int *stat;              // per-step counters; the sticky word collects their error flags
 };
 
+// Fixed-order binary64 sums of e0 and e1 over the nb blocks of a launch (blocks
+// 0..nb-1 of blockIdx.y's context): a tree over each block, per-block partials,
+// and the last block to finish sums the partials by index.  Called by every
+// thread of a block; true in every thread of the last block, which receives the
+// totals (and resets the counter for the next launch).
+__device__ bool energy_reduce(double e0, double e1, int nb, double *epart, unsigned *ecnt, double &E0, double &E1)
+{
+    __shared__ double s_e0[256], s_e1[256];
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    s_e0[t] = e0;
+    s_e1[t] = e1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            s_e0[t] += s_e0[t + o];
+            s_e1[t] += s_e1[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        epart[2 * blockIdx.x] = s_e0[0];
+        epart[2 * blockIdx.x + 1] = s_e1[0];
+        __threadfence();                         // partial visible device-wide before the count
+        s_last = atomicAdd(ecnt, 1u) == (unsigned)(nb - 1);
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();                             // every block's partial is in memory
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = t; b < nb; b += 256) {
+        a0 += __hip_atomic_load(&epart[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a1 += __hip_atomic_load(&epart[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();                             // s_e0/s_e1 reused
+    s_e0[t] = a0;
+    s_e1[t] = a1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            s_e0[t] += s_e0[t + o];
+            s_e1[t] += s_e1[t + o];
+        }
+        __syncthreads();
+    }
+    E0 = s_e0[0];
+    E1 = s_e1[0];
+    if (t == 0) *ecnt = 0u;
+    return true;
+}
+
 __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
 {
     const ProjArgs A = G.a[blockIdx.y];
     __shared__ double s_w[256];
-    __shared__ double s_e0[256], s_e1[256];
-    __shared__ int s_last;
     const int N = A.N, P = A.P, cpb = A.cpb;
     const int nb = (N + cpb - 1) / cpb;
     if ((int)blockIdx.x >= nb) return;          // whole block: contexts of the group differ in size
@@ -734,56 +788,203 @@ __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
         e0 = A.dx * (A.rho_n[jc] / A.c + A.cv * A.Tn[jc]);
         e1 = A.dx * (s / A.c + A.cv * A.Tnew[jc]);
     }
-    s_e0[t] = e0;
-    s_e1[t] = e1;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (t < o) {
-            s_e0[t] += s_e0[t + o];
-            s_e1[t] += s_e1[t + o];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        A.epart[2 * blockIdx.x] = s_e0[0];
-        A.epart[2 * blockIdx.x + 1] = s_e1[0];
-        __threadfence();                         // partial visible device-wide before the count
-        s_last = atomicAdd(A.ecnt, 1u) == (unsigned)(nb - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();                             // every block's partial is in memory
-    double a0 = 0.0, a1 = 0.0;
-    for (int b = t; b < nb; b += 256) {
-        a0 += __hip_atomic_load(&A.epart[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a1 += __hip_atomic_load(&A.epart[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();                             // s_e0/s_e1 reused
-    s_e0[t] = a0;
-    s_e1[t] = a1;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (t < o) {
-            s_e0[t] += s_e0[t + o];
-            s_e1[t] += s_e1[t + o];
-        }
-        __syncthreads();
-    }
+    double eb, ea;
+    if (!energy_reduce(e0, e1, nb, A.epart, A.ecnt, eb, ea)) return;
     if (t == 0) {
         double fl = 0.0;
         for (int q = 0; q < P; ++q) fl += A.omega[q] * A.mu[q] * (A.obnd[P + q] - A.obnd[q]);
-        const double eb = s_e0[0], ea = s_e1[0], fdt = A.dt * fl;
+        const double fdt = A.dt * fl;
         A.energy[0] = eb;
         A.energy[1] = ea;
         A.energy[2] = fdt;
         A.energy[3] = (ea - eb) + fdt;
-        *A.ecnt = 0u;
         // error flags of this step, kept until read (the counters are cleared next step)
         int f = 0;
         if (A.stat[6]) f |= GRTE_ERRF_SYNC;
         if (!A.stat[1]) f |= GRTE_ERRF_PRED_NOCONV;
         if (A.stat[3]) f |= GRTE_ERRF_NEWTON;
         if (A.stat[5]) f |= GRTE_ERRF_NEGATIVE_ROOT;
+        if (f) A.stat[STAT_STICKY] |= f;
+    }
+}
+
+// -------------------------------------------------------------------------
+// The alternative correction of the remark closing Section 3, (3.14): the time
+// derivative taken from the prediction's update, the emission at U*, no
+// nonlinear solve.  For the state a c U* + eps Jh its per-direction equations
+// are (4.11a,b) with U^{n+1} -> U* and the time-derivative terms known:
+//   nodes: K_i [(O*_i - O^n_i)/(c dt) + ac mu (U*_i - U*_{i-1})/(eps^2 dx)
+//               + mu (E_J,i - E_J,i-1)/(eps dx)] = -sigma_i O_J,i / eps^2
+//   cells: K_j [(E*_j - E^n_j)/(c dt) + mu (O_J,j+1 - O_J,j)/dx] = -sigma0_j E_J,j / eps
+// with the inflow relations (4.6) for a c U* + eps E_J, K = (T^n)^m (the
+// prediction's).  The node rows give O_J,i = alpha_i - mu beta_i (E_J,i - E_J,i-1),
+// beta_i = K_i eps / (sigma_i dx), so each direction is tridiagonal in E_J (the
+// operator form of the correction kernel: Lam = sigma0 c dt, face weights
+// -h beta, doubled at the two ends, and 2h in the boundary cells, h = K eps c dt
+// / dx; rows scaled by eps c dt).  Then (3.14b), T^{n+1} = T^n + dt sigma0
+// rho_J / (eps K Cv), and the projection (4.14).  Needs sigma0 > 0.
+// -------------------------------------------------------------------------
+struct AltArgs {
+    int N, P, m, cpb, M;
+    double a, c, cv, eps, dt, dx;
+    const double *Tn, *sigma0, *mu, *omega, *bL, *bR;
+    const double *En, *On, *Es, *Os, *Us;   // E^n, O^n, E*, O* (cell-major), U*
+    double *Ll, *Lu, *Lam, *Bd, *r;         // the per-direction operators and right-hand sides
+    const double *EJ;                       // E_J, cell-major (projection)
+    double *Enew, *Onew, *Tnew, *rho_out;
+    const double *rho_n;
+    double *epart, *energy;
+    unsigned *ecnt;
+    int *stat;
+};
+
+// node quantities of interior node i (1..N-1): K_i / sigma_i and K_i (the node
+// opacity is the harmonic mean of the two cells', K the mean of theirs)
+__device__ __forceinline__ void alt_node_coef(const AltArgs &A, int i, double &Ki, double &ksig)
+{
+    Ki = 0.5 * (kpow(A.Tn[i - 1], A.m) + kpow(A.Tn[i], A.m));
+    const double sl = A.sigma0[i - 1], sr = A.sigma0[i];
+    const double sn = 2.0 * sl * sr / (sl + sr);
+    ksig = Ki / sn;
+}
+
+// alpha_i of interior node i for direction p
+__device__ __forceinline__ double alt_alpha(const AltArgs &A, int i, int p, double Ki, double ksig)
+{
+    const int P = A.P;
+    const double mu = A.mu[p];
+    const double dO = A.Os[(size_t)i * P + p] - A.On[(size_t)i * P + p];
+    const double dU = A.Us[i] - A.Us[i - 1];
+    return -(ksig / (A.c * A.dt)) * (A.eps * A.eps * dO + A.a * A.c * mu * A.c * A.dt * dU / A.dx);
+}
+
+__global__ void __launch_bounds__(256) alt_coef_kernel(Group<AltArgs> G)
+{
+    const AltArgs A = G.a[blockIdx.y];
+    __shared__ double s_h[256], s_bl[256], s_br[256], s_kl[256], s_kr[256], s_nl[256], s_nr[256], s_K[256];
+    const int N = A.N, P = A.P, cpb = A.cpb;
+    const int c0 = blockIdx.x * cpb, t = threadIdx.x;
+    if (c0 >= N) return;
+    if (t < cpb && c0 + t < N) {
+        const int j = c0 + t;
+        const double K = kpow(A.Tn[j], A.m);
+        const double h = K * A.eps * A.c * A.dt / A.dx;
+        double Kl = 0.0, kl = 0.0, Kr = 0.0, kr = 0.0;
+        if (j >= 1) alt_node_coef(A, j, Kl, kl);
+        if (j <= N - 2) alt_node_coef(A, j + 1, Kr, kr);
+        const double bl = (j >= 1) ? kl * A.eps / A.dx : 0.0;      // beta at node j
+        const double br = (j <= N - 2) ? kr * A.eps / A.dx : 0.0;  // beta at node j + 1
+        A.Lam[j] = A.sigma0[j] * A.c * A.dt;
+        A.Ll[j] = (j >= 1) ? -h * bl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+        A.Lu[j] = (j <= N - 2) ? -h * br * (j == 0 ? 2.0 : 1.0) : 0.0;
+        A.Bd[j] = (j == 0 || j == N - 1) ? 2.0 * h : 0.0;
+        s_h[t] = h;
+        s_K[t] = K;
+        s_kl[t] = Kl;
+        s_nl[t] = kl;
+        s_kr[t] = Kr;
+        s_nr[t] = kr;
+        s_bl[t] = bl;
+        s_br[t] = br;
+    }
+    __syncthreads();
+    const int cl = t / P, p = t - (t / P) * P;
+    const int j = c0 + cl;
+    if (cl < cpb && j < N) {
+        const double mu = A.mu[p], h = s_h[cl], eps = A.eps;
+        double rv = -s_K[cl] * eps * (A.Es[(size_t)j * P + p] - A.En[(size_t)j * P + p]);
+        const double al = (j >= 1) ? alt_alpha(A, j, p, s_kl[cl], s_nl[cl]) : 0.0;
+        const double ar = (j <= N - 2) ? alt_alpha(A, j + 1, p, s_kr[cl], s_nr[cl]) : 0.0;
+        if (j == 0) {
+            rv += -2.0 * h * mu * ar + 2.0 * h * mu / eps * (A.bL[p] - A.a * A.c * A.Us[0]);
+        } else if (j == N - 1) {
+            rv += -2.0 * h * mu / eps * (A.a * A.c * A.Us[N - 1] - A.bR[p]) + 2.0 * h * mu * al;
+        } else {
+            rv += -h * mu * (ar - al);
+        }
+        A.r[(size_t)p * NT * A.M + (j % A.M) * NT + j / A.M] = rv;   // pair-major, position order
+    }
+}
+
+// O_J at node i of direction p from E_J (interior: the node row; ends: the
+// inflow relations for a c U* + eps E_J)
+__device__ __forceinline__ double alt_oj(const AltArgs &A, int i, int p)
+{
+    const int N = A.N, P = A.P;
+    const double mu = A.mu[p];
+    auto inner = [&](int ii) {
+        double Ki, ks;
+        alt_node_coef(A, ii, Ki, ks);
+        return alt_alpha(A, ii, p, Ki, ks) -
+               mu * (ks * A.eps / A.dx) * (A.EJ[(size_t)ii * P + p] - A.EJ[(size_t)(ii - 1) * P + p]);
+    };
+    if (i >= 1 && i <= N - 1) return inner(i);
+    const double ac = A.a * A.c;
+    if (i == 0) return 2.0 / A.eps * (A.bL[p] - ac * A.Us[0] - A.eps * A.EJ[p]) - inner(1);
+    return 2.0 / A.eps * (ac * A.Us[N - 1] + A.eps * A.EJ[(size_t)(N - 1) * P + p] - A.bR[p]) - inner(N - 1);
+}
+
+__global__ void __launch_bounds__(256) alt_project_kernel(Group<AltArgs> G)
+{
+    const AltArgs A = G.a[blockIdx.y];
+    __shared__ double s_w[256], s_T[256];
+    const int N = A.N, P = A.P, cpb = A.cpb;
+    const int nb = (N + cpb - 1) / cpb;
+    if ((int)blockIdx.x >= nb) return;
+    const int c0 = blockIdx.x * cpb, t = threadIdx.x;
+    const int cl = t / P, p = t - (t / P) * P;
+    const int j = c0 + cl;
+    const bool own = cl < cpb && j < N;
+    double ej = 0.0;
+    if (own) {
+        ej = A.EJ[(size_t)j * P + p];
+        A.Onew[(size_t)j * P + p] = alt_oj(A, j, p);
+        if (j == N - 1) A.Onew[(size_t)N * P + p] = alt_oj(A, N, p);
+    }
+    s_w[t] = own ? A.omega[p] * ej : 0.0;
+    __syncthreads();
+    double e0 = 0.0, e1 = 0.0;
+    if (t < cpb && c0 + t < N) {
+        const int jc = c0 + t;
+        double rj = 0.0;
+        for (int q = 0; q < P; ++q) rj += s_w[t * P + q];
+        // (3.14b): Cv (T^{n+1} - T^n)/dt = sigma rho_J, sigma = sigma0 / K, rho_J = rho(E_J) / eps
+        const double tn = A.Tn[jc];
+        const double T1 = tn + A.dt * A.sigma0[jc] * rj / (A.eps * kpow(tn, A.m) * A.cv);
+        A.Tnew[jc] = T1;
+        s_T[t] = T1;
+        e0 = A.dx * (A.rho_n[jc] / A.c + A.cv * tn);
+    }
+    __syncthreads();
+    if (own) {
+        const double T1 = s_T[cl];
+        const double e = A.a * A.c * ((T1 * T1) * (T1 * T1)) + A.eps * ej;
+        A.Enew[(size_t)j * P + p] = e;
+        s_w[t] = A.omega[p] * e;
+    }
+    __syncthreads();
+    if (t < cpb && c0 + t < N) {
+        double r1 = 0.0;
+        for (int q = 0; q < P; ++q) r1 += s_w[t * P + q];
+        A.rho_out[c0 + t] = r1;
+        e1 = A.dx * (r1 / A.c + A.cv * s_T[t]);
+    }
+    double eb, ea;
+    const bool last = energy_reduce(e0, e1, nb, A.epart, A.ecnt, eb, ea);
+    if (!last) return;
+    if (t == 0) {
+        // the outflow of the fluxes the alternative's moment equation uses: O_J
+        // at the two end nodes (formed again here from the inputs)
+        double fl = 0.0;
+        for (int q = 0; q < P; ++q) fl += A.omega[q] * A.mu[q] * (alt_oj(A, N, q) - alt_oj(A, 0, q));
+        const double fdt = A.dt * fl;
+        A.energy[0] = eb;
+        A.energy[1] = ea;
+        A.energy[2] = fdt;
+        A.energy[3] = (ea - eb) + fdt;
+        int f = 0;
+        if (A.stat[6]) f |= GRTE_ERRF_SYNC;
+        if (!A.stat[1]) f |= GRTE_ERRF_PRED_NOCONV;
         if (f) A.stat[STAT_STICKY] |= f;
     }
 }
@@ -899,6 +1100,7 @@ struct grte_ctx {
     int coop_capacity = 0;                 // co-resident prediction work-groups on the device
     int coop_launch = 1;                   // 1: cooperative launch of the prediction; 0: ordinary launch
     int keep = 1;
+    int corr_kind = GRTE_CORRECTION_CONSERVATIVE;   // grte_set_correction
     hipStream_t stream = nullptr;
     std::vector<double *> allocs;
     double *E = nullptr, *O = nullptr, *T = nullptr;       // current state
@@ -1401,7 +1603,9 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     Group<NewtonArgs> gn{};
     Group<CorrArgs> gr{};
     Group<ProjArgs> gj{};
-    gc.n = gp.n = gn.n = gr.n = gj.n = n;
+    Group<AltArgs> ga{};
+    gc.n = gp.n = gn.n = gr.n = gj.n = ga.n = n;
+    const bool alt = c0->corr_kind == GRTE_CORRECTION_ALT;
     unsigned ncb_max = 1, maxP = 1;
     int grid = 0;
     for (int g = 0; g < n; ++g) {
@@ -1447,6 +1651,19 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         na.bL = ctx->bL; na.bR = ctx->bR; na.Tnew = ctx->T2; na.ustar = ctx->ustar; na.Dv = ctx->Dv;
         na.ostar = ctx->ostar; na.stat = ctx->stat; na.rstar = ctx->rstar;
         na.obnd = ctx->obnd;
+        na.moments_only = alt ? 1 : 0;
+        // the alternative correction (3.14): its operators, E_J into the scratch
+        // `part` (cell-major), then the explicit temperature and the projection
+        AltArgs &aa = ga.a[g];
+        aa.N = N; aa.P = P; aa.m = ctx->m; aa.cpb = ctx->cpb; aa.M = ctx->M;
+        aa.a = ctx->a; aa.c = ctx->c; aa.cv = ctx->cv; aa.eps = eps; aa.dt = dt; aa.dx = dx;
+        aa.Tn = ctx->T; aa.sigma0 = ctx->sigma0; aa.mu = ctx->mu; aa.omega = ctx->omega;
+        aa.bL = ctx->bL; aa.bR = ctx->bR; aa.En = ctx->E; aa.On = ctx->O; aa.Es = ctx->estar;
+        aa.Os = ctx->ostar; aa.Us = ctx->ustar;
+        aa.Ll = ctx->Ll; aa.Lu = ctx->Lu; aa.Lam = ctx->Lam; aa.Bd = ctx->Bd; aa.r = ctx->r;
+        aa.EJ = ctx->part; aa.Enew = ctx->E2; aa.Onew = ctx->O2; aa.Tnew = ctx->T2; aa.rho_out = ctx->rho1;
+        aa.rho_n = ctx->rho_n; aa.epart = ctx->epart; aa.energy = ctx->energy; aa.ecnt = ctx->ecnt;
+        aa.stat = ctx->stat;
         na.gw = ctx->guess_w; na.gnorm = ctx->guess_norm; na.gtol = ctx->guess_tol;
         na.O32 = ctx->O32; na.f32 = ctx->f32;
         ctx->last_dt = dt;
@@ -1455,8 +1672,8 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         // correction substep 2: E^{n+1} straight into the next state
         CorrArgs &cc = gr.a[g];
         cc.N = N; cc.P = P; cc.Ll = ctx->Ll; cc.Lu = ctx->Lu; cc.Lam = ctx->Lam; cc.Bd = ctx->Bd;
-        cc.r = ctx->r; cc.mu = ctx->mu; cc.Enew = ctx->E2;
-        cc.E32new = ctx->E32b; cc.Tnew = ctx->T2; cc.ac = ctx->a * ctx->c; cc.f32 = ctx->f32;
+        cc.r = ctx->r; cc.mu = ctx->mu; cc.Enew = alt ? ctx->part : ctx->E2;
+        cc.E32new = ctx->E32b; cc.Tnew = ctx->T2; cc.ac = ctx->a * ctx->c; cc.f32 = alt ? 0 : ctx->f32;
         // projection: O^{n+1} at the nodes, rho^{n+1}
         ProjArgs &pj = gj.a[g];
         pj.N = N; pj.P = P; pj.keep = ctx->keep; pj.cpb = ctx->cpb; pj.eps = eps;
@@ -1493,11 +1710,15 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     if (any_guess) hipLaunchKernelGGL(newton_kernel<true>, dim3(ncb_max, n), dim3(256), 0, stream, gn);
     else hipLaunchKernelGGL(newton_kernel<false>, dim3(ncb_max, n), dim3(256), 0, stream, gn);
     HIPCHK(hipGetLastError());
-    for (int g = 0; g < n; ++g) {     // coefficients of the correction: K from T^{n+1}
-        gc.a[g].mode = 1;
-        gc.a[g].T = ctxs[g]->T2;
+    if (alt) {
+        hipLaunchKernelGGL(alt_coef_kernel, dim3(ncb_max, n), dim3(256), 0, stream, ga);
+    } else {
+        for (int g = 0; g < n; ++g) {     // coefficients of the correction: K from T^{n+1}
+            gc.a[g].mode = 1;
+            gc.a[g].T = ctxs[g]->T2;
+        }
+        hipLaunchKernelGGL(coef_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gc);
     }
-    hipLaunchKernelGGL(coef_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gc);
     HIPCHK(hipGetLastError());
     switch (M) {
     case 2: st = launch_corr<2>(stream, gr, (int)maxP); break;
@@ -1506,7 +1727,8 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     default: st = launch_corr<16>(stream, gr, (int)maxP); break;
     }
     if (st != GRTE_OK) return st;
-    hipLaunchKernelGGL(project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gj);
+    if (alt) hipLaunchKernelGGL(alt_project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, ga);
+    else hipLaunchKernelGGL(project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gj);
     HIPCHK(hipGetLastError());
     if ((st = prof_end(c0, ev_step)) != GRTE_OK) return st;   // whole step
     for (int g = 0; g < n; ++g) {
@@ -1570,6 +1792,7 @@ grte_status grte_step_group(grte_ctx *const *ctxs, int n, const double *dt, cons
         if (!ctxs[g] || !(dt[g] > 0) || !(eps[g] > 0) || !std::isfinite(dt[g]) || !std::isfinite(eps[g]))
             return GRTE_E_INVAL;
         if (ctxs[g]->M != ctxs[0]->M || ctxs[g]->dev != ctxs[0]->dev) return GRTE_E_INVAL;
+        if (ctxs[g]->corr_kind != ctxs[0]->corr_kind) return GRTE_E_INVAL;
         for (int h = 0; h < g; ++h)
             if (ctxs[h] == ctxs[g]) return GRTE_E_INVAL;
     }
@@ -1676,6 +1899,14 @@ grte_status grte_reference_step(grte_ctx *ctx, double dt, double eps, double tol
     return (converged && !pred_fail) ? GRTE_OK : GRTE_E_NOCONV;
 }
 
+grte_status grte_set_correction(grte_ctx *ctx, int kind)
+{
+    if (!ctx || (kind != GRTE_CORRECTION_CONSERVATIVE && kind != GRTE_CORRECTION_ALT)) return GRTE_E_INVAL;
+    if (kind == GRTE_CORRECTION_ALT && ctx->f32) return GRTE_E_UNSUPPORTED;
+    ctx->corr_kind = kind;
+    return GRTE_OK;
+}
+
 grte_status grte_get_error_flags(grte_ctx *ctx, int *flags, int clear)
 {
     if (!ctx || !flags) return GRTE_E_INVAL;
@@ -1700,6 +1931,7 @@ grte_status grte_set_storage(grte_ctx *ctx, int fp32)
 {
     if (!ctx || (fp32 != 0 && fp32 != 1)) return GRTE_E_INVAL;
     if (fp32 == ctx->f32) return GRTE_OK;
+    if (fp32 && ctx->corr_kind == GRTE_CORRECTION_ALT) return GRTE_E_UNSUPPORTED;
     if (fp32 && !ctx->E32) {
         const size_t ne = (size_t)ctx->N * ctx->P, no = (size_t)(ctx->N + 1) * ctx->P;
         float **bufs[] = {&ctx->E32, &ctx->E32b, &ctx->O32, &ctx->O32b};

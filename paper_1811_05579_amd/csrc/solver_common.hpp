@@ -645,17 +645,21 @@ __device__ __forceinline__ void cheb_record(ChebState &C, float q)
 
 // Stopping test of the prediction iteration for update norm md and iterate
 // norm mr, with the relative update norms q = md / mr of this update and
-// qprev, qprev2 of the two before: 1 if md <= tol mr; 2 (a safeguard) if
-// md <= PRED_FLOOR tol mr and the relative update norm has not decreased over
-// the last two updates -- the updates have then reached the rounding level of
-// the residual, where they only fluctuate and further updates do not improve
-// the iterate; 0 otherwise.
-constexpr double PRED_FLOOR = 16.0;
-__device__ __forceinline__ int pred_stop(double md, double mr, float q, float qprev, float qprev2, int it,
-                                         double tol)
+// qprev, qprev2, qprev3 of the three before: 1 if md <= tol mr; 2 (a
+// safeguard) when the updates have reached the rounding level of the residual,
+// where they only fluctuate and further updates do not improve the iterate:
+// either md <= PRED_FLOOR tol mr and the relative update norm has not
+// decreased over the last two updates, or md <= PRED_STALL tol mr and it is
+// still above 0.9 of what it was three updates earlier (no progress; a
+// converging iteration shrinks it by the contraction ratio every update, well
+// below 0.9^(1/3) here).  0 otherwise.
+constexpr double PRED_FLOOR = 16.0, PRED_STALL = 64.0;
+__device__ __forceinline__ int pred_stop(double md, double mr, float q, float qprev, float qprev2, float qprev3,
+                                         int it, double tol)
 {
     if (md <= tol * mr) return 1;
     if (it > 2 && md <= PRED_FLOOR * tol * mr && q >= qprev && qprev >= qprev2) return 2;
+    if (it > 3 && md <= PRED_STALL * tol * mr && q >= 0.9f * qprev3) return 2;
     return 0;
 }
 

@@ -14,7 +14,7 @@ that global level), and the scalar equation (4.13) in sampled cells.
 import numpy as np
 import pytest
 
-from fp64_bar import fp64_bar
+from fp64_bar import FLOOR, STIFF, bars, sensitivity, stiffness
 from oracle import ap2d
 from oracle.ap1d import Physics
 from paper_1811_05579_amd import Grte2D, GrteError
@@ -53,12 +53,27 @@ def oracle_step(w, E, Ox, Oy, T):
     return ap2d.ap_step(grid, E, Ox, Oy, T, w.sigma0, w.mu, w.eta, w.omega, w.b, _ph(w))
 
 
-def _compare(w, r, o, T, keys=("T", "E", "Ox", "Oy", "E_star", "U_star", "D", "rho_n")):
-    bar = fp64_bar(w, T)
+KEYS = ("T", "E", "Ox", "Oy", "E_star", "U_star", "D", "rho_n")
+
+
+def oracle_with_bars(w, E, Ox, Oy, T, keys=KEYS):
+    """The oracle's step and the FP64 bar per array (fp64_bar.py: 1e-12 up to
+    a stiffness a c beta of 1e6, above it ten times the oracle's measured
+    one-ulp sensitivity)."""
+    grid = ap2d.Grid2D(w.nx, w.ny, w.Lx, w.Ly)
+    step = lambda E_, X_, Y_, T_, s_: ap2d.ap_step(grid, E_, X_, Y_, T_, s_, w.mu, w.eta, w.omega, w.b, _ph(w))
+    if stiffness(w, T) <= STIFF:
+        return step(E, Ox, Oy, T, w.sigma0), {k: FLOOR for k in keys}
+    o, sens = sensitivity(step, [E, Ox, Oy, T, w.sigma0], keys)
+    return o, bars(w, T, keys, sens)
+
+
+def _compare(w, r, o, T, bar, keys=KEYS):
     errs = {k: _rel(r[k], o[k]) for k in keys}
-    print(w.name, {k: f"{v:.2e}" for k, v in errs.items()}, f"bar {bar:.0e}", flush=True)
+    print(w.name, f"a c beta {stiffness(w, T):.1e}", {k: f"{v:.2e}/{bar[k]:.0e}" for k, v in errs.items()},
+          flush=True)
     for k, e in errs.items():
-        assert e <= bar, (k, e, bar)
+        assert e <= bar[k], (k, e, bar[k])
     return errs
 
 
@@ -82,8 +97,8 @@ def test_one_step_matches_oracle(nx, ny, nv, m, eps, seed):
     g.close()
     assert info["status"] == 0, info
     assert info["pred_converged"] and info["corr_converged"], info
-    o = oracle_step(w, w.E, w.Ox, w.Oy, w.T)
-    _compare(w, r, o, w.T)
+    o, bar = oracle_with_bars(w, w.E, w.Ox, w.Oy, w.T)
+    _compare(w, r, o, w.T, bar)
 
 
 def _two_material(n, nv, sig, eps, seed):
@@ -101,8 +116,8 @@ def test_cold_start_two_material_steps(n, nv, sig, eps):
     for k in range(3):
         r, info = gpu_step(g, w, E, Ox, Oy, T)
         assert info["status"] == 0, info
-        o = oracle_step(w, E, Ox, Oy, T)
-        _compare(w, r, o, T)
+        o, bar = oracle_with_bars(w, E, Ox, Oy, T)
+        _compare(w, r, o, T, bar)
         E, Ox, Oy, T = r["E"], r["Ox"], r["Oy"], r["T"]
     g.close()
 
@@ -204,8 +219,8 @@ def test_fp32_storage_round_trip_and_step_against_oracle():
     assert info["status"] == 0, info
     E1, Ox1, Oy1, T1 = g.get_state()
     g.close()
-    o = oracle_step(w, E, Ox, Oy, T)
-    assert _rel(T1, o["T"]) <= fp64_bar(w, T)
+    o, bar = oracle_with_bars(w, E, Ox, Oy, T, keys=("T",))
+    assert _rel(T1, o["T"]) <= bar["T"]
     dev = o["E"] - w.a * w.c * (o["T"] ** 4)[:, :, None]
     assert np.max(np.abs(E1 - o["E"])) <= 2 * U32 * np.max(np.abs(dev)) + 1e-12 * np.max(np.abs(o["E"]))
     for k, x in (("Ox", Ox1), ("Oy", Oy1)):
@@ -393,8 +408,8 @@ def test_degenerate_sizes_match_oracle(nx, ny, pairs):
     r, info = gpu_step(g, w, E, Ox, Oy, T)
     g.close()
     assert info["status"] == 0, info
-    o = oracle_step(w, E, Ox, Oy, T)
-    _compare(w, r, o, T)
+    o, bar = oracle_with_bars(w, E, Ox, Oy, T)
+    _compare(w, r, o, T, bar)
 
 
 def test_iteration_cap_holds_for_the_whole_solve():
@@ -410,3 +425,63 @@ def test_iteration_cap_holds_for_the_whole_solve():
     g.close()
     assert info["pred_iters"] <= 5 and info["corr_iters"] <= 5, info
     assert info["status"] == -4 and not info["pred_converged"], info
+
+
+@pytest.mark.parametrize("case,shape", [("random", (1, 4)), ("two_material", (1, 2)), ("random", (3, 1))])
+def test_many_block_two_level_path_against_oracle(case, shape):
+    """A launch shape of one or three items per thread and a first reduction
+    level of one to four partials makes these grids run the path of the
+    full-size workloads -- many blocks, the partial sums reduced in two
+    levels -- which the default shape only takes above ~2 million items;
+    the step still matches the oracle and the default shape's step."""
+    if case == "random":
+        w = random_state_2d(37, 29, 8, 8, m=0, eps=1e-2)
+    else:
+        w = _two_material(24, 32, (1.0, 100.0), 1e-3, 18110000 + 3)
+    ref_g = _ctx(w)
+    r_def, _ = gpu_step(ref_g, w, w.E, w.Ox, w.Oy, w.T)
+    ref_g.close()
+    g = _ctx(w)
+    g.set_launch_shape(*shape)
+    r, info = gpu_step(g, w, w.E, w.Ox, w.Oy, w.T)
+    g.close()
+    assert info["status"] == 0, info
+    nblk = -(-w.nx * w.ny * w.P // (256 * shape[0]))
+    print(f"{w.name}: {nblk} blocks, first level of {shape[1]}", flush=True)
+    assert nblk > shape[1]
+    o, bar = oracle_with_bars(w, w.E, w.Ox, w.Oy, w.T)
+    _compare(w, r, o, w.T, bar)
+    for k in ("T", "E", "Ox", "Oy"):
+        assert _rel(r[k], r_def[k]) <= 2 * bar[k], k
+
+
+def test_64x64_two_material_cold_start_against_oracle():
+    """The workload shape of the 1024^2 run (two-material Voronoi opacity
+    sigma in {1, 100}, eps = 1e-3, 32 directions, cold start, hot inflow) on
+    64 x 64 cells: four 32 x 32 tiles of the isotropic correction with their
+    halos, 1024 Krylov blocks; one step against the oracle."""
+    w = _two_material(64, 32, (1.0, 100.0), 1e-3, 18110000 + 3)
+    g = _ctx(w)
+    r, info = gpu_step(g, w, w.E, w.Ox, w.Oy, w.T)
+    g.close()
+    assert info["status"] == 0, info
+    o, bar = oracle_with_bars(w, w.E, w.Ox, w.Oy, w.T)
+    _compare(w, r, o, w.T, bar)
+
+
+def test_40x40_two_material_developed_state_against_oracle():
+    """The same workload shape on 40 x 40 cells (2 x 2 tiles, ragged): ten GPU
+    steps from the cold start (the heated cells of the sigma = 100 material
+    are then stiff, a c beta above 1e6), then one GPU step and one oracle
+    step from that GPU state."""
+    w = _two_material(40, 32, (1.0, 100.0), 1e-3, 18110000 + 3)
+    g = _ctx(w)
+    g.set_state(w.E, w.Ox, w.Oy, w.T)
+    for _ in range(10):
+        assert g.step(w.dt, w.eps, info=True)["status"] == 0
+    E, Ox, Oy, T = g.get_state()
+    r, info = gpu_step(g, w, E, Ox, Oy, T)
+    g.close()
+    assert info["status"] == 0, info
+    o, bar = oracle_with_bars(w, E, Ox, Oy, T)
+    _compare(w, r, o, T, bar)

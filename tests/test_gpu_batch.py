@@ -2,10 +2,11 @@
 path and the CPU oracle.
 
 Every instance of a batch computes the step of Algorithm 2 on its own data,
-so the batch must reproduce (i) the single-instance library step of the same
-instance to rounding (different tile partitions of the tridiagonal solves:
-FP64 bar 1e-12, growing above a stiffness a c beta of 1e6 as fp64_bar.py
-states) and (ii) the oracle to the same bar.  The batch is built from instances that cover both
+so the batch must reproduce (i) the oracle to the FP64 bar (1e-12 up to a
+stiffness a c beta of 1e6, above it ten times the oracle's measured one-ulp
+sensitivity, fp64_bar.py) and (ii) the single-instance library step of the
+same instance (different tile partitions of the tridiagonal solves) to twice
+that bar.  The batch is built from instances that cover both
 tile kinds (one wavefront: N <= 256; one work-group: 2, 4, 8 rows per
 thread), ragged sizes, 1 to 64 pairs, both opacity laws and eps from 1 to
 1e-5, with the generic seeded states of the parity tests.
@@ -13,7 +14,7 @@ thread), ragged sizes, 1 to 64 pairs, both opacity laws and eps from 1 to
 import numpy as np
 import pytest
 
-from fp64_bar import fp64_bar
+from fp64_bar import FLOOR, STIFF, bars, sensitivity, stiffness
 from oracle.ap1d import Physics, ap_step
 from paper_1811_05579_amd import Grte, GrteBatch
 from paper_1811_05579_amd.workloads import Ensemble, config4, random_state
@@ -26,8 +27,32 @@ def _rel(x, y):
     return float(np.max(np.abs(x - y)) / den) if den > 0 else float(np.max(np.abs(x)))
 
 
+KEYS = ("T", "E", "O")
+
+
+def _ph(w):
+    return Physics(a=w.a, c=w.c, Cv=w.Cv, eps=w.eps, dt=w.dt, L=w.L, m=w.m)
+
+
+def _oracle(w, E, O, T):
+    """The oracle's step from (E, O, T) and its FP64 bars per array."""
+    step = lambda E_, O_, T_, s_: ap_step(E_, O_, T_, s_, w.mu, w.omega, w.bL, w.bR, _ph(w))
+    if stiffness(w, T) <= STIFF:
+        return step(E, O, T, w.sigma0), {k: FLOOR for k in KEYS}
+    ref, sens = sensitivity(step, [E, O, T, w.sigma0], KEYS)
+    return ref, bars(w, T, KEYS, sens)
+
+
+_BARS = {}
+
+
 def _tol(w):
-    return fp64_bar(w, w.T)
+    """The largest FP64 bar over T, E, O of one step of w from its own state
+    (measured once per instance)."""
+    key = (w.name, w.N, w.P, w.m, w.eps, float(w.T[0]), float(w.E.flat[0]))
+    if key not in _BARS:
+        _BARS[key] = FLOOR if stiffness(w, w.T) <= STIFF else max(_oracle(w, w.E, w.O, w.T)[1].values())
+    return _BARS[key]
 
 
 # (N, nv, m, eps): wavefront tiles (N <= 256) and work-group tiles (M = 2, 4, 8)
@@ -75,7 +100,7 @@ def test_batch_matches_single_instance(wave_max_n):
     parts = b.split(*b.get_state())
     for w, (E, O, T), inf in zip(ens.members, parts, infos):
         (Es, Os, Ts), si = _single(w)
-        tol = _tol(w)
+        tol = 2 * _tol(w)           # two GPU paths, each within the bar of the oracle
         assert abs(inf["pred_iters"] - si["pred_iters"]) <= 1, (w.name, inf, si)
         for name, x, y in (("T", T, Ts), ("E", E, Es), ("O", O, Os)):
             assert _rel(x, y) <= tol, (w.name, name, _rel(x, y), tol)
@@ -91,11 +116,9 @@ def test_batch_matches_oracle():
     for w, (E, O, T) in zip(ens.members, parts):
         if w.N * w.P > 20000:
             continue     # oracle time; the large tiles are covered against the single path
-        ph = Physics(a=w.a, c=w.c, Cv=w.Cv, eps=w.eps, dt=w.dt, L=w.L, m=w.m)
-        r = ap_step(w.E, w.O, w.T, w.sigma0, w.mu, w.omega, w.bL, w.bR, ph)
-        tol = _tol(w)
+        r, bar = _oracle(w, w.E, w.O, w.T)
         for name, x in (("T", T), ("E", E), ("O", O)):
-            assert _rel(x, r[name]) <= tol, (w.name, name, _rel(x, r[name]), tol)
+            assert _rel(x, r[name]) <= bar[name], (w.name, name, _rel(x, r[name]), bar[name])
     b.close()
 
 
@@ -132,7 +155,7 @@ def test_tune_keeps_state_and_result():
     E, O, T = b.get_state()
     for w, p, q in zip(ens.members, b.split(E, O, T), b.split(Er, Or, Tr)):
         for x, y in zip(p, q):
-            assert _rel(x, y) <= _tol(w)
+            assert _rel(x, y) <= 2 * _tol(w)
     ref.close()
     b.close()
 
@@ -155,8 +178,9 @@ def test_config4_full_batch_sampled_against_single_instance():
         w = ens.members[i]
         (Es, Os, Ts), si = _single(w)
         E, O, T = parts[i]
-        assert _rel(T, Ts) <= 1e-11, (i, _rel(T, Ts))
-        assert _rel(E, Es) <= 1e-11 and _rel(O, Os) <= 1e-11, (i, _rel(E, Es), _rel(O, Os))
+        tol = 2 * _tol(w)           # two GPU paths, each within the bar of the oracle
+        assert _rel(T, Ts) <= tol, (i, _rel(T, Ts), tol)
+        assert _rel(E, Es) <= tol and _rel(O, Os) <= tol, (i, _rel(E, Es), _rel(O, Os), tol)
         assert np.max(np.abs(T - Ts) / Ts) < 1e-6
     b.close()
 
@@ -164,26 +188,75 @@ def test_config4_full_batch_sampled_against_single_instance():
 def test_stiffest_ensemble_members_against_oracle():
     """The six stiffest small slabs of the 4096-slab ensemble (a c beta of
     2e9 to 7e9: cold T = 0.01 starts with sigma0 up to 100 and eps ~ 1e-5),
-    four batched steps, each against the oracle's step from the same state.
-    The bar is that of fp64_bar.py, 2e-9 to 7e-9 here (errors measured: up
-    to ~2e-11 in E and T, ~1e-9 in O)."""
+    four batched steps, each against the oracle's step from the same state,
+    at ten times the oracle's own one-ulp sensitivity of each array
+    (fp64_bar.py).  Measured: the sensitivity reaches 2e-11 in T, 1e-10 in E
+    and 2e-10 in O; the GPU's errors are 0.2 to 5 times it."""
     full = config4(n=4096)
     idx = [1276, 1053, 2171, 3750, 1545, 3779]
     sub = Ensemble("stiffest", [full.members[i] for i in idx])
     b = _batch(sub)
     states = [(w.E, w.O, w.T) for w in sub.members]
     for _ in range(4):
-        refs, bars = [], []
+        refs, bars_ = [], []
         for w, (E, O, T) in zip(sub.members, states):
-            ph = Physics(a=w.a, c=w.c, Cv=w.Cv, eps=w.eps, dt=w.dt, L=w.L, m=w.m)
-            refs.append(ap_step(E, O, T, w.sigma0, w.mu, w.omega, w.bL, w.bR, ph))
-            bars.append(fp64_bar(w, T))
+            r, bar = _oracle(w, E, O, T)
+            refs.append(r)
+            bars_.append(bar)
         st, infos = b.step(info=True)
         assert st == 0
-        for w, r, bar, (E, O, T) in zip(sub.members, refs, bars, b.split(*b.get_state())):
-            for name, x in (("T", T), ("E", E), ("O", O)):
-                assert _rel(x, r[name]) <= bar, (w.name, name, _rel(x, r[name]), bar)
+        for w, r, bar, (E, O, T) in zip(sub.members, refs, bars_, b.split(*b.get_state())):
+            errs = {name: _rel(x, r[name]) for name, x in (("T", T), ("E", E), ("O", O))}
+            print(f"[stiff] {w.name} " + " ".join(f"{k}={v:.1e}/{bar[k]:.1e}" for k, v in errs.items()), flush=True)
+            for name, e in errs.items():
+                assert e <= bar[name], (w.name, name, e, bar[name])
         states = [(r["E"], r["O"], r["T"]) for r in refs]
         b.set_state(np.concatenate([s_[0].ravel() for s_ in states]), np.concatenate([s_[1].ravel() for s_ in states]),
                     np.concatenate([s_[2] for s_ in states]))
     b.close()
+
+
+def test_binary32_cold_start_converges():
+    """Two ensemble slabs whose binary32-stored state right after the cold start
+    leaves the prediction's relative update fluctuating at ~2.3e-14 (its
+    rounding level there, above 16 x the 1e-15 tolerance): the iteration must
+    recognise the stall and stop (pred_floor_stop) instead of running to its
+    cap, in the batched and the single-slab path, with both accelerations; the
+    temperature then agrees with the binary64-stored run far inside the
+    binary32 storage error."""
+    full = config4(n=4096)
+    for i in (74, 2142):
+        w = full.members[i]
+        ref = GrteBatch([w])
+        pk = Ensemble("one", [w]).packed()
+        ref.set_opacity(pk["sigma0"])
+        ref.set_inflow(pk["bL"], pk["bR"])
+        ref.set_state(pk["E"], pk["O"], pk["T"])
+        for _ in range(3):
+            assert ref.step(info=True)[0] == 0
+        T64 = ref.get_state()[2]
+        ref.close()
+        for mode in ("chebyshev", "richardson"):
+            b = GrteBatch([w])
+            b.set_opacity(pk["sigma0"])
+            b.set_inflow(pk["bL"], pk["bR"])
+            b.set_storage(True)
+            b.set_state(pk["E"], pk["O"], pk["T"])
+            b.set_acceleration(mode)
+            for s in range(3):
+                st, inf = b.step(info=True)
+                print(f"slab {i} batched binary32 {mode} step {s + 1}: {inf[0]['pred_iters']} updates, "
+                      f"floor stop {inf[0]['pred_floor_stop']}", flush=True)
+                assert st == 0 and inf[0]["pred_converged"] == 1, (i, mode, s, inf[0])
+            assert _rel(b.get_state()[2], T64) < 1e-6
+            b.close()
+            g = Grte(w.N, w.mu, w.omega, length=w.L, a=w.a, c=w.c, cv=w.Cv, opacity_law=w.m)
+            g.set_opacity(w.sigma0)
+            g.set_inflow(w.bL, w.bR)
+            g.set_storage(True)
+            g.set_state(w.E, w.O, w.T)
+            g.set_acceleration(mode)
+            for s in range(3):
+                info = g.step(w.dt, w.eps, info=True)
+                assert info["status"] == 0 and info["pred_converged"] == 1, (i, mode, s, info)
+            g.close()
