@@ -1091,21 +1091,50 @@ struct NewtArgs {
     double *bflux;               // edge cells: outflow through their edge faces, sum_p omega_p (...)
     int *stat;                   // [0] max its, [1] failed, [2] K* clamped, [3] negative root, [4] sum its,
                                  // [5] guesses accepted, [6] guesses not used, [7] Newton started from a guess
-    const uint16_t *gw;          // learned initial guess: bfloat16 weights (null: Newton from T^n)
-    const float *gnorm;          // and its normalisation
+    const double *tg;            // learned starting values (guess2d_kernel; GUESS kernels only)
     double gtol;                 // residual below which the guess is taken as the root
 };
+
+// The learned starting values of the temperature solve, one thread per cell:
+// the network's features from (rho*, T^n, sigma0, eps, dt), rho* = sum_p
+// omega_p E*_p, and T_g = T^n exp(mean + sd y) into tg (NaN where the network
+// has no input: sigma0 = 0 or T^n <= 0).  A kernel of its own, so that the
+// network's 64 hidden values live in the registers of every lane rather than
+// in one lane per cell of the temperature kernel.
+struct GuessArgs {
+    int n, P, m;
+    double eps, dt;
+    const double *Es, *Tn, *sigma0, *om;
+    const uint16_t *gw;
+    const float *gnorm;
+    double *tg;
+};
+
+__global__ void __launch_bounds__(B2) guess2d_kernel(GuessArgs A)
+{
+    __shared__ uint16_t sW[MLP_NPARAM + 3];
+    __shared__ float sN[MLP_NNORM];
+    for (int e = threadIdx.x; e < MLP_NPARAM; e += B2) sW[e] = A.gw[e];
+    if (threadIdx.x < MLP_NNORM) sN[threadIdx.x] = A.gnorm[threadIdx.x];
+    __syncthreads();
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < A.n; j += gridDim.x * B2) {
+        const double Tn = A.Tn[j], s0 = A.sigma0[j];
+        double tg = NAN;
+        if (s0 > 0.0 && Tn > 0.0) {
+            double rho = 0.0;
+            for (int p = 0; p < A.P; ++p) rho += A.om[p] * A.Es[(size_t)j * A.P + p];
+            float f[MLP_IN];
+            mlp_features(rho, Tn, s0, A.m, A.eps, A.dt, f);
+            const float y = mlp_eval_streamed(sW, sN, f);
+            tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
+        }
+        A.tg[j] = tg;
+    }
+}
 
 template <bool GUESS>
 __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
 {
-    __shared__ uint16_t sW[GUESS ? MLP_NPARAM + 3 : 1];
-    __shared__ float sN[GUESS ? MLP_NNORM : 1];
-    if constexpr (GUESS) {
-        for (int e = threadIdx.x; e < MLP_NPARAM; e += B2) sW[e] = A.gw[e];
-        if (threadIdx.x < MLP_NNORM) sN[threadIdx.x] = A.gnorm[threadIdx.x];
-        __syncthreads();
-    }
     int acc = 0, unused = 0, started = 0;
     const Sys &S = A.S;
     const int P = S.P;
@@ -1162,13 +1191,11 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
             if (Tn + rhs / lin < 0.0) ++neg;
             bool ok = false, done = false;
             if (GUESS && s0 > 0.0 && Tn > 0.0) {
-                // learned starting value, judged by the normalised residual of (4.13):
-                // taken as the root below gtol, used as Newton's start if its residual
-                // is below that of T^n, otherwise Newton starts from T^n
-                float f[MLP_IN];
-                mlp_features(rhs_s, Tn, s0, A.m, S.eps, A.dt, f);
-                const float y = mlp_eval(sW, sN, f);
-                const double Tg = Tn * exp((double)sN[10] + (double)sN[11] * (double)y);
+                // learned starting value (guess2d_kernel), judged by the normalised
+                // residual of (4.13): taken as the root below gtol, used as Newton's
+                // start if its residual is below that of T^n, otherwise Newton starts
+                // from T^n
+                const double Tg = A.tg[j];
                 if (isfinite(Tg) && Tg > 0.0) {
                     const double T2 = Tg * Tg;
                     const double rg = fabs(q4 * T2 * T2 + lin * (Tg - Tn) - rhs) / lin;
@@ -1407,6 +1434,7 @@ struct grte2d_ctx {
     // energy balance: edge outflow per edge cell, rho^{n+1}, block partials,
     // the blocks-done counter and the four results
     double *bflux = nullptr, *rho1 = nullptr, *epart = nullptr, *energy = nullptr;
+    double *tguess = nullptr;            // learned starting values of the temperature solve
     unsigned *ecnt = nullptr;
     double *idg = nullptr;               // per-(cell, pair) inverse diagonal of the block inverse
     double *mr = nullptr, *mv = nullptr;  // angular moments of r and v (isotropic correction)
@@ -1871,7 +1899,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
               dalloc(c, c->Dv, c->N) && dalloc(c, c->rhon, c->N) && dalloc(c, c->bv, c->nE) &&
               dalloc(c, c->sab, c->N) && dalloc(c, c->ue, c->N) &&
               dalloc(c, c->yP, c->N) && dalloc(c, c->yS, c->N) && dalloc(c, c->dP, c->N) &&
-              dalloc(c, c->rstar, c->N) && dalloc(c, c->bflux, c->N) && dalloc(c, c->rho1, c->N) &&
+              dalloc(c, c->rstar, c->N) && dalloc(c, c->bflux, c->N) && dalloc(c, c->rho1, c->N) && dalloc(c, c->tguess, c->N) &&
               dalloc(c, c->epart, 3 * ENERGY_BLOCKS) && dalloc(c, c->energy, 4) && dalloc(c, c->ecnt, 1) &&
               [&] {
                   for (auto &L : c->mg) {
@@ -2208,13 +2236,29 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     na.stat = c->stat;
     na.rstar = c->rstar;
     na.bflux = c->bflux;
-    na.gw = c->guess_w;
-    na.gnorm = c->guess_norm;
+    na.tg = c->tguess;
     na.gtol = c->guess_tol;
     // (fewer, longer-lived blocks: one atomic per wavefront and counter)
     const int nbn = std::min(nb, 2048);
-    if (c->guess_w) hipLaunchKernelGGL(newton2d_kernel<true>, dim3(nbn), dim3(B2), 0, st, na);
-    else hipLaunchKernelGGL(newton2d_kernel<false>, dim3(nbn), dim3(B2), 0, st, na);
+    if (c->guess_w) {
+        GuessArgs ga;
+        ga.n = (int)c->N;
+        ga.P = c->P;
+        ga.m = c->m;
+        ga.eps = eps;
+        ga.dt = dt;
+        ga.Es = c->Es;
+        ga.Tn = c->T;
+        ga.sigma0 = c->sigma0;
+        ga.om = c->om;
+        ga.gw = c->guess_w;
+        ga.gnorm = c->guess_norm;
+        ga.tg = c->tguess;
+        hipLaunchKernelGGL(guess2d_kernel, dim3(nbc), dim3(B2), 0, st, ga);
+        hipLaunchKernelGGL(newton2d_kernel<true>, dim3(nbn), dim3(B2), 0, st, na);
+    } else {
+        hipLaunchKernelGGL(newton2d_kernel<false>, dim3(nbn), dim3(B2), 0, st, na);
+    }
 
     // ---- correction, substep 2 (4.11) with K^{n+1}, U^{n+1}
     ca.corr = 1;

@@ -89,4 +89,32 @@ __device__ __forceinline__ float mlp_eval(const uint16_t *W, const float *norm, 
     return y;
 }
 
+// The same network output, its second layer accumulated input by input: the
+// 64 second-layer sums stay in registers while each first-layer unit is formed
+// once and used at once (the 64 first-layer values are never all live), so a
+// kernel doing nothing else keeps it in registers.  The sums run over the
+// inputs in increasing order from the bias, as in mlp_eval.
+__device__ __forceinline__ float mlp_eval_streamed(const uint16_t *W, const float *norm, const float (&f)[MLP_IN])
+{
+    float x[MLP_IN];
+#pragma unroll
+    for (int q = 0; q < MLP_IN; ++q) x[q] = (f[q] - norm[q]) / norm[MLP_IN + q];
+    float z2[MLP_H];
+#pragma unroll
+    for (int k = 0; k < MLP_H; ++k) z2[k] = bf16_to_f(W[MLP_OB2 + k]);
+#pragma unroll 1
+    for (int i = 0; i < MLP_H; ++i) {
+        float z = bf16_to_f(W[MLP_OB1 + i]);
+#pragma unroll
+        for (int q = 0; q < MLP_IN; ++q) z += bf16_to_f(W[MLP_OW1 + MLP_IN * i + q]) * x[q];
+        const float h = gelu_f(z);
+#pragma unroll
+        for (int k = 0; k < MLP_H; ++k) z2[k] += bf16_to_f(W[MLP_OW2 + MLP_H * k + i]) * h;
+    }
+    float y = bf16_to_f(W[MLP_OB3]);
+#pragma unroll
+    for (int k = 0; k < MLP_H; ++k) y += bf16_to_f(W[MLP_OW3 + k]) * gelu_f(z2[k]);
+    return y;
+}
+
 }  // namespace
