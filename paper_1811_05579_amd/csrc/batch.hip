@@ -202,7 +202,13 @@ struct BState {
     }
 };
 
-// right-hand sides of the per-pair systems into Rt (pair-major, cell order)
+// right-hand sides of the per-pair systems into Rt (pair-major, cell order).
+// A thread takes rows j = k, k + W, ... and, per row, the pairs in groups of
+// RHS_U: the group's state loads are all issued before its arithmetic, so a
+// thread keeps RHS_U memory round trips in flight (these loops are latency-
+// bound at one wavefront per SIMD), and the row's coefficients are read once.
+constexpr int RHS_U = 4;
+
 template <int W, int M, bool F32>
 __device__ void b_rhs(const BInst &I, const double *C, int N1, const BState<F32> &S,
                       const double *mu, const double *bL, const double *bR, double *Rt)
@@ -210,16 +216,29 @@ __device__ void b_rhs(const BInst &I, const double *C, int N1, const BState<F32>
     constexpr int NP = W * M;
     const int N = I.N, P = I.P;
     const int k = tile_lane<W>();
-    for (int idx = k; idx < N * P; idx += W) {
-        const int j = idx / P, p = idx - (idx / P) * P;
-        const double h = C[C_H * N1 + j];
-        const double On_r = (j <= N - 2) ? S.o((size_t)(j + 1) * P + p) : 0.0;
-        const double On_l = (j >= 1) ? S.o((size_t)j * P + p) : 0.0;
-        double rv = C[C_KEPS * N1 + j] * S.e(j, idx) + C[C_SRC * N1 + j]
-                  - h * mu[p] * (C[C_AWR * N1 + j] * On_r - C[C_AWL * N1 + j] * On_l);
-        if (j == 0) rv += 2.0 * h * mu[p] * bL[p] / I.eps;
-        if (j == N - 1) rv += 2.0 * h * mu[p] * bR[p] / I.eps;
-        Rt[(size_t)p * NP + j] = rv;
+    for (int j = k; j < N; j += W) {
+        const double h = C[C_H * N1 + j], keps = C[C_KEPS * N1 + j], src = C[C_SRC * N1 + j];
+        const double awr = C[C_AWR * N1 + j], awl = C[C_AWL * N1 + j];
+        const bool has_r = j <= N - 2, has_l = j >= 1;
+        for (int p0 = 0; p0 < P; p0 += RHS_U) {
+            double e[RHS_U], orr[RHS_U], ol[RHS_U];
+#pragma unroll
+            for (int u = 0; u < RHS_U; ++u) {
+                const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
+                e[u] = S.e(j, j * P + p);
+                orr[u] = has_r ? S.o((size_t)(j + 1) * P + p) : 0.0;
+                ol[u] = has_l ? S.o((size_t)j * P + p) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RHS_U; ++u) {
+                const int p = p0 + u;
+                if (p >= P) break;
+                double rv = keps * e[u] + src - h * mu[p] * (awr * orr[u] - awl * ol[u]);
+                if (j == 0) rv += 2.0 * h * mu[p] * bL[p] / I.eps;
+                if (j == N - 1) rv += 2.0 * h * mu[p] * bR[p] / I.eps;
+                Rt[(size_t)p * NP + j] = rv;
+            }
+        }
     }
 }
 
@@ -256,6 +275,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     for (int j = k; j < N; j += W) {
         b_cell(I, 0, Tn, Tn, sg, j, C, N1);
         double rn = 0.0;
+#pragma unroll 4
         for (int p = 0; p < P; ++p) rn += om[p] * S.e(j, j * P + p);
         C[C_RHON * N1 + j] = rn;
     }
@@ -395,23 +415,50 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     int n_its = 0, n_fail = 0, n_clamp = 0, n_neg = 0;
     for (int j = k; j < N; j += W) {
         double rs = 0.0, D = 0.0, f0 = 0.0, fN = 0.0;
-        for (int p = 0; p < P; ++p) {
-            const double *ep = Et + (size_t)p * NP;
-            const double m1 = mu[p];
-            const double ej = ep[j];
-            // O* at nodes j and j+1 from the node relation and the inflow relations (4.7)
-            double ol, orr;
-            if constexpr (F32) {
-                ol = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
-                orr = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
-            } else {
-                ol = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
-                orr = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
+        // O* at nodes j and j+1 from the node relation (inline for interior
+        // nodes) and the inflow relations (4.7) at the two ends (node_pc); the
+        // pairs in groups of RHS_U whose loads are issued first
+        const bool inner_l = j >= 1, inner_r = j + 1 <= N - 1;
+        const double awl = C[C_AW * N1 + j], bcl = C[C_BC * N1 + j];
+        const double awr = inner_r ? C[C_AW * N1 + j + 1] : 0.0, bcr = inner_r ? C[C_BC * N1 + j + 1] : 0.0;
+        for (int p0 = 0; p0 < P; p0 += RHS_U) {
+            double em[RHS_U], ej[RHS_U], ep1[RHS_U], onl[RHS_U], onr[RHS_U];
+#pragma unroll
+            for (int u = 0; u < RHS_U; ++u) {
+                const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
+                const double *ep = Et + (size_t)p * NP;
+                ej[u] = ep[j];
+                em[u] = inner_l ? ep[j - 1] : 0.0;
+                ep1[u] = inner_r ? ep[j + 1] : 0.0;
+                onl[u] = inner_l ? S.o((size_t)j * P + p) : 0.0;
+                onr[u] = inner_r ? S.o((size_t)(j + 1) * P + p) : 0.0;
             }
-            rs += om[p] * ej;
-            D += om[p] * m1 * (orr - ol);
-            f0 += om[p] * m1 * ol;
-            fN += om[p] * m1 * orr;
+#pragma unroll
+            for (int u = 0; u < RHS_U; ++u) {
+                const int p = p0 + u;
+                if (p >= P) break;
+                const double *ep = Et + (size_t)p * NP;
+                const double m1 = mu[p];
+                double ol, orr;
+                if (inner_l) {
+                    ol = awl * onl[u] - bcl * m1 * (ej[u] - em[u]);
+                } else if constexpr (F32) {
+                    ol = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
+                } else {
+                    ol = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
+                }
+                if (inner_r) {
+                    orr = awr * onr[u] - bcr * m1 * (ep1[u] - ej[u]);
+                } else if constexpr (F32) {
+                    orr = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
+                } else {
+                    orr = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
+                }
+                rs += om[p] * ej[u];
+                D += om[p] * m1 * (orr - ol);
+                f0 += om[p] * m1 * ol;
+                fN += om[p] * m1 * orr;
+            }
         }
         if (j == 0) C[C_FLUX * N1] = f0;
         if (j == N - 1) C[C_FLUX * N1 + 1] = fN;
@@ -527,39 +574,55 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     // then the tile sum).
     const double *Aw = C + C_AW * N1, *Bc = C + C_BC * N1;
     double eb = 0.0, ea = 0.0;
-    if constexpr (F32) {
-        float *E32o = A.E32o + I.oE, *O32o = A.O32o + I.oO;
-        for (int j = k; j < N; j += W) {
-            const double t1 = T2[j];
-            const double base = S.ac * (t1 * t1) * (t1 * t1);
-            double r1 = 0.0;
-            for (int p = 0; p < P; ++p) {
+    // per row, the pairs in groups of RHS_U: the group's loads are issued before
+    // its stores (O at node j from the node relation, the interior case inline;
+    // the two end nodes by node_pc)
+    float *E32o = F32 ? A.E32o + I.oE : nullptr, *O32o = F32 ? A.O32o + I.oO : nullptr;
+    double *E2 = F32 ? nullptr : A.E2 + I.oE, *O2 = F32 ? nullptr : A.O2 + I.oO;
+    for (int j = k; j < N; j += W) {
+        const double t1 = T2[j];
+        const double base = S.ac * (t1 * t1) * (t1 * t1);
+        const double awj = Aw[j], bcj = Bc[j];
+        double r1 = 0.0;
+        for (int p0 = 0; p0 < P; p0 += RHS_U) {
+            double ej[RHS_U], em[RHS_U], on[RHS_U];
+#pragma unroll
+            for (int u = 0; u < RHS_U; ++u) {
+                const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
                 const double *ep = Et + (size_t)p * NP;
-                r1 += om[p] * ep[j];
-                E32o[(size_t)j * P + p] = (float)(ep[j] - base);
-                O32o[(size_t)j * P + p] = (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
-                if (j == N - 1)
-                    O32o[(size_t)N * P + p] =
-                        (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+                ej[u] = ep[j];
+                em[u] = j >= 1 ? ep[j - 1] : 0.0;
+                on[u] = j >= 1 ? S.o((size_t)j * P + p) : 0.0;
             }
-            eb += I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
-            ea += I.dx * (r1 / I.c + I.cv * t1);
-        }
-    } else {
-        double *E2 = A.E2 + I.oE, *O2 = A.O2 + I.oO;
-        for (int j = k; j < N; j += W) {
-            double r1 = 0.0;
-            for (int p = 0; p < P; ++p) {
+#pragma unroll
+            for (int u = 0; u < RHS_U; ++u) {
+                const int p = p0 + u;
+                if (p >= P) break;
                 const double *ep = Et + (size_t)p * NP;
-                r1 += om[p] * ep[j];
-                E2[(size_t)j * P + p] = ep[j];
-                O2[(size_t)j * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, j, p);
-                if (j == N - 1)
-                    O2[(size_t)N * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+                r1 += om[p] * ej[u];
+                double oj;
+                if (j >= 1) {
+                    oj = awj * on[u] - bcj * mu[p] * (ej[u] - em[u]);
+                } else {
+                    if constexpr (F32) oj = node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, 0, p);
+                    else oj = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, 0, p);
+                }
+                if constexpr (F32) {
+                    E32o[(size_t)j * P + p] = (float)(ej[u] - base);
+                    O32o[(size_t)j * P + p] = (float)oj;
+                    if (j == N - 1)
+                        O32o[(size_t)N * P + p] =
+                            (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+                } else {
+                    E2[(size_t)j * P + p] = ej[u];
+                    O2[(size_t)j * P + p] = oj;
+                    if (j == N - 1)
+                        O2[(size_t)N * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
+                }
             }
-            eb += I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
-            ea += I.dx * (r1 / I.c + I.cv * T2[j]);
         }
+        eb += I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
+        ea += I.dx * (r1 / I.c + I.cv * t1);
     }
     tile_sum2<W>(eb, ea, sh);
     if (k == 0) {
