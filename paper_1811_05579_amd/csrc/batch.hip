@@ -4,7 +4,11 @@
 //
 // Every instance is advanced by one "tile": a whole work-group (W = 256
 // threads) or, for small slabs, one wavefront (W = 64; four independent
-// instances per work-group).  Inside a tile the step is the algebra of the
+// instances per work-group).  In a work-group tile the per-cell phases use all
+// 256 threads, while the per-pair tridiagonal solves are split over its four
+// wavefronts (pairs p = w, w + 4, ... on wavefront w), each solving its pair
+// alone with 4 M rows per lane: four independent elimination chains in flight
+// per work-group.  Inside a tile the step is the algebra of the
 // single-instance path (Algorithm 2 and Section 5 of Tang, Wang & Zhang):
 // the per-pair tridiagonal operators T_p = Lam + mu_p^2 L + mu_p B with U*
 // eliminated through (4.5c), the angular coupling of the prediction solved by
@@ -12,7 +16,9 @@
 // updates (warm-started from the previous step's rho*),
 // Newton on (4.13)/(5.5), the per-pair correction (4.11) and the projection
 // (4.14).  One tile owns all parity pairs of its instance, so the angular sum
-// is accumulated in registers and no grid-wide synchronisation exists.
+// is accumulated in registers (and, across the wavefronts of a work-group,
+// summed through LDS in a fixed order) and no grid-wide synchronisation
+// exists.
 // Instances are taken from two work queues -- work-group tiles first, then
 // wavefront tiles -- in an order chosen by the host (longest expected work
 // first), so that work-groups that finish their large slabs early drain the
@@ -46,8 +52,13 @@ enum {
     NCA
 };
 
-// LDS of one tile (doubles): rho, Ll, Lu in position order + the solver's scratch
-constexpr int LDS_WG = 3 * BMAX_N + tile_scratch<BNT>();
+// LDS of one tile (doubles).  A work-group tile (NP = 256 M padded rows, in
+// the layout of the wavefront solver: 64 lanes of 4 M rows) holds rho, Ll, Lu,
+// Lam and Lam - G, the angular sums of its four wavefronts (4 NP), the last
+// Chebyshev update of every row (NP binary32) and a 32-double reduction area;
+// a wavefront tile holds rho, Ll, Lu in its position order and its solver's
+// scratch.
+constexpr int LDS_WG = 9 * BMAX_N + BMAX_N / 2 + 32;
 constexpr int LDS_WAVE = 3 * WAVE_MAX_N + tile_scratch<WAVE>();
 static_assert(4 * LDS_WAVE <= LDS_WG, "four wavefront tiles fit in the work-group LDS");
 
@@ -97,7 +108,13 @@ __device__ __forceinline__ void tsync()
     }
 }
 
-__device__ __forceinline__ int bpos(int j, int W, int M) { return (j % M) * W + j / M; }
+// v through an empty asm: the compiler cannot hoist what is derived from the
+// result out of the enclosing loop (keeps per-row addresses out of registers)
+__device__ __forceinline__ int opaque(int v)
+{
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
 
 // interior node i (1..N-1): harmonic-mean sigma, arithmetic-mean K
 __device__ __forceinline__ void b_node(const BInst &I, const double *Tk, const double *sg, int i,
@@ -215,7 +232,7 @@ __device__ void b_rhs(const BInst &I, const double *C, int N1, const BState<F32>
 {
     constexpr int NP = W * M;
     const int N = I.N, P = I.P;
-    const int k = tile_lane<W>();
+    const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
     for (int j = k; j < N; j += W) {
         const double h = C[C_H * N1 + j], keps = C[C_KEPS * N1 + j], src = C[C_SRC * N1 + j];
         const double awr = C[C_AWR * N1 + j], awl = C[C_AWL * N1 + j];
@@ -248,7 +265,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     constexpr int NP = W * M;
     const BInst I = A.inst[i];
     const int N = I.N, P = I.P, N1 = N + 1;
-    const int k = tile_lane<W>();
+    const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
     const int j0 = k * M;
     const double eps = I.eps;
     const double *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
@@ -269,7 +286,22 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     double *Rt = A.pairs + I.oR;                  // right-hand sides
     double *Et = Rt + (size_t)P * I.NPa;          // E* (prediction), then E^{n+1} (correction)
     int *st = A.istat + 8 * i;
+    // Work-group tiles keep the per-row arrays in the layout of the wavefront
+    // solver (LM = 4 M rows per lane, row j at LDS position (j % LM) 64 + j / LM);
+    // wavefront tiles in their own position order (LM = M, the same formula).
+    constexpr bool WG = (W == BNT);
+    constexpr int LM = WG ? 4 * M : M;
+    auto lpos = [](int j) { return (j % LM) * 64 + j / LM; };
     double *rho = sm, *sLl = sm + NP, *sLu = sm + 2 * NP, *sh = sm + 3 * NP;
+    double *slam = nullptr, *slmg = nullptr, *accw = nullptr, *red = nullptr;
+    float *sdch = nullptr;
+    if constexpr (WG) {
+        slam = sm + 3 * NP;
+        slmg = sm + 4 * NP;
+        accw = sm + 5 * NP;
+        sdch = reinterpret_cast<float *>(sm + 9 * NP);
+        red = sm + 9 * NP + NP / 2;
+    }
 
     // ---------------- coefficients of the prediction (K from T^n) and rho^n
     for (int j = k; j < N; j += W) {
@@ -283,128 +315,259 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     b_rhs<W, M, F32>(I, C, N1, S, mu, bL, bR, Rt);
     double *rp = A.rprev + I.oT;
     for (int j = k; j < NP; j += W) {
-        const int t = bpos(j, W, M);
+        const int t = lpos(j);
         const bool in = j < N;
         rho[t] = in ? (A.warm ? rp[j] : C[C_RHON * N1 + j]) : 0.0;
         sLl[t] = in ? C[C_LL * N1 + j] : 0.0;
         sLu[t] = in ? C[C_LU * N1 + j] : 0.0;
+        if constexpr (WG) {
+            slam[t] = in ? C[C_LAM * N1 + j] : 1.0;   // padding rows: T_p = D = 1, no coupling
+            slmg[t] = in ? C[C_LMG * N1 + j] : 1.0;
+            sdch[t] = 0.0f;
+        }
     }
     tsync<W>();
     const double bd0 = C[C_BD * N1 + 0], bdN = C[C_BD * N1 + N - 1];
 
     // ---------------- prediction: DSA-preconditioned iteration (plain or Chebyshev updates)
-    double lam[M], lmg[M];
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-        const int j = j0 + r;
-        const bool in = j < N;
-        lam[r] = in ? C[C_LAM * N1 + j] : 1.0;
-        lmg[r] = in ? C[C_LMG * N1 + j] : 0.0;
-    }
     int it = 0, converged = 0, ph = 0;
     ChebState Cs;
-    float dch[M];                             // previous update (steers the next one only)
+    if constexpr (WG) {
+        const int w = threadIdx.x >> 6;
+        // Per lane: jq = first row, nv = rows inside the slab, rl1 = lane row of
+        // the slab's last row.  The lane index is re-derived through opaque() in
+        // every pair step, so each array costs one base register there and the
+        // rows are immediate offsets r * 64 doubles.
+        // Padding rows (j >= N) need no tests: their right-hand sides are zero,
+        // Lam = Lam - G = 1 and Ll = Lu = 0 there, so every solve and update
+        // below yields exact zeros in them.
+        auto load_r = [&](int p, double (&v)[LM]) {
+            const double *src = Rt + (size_t)p * NP + opaque(threadIdx.x & 63) * LM;
 #pragma unroll
-    for (int r = 0; r < M; ++r) dch[r] = 0.0f;
-    // One sweep over the pairs from the current rho, v_p = T_p^{-1} [r_p -
-    // (Lam - G + mu^2 L + mu B) rho]: accumulates sum_p omega_p v_p into acc,
-    // or (final) writes E*_p = rho + v_p of the final iterate.
-    auto sweep = [&](double (&acc)[M], bool final_sweep) {
-        double rnext[M];
+            for (int r = 0; r < LM; ++r) v[r] = src[r];
+        };
+        // One sweep of this wavefront's pairs from the current rho: v_p = T_p^{-1}
+        // [r_p - (Lam - G + mu^2 L + mu B) rho], summed as omega_p v_p into the
+        // wavefront's LDS row sums, or (final) E*_p = rho + v_p written.  rnext
+        // holds pair w's right-hand side on entry and again on return (loaded
+        // while the tile waits).
+        double rnext[LM];
+        if (w < P) load_r(w, rnext);
+        auto sweep = [&](bool final_sweep) {
+            if (!final_sweep) {
+                double *acc = accw + w * NP + opaque(threadIdx.x & 63);
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            acc[r] = 0.0;
-            rnext[r] = Rt[j0 + r];              // right-hand side of pair 0
-        }
-        for (int p = 0; p < P; ++p) {
-            const double m1 = mu[p], m2 = m1 * m1, wp = om[p];
-            double rcur[M];
-#pragma unroll
-            for (int r = 0; r < M; ++r) {       // this pair's right-hand side; fetch the next one
-                rcur[r] = rnext[r];
-                if (p + 1 < P) rnext[r] = Rt[(size_t)(p + 1) * NP + j0 + r];
+                for (int r = 0; r < LM; ++r) acc[r * 64] = 0.0;
             }
-            double b[M], y[M], v[M];
+            for (int p = w; p < P; p += 4) {
+                const double m1 = mu[p], m2 = m1 * m1, wp = om[p];
+                double x[LM];
 #pragma unroll
-            for (int r = 0; r < M; ++r) {
-                const int j = j0 + r;
-                const int t = r * W + k;
-                if (j < N) {
-                    const double ll = sLl[t], lu = sLu[t];
-                    const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
-                    b[r] = lam[r] + m2 * (-(ll + lu)) + m1 * bdj;
-                    const double rj = rho[t];
-                    double rl = rj, rn = rj;   // boundary rows: ll or lu is 0
-                    if (j > 0) rl = (r > 0) ? rho[t - W] : rho[(M - 1) * W + k - 1];
-                    if (j < N - 1) rn = (r < M - 1) ? rho[t + W] : rho[k + 1];
-                    const double q = ll * (rl - rj) + lu * (rn - rj);   // difference form (low rounding floor)
-                    y[r] = rcur[r] - lmg[r] * rj - m2 * q - m1 * bdj * rj;
+                for (int r = 0; r < LM; ++r) x[r] = rnext[r];
+                load_r(p + 4 < P ? p + 4 : w, rnext);
+                const int lq = opaque(threadIdx.x & 63), jq = lq * LM, rl1 = N - 1 - jq;
+                const double *rh = rho + lq, *ll = sLl + lq, *lu = sLu + lq, *la = slam + lq, *lg = slmg + lq;
+                const double b0 = jq == 0 ? bd0 : 0.0;
+                auto bdr = [&](int r) { return (r == 0 ? b0 : 0.0) + (r == rl1 ? bdN : 0.0); };
+#pragma unroll
+                for (int r = 0; r < LM; ++r) {
+                    // the neighbours' rho (an in-bounds dummy where there is none: its
+                    // coefficient ll or lu is 0 there)
+                    const double rj = rh[r * 64];
+                    const double rl = (r > 0) ? rh[(r - 1) * 64] : (jq > 0 ? rh[(LM - 1) * 64 - 1] : rj);
+                    const double rn = (r < LM - 1) ? rh[(r + 1) * 64] : (lq < 63 ? rh[1] : rj);
+                    const double q = ll[r * 64] * (rl - rj) + lu[r * 64] * (rn - rj);   // difference form
+                    x[r] = x[r] - lg[r * 64] * rj - m2 * q - m1 * bdr(r) * rj;
+                }
+                lane_chunk_solve<LM>(
+                    [&](int r) { return m2 * ll[r * 64]; },
+                    [&](int r) { return la[r * 64] + m2 * (-(ll[r * 64] + lu[r * 64])) + m1 * bdr(r); },
+                    [&](int r) { return m2 * lu[r * 64]; }, x);
+                if (final_sweep) {
+                    double *ep = Et + (size_t)p * NP + jq;
+#pragma unroll
+                    for (int r = 0; r < LM; ++r) ep[r] = rh[r * 64] + x[r];
                 } else {
-                    b[r] = 1.0;
-                    y[r] = 0.0;
+                    double *acc = accw + w * NP + lq;
+#pragma unroll
+                    for (int r = 0; r < LM; ++r) acc[r * 64] += wp * x[r];
                 }
             }
-            tri_factor_solve<W, M>(m2, sLl, sLu, b, y, v, sh, ph);
-            if (final_sweep) {
-                double *ep = Et + (size_t)p * NP;
+        };
+        while (true) {
+            {
+                sweep(false);
+                __syncthreads();
+                double alpha, beta;
+                cheb_coeffs(Cs, A.accel, A.tol, alpha, beta);   // every wavefront: the same state
+                if (w == 0) {
+                    // res = sum_p omega_p v_p - (1 - W) rho (the four wavefronts' sums in
+                    // a fixed order);  rho += res + D^{-1} (G res), G = Lam - (Lam - G),
+                    // D = Lam - G + <mu^2> L + <mu> B (the diffusion operator of the DSA)
+                    const int lq = opaque(threadIdx.x & 63), jq = lq * LM, rl1 = N - 1 - jq;
+                    const double *ll = sLl + lq, *lu = sLu + lq, *la = slam + lq, *lg = slmg + lq;
+                    double *rh = rho + lq, *a0 = accw + lq;
+                    float *dc = sdch + lq;
+                    const double b0 = jq == 0 ? bd0 : 0.0;
+                    auto bdr = [&](int r) { return (r == 0 ? b0 : 0.0) + (r == rl1 ? bdN : 0.0); };
+                    double x[LM];
 #pragma unroll
-                for (int r = 0; r < M; ++r) ep[j0 + r] = rho[r * W + k] + v[r];
-            } else {
+                    for (int r = 0; r < LM; ++r) {
+                        const int t = r * 64;
+                        const double tot = ((a0[t] + a0[NP + t]) + a0[2 * NP + t]) + a0[3 * NP + t];
+                        const double rl = tot - I.one_minus_W * rh[t];
+                        a0[t] = rl;
+                        x[r] = (la[t] - lg[t]) * rl;
+                    }
+                    lane_chunk_solve<LM>(
+                        [&](int r) { return I.mu2 * ll[r * 64]; },
+                        [&](int r) { return lg[r * 64] + I.mu2 * (-(ll[r * 64] + lu[r * 64])) + I.mu1 * bdr(r); },
+                        [&](int r) { return I.mu2 * lu[r * 64]; }, x);
+                    double md = 0.0, mr = 0.0;
 #pragma unroll
-                for (int r = 0; r < M; ++r) acc[r] += wp * v[r];
+                    for (int r = 0; r < LM; ++r) {
+                        const int t = r * 64;
+                        const double z = a0[t] + x[r];
+                        const double upd = alpha * (double)dc[t] + beta * z;
+                        dc[t] = (float)upd;
+                        const double nw = rh[t] + upd;
+                        rh[t] = nw;
+                        md = fmax(md, fabs(z));
+                        mr = fmax(mr, fabs(nw));
+                    }
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        md = fmax(md, __shfl_xor(md, o, 64));
+                        mr = fmax(mr, __shfl_xor(mr, o, 64));
+                    }
+                    if (lq == 0) {
+                        red[0] = md;
+                        red[1] = mr;
+                    }
+                }
+                __syncthreads();                      // the rho update and its norms visible to the tile
             }
+            const double md = red[0], mr = red[1];
+            ++it;
+            const float qprev = Cs.q1, qprev2 = Cs.q2, qprev3 = Cs.q3;
+            const float q = (float)(mr > 0.0 ? md / mr : md);
+            cheb_record(Cs, q);
+            converged = pred_stop(md, mr, q, qprev, qprev2, qprev3, it, A.tol);
+            if (converged || it >= A.maxit) break;
         }
-    };
-    while (true) {
-        double acc[M];
-        sweep(acc, false);
-        // res = sum_p omega_p v_p - (1 - W) rho;  rho += res + D^{-1} (G res).
-        // Every operator is factored and solved in one call (one barrier); the
-        // diffusion operator is factored again each iteration rather than held
-        // in registers across the pair loop (one factorisation per P solves).
-        double rl[M], d[M], f[M];
-        {
-            double b[M];
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-                const int j = j0 + r;
-                const bool in = j < N;
-                rl[r] = in ? acc[r] - I.one_minus_W * rho[r * W + k] : 0.0;
-                d[r] = in ? C[C_G * N1 + j] * rl[r] : 0.0;
-                b[r] = in ? C[C_DD * N1 + j] : 1.0;
-            }
-            tri_factor_solve<W, M>(I.mu2, sLl, sLu, b, d, f, sh, ph);
-        }
-        double alpha, beta;
-        cheb_coeffs(Cs, A.accel, A.tol, alpha, beta);
-        double md = 0.0, mr = 0.0;
+        sweep(true);                                  // E* of the final iterate
+    } else {
+        double lam[M], lmg[M];
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-            if (j0 + r < N) {
-                const int t = r * W + k;
-                const double z = rl[r] + f[r];
-                const double upd = alpha * (double)dch[r] + beta * z;
-                dch[r] = (float)upd;
-                const double nw = rho[t] + upd;
-                rho[t] = nw;
-                md = fmax(md, fabs(z));
-                mr = fmax(mr, fabs(nw));
-            }
+            const int j = j0 + r;
+            const bool in = j < N;
+            lam[r] = in ? C[C_LAM * N1 + j] : 1.0;
+            lmg[r] = in ? C[C_LMG * N1 + j] : 0.0;
         }
-        tile_max2<W>(md, mr, sh);
-        tsync<W>();                               // rho update visible to the tile
-        ++it;
-        const float qprev = Cs.q1, qprev2 = Cs.q2, qprev3 = Cs.q3;
-        const float q = (float)(mr > 0.0 ? md / mr : md);
-        cheb_record(Cs, q);
-        converged = pred_stop(md, mr, q, qprev, qprev2, qprev3, it, A.tol);
-        if (converged || it >= A.maxit) break;
+        float dch[M];                             // previous update (steers the next one only)
+#pragma unroll
+        for (int r = 0; r < M; ++r) dch[r] = 0.0f;
+        // One sweep over the pairs from the current rho, v_p = T_p^{-1} [r_p -
+        // (Lam - G + mu^2 L + mu B) rho]: accumulates sum_p omega_p v_p into acc,
+        // or (final) writes E*_p = rho + v_p of the final iterate.
+        auto sweep = [&](double (&acc)[M], bool final_sweep) {
+            double rnext[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                acc[r] = 0.0;
+                rnext[r] = Rt[j0 + r];              // right-hand side of pair 0
+            }
+            for (int p = 0; p < P; ++p) {
+                const double m1 = mu[p], m2 = m1 * m1, wp = om[p];
+                double rcur[M];
+#pragma unroll
+                for (int r = 0; r < M; ++r) {       // this pair's right-hand side; fetch the next one
+                    rcur[r] = rnext[r];
+                    if (p + 1 < P) rnext[r] = Rt[(size_t)(p + 1) * NP + j0 + r];
+                }
+                double b[M], y[M], v[M];
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    const int j = j0 + r;
+                    const int t = r * W + k;
+                    if (j < N) {
+                        const double ll = sLl[t], lu = sLu[t];
+                        const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
+                        b[r] = lam[r] + m2 * (-(ll + lu)) + m1 * bdj;
+                        const double rj = rho[t];
+                        double rl = rj, rn = rj;   // boundary rows: ll or lu is 0
+                        if (j > 0) rl = (r > 0) ? rho[t - W] : rho[(M - 1) * W + k - 1];
+                        if (j < N - 1) rn = (r < M - 1) ? rho[t + W] : rho[k + 1];
+                        const double q = ll * (rl - rj) + lu * (rn - rj);   // difference form (low rounding floor)
+                        y[r] = rcur[r] - lmg[r] * rj - m2 * q - m1 * bdj * rj;
+                    } else {
+                        b[r] = 1.0;
+                        y[r] = 0.0;
+                    }
+                }
+                tri_factor_solve<W, M>(m2, sLl, sLu, b, y, v, sh, ph);
+                if (final_sweep) {
+                    double *ep = Et + (size_t)p * NP;
+#pragma unroll
+                    for (int r = 0; r < M; ++r) ep[j0 + r] = rho[r * W + k] + v[r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < M; ++r) acc[r] += wp * v[r];
+                }
+            }
+        };
+        while (true) {
+            double acc[M];
+            sweep(acc, false);
+            // res = sum_p omega_p v_p - (1 - W) rho;  rho += res + D^{-1} (G res).
+            // Every operator is factored and solved in one call (one barrier); the
+            // diffusion operator is factored again each iteration rather than held
+            // in registers across the pair loop (one factorisation per P solves).
+            double rl[M], d[M], f[M];
+            {
+                double b[M];
+#pragma unroll
+                for (int r = 0; r < M; ++r) {
+                    const int j = j0 + r;
+                    const bool in = j < N;
+                    rl[r] = in ? acc[r] - I.one_minus_W * rho[r * W + k] : 0.0;
+                    d[r] = in ? C[C_G * N1 + j] * rl[r] : 0.0;
+                    b[r] = in ? C[C_DD * N1 + j] : 1.0;
+                }
+                tri_factor_solve<W, M>(I.mu2, sLl, sLu, b, d, f, sh, ph);
+            }
+            double alpha, beta;
+            cheb_coeffs(Cs, A.accel, A.tol, alpha, beta);
+            double md = 0.0, mr = 0.0;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                if (j0 + r < N) {
+                    const int t = r * W + k;
+                    const double z = rl[r] + f[r];
+                    const double upd = alpha * (double)dch[r] + beta * z;
+                    dch[r] = (float)upd;
+                    const double nw = rho[t] + upd;
+                    rho[t] = nw;
+                    md = fmax(md, fabs(z));
+                    mr = fmax(mr, fabs(nw));
+                }
+            }
+            tile_max2<W>(md, mr, sh);
+            tsync<W>();                               // rho update visible to the tile
+            ++it;
+            const float qprev = Cs.q1, qprev2 = Cs.q2, qprev3 = Cs.q3;
+            const float q = (float)(mr > 0.0 ? md / mr : md);
+            cheb_record(Cs, q);
+            converged = pred_stop(md, mr, q, qprev, qprev2, qprev3, it, A.tol);
+            if (converged || it >= A.maxit) break;
+        }
+        {
+            double acc[M];
+            sweep(acc, true);                         // E* of the final iterate
+        }
     }
-    {
-        double acc[M];
-        sweep(acc, true);                         // E* of the final iterate
-    }
-    for (int j = k; j < N; j += W) rp[j] = rho[bpos(j, W, M)];   // next step's starting iterate
+    for (int j = k; j < N; j += W) rp[j] = rho[lpos(j)];   // next step's starting iterate
     tsync<W>();                                   // E* visible to the tile
     if (k == 0) {
         st[0] = it;
@@ -534,36 +697,68 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     tsync<W>();
     b_rhs<W, M, F32>(I, C, N1, S, mu, bL, bR, Rt);
     for (int j = k; j < NP; j += W) {
-        const int t = bpos(j, W, M);
+        const int t = lpos(j);
         const bool in = j < N;
         sLl[t] = in ? C[C_LL * N1 + j] : 0.0;
         sLu[t] = in ? C[C_LU * N1 + j] : 0.0;
+        if constexpr (WG) slam[t] = in ? C[C_LAM * N1 + j] : 1.0;
     }
-#pragma unroll
-    for (int r = 0; r < M; ++r) lam[r] = (j0 + r < N) ? C[C_LAM * N1 + j0 + r] : 1.0;
     tsync<W>();
     const double cb0 = C[C_BD * N1 + 0], cbN = C[C_BD * N1 + N - 1];
-    for (int p = 0; p < P; ++p) {
-        const double m1 = mu[p], m2 = m1 * m1;
-        const double *rp = Rt + (size_t)p * NP;
-        double b[M], d[M], x[M];
+    if constexpr (WG) {
+        // wavefront w solves pairs w, w + 4, ... alone; E*, no longer needed, takes E^{n+1}
+        const int w = threadIdx.x >> 6;
+        auto load_r = [&](int p, double (&v)[LM]) {   // padding rows hold zeros
+            const double *src = Rt + (size_t)p * NP + opaque(threadIdx.x & 63) * LM;
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            const int j = j0 + r;
-            const int t = r * W + k;
-            if (j < N) {
-                const double bdj = (j == 0 ? cb0 : 0.0) + (j == N - 1 ? cbN : 0.0);
-                b[r] = lam[r] + m2 * (-(sLl[t] + sLu[t])) + m1 * bdj;
-                d[r] = rp[j];
-            } else {
-                b[r] = 1.0;
-                d[r] = 0.0;
-            }
+            for (int r = 0; r < LM; ++r) v[r] = src[r];
+        };
+        double rnext[LM];
+        if (w < P) load_r(w, rnext);
+        for (int p = w; p < P; p += 4) {
+            const double m1 = mu[p], m2 = m1 * m1;
+            double x[LM];
+#pragma unroll
+            for (int r = 0; r < LM; ++r) x[r] = rnext[r];
+            if (p + 4 < P) load_r(p + 4, rnext);
+            const int lq = opaque(threadIdx.x & 63), jq = lq * LM, rl1 = N - 1 - jq;
+            const double *ll = sLl + lq, *lu = sLu + lq, *la = slam + lq;
+            const double c0 = jq == 0 ? cb0 : 0.0;
+            auto bdc = [&](int r) { return (r == 0 ? c0 : 0.0) + (r == rl1 ? cbN : 0.0); };
+            lane_chunk_solve<LM>(
+                [&](int r) { return m2 * ll[r * 64]; },
+                [&](int r) { return la[r * 64] + m2 * (-(ll[r * 64] + lu[r * 64])) + m1 * bdc(r); },
+                [&](int r) { return m2 * lu[r * 64]; }, x);
+            double *ep = Et + (size_t)p * NP + jq;
+#pragma unroll
+            for (int r = 0; r < LM; ++r) ep[r] = x[r];
         }
-        tri_factor_solve<W, M>(m2, sLl, sLu, b, d, x, sh, ph);
-        double *ep = Et + (size_t)p * NP;   // E*, no longer needed, takes E^{n+1}
+    } else {
+        double lam[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) ep[j0 + r] = x[r];
+        for (int r = 0; r < M; ++r) lam[r] = (j0 + r < N) ? C[C_LAM * N1 + j0 + r] : 1.0;
+        for (int p = 0; p < P; ++p) {
+            const double m1 = mu[p], m2 = m1 * m1;
+            const double *rp = Rt + (size_t)p * NP;
+            double b[M], d[M], x[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                const int j = j0 + r;
+                const int t = r * W + k;
+                if (j < N) {
+                    const double bdj = (j == 0 ? cb0 : 0.0) + (j == N - 1 ? cbN : 0.0);
+                    b[r] = lam[r] + m2 * (-(sLl[t] + sLu[t])) + m1 * bdj;
+                    d[r] = rp[j];
+                } else {
+                    b[r] = 1.0;
+                    d[r] = 0.0;
+                }
+            }
+            tri_factor_solve<W, M>(m2, sLl, sLu, b, d, x, sh, ph);
+            double *ep = Et + (size_t)p * NP;   // E*, no longer needed, takes E^{n+1}
+#pragma unroll
+            for (int r = 0; r < M; ++r) ep[j0 + r] = x[r];
+        }
     }
     tsync<W>();
 
@@ -624,7 +819,8 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         eb += I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
         ea += I.dx * (r1 / I.c + I.cv * t1);
     }
-    tile_sum2<W>(eb, ea, sh);
+    if constexpr (WG) tile_sum2_at<W>(eb, ea, red);
+    else tile_sum2<W>(eb, ea, sh);
     if (k == 0) {
         const double fdt = I.dt * (C[C_FLUX * N1 + 1] - C[C_FLUX * N1]);
         double *en = A.ienergy + 4 * (size_t)i;
@@ -1010,8 +1206,12 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
     if (st == GRTE_OK) st = balloc(b, &b->rprev, oT);
     if (st == GRTE_OK) st = balloc(b, &b->d_energy, (size_t)4 * n);
     if (st == GRTE_OK) st = balloc(b, &b->d_sticky, 1);
+    // the pair scratch is cleared once: its padding rows (N..NP-1 of every pair)
+    // are never written with anything but zeros, which the work-group tiles'
+    // solves read as decoupled rows with a zero right-hand side
     if (st == GRTE_OK && (hipMemset(b->d_sticky, 0, sizeof(int)) != hipSuccess ||
-                          hipMemset(b->d_energy, 0, (size_t)4 * n * sizeof(double)) != hipSuccess))
+                          hipMemset(b->d_energy, 0, (size_t)4 * n * sizeof(double)) != hipSuccess ||
+                          hipMemset(b->pairs, 0, (size_t)oR * sizeof(double)) != hipSuccess))
         st = GRTE_E_HIP;
     if (st != GRTE_OK) { grte_batch_destroy(b); return st; }
     if (hipFuncSetAttribute((const void *)batch_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,

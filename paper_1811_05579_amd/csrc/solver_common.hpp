@@ -411,6 +411,121 @@ __device__ __forceinline__ void tri_factor_solve(double s, const double *Lo, con
     }
 }
 
+// -------------------------------------------------------------------------
+// wavefront solver with many rows per lane and O(M) registers
+// -------------------------------------------------------------------------
+// One wavefront solves a tridiagonal system of 64 M rows on its own (row
+// j = lane M + i of the lane's chunk i = 0..M-1, LDS position i * 64 + lane),
+// so the four wavefronts of a work-group can take four different systems at
+// once: four dependent elimination chains in flight per work-group instead of
+// the one a work-group-wide solve gives.  The interior rows 0..M-2 of a chunk
+// are eliminated twice, top-down (LU: the pivots are kept for the final
+// substitution; the last interior row's responses to the right-hand side and
+// to the two separators) and bottom-up (UL: the first interior row's
+// responses), two recurrences independent of each other; the separators (row
+// M-1 of every lane) then form a 64-row tridiagonal system, solved by parallel
+// cyclic reduction over lane shuffles with the right-hand side carried along;
+// a last top-down substitution with the separators known gives the interior
+// rows.  a(i), b(i), c(i) return the sub-, main and super-diagonal of the
+// lane's row i (a = 0 in row 0 of the system, c = 0 in its last row); x holds
+// the right-hand side on entry and the solution on return.  Reciprocals are
+// v_rcp_f64 refined by two Newton steps, within about an ulp of the quotient
+// (the pivots of these diagonally dominant systems are finite, normal, and
+// far from zero).
+
+constexpr int LCS_WIN = 4;       // rows of coefficient loads in flight ahead of a recurrence
+constexpr int LCS_IL_MAX = 16;   // chunks up to this size run their two recurrences interleaved
+
+__device__ __forceinline__ double rcp64(double v)
+{
+    double r = __builtin_amdgcn_rcp(v);
+    double e = fma(-v, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-v, r, 1.0);
+    return fma(r, e, r);
+}
+
+template <int M, class GA, class GB, class GC>
+__device__ __forceinline__ void lane_chunk_solve(GA a, GB b, GC c, double (&x)[M])
+{
+    static_assert(M >= 2, "at least two rows per lane");
+    double inv[M - 1];
+    double yf = 0.0, qf = 0.0, cp = 0.0;       // LU: y and the response to the left separator
+    double ei = rcp64(b(M - 2)), w = x[M - 2], pr = 1.0;   // UL: 1/e, w, prod(-c_i / e_{i+1})
+    auto lu_row = [&](int i) {
+        const double ai = a(i);
+        inv[i] = rcp64(i > 0 ? b(i) - ai * cp : b(i));
+        yf = (i > 0 ? x[i] - ai * yf : x[i]) * inv[i];
+        qf = (i > 0 ? -ai * qf : -ai) * inv[i];
+        cp = c(i) * inv[i];
+    };
+    auto ul_row = [&](int i) {
+        const double f = c(i) * ei;
+        w = x[i] - f * w;
+        pr *= -f;
+        ei = rcp64(b(i) - f * a(i + 1));
+    };
+    if constexpr (M <= LCS_IL_MAX) {
+        // the two recurrences interleaved (two chains in flight); the
+        // coefficient loads may run at most LCS_WIN rows ahead (registers)
+#pragma unroll
+        for (int s = 0; s < M - 1; ++s) {
+            lu_row(s);
+            if (s < M - 2) ul_row(M - 3 - s);
+            if (s % LCS_WIN == LCS_WIN - 1) __asm__ volatile("" ::: "memory");
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < M - 1; ++s) {
+            lu_row(s);
+            if (s % LCS_WIN == LCS_WIN - 1) __asm__ volatile("" ::: "memory");
+        }
+#pragma unroll
+        for (int s = 0; s < M - 2; ++s) {
+            ul_row(M - 3 - s);
+            if (s % LCS_WIN == LCS_WIN - 1) __asm__ volatile("" ::: "memory");
+        }
+    }
+    // Chunk k's interior rows in terms of the separators z_{k-1} (left) and z_k:
+    //   x_0 = W0 + A0 z_{k-1} + C0 z_k,  x_{M-2} = yf + qf z_{k-1} + Dk z_k.
+    __asm__ volatile("" ::: "memory");
+    const double cm2 = c(M - 2);
+    const double W0 = w * ei, A0 = -a(0) * ei, C0 = -cm2 * pr * ei;
+    const double Dk = -cm2 * inv[M - 2];
+    const double W0n = wave_nb(W0, 1, 0.0), A0n = wave_nb(A0, 1, 0.0), C0n = wave_nb(C0, 1, 0.0);
+    const double as = a(M - 1), cs = c(M - 1);
+    double PA = as * qf, PB = b(M - 1) + as * Dk + cs * A0n, PC = cs * C0n;
+    double PD = x[M - 1] - as * yf - cs * W0n;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const int st = 1 << l;
+        const double Am = wave_nb(PA, -st, 0.0), Bm = wave_nb(PB, -st, 1.0), Cm = wave_nb(PC, -st, 0.0),
+                     Dm = wave_nb(PD, -st, 0.0);
+        const double Ap = wave_nb(PA, st, 0.0), Bp = wave_nb(PB, st, 1.0), Cp = wave_nb(PC, st, 0.0),
+                     Dp = wave_nb(PD, st, 0.0);
+        const double k1 = PA * rcp64(Bm), k2 = PC * rcp64(Bp);
+        PA = -Am * k1;
+        PC = -Cp * k2;
+        PB = PB - Cm * k1 - Ap * k2;
+        PD = PD - Dm * k1 - Dp * k2;
+    }
+    const double z = PD * rcp64(PB);
+    const double zl = wave_nb(z, -1, 0.0);
+    // (the compiler barriers make the coefficients be re-read from LDS rather
+    // than kept live in registers across the phases)
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < M - 1; ++i) {
+        double di = x[i];
+        if (i == 0) di -= a(0) * zl;
+        if (i == M - 2) di -= cm2 * z;
+        x[i] = (i > 0 ? di - a(i) * x[i - 1] : di) * inv[i];
+    }
+#pragma unroll
+    for (int i = M - 3; i >= 0; --i) x[i] -= c(i) * inv[i] * x[i + 1];
+    x[M - 1] = z;
+}
+
 // max over the tile of two values at once (fixed order; same result in every tile thread)
 template <int W>
 __device__ __forceinline__ void tile_max2(double &a, double &b, double *sh)
@@ -441,9 +556,9 @@ __device__ __forceinline__ void tile_max2(double &a, double &b, double *sh)
 
 // sum over the tile of two values at once (fixed order: a butterfly within
 // each wavefront, then the wavefronts' sums in wave order; result in every
-// tile thread)
+// tile thread), exchanging through the 16 doubles at m2 (work-group tiles)
 template <int W>
-__device__ __forceinline__ void tile_sum2(double &a, double &b, double *sh)
+__device__ __forceinline__ void tile_sum2_at(double &a, double &b, double *m2)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -451,7 +566,6 @@ __device__ __forceinline__ void tile_sum2(double &a, double &b, double *sh)
         b += __shfl_xor(b, o, 64);
     }
     if constexpr (W == 256) {
-        double *m2 = sh + 14 * W;
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             m2[w] = a;
@@ -467,6 +581,13 @@ __device__ __forceinline__ void tile_sum2(double &a, double &b, double *sh)
         }
         __syncthreads();
     }
+}
+
+// the same with the 16-double exchange area at sh + 14 W (the solver scratch)
+template <int W>
+__device__ __forceinline__ void tile_sum2(double &a, double &b, double *sh)
+{
+    tile_sum2_at<W>(a, b, sh + 14 * W);
 }
 
 // block-wide max of a non-negative value (fixed order; result in every thread)
