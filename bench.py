@@ -58,7 +58,7 @@ TRAFFIC = {
     ("config2", "fp64"): (9.2663e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
     ("config2", "fp32"): (None, None),
     ("config4", "fp64"): (None, None),
-    ("config4", "fp32"): (None, None),
+    ("config4", "fp32"): (1.8512e10, "profiles/batch_kernel_config4_hbm_traffic.txt"),
     ("config3", "fp64"): (3.417e8, "profiles/apply2d_config3_hbm_traffic.txt"),
     ("config3", "fp32"): (3.417e8, "profiles/apply2d_config3_hbm_traffic.txt"),   # Krylov vectors are binary64 either way
     ("config5", "fp64"): (1.767e8, "profiles/apply2d_config5_hbm_traffic.txt"),
