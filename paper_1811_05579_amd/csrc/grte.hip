@@ -680,7 +680,7 @@ __global__ void __launch_bounds__(NT) corr_kernel(Group<CorrArgs> G)
 //   fluxes (the correction's moment equation uses D from O*), and the defect
 //   E_tot^{n+1} - E_tot^n + outflow.
 // Binary64 sums in a fixed order: a tree over each block's cells, per-block
-// partials, and the last block to finish sums the partials by index.
+// partials, and a one-block-per-context kernel that sums the partials by index.
 // -------------------------------------------------------------------------
 struct ProjArgs {
     int N, P, keep, cpb;
@@ -694,20 +694,18 @@ struct ProjArgs {
     double dx, c, cv, dt;
     const double *Tn, *Tnew, *rho_n, *obnd;
     double *epart;          // 2 per block
-    unsigned *ecnt;         // blocks done (reset to 0 by the last one)
     double *energy;         // E_before, E_after, outflow dt, defect
     int *stat;              // per-step counters; the sticky word collects their error flags
 };
 
-// Fixed-order binary64 sums of e0 and e1 over the nb blocks of a launch (blocks
-// 0..nb-1 of blockIdx.y's context): a tree over each block, per-block partials,
-// and the last block to finish sums the partials by index.  Called by every
-// thread of a block; true in every thread of the last block, which receives the
-// totals (and resets the counter for the next launch).
-__device__ bool energy_reduce(double e0, double e1, int nb, double *epart, unsigned *ecnt, double &E0, double &E1)
+// Energy balance, first level: the block's sum of e0 and e1 (fixed order, a
+// tree in LDS) written to epart[2 b], epart[2 b + 1].  The sums over the
+// blocks are formed by the next kernel on the stream (energy_final_kernel),
+// whose launch makes every block's partials visible without a device-scope
+// fence per block (on this chip such a fence writes back the XCD's L2).
+__device__ void energy_partial(double e0, double e1, double *epart)
 {
     __shared__ double s_e0[256], s_e1[256];
-    __shared__ int s_last;
     const int t = threadIdx.x;
     s_e0[t] = e0;
     s_e1[t] = e1;
@@ -722,18 +720,20 @@ __device__ bool energy_reduce(double e0, double e1, int nb, double *epart, unsig
     if (t == 0) {
         epart[2 * blockIdx.x] = s_e0[0];
         epart[2 * blockIdx.x + 1] = s_e1[0];
-        __threadfence();                         // partial visible device-wide before the count
-        s_last = atomicAdd(ecnt, 1u) == (unsigned)(nb - 1);
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();                             // every block's partial is in memory
+}
+
+// Second level: the nb partials of one context summed in a fixed order (each
+// thread its strided share, then a tree), result in every thread's E0, E1.
+__device__ void energy_total(const double *epart, int nb, double &E0, double &E1)
+{
+    __shared__ double s_e0[256], s_e1[256];
+    const int t = threadIdx.x;
     double a0 = 0.0, a1 = 0.0;
     for (int b = t; b < nb; b += 256) {
-        a0 += __hip_atomic_load(&epart[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a1 += __hip_atomic_load(&epart[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a0 += epart[2 * b];
+        a1 += epart[2 * b + 1];
     }
-    __syncthreads();                             // s_e0/s_e1 reused
     s_e0[t] = a0;
     s_e1[t] = a1;
     __syncthreads();
@@ -746,8 +746,6 @@ __device__ bool energy_reduce(double e0, double e1, int nb, double *epart, unsig
     }
     E0 = s_e0[0];
     E1 = s_e1[0];
-    if (t == 0) *ecnt = 0u;
-    return true;
 }
 
 __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
@@ -788,9 +786,19 @@ __global__ void __launch_bounds__(256) project_kernel(Group<ProjArgs> G)
         e0 = A.dx * (A.rho_n[jc] / A.c + A.cv * A.Tn[jc]);
         e1 = A.dx * (s / A.c + A.cv * A.Tnew[jc]);
     }
+    energy_partial(e0, e1, A.epart);
+}
+
+// the energy balance of each context (one block per context) and the step's
+// error flags, after project_kernel
+__global__ void __launch_bounds__(256) energy_final_kernel(Group<ProjArgs> G)
+{
+    const ProjArgs A = G.a[blockIdx.x];
+    const int nb = (A.N + A.cpb - 1) / A.cpb;
     double eb, ea;
-    if (!energy_reduce(e0, e1, nb, A.epart, A.ecnt, eb, ea)) return;
-    if (t == 0) {
+    energy_total(A.epart, nb, eb, ea);
+    if (threadIdx.x == 0) {
+        const int P = A.P;
         double fl = 0.0;
         for (int q = 0; q < P; ++q) fl += A.omega[q] * A.mu[q] * (A.obnd[P + q] - A.obnd[q]);
         const double fdt = A.dt * fl;
@@ -834,7 +842,6 @@ struct AltArgs {
     double *Enew, *Onew, *Tnew, *rho_out;
     const double *rho_n;
     double *epart, *energy;
-    unsigned *ecnt;
     int *stat;
 };
 
@@ -969,10 +976,18 @@ __global__ void __launch_bounds__(256) alt_project_kernel(Group<AltArgs> G)
         A.rho_out[c0 + t] = r1;
         e1 = A.dx * (r1 / A.c + A.cv * s_T[t]);
     }
+    energy_partial(e0, e1, A.epart);
+}
+
+// the energy balance of each context after alt_project_kernel (one block per context)
+__global__ void __launch_bounds__(256) alt_energy_final_kernel(Group<AltArgs> G)
+{
+    const AltArgs A = G.a[blockIdx.x];
+    const int N = A.N, P = A.P;
+    const int nb = (N + A.cpb - 1) / A.cpb;
     double eb, ea;
-    const bool last = energy_reduce(e0, e1, nb, A.epart, A.ecnt, eb, ea);
-    if (!last) return;
-    if (t == 0) {
+    energy_total(A.epart, nb, eb, ea);
+    if (threadIdx.x == 0) {
         // the outflow of the fluxes the alternative's moment equation uses: O_J
         // at the two end nodes (formed again here from the inputs)
         double fl = 0.0;
@@ -1131,9 +1146,8 @@ struct grte_ctx {
     size_t pred_lds = 0;
     int *stat = nullptr;
     // energy balance of the last step (projection kernel): O* at the end nodes,
-    // per-block partial sums, the blocks-done counter, and the four results
+    // per-block partial sums, and the four results
     double *obnd = nullptr, *epart = nullptr, *energy = nullptr;
-    unsigned *ecnt = nullptr;
     // optional stage timing: event pairs recorded on the context stream
     int profiling = 0;            // 0 off, k: time every k-th step
     long long prof_count = 0;     // steps since profiling was set
@@ -1413,9 +1427,6 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     if (st == GRTE_OK) st = alloc(ctx, &ctx->obnd, 2 * P);
     if (st == GRTE_OK) st = alloc(ctx, &ctx->epart, 2 * N);   // 2 per cell block (at most N blocks)
     if (st == GRTE_OK) st = alloc(ctx, &ctx->energy, 4);
-    double *cntmem = nullptr;
-    if (st == GRTE_OK) st = alloc(ctx, &cntmem, 1);
-    ctx->ecnt = (unsigned *)cntmem;
     if (st != GRTE_OK) { grte_destroy(ctx); return st; }
 
     // co-resident blocks for the cooperative prediction kernel
@@ -1454,7 +1465,6 @@ grte_status grte_create(const grte_problem *pb, const double *mu, const double *
     hipLaunchKernelGGL(fill_kernel, dim3((P + b - 1) / b), dim3(b), 0, nullptr, ctx->bR, P, 0.0);
     hipLaunchKernelGGL(fill_kernel, dim3((MAX_P * BAR_STRIDE + b - 1) / b), dim3(b), 0, nullptr, flagmem,
                        (size_t)MAX_P * BAR_STRIDE, 0.0);   // all-zero bits: generation 0
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(b), 0, nullptr, cntmem, 1, 0.0);        // counter 0
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(b), 0, nullptr, ctx->energy, 4, 0.0);
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, nullptr, ctx->stat, NSTAT, 0);
     // padded rows of the position-ordered arrays stay zero
@@ -1662,7 +1672,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         aa.Os = ctx->ostar; aa.Us = ctx->ustar;
         aa.Ll = ctx->Ll; aa.Lu = ctx->Lu; aa.Lam = ctx->Lam; aa.Bd = ctx->Bd; aa.r = ctx->r;
         aa.EJ = ctx->part; aa.Enew = ctx->E2; aa.Onew = ctx->O2; aa.Tnew = ctx->T2; aa.rho_out = ctx->rho1;
-        aa.rho_n = ctx->rho_n; aa.epart = ctx->epart; aa.energy = ctx->energy; aa.ecnt = ctx->ecnt;
+        aa.rho_n = ctx->rho_n; aa.epart = ctx->epart; aa.energy = ctx->energy;
         aa.stat = ctx->stat;
         na.gw = ctx->guess_w; na.gnorm = ctx->guess_norm; na.gtol = ctx->guess_tol;
         na.O32 = ctx->O32; na.f32 = ctx->f32;
@@ -1683,7 +1693,7 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
         pj.O32 = ctx->O32; pj.O32out = ctx->O32b; pj.f32 = ctx->f32;
         pj.dx = dx; pj.c = ctx->c; pj.cv = ctx->cv; pj.dt = dt;
         pj.Tn = ctx->T; pj.Tnew = ctx->T2; pj.rho_n = ctx->rho_n; pj.obnd = ctx->obnd;
-        pj.epart = ctx->epart; pj.ecnt = ctx->ecnt; pj.energy = ctx->energy; pj.stat = ctx->stat;
+        pj.epart = ctx->epart; pj.energy = ctx->energy; pj.stat = ctx->stat;
     }
     gp.first[n] = grid;
     if (grid > c0->coop_capacity) return GRTE_E_UNSUPPORTED;
@@ -1727,8 +1737,15 @@ grte_status step_group(grte_ctx *const *ctxs, int n, const double *dts, const do
     default: st = launch_corr<16>(stream, gr, (int)maxP); break;
     }
     if (st != GRTE_OK) return st;
-    if (alt) hipLaunchKernelGGL(alt_project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, ga);
-    else hipLaunchKernelGGL(project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gj);
+    if (alt) {
+        hipLaunchKernelGGL(alt_project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, ga);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(alt_energy_final_kernel, dim3(n), dim3(256), 0, stream, ga);
+    } else {
+        hipLaunchKernelGGL(project_kernel, dim3(ncb_max, n), dim3(256), 0, stream, gj);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(energy_final_kernel, dim3(n), dim3(256), 0, stream, gj);
+    }
     HIPCHK(hipGetLastError());
     if ((st = prof_end(c0, ev_step)) != GRTE_OK) return st;   // whole step
     for (int g = 0; g < n; ++g) {
