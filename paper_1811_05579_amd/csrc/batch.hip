@@ -939,6 +939,7 @@ struct grte_batch {
     int f32 = 0;
     double *sigma0 = nullptr, *mu = nullptr, *omega = nullptr, *bL = nullptr, *bR = nullptr;
     double *cells = nullptr, *pairs = nullptr;
+    long long pairs_doubles = 0;               // size of the pair scratch
     double *rprev = nullptr;                   // per cell: the last prediction's rho*
     double *d_energy = nullptr;                // per instance: energy balance of the last step (4)
     int *d_sticky = nullptr;                   // error flags OR-ed over steps (GRTE_ERRF_*)
@@ -1008,6 +1009,12 @@ grte_status assign_tiles(grte_batch *b)
     b->h_order.insert(b->h_order.end(), wv.begin(), wv.end());
     b->n_wg = (int)wg.size();
     b->n_wave = (int)wv.size();
+    // The work-group tiles read the padding rows (N..NP-1) of every pair of the
+    // pair scratch as decoupled rows with a zero right-hand side; no step writes
+    // them, but a slab run by a wavefront tile uses a smaller pair stride whose
+    // rows fall into another layout's padding.  The scratch is cleared whenever
+    // the tiles are (re)assigned (never inside a captured step).
+    BCHK(hipMemsetAsync(b->pairs, 0, (size_t)b->pairs_doubles * sizeof(double), b->stream));
     BCHK(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->n * sizeof(BInst), hipMemcpyHostToDevice, b->stream));
     BCHK(hipMemcpyAsync(b->d_order, b->h_order.data(), b->n * sizeof(int), hipMemcpyHostToDevice, b->stream));
     BCHK(hipStreamSynchronize(b->stream));
@@ -1203,15 +1210,12 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
     if (st == GRTE_OK) st = balloc(b, &b->bR, oP);
     if (st == GRTE_OK) st = balloc(b, &b->cells, oC);
     if (st == GRTE_OK) st = balloc(b, &b->pairs, oR);
+    b->pairs_doubles = oR;
     if (st == GRTE_OK) st = balloc(b, &b->rprev, oT);
     if (st == GRTE_OK) st = balloc(b, &b->d_energy, (size_t)4 * n);
     if (st == GRTE_OK) st = balloc(b, &b->d_sticky, 1);
-    // the pair scratch is cleared once: its padding rows (N..NP-1 of every pair)
-    // are never written with anything but zeros, which the work-group tiles'
-    // solves read as decoupled rows with a zero right-hand side
     if (st == GRTE_OK && (hipMemset(b->d_sticky, 0, sizeof(int)) != hipSuccess ||
-                          hipMemset(b->d_energy, 0, (size_t)4 * n * sizeof(double)) != hipSuccess ||
-                          hipMemset(b->pairs, 0, (size_t)oR * sizeof(double)) != hipSuccess))
+                          hipMemset(b->d_energy, 0, (size_t)4 * n * sizeof(double)) != hipSuccess))
         st = GRTE_E_HIP;
     if (st != GRTE_OK) { grte_batch_destroy(b); return st; }
     if (hipFuncSetAttribute((const void *)batch_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,

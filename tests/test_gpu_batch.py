@@ -140,6 +140,32 @@ def test_graph_replay_equals_direct_launch():
     g.close()
 
 
+def test_tile_switch_leaves_no_stale_padding():
+    """A slab run by a wavefront tile writes its right-hand sides with a smaller
+    pair stride than a work-group tile, into rows that are padding in the
+    work-group layout, which the work-group solves read as zeros.  After the
+    tiles are reassigned, a step must equal, bit for bit, the step of a batch
+    that never used wavefront tiles, from the same state."""
+    ens = _mix(seed0=300)
+    pk = ens.packed()
+    a = _batch(ens)
+    grid = a.get_tuning()["grid"]
+    a.set_tuning(wave_max_n=256, grid=grid)
+    a.step()
+    a.set_tuning(wave_max_n=0, grid=grid)
+    a.set_state(pk["E"], pk["O"], pk["T"])
+    st_a, inf_a = a.step(info=True)
+    b = _batch(ens)
+    b.set_tuning(wave_max_n=0, grid=grid)
+    st_b, inf_b = b.step(info=True)
+    assert st_a == 0 and st_b == 0
+    assert [i["pred_iters"] for i in inf_a] == [i["pred_iters"] for i in inf_b]
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+
+
 def test_tune_keeps_state_and_result():
     ens = _mix(seed0=200)
     ref = _batch(ens)
