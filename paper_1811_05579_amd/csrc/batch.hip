@@ -1,14 +1,18 @@
 // batch.hip -- batched form of the AP step: many independent 1-D slabs of
-// different size, ordinate count, eps, dt and opacity advanced by one
-// persistent launch per step (the grte_batch_* calls of include/grte.h).
+// different size, ordinate count, eps, dt and opacity advanced together, one
+// graph of eight launches per step (the grte_batch_* calls of include/grte.h):
+// the per-cell phases (coefficients and right-hand sides, moments and Newton,
+// the correction's right-hand sides, the projection) as flat kernels over all
+// cells, the two per-slab solves (prediction, correction) as persistent tile
+// kernels.
 //
-// Every instance is advanced by one "tile": a whole work-group (W = 256
-// threads) or, for small slabs, one wavefront (W = 64; four independent
-// instances per work-group).  In a work-group tile the per-cell phases use all
-// 256 threads, while the per-pair tridiagonal solves are split over its four
-// wavefronts (pairs p = w, w + 4, ... on wavefront w), each solving its pair
-// alone with 4 M rows per lane: four independent elimination chains in flight
-// per work-group.  Inside a tile the step is the algebra of the
+// In the solve kernels every instance is advanced by one "tile": a whole
+// work-group (W = 256 threads) or, for small slabs, one wavefront (W = 64; four
+// independent instances per work-group).  In a work-group tile the per-pair
+// tridiagonal solves are split over its four wavefronts (pairs p = w, w + 4,
+// ... on wavefront w), each solving its pair alone with 4 M rows per lane:
+// four independent elimination chains in flight per work-group.  The step is
+// the algebra of the
 // single-instance path (Algorithm 2 and Section 5 of Tang, Wang & Zhang):
 // the per-pair tridiagonal operators T_p = Lam + mu_p^2 L + mu_p B with U*
 // eliminated through (4.5c), the angular coupling of the prediction solved by
@@ -64,6 +68,7 @@ static_assert(4 * LDS_WAVE <= LDS_WG, "four wavefront tiles fit in the work-grou
 
 struct BInst {
     int N, P, m, W, M;                 // tile of W threads, M rows each
+    int cb0, ncb;                      // the instance's blocks of the per-cell kernels (cblk)
     int pad;
     double dx, a, c, cv, eps, dt;
     double one_minus_W, mu1, mu2;      // 1 - sum omega (exact), sum omega mu, sum omega mu^2
@@ -75,7 +80,10 @@ struct BatchArgs {
     int n_wg, n_wave;
     const BInst *inst;
     const int *order;                  // n_wg work-group instances, then n_wave wavefront instances
-    int *queue;                        // [0] work-group queue head, [1] wavefront queue head
+    int *queue;                        // per solve kernel: [0] work-group queue head, [1] wavefront queue head
+    const int2 *cblk;                  // blocks of the per-cell kernels: (instance, first cell)
+    double *epart;                     // 2 per block of the projection: the energy partial sums
+    int n_inst;
     const double *E, *O, *T, *sigma0;
     double *E2, *O2, *T2;
     // binary32 storage (f32 != 0): E^n = a c (T^n)^4 + E32, O^n = O32 in;
@@ -183,84 +191,334 @@ __device__ void b_cell(const BInst &I, int mode, const double *Tk, const double 
     }
 }
 
-// O at node i of pair p from cell values ec[] of that pair (cell order): the
-// node relation at interior nodes, the inflow relations (4.7) at the two ends
-template <class OT>
-__device__ __forceinline__ double node_pc(const double *ec, const OT *O, const double *Aw, const double *Bc,
-                                          double mu, double bl, double br, double eps, int N, int P, int i, int p)
-{
-    auto inner = [&](int ii) {
-        return Aw[ii] * (double)O[(size_t)ii * P + p] - Bc[ii] * mu * (ec[ii] - ec[ii - 1]);
-    };
-    if (i >= 1 && i <= N - 1) return inner(i);
-    if (i == 0) return 2.0 / eps * (bl - ec[0]) - inner(1);
-    return 2.0 / eps * (ec[N - 1] - br) - inner(N - 1);
-}
-
-// The state E^n, O^n of one instance: binary64 arrays, or the binary32
-// storage E32 = E^n - a c (T^n)^4, O32 = O^n (f32 != 0).
+// The state E^n, O^n of one instance: binary64 arrays in the caller's
+// cell-major layout (E[j P + p], O[i P + p]), or the binary32 storage
+// E32 = E^n - a c (T^n)^4, O32 = O^n (f32 != 0), kept pair-major
+// (E32[p N + j], O32[p (N + 1) + i]): the per-cell kernels take consecutive
+// cells on consecutive lanes, so their loads and stores of one pair are
+// contiguous (set_state / get_state transpose, batch_convert).
 template <bool F32>
 struct BState {
     static constexpr bool f32 = F32;
     const double *E, *O, *Tn;
     const float *E32, *O32;
     double ac;
-    int P;
-    __device__ __forceinline__ double e(int j, int idx) const
+    int P, N;
+    __device__ __forceinline__ size_t ei(int j, int p) const
     {
-        if constexpr (!F32) return E[idx];
-        const double t = Tn[j];
-        return ac * (t * t) * (t * t) + (double)E32[idx];
+        return F32 ? (size_t)p * N + j : (size_t)j * P + p;
     }
-    __device__ __forceinline__ double o(size_t idx) const
+    __device__ __forceinline__ size_t oi(int i, int p) const
     {
-        if constexpr (F32) return (double)O32[idx];
-        else return O[idx];
+        return F32 ? (size_t)p * (N + 1) + i : (size_t)i * P + p;
+    }
+    __device__ __forceinline__ double e(int j, int p) const
+    {
+        if constexpr (!F32) return E[ei(j, p)];
+        const double t = Tn[j];
+        return ac * (t * t) * (t * t) + (double)E32[ei(j, p)];
+    }
+    __device__ __forceinline__ double o(int i, int p) const
+    {
+        if constexpr (F32) return (double)O32[oi(i, p)];
+        else return O[oi(i, p)];
     }
 };
 
-// right-hand sides of the per-pair systems into Rt (pair-major, cell order).
-// A thread takes rows j = k, k + W, ... and, per row, the pairs in groups of
-// RHS_U: the group's state loads are all issued before its arithmetic, so a
-// thread keeps RHS_U memory round trips in flight (these loops are latency-
-// bound at one wavefront per SIMD), and the row's coefficients are read once.
+// O at node i of pair p from cell values ec[] of that pair (cell order) and
+// the stored O^n: the node relation at interior nodes, the inflow relations
+// (4.7) at the two ends
+template <bool F32>
+__device__ __forceinline__ double node_pc(const double *ec, const BState<F32> &S, const double *Aw,
+                                          const double *Bc, double mu, double bl, double br, double eps, int N,
+                                          int i, int p)
+{
+    auto inner = [&](int ii) { return Aw[ii] * S.o(ii, p) - Bc[ii] * mu * (ec[ii] - ec[ii - 1]); };
+    if (i >= 1 && i <= N - 1) return inner(i);
+    if (i == 0) return 2.0 / eps * (bl - ec[0]) - inner(1);
+    return 2.0 / eps * (ec[N - 1] - br) - inner(N - 1);
+}
+
+// The per-cell phases take the pairs of their cell in groups of RHS_U: the
+// group's state loads are all issued before its arithmetic (RHS_U memory round
+// trips in flight per thread), and the cell's coefficients are read once.
 constexpr int RHS_U = 4;
 
-template <int W, int M, bool F32>
-__device__ void b_rhs(const BInst &I, const double *C, int N1, const BState<F32> &S,
-                      const double *mu, const double *bL, const double *bR, double *Rt)
+// ---------------------------------------------------------------------------
+// The per-cell phases run as flat kernels over every cell of every slab (one
+// thread per cell, blocks of 256 cells of one slab, cblk): they stream the
+// state and the pair scratch, and at the occupancy of a small kernel many more
+// of their memory round trips are in flight than inside the solve kernels,
+// which hold one work-group per CU for their LDS and registers.
+
+// one instance's arrays, as the phases see them
+template <bool F32>
+struct IView {
+    BInst I;
+    int N, P, N1, NP;               // NP: pair stride of the pair scratch (the instance's tile, W M)
+    const double *Tn, *sg, *mu, *om, *bL, *bR;
+    double *T2, *C, *Rt, *Et;
+    int *st;
+    BState<F32> S;
+};
+
+template <bool F32>
+__device__ __forceinline__ IView<F32> iview(const BatchArgs &A, int i)
 {
-    constexpr int NP = W * M;
-    const int N = I.N, P = I.P;
-    const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
-    for (int j = k; j < N; j += W) {
-        const double h = C[C_H * N1 + j], keps = C[C_KEPS * N1 + j], src = C[C_SRC * N1 + j];
-        const double awr = C[C_AWR * N1 + j], awl = C[C_AWL * N1 + j];
-        const bool has_r = j <= N - 2, has_l = j >= 1;
-        for (int p0 = 0; p0 < P; p0 += RHS_U) {
-            double e[RHS_U], orr[RHS_U], ol[RHS_U];
+    IView<F32> V;
+    V.I = A.inst[i];
+    const BInst &I = V.I;
+    V.N = I.N;
+    V.P = I.P;
+    V.N1 = I.N + 1;
+    V.NP = I.W * I.M;
+    V.Tn = A.T + I.oT;
+    V.sg = A.sigma0 + I.oT;
+    V.mu = A.mu + I.oP;
+    V.om = A.omega + I.oP;
+    V.bL = A.bL + I.oP;
+    V.bR = A.bR + I.oP;
+    V.T2 = A.T2 + I.oT;
+    V.C = A.cells + I.oC;
+    V.Rt = A.pairs + I.oR;
+    V.Et = V.Rt + (size_t)I.P * I.NPa;
+    V.st = A.istat + 8 * i;
+    V.S.P = I.P;
+    V.S.N = I.N;
+    V.S.ac = I.a * I.c;
+    V.S.Tn = V.Tn;
+    V.S.E = F32 ? nullptr : A.E + I.oE;
+    V.S.O = F32 ? nullptr : A.O + I.oO;
+    V.S.E32 = F32 ? A.E32 + I.oE : nullptr;
+    V.S.O32 = F32 ? A.O32 + I.oO : nullptr;
+    return V;
+}
+
+// right-hand sides of cell j's per-pair systems into Rt (pair-major, cell order)
+template <bool F32>
+__device__ __forceinline__ void rhs_cell(const IView<F32> &V, int j)
+{
+    const BInst &I = V.I;
+    const int N = V.N, P = V.P, N1 = V.N1, NP = V.NP;
+    const double *C = V.C, *mu = V.mu, *bL = V.bL, *bR = V.bR;
+    double *Rt = V.Rt;
+    const BState<F32> &S = V.S;
+    const double h = C[C_H * N1 + j], keps = C[C_KEPS * N1 + j], src = C[C_SRC * N1 + j];
+    const double awr = C[C_AWR * N1 + j], awl = C[C_AWL * N1 + j];
+    const bool has_r = j <= N - 2, has_l = j >= 1;
+    for (int p0 = 0; p0 < P; p0 += RHS_U) {
+        double e[RHS_U], orr[RHS_U], ol[RHS_U];
 #pragma unroll
-            for (int u = 0; u < RHS_U; ++u) {
-                const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
-                e[u] = S.e(j, j * P + p);
-                orr[u] = has_r ? S.o((size_t)(j + 1) * P + p) : 0.0;
-                ol[u] = has_l ? S.o((size_t)j * P + p) : 0.0;
-            }
+        for (int u = 0; u < RHS_U; ++u) {
+            const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
+            e[u] = S.e(j, p);
+            orr[u] = has_r ? S.o(j + 1, p) : 0.0;
+            ol[u] = has_l ? S.o(j, p) : 0.0;
+        }
 #pragma unroll
-            for (int u = 0; u < RHS_U; ++u) {
-                const int p = p0 + u;
-                if (p >= P) break;
-                double rv = keps * e[u] + src - h * mu[p] * (awr * orr[u] - awl * ol[u]);
-                if (j == 0) rv += 2.0 * h * mu[p] * bL[p] / I.eps;
-                if (j == N - 1) rv += 2.0 * h * mu[p] * bR[p] / I.eps;
-                Rt[(size_t)p * NP + j] = rv;
-            }
+        for (int u = 0; u < RHS_U; ++u) {
+            const int p = p0 + u;
+            if (p >= P) break;
+            double rv = keps * e[u] + src - h * mu[p] * (awr * orr[u] - awl * ol[u]);
+            if (j == 0) rv += 2.0 * h * mu[p] * bL[p] / I.eps;
+            if (j == N - 1) rv += 2.0 * h * mu[p] * bR[p] / I.eps;
+            Rt[(size_t)p * NP + j] = rv;
         }
     }
 }
 
+// prediction set-up of cell j: coefficients (K from T^n), rho^n, the pairs'
+// right-hand sides
+template <bool F32>
+__device__ __forceinline__ void cell_pred_setup(const IView<F32> &V, int j)
+{
+    const BInst &I = V.I;
+    const int P = V.P, N1 = V.N1;
+    double *C = V.C;
+    b_cell(I, 0, V.Tn, V.Tn, V.sg, j, C, N1);
+    double rn = 0.0;
+#pragma unroll 4
+    for (int p = 0; p < P; ++p) rn += V.om[p] * V.S.e(j, p);
+    C[C_RHON * N1 + j] = rn;
+    rhs_cell(V, j);
+}
+
+// correction set-up of cell j: coefficients with K from T^{n+1}, right-hand sides
+template <bool F32>
+__device__ __forceinline__ void cell_corr_setup(const IView<F32> &V, int j)
+{
+    b_cell(V.I, 1, V.C + C_TNEW * V.N1, V.Tn, V.sg, j, V.C, V.N1);
+    rhs_cell(V, j);
+}
+
+// correction substep 1 of cell j: moments of E*, D from the prediction's node
+// fluxes, U*, K*, Newton on (4.13)/(5.5); step counters accumulated in the caller's
+template <bool F32>
+__device__ __forceinline__ void cell_newton(const BatchArgs &A, const IView<F32> &V, int j, int &n_its,
+                                            int &n_fail, int &n_clamp, int &n_neg)
+{
+    const BInst &I = V.I;
+    const int N = V.N, P = V.P, N1 = V.N1, NP = V.NP;
+    const double eps = I.eps;
+    const double *Tn = V.Tn, *sg = V.sg, *mu = V.mu, *om = V.om, *bL = V.bL, *bR = V.bR;
+    double *C = V.C, *T2 = V.T2;
+    const double *Et = V.Et;
+    const BState<F32> &S = V.S;
+    double rs = 0.0, D = 0.0, f0 = 0.0, fN = 0.0;
+    // O* at nodes j and j+1 from the node relation (inline for interior
+    // nodes) and the inflow relations (4.7) at the two ends (node_pc); the
+    // pairs in groups of RHS_U whose loads are issued first
+    const bool inner_l = j >= 1, inner_r = j + 1 <= N - 1;
+    const double awl = C[C_AW * N1 + j], bcl = C[C_BC * N1 + j];
+    const double awr = inner_r ? C[C_AW * N1 + j + 1] : 0.0, bcr = inner_r ? C[C_BC * N1 + j + 1] : 0.0;
+    for (int p0 = 0; p0 < P; p0 += RHS_U) {
+        double em[RHS_U], ej[RHS_U], ep1[RHS_U], onl[RHS_U], onr[RHS_U];
+#pragma unroll
+        for (int u = 0; u < RHS_U; ++u) {
+            const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
+            const double *ep = Et + (size_t)p * NP;
+            ej[u] = ep[j];
+            em[u] = inner_l ? ep[j - 1] : 0.0;
+            ep1[u] = inner_r ? ep[j + 1] : 0.0;
+            onl[u] = inner_l ? S.o(j, p) : 0.0;
+            onr[u] = inner_r ? S.o(j + 1, p) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RHS_U; ++u) {
+            const int p = p0 + u;
+            if (p >= P) break;
+            const double *ep = Et + (size_t)p * NP;
+            const double m1 = mu[p];
+            double ol, orr;
+            if (inner_l) {
+                ol = awl * onl[u] - bcl * m1 * (ej[u] - em[u]);
+            } else {
+                ol = node_pc(ep, S, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, j, p);
+            }
+            if (inner_r) {
+                orr = awr * onr[u] - bcr * m1 * (ep1[u] - ej[u]);
+            } else {
+                orr = node_pc(ep, S, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, j + 1, p);
+            }
+            rs += om[p] * ej[u];
+            D += om[p] * m1 * (orr - ol);
+            f0 += om[p] * m1 * ol;
+            fN += om[p] * m1 * orr;
+        }
+    }
+    if (j == 0) C[C_FLUX * N1] = f0;
+    if (j == N - 1) C[C_FLUX * N1 + 1] = fN;
+    D /= I.dx;
+    const double ac = I.a * I.c;
+    const double t = Tn[j];
+    const double Un = t * t * t * t;
+    const double beta = C[C_BETA * N1 + j];
+    const double us = (Un + beta * rs) / (1.0 + ac * beta);
+    C[C_USTAR * N1 + j] = us;
+    C[C_D * N1 + j] = D;
+    double Ks = 1.0;
+    if (I.m == 3) {
+        if (us < 0.0) {
+            Ks = 0.0;
+            ++n_clamp;
+        } else {
+            Ks = pow(us, 0.75);
+        }
+    }
+    const double s0 = sg[j];
+    const double lin = I.cv * (eps * eps * Ks + I.c * s0 * I.dt);
+    const double q4 = ac * s0 * I.dt;
+    const double rhs = s0 * I.dt * (C[C_RHON * N1 + j] - I.c * I.dt * D);
+    double T = t;
+    int its = 0;
+    if (!(s0 == 0.0 && Ks == 0.0)) {
+        if (t + rhs / lin < 0.0) ++n_neg;
+        bool ok = false;
+        // Newton from T^n, iterates clamped to the upper bound of the root
+        // (the smaller single-term root of q4 T^4 + lin T = rhs + lin T^n)
+        const double Cq = rhs + lin * t;
+        const double cap = (Cq > 0.0 && q4 > 0.0)
+                               ? fmin(sqrt(sqrt(Cq / q4)), Cq / lin) * (1.0 + 0x1p-50) : INFINITY;
+        for (its = 0; its < A.newton_maxit;) {
+            const double T2v = T * T;
+            const double g = q4 * T2v * T2v + lin * (T - t) - rhs;
+            const double dg = 4.0 * q4 * T2v * T + lin;
+            const double Tp = T;
+            T = fmin(T - g / dg, cap);
+            const double step = Tp - T;
+            ++its;
+            if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(t))) { ok = true; break; }
+        }
+        if (!ok) ++n_fail;
+    }
+    C[C_TNEW * N1 + j] = T;
+    T2[j] = T;
+    n_its = max(n_its, its);
+}
+
+// projection (4.14) of cell j: E^{n+1} and O^{n+1} (node relation with K^{n+1})
+// into the state, and cell j's terms of the energy balance ((3.12)-(3.13)):
+// E_tot = sum_j dx (rho_j / c + Cv T_j) before (eb) and after (ea) the step
+template <bool F32>
+__device__ __forceinline__ void cell_project(const BatchArgs &A, const IView<F32> &V, int j, double &eb,
+                                             double &ea)
+{
+    const BInst &I = V.I;
+    const int N = V.N, P = V.P, N1 = V.N1, NP = V.NP;
+    const double eps = I.eps;
+    const double *Tn = V.Tn, *mu = V.mu, *om = V.om, *bL = V.bL, *bR = V.bR;
+    const double *C = V.C, *T2 = V.T2, *Et = V.Et;
+    const BState<F32> &S = V.S;
+    const double *Aw = C + C_AW * N1, *Bc = C + C_BC * N1;
+    // the pairs in groups of RHS_U: the group's loads are issued before its
+    // stores (O at node j from the node relation, the interior case inline;
+    // the two end nodes by node_pc)
+    float *E32o = F32 ? A.E32o + I.oE : nullptr, *O32o = F32 ? A.O32o + I.oO : nullptr;
+    double *E2 = F32 ? nullptr : A.E2 + I.oE, *O2 = F32 ? nullptr : A.O2 + I.oO;
+    const double t1 = T2[j];
+    const double base = S.ac * (t1 * t1) * (t1 * t1);
+    const double awj = Aw[j], bcj = Bc[j];
+    double r1 = 0.0;
+    for (int p0 = 0; p0 < P; p0 += RHS_U) {
+        double ej[RHS_U], em[RHS_U], on[RHS_U];
+#pragma unroll
+        for (int u = 0; u < RHS_U; ++u) {
+            const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
+            const double *ep = Et + (size_t)p * NP;
+            ej[u] = ep[j];
+            em[u] = j >= 1 ? ep[j - 1] : 0.0;
+            on[u] = j >= 1 ? S.o(j, p) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RHS_U; ++u) {
+            const int p = p0 + u;
+            if (p >= P) break;
+            const double *ep = Et + (size_t)p * NP;
+            r1 += om[p] * ej[u];
+            double oj;
+            if (j >= 1) {
+                oj = awj * on[u] - bcj * mu[p] * (ej[u] - em[u]);
+            } else {
+                oj = node_pc(ep, S, Aw, Bc, mu[p], bL[p], bR[p], eps, N, 0, p);
+            }
+            // the new state in the layout of the stored one (S.ei, S.oi)
+            if constexpr (F32) {
+                E32o[S.ei(j, p)] = (float)(ej[u] - base);
+                O32o[S.oi(j, p)] = (float)oj;
+                if (j == N - 1) O32o[S.oi(N, p)] = (float)node_pc(ep, S, Aw, Bc, mu[p], bL[p], bR[p], eps, N, N, p);
+            } else {
+                E2[S.ei(j, p)] = ej[u];
+                O2[S.oi(j, p)] = oj;
+                if (j == N - 1) O2[S.oi(N, p)] = node_pc(ep, S, Aw, Bc, mu[p], bL[p], bR[p], eps, N, N, p);
+            }
+        }
+    }
+    eb = I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
+    ea = I.dx * (r1 / I.c + I.cv * t1);
+}
+
 template <int W, int M, bool F32>
-__device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *sm)
+__device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm)
 {
     constexpr int NP = W * M;
     const BInst I = A.inst[i];
@@ -271,6 +529,7 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     const double *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
     BState<F32> S;
     S.P = I.P;
+    S.N = I.N;
     S.ac = I.a * I.c;
     S.Tn = Tn;
     S.E = F32 ? nullptr : A.E + I.oE;
@@ -303,16 +562,6 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         red = sm + 9 * NP + NP / 2;
     }
 
-    // ---------------- coefficients of the prediction (K from T^n) and rho^n
-    for (int j = k; j < N; j += W) {
-        b_cell(I, 0, Tn, Tn, sg, j, C, N1);
-        double rn = 0.0;
-#pragma unroll 4
-        for (int p = 0; p < P; ++p) rn += om[p] * S.e(j, j * P + p);
-        C[C_RHON * N1 + j] = rn;
-    }
-    tsync<W>();
-    b_rhs<W, M, F32>(I, C, N1, S, mu, bL, bR, Rt);
     double *rp = A.rprev + I.oT;
     for (int j = k; j < NP; j += W) {
         const int t = lpos(j);
@@ -574,128 +823,43 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
         st[1] = converged;
     }
 
-    // ---------------- correction substep 1: moments, D, K*, Newton on (4.13)/(5.5)
-    int n_its = 0, n_fail = 0, n_clamp = 0, n_neg = 0;
-    for (int j = k; j < N; j += W) {
-        double rs = 0.0, D = 0.0, f0 = 0.0, fN = 0.0;
-        // O* at nodes j and j+1 from the node relation (inline for interior
-        // nodes) and the inflow relations (4.7) at the two ends (node_pc); the
-        // pairs in groups of RHS_U whose loads are issued first
-        const bool inner_l = j >= 1, inner_r = j + 1 <= N - 1;
-        const double awl = C[C_AW * N1 + j], bcl = C[C_BC * N1 + j];
-        const double awr = inner_r ? C[C_AW * N1 + j + 1] : 0.0, bcr = inner_r ? C[C_BC * N1 + j + 1] : 0.0;
-        for (int p0 = 0; p0 < P; p0 += RHS_U) {
-            double em[RHS_U], ej[RHS_U], ep1[RHS_U], onl[RHS_U], onr[RHS_U];
-#pragma unroll
-            for (int u = 0; u < RHS_U; ++u) {
-                const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
-                const double *ep = Et + (size_t)p * NP;
-                ej[u] = ep[j];
-                em[u] = inner_l ? ep[j - 1] : 0.0;
-                ep1[u] = inner_r ? ep[j + 1] : 0.0;
-                onl[u] = inner_l ? S.o((size_t)j * P + p) : 0.0;
-                onr[u] = inner_r ? S.o((size_t)(j + 1) * P + p) : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < RHS_U; ++u) {
-                const int p = p0 + u;
-                if (p >= P) break;
-                const double *ep = Et + (size_t)p * NP;
-                const double m1 = mu[p];
-                double ol, orr;
-                if (inner_l) {
-                    ol = awl * onl[u] - bcl * m1 * (ej[u] - em[u]);
-                } else if constexpr (F32) {
-                    ol = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
-                } else {
-                    ol = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j, p);
-                }
-                if (inner_r) {
-                    orr = awr * onr[u] - bcr * m1 * (ep1[u] - ej[u]);
-                } else if constexpr (F32) {
-                    orr = node_pc(ep, S.O32, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
-                } else {
-                    orr = node_pc(ep, S.O, C + C_AW * N1, C + C_BC * N1, m1, bL[p], bR[p], eps, N, P, j + 1, p);
-                }
-                rs += om[p] * ej[u];
-                D += om[p] * m1 * (orr - ol);
-                f0 += om[p] * m1 * ol;
-                fN += om[p] * m1 * orr;
-            }
-        }
-        if (j == 0) C[C_FLUX * N1] = f0;
-        if (j == N - 1) C[C_FLUX * N1 + 1] = fN;
-        D /= I.dx;
-        const double ac = I.a * I.c;
-        const double t = Tn[j];
-        const double Un = t * t * t * t;
-        const double beta = C[C_BETA * N1 + j];
-        const double us = (Un + beta * rs) / (1.0 + ac * beta);
-        C[C_USTAR * N1 + j] = us;
-        C[C_D * N1 + j] = D;
-        double Ks = 1.0;
-        if (I.m == 3) {
-            if (us < 0.0) {
-                Ks = 0.0;
-                ++n_clamp;
-            } else {
-                Ks = pow(us, 0.75);
-            }
-        }
-        const double s0 = sg[j];
-        const double lin = I.cv * (eps * eps * Ks + I.c * s0 * I.dt);
-        const double q4 = ac * s0 * I.dt;
-        const double rhs = s0 * I.dt * (C[C_RHON * N1 + j] - I.c * I.dt * D);
-        double T = t;
-        int its = 0;
-        if (!(s0 == 0.0 && Ks == 0.0)) {
-            if (t + rhs / lin < 0.0) ++n_neg;
-            bool ok = false;
-            // Newton from T^n, iterates clamped to the upper bound of the root
-            // (the smaller single-term root of q4 T^4 + lin T = rhs + lin T^n)
-            const double Cq = rhs + lin * t;
-            const double cap = (Cq > 0.0 && q4 > 0.0)
-                                   ? fmin(sqrt(sqrt(Cq / q4)), Cq / lin) * (1.0 + 0x1p-50) : INFINITY;
-            for (its = 0; its < A.newton_maxit;) {
-                const double T2v = T * T;
-                const double g = q4 * T2v * T2v + lin * (T - t) - rhs;
-                const double dg = 4.0 * q4 * T2v * T + lin;
-                const double Tp = T;
-                T = fmin(T - g / dg, cap);
-                const double step = Tp - T;
-                ++its;
-                if (fabs(step) <= 0x1p-50 * fmax(fabs(T), fabs(t))) { ok = true; break; }
-            }
-            if (!ok) ++n_fail;
-        }
-        C[C_TNEW * N1 + j] = T;
-        T2[j] = T;
-        n_its = max(n_its, its);
-    }
-    // one atomic per wavefront for the step counters
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        n_its = max(n_its, __shfl_xor(n_its, o, 64));
-        n_fail += __shfl_xor(n_fail, o, 64);
-        n_clamp += __shfl_xor(n_clamp, o, 64);
-        n_neg += __shfl_xor(n_neg, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&st[2], n_its);
-        if (n_fail) atomicAdd(&st[3], n_fail);
-        if (n_clamp) atomicAdd(&st[4], n_clamp);
-        if (n_neg) atomicAdd(&st[5], n_neg);
-        const int ef = (n_fail ? GRTE_ERRF_NEWTON : 0) | (n_neg ? GRTE_ERRF_NEGATIVE_ROOT : 0) |
-                       ((k == 0 && !converged) ? GRTE_ERRF_PRED_NOCONV : 0);
-        if (ef) atomicOr(A.sticky, ef);
-    }
-    tsync<W>();
+    if (k == 0 && !converged) atomicOr(A.sticky, GRTE_ERRF_PRED_NOCONV);
+}
 
-    // ---------------- correction substep 2 (K from T^{n+1}): E^{n+1} per pair
-    const double *Tnew = C + C_TNEW * N1;
-    for (int j = k; j < N; j += W) b_cell(I, 1, Tnew, Tn, sg, j, C, N1);
-    tsync<W>();
-    b_rhs<W, M, F32>(I, C, N1, S, mu, bL, bR, Rt);
+template <int W, int M, bool F32>
+__device__ __forceinline__ void corr_solve(const BatchArgs &A, int i, double *sm)
+{
+    constexpr int NP = W * M;
+    const BInst I = A.inst[i];
+    const int N = I.N, P = I.P, N1 = N + 1;
+    const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
+    const int j0 = k * M;
+    const double eps = I.eps;
+    const double *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
+    BState<F32> S;
+    S.P = I.P;
+    S.N = I.N;
+    S.ac = I.a * I.c;
+    S.Tn = Tn;
+    S.E = F32 ? nullptr : A.E + I.oE;
+    S.O = F32 ? nullptr : A.O + I.oO;
+    S.E32 = F32 ? A.E32 + I.oE : nullptr;
+    S.O32 = F32 ? A.O32 + I.oO : nullptr;
+    const double *mu = A.mu + I.oP, *om = A.omega + I.oP, *bL = A.bL + I.oP, *bR = A.bR + I.oP;
+    double *T2 = A.T2 + I.oT;
+    double *C = A.cells + I.oC;
+    // Per-pair global arrays are pair-major in cell order: thread k's rows
+    // j0 .. j0+M-1 are contiguous, so its loads and stores are wide and the
+    // later per-cell phases read along cells.
+    double *Rt = A.pairs + I.oR;                  // right-hand sides
+    double *Et = Rt + (size_t)P * I.NPa;          // E* (prediction), then E^{n+1} (correction)
+    int *st = A.istat + 8 * i;
+    constexpr bool WG = (W == BNT);
+    constexpr int LM = WG ? 4 * M : M;
+    auto lpos = [](int j) { return (j % LM) * 64 + j / LM; };
+    double *sLl = sm + NP, *sLu = sm + 2 * NP, *sh = sm + 3 * NP;
+    double *slam = WG ? sm + 3 * NP : nullptr;
+    int ph = 0;
     for (int j = k; j < NP; j += W) {
         const int t = lpos(j);
         const bool in = j < N;
@@ -762,133 +926,160 @@ __device__ __forceinline__ void run_instance(const BatchArgs &A, int i, double *
     }
     tsync<W>();
 
-    // ---------------- projection (4.14): E^{n+1} and O^{n+1} (node relation with K^{n+1})
-    // into the cell-major state; a thread takes cells, its lanes read along cells.
-    // With it, the energy balance ((3.12)-(3.13)): E_tot = sum_j dx (rho_j / c +
-    // Cv T_j) before and after, in a fixed order (each thread's cells in order,
-    // then the tile sum).
-    const double *Aw = C + C_AW * N1, *Bc = C + C_BC * N1;
-    double eb = 0.0, ea = 0.0;
-    // per row, the pairs in groups of RHS_U: the group's loads are issued before
-    // its stores (O at node j from the node relation, the interior case inline;
-    // the two end nodes by node_pc)
-    float *E32o = F32 ? A.E32o + I.oE : nullptr, *O32o = F32 ? A.O32o + I.oO : nullptr;
-    double *E2 = F32 ? nullptr : A.E2 + I.oE, *O2 = F32 ? nullptr : A.O2 + I.oO;
-    for (int j = k; j < N; j += W) {
-        const double t1 = T2[j];
-        const double base = S.ac * (t1 * t1) * (t1 * t1);
-        const double awj = Aw[j], bcj = Bc[j];
-        double r1 = 0.0;
-        for (int p0 = 0; p0 < P; p0 += RHS_U) {
-            double ej[RHS_U], em[RHS_U], on[RHS_U];
-#pragma unroll
-            for (int u = 0; u < RHS_U; ++u) {
-                const int p = p0 + u < P ? p0 + u : P - 1;   // tail: a valid index, result unused
-                const double *ep = Et + (size_t)p * NP;
-                ej[u] = ep[j];
-                em[u] = j >= 1 ? ep[j - 1] : 0.0;
-                on[u] = j >= 1 ? S.o((size_t)j * P + p) : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < RHS_U; ++u) {
-                const int p = p0 + u;
-                if (p >= P) break;
-                const double *ep = Et + (size_t)p * NP;
-                r1 += om[p] * ej[u];
-                double oj;
-                if (j >= 1) {
-                    oj = awj * on[u] - bcj * mu[p] * (ej[u] - em[u]);
-                } else {
-                    if constexpr (F32) oj = node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, 0, p);
-                    else oj = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, 0, p);
-                }
-                if constexpr (F32) {
-                    E32o[(size_t)j * P + p] = (float)(ej[u] - base);
-                    O32o[(size_t)j * P + p] = (float)oj;
-                    if (j == N - 1)
-                        O32o[(size_t)N * P + p] =
-                            (float)node_pc(ep, S.O32, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
-                } else {
-                    E2[(size_t)j * P + p] = ej[u];
-                    O2[(size_t)j * P + p] = oj;
-                    if (j == N - 1)
-                        O2[(size_t)N * P + p] = node_pc(ep, S.O, Aw, Bc, mu[p], bL[p], bR[p], eps, N, P, N, p);
-                }
-            }
-        }
-        eb += I.dx * (C[C_RHON * N1 + j] / I.c + I.cv * Tn[j]);
-        ea += I.dx * (r1 / I.c + I.cv * t1);
-    }
-    if constexpr (WG) tile_sum2_at<W>(eb, ea, red);
-    else tile_sum2<W>(eb, ea, sh);
-    if (k == 0) {
-        const double fdt = I.dt * (C[C_FLUX * N1 + 1] - C[C_FLUX * N1]);
-        double *en = A.ienergy + 4 * (size_t)i;
-        en[0] = eb;
-        en[1] = ea;
-        en[2] = fdt;
-        en[3] = (ea - eb) + fdt;
-    }
-    tsync<W>();
 }
 
 // binary64 state <-> binary32 storage of every instance (one block per
-// instance): E32 = E - a c T^4, O32 = O (to32), or back
+// instance): E32 = E - a c T^4, O32 = O (to32), or back; the binary32 arrays
+// are pair-major (see BState)
 __global__ void __launch_bounds__(256) batch_convert(const BInst *inst, const double *T, double *E, double *O,
                                                     float *E32, float *O32, int to32)
 {
     const BInst I = inst[blockIdx.x];
-    const int ne = I.N * I.P, no = (I.N + 1) * I.P;     // per instance: well below 2^31
+    const int N = I.N, P = I.P;
+    const int ne = N * P, no = (N + 1) * P;     // per instance: well below 2^31
     const double ac = I.a * I.c;
+    // t runs over the binary64 (cell-major) index j P + p; the binary32 state is
+    // pair-major, p N + j (cells) and p (N + 1) + i (nodes)
     for (int t = threadIdx.x; t < ne; t += blockDim.x) {
-        const double tj = T[I.oT + t / I.P];
+        const int j = t / P, p = t - j * P;
+        const double tj = T[I.oT + j];
         const double base = ac * (tj * tj) * (tj * tj);
-        if (to32) E32[I.oE + t] = (float)(E[I.oE + t] - base);
-        else E[I.oE + t] = base + (double)E32[I.oE + t];
+        const size_t q = I.oE + (size_t)p * N + j;
+        if (to32) E32[q] = (float)(E[I.oE + t] - base);
+        else E[I.oE + t] = base + (double)E32[q];
     }
     for (int t = threadIdx.x; t < no; t += blockDim.x) {
-        if (to32) O32[I.oO + t] = (float)O[I.oO + t];
-        else O[I.oO + t] = (double)O32[I.oO + t];
+        const int i = t / P, p = t - i * P;
+        const size_t q = I.oO + (size_t)p * (N + 1) + i;
+        if (to32) O32[q] = (float)O[I.oO + t];
+        else O[I.oO + t] = (double)O32[q];
     }
 }
 
-template <bool F32>
-__global__ void __launch_bounds__(BNT) batch_kernel(BatchArgs A)
+
+// The step's kernels, in stream order (one graph per state-buffer parity):
+//   batch_reset, cells_kernel<CP_PRED>, solve_kernel<0>, cells_kernel<CP_NEWTON>,
+//   cells_kernel<CP_CORR>, solve_kernel<1>, cells_kernel<CP_PROJECT>, batch_energy.
+enum { CP_PRED = 0, CP_NEWTON = 1, CP_CORR = 2, CP_PROJECT = 3 };
+
+template <int PH, bool F32>
+__global__ void __launch_bounds__(256) cells_kernel(BatchArgs A)
+{
+    const int2 cb = A.cblk[blockIdx.x];          // (instance, first cell)
+    const IView<F32> V = iview<F32>(A, cb.x);
+    const int j = cb.y + (int)threadIdx.x;
+    const bool in = j < V.N;
+    if constexpr (PH == CP_PRED) {
+        if (in) cell_pred_setup(V, j);
+    } else if constexpr (PH == CP_CORR) {
+        if (in) cell_corr_setup(V, j);
+    } else if constexpr (PH == CP_NEWTON) {
+        int n_its = 0, n_fail = 0, n_clamp = 0, n_neg = 0;
+        if (in) cell_newton(A, V, j, n_its, n_fail, n_clamp, n_neg);
+        // one atomic per wavefront for the step counters
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            n_its = max(n_its, __shfl_xor(n_its, o, 64));
+            n_fail += __shfl_xor(n_fail, o, 64);
+            n_clamp += __shfl_xor(n_clamp, o, 64);
+            n_neg += __shfl_xor(n_neg, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            int *st = V.st;
+            atomicMax(&st[2], n_its);
+            if (n_fail) atomicAdd(&st[3], n_fail);
+            if (n_clamp) atomicAdd(&st[4], n_clamp);
+            if (n_neg) atomicAdd(&st[5], n_neg);
+            const int ef = (n_fail ? GRTE_ERRF_NEWTON : 0) | (n_neg ? GRTE_ERRF_NEGATIVE_ROOT : 0);
+            if (ef) atomicOr(A.sticky, ef);
+        }
+    } else {
+        __shared__ double s_red[16];
+        double eb = 0.0, ea = 0.0;
+        if (in) cell_project(A, V, j, eb, ea);
+        // the block's sums (fixed order: a butterfly per wavefront, then the
+        // wavefronts in order); batch_energy adds the slab's blocks in order
+        tile_sum2_at<256>(eb, ea, s_red);
+        if (threadIdx.x == 0) {
+            A.epart[2 * blockIdx.x] = eb;
+            A.epart[2 * blockIdx.x + 1] = ea;
+        }
+    }
+}
+
+// the two per-slab solves: work-group tiles first (largest work first), then
+// wavefront tiles; PH 0: the prediction, 1: the correction
+template <int PH, bool F32>
+__global__ void __launch_bounds__(BNT) solve_kernel(BatchArgs A)
 {
     extern __shared__ double smem[];
     __shared__ int s_q;
-    // ---- work-group tiles, largest work first
+    int *queue = A.queue + 2 * PH;
     while (true) {
-        if (threadIdx.x == 0) s_q = atomicAdd(&A.queue[0], 1);
+        if (threadIdx.x == 0) s_q = atomicAdd(&queue[0], 1);
         __syncthreads();
         const int q = __builtin_amdgcn_readfirstlane(s_q);   // uniform: instance data in SGPRs
         __syncthreads();
         if (q >= A.n_wg) break;
         const int i = A.order[q];
-        switch (A.inst[i].M) {
-        case 2: run_instance<BNT, 2, F32>(A, i, smem); break;
-        case 4: run_instance<BNT, 4, F32>(A, i, smem); break;
-        default: run_instance<BNT, 8, F32>(A, i, smem); break;
+        if constexpr (PH == 0) {
+            switch (A.inst[i].M) {
+            case 2: pred_solve<BNT, 2, F32>(A, i, smem); break;
+            case 4: pred_solve<BNT, 4, F32>(A, i, smem); break;
+            default: pred_solve<BNT, 8, F32>(A, i, smem); break;
+            }
+        } else {
+            switch (A.inst[i].M) {
+            case 2: corr_solve<BNT, 2, F32>(A, i, smem); break;
+            case 4: corr_solve<BNT, 4, F32>(A, i, smem); break;
+            default: corr_solve<BNT, 8, F32>(A, i, smem); break;
+            }
         }
     }
-    // ---- wavefront tiles: each wave takes instances on its own
     double *wsm = smem + (threadIdx.x >> 6) * LDS_WAVE;
     while (true) {
         int q = 0;
-        if ((threadIdx.x & 63) == 0) q = atomicAdd(&A.queue[1], 1);
+        if ((threadIdx.x & 63) == 0) q = atomicAdd(&queue[1], 1);
         q = __builtin_amdgcn_readfirstlane(q);
         if (q >= A.n_wave) break;
         const int i = A.order[A.n_wg + q];
-        if (A.inst[i].M == 2) run_instance<WAVE, 2, F32>(A, i, wsm);
-        else run_instance<WAVE, 4, F32>(A, i, wsm);
+        if constexpr (PH == 0) {
+            if (A.inst[i].M == 2) pred_solve<WAVE, 2, F32>(A, i, wsm);
+            else pred_solve<WAVE, 4, F32>(A, i, wsm);
+        } else {
+            if (A.inst[i].M == 2) corr_solve<WAVE, 2, F32>(A, i, wsm);
+            else corr_solve<WAVE, 4, F32>(A, i, wsm);
+        }
     }
+}
+
+// the energy balance of every slab: its blocks' partial sums in block order,
+// the outflow of the prediction's fluxes over the step, the defect
+__global__ void __launch_bounds__(256) batch_energy(BatchArgs A)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n_inst) return;
+    const BInst I = A.inst[i];
+    double eb = 0.0, ea = 0.0;
+    for (int q = 0; q < I.ncb; ++q) {
+        eb += A.epart[2 * (I.cb0 + q)];
+        ea += A.epart[2 * (I.cb0 + q) + 1];
+    }
+    const double *C = A.cells + I.oC;
+    const int N1 = I.N + 1;
+    const double fdt = I.dt * (C[C_FLUX * N1 + 1] - C[C_FLUX * N1]);
+    double *en = A.ienergy + 4 * (size_t)i;
+    en[0] = eb;
+    en[1] = ea;
+    en[2] = fdt;
+    en[3] = (ea - eb) + fdt;
 }
 
 // queue heads and per-instance counters cleared by a kernel (not a memset node)
 __global__ void batch_reset(int *queue, int *istat, int n8)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < 2) queue[t] = 0;
+    if (t < 4) queue[t] = 0;
     if (t < n8) istat[t] = 0;
 }
 
@@ -931,6 +1122,9 @@ struct grte_batch {
     std::vector<void *> allocs;
     BInst *d_inst = nullptr;
     int *d_order = nullptr, *d_queue = nullptr, *d_istat = nullptr;
+    int2 *d_cblk = nullptr;                    // blocks of the per-cell kernels
+    double *d_epart = nullptr;                 // their energy partial sums (2 per block)
+    int n_cblk = 0;
     double *E[2] = {nullptr, nullptr}, *O[2] = {nullptr, nullptr}, *T[2] = {nullptr, nullptr};
     int cur = 0;                               // state buffers in use: E[cur], O[cur], T[cur]
     // binary32 storage (f32 != 0): the state is E32[cur], O32[cur] with T[cur];
@@ -1030,6 +1224,9 @@ BatchArgs make_args(const grte_batch *b, int src)
     A.inst = b->d_inst;
     A.order = b->d_order;
     A.queue = b->d_queue;
+    A.cblk = b->d_cblk;
+    A.epart = b->d_epart;
+    A.n_inst = b->n;
     A.E = b->E[src]; A.O = b->O[src]; A.T = b->T[src];
     A.E2 = b->E[1 - src]; A.O2 = b->O[1 - src]; A.T2 = b->T[1 - src];
     A.sigma0 = b->sigma0; A.mu = b->mu; A.omega = b->omega; A.bL = b->bL; A.bR = b->bR;
@@ -1051,13 +1248,27 @@ grte_status enqueue_step(grte_batch *b, hipStream_t s, int src)
 {
     BatchArgs A = make_args(b, src);
     const int n8 = 8 * b->n;
-    hipLaunchKernelGGL(batch_reset, dim3((unsigned)((std::max(n8, 2) + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(batch_reset, dim3((unsigned)((std::max(n8, 4) + 255) / 256)), dim3(256), 0, s,
                        b->d_queue, b->d_istat, n8);
     BCHK(hipGetLastError());
-    if (b->f32)
-        hipLaunchKernelGGL(batch_kernel<true>, dim3((unsigned)b->grid), dim3(BNT), BATCH_LDS, s, A);
-    else
-        hipLaunchKernelGGL(batch_kernel<false>, dim3((unsigned)b->grid), dim3(BNT), BATCH_LDS, s, A);
+    const dim3 cg((unsigned)b->n_cblk), sg((unsigned)b->grid), eg((unsigned)((b->n + 255) / 256));
+    if (b->f32) {
+        hipLaunchKernelGGL((cells_kernel<CP_PRED, true>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((solve_kernel<0, true>), sg, dim3(BNT), BATCH_LDS, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_NEWTON, true>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_CORR, true>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((solve_kernel<1, true>), sg, dim3(BNT), BATCH_LDS, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_PROJECT, true>), cg, dim3(256), 0, s, A);
+    } else {
+        hipLaunchKernelGGL((cells_kernel<CP_PRED, false>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((solve_kernel<0, false>), sg, dim3(BNT), BATCH_LDS, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_NEWTON, false>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_CORR, false>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((solve_kernel<1, false>), sg, dim3(BNT), BATCH_LDS, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_PROJECT, false>), cg, dim3(256), 0, s, A);
+    }
+    BCHK(hipGetLastError());
+    hipLaunchKernelGGL(batch_energy, eg, dim3(256), 0, s, A);
     BCHK(hipGetLastError());
     return GRTE_OK;
 }
@@ -1193,10 +1404,25 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
         b->cost[i] = (double)I.N * I.P;
     }
     b->tot_E = oE; b->tot_O = oO; b->tot_cells = oT; b->tot_pairs = oP;
+    // blocks of the per-cell kernels: 256 consecutive cells of one instance each,
+    // the instances' blocks contiguous and in instance order
+    std::vector<int2> cblk;
+    for (int i = 0; i < n; ++i) {
+        BInst &I = b->h_inst[i];
+        I.cb0 = (int)cblk.size();
+        for (int c0 = 0; c0 < I.N; c0 += 256) cblk.push_back(make_int2(i, c0));
+        I.ncb = (int)cblk.size() - I.cb0;
+    }
+    b->n_cblk = (int)cblk.size();
     grte_status st = GRTE_OK;
+    if (st == GRTE_OK) st = balloc(b, &b->d_cblk, cblk.size());
+    if (st == GRTE_OK) st = balloc(b, &b->d_epart, 2 * cblk.size());
+    if (st == GRTE_OK &&
+        hipMemcpy(b->d_cblk, cblk.data(), cblk.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        st = GRTE_E_HIP;
     if (st == GRTE_OK) st = balloc(b, &b->d_inst, n);
     if (st == GRTE_OK) st = balloc(b, &b->d_order, n);
-    if (st == GRTE_OK) st = balloc(b, &b->d_queue, 2);
+    if (st == GRTE_OK) st = balloc(b, &b->d_queue, 4);
     if (st == GRTE_OK) st = balloc(b, &b->d_istat, (size_t)8 * n);
     for (int q = 0; q < 2 && st == GRTE_OK; ++q) {
         st = balloc(b, &b->E[q], oE);
@@ -1218,22 +1444,19 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
                           hipMemset(b->d_energy, 0, (size_t)4 * n * sizeof(double)) != hipSuccess))
         st = GRTE_E_HIP;
     if (st != GRTE_OK) { grte_batch_destroy(b); return st; }
-    if (hipFuncSetAttribute((const void *)batch_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)BATCH_LDS) != hipSuccess ||
-        hipFuncSetAttribute((const void *)batch_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)BATCH_LDS) != hipSuccess) {
-        grte_batch_destroy(b);
-        return GRTE_E_HIP;
+    const void *solvers[] = {(const void *)solve_kernel<0, false>, (const void *)solve_kernel<1, false>,
+                             (const void *)solve_kernel<0, true>, (const void *)solve_kernel<1, true>};
+    int nbmin = 1 << 30;
+    for (const void *f : solvers) {
+        int nb = 0;
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BATCH_LDS) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, BNT, BATCH_LDS) != hipSuccess || nb < 1) {
+            grte_batch_destroy(b);
+            return GRTE_E_HIP;
+        }
+        nbmin = std::min(nbmin, nb);
     }
-    int nb = 0, nb32 = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)batch_kernel<false>, BNT, BATCH_LDS) !=
-            hipSuccess || nb < 1 ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb32, (const void *)batch_kernel<true>, BNT, BATCH_LDS) !=
-            hipSuccess || nb32 < 1) {
-        grte_batch_destroy(b);
-        return GRTE_E_HIP;
-    }
-    b->grid = std::min(nb, nb32) * b->ncu;
+    b->grid = nbmin * b->ncu;
     if (hipMemcpy(b->mu, mu, oP * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b->omega, omega, oP * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         grte_batch_destroy(b);
@@ -1502,7 +1725,7 @@ grte_status grte_batch_tune(grte_batch *b, int trials, grte_batch_tuning *best)
     }
     update_cost(b, h);
     int nb = 0;
-    const void *kfn = b->f32 ? (const void *)batch_kernel<true> : (const void *)batch_kernel<false>;
+    const void *kfn = b->f32 ? (const void *)solve_kernel<0, true> : (const void *)solve_kernel<0, false>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kfn, BNT, BATCH_LDS) != hipSuccess) nb = 1;
     const int waves[] = {0, 128, 256};
     std::vector<int> grids;
