@@ -508,10 +508,16 @@ grte_status grte_batch_get_tuning(const grte_batch *b, grte_batch_tuning *t);
 /* on != 0: every step replays a captured HIP graph (one per state-buffer
  * parity, captured at first use and after any change of tuning or solver). */
 grte_status grte_batch_use_graph(grte_batch *b, int on);
-/* Event timing of whole steps on the batch stream (as grte_set_profiling /
- * grte_read_timing, one stage). */
+/* Event timing on the batch stream.  While profiling is on, every step runs
+ * its kernels as direct launches (not a graph replay) with HIP events around
+ * the whole step and around its prediction-solve kernel (the per-slab solves
+ * of (4.5), the step's dominant kernel).  grte_batch_read_timing returns the
+ * summed step milliseconds and the number of steps since the last read;
+ * grte_batch_read_timing2 also the summed prediction-solve milliseconds.  Both
+ * synchronise the batch stream and start a new count. */
 grte_status grte_batch_set_profiling(grte_batch *b, int on);
 grte_status grte_batch_read_timing(grte_batch *b, double *total_ms, int *count);
+grte_status grte_batch_read_timing2(grte_batch *b, double *step_ms, double *solve_ms, int *count);
 
 /* ===========================================================================
  * The AP step on a 2-D rectangle [0, lx] x [0, ly] (nx x ny cells).

@@ -500,6 +500,16 @@ class GrteBatch:
                                                                          ctypes.byref(cnt)))
         return float(ms.value), int(cnt.value)
 
+    def read_timing2(self):
+        """(summed step ms, summed prediction-solve kernel ms, steps) of the
+        profiled steps since the last read."""
+        ms = ctypes.c_double()
+        ks = ctypes.c_double()
+        cnt = ctypes.c_int()
+        check("grte_batch_read_timing2", self._lib.grte_batch_read_timing2(self._h, ctypes.byref(ms),
+                                                                           ctypes.byref(ks), ctypes.byref(cnt)))
+        return float(ms.value), float(ks.value), int(cnt.value)
+
 
 class GrteDiff:
     """Discrete nonlinear diffusion limit: three-stage (2.7)/(2.9) or two-stage

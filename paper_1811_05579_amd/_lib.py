@@ -154,6 +154,8 @@ _SIGS = {
     "grte_batch_use_graph": (c_int, [c_void_p, c_int]),
     "grte_batch_set_profiling": (c_int, [c_void_p, c_int]),
     "grte_batch_read_timing": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_int)]),
+    "grte_batch_read_timing2": (c_int, [c_void_p, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                        ctypes.POINTER(c_int)]),
     "grte2d_circle_directions": (c_int, [c_int, c_void_p, c_void_p, c_void_p]),
     "grte2d_create": (c_int, [ctypes.POINTER(Problem2D), c_void_p, c_void_p, c_void_p,
                               ctypes.POINTER(c_void_p)]),

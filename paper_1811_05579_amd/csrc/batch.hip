@@ -1244,7 +1244,8 @@ BatchArgs make_args(const grte_batch *b, int src)
 
 constexpr size_t BATCH_LDS = (size_t)LDS_WG * sizeof(double);
 
-grte_status enqueue_step(grte_batch *b, hipStream_t s, int src)
+// kev: if given, an event pair recorded around the prediction-solve kernel
+grte_status enqueue_step(grte_batch *b, hipStream_t s, int src, const hipEvent_t *kev = nullptr)
 {
     BatchArgs A = make_args(b, src);
     const int n8 = 8 * b->n;
@@ -1254,14 +1255,18 @@ grte_status enqueue_step(grte_batch *b, hipStream_t s, int src)
     const dim3 cg((unsigned)b->n_cblk), sg((unsigned)b->grid), eg((unsigned)((b->n + 255) / 256));
     if (b->f32) {
         hipLaunchKernelGGL((cells_kernel<CP_PRED, true>), cg, dim3(256), 0, s, A);
+        if (kev) BCHK(hipEventRecord(kev[0], s));
         hipLaunchKernelGGL((solve_kernel<0, true>), sg, dim3(BNT), BATCH_LDS, s, A);
+        if (kev) BCHK(hipEventRecord(kev[1], s));
         hipLaunchKernelGGL((cells_kernel<CP_NEWTON, true>), cg, dim3(256), 0, s, A);
         hipLaunchKernelGGL((cells_kernel<CP_CORR, true>), cg, dim3(256), 0, s, A);
         hipLaunchKernelGGL((solve_kernel<1, true>), sg, dim3(BNT), BATCH_LDS, s, A);
         hipLaunchKernelGGL((cells_kernel<CP_PROJECT, true>), cg, dim3(256), 0, s, A);
     } else {
         hipLaunchKernelGGL((cells_kernel<CP_PRED, false>), cg, dim3(256), 0, s, A);
+        if (kev) BCHK(hipEventRecord(kev[0], s));
         hipLaunchKernelGGL((solve_kernel<0, false>), sg, dim3(BNT), BATCH_LDS, s, A);
+        if (kev) BCHK(hipEventRecord(kev[1], s));
         hipLaunchKernelGGL((cells_kernel<CP_NEWTON, false>), cg, dim3(256), 0, s, A);
         hipLaunchKernelGGL((cells_kernel<CP_CORR, false>), cg, dim3(256), 0, s, A);
         hipLaunchKernelGGL((solve_kernel<1, false>), sg, dim3(BNT), BATCH_LDS, s, A);
@@ -1628,20 +1633,25 @@ grte_status grte_batch_step(grte_batch *b, grte_batch_info *info)
 {
     if (!b) return GRTE_E_INVAL;
     int k = -1;
+    grte_status st;
     if (b->profiling) {
-        if (b->ev_used * 2 + 2 > b->ev.size()) {
-            for (int q = 0; q < 2; ++q) {
-                hipEvent_t e;
-                BCHK(hipEventCreate(&e));
-                b->ev.push_back(e);
-            }
+        // a profiled step runs its kernels as direct launches (an event pair
+        // can then bracket the prediction-solve kernel): events 4k, 4k+3 around
+        // the step, 4k+1, 4k+2 around that kernel
+        while (b->ev_used * 4 + 4 > b->ev.size()) {
+            hipEvent_t e;
+            BCHK(hipEventCreate(&e));
+            b->ev.push_back(e);
         }
         k = (int)b->ev_used++;
-        BCHK(hipEventRecord(b->ev[2 * k], b->stream));
+        BCHK(hipEventRecord(b->ev[4 * k], b->stream));
+        st = enqueue_step(b, b->stream, b->cur, &b->ev[4 * k + 1]);
+        if (st != GRTE_OK) return st;
+        BCHK(hipEventRecord(b->ev[4 * k + 3], b->stream));
+    } else {
+        st = run_step(b, b->cur);
+        if (st != GRTE_OK) return st;
     }
-    grte_status st = run_step(b, b->cur);
-    if (st != GRTE_OK) return st;
-    if (k >= 0) BCHK(hipEventRecord(b->ev[2 * k + 1], b->stream));
     b->cur = 1 - b->cur;
     if (!b->warm) {          // rprev now belongs to the current state; the launch changes
         b->warm = 1;
@@ -1796,13 +1806,23 @@ grte_status grte_batch_set_profiling(grte_batch *b, int on)
 grte_status grte_batch_read_timing(grte_batch *b, double *total_ms, int *count)
 {
     if (!b || !total_ms || !count) return GRTE_E_INVAL;
-    *total_ms = 0.0;
+    double solve_ms = 0.0;
+    return grte_batch_read_timing2(b, total_ms, &solve_ms, count);
+}
+
+grte_status grte_batch_read_timing2(grte_batch *b, double *step_ms, double *solve_ms, int *count)
+{
+    if (!b || !step_ms || !solve_ms || !count) return GRTE_E_INVAL;
+    *step_ms = 0.0;
+    *solve_ms = 0.0;
     *count = 0;
     BCHK(hipStreamSynchronize(b->stream));
     for (size_t k = 0; k < b->ev_used; ++k) {
-        float ms = 0.0f;
-        BCHK(hipEventElapsedTime(&ms, b->ev[2 * k], b->ev[2 * k + 1]));
-        *total_ms += ms;
+        float ms = 0.0f, ks = 0.0f;
+        BCHK(hipEventElapsedTime(&ms, b->ev[4 * k], b->ev[4 * k + 3]));
+        BCHK(hipEventElapsedTime(&ks, b->ev[4 * k + 1], b->ev[4 * k + 2]));
+        *step_ms += ms;
+        *solve_ms += ks;
         *count += 1;
     }
     b->ev_used = 0;
