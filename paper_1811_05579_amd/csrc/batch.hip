@@ -649,54 +649,55 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
                 __syncthreads();
                 double alpha, beta;
                 cheb_coeffs(Cs, A.accel, A.tol, alpha, beta);   // every wavefront: the same state
-                if (w == 0) {
+                {
                     // res = sum_p omega_p v_p - (1 - W) rho (the four wavefronts' sums in
                     // a fixed order);  rho += res + D^{-1} (G res), G = Lam - (Lam - G),
-                    // D = Lam - G + <mu^2> L + <mu> B (the diffusion operator of the DSA)
-                    const int lq = opaque(threadIdx.x & 63), jq = lq * LM, rl1 = N - 1 - jq;
-                    const double *ll = sLl + lq, *lu = sLu + lq, *la = slam + lq, *lg = slmg + lq;
-                    double *rh = rho + lq, *a0 = accw + lq;
-                    float *dc = sdch + lq;
-                    const double b0 = jq == 0 ? bd0 : 0.0;
-                    auto bdr = [&](int r) { return (r == 0 ? b0 : 0.0) + (r == rl1 ? bdN : 0.0); };
-                    double x[LM];
+                    // D = Lam - G + <mu^2> L + <mu> B (the diffusion operator of the DSA),
+                    // solved by the whole work-group (tri_factor_solve): thread k takes the
+                    // M rows j = k M + r, which lie in lane k / 4 of the wavefront layout
+                    // at rows (k % 4) M + r, i.e. at LDS position base + 64 r
+                    const int kk = opaque((int)threadIdx.x);
+                    const int base = (kk & 3) * M * 64 + (kk >> 2), jk = kk * M;
+                    double rl[M], d[M], bb[M], f[M];
 #pragma unroll
-                    for (int r = 0; r < LM; ++r) {
-                        const int t = r * 64;
-                        const double tot = ((a0[t] + a0[NP + t]) + a0[2 * NP + t]) + a0[3 * NP + t];
-                        const double rl = tot - I.one_minus_W * rh[t];
-                        a0[t] = rl;
-                        x[r] = (la[t] - lg[t]) * rl;
+                    for (int r = 0; r < M; ++r) {
+                        const int t = base + r * 64, j = jk + r;
+                        const double tot = ((accw[t] + accw[NP + t]) + accw[2 * NP + t]) + accw[3 * NP + t];
+                        rl[r] = tot - I.one_minus_W * rho[t];
+                        d[r] = (slam[t] - slmg[t]) * rl[r];
+                        const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
+                        bb[r] = slmg[t] + I.mu2 * (-(sLl[t] + sLu[t])) + I.mu1 * bdj;
                     }
-                    lane_chunk_solve<LM>(
-                        [&](int r) { return I.mu2 * ll[r * 64]; },
-                        [&](int r) { return lg[r * 64] + I.mu2 * (-(ll[r * 64] + lu[r * 64])) + I.mu1 * bdr(r); },
-                        [&](int r) { return I.mu2 * lu[r * 64]; }, x);
+                    __syncthreads();                  // every angular sum read: accw is the solver's scratch now
+                    int ph0 = 0;
+                    tri_factor_solve<BNT, M>(I.mu2, sLl, sLu, bb, d, f, accw, ph0, base, 64);
                     double md = 0.0, mr = 0.0;
 #pragma unroll
-                    for (int r = 0; r < LM; ++r) {
-                        const int t = r * 64;
-                        const double z = a0[t] + x[r];
-                        const double upd = alpha * (double)dc[t] + beta * z;
-                        dc[t] = (float)upd;
-                        const double nw = rh[t] + upd;
-                        rh[t] = nw;
+                    for (int r = 0; r < M; ++r) {
+                        const int t = base + r * 64;
+                        const double z = rl[r] + f[r];
+                        const double upd = alpha * (double)sdch[t] + beta * z;
+                        sdch[t] = (float)upd;
+                        const double nw = rho[t] + upd;
+                        rho[t] = nw;
                         md = fmax(md, fabs(z));
                         mr = fmax(mr, fabs(nw));
                     }
+                    // maxima over the tile: a butterfly per wavefront, then the four in order
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
                         md = fmax(md, __shfl_xor(md, o, 64));
                         mr = fmax(mr, __shfl_xor(mr, o, 64));
                     }
-                    if (lq == 0) {
-                        red[0] = md;
-                        red[1] = mr;
+                    if ((threadIdx.x & 63) == 0) {
+                        red[w] = md;
+                        red[8 + w] = mr;
                     }
                 }
                 __syncthreads();                      // the rho update and its norms visible to the tile
             }
-            const double md = red[0], mr = red[1];
+            const double md = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            const double mr = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
             ++it;
             const float qprev = Cs.q1, qprev2 = Cs.q2, qprev3 = Cs.q3;
             const float q = (float)(mr > 0.0 ? md / mr : md);

@@ -349,14 +349,17 @@ __device__ __forceinline__ void tri_solve(double s, const double *Lo, const doub
 // (nothing is kept): the reduced coefficients and the reduced right-hand side
 // are published together, so a work-group tile needs a single barrier.  LDS
 // use (work-group tiles): the solve buffers sh[5W, 9W) selected by `ph`.
+// (Lo, Up of the thread's row r at position base + r * rs; by default the
+// tile's position order, base = the thread's tile index, rs = W.)
 template <int W, int M>
 __device__ __forceinline__ void tri_factor_solve(double s, const double *Lo, const double *Up,
                                                  const double (&b)[M], const double (&d)[M], double (&x)[M],
-                                                 double *sh, int &ph)
+                                                 double *sh, int &ph, int base = -1, int rs = W)
 {
     const int k = tile_lane<W>();
-    auto a = [&](int r) { return s * Lo[r * W + k]; };
-    auto c = [&](int r) { return s * Up[r * W + k]; };
+    if (base < 0) base = k;
+    auto a = [&](int r) { return s * Lo[base + r * rs]; };
+    auto c = [&](int r) { return s * Up[base + r * rs]; };
     if constexpr (W == 64) {
         WaveFac<M> F;
         wave_factor<M>(a, c, b, F);
@@ -434,7 +437,7 @@ __device__ __forceinline__ void tri_factor_solve(double s, const double *Lo, con
 // far from zero).
 
 constexpr int LCS_WIN = 4;       // rows of coefficient loads in flight ahead of a recurrence
-constexpr int LCS_IL_MAX = 16;   // chunks up to this size run their two recurrences interleaved
+constexpr int LCS_IL_MAX = 32;   // chunks up to this size run their two recurrences interleaved
 
 __device__ __forceinline__ double rcp64(double v)
 {
