@@ -50,8 +50,7 @@ constexpr int WAVE_MAX_N = 256;       // largest slab a wavefront tile can take 
 
 // per-instance cell scratch: NCA arrays of N+1 entries
 enum {
-    C_AW, C_BC, C_LL, C_LU, C_LAM, C_LMG, C_G, C_BD, C_DD, C_BETA, C_RHON, C_H, C_AWR, C_AWL,
-    C_SRC, C_KEPS, C_USTAR, C_D, C_TNEW,
+    C_AW, C_BC, C_LL, C_LU, C_LAM, C_LMG, C_BD, C_BETA, C_RHON, C_TNEW,
     C_FLUX,     // [0], [1]: sum_p omega_p mu_p O*_{0,p} and O*_{N,p} (energy balance)
     NCA
 };
@@ -142,11 +141,19 @@ __device__ __forceinline__ void b_node(const BInst &I, const double *Tk, const d
     }
 }
 
+// the coefficients of cell j's right-hand sides (used by the thread that
+// formed them, not stored): h = K eps^2 c dt / dx, K eps^2, the source term,
+// and the two face weights of the node relations (doubled at the ends)
+struct CellRhs {
+    double h, keps, src, awr, awl;
+};
+
 // per-cell coefficients of cell j; mode 0: prediction (K from T^n, with the
 // U* elimination of (4.5c)), 1: correction (K from T^{n+1})
-__device__ void b_cell(const BInst &I, int mode, const double *Tk, const double *Tn, const double *sg,
-                       int j, double *C, int N1)
+__device__ CellRhs b_cell(const BInst &I, int mode, const double *Tk, const double *Tn, const double *sg,
+                          int j, double *C, int N1)
 {
+    CellRhs R;
     const int N = I.N;
     const double eps = I.eps, c = I.c, dt = I.dt;
     double awl = 0.0, bcl = 0.0, awr = 0.0, bcr = 0.0;
@@ -168,10 +175,10 @@ __device__ void b_cell(const BInst &I, int mode, const double *Tk, const double 
     C[C_LU * N1 + j] = -fr;
     C[C_BD * N1 + j] = bd;
     C[C_LAM * N1 + j] = Kc * eps * eps + s0 * c * dt;
-    C[C_H * N1 + j] = h;
-    C[C_AWR * N1 + j] = (j <= N - 2) ? awr * (j == 0 ? 2.0 : 1.0) : 0.0;
-    C[C_AWL * N1 + j] = (j >= 1) ? awl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
-    C[C_KEPS * N1 + j] = Kc * eps * eps;
+    R.h = h;
+    R.awr = (j <= N - 2) ? awr * (j == 0 ? 2.0 : 1.0) : 0.0;
+    R.awl = (j >= 1) ? awl * (j == N - 1 ? 2.0 : 1.0) : 0.0;
+    R.keps = Kc * eps * eps;
     const double ac = I.a * c;
     if (mode == 0) {
         const double t = Tn[j];
@@ -182,13 +189,12 @@ __device__ void b_cell(const BInst &I, int mode, const double *Tk, const double 
         const double lmg = Kc * eps * eps + s0 * c * dt / opb;
         C[C_BETA * N1 + j] = beta;
         C[C_LMG * N1 + j] = lmg;
-        C[C_G * N1 + j] = s0 * c * dt * (ac * beta) / opb;
-        C[C_DD * N1 + j] = lmg + I.mu2 * (fl + fr) + I.mu1 * bd;
-        C[C_SRC * N1 + j] = s0 * c * dt * ac * Un / opb;
+        R.src = s0 * c * dt * ac * Un / opb;
     } else {
         const double t1 = Tk[j];
-        C[C_SRC * N1 + j] = s0 * c * dt * ac * (t1 * t1 * t1 * t1);
+        R.src = s0 * c * dt * ac * (t1 * t1 * t1 * t1);
     }
+    return R;
 }
 
 // The state E^n, O^n of one instance: binary64 arrays in the caller's
@@ -296,15 +302,14 @@ __device__ __forceinline__ IView<F32> iview(const BatchArgs &A, int i)
 
 // right-hand sides of cell j's per-pair systems into Rt (pair-major, cell order)
 template <bool F32>
-__device__ __forceinline__ void rhs_cell(const IView<F32> &V, int j)
+__device__ __forceinline__ void rhs_cell(const IView<F32> &V, int j, const CellRhs &R)
 {
     const BInst &I = V.I;
-    const int N = V.N, P = V.P, N1 = V.N1, NP = V.NP;
-    const double *C = V.C, *mu = V.mu, *bL = V.bL, *bR = V.bR;
+    const int N = V.N, P = V.P, NP = V.NP;
+    const double *mu = V.mu, *bL = V.bL, *bR = V.bR;
     double *Rt = V.Rt;
     const BState<F32> &S = V.S;
-    const double h = C[C_H * N1 + j], keps = C[C_KEPS * N1 + j], src = C[C_SRC * N1 + j];
-    const double awr = C[C_AWR * N1 + j], awl = C[C_AWL * N1 + j];
+    const double h = R.h, keps = R.keps, src = R.src, awr = R.awr, awl = R.awl;
     const bool has_r = j <= N - 2, has_l = j >= 1;
     for (int p0 = 0; p0 < P; p0 += RHS_U) {
         double e[RHS_U], orr[RHS_U], ol[RHS_U];
@@ -335,20 +340,20 @@ __device__ __forceinline__ void cell_pred_setup(const IView<F32> &V, int j)
     const BInst &I = V.I;
     const int P = V.P, N1 = V.N1;
     double *C = V.C;
-    b_cell(I, 0, V.Tn, V.Tn, V.sg, j, C, N1);
+    const CellRhs R = b_cell(I, 0, V.Tn, V.Tn, V.sg, j, C, N1);
     double rn = 0.0;
 #pragma unroll 4
     for (int p = 0; p < P; ++p) rn += V.om[p] * V.S.e(j, p);
     C[C_RHON * N1 + j] = rn;
-    rhs_cell(V, j);
+    rhs_cell(V, j, R);
 }
 
 // correction set-up of cell j: coefficients with K from T^{n+1}, right-hand sides
 template <bool F32>
 __device__ __forceinline__ void cell_corr_setup(const IView<F32> &V, int j)
 {
-    b_cell(V.I, 1, V.C + C_TNEW * V.N1, V.Tn, V.sg, j, V.C, V.N1);
-    rhs_cell(V, j);
+    const CellRhs R = b_cell(V.I, 1, V.C + C_TNEW * V.N1, V.Tn, V.sg, j, V.C, V.N1);
+    rhs_cell(V, j, R);
 }
 
 // correction substep 1 of cell j: moments of E*, D from the prediction's node
@@ -414,8 +419,6 @@ __device__ __forceinline__ void cell_newton(const BatchArgs &A, const IView<F32>
     const double Un = t * t * t * t;
     const double beta = C[C_BETA * N1 + j];
     const double us = (Un + beta * rs) / (1.0 + ac * beta);
-    C[C_USTAR * N1 + j] = us;
-    C[C_D * N1 + j] = D;
     double Ks = 1.0;
     if (I.m == 3) {
         if (us < 0.0) {
@@ -782,8 +785,10 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
                     const int j = j0 + r;
                     const bool in = j < N;
                     rl[r] = in ? acc[r] - I.one_minus_W * rho[r * W + k] : 0.0;
-                    d[r] = in ? C[C_G * N1 + j] * rl[r] : 0.0;
-                    b[r] = in ? C[C_DD * N1 + j] : 1.0;
+                    const int t = r * W + k;
+                    const double bdj = (j == 0 ? bd0 : 0.0) + (j == N - 1 ? bdN : 0.0);
+                    d[r] = in ? (lam[r] - lmg[r]) * rl[r] : 0.0;                 // G res
+                    b[r] = in ? lmg[r] + I.mu2 * (-(sLl[t] + sLu[t])) + I.mu1 * bdj : 1.0;
                 }
                 tri_factor_solve<W, M>(I.mu2, sLl, sLu, b, d, f, sh, ph);
             }
