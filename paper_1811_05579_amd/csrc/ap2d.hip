@@ -457,6 +457,135 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
     block_sums(acc, MODE == 0 ? 4 : (MODE == 1 ? 1 : 2), A.part);
 }
 
+// The operator products of the iteration by columns: the grid is cut into tiles
+// of (B2 / P) cells across by OP_ROWS cells down; thread (cell c, pair p) of a
+// tile walks down its column keeping the 3 x 3 neighbourhood of its pair in
+// registers, so that a row costs three new loads of x instead of nine and the
+// shared face coefficient of two rows one, and it loads the next row's values
+// and coefficients before it computes the current row (their latency overlaps
+// the arithmetic).  The arithmetic is that of apply_at.  A block takes tiles
+// blockIdx.x, + gridDim.x, ...; its partial sums go to part[k * KRYB + blockIdx.x].
+// MODE 1: v = A ph, partial (h, v) and, with the isotropic correction, the moment
+// of v;  MODE 2: t = A sh, partial (t, s), (t, t)
+constexpr int OP_ROWS = 16;
+
+__device__ __forceinline__ void block_sums_at(double *vals, int k, double *part, int bid)
+{
+    __shared__ double red[4][B2 / 64];
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    for (int q = 0; q < k; ++q) {
+        double v = vals[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[q][w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double v = 0.0;
+        for (int i = 0; i < B2 / 64; ++i) v += red[threadIdx.x][i];
+        part[threadIdx.x * KRYB + bid] = v;
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, int ntile)
+{
+    if (A.fl[F_STATE] != 0) return;
+    const Sys &S = A.S;
+    const int P = S.P, lgP = S.lgP, nx = S.nx, ny = S.ny;
+    const int c = threadIdx.x >> lgP, p = threadIdx.x & (P - 1);
+    const int cw = B2 >> lgP, rs = nx * P;
+    const double *xv = MODE == 1 ? A.ph : A.sh;
+    const double mu = S.mu[p], eta = S.eta[p], w = S.om[p];
+    const double sx = mu > 0.0 ? 1.0 : -1.0, sy = eta > 0.0 ? 1.0 : -1.0;
+    double acc[2] = {0.0, 0.0};
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int ty = tile / ncol, tx = tile - ty * ncol;
+        const int ix = tx * cw + c;
+        if (ix >= nx) continue;                 // whole cells: a cell's P lanes agree
+        const int iy0 = ty * OP_ROWS, iy1 = min(iy0 + OP_ROWS, ny);
+        const int o0 = max(ix - 1, 0) * P + p, o1 = ix * P + p, o2 = min(ix + 1, nx - 1) * P + p;
+        auto ldrow = [&](int row, double(&v)[3]) {
+            const double *q = xv + row * rs;
+            v[0] = q[o0];
+            v[1] = q[o1];
+            v[2] = q[o2];
+        };
+        Nb X;
+        ldrow(max(iy0 - 1, 0), X.v[0]);
+        ldrow(iy0, X.v[1]);
+        ldrow(min(iy0 + 1, ny - 1), X.v[2]);
+        int j = iy0 * nx + ix;
+        double gl = S.gx[j + iy0], gr = S.gx[j + iy0 + 1], gb = S.gy[j], gt = S.gy[j + nx];
+        double dm = S.dmg[j], cgv = S.cg[j], kc = S.kco[j];
+        double sv = MODE == 2 ? A.s[j * P + p] : 0.0;
+        for (int iy = iy0; iy < iy1; ++iy) {
+            // the next row's loads (row indices clamped in range; unused after
+            // the tile's last row)
+            const int yn = min(iy + 1, ny - 1), jn = yn * nx + ix;
+            double xn[3];
+            ldrow(min(iy + 2, ny - 1), xn);
+            const double gln = S.gx[jn + yn], grn = S.gx[jn + yn + 1], gtn = S.gy[jn + nx];
+            const double dmn = S.dmg[jn], cgn = S.cg[jn], kcn = S.kco[jn];
+            const double svn = MODE == 2 ? A.s[jn * P + p] : 0.0;
+            // row iy: faces<false, true> and apply_at with the coefficients in registers
+            const Grad g = face_grad(X, mu, eta, S, iy, ix);
+            Grad O;
+            O.l = -gl * g.l;
+            O.r = -gr * g.r;
+            O.b = -gb * g.b;
+            O.t = -gt * g.t;
+            const double xp = X.v[1][1];
+            const double k2 = S.k2;
+            auto edge = [&](double sg) {
+                const double d = -S.fe * xp;
+                return sg * k2 * d;
+            };
+            if (ix == 0) O.l = edge(sx) - O.r;
+            if (ix == nx - 1) O.r = edge(-sx) - O.l;
+            if (iy == 0) O.b = edge(sy) - O.t;
+            if (iy == ny - 1) O.t = edge(-sy) - O.b;
+            const double div = mu * (O.r - O.l) * S.idx + eta * (O.t - O.b) * S.idy;
+            double y;
+            if (S.corr) {
+                y = dm * xp + kc * div;             // no angular coupling (g = 0)
+            } else {
+                const double xr = group_lane0(xp, P);
+                const double cpl = S.W1 * (xp - xr) - group_sum(w * (xp - xr), P);
+                y = dm * xp + cgv * cpl + kc * div;
+            }
+            const int t = j * P + p;
+            if (MODE == 1) {
+                A.v[t] = y;
+                if (A.mv) {
+                    const double m = group_sum(w * y, P);
+                    if (p == 0) A.mv[j] = m;
+                }
+                acc[0] += shadow(t) * y;
+            } else {
+                A.t[t] = y;
+                acc[0] += y * sv;
+                acc[1] += y * y;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                X.v[0][k] = X.v[1][k];
+                X.v[1][k] = X.v[2][k];
+                X.v[2][k] = xn[k];
+            }
+            j = jn;
+            gl = gln;
+            gr = grn;
+            gb = gt;
+            gt = gtn;
+            dm = dmn;
+            cgv = cgn;
+            kc = kcn;
+            sv = svn;
+        }
+    }
+    block_sums_at(acc, MODE == 1 ? 1 : 2, A.part, blockIdx.x);
+}
+
 // 1 / d_p: the inverse of the direction-diagonal part of a cell's block
 __device__ __forceinline__ double block_idiag(const Sys &S, int j, int p)
 {
@@ -1714,10 +1843,14 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.red_b = c->red_b;
     hipStream_t st = c->stream;
     // the scalar step `which` of the iteration after a kernel that left k partial sums per block
-    auto fin = [&](int which, int k) {
-        if (nb > c->red_b)
-            hipLaunchKernelGGL(red2d_kernel, dim3((nb + c->red_b - 1) / c->red_b), dim3(B2), 0, st, A, which, k, nb);
-        hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, which, nb);
+    // (the operator products of the iteration run on their own grid of column tiles)
+    const int ncol = (c->nx + (B2 / c->P) - 1) / (B2 / c->P), ntile = ncol * ((c->ny + OP_ROWS - 1) / OP_ROWS);
+    const int nbo = std::min(ntile, KRYB);
+    auto fin = [&](int which, int k, int nbk) {
+        if (nbk > c->red_b)
+            hipLaunchKernelGGL(red2d_kernel, dim3((nbk + c->red_b - 1) / c->red_b), dim3(B2), 0, st, A, which, k,
+                               nbk);
+        hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, which, nbk);
     };
     int its_total = 0, state = 0;
     // iterations are enqueued in batches between convergence checks; the
@@ -1728,7 +1861,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     for (int restart = 0; restart <= KRY_RESTARTS; ++restart) {
         hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
         hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
-        fin(0, 4);
+        fin(0, 4, nb);
         hipLaunchKernelGGL(zero2_kernel, dim3(nb), dim3(B2), 0, st, c->p, c->v, c->nE);
         // the moments of p and v start from zero with them
         if (iso) hipLaunchKernelGGL(zero2_kernel, dim3(nbc), dim3(B2), 0, st, c->yP, c->mv, c->N);
@@ -1768,18 +1901,18 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
                 }
                 hipLaunchKernelGGL(pupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
                 if (timed && k == 0) (void)hipEventRecord(c->ev0, st);
-                hipLaunchKernelGGL(apply2d_kernel<1>, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(apply2d_col_kernel<1>, dim3(nbo), dim3(B2), 0, st, A, ncol, ntile);
                 if (timed && k == 0) (void)hipEventRecord(c->ev1, st);
-                fin(1, 1);
+                fin(1, 1, nbo);
                 if (iso) {
                     hipLaunchKernelGGL(ymom2d_kernel, dim3(nbc), dim3(B2), 0, st, A, 1, (int)c->N);
                     iso_solve(c, S, c->yS, c->dS, st);
                 }
                 hipLaunchKernelGGL(supd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
-                hipLaunchKernelGGL(apply2d_kernel<2>, dim3(nb), dim3(B2), 0, st, A);
-                fin(2, 2);
+                hipLaunchKernelGGL(apply2d_col_kernel<2>, dim3(nbo), dim3(B2), 0, st, A, ncol, ntile);
+                fin(2, 2, nbo);
                 hipLaunchKernelGGL(xupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
-                fin(3, 2);
+                fin(3, 2, nb);
             }
             if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
             if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1801,7 +1934,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             // one more true residual for the report
             hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
             hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
-            fin(0, 4);
+            fin(0, 4, nb);
             if (hipMemcpyAsync(c->h_sc, c->sc, S_NS * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GRTE_E_HIP;
             if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
