@@ -388,7 +388,7 @@ def main_2d(args):
     its = []
     for _ in range(args.steps):
         d = g.step(w.dt, w.eps, info=True)
-        its.append((d["pred_iters"], d["corr_iters"], d["status"]))
+        its.append((d["pred_iters"], d["corr_iters"], d["status"], d["pred_narrow"], d["corr_narrow"]))
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -420,6 +420,9 @@ def main_2d(args):
             "steps_from_cold_start": [args.warmup, args.warmup + args.steps],
             "pred_iters_mean": sum(i[0] for i in its) / len(its), "pred_iters_max": max(i[0] for i in its),
             "corr_iters_mean": sum(i[1] for i in its) / len(its), "status_worst": min(i[2] for i in its),
+            # solves whose Krylov vectors were binary32 (the rest binary64)
+            "krylov_binary32_solves": {"pred": sum(i[3] for i in its), "corr": sum(i[4] for i in its),
+                                       "of": len(its)},
             "host_wall_s": wall,
         },
         "roofline": {

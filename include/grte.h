@@ -588,6 +588,9 @@ typedef struct grte2d_step_info {
                                 O*y_bottom), the prediction's edge face values    */
     double energy_defect;    /* energy_after - energy_before + boundary_flux_dt:
                                 the defect of (3.13)                              */
+    int pred_narrow;         /* 1 if the prediction's Krylov vectors were stored in
+                                binary32 (grte2d_set_krylov_storage)              */
+    int corr_narrow;         /* the same for the correction                        */
 } grte2d_step_info;
 
 enum {
@@ -634,6 +637,23 @@ grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
  * a small grid run the many-block, two-level path of a large one (tests).
  * GRTE_E_INVAL outside those ranges. */
 grte_status grte2d_set_launch_shape(grte2d_ctx *ctx, int items_per_thread, int first_level);
+
+/* Storage of the Krylov vectors (r, p, B^-1 p, A B^-1 p, s, B^-1 s, A B^-1 s and
+ * the block inverse's 1/d_p; the arithmetic is binary64 either way).
+ * narrow = 1 (the default): binary32 where the solve allows it, else binary64;
+ * narrow = 0: always binary64.  The iterate x and the true residual b - A x,
+ * recomputed from the equations at the start of every pass, are binary64.
+ * With binary32 vectors a pass ends once the recursion has reduced its
+ * residual to 1e-5 of the pass's starting true residual or to a tenth of the
+ * tolerance, so that a solve takes several passes.  The prediction keeps
+ * binary64 vectors when some cell's block inverse (diagonal plus the rank-one
+ * angular coupling g of (4.5c)) has a Sherman-Morrison denominator
+ * 1 - g sum_p omega_p / d_p below 1e-5: it falls like 1 / (a c beta) in stiff
+ * cells, where binary32 directions would lose the near-isotropic mode the
+ * inverse amplifies.  The correction's blocks are diagonal.  The info struct
+ * reports the storage each solve used.  GRTE_E_INVAL for a NULL context or
+ * narrow not 0 or 1. */
+grte_status grte2d_set_krylov_storage(grte2d_ctx *ctx, int narrow);
 
 /* The Krylov preconditioner inverts each cell's P x P block (the direction-
  * diagonal part plus the rank-one angular coupling of (4.5c)) and, in the

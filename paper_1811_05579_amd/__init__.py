@@ -625,6 +625,11 @@ class Grte2D:
         check("grte2d_set_launch_shape",
               self._lib.grte2d_set_launch_shape(self._h, int(items_per_thread), int(first_level)))
 
+    def set_krylov_storage(self, narrow=True):
+        """Binary32 Krylov vectors where the solve allows them (True, the
+        default) or binary64 always (grte2d_set_krylov_storage)."""
+        check("grte2d_set_krylov_storage", self._lib.grte2d_set_krylov_storage(self._h, int(bool(narrow))))
+
     def set_opacity(self, sigma0):
         p, dev = _ptr(sigma0, self.N, "sigma0")
         check("grte2d_set_opacity", self._lib.grte2d_set_opacity(self._h, _addr(p), dev))

@@ -75,7 +75,8 @@ class StepInfo2D(ctypes.Structure):
                 ("negative_root", c_int), ("newton_total_iters", c_int), ("guess_accepted", c_int),
                 ("guess_rejected", c_int), ("guess_started", c_int), ("pred_floor_stop", c_int),
                 ("corr_floor_stop", c_int), ("energy_before", c_double), ("energy_after", c_double),
-                ("boundary_flux_dt", c_double), ("energy_defect", c_double)]
+                ("boundary_flux_dt", c_double), ("energy_defect", c_double), ("pred_narrow", c_int),
+                ("corr_narrow", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -163,6 +164,7 @@ _SIGS = {
     "grte2d_set_stream": (c_int, [c_void_p, c_void_p]),
     "grte2d_set_solver": (c_int, [c_void_p, c_double, c_int]),
     "grte2d_set_launch_shape": (c_int, [c_void_p, c_int, c_int]),
+    "grte2d_set_krylov_storage": (c_int, [c_void_p, c_int]),
     "grte2d_set_opacity": (c_int, [c_void_p, c_void_p, c_int]),
     "grte2d_set_inflow": (c_int, [c_void_p, c_void_p]),
     "grte2d_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),

@@ -54,12 +54,28 @@ constexpr int MAXB = 2048;     // blocks of the grid-stride kernels outside the 
 // than RED_B of them (both figures can be set per context)
 constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = 2048;
 constexpr int CHUNK = 8;       // most BiCGStab iterations enqueued between convergence checks
-constexpr int KRY_RESTARTS = 6;      // restarts from the true residual per solve
+constexpr int KRY_RESTARTS = 12;     // restarts from the true residual per solve
+// a pass of binary32-stored iterations ends once the recursion's residual is
+// this fraction of the pass's true starting residual (the recursion and the
+// true residual part at the level of binary32 rounding)
+constexpr double KRY_PASS_RED = 1e-5;
+// binary32 Krylov vectors only where every cell's block inverse amplifies
+// rounding by at most 1 / KRY_F32_GAP (its Sherman-Morrison denominator 1 - g
+// sum_p omega_p / d_p is at least KRY_F32_GAP; it falls like 1 / (a c beta) in
+// stiff cells, where a binary32 direction would carry too little of the
+// near-isotropic mode to precondition)
+constexpr double KRY_F32_GAP = 1e-5;
+// the recursion runs on to this fraction of the tolerance before the true
+// residual is taken: a restarted binary32 recursion stopped at the tolerance
+// itself leaves, on stiff systems whose residual sits at the rounding floor,
+// errors in modes with small residuals (E* up to 1e-11 where one binary64
+// Krylov space reaches 2e-13 at the same residual)
+constexpr double KRY_REC = 0.1;
 constexpr double CHEB2_A = 0.01, CHEB2_B = 2.0;   // eigenvalue interval of the Jacobi-scaled isotropic operator
 constexpr double KRY_FLOOR = 64.0;   // floor stop: true residual within this factor of its rounding level
 
 // scalars of the Krylov solve, in device memory
-enum { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_RV, S_TS, S_TT, S_MM, S_NS };
+enum { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_BB, S_RV, S_TS, S_TT, S_MM, S_R0, S_NS };
 enum { F_STATE = 0, F_ITS, F_NF };          // F_STATE: 0 running, 1 converged, 2 breakdown
 
 struct Sys {
@@ -73,7 +89,6 @@ struct Sys {
     const double *rb1, *rb0, *acU;       // rhs = rb1 E^n_p + rb0; acU (correction's known part)
     const double *sab, *ue;              // residual in difference form (see residual_at)
     const double *pgc;                   // cell: g / (1 - g sum_p omega_p / d_p) of the block inverse
-    const double *idg;                   // (cell, pair): 1 / d_p of the block inverse
 };
 
 // (iy, ix) of cell j without an integer division: the binary64 product is off
@@ -283,7 +298,14 @@ struct VecArgs {
     Sys S;
     size_t n;                  // N * P
     const double *En;          // E^n (rhs)
-    double *bv, *x, *r, *p, *ph, *v, *s, *sh, *t;
+    double *bv, *x;            // right-hand side, iterate (binary64)
+    // the Krylov vectors and the block inverse's 1/d_p, stored in binary32 or
+    // binary64 (the kernels' template type V; the arithmetic is binary64): a
+    // pass of iterations ends when the recursion has reduced the residual by
+    // KRY_PASS_RED, and the next starts from the binary64 true residual
+    void *r, *p, *ph, *v, *s, *sh, *t;
+    const void *idg;
+    double pass_red, rec;      // a pass ends at pass_red x its start, or at rec x tol
     double *part;              // [k * KRYB + block]
     double *part2;             // [k * KRYB + block] (first reduction level)
     int red_b;                 // partials per block of the first reduction level
@@ -345,24 +367,6 @@ __global__ void __launch_bounds__(B2) rhs2d_kernel(VecArgs A)
     }
 }
 
-// y = A x for the (cell, pair) of thread t
-__device__ __forceinline__ double apply_at(const Sys &S, const double *x, int t, int j, int p)
-{
-    const int P = S.P;
-    int iy, ix;
-    cell_yx(S, j, iy, ix);
-    const Nb X = load_nb(x, S.nx, S.ny, iy, ix, P, p);
-    const double xp = X.v[1][1];
-    Grad O;
-    faces<false, true>(S, iy, ix, p, &X, O);
-    // W1 x_p - sum_q omega_q x_q, referred to the cell's first pair to keep it
-    // exact for a nearly isotropic x
-    const double xr = group_lane0(xp, P);
-    const double w = S.om[p];
-    const double cpl = S.W1 * (xp - xr) - group_sum(w * (xp - xr), P);
-    return S.dmg[j] * X.v[1][1] + S.cg[j] * cpl + S.kco[j] * divergence(S, O, p);
-}
-
 // b - A x evaluated from the full face values and differences of nearly equal
 // quantities (E^n - x, a c U - x), so that its rounding stays at the level of the
 // residual itself rather than of the large terms that cancel in it (the inflow
@@ -414,47 +418,32 @@ __device__ __forceinline__ double residual_at(const Sys &S, const double *En, co
     return S.rb1[j] * (En[t] - xp) + S.sab[j] * (S.ue[j] - xp) - g * (1.0 - S.W1) * xp - g * cpl - div;
 }
 
-// mode 0: r = b - A x, partial (r, r), (b, b), the backward-error scale and (h, r)
-// mode 1: v = A ph, partial (h, v)   (h: the shadow vector)
-// mode 2: t = A sh, partial (t, s), (t, t)
-template <int MODE>
-__global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
+// r = b - A x (the pass's starting residual, stored as V), partial (r, r)
+// of the binary64 residual, (b, b), the backward-error scale and (h, r)
+// (h: the shadow vector)
+template <class V>
+__global__ void __launch_bounds__(B2) residual2d_kernel(VecArgs A)
 {
-    if (A.fl[F_STATE] != 0 && MODE != 0) return;
     const Sys &S = A.S;
     const int P = S.P;
+    V *r = (V *)A.r;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
         const int j = t >> A.S.lgP, p = t & (P - 1);
-        if (MODE == 0) {
-            double mag;
-            const double rr = residual_at(S, A.En, A.x, t, j, p, mag);
-            A.r[t] = rr;
-            if (A.mr) {
-                const double m = group_sum(S.om[p] * rr, P);
-                if (p == 0) A.mr[j] = m;
-            }
-            acc[0] += rr * rr;
-            acc[1] += A.bv[t] * A.bv[t];
-            acc[2] += mag * mag;
-            acc[3] += shadow(t) * rr;
-        } else if (MODE == 1) {
-            const double y = apply_at(S, A.ph, t, j, p);
-            A.v[t] = y;
-            if (A.mv) {
-                const double m = group_sum(S.om[p] * y, P);
-                if (p == 0) A.mv[j] = m;
-            }
-            acc[0] += shadow(t) * y;
-        } else {
-            const double y = apply_at(S, A.sh, t, j, p);
-            A.t[t] = y;
-            const double sv = A.s[t];
-            acc[0] += y * sv;
-            acc[1] += y * y;
+        double mag;
+        const double rr = residual_at(S, A.En, A.x, t, j, p, mag);
+        const V rf = (V)rr;
+        r[t] = rf;
+        if (A.mr) {
+            const double m = group_sum(S.om[p] * (double)rf, P);
+            if (p == 0) A.mr[j] = m;
         }
+        acc[0] += rr * rr;
+        acc[1] += A.bv[t] * A.bv[t];
+        acc[2] += mag * mag;
+        acc[3] += shadow(t) * (double)rf;
     }
-    block_sums(acc, MODE == 0 ? 4 : (MODE == 1 ? 1 : 2), A.part);
+    block_sums(acc, 4, A.part);
 }
 
 // The operator products of the iteration by columns: the grid is cut into tiles
@@ -463,8 +452,11 @@ __global__ void __launch_bounds__(B2) apply2d_kernel(VecArgs A)
 // registers, so that a row costs three new loads of x instead of nine and the
 // shared face coefficient of two rows one, and it loads the next row's values
 // and coefficients before it computes the current row (their latency overlaps
-// the arithmetic).  The arithmetic is that of apply_at.  A block takes tiles
-// blockIdx.x, + gridDim.x, ...; its partial sums go to part[k * KRYB + blockIdx.x].
+// the arithmetic).  Per (cell, pair): y = (Lambda - g W1) x_p + g (W1 x_p -
+// sum_q omega_q x_q) + k div O(x) with O(x) the part of faces() linear in x (the
+// coupling referred to the cell's first pair, exact for a nearly isotropic x).
+// A block takes tiles blockIdx.x, + gridDim.x, ...; its partial sums go to
+// part[k * KRYB + blockIdx.x].  The products are stored as V.
 // MODE 1: v = A ph, partial (h, v) and, with the isotropic correction, the moment
 // of v;  MODE 2: t = A sh, partial (t, s), (t, t)
 constexpr int OP_ROWS = 16;
@@ -486,7 +478,7 @@ __device__ __forceinline__ void block_sums_at(double *vals, int k, double *part,
     }
 }
 
-template <int MODE>
+template <int MODE, class V>
 __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, int ntile)
 {
     if (A.fl[F_STATE] != 0) return;
@@ -494,7 +486,9 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
     const int P = S.P, lgP = S.lgP, nx = S.nx, ny = S.ny;
     const int c = threadIdx.x >> lgP, p = threadIdx.x & (P - 1);
     const int cw = B2 >> lgP, rs = nx * P;
-    const double *xv = MODE == 1 ? A.ph : A.sh;
+    const V *xv = (const V *)(MODE == 1 ? A.ph : A.sh);
+    const V *sa = (const V *)A.s;
+    V *out = (V *)(MODE == 1 ? A.v : A.t);
     const double mu = S.mu[p], eta = S.eta[p], w = S.om[p];
     const double sx = mu > 0.0 ? 1.0 : -1.0, sy = eta > 0.0 ? 1.0 : -1.0;
     double acc[2] = {0.0, 0.0};
@@ -505,7 +499,7 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
         const int iy0 = ty * OP_ROWS, iy1 = min(iy0 + OP_ROWS, ny);
         const int o0 = max(ix - 1, 0) * P + p, o1 = ix * P + p, o2 = min(ix + 1, nx - 1) * P + p;
         auto ldrow = [&](int row, double(&v)[3]) {
-            const double *q = xv + row * rs;
+            const V *q = xv + row * rs;
             v[0] = q[o0];
             v[1] = q[o1];
             v[2] = q[o2];
@@ -517,7 +511,7 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
         int j = iy0 * nx + ix;
         double gl = S.gx[j + iy0], gr = S.gx[j + iy0 + 1], gb = S.gy[j], gt = S.gy[j + nx];
         double dm = S.dmg[j], cgv = S.cg[j], kc = S.kco[j];
-        double sv = MODE == 2 ? A.s[j * P + p] : 0.0;
+        double sv = MODE == 2 ? (double)sa[j * P + p] : 0.0;
         for (int iy = iy0; iy < iy1; ++iy) {
             // the next row's loads (row indices clamped in range; unused after
             // the tile's last row)
@@ -526,8 +520,8 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
             ldrow(min(iy + 2, ny - 1), xn);
             const double gln = S.gx[jn + yn], grn = S.gx[jn + yn + 1], gtn = S.gy[jn + nx];
             const double dmn = S.dmg[jn], cgn = S.cg[jn], kcn = S.kco[jn];
-            const double svn = MODE == 2 ? A.s[jn * P + p] : 0.0;
-            // row iy: faces<false, true> and apply_at with the coefficients in registers
+            const double svn = MODE == 2 ? (double)sa[jn * P + p] : 0.0;
+            // row iy: faces<false, true> with the coefficients in registers
             const Grad g = face_grad(X, mu, eta, S, iy, ix);
             Grad O;
             O.l = -gl * g.l;
@@ -554,17 +548,17 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
                 y = dm * xp + cgv * cpl + kc * div;
             }
             const int t = j * P + p;
+            const double yf = (double)(V)y;         // the stored product
+            out[t] = (V)y;
             if (MODE == 1) {
-                A.v[t] = y;
                 if (A.mv) {
-                    const double m = group_sum(w * y, P);
+                    const double m = group_sum(w * yf, P);
                     if (p == 0) A.mv[j] = m;
                 }
-                acc[0] += shadow(t) * y;
+                acc[0] += shadow(t) * yf;
             } else {
-                A.t[t] = y;
-                acc[0] += y * sv;
-                acc[1] += y * y;
+                acc[0] += yf * sv;
+                acc[1] += yf * yf;
             }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -611,25 +605,37 @@ __device__ __forceinline__ double block_idiag(const Sys &S, int j, int p)
 // the system-dependent parts of each cell's block inverse, once per solve:
 // 1 / d_p for every (cell, pair) and, with angular coupling (the prediction),
 // the Sherman-Morrison scalar g / (1 - g sum_p omega_p / d_p) of the cell
-__global__ void __launch_bounds__(B2) pgc2d_kernel(Sys S, double *idg, double *pgc, size_t n)
+// (1/d_p in binary64 and binary32; *narrow cleared where a cell's denominator
+// is below KRY_F32_GAP)
+__global__ void __launch_bounds__(B2) pgc2d_kernel(Sys S, double *idg, float *idg32, double *pgc, int *narrow,
+                                                   size_t n)
 {
     const int P = S.P;
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) {
         const int j = t >> S.lgP, p = t & (P - 1);
         const double id = block_idiag(S, j, p);
         idg[t] = id;
+        idg32[t] = (float)id;
         if (S.corr) continue;
         const double s2 = group_sum(S.om[p] * id, P);
         const double g = S.cg[j];
-        if (p == 0) pgc[j] = g / (1.0 - g * s2);
+        const double den = 1.0 - g * s2;
+        if (p == 0) {
+            pgc[j] = g / den;
+            if (!(den >= KRY_F32_GAP)) *narrow = 0;
+        }
     }
+}
+
+__global__ void set_int_kernel(int *a, int v)
+{
+    if (threadIdx.x == 0) *a = v;
 }
 
 // cell-block Jacobi: z = B^{-1} y, B = diag(d_p) - g 1 omega^T (Sherman-Morrison);
 // the correction's blocks have g = 0 and are diagonal
-__device__ __forceinline__ double precond_at(const Sys &S, double y, int t, int j, int p)
+__device__ __forceinline__ double precond_at(const Sys &S, double y, double id, int j, int p)
 {
-    const double id = S.idg[t];
     const double u = y * id;
     if (S.corr) return u;
     const double s1 = group_sum(S.om[p] * u, S.P);
@@ -637,30 +643,36 @@ __device__ __forceinline__ double precond_at(const Sys &S, double y, int t, int 
 }
 
 // p = r + beta (p - omega v); ph = B^{-1} p (+ dP)
+template <class V>
 __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double beta = A.sc[S_BETA], omega = A.sc[S_OMEGA];
     const int P = A.S.P;
+    const V *r = (const V *)A.r, *v = (const V *)A.v, *idg = (const V *)A.idg;
+    V *pp = (V *)A.p, *ph = (V *)A.ph;
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
         const int j = t >> A.S.lgP, p = t & (P - 1);
-        const double pv = A.r[t] + beta * (A.p[t] - omega * A.v[t]);
-        A.p[t] = pv;
-        A.ph[t] = precond_at(A.S, pv, t, j, p) + (A.dP ? A.dP[j] : 0.0);
+        const V pv = (V)((double)r[t] + beta * ((double)pp[t] - omega * (double)v[t]));
+        pp[t] = pv;
+        ph[t] = (V)(precond_at(A.S, pv, idg[t], j, p) + (A.dP ? A.dP[j] : 0.0));
     }
 }
 
 // s = r - alpha v; sh = B^{-1} s (+ dS)
+template <class V>
 __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double alpha = A.sc[S_ALPHA];
     const int P = A.S.P;
+    const V *r = (const V *)A.r, *v = (const V *)A.v, *idg = (const V *)A.idg;
+    V *sa = (V *)A.s, *sh = (V *)A.sh;
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
         const int j = t >> A.S.lgP, p = t & (P - 1);
-        const double sv = A.r[t] - alpha * A.v[t];
-        A.s[t] = sv;
-        A.sh[t] = precond_at(A.S, sv, t, j, p) + (A.dS ? A.dS[j] : 0.0);
+        const V sv = (V)((double)r[t] - alpha * (double)v[t]);
+        sa[t] = sv;
+        sh[t] = (V)(precond_at(A.S, sv, idg[t], j, p) + (A.dS ? A.dS[j] : 0.0));
     }
 }
 
@@ -679,17 +691,21 @@ __global__ void __launch_bounds__(B2) ymom2d_kernel(VecArgs A, int which, int n)
 
 // x += alpha ph + omega sh (one pass over x); r = s - omega t (and its moment);
 // partial (h, r), (r, r)
+template <class V>
 __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double alpha = A.sc[S_ALPHA], omega = A.sc[S_OMEGA];
     const int P = A.S.P;
+    const V *ph = (const V *)A.ph, *sh = (const V *)A.sh, *sa = (const V *)A.s, *ta = (const V *)A.t;
+    V *r = (V *)A.r;
     double acc[2] = {0.0, 0.0};
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
         const int j = t >> A.S.lgP, p = t & (P - 1);
-        A.x[t] += alpha * A.ph[t] + omega * A.sh[t];
-        const double rv = A.s[t] - omega * A.t[t];
-        A.r[t] = rv;
+        A.x[t] += alpha * (double)ph[t] + omega * (double)sh[t];
+        const V rs = (V)((double)sa[t] - omega * (double)ta[t]);
+        r[t] = rs;
+        const double rv = rs;
         if (A.mr) {
             const double m = group_sum(A.S.om[p] * rv, P);
             if (p == 0) A.mr[j] = m;
@@ -1105,6 +1121,7 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
         if (threadIdx.x == 0) {
             sc[S_RHO] = hr;
             sc[S_RR] = rr;
+            sc[S_R0] = rr;
             sc[S_BB] = bb;
             sc[S_MM] = mm;
             sc[S_ALPHA] = sc[S_OMEGA] = 1.0;
@@ -1134,10 +1151,12 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
             const int its = A.fl[F_ITS] + 1;
             A.fl[F_ITS] = its;
             sc[S_RR] = rr;
-            if (!(rr <= A.tol * A.tol * sc[S_BB]) && its >= A.maxit) {
+            const double rec = A.rec * A.tol;
+            const bool done = rr <= rec * rec * sc[S_BB] || rr <= A.pass_red * A.pass_red * sc[S_R0];
+            if (!done && its >= A.maxit) {
                 A.fl[F_STATE] = 3;
-            } else if (rr <= A.tol * A.tol * sc[S_BB]) {
-                A.fl[F_STATE] = 1;
+            } else if (done) {
+                A.fl[F_STATE] = 1;              // the end of the pass
             } else if (sc[S_OMEGA] == 0.0 || rho == 0.0 || !isfinite(rho)) {
                 A.fl[F_STATE] = 2;
             } else {
@@ -1151,6 +1170,13 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
 __global__ void __launch_bounds__(B2) zero2_kernel(double *a, double *b, size_t n)
 {
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) a[t] = b[t] = 0.0;
+}
+
+template <class V>
+__global__ void __launch_bounds__(B2) zero2v_kernel(void *av, void *bv, size_t n)
+{
+    V *a = (V *)av, *b = (V *)bv;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) a[t] = b[t] = (V)0;
 }
 
 __global__ void reset_flags_kernel(int *fl)
@@ -1527,8 +1553,14 @@ struct grte2d_ctx {
     double *acU = nullptr, *beta = nullptr, *ustar = nullptr, *Dv = nullptr, *rhon = nullptr;
     double *sab = nullptr, *ue = nullptr;
     // Krylov
-    double *bv = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *ph = nullptr;
-    double *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr, *Es = nullptr;
+    double *bv = nullptr, *x = nullptr, *Es = nullptr;
+    // the Krylov vectors: binary64 arrays, used as binary32 ones when the
+    // solve's vectors are narrow
+    double *r = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr;
+    int *narrow = nullptr;               // the solve's vectors are binary32 (set per solve)
+    int narrow_ok = 1;                   // binary32 Krylov vectors allowed (grte2d_set_krylov_storage)
+    int last_narrow[2] = {-1, -1};       // the storage of the last prediction / correction solve
+    int narrow_used[2] = {0, 0};         // (reported in the step info)
     double *part = nullptr, *part2 = nullptr, *sc = nullptr;
     int *fl = nullptr, *stat = nullptr;
     int *h_fl = nullptr;      // pinned
@@ -1548,7 +1580,8 @@ struct grte2d_ctx {
     // isotropic correction of the preconditioner
     int iso_kind = 1;                    // 0 none, 1 Chebyshev (tiled), 2 multigrid V-cycle, 3 Chebyshev per step
     int iso_k = 19;                      // Chebyshev steps (two tiled launches)
-    int last_its[2] = {-1, -1};          // iterations of the last prediction / correction solve (-1: none yet)
+    // iterations of each pass of the last prediction / correction solve (-1: none yet)
+    int last_its[2][KRY_RESTARTS + 1];
     int mg_nu = 2;                       // multigrid: Jacobi sweeps before and after the coarse correction
     struct Lv {
         MgRows R;
@@ -1566,6 +1599,7 @@ struct grte2d_ctx {
     double *tguess = nullptr;            // learned starting values of the temperature solve
     unsigned *ecnt = nullptr;
     double *idg = nullptr;               // per-(cell, pair) inverse diagonal of the block inverse
+    float *idg32 = nullptr;              // the same in binary32
     double *mr = nullptr, *mv = nullptr;  // angular moments of r and v (isotropic correction)
     double *idir2 = nullptr;             // second Chebyshev direction buffer of the tiled launches
     // sampled timing of the operator kernel (first iteration of every chunk)
@@ -1647,7 +1681,6 @@ Sys make_sys(grte2d_ctx *c, int corr, double eps)
     S.sab = c->sab;
     S.ue = c->ue;
     S.pgc = c->pgc;
-    S.idg = c->idg;
     return S;
 }
 
@@ -1805,7 +1838,8 @@ void iso_solve(grte2d_ctx *c, const Sys &S, const double *y, double *out, hipStr
 // BiCGStab on the system currently described by the coefficient arrays; x holds
 // the start and receives the solution.  Returns iterations, state and the
 // final true relative residual.
-grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, double &res_out, int &floor_out)
+template <class V>
+grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, double &res_out, int &floor_out)
 {
     int floor = 0;
     VecArgs A;
@@ -1821,6 +1855,17 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     A.s = c->s;
     A.sh = c->sh;
     A.t = c->t;
+    const bool narrow = sizeof(V) == 4;
+    A.idg = narrow ? (const void *)c->idg32 : (const void *)c->idg;
+    // binary32 passes end at KRY_PASS_RED of their starting residual, with the
+    // recursion run on to KRY_REC of the tolerance; binary64 passes at the tolerance
+    A.pass_red = narrow ? KRY_PASS_RED : 0.0;
+    A.rec = narrow ? KRY_REC : 1.0;
+    // the pass lengths of the last solve of this kind size the batches when it
+    // had the same storage
+    if (c->last_narrow[S.corr] != (int)narrow)
+        for (int &n : c->last_its[S.corr]) n = -1;
+    c->last_narrow[S.corr] = narrow;
     A.part = c->part;
     A.part2 = c->part2;
     A.sc = c->sc;
@@ -1830,7 +1875,6 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     // the isotropic correction targets the angular coupling of the prediction;
     // the correction's systems have none
     const bool iso = c->iso_kind != 0 && !S.corr;
-    hipLaunchKernelGGL(pgc2d_kernel, dim3(nblocks(c->nE)), dim3(B2), 0, c->stream, S, c->idg, c->pgc, c->nE);
     if (iso && c->iso_kind == 2) mg_setup(c, S, c->stream);
     A.dP = iso ? c->dP : nullptr;
     A.dS = iso ? c->dS : nullptr;
@@ -1854,15 +1898,17 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     };
     int its_total = 0, state = 0;
     // iterations are enqueued in batches between convergence checks; the
-    // batches are sized to end where the last solve of the same kind ended
-    // (iteration counts change slowly from step to step), and iterations
-    // enqueued past convergence return at once
+    // batches are sized to end where the same pass of the last solve of the
+    // same kind ended (iteration counts change slowly from step to step), and
+    // iterations enqueued past the end of a pass return at once
     double res = INFINITY;
+    int pass_its[KRY_RESTARTS + 1];
+    for (int k = 0; k <= KRY_RESTARTS; ++k) pass_its[k] = -1;
     for (int restart = 0; restart <= KRY_RESTARTS; ++restart) {
         hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
-        hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
+        hipLaunchKernelGGL(residual2d_kernel<V>, dim3(nb), dim3(B2), 0, st, A);
         fin(0, 4, nb);
-        hipLaunchKernelGGL(zero2_kernel, dim3(nb), dim3(B2), 0, st, c->p, c->v, c->nE);
+        hipLaunchKernelGGL(zero2v_kernel<V>, dim3(nb), dim3(B2), 0, st, (void *)c->p, (void *)c->v, c->nE);
         // the moments of p and v start from zero with them
         if (iso) hipLaunchKernelGGL(zero2_kernel, dim3(nbc), dim3(B2), 0, st, c->yP, c->mv, c->N);
         if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1891,7 +1937,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
         int inpass = 0;                    // iterations enqueued in this pass
         while (true) {
             const bool timed = c->profiling != 0;
-            const int last = c->last_its[S.corr], left = last - (its_total + inpass);
+            const int last = c->last_its[S.corr][restart], left = last - inpass;
             const int batch = last < 0 ? CHUNK : (left >= 1 ? std::min(CHUNK, left) : 2);
             inpass += batch;
             for (int k = 0; k < batch; ++k) {
@@ -1899,19 +1945,19 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
                     hipLaunchKernelGGL(ymom2d_kernel, dim3(nbc), dim3(B2), 0, st, A, 0, (int)c->N);
                     iso_solve(c, S, c->yP, c->dP, st);
                 }
-                hipLaunchKernelGGL(pupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(pupd2d_kernel<V>, dim3(nb), dim3(B2), 0, st, A);
                 if (timed && k == 0) (void)hipEventRecord(c->ev0, st);
-                hipLaunchKernelGGL(apply2d_col_kernel<1>, dim3(nbo), dim3(B2), 0, st, A, ncol, ntile);
+                hipLaunchKernelGGL((apply2d_col_kernel<1, V>), dim3(nbo), dim3(B2), 0, st, A, ncol, ntile);
                 if (timed && k == 0) (void)hipEventRecord(c->ev1, st);
                 fin(1, 1, nbo);
                 if (iso) {
                     hipLaunchKernelGGL(ymom2d_kernel, dim3(nbc), dim3(B2), 0, st, A, 1, (int)c->N);
                     iso_solve(c, S, c->yS, c->dS, st);
                 }
-                hipLaunchKernelGGL(supd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
-                hipLaunchKernelGGL(apply2d_col_kernel<2>, dim3(nbo), dim3(B2), 0, st, A, ncol, ntile);
+                hipLaunchKernelGGL(supd2d_kernel<V>, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL((apply2d_col_kernel<2, V>), dim3(nbo), dim3(B2), 0, st, A, ncol, ntile);
                 fin(2, 2, nbo);
-                hipLaunchKernelGGL(xupd2d_kernel, dim3(nb), dim3(B2), 0, st, A);
+                hipLaunchKernelGGL(xupd2d_kernel<V>, dim3(nb), dim3(B2), 0, st, A);
                 fin(3, 2, nb);
             }
             if (hipGetLastError() != hipSuccess) return GRTE_E_HIP;
@@ -1928,12 +1974,13 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             if (c->h_fl[F_STATE] != 0) break;
         }
         its_total += c->h_fl[F_ITS];
+        pass_its[restart] = c->h_fl[F_ITS];
         // the recursion's residual has met the tolerance (or broken down): the
         // next pass recomputes the true residual and restarts from it if needed
         if (c->h_fl[F_STATE] == 3 && its_total >= c->maxit) {
             // one more true residual for the report
             hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
-            hipLaunchKernelGGL(apply2d_kernel<0>, dim3(nb), dim3(B2), 0, st, A);
+            hipLaunchKernelGGL(residual2d_kernel<V>, dim3(nb), dim3(B2), 0, st, A);
             fin(0, 4, nb);
             if (hipMemcpyAsync(c->h_sc, c->sc, S_NS * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GRTE_E_HIP;
@@ -1943,12 +1990,34 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
             break;
         }
     }
-    c->last_its[S.corr] = its_total;
+    for (int k = 0; k <= KRY_RESTARTS; ++k) c->last_its[S.corr][k] = pass_its[k];
     its_out = its_total;
     state_out = state;
     res_out = res;
     floor_out = floor;
     return GRTE_OK;
+}
+
+// BiCGStab on the system currently described by the coefficient arrays, with
+// binary32 Krylov vectors where allowed and where the block inverse is well
+// enough conditioned for them (every cell's Sherman-Morrison denominator at
+// least KRY_F32_GAP; the correction's blocks are diagonal), else binary64 ones
+grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, double &res_out, int &floor_out)
+{
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, st, c->narrow, c->narrow_ok);
+    hipLaunchKernelGGL(pgc2d_kernel, dim3(nblocks(c->nE)), dim3(B2), 0, st, S, c->idg, c->idg32, c->pgc, c->narrow,
+                       c->nE);
+    int narrow = c->narrow_ok;
+    if (narrow && !S.corr) {
+        if (hipMemcpyAsync(c->h_fl, c->narrow, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+            return GRTE_E_HIP;
+        if (hipStreamSynchronize(st) != hipSuccess) return GRTE_E_HIP;
+        narrow = c->h_fl[0];
+    }
+    c->narrow_used[S.corr] = narrow;
+    return narrow ? krylov_run<float>(c, S, its_out, state_out, res_out, floor_out)
+                  : krylov_run<double>(c, S, its_out, state_out, res_out, floor_out);
 }
 
 }  // namespace
@@ -1984,6 +2053,8 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
         if (!(eta[p] > 0.0) || mu[p] == 0.0 || !(omega[p] > 0.0)) return GRTE_E_INVAL;
     grte2d_ctx *c = new (std::nothrow) grte2d_ctx();
     if (!c) return GRTE_E_NOMEM;
+    for (auto &kind : c->last_its)
+        for (int &n : kind) n = -1;
     c->nx = pb->nx;
     c->ny = pb->ny;
     c->P = P;
@@ -2044,7 +2115,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   }
                   return true;
               }() &&
-              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->idg32, c->nE) && dalloc(c, c->narrow, 1) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
@@ -2181,6 +2252,13 @@ grte_status grte2d_set_launch_shape(grte2d_ctx *c, int items_per_thread, int fir
         return GRTE_E_INVAL;
     c->kry_items = items_per_thread;
     c->red_b = first_level;
+    return GRTE_OK;
+}
+
+grte_status grte2d_set_krylov_storage(grte2d_ctx *c, int narrow)
+{
+    if (!c || (narrow != 0 && narrow != 1)) return GRTE_E_INVAL;
+    c->narrow_ok = narrow;
     return GRTE_OK;
 }
 
@@ -2343,6 +2421,7 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     if (s != GRTE_OK) return s;
     inf.pred_iters = its;
     inf.pred_converged = state == 1;
+    inf.pred_narrow = c->narrow_used[0];
     inf.pred_residual = res;
     inf.pred_floor_stop = floor;
     if (hipMemcpyAsync(c->Es, c->x, c->nE * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -2413,6 +2492,7 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     if (s != GRTE_OK) return s;
     inf.corr_iters = its;
     inf.corr_converged = state == 1;
+    inf.corr_narrow = c->narrow_used[1];
     inf.corr_residual = res;
     inf.corr_floor_stop = floor;
 

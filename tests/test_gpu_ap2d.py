@@ -89,14 +89,22 @@ CASES = [  # nx, ny, nv, m, eps, seed
 ]
 
 
+@pytest.mark.parametrize("narrow", [True, False])
 @pytest.mark.parametrize("nx,ny,nv,m,eps,seed", CASES)
-def test_one_step_matches_oracle(nx, ny, nv, m, eps, seed):
+def test_one_step_matches_oracle(nx, ny, nv, m, eps, seed, narrow):
+    """Both storages of the Krylov vectors: binary32 where the solve allows it
+    (the default) and binary64 throughout."""
     w = random_state_2d(nx, ny, nv, seed, m=m, eps=eps)
     g = _ctx(w)
+    g.set_krylov_storage(narrow)
     r, info = gpu_step(g, w, w.E, w.Ox, w.Oy, w.T)
     g.close()
     assert info["status"] == 0, info
     assert info["pred_converged"] and info["corr_converged"], info
+    # the correction's blocks are diagonal: binary32 whenever allowed
+    assert info["corr_narrow"] == int(narrow), info
+    if not narrow:
+        assert info["pred_narrow"] == 0, info
     o, bar = oracle_with_bars(w, w.E, w.Ox, w.Oy, w.T)
     _compare(w, r, o, w.T, bar)
 
