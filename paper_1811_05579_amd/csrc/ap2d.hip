@@ -634,13 +634,24 @@ __global__ void set_int_kernel(int *a, int v)
 
 // cell-block Jacobi: z = B^{-1} y, B = diag(d_p) - g 1 omega^T (Sherman-Morrison);
 // the correction's blocks have g = 0 and are diagonal
-__device__ __forceinline__ double precond_at(const Sys &S, double y, double id, int j, int p)
+// (id = 1/d_p of the item, pg = the cell's g / (1 - g sum_p omega_p / d_p),
+// wp = omega_p)
+__device__ __forceinline__ double precond_at(const Sys &S, double y, double id, double pg, double wp)
 {
     const double u = y * id;
     if (S.corr) return u;
-    const double s1 = group_sum(S.om[p] * u, S.P);
-    return u + S.pgc[j] * s1 * id;
+    const double s1 = group_sum(wp * u, S.P);
+    return u + pg * s1 * id;
 }
+
+// The vector updates take KI items per thread and loop trip (items t, t + G,
+// t + 2G, ... for a grid of G threads, the order of the grid-stride loop they
+// replace): every load of a trip is issued before its arithmetic and stores,
+// through restrict-qualified pointers, so that one wave keeps several
+// independent loads in flight.  Items past the end read item t (always in
+// range) and store nothing; a cell's P lanes are in or out together, so the
+// angular sums stay within whole cells.
+constexpr int KI = 4;
 
 // p = r + beta (p - omega v); ph = B^{-1} p (+ dP)
 template <class V>
@@ -648,14 +659,36 @@ __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double beta = A.sc[S_BETA], omega = A.sc[S_OMEGA];
-    const int P = A.S.P;
-    const V *r = (const V *)A.r, *v = (const V *)A.v, *idg = (const V *)A.idg;
-    V *pp = (V *)A.p, *ph = (V *)A.ph;
-    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
-        const int j = t >> A.S.lgP, p = t & (P - 1);
-        const V pv = (V)((double)r[t] + beta * ((double)pp[t] - omega * (double)v[t]));
-        pp[t] = pv;
-        ph[t] = (V)(precond_at(A.S, pv, idg[t], j, p) + (A.dP ? A.dP[j] : 0.0));
+    const int P = A.S.P, lgP = A.S.lgP, n = (int)A.n, G = gridDim.x * B2;
+    const V *__restrict__ r = (const V *)A.r;
+    const V *__restrict__ v = (const V *)A.v;
+    const V *__restrict__ idg = (const V *)A.idg;
+    V *__restrict__ pp = (V *)A.p;
+    V *__restrict__ ph = (V *)A.ph;
+    const double *__restrict__ dP = A.dP;
+    const double *__restrict__ pgc = A.S.pgc;
+    // the pair of every item of this thread (G is a multiple of P)
+    const double wp = A.S.om[(blockIdx.x * B2 + threadIdx.x) & (P - 1)];
+    for (int t0 = blockIdx.x * B2 + threadIdx.x; t0 < n; t0 += KI * G) {
+        double rv[KI], pv[KI], vv[KI], id[KI], dd[KI], pg[KI];
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int t = t0 + k * G < n ? t0 + k * G : t0;
+            rv[k] = r[t];
+            pv[k] = pp[t];
+            vv[k] = v[t];
+            id[k] = idg[t];
+            dd[k] = dP ? dP[t >> lgP] : 0.0;
+            pg[k] = A.S.corr ? 0.0 : pgc[t >> lgP];
+        }
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int t = t0 + k * G;
+            if (t >= n) break;
+            const V pn = (V)(rv[k] + beta * (pv[k] - omega * vv[k]));
+            pp[t] = pn;
+            ph[t] = (V)(precond_at(A.S, pn, id[k], pg[k], wp) + dd[k]);
+        }
     }
 }
 
@@ -665,14 +698,35 @@ __global__ void __launch_bounds__(B2) supd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double alpha = A.sc[S_ALPHA];
-    const int P = A.S.P;
-    const V *r = (const V *)A.r, *v = (const V *)A.v, *idg = (const V *)A.idg;
-    V *sa = (V *)A.s, *sh = (V *)A.sh;
-    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
-        const int j = t >> A.S.lgP, p = t & (P - 1);
-        const V sv = (V)((double)r[t] - alpha * (double)v[t]);
-        sa[t] = sv;
-        sh[t] = (V)(precond_at(A.S, sv, idg[t], j, p) + (A.dS ? A.dS[j] : 0.0));
+    const int P = A.S.P, lgP = A.S.lgP, n = (int)A.n, G = gridDim.x * B2;
+    const V *__restrict__ r = (const V *)A.r;
+    const V *__restrict__ v = (const V *)A.v;
+    const V *__restrict__ idg = (const V *)A.idg;
+    V *__restrict__ sa = (V *)A.s;
+    V *__restrict__ sh = (V *)A.sh;
+    const double *__restrict__ dS = A.dS;
+    const double *__restrict__ pgc = A.S.pgc;
+    // the pair of every item of this thread (G is a multiple of P)
+    const double wp = A.S.om[(blockIdx.x * B2 + threadIdx.x) & (P - 1)];
+    for (int t0 = blockIdx.x * B2 + threadIdx.x; t0 < n; t0 += KI * G) {
+        double rv[KI], vv[KI], id[KI], dd[KI], pg[KI];
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int t = t0 + k * G < n ? t0 + k * G : t0;
+            rv[k] = r[t];
+            vv[k] = v[t];
+            id[k] = idg[t];
+            dd[k] = dS ? dS[t >> lgP] : 0.0;
+            pg[k] = A.S.corr ? 0.0 : pgc[t >> lgP];
+        }
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int t = t0 + k * G;
+            if (t >= n) break;
+            const V sv = (V)(rv[k] - alpha * vv[k]);
+            sa[t] = sv;
+            sh[t] = (V)(precond_at(A.S, sv, id[k], pg[k], wp) + dd[k]);
+        }
     }
 }
 
@@ -696,22 +750,43 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
     const double alpha = A.sc[S_ALPHA], omega = A.sc[S_OMEGA];
-    const int P = A.S.P;
-    const V *ph = (const V *)A.ph, *sh = (const V *)A.sh, *sa = (const V *)A.s, *ta = (const V *)A.t;
-    V *r = (V *)A.r;
+    const int P = A.S.P, lgP = A.S.lgP, n = (int)A.n, G = gridDim.x * B2;
+    const V *__restrict__ ph = (const V *)A.ph;
+    const V *__restrict__ sh = (const V *)A.sh;
+    const V *__restrict__ sa = (const V *)A.s;
+    const V *__restrict__ ta = (const V *)A.t;
+    V *__restrict__ r = (V *)A.r;
+    double *__restrict__ x = A.x;
     double acc[2] = {0.0, 0.0};
-    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)A.n; t += gridDim.x * B2) {
-        const int j = t >> A.S.lgP, p = t & (P - 1);
-        A.x[t] += alpha * (double)ph[t] + omega * (double)sh[t];
-        const V rs = (V)((double)sa[t] - omega * (double)ta[t]);
-        r[t] = rs;
-        const double rv = rs;
-        if (A.mr) {
-            const double m = group_sum(A.S.om[p] * rv, P);
-            if (p == 0) A.mr[j] = m;
+    // the pair of every item of this thread (G is a multiple of P)
+    const double wp = A.S.om[(blockIdx.x * B2 + threadIdx.x) & (P - 1)];
+    for (int t0 = blockIdx.x * B2 + threadIdx.x; t0 < n; t0 += KI * G) {
+        double xv[KI], pv[KI], hv[KI], sv[KI], tv[KI];
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int t = t0 + k * G < n ? t0 + k * G : t0;
+            xv[k] = x[t];
+            pv[k] = ph[t];
+            hv[k] = sh[t];
+            sv[k] = sa[t];
+            tv[k] = ta[t];
         }
-        acc[0] += shadow(t) * rv;
-        acc[1] += rv * rv;
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const int t = t0 + k * G;
+            if (t >= n) break;
+            const int j = t >> lgP, p = t & (P - 1);
+            x[t] = xv[k] + (alpha * pv[k] + omega * hv[k]);
+            const V rs = (V)(sv[k] - omega * tv[k]);
+            r[t] = rs;
+            const double rv = rs;
+            if (A.mr) {
+                const double m = group_sum(wp * rv, P);
+                if (p == 0) A.mr[j] = m;
+            }
+            acc[0] += shadow(t) * rv;
+            acc[1] += rv * rv;
+        }
     }
     block_sums(acc, 2, A.part);
 }
