@@ -843,27 +843,47 @@ __device__ __forceinline__ double iso_diag(const IsoArgs &A, int iy, int ix, int
     return S.W1 * S.dmg[j] + k * (cx * (g.l + g.r) + cy * (g.b + g.t) + ed);
 }
 
-// (D x)_cell from the cell's value and its neighbours' (0 beyond a wall)
-__device__ __forceinline__ double iso_Dx(const IsoArgs &A, double k, double diag, const Faces &g, double xc,
-                                         double xl, double xr, double xb, double xt)
+// A cell's Jacobi-scaled row: the Chebyshev steps need r = (y - D x) / diag,
+// formed as y / diag - x_c + sum_nb w_nb x_nb with w_nb = k c g_nb / diag
+// (c = M h^-2 of the face's direction; 0 beyond a wall), the weights held per
+// cell for all of a launch's steps
+struct IsoRow {
+    double diag, rdg, wl, wr, wb, wt;
+};
+
+__device__ __forceinline__ IsoRow iso_row_coefs(const IsoArgs &A, int iy, int ix, int j, double gl, double gr,
+                                                double gb, double gt)
 {
     const Sys &S = A.S;
+    const Faces g = iso_walls(S, iy, ix, Faces{gl, gr, gb, gt});
+    IsoRow R;
+    R.diag = iso_diag(A, iy, ix, j, g);
+    R.rdg = 1.0 / R.diag;
+    const double k = S.kco[j];
     const double cx = A.Mxx * S.idx * S.idx, cy = A.Myy * S.idy * S.idy;
-    return diag * xc - k * (cx * (g.l * xl + g.r * xr) + cy * (g.b * xb + g.t * xt));
+    R.wl = k * cx * g.l * R.rdg;
+    R.wr = k * cx * g.r * R.rdg;
+    R.wb = k * cy * g.b * R.rdg;
+    R.wt = k * cy * g.t * R.rdg;
+    return R;
 }
 
-__device__ __forceinline__ void iso_row(const IsoArgs &A, int j, const double *x, double &Dx, double &diag)
+// (y - D x) / diag from y / diag, the cell's value and its neighbours' (0 beyond a wall)
+// (no contraction into fused multiply-adds: the tiled and the per-step kernels
+// then round every term alike, whatever the code around them)
+__device__ __forceinline__ double iso_jres(double yr, double wl, double wr, double wb, double wt, double xc,
+                                           double xl, double xr, double xb, double xt)
+{
+#pragma clang fp contract(off)
+    return (yr - xc) + ((wl * xl + wr * xr) + (wb * xb + wt * xt));
+}
+
+__device__ __forceinline__ IsoRow iso_row_at(const IsoArgs &A, int j, int &iy, int &ix)
 {
     const Sys &S = A.S;
-    int iy, ix;
     cell_yx(S, j, iy, ix);
     const int fl = iy * (S.nx + 1) + ix, fb = iy * S.nx + ix;
-    const Faces g = iso_walls(S, iy, ix, Faces{S.gx[fl], S.gx[fl + 1], S.gy[fb], S.gy[fb + S.nx]});
-    diag = iso_diag(A, iy, ix, j, g);
-    const double xc = x[j];
-    const double xl = ix > 0 ? x[j - 1] : 0.0, xr = ix < S.nx - 1 ? x[j + 1] : 0.0;
-    const double xb = iy > 0 ? x[j - S.nx] : 0.0, xt = iy < S.ny - 1 ? x[j + S.nx] : 0.0;
-    Dx = iso_Dx(A, S.kco[j], diag, g, xc, xl, xr, xb, xt);
+    return iso_row_coefs(A, iy, ix, j, S.gx[fl], S.gx[fl + 1], S.gy[fb], S.gy[fb + S.nx]);
 }
 
 // first step: x1 = d0 = (y / diag) / theta
@@ -872,9 +892,9 @@ __global__ void __launch_bounds__(B2) iso_first_kernel(IsoArgs A)
     if (A.fl[F_STATE] != 0) return;
     const int n = A.S.nx * A.S.ny;
     for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
-        double Dx, diag;
-        iso_row(A, j, A.y, Dx, diag);       // only the diagonal is used here
-        const double d0 = A.y[j] / (diag * A.th);
+        int iy, ix;
+        const IsoRow R = iso_row_at(A, j, iy, ix);
+        const double d0 = A.y[j] / (R.diag * A.th);
         A.d[j] = d0;
         A.xout[j] = d0;
     }
@@ -884,29 +904,34 @@ __global__ void __launch_bounds__(B2) iso_first_kernel(IsoArgs A)
 __global__ void __launch_bounds__(B2) iso_step_kernel(IsoArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
-    const int n = A.S.nx * A.S.ny;
+    const Sys &S = A.S;
+    const int n = S.nx * S.ny;
     for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
-        double Dx, diag;
-        iso_row(A, j, A.xin, Dx, diag);
-        const double r = (A.y[j] - Dx) * (1.0 / diag);
+        int iy, ix;
+        const IsoRow R = iso_row_at(A, j, iy, ix);
+        const double *x = A.xin;
+        const double xc = x[j];
+        const double xl = ix > 0 ? x[j - 1] : 0.0, xr = ix < S.nx - 1 ? x[j + 1] : 0.0;
+        const double xb = iy > 0 ? x[j - S.nx] : 0.0, xt = iy < S.ny - 1 ? x[j + S.nx] : 0.0;
+        const double r = iso_jres(A.y[j] * R.rdg, R.wl, R.wr, R.wb, R.wt, xc, xl, xr, xb, xt);
         const double dn = A.c1 * A.d[j] + A.c2 * r;
         A.d[j] = dn;
-        A.xout[j] = A.xin[j] + dn;
+        A.xout[j] = xc + dn;
     }
 }
 
 // Up to ISO_HALO stencil steps of the Chebyshev map in one launch, preceded
 // by the local first step (first = 1) or continuing from a stored iterate and
 // direction.  A block owns a tile of ISO_T x ISO_T cells and works on the tile
-// plus a halo of as many cells as it takes stencil steps: the iterate and the
-// face values sit in LDS, each cell's own values (y, diagonal, k, the
-// Chebyshev direction) in registers.  Stencil step s updates the region cells
+// plus a halo of as many cells as it takes stencil steps: the iterate sits in
+// LDS, each cell's own values (its Jacobi-scaled row, y / diag, the Chebyshev
+// direction) in registers.  Stencil step s updates the region cells
 // at least s + 1 cells inside its border (their neighbours hold step-s
 // values), so after the launch's steps the tile's cells are exact; cells
 // outside the grid are never read (their neighbours' weights are zero and
 // their values taken as 0, as in the per-step form).  The arithmetic is the
 // per-step kernels' own, term for term, so the result is the same to the bit.
-constexpr int ISO_T = 32, ISO_HALO = 9, ISO_RMAX = ISO_T + 2 * ISO_HALO, ISO_TB = 512;
+constexpr int ISO_T = 32, ISO_HALO = 9, ISO_RMAX = ISO_T + 2 * ISO_HALO, ISO_TB = 1024;
 constexpr int ISO_CPT = (ISO_RMAX * ISO_RMAX + ISO_TB - 1) / ISO_TB;
 
 struct IsoFused {
@@ -918,7 +943,7 @@ struct IsoFused {
     double c1[ISO_HALO], c2[ISO_HALO];
 };
 
-__global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
+__global__ void __launch_bounds__(ISO_TB, 8) iso_fused_kernel(IsoFused F)
 {
     const IsoArgs &A = F.A;
     if (A.fl[F_STATE] != 0) return;
@@ -926,30 +951,17 @@ __global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
     const int h = F.nsteps, R = ISO_T + 2 * h;
     const int ox = blockIdx.x * ISO_T - h, oy = blockIdx.y * ISO_T - h;   // grid position of region cell (0, 0)
     __shared__ double X[ISO_RMAX * ISO_RMAX];
-    __shared__ double GX[ISO_RMAX * (ISO_RMAX + 1)];     // x-faces: row ry, face fx = left face of region cell fx
-    __shared__ double GY[(ISO_RMAX + 1) * ISO_RMAX];     // y-faces: face row fy = bottom face of region row fy
     const int t = threadIdx.x;
-    for (int f = t; f < R * (R + 1); f += ISO_TB) {
-        const int ry = f / (R + 1), fx = f - ry * (R + 1);
-        const int iy = oy + ry, ix = ox + fx;
-        GX[f] = (iy >= 0 && iy < S.ny && ix >= 0 && ix <= S.nx) ? S.gx[iy * (S.nx + 1) + ix] : 0.0;
-    }
-    for (int f = t; f < (R + 1) * R; f += ISO_TB) {
-        const int fy = f / R, rx = f - fy * R;
-        const int iy = oy + fy, ix = ox + rx;
-        GY[f] = (iy >= 0 && iy <= S.ny && ix >= 0 && ix < S.nx) ? S.gy[iy * S.nx + ix] : 0.0;
-    }
-    __syncthreads();
-    // per cell: its own values in registers, and its region position packed as
-    // rx | ry << 8 | (depth + 1) << 16, depth = distance to the region's border
-    // (-1: outside the region or the grid), so that stencil step s updates the
-    // cells of depth > s and the tile is the cells of depth >= h
-    double y[ISO_CPT], dg[ISO_CPT], rdg[ISO_CPT], kc[ISO_CPT], d[ISO_CPT], xn[ISO_CPT];
+    // per cell: its Jacobi-scaled row and y / diag in registers, and its region
+    // position packed as rx | ry << 8 | (depth + 1) << 16, depth = distance to
+    // the region's border (-1: outside the region or the grid), so that stencil
+    // step s updates the cells of depth > s and the tile is the cells of depth >= h
+    double yr[ISO_CPT], wl[ISO_CPT], wr[ISO_CPT], wb[ISO_CPT], wt[ISO_CPT], d[ISO_CPT], xn[ISO_CPT];
     int pk[ISO_CPT];
 #pragma unroll
     for (int i = 0; i < ISO_CPT; ++i) {
         const int c = t + i * ISO_TB;
-        y[i] = dg[i] = rdg[i] = kc[i] = d[i] = xn[i] = 0.0;
+        yr[i] = wl[i] = wr[i] = wb[i] = wt[i] = d[i] = xn[i] = 0.0;
         pk[i] = 0;
         if (c >= R * R) continue;
         const int ry = c / R, rx = c - ry * R;
@@ -957,15 +969,16 @@ __global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
         if (iy < 0 || iy >= S.ny || ix < 0 || ix >= S.nx) continue;
         const int dep = min(min(rx, R - 1 - rx), min(ry, R - 1 - ry));
         pk[i] = rx | (ry << 8) | ((dep + 1) << 16);
-        const int j = iy * S.nx + ix;
-        const Faces g = iso_walls(S, iy, ix, Faces{GX[ry * (R + 1) + rx], GX[ry * (R + 1) + rx + 1],
-                                                    GY[ry * R + rx], GY[(ry + 1) * R + rx]});
-        dg[i] = iso_diag(A, iy, ix, j, g);
-        rdg[i] = 1.0 / dg[i];
-        kc[i] = S.kco[j];
-        y[i] = A.y[j];
+        const int j = iy * S.nx + ix, fl = iy * (S.nx + 1) + ix;
+        const IsoRow Rw = iso_row_coefs(A, iy, ix, j, S.gx[fl], S.gx[fl + 1], S.gy[j], S.gy[j + S.nx]);
+        wl[i] = Rw.wl;
+        wr[i] = Rw.wr;
+        wb[i] = Rw.wb;
+        wt[i] = Rw.wt;
+        const double y = A.y[j];
+        yr[i] = y * Rw.rdg;
         if (F.first) {
-            d[i] = y[i] / (dg[i] * A.th);   // the first step: x1 = d0
+            d[i] = y / (Rw.diag * A.th);   // the first step: x1 = d0
             xn[i] = d[i];
         } else {
             d[i] = F.din[j];
@@ -986,13 +999,10 @@ __global__ void __launch_bounds__(ISO_TB) iso_fused_kernel(IsoFused F)
             const int c = t + i * ISO_TB;
             const int rx = pk[i] & 0xff, ry = (pk[i] >> 8) & 0xff;
             const int iy = oy + ry, ix = ox + rx;
-            const Faces g = iso_walls(S, iy, ix, Faces{GX[ry * (R + 1) + rx], GX[ry * (R + 1) + rx + 1],
-                                                        GY[ry * R + rx], GY[(ry + 1) * R + rx]});
             const double xc = X[c];
             const double xl = ix > 0 ? X[c - 1] : 0.0, xr = ix < S.nx - 1 ? X[c + 1] : 0.0;
             const double xb = iy > 0 ? X[c - R] : 0.0, xt = iy < S.ny - 1 ? X[c + R] : 0.0;
-            const double Dx = iso_Dx(A, kc[i], dg[i], g, xc, xl, xr, xb, xt);
-            const double r = (y[i] - Dx) * rdg[i];
+            const double r = iso_jres(yr[i], wl[i], wr[i], wb[i], wt[i], xc, xl, xr, xb, xt);
             const double dn = c1 * d[i] + c2 * r;
             d[i] = dn;
             xn[i] = xc + dn;
