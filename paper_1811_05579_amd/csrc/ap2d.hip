@@ -304,6 +304,7 @@ struct VecArgs {
     // pass of iterations ends when the recursion has reduced the residual by
     // KRY_PASS_RED, and the next starts from the binary64 true residual
     void *r, *p, *ph, *v, *s, *sh, *t;
+    void *dx;                  // the pass's correction of x (added to x when the pass ends)
     const void *idg;
     double pass_red, rec;      // a pass ends at pass_red x its start, or at rec x tol
     double *part;              // [k * KRYB + block]
@@ -743,7 +744,8 @@ __global__ void __launch_bounds__(B2) ymom2d_kernel(VecArgs A, int which, int n)
     }
 }
 
-// x += alpha ph + omega sh (one pass over x); r = s - omega t (and its moment);
+// dx += alpha ph + omega sh (the pass's correction of x, stored as V and added
+// to the binary64 x when the pass ends); r = s - omega t (and its moment);
 // partial (h, r), (r, r)
 template <class V>
 __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
@@ -756,7 +758,7 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
     const V *__restrict__ sa = (const V *)A.s;
     const V *__restrict__ ta = (const V *)A.t;
     V *__restrict__ r = (V *)A.r;
-    double *__restrict__ x = A.x;
+    V *__restrict__ dx = (V *)A.dx;
     double acc[2] = {0.0, 0.0};
     // the pair of every item of this thread (G is a multiple of P)
     const double wp = A.S.om[(blockIdx.x * B2 + threadIdx.x) & (P - 1)];
@@ -765,7 +767,7 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
             const int t = t0 + k * G < n ? t0 + k * G : t0;
-            xv[k] = x[t];
+            xv[k] = dx[t];
             pv[k] = ph[t];
             hv[k] = sh[t];
             sv[k] = sa[t];
@@ -776,7 +778,7 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
             const int t = t0 + k * G;
             if (t >= n) break;
             const int j = t >> lgP, p = t & (P - 1);
-            x[t] = xv[k] + (alpha * pv[k] + omega * hv[k]);
+            dx[t] = (V)(xv[k] + (alpha * pv[k] + omega * hv[k]));
             const V rs = (V)(sv[k] - omega * tv[k]);
             r[t] = rs;
             const double rv = rs;
@@ -1258,10 +1260,18 @@ __global__ void __launch_bounds__(B2) zero2_kernel(double *a, double *b, size_t 
 }
 
 template <class V>
-__global__ void __launch_bounds__(B2) zero2v_kernel(void *av, void *bv, size_t n)
+__global__ void __launch_bounds__(B2) zero3v_kernel(void *av, void *bv, void *cv, size_t n)
 {
-    V *a = (V *)av, *b = (V *)bv;
-    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) a[t] = b[t] = (V)0;
+    V *a = (V *)av, *b = (V *)bv, *c = (V *)cv;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) a[t] = b[t] = c[t] = (V)0;
+}
+
+// x += dx at the end of a pass
+template <class V>
+__global__ void __launch_bounds__(B2) xadd_kernel(double *x, const void *dv, size_t n)
+{
+    const V *d = (const V *)dv;
+    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) x[t] += (double)d[t];
 }
 
 __global__ void reset_flags_kernel(int *fl)
@@ -1642,6 +1652,7 @@ struct grte2d_ctx {
     // the Krylov vectors: binary64 arrays, used as binary32 ones when the
     // solve's vectors are narrow
     double *r = nullptr, *p = nullptr, *ph = nullptr, *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr;
+    double *dxv = nullptr;
     int *narrow = nullptr;               // the solve's vectors are binary32 (set per solve)
     int narrow_ok = 1;                   // binary32 Krylov vectors allowed (grte2d_set_krylov_storage)
     int last_narrow[2] = {-1, -1};       // the storage of the last prediction / correction solve
@@ -1940,6 +1951,7 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
     A.s = c->s;
     A.sh = c->sh;
     A.t = c->t;
+    A.dx = c->dxv;
     const bool narrow = sizeof(V) == 4;
     A.idg = narrow ? (const void *)c->idg32 : (const void *)c->idg;
     // binary32 passes end at KRY_PASS_RED of their starting residual, with the
@@ -1993,7 +2005,8 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
         hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
         hipLaunchKernelGGL(residual2d_kernel<V>, dim3(nb), dim3(B2), 0, st, A);
         fin(0, 4, nb);
-        hipLaunchKernelGGL(zero2v_kernel<V>, dim3(nb), dim3(B2), 0, st, (void *)c->p, (void *)c->v, c->nE);
+        hipLaunchKernelGGL(zero3v_kernel<V>, dim3(nb), dim3(B2), 0, st, (void *)c->p, (void *)c->v, (void *)c->dxv,
+                           c->nE);
         // the moments of p and v start from zero with them
         if (iso) hipLaunchKernelGGL(zero2_kernel, dim3(nbc), dim3(B2), 0, st, c->yP, c->mv, c->N);
         if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -2060,6 +2073,7 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
         }
         its_total += c->h_fl[F_ITS];
         pass_its[restart] = c->h_fl[F_ITS];
+        hipLaunchKernelGGL(xadd_kernel<V>, dim3(nb), dim3(B2), 0, st, c->x, (const void *)c->dxv, c->nE);
         // the recursion's residual has met the tolerance (or broken down): the
         // next pass recomputes the true residual and restarts from it if needed
         if (c->h_fl[F_STATE] == 3 && its_total >= c->maxit) {
@@ -2200,7 +2214,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   }
                   return true;
               }() &&
-              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->idg32, c->nE) && dalloc(c, c->narrow, 1) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->idg32, c->nE) && dalloc(c, c->dxv, c->nE) && dalloc(c, c->narrow, 1) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
