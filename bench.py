@@ -58,12 +58,13 @@ TRAFFIC = {
     ("config2", "fp64"): (9.2663e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
     ("config2", "fp32"): (None, None),
     ("config4", "fp64"): (None, None),
-    ("config4", "fp32"): (1.6948e10, "profiles/batch_step_config4_hbm_traffic.txt"),
+    ("config4", "fp32"): (1.6091e10, "profiles/batch_step_config4_hbm_traffic.txt"),
     ("config4-solve", "fp64"): (None, None),
-    ("config4-solve", "fp32"): (8.4490e9, "profiles/batch_step_config4_hbm_traffic.txt"),
-    ("config3", "fp64"): (3.417e8, "profiles/apply2d_config3_hbm_traffic.txt"),
-    ("config3", "fp32"): (3.417e8, "profiles/apply2d_config3_hbm_traffic.txt"),   # Krylov vectors are binary64 either way
-    ("config5", "fp64"): (1.767e8, "profiles/apply2d_config5_hbm_traffic.txt"),
+    ("config4-solve", "fp32"): (8.3813e9, "profiles/batch_step_config4_hbm_traffic.txt"),
+    # the timed 2-D operator launches have binary32 Krylov vectors whatever the state storage
+    ("config3", "fp64"): (2.2082e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config3", "fp32"): (2.2082e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config5", "fp64"): (1.0641e8, "profiles/apply2d_config5_hbm_traffic.txt"),
 }
 
 
@@ -318,12 +319,13 @@ def main_batch(args):
 
 
 def op2d_algorithmic_bytes(N, P):
-    """Bytes the 2-D operator kernel (v = A p-hat) must move at least once per
-    launch: read the preconditioned direction and write the product (N*P each,
-    FP64) and read five N-sized cell and face coefficient arrays (the
-    prediction's launches also write the product's angular moment, N values,
-    left out here)."""
-    return 8 * (2 * N * P + 5 * N)
+    """Bytes the 2-D operator kernel (v = A p-hat, the launches the library
+    times: those with binary32 Krylov vectors) must move at least once per
+    launch: read the preconditioned direction and write the product (N*P
+    binary32 values each) and read five N-sized binary64 cell and face
+    coefficient arrays (the prediction's launches also write the product's
+    angular moment, N values, left out here)."""
+    return 4 * 2 * N * P + 8 * 5 * N
 
 
 def cpu_baseline_2d(w, budget_s=20.0, n=32):
@@ -427,7 +429,8 @@ def main_2d(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "apply2d_kernel<1> (matrix-free operator product of the Krylov iteration)",
+            "kernel": "apply2d_col_kernel<1, float> (matrix-free operator product of the Krylov iteration, "
+                      "binary32 vectors)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -716,9 +716,10 @@ grte_status grte2d_step(grte2d_ctx *ctx, double dt, double eps, grte2d_step_info
 
 /* Timing of the operator kernel (the matrix-free product inside the Krylov
  * iterations, the step's dominant kernel): with on != 0, HIP events on the
- * context's stream bracket the first product of every batch of eight
- * iterations; grte2d_read_timing returns the summed milliseconds and the
- * number of timed launches since the last grte2d_set_profiling call. */
+ * context's stream bracket the first product of every batch of iterations of
+ * the solves with binary32 Krylov vectors (grte2d_set_krylov_storage);
+ * grte2d_read_timing returns the summed milliseconds and the number of timed
+ * launches since the last grte2d_set_profiling call. */
 grte_status grte2d_set_profiling(grte2d_ctx *ctx, int on);
 grte_status grte2d_read_timing(grte2d_ctx *ctx, double *ms, int *count);
 

@@ -2034,7 +2034,7 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
         A.maxit = c->maxit - its_total;    // the cap holds for the whole solve
         int inpass = 0;                    // iterations enqueued in this pass
         while (true) {
-            const bool timed = c->profiling != 0;
+            const bool timed = c->profiling != 0 && narrow;   // the binary32 products only
             const int last = c->last_its[S.corr][restart], left = last - inpass;
             const int batch = last < 0 ? CHUNK : (left >= 1 ? std::min(CHUNK, left) : 2);
             inpass += batch;
