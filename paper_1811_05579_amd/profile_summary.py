@@ -13,6 +13,13 @@
   python3 profile_summary.py --launches RUN_results.db KERNEL_SUBSTRING MIN_US
       count, mean, min, max duration of the matching kernel's launches that
       took at least MIN_US microseconds.
+  python3 profile_summary.py --pmc-steps FETCH_CSV WRITE_CSV FETCH_SCALE WRITE_SCALE MARK FROM TO [PER]
+      HBM bytes per step from one FETCH_SIZE and one WRITE_SIZE run of the same
+      program: every dispatch (all kernels) from the FROM-th to before the TO-th
+      dispatch of the kernel whose name contains MARK (0-based; TO past the last
+      one: to the end of the run), KiB x 1024 x the copy-calibrated scale,
+      summed per kernel and divided by the steps, (TO - FROM) / PER for PER
+      dispatches of MARK per step (default 1).
   python3 profile_summary.py --window RUN_results.db KERNEL_SUBSTRING FIRST COUNT
       durations of COUNT launches of the matching kernel, in launch order,
       starting at launch FIRST (negative: counted from the last launch), e.g.
@@ -92,6 +99,43 @@ def summarise_pmc(csv_path, kernel_substring, vmin=None):
     return "\n".join(lines) if lines else f"no '{kernel_substring}' dispatches in {csv_path}"
 
 
+def _short(name):
+    name = name.replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(", 1)[0]
+
+
+def summarise_pmc_steps(fetch_csv, write_csv, fetch_scale, write_scale, mark, first, last, per_step=1):
+    steps = (last - first) / per_step
+    out = []
+    per = {}
+    totals = {}
+    for counter, path, scale in (("FETCH_SIZE", fetch_csv, fetch_scale), ("WRITE_SIZE", write_csv, write_scale)):
+        rows = {}
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                d = int(row["Dispatch_Id"])
+                if d not in rows:
+                    rows[d] = [row["Kernel_Name"], 0.0]
+                rows[d][1] += float(row["Counter_Value"])
+        marks = sorted(d for d, (k, _) in rows.items() if mark in k)
+        lo, hi = marks[first], (marks[last] if last < len(marks) else max(rows) + 1)
+        tot = 0.0
+        for d, (k, v) in rows.items():
+            if lo <= d < hi:
+                b = v * 1024.0 * scale / steps
+                per.setdefault(_short(k), [0.0, 0.0])[0 if counter == "FETCH_SIZE" else 1] += b
+                tot += b
+        totals[counter] = tot
+    out.append(f"{'kernel':44s} {'read B/step':>12s} {'write B/step':>12s} {'total':>12s}")
+    for k, (r, w) in sorted(per.items(), key=lambda kv: -(kv[1][0] + kv[1][1])):
+        out.append(f"{k[:44]:44s} {r:12.4e} {w:12.4e} {r + w:12.4e}")
+    out.append(f"{'per step':44s} {totals['FETCH_SIZE']:12.4e} {totals['WRITE_SIZE']:12.4e} "
+               f"{totals['FETCH_SIZE'] + totals['WRITE_SIZE']:12.4e}  ({steps} steps)")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if len(sys.argv) < 2 or sys.argv[1] in ("-h", "--help"):
         print(__doc__)
@@ -99,6 +143,9 @@ if __name__ == "__main__":
         print(summarise_window(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5])))
     elif len(sys.argv) >= 2 and sys.argv[1] == "--launches":
         print(summarise_launches(sys.argv[2], sys.argv[3], float(sys.argv[4])))
+    elif sys.argv[1] == "--pmc-steps":
+        print(summarise_pmc_steps(sys.argv[2], sys.argv[3], float(sys.argv[4]), float(sys.argv[5]), sys.argv[6],
+                                  int(sys.argv[7]), int(sys.argv[8]), int(sys.argv[9]) if len(sys.argv) > 9 else 1))
     elif len(sys.argv) >= 2 and sys.argv[1] == "--pmc":
         print(summarise_pmc(sys.argv[2], sys.argv[3], float(sys.argv[4]) if len(sys.argv) > 4 else None))
     else:
