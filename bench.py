@@ -282,6 +282,10 @@ def main_batch(args):
             "energy_defect_max_rel": max(abs(i["energy_defect"]) / max(abs(i["energy_before"]),
                                                                        abs(i["energy_after"]), 1e-300)
                                          for i in infos),
+            # the defect is the extra term of (3.13), which vanishes with eps: the
+            # largest values come from the slabs with eps near 1
+            "energy_defect_note": "E^{n+1} - E^n + outflow*dt per slab over max(E^n, E^{n+1}); the "
+                                  "extra term of (3.13), O(eps^2), largest on the eps ~ 1 slabs",
         },
         "roofline": {
             "bound": "hbm",
