@@ -1382,14 +1382,15 @@ __global__ void __launch_bounds__(B2) guess2d_kernel(GuessArgs A)
     }
 }
 
-template <bool GUESS>
-__global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
+// The prediction's moments, one thread per (cell, pair): rho* = sum_p omega_p
+// E*_p, rho^n, the flux divergence D of the prediction's face values and, at
+// the domain's edges, the outflow through the cell's edge faces (the face
+// values are those whose divergence is D; interior faces cancel in the sum of D)
+__global__ void __launch_bounds__(B2) moments2d_kernel(NewtArgs A)
 {
-    int acc = 0, unused = 0, started = 0;
     const Sys &S = A.S;
     const int P = S.P;
     const size_t n = (size_t)S.nx * S.ny * P;
-    int mx = 0, sum = 0, failed = 0, clamped = 0, neg = 0;
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) {
         const int j = t >> S.lgP, p = t & (P - 1);
         int iy, ix;
@@ -1401,8 +1402,6 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
         const double D = group_sum(w * divergence(S, O, p), P);
         const double rhs_s = group_sum(w * X.v[1][1], P);
         const double rn = group_sum(w * A.En[t], P);
-        // outflow through the domain's edge faces of this cell (the face values
-        // are those whose divergence is D; interior faces cancel in the sum of D)
         double fo = 0.0;
         if (ix == S.nx - 1) fo += S.mu[p] * O.r * S.dy;
         if (ix == 0) fo -= S.mu[p] * O.l * S.dy;
@@ -1411,15 +1410,29 @@ __global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
         const double fout = group_sum(w * fo, P);
         if (p != 0) continue;
         if (ix == 0 || iy == 0 || ix == S.nx - 1 || iy == S.ny - 1) A.bflux[j] = fout;
+        A.Dv[j] = D;
+        A.rhon[j] = rn;
+        A.rstar[j] = rhs_s;
+    }
+}
+
+// U* of (4.5c) and the temperature of (4.13), one thread per cell (from the
+// moments above)
+template <bool GUESS>
+__global__ void __launch_bounds__(B2) newton2d_kernel(NewtArgs A)
+{
+    int acc = 0, unused = 0, started = 0;
+    const Sys &S = A.S;
+    const int n = S.nx * S.ny;
+    int mx = 0, sum = 0, failed = 0, clamped = 0, neg = 0;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        const double D = A.Dv[j], rn = A.rhon[j], rhs_s = A.rstar[j];
         const double ac = A.a * A.c;
         const double Tn = A.Tn[j];
         const double Un = Tn * Tn * Tn * Tn;
         const double beta = A.beta[j];
         const double us = (Un + beta * rhs_s) / (1.0 + ac * beta);
         A.ustar[j] = us;
-        A.Dv[j] = D;
-        A.rhon[j] = rn;
-        A.rstar[j] = rhs_s;
         double Ks = 1.0;
         if (A.m == 3) {
             if (us < 0.0) {
@@ -2549,8 +2562,9 @@ grte_status grte2d_step(grte2d_ctx *c, double dt, double eps, grte2d_step_info *
     na.bflux = c->bflux;
     na.tg = c->tguess;
     na.gtol = c->guess_tol;
-    // (fewer, longer-lived blocks: one atomic per wavefront and counter)
-    const int nbn = std::min(nb, 2048);
+    hipLaunchKernelGGL(moments2d_kernel, dim3(kblocks(c->nE, KRY_ITEMS)), dim3(B2), 0, st, na);
+    // (one thread per cell; fewer, longer-lived blocks: one atomic per wavefront and counter)
+    const int nbn = std::min(nbc, 2048);
     if (c->guess_w) {
         GuessArgs ga;
         ga.n = (int)c->N;
