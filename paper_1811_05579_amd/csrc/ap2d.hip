@@ -53,6 +53,7 @@ constexpr int MAXB = 2048;     // blocks of the grid-stride kernels outside the 
 // partials per block of the first level, then one block) when there are more
 // than RED_B of them (both figures can be set per context)
 constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = 2048;
+constexpr int OPC_N = 8;       // doubles per cell of the operator's packed coefficients (opc2d_kernel)
 constexpr int CHUNK = 8;       // most BiCGStab iterations enqueued between convergence checks
 constexpr int KRY_RESTARTS = 12;     // restarts from the true residual per solve
 // a pass of binary32-stored iterations ends once the recursion's residual is
@@ -89,6 +90,7 @@ struct Sys {
     const double *rb1, *rb0, *acU;       // rhs = rb1 E^n_p + rb0; acU (correction's known part)
     const double *sab, *ue;              // residual in difference form (see residual_at)
     const double *pgc;                   // cell: g / (1 - g sum_p omega_p / d_p) of the block inverse
+    const double *opc;                   // cell: the operator's coefficients packed, OPC_N per cell (opc2d_kernel)
 };
 
 // (iy, ix) of cell j without an integer division: the binary64 product is off
@@ -510,8 +512,13 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
         ldrow(iy0, X.v[1]);
         ldrow(min(iy0 + 1, ny - 1), X.v[2]);
         int j = iy0 * nx + ix;
-        double gl = S.gx[j + iy0], gr = S.gx[j + iy0 + 1], gb = S.gy[j], gt = S.gy[j + nx];
-        double dm = S.dmg[j], cgv = S.cg[j], kc = S.kco[j];
+        auto ldc = [&](int jj, double2(&c)[4]) {
+            const double2 *q = (const double2 *)(S.opc + (size_t)OPC_N * jj);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = q[k];
+        };
+        double2 cf[4];
+        ldc(j, cf);
         double sv = MODE == 2 ? (double)sa[j * P + p] : 0.0;
         for (int iy = iy0; iy < iy1; ++iy) {
             // the next row's loads (row indices clamped in range; unused after
@@ -519,16 +526,17 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
             const int yn = min(iy + 1, ny - 1), jn = yn * nx + ix;
             double xn[3];
             ldrow(min(iy + 2, ny - 1), xn);
-            const double gln = S.gx[jn + yn], grn = S.gx[jn + yn + 1], gtn = S.gy[jn + nx];
-            const double dmn = S.dmg[jn], cgn = S.cg[jn], kcn = S.kco[jn];
+            double2 cfn[4];
+            ldc(jn, cfn);
             const double svn = MODE == 2 ? (double)sa[jn * P + p] : 0.0;
             // row iy: faces<false, true> with the coefficients in registers
+            const double dm = cf[0].x, cgv = cf[0].y, kc = cf[1].x;
             const Grad g = face_grad(X, mu, eta, S, iy, ix);
             Grad O;
-            O.l = -gl * g.l;
-            O.r = -gr * g.r;
-            O.b = -gb * g.b;
-            O.t = -gt * g.t;
+            O.l = -cf[2].x * g.l;
+            O.r = -cf[2].y * g.r;
+            O.b = -cf[3].x * g.b;
+            O.t = -cf[3].y * g.t;
             const double xp = X.v[1][1];
             const double k2 = S.k2;
             auto edge = [&](double sg) {
@@ -568,13 +576,8 @@ __global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, in
                 X.v[2][k] = xn[k];
             }
             j = jn;
-            gl = gln;
-            gr = grn;
-            gb = gt;
-            gt = gtn;
-            dm = dmn;
-            cgv = cgn;
-            kc = kcn;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cf[k] = cfn[k];
             sv = svn;
         }
     }
@@ -631,6 +634,25 @@ __global__ void __launch_bounds__(B2) pgc2d_kernel(Sys S, double *idg, float *id
 __global__ void set_int_kernel(int *a, int v)
 {
     if (threadIdx.x == 0) *a = v;
+}
+
+// The coefficients the operator products read per cell and row, packed once per
+// solve so that a row takes four 16-byte loads instead of six 8-byte ones:
+// {Lambda - g W1, g, k, 0, gamma of the left, right, bottom and top faces}
+
+__global__ void __launch_bounds__(B2) opc2d_kernel(Sys S, double *opc)
+{
+    const int n = S.nx * S.ny;
+    for (int j = blockIdx.x * B2 + threadIdx.x; j < n; j += gridDim.x * B2) {
+        int iy, ix;
+        cell_yx(S, j, iy, ix);
+        const int fl = j + iy;
+        double2 *q = (double2 *)(opc + (size_t)OPC_N * j);
+        q[0] = make_double2(S.dmg[j], S.cg[j]);
+        q[1] = make_double2(S.kco[j], 0.0);
+        q[2] = make_double2(S.gx[fl], S.gx[fl + 1]);
+        q[3] = make_double2(S.gy[j], S.gy[j + S.nx]);
+    }
 }
 
 // cell-block Jacobi: z = B^{-1} y, B = diag(d_p) - g 1 omega^T (Sherman-Morrison);
@@ -1709,6 +1731,7 @@ struct grte2d_ctx {
     unsigned *ecnt = nullptr;
     double *idg = nullptr;               // per-(cell, pair) inverse diagonal of the block inverse
     float *idg32 = nullptr;              // the same in binary32
+    double *opc = nullptr;               // the operator's packed per-cell coefficients (OPC_N per cell)
     double *mr = nullptr, *mv = nullptr;  // angular moments of r and v (isotropic correction)
     double *idir2 = nullptr;             // second Chebyshev direction buffer of the tiled launches
     // sampled timing of the operator kernel (first iteration of every chunk)
@@ -1755,6 +1778,7 @@ int kblocks(size_t n, int items)
 Sys make_sys(grte2d_ctx *c, int corr, double eps)
 {
     Sys S;
+    S.opc = nullptr;                     // (set where the operator products run)
     S.nx = c->nx;
     S.ny = c->ny;
     S.P = c->P;
@@ -1953,6 +1977,7 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
     int floor = 0;
     VecArgs A;
     A.S = S;
+    A.S.opc = c->opc;
     A.n = c->nE;
     A.En = c->E;
     A.bv = c->bv;
@@ -2120,6 +2145,7 @@ grte_status krylov(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out, do
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, st, c->narrow, c->narrow_ok);
     hipLaunchKernelGGL(pgc2d_kernel, dim3(nblocks(c->nE)), dim3(B2), 0, st, S, c->idg, c->idg32, c->pgc, c->narrow,
                        c->nE);
+    hipLaunchKernelGGL(opc2d_kernel, dim3(nblocks(c->N)), dim3(B2), 0, st, S, c->opc);
     int narrow = c->narrow_ok;
     if (narrow && !S.corr) {
         if (hipMemcpyAsync(c->h_fl, c->narrow, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -2227,7 +2253,7 @@ grte_status grte2d_create(const grte2d_problem *pb, const double *mu, const doub
                   }
                   return true;
               }() &&
-              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->idg32, c->nE) && dalloc(c, c->dxv, c->nE) && dalloc(c, c->narrow, 1) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
+              dalloc(c, c->dS, c->N) && dalloc(c, c->itmp, c->N) && dalloc(c, c->idir, c->N) && dalloc(c, c->idir2, c->N) && dalloc(c, c->pgc, c->N) && dalloc(c, c->idg, c->nE) && dalloc(c, c->idg32, c->nE) && dalloc(c, c->opc, OPC_N * c->N) && dalloc(c, c->dxv, c->nE) && dalloc(c, c->narrow, 1) && dalloc(c, c->mr, c->N) && dalloc(c, c->mv, c->N) &&
               dalloc(c, c->x, c->nE) && dalloc(c, c->r, c->nE) &&
               dalloc(c, c->p, c->nE) && dalloc(c, c->ph, c->nE) && dalloc(c, c->v, c->nE) &&
               dalloc(c, c->s, c->nE) && dalloc(c, c->sh, c->nE) && dalloc(c, c->t, c->nE) &&
