@@ -62,9 +62,9 @@ TRAFFIC = {
     ("config4-solve", "fp64"): (None, None),
     ("config4-solve", "fp32"): (8.3813e9, "profiles/batch_step_config4_hbm_traffic.txt"),
     # the timed 2-D operator launches have binary32 Krylov vectors whatever the state storage
-    ("config3", "fp64"): (None, None),
-    ("config3", "fp32"): (None, None),
-    ("config5", "fp64"): (None, None),
+    ("config3", "fp64"): (2.3909e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config3", "fp32"): (2.3909e8, "profiles/apply2d_config3_hbm_traffic.txt"),
+    ("config5", "fp64"): (9.8288e7, "profiles/apply2d_config5_hbm_traffic.txt"),
 }
 
 
