@@ -528,8 +528,7 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
     const int N = I.N, P = I.P, N1 = N + 1;
     const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
     const int j0 = k * M;
-    const double eps = I.eps;
-    const double *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
+    const double *Tn = A.T + I.oT;
     BState<F32> S;
     S.P = I.P;
     S.N = I.N;
@@ -539,8 +538,7 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
     S.O = F32 ? nullptr : A.O + I.oO;
     S.E32 = F32 ? A.E32 + I.oE : nullptr;
     S.O32 = F32 ? A.O32 + I.oO : nullptr;
-    const double *mu = A.mu + I.oP, *om = A.omega + I.oP, *bL = A.bL + I.oP, *bR = A.bR + I.oP;
-    double *T2 = A.T2 + I.oT;
+    const double *mu = A.mu + I.oP, *om = A.omega + I.oP;
     double *C = A.cells + I.oC;
     // Per-pair global arrays are pair-major in cell order: thread k's rows
     // j0 .. j0+M-1 are contiguous, so its loads and stores are wide and the
@@ -840,8 +838,7 @@ __device__ __forceinline__ void corr_solve(const BatchArgs &A, int i, double *sm
     const int N = I.N, P = I.P, N1 = N + 1;
     const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
     const int j0 = k * M;
-    const double eps = I.eps;
-    const double *Tn = A.T + I.oT, *sg = A.sigma0 + I.oT;
+    const double *Tn = A.T + I.oT;
     BState<F32> S;
     S.P = I.P;
     S.N = I.N;
@@ -851,15 +848,13 @@ __device__ __forceinline__ void corr_solve(const BatchArgs &A, int i, double *sm
     S.O = F32 ? nullptr : A.O + I.oO;
     S.E32 = F32 ? A.E32 + I.oE : nullptr;
     S.O32 = F32 ? A.O32 + I.oO : nullptr;
-    const double *mu = A.mu + I.oP, *om = A.omega + I.oP, *bL = A.bL + I.oP, *bR = A.bR + I.oP;
-    double *T2 = A.T2 + I.oT;
+    const double *mu = A.mu + I.oP;
     double *C = A.cells + I.oC;
     // Per-pair global arrays are pair-major in cell order: thread k's rows
     // j0 .. j0+M-1 are contiguous, so its loads and stores are wide and the
     // later per-cell phases read along cells.
     double *Rt = A.pairs + I.oR;                  // right-hand sides
     double *Et = Rt + (size_t)P * I.NPa;          // E* (prediction), then E^{n+1} (correction)
-    int *st = A.istat + 8 * i;
     constexpr bool WG = (W == BNT);
     constexpr int LM = WG ? 4 * M : M;
     auto lpos = [](int j) { return (j % LM) * 64 + j / LM; };
