@@ -1026,13 +1026,17 @@ __global__ void __launch_bounds__(BNT) solve_kernel(BatchArgs A)
         if constexpr (PH == 0) {
             switch (A.inst[i].M) {
             case 2: pred_solve<BNT, 2, F32>(A, i, smem); break;
+            case 3: pred_solve<BNT, 3, F32>(A, i, smem); break;
             case 4: pred_solve<BNT, 4, F32>(A, i, smem); break;
+            case 6: pred_solve<BNT, 6, F32>(A, i, smem); break;
             default: pred_solve<BNT, 8, F32>(A, i, smem); break;
             }
         } else {
             switch (A.inst[i].M) {
             case 2: corr_solve<BNT, 2, F32>(A, i, smem); break;
+            case 3: corr_solve<BNT, 3, F32>(A, i, smem); break;
             case 4: corr_solve<BNT, 4, F32>(A, i, smem); break;
+            case 6: corr_solve<BNT, 6, F32>(A, i, smem); break;
             default: corr_solve<BNT, 8, F32>(A, i, smem); break;
             }
         }
@@ -1101,6 +1105,18 @@ int pow2_rows(int N, int W)
     int M = 2;
     while (W * M < N) M *= 2;
     return M;
+}
+
+// rows per thread of a slab's tile: a wavefront tile takes 2 or 4 (powers of
+// two), a work-group tile the smallest of 2, 3, 4, 6, 8 whose 256 M rows hold
+// the slab -- the padding rows cost as much as real ones, and with powers of
+// two alone a third of the solves' rows were padding on slabs of N ~ U{64..2048}
+int tile_rows(int N, int W)
+{
+    if (W != BNT) return pow2_rows(N, W);
+    for (const int M : {2, 3, 4, 6, 8})
+        if (BNT * M >= N) return M;
+    return 8;
 }
 
 }  // namespace
@@ -1195,7 +1211,7 @@ grte_status assign_tiles(grte_batch *b)
             I.W = BNT;
             wg.push_back(i);
         }
-        I.M = pow2_rows(I.N, I.W);
+        I.M = tile_rows(I.N, I.W);
     }
     auto by_cost = [&](int x, int y) { return b->cost[x] > b->cost[y] || (b->cost[x] == b->cost[y] && x < y); };
     std::sort(wg.begin(), wg.end(), by_cost);
@@ -1400,7 +1416,7 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
         I.mu1 = m1;
         I.mu2 = m2;
         I.oE = oE; I.oO = oO; I.oT = oT; I.oP = oP; I.oC = oC; I.oR = oR;
-        I.NPa = (long long)BNT * pow2_rows(I.N, BNT);   // also covers every wavefront tile
+        I.NPa = (long long)BNT * tile_rows(I.N, BNT);   // also covers every wavefront tile (N <= 256)
         oE += (long long)I.N * I.P;
         oO += (long long)(I.N + 1) * I.P;
         oT += I.N;
