@@ -1028,7 +1028,9 @@ __global__ void __launch_bounds__(BNT) solve_kernel(BatchArgs A)
             case 2: pred_solve<BNT, 2, F32>(A, i, smem); break;
             case 3: pred_solve<BNT, 3, F32>(A, i, smem); break;
             case 4: pred_solve<BNT, 4, F32>(A, i, smem); break;
+            case 5: pred_solve<BNT, 5, F32>(A, i, smem); break;
             case 6: pred_solve<BNT, 6, F32>(A, i, smem); break;
+            case 7: pred_solve<BNT, 7, F32>(A, i, smem); break;
             default: pred_solve<BNT, 8, F32>(A, i, smem); break;
             }
         } else {
@@ -1036,7 +1038,9 @@ __global__ void __launch_bounds__(BNT) solve_kernel(BatchArgs A)
             case 2: corr_solve<BNT, 2, F32>(A, i, smem); break;
             case 3: corr_solve<BNT, 3, F32>(A, i, smem); break;
             case 4: corr_solve<BNT, 4, F32>(A, i, smem); break;
+            case 5: corr_solve<BNT, 5, F32>(A, i, smem); break;
             case 6: corr_solve<BNT, 6, F32>(A, i, smem); break;
+            case 7: corr_solve<BNT, 7, F32>(A, i, smem); break;
             default: corr_solve<BNT, 8, F32>(A, i, smem); break;
             }
         }
@@ -1108,15 +1112,15 @@ int pow2_rows(int N, int W)
 }
 
 // rows per thread of a slab's tile: a wavefront tile takes 2 or 4 (powers of
-// two), a work-group tile the smallest of 2, 3, 4, 6, 8 whose 256 M rows hold
-// the slab -- the padding rows cost as much as real ones, and with powers of
-// two alone a third of the solves' rows were padding on slabs of N ~ U{64..2048}
+// two), a work-group tile the smallest M = 2 .. 8 whose 256 M rows hold the
+// slab -- the padding rows cost as much as real ones, and with powers of two
+// alone a third of the solves' rows were padding on slabs of N ~ U{64..2048}
 int tile_rows(int N, int W)
 {
     if (W != BNT) return pow2_rows(N, W);
-    for (const int M : {2, 3, 4, 6, 8})
-        if (BNT * M >= N) return M;
-    return 8;
+    int M = 2;
+    while (BNT * M < N) ++M;
+    return M;
 }
 
 }  // namespace
