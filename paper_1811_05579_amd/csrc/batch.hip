@@ -252,7 +252,7 @@ constexpr int RHS_U = 4;
 
 // ---------------------------------------------------------------------------
 // The per-cell phases run as flat kernels over every cell of every slab (one
-// thread per cell, blocks of 256 cells of one slab, cblk): they stream the
+// thread per cell, blocks of CB cells of one slab, cblk): they stream the
 // state and the pair scratch, and at the occupancy of a small kernel many more
 // of their memory round trips are in flight than inside the solve kernels,
 // which hold one work-group per CU for their LDS and registers.
@@ -962,9 +962,10 @@ __global__ void __launch_bounds__(256) batch_convert(const BInst *inst, const do
 //   batch_reset, cells_kernel<CP_PRED>, solve_kernel<0>, cells_kernel<CP_NEWTON>,
 //   cells_kernel<CP_CORR>, solve_kernel<1>, cells_kernel<CP_PROJECT>, batch_energy.
 enum { CP_PRED = 0, CP_NEWTON = 1, CP_CORR = 2, CP_PROJECT = 3 };
+constexpr int CB = 128;   // cells per block of the per-cell kernels (a multiple of 64, at most 512)
 
 template <int PH, bool F32>
-__global__ void __launch_bounds__(256) cells_kernel(BatchArgs A)
+__global__ void __launch_bounds__(CB) cells_kernel(BatchArgs A)
 {
     const int2 cb = A.cblk[blockIdx.x];          // (instance, first cell)
     const IView<F32> V = iview<F32>(A, cb.x);
@@ -1000,13 +1001,30 @@ __global__ void __launch_bounds__(256) cells_kernel(BatchArgs A)
         if (in) cell_project(A, V, j, eb, ea);
         // the block's sums (fixed order: a butterfly per wavefront, then the
         // wavefronts in order); batch_energy adds the slab's blocks in order
-        tile_sum2_at<256>(eb, ea, s_red);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            eb += __shfl_xor(eb, o, 64);
+            ea += __shfl_xor(ea, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            s_red[threadIdx.x >> 6] = eb;
+            s_red[8 + (threadIdx.x >> 6)] = ea;
+        }
+        __syncthreads();
         if (threadIdx.x == 0) {
+            eb = s_red[0];
+            ea = s_red[8];
+#pragma unroll
+            for (int q = 1; q < CB / 64; ++q) {
+                eb += s_red[q];
+                ea += s_red[8 + q];
+            }
             A.epart[2 * blockIdx.x] = eb;
             A.epart[2 * blockIdx.x + 1] = ea;
         }
     }
 }
+static_assert(CB % 64 == 0 && CB <= 512, "per-cell blocks: whole wavefronts, at most eight");
 
 // the two per-slab solves: work-group tiles first (largest work first), then
 // wavefront tiles; PH 0: the prediction, 1: the correction
@@ -1275,23 +1293,23 @@ grte_status enqueue_step(grte_batch *b, hipStream_t s, int src, const hipEvent_t
     BCHK(hipGetLastError());
     const dim3 cg((unsigned)b->n_cblk), sg((unsigned)b->grid), eg((unsigned)((b->n + 255) / 256));
     if (b->f32) {
-        hipLaunchKernelGGL((cells_kernel<CP_PRED, true>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_PRED, true>), cg, dim3(CB), 0, s, A);
         if (kev) BCHK(hipEventRecord(kev[0], s));
         hipLaunchKernelGGL((solve_kernel<0, true>), sg, dim3(BNT), BATCH_LDS, s, A);
         if (kev) BCHK(hipEventRecord(kev[1], s));
-        hipLaunchKernelGGL((cells_kernel<CP_NEWTON, true>), cg, dim3(256), 0, s, A);
-        hipLaunchKernelGGL((cells_kernel<CP_CORR, true>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_NEWTON, true>), cg, dim3(CB), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_CORR, true>), cg, dim3(CB), 0, s, A);
         hipLaunchKernelGGL((solve_kernel<1, true>), sg, dim3(BNT), BATCH_LDS, s, A);
-        hipLaunchKernelGGL((cells_kernel<CP_PROJECT, true>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_PROJECT, true>), cg, dim3(CB), 0, s, A);
     } else {
-        hipLaunchKernelGGL((cells_kernel<CP_PRED, false>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_PRED, false>), cg, dim3(CB), 0, s, A);
         if (kev) BCHK(hipEventRecord(kev[0], s));
         hipLaunchKernelGGL((solve_kernel<0, false>), sg, dim3(BNT), BATCH_LDS, s, A);
         if (kev) BCHK(hipEventRecord(kev[1], s));
-        hipLaunchKernelGGL((cells_kernel<CP_NEWTON, false>), cg, dim3(256), 0, s, A);
-        hipLaunchKernelGGL((cells_kernel<CP_CORR, false>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_NEWTON, false>), cg, dim3(CB), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_CORR, false>), cg, dim3(CB), 0, s, A);
         hipLaunchKernelGGL((solve_kernel<1, false>), sg, dim3(BNT), BATCH_LDS, s, A);
-        hipLaunchKernelGGL((cells_kernel<CP_PROJECT, false>), cg, dim3(256), 0, s, A);
+        hipLaunchKernelGGL((cells_kernel<CP_PROJECT, false>), cg, dim3(CB), 0, s, A);
     }
     BCHK(hipGetLastError());
     hipLaunchKernelGGL(batch_energy, eg, dim3(256), 0, s, A);
@@ -1436,7 +1454,7 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
     for (int i = 0; i < n; ++i) {
         BInst &I = b->h_inst[i];
         I.cb0 = (int)cblk.size();
-        for (int c0 = 0; c0 < I.N; c0 += 256) cblk.push_back(make_int2(i, c0));
+        for (int c0 = 0; c0 < I.N; c0 += CB) cblk.push_back(make_int2(i, c0));
         I.ncb = (int)cblk.size() - I.cb0;
     }
     b->n_cblk = (int)cblk.size();
