@@ -263,6 +263,35 @@ def test_fp32_storage_full_size_against_fp64_storage():
     assert errs["E"] < 1e-5 and errs["Ox"] < 1e-5 and errs["Oy"] < 1e-5
 
 
+def test_binary32_krylov_full_size_against_binary64_krylov():
+    """Three steps of the 1024 x 1024 workload from its cold start with the
+    Krylov vectors in binary32 (passes of binary32 iterations inside binary64
+    true-residual restarts) and in binary64 throughout: both meet the same
+    binary64 residual tolerance, so the states agree to the solves' accuracy
+    (many column tiles, two-level reductions, several passes per solve)."""
+    w = config3()
+    res, infos = [], []
+    for narrow in (False, True):
+        g = _ctx(w)
+        g.set_storage(False)
+        g.set_krylov_storage(narrow)
+        g.set_state(w.E, w.Ox, w.Oy, w.T)
+        for _ in range(3):
+            info = g.step(w.dt, w.eps, info=True)
+            assert info["status"] == 0, info
+            assert info["pred_converged"] and info["corr_converged"], info
+            assert info["corr_narrow"] == int(narrow), info
+        infos.append(info)
+        res.append(g.get_state())
+        g.close()
+    (E0, X0, Y0, T0), (E1, X1, Y1, T1) = res
+    errs = {"T": _rel(T1, T0), "E": _rel(E1, E0), "Ox": _rel(X1, X0), "Oy": _rel(Y1, Y0)}
+    print("config3, 3 steps, binary32 vs binary64 Krylov vectors:", {k: f"{v:.2e}" for k, v in errs.items()},
+          "iterations", [(i["pred_iters"], i["corr_iters"]) for i in infos], flush=True)
+    for k, v in errs.items():
+        assert v < 1e-10, (k, v)
+
+
 @pytest.mark.parametrize("kind,steps", [("none", 1), ("multigrid", 1), ("multigrid", 2), ("chebyshev", 4)])
 def test_isotropic_correction_variants_agree(kind, steps):
     """The isotropic correction only changes the preconditioner: three
