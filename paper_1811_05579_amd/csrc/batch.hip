@@ -277,7 +277,7 @@ __device__ __forceinline__ IView<F32> iview(const BatchArgs &A, int i)
     V.N = I.N;
     V.P = I.P;
     V.N1 = I.N + 1;
-    V.NP = I.W * I.M;
+    V.NP = 64 * I.M;                           // rows per lane: wavefront M, work-group LMW
     V.Tn = A.T + I.oT;
     V.sg = A.sigma0 + I.oT;
     V.mu = A.mu + I.oP;
@@ -520,10 +520,13 @@ __device__ __forceinline__ void cell_project(const BatchArgs &A, const IView<F32
     ea = I.dx * (r1 / I.c + I.cv * t1);
 }
 
-template <int W, int M, bool F32>
+// W = BNT: a work-group tile of LMW rows per lane (NP = 64 LMW; M = LMW / 4 rows per
+// thread of the work-group-wide diffusion solve where LMW is a multiple of 4 and at
+// least 8); W = 64: a wavefront tile of M rows per lane
+template <int W, int M, bool F32, int LMW = 4 * M>
 __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm)
 {
-    constexpr int NP = W * M;
+    constexpr int NP = 64 * (W == BNT ? LMW : M);
     const BInst I = A.inst[i];
     const int N = I.N, P = I.P, N1 = N + 1;
     const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
@@ -550,7 +553,7 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
     // solver (LM = 4 M rows per lane, row j at LDS position (j % LM) 64 + j / LM);
     // wavefront tiles in their own position order (LM = M, the same formula).
     constexpr bool WG = (W == BNT);
-    constexpr int LM = WG ? 4 * M : M;
+    constexpr int LM = WG ? LMW : M;
     auto lpos = [](int j) { return (j % LM) * 64 + j / LM; };
     double *rho = sm, *sLl = sm + NP, *sLu = sm + 2 * NP, *sh = sm + 3 * NP;
     double *slam = nullptr, *slmg = nullptr, *accw = nullptr, *red = nullptr;
@@ -650,7 +653,7 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
                 __syncthreads();
                 double alpha, beta;
                 cheb_coeffs(Cs, A.accel, A.tol, alpha, beta);   // every wavefront: the same state
-                {
+                if constexpr (LM % 4 == 0 && LM >= 8) {
                     // res = sum_p omega_p v_p - (1 - W) rho (the four wavefronts' sums in
                     // a fixed order);  rho += res + D^{-1} (G res), G = Lam - (Lam - G),
                     // D = Lam - G + <mu^2> L + <mu> B (the diffusion operator of the DSA),
@@ -685,6 +688,50 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
                         mr = fmax(mr, fabs(nw));
                     }
                     // maxima over the tile: a butterfly per wavefront, then the four in order
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        md = fmax(md, __shfl_xor(md, o, 64));
+                        mr = fmax(mr, __shfl_xor(mr, o, 64));
+                    }
+                    if ((threadIdx.x & 63) == 0) {
+                        red[w] = md;
+                        red[8 + w] = mr;
+                    }
+                } else {
+                    // the same correction where the tile's rows per lane are not 4 M
+                    // (M >= 2): every wavefront solves the whole diffusion system in the
+                    // wavefront layout (lane_chunk_solve, LM rows per lane), the same in
+                    // all four; wavefront w then updates the rows r = w (mod 4) of its lanes
+                    const int lq = opaque(threadIdx.x & 63), jq = lq * LM, rl1 = N - 1 - jq;
+                    const double *ll = sLl + lq, *lu = sLu + lq, *lg = slmg + lq;
+                    auto res_at = [&](int r) {
+                        const int t = r * 64 + lq;
+                        const double tot = ((accw[t] + accw[NP + t]) + accw[2 * NP + t]) + accw[3 * NP + t];
+                        return tot - I.one_minus_W * rho[t];
+                    };
+                    double f[LM];
+#pragma unroll
+                    for (int r = 0; r < LM; ++r) f[r] = (slam[r * 64 + lq] - slmg[r * 64 + lq]) * res_at(r);
+                    __syncthreads();                  // every wavefront has read rho before any update
+                    const double b0 = jq == 0 ? bd0 : 0.0;
+                    auto bdr = [&](int r) { return (r == 0 ? b0 : 0.0) + (r == rl1 ? bdN : 0.0); };
+                    lane_chunk_solve<LM>(
+                        [&](int r) { return I.mu2 * ll[r * 64]; },
+                        [&](int r) { return lg[r * 64] + I.mu2 * (-(ll[r * 64] + lu[r * 64])) + I.mu1 * bdr(r); },
+                        [&](int r) { return I.mu2 * lu[r * 64]; }, f);
+                    double md = 0.0, mr = 0.0;
+#pragma unroll
+                    for (int r = 0; r < LM; ++r) {
+                        if ((r & 3) != w) continue;
+                        const int t = r * 64 + lq;
+                        const double z = res_at(r) + f[r];
+                        const double upd = alpha * (double)sdch[t] + beta * z;
+                        sdch[t] = (float)upd;
+                        const double nw = rho[t] + upd;
+                        rho[t] = nw;
+                        md = fmax(md, fabs(z));
+                        mr = fmax(mr, fabs(nw));
+                    }
 #pragma unroll
                     for (int o = 32; o > 0; o >>= 1) {
                         md = fmax(md, __shfl_xor(md, o, 64));
@@ -830,10 +877,10 @@ __device__ __forceinline__ void pred_solve(const BatchArgs &A, int i, double *sm
     if (k == 0 && !converged) atomicOr(A.sticky, GRTE_ERRF_PRED_NOCONV);
 }
 
-template <int W, int M, bool F32>
+template <int W, int M, bool F32, int LMW = 4 * M>
 __device__ __forceinline__ void corr_solve(const BatchArgs &A, int i, double *sm)
 {
-    constexpr int NP = W * M;
+    constexpr int NP = 64 * (W == BNT ? LMW : M);
     const BInst I = A.inst[i];
     const int N = I.N, P = I.P, N1 = N + 1;
     const int k = opaque(tile_lane<W>());   // opaque: per-thread addresses are formed per instance, not held across the queue loop
@@ -856,7 +903,7 @@ __device__ __forceinline__ void corr_solve(const BatchArgs &A, int i, double *sm
     double *Rt = A.pairs + I.oR;                  // right-hand sides
     double *Et = Rt + (size_t)P * I.NPa;          // E* (prediction), then E^{n+1} (correction)
     constexpr bool WG = (W == BNT);
-    constexpr int LM = WG ? 4 * M : M;
+    constexpr int LM = WG ? LMW : M;
     auto lpos = [](int j) { return (j % LM) * 64 + j / LM; };
     double *sLl = sm + NP, *sLu = sm + 2 * NP, *sh = sm + 3 * NP;
     double *slam = WG ? sm + 3 * NP : nullptr;
@@ -1042,24 +1089,40 @@ __global__ void __launch_bounds__(BNT) solve_kernel(BatchArgs A)
         if (q >= A.n_wg) break;
         const int i = A.order[q];
         if constexpr (PH == 0) {
-            switch (A.inst[i].M) {
-            case 2: pred_solve<BNT, 2, F32>(A, i, smem); break;
-            case 3: pred_solve<BNT, 3, F32>(A, i, smem); break;
-            case 4: pred_solve<BNT, 4, F32>(A, i, smem); break;
-            case 5: pred_solve<BNT, 5, F32>(A, i, smem); break;
-            case 6: pred_solve<BNT, 6, F32>(A, i, smem); break;
-            case 7: pred_solve<BNT, 7, F32>(A, i, smem); break;
-            default: pred_solve<BNT, 8, F32>(A, i, smem); break;
+            switch (A.inst[i].M) {   // rows per lane
+            case 4: pred_solve<BNT, 1, F32, 4>(A, i, smem); break;
+            case 6: pred_solve<BNT, 1, F32, 6>(A, i, smem); break;
+            case 8: pred_solve<BNT, 2, F32, 8>(A, i, smem); break;
+            case 10: pred_solve<BNT, 1, F32, 10>(A, i, smem); break;
+            case 12: pred_solve<BNT, 3, F32, 12>(A, i, smem); break;
+            case 14: pred_solve<BNT, 1, F32, 14>(A, i, smem); break;
+            case 16: pred_solve<BNT, 4, F32, 16>(A, i, smem); break;
+            case 18: pred_solve<BNT, 1, F32, 18>(A, i, smem); break;
+            case 20: pred_solve<BNT, 5, F32, 20>(A, i, smem); break;
+            case 22: pred_solve<BNT, 1, F32, 22>(A, i, smem); break;
+            case 24: pred_solve<BNT, 6, F32, 24>(A, i, smem); break;
+            case 26: pred_solve<BNT, 1, F32, 26>(A, i, smem); break;
+            case 28: pred_solve<BNT, 7, F32, 28>(A, i, smem); break;
+            case 30: pred_solve<BNT, 1, F32, 30>(A, i, smem); break;
+            case 32: pred_solve<BNT, 8, F32, 32>(A, i, smem); break;
             }
         } else {
             switch (A.inst[i].M) {
-            case 2: corr_solve<BNT, 2, F32>(A, i, smem); break;
-            case 3: corr_solve<BNT, 3, F32>(A, i, smem); break;
-            case 4: corr_solve<BNT, 4, F32>(A, i, smem); break;
-            case 5: corr_solve<BNT, 5, F32>(A, i, smem); break;
-            case 6: corr_solve<BNT, 6, F32>(A, i, smem); break;
-            case 7: corr_solve<BNT, 7, F32>(A, i, smem); break;
-            default: corr_solve<BNT, 8, F32>(A, i, smem); break;
+            case 4: corr_solve<BNT, 1, F32, 4>(A, i, smem); break;
+            case 6: corr_solve<BNT, 1, F32, 6>(A, i, smem); break;
+            case 8: corr_solve<BNT, 2, F32, 8>(A, i, smem); break;
+            case 10: corr_solve<BNT, 1, F32, 10>(A, i, smem); break;
+            case 12: corr_solve<BNT, 3, F32, 12>(A, i, smem); break;
+            case 14: corr_solve<BNT, 1, F32, 14>(A, i, smem); break;
+            case 16: corr_solve<BNT, 4, F32, 16>(A, i, smem); break;
+            case 18: corr_solve<BNT, 1, F32, 18>(A, i, smem); break;
+            case 20: corr_solve<BNT, 5, F32, 20>(A, i, smem); break;
+            case 22: corr_solve<BNT, 1, F32, 22>(A, i, smem); break;
+            case 24: corr_solve<BNT, 6, F32, 24>(A, i, smem); break;
+            case 26: corr_solve<BNT, 1, F32, 26>(A, i, smem); break;
+            case 28: corr_solve<BNT, 7, F32, 28>(A, i, smem); break;
+            case 30: corr_solve<BNT, 1, F32, 30>(A, i, smem); break;
+            case 32: corr_solve<BNT, 8, F32, 32>(A, i, smem); break;
             }
         }
     }
@@ -1129,16 +1192,17 @@ int pow2_rows(int N, int W)
     return M;
 }
 
-// rows per thread of a slab's tile: a wavefront tile takes 2 or 4 (powers of
-// two), a work-group tile the smallest M = 2 .. 8 whose 256 M rows hold the
-// slab -- the padding rows cost as much as real ones, and with powers of two
-// alone a third of the solves' rows were padding on slabs of N ~ U{64..2048}
+// rows per lane of a slab's tile (the tile holds 64 x that many rows): a
+// wavefront tile takes 2 or 4 (powers of two), a work-group tile the smallest
+// even LM = 4 .. 32 that holds the slab -- the padding rows cost as much as
+// real ones, and with 256-row steps 12 % of the solves' rows were padding on
+// slabs of N ~ U{64..2048}
 int tile_rows(int N, int W)
 {
     if (W != BNT) return pow2_rows(N, W);
-    int M = 2;
-    while (BNT * M < N) ++M;
-    return M;
+    int LM = 4;
+    while (64 * LM < N) LM += 2;
+    return LM;
 }
 
 }  // namespace
@@ -1438,7 +1502,7 @@ grte_status grte_batch_create(int n, const grte_instance *inst, const double *mu
         I.mu1 = m1;
         I.mu2 = m2;
         I.oE = oE; I.oO = oO; I.oT = oT; I.oP = oP; I.oC = oC; I.oR = oR;
-        I.NPa = (long long)BNT * tile_rows(I.N, BNT);   // also covers every wavefront tile (N <= 256)
+        I.NPa = 64LL * tile_rows(I.N, BNT);   // also covers every wavefront tile (N <= 256)
         oE += (long long)I.N * I.P;
         oO += (long long)(I.N + 1) * I.P;
         oT += I.N;
