@@ -55,9 +55,9 @@ def _tol(w):
     return _BARS[key]
 
 
-# (N, nv, m, eps): wavefront tiles (N <= 256) and work-group tiles of every size
-# (256 M rows, M = 2 .. 8; the last three with few pairs, so that the oracle
-# comparison takes the M = 3, 5 and 7 tiles too)
+# (N, nv, m, eps): wavefront tiles (N <= 256) and work-group tiles of many sizes
+# (64 LM rows, LM even, 4 .. 32; the last three with few pairs, so that the oracle
+# comparison takes tiles whose LM is not a multiple of 4 too)
 MIX = [(2, 2, 0, 1.0), (37, 16, 3, 1e-2), (64, 8, 0, 1e-4), (129, 32, 3, 1.0), (256, 64, 3, 1e-3),
        (257, 16, 0, 1e-2), (511, 8, 3, 1e-5), (512, 32, 0, 1.0), (700, 64, 3, 1e-2),
        (1024, 4, 3, 1e-4), (1500, 16, 0, 1e-1), (2048, 32, 3, 1e-2), (97, 128, 3, 1e-3),
