@@ -58,9 +58,9 @@ TRAFFIC = {
     ("config2", "fp64"): (9.2663e7, "profiles/pred_kernel_config2_hbm_traffic.txt"),
     ("config2", "fp32"): (None, None),
     ("config4", "fp64"): (None, None),
-    ("config4", "fp32"): (1.4957e+10, "profiles/batch_step_config4_hbm_traffic.txt"),
+    ("config4", "fp32"): (1.4518e+10, "profiles/batch_step_config4_hbm_traffic.txt"),
     ("config4-solve", "fp64"): (None, None),
-    ("config4-solve", "fp32"): (7.0179e+09, "profiles/batch_step_config4_hbm_traffic.txt"),
+    ("config4-solve", "fp32"): (6.6451e+09, "profiles/batch_step_config4_hbm_traffic.txt"),
     # the timed 2-D operator launches have binary32 Krylov vectors whatever the state storage
     ("config3", "fp64"): (2.3909e8, "profiles/apply2d_config3_hbm_traffic.txt"),
     ("config3", "fp32"): (2.3909e8, "profiles/apply2d_config3_hbm_traffic.txt"),
