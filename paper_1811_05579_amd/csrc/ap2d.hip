@@ -482,7 +482,7 @@ __device__ __forceinline__ void block_sums_at(double *vals, int k, double *part,
 }
 
 template <int MODE, class V>
-__global__ void __launch_bounds__(B2) apply2d_col_kernel(VecArgs A, int ncol, int ntile)
+__global__ void __launch_bounds__(B2, 5) apply2d_col_kernel(VecArgs A, int ncol, int ntile)
 {
     if (A.fl[F_STATE] != 0) return;
     const Sys &S = A.S;
