@@ -49,10 +49,11 @@ namespace {
 constexpr int B2 = 256;        // threads per block of the (cell, pair) kernels
 constexpr int MAXB = 2048;     // blocks of the grid-stride kernels outside the Krylov loop
 // the Krylov kernels over the N*P items run KRY_ITEMS items per thread (up to
-// KRYB blocks); their per-block partial sums are reduced in two levels (RED_B
-// partials per block of the first level, then one block) when there are more
-// than RED_B of them (both figures can be set per context)
-constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = 2048;
+// KRYB blocks); their per-block partial sums are reduced by one block of
+// FIN_T threads, or in two levels (RED_B partials per block of the first
+// level, then that block) when there are more than RED_B of them (both figures
+// can be set per context; by default every count takes the one level)
+constexpr int KRYB = 16384, KRY_ITEMS = 4, RED_B = KRYB;
 constexpr int OPC_N = 8;       // doubles per cell of the operator's packed coefficients (opc2d_kernel)
 constexpr int CHUNK = 8;       // most BiCGStab iterations enqueued between convergence checks
 constexpr int KRY_RESTARTS = 12;     // restarts from the true residual per solve
@@ -1208,25 +1209,51 @@ __global__ void __launch_bounds__(B2) red2d_kernel(VecArgs A, int which, int k, 
     }
 }
 
-// sum k of the nb partials (through the first level when nb > red_b)
-__device__ __forceinline__ double fin_sum(const VecArgs &A, int k, int nb)
+// the final reduction: one block of FIN_T threads
+constexpr int FIN_T = 1024;
+
+// the K sums of nb partials each (through the first level when nb > red_b):
+// thread i adds partials i, i + FIN_T, ... in that order, then each wavefront
+// reduces by a butterfly and the wavefronts are added in order (a fixed order,
+// independent of timing); every thread gets the totals
+template <int K>
+__device__ __forceinline__ void fin_sums(const VecArgs &A, int nb, double (&s)[K])
 {
+    __shared__ double red[K][FIN_T / 64];
     const bool two = nb > A.red_b;
     const double *part = two ? A.part2 : A.part;
     const int cnt = two ? (nb + A.red_b - 1) / A.red_b : nb;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < cnt; i += B2) v += part[k * KRYB + i];
-    return block_reduce(v);
+    double v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = 0.0;
+#pragma unroll 4
+    for (int i = threadIdx.x; i < cnt; i += FIN_T)
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] += part[q * KRYB + i];
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+        if (lane == 0) red[q][w] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double t = 0.0;
+        for (int i = 0; i < FIN_T / 64; ++i) t += red[q][i];
+        s[q] = t;
+    }
 }
 
 // which: 0 = start (rho = (h, r), rr = (r, r), bb, test), 1 = alpha, 2 = omega, 3 = rho/beta/test
-__global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
+__global__ void __launch_bounds__(FIN_T) fin2d_kernel(VecArgs A, int which, int nb)
 {
     if (which != 0 && A.fl[F_STATE] != 0) return;
     double *sc = A.sc;
     if (which == 0) {
-        const double rr = fin_sum(A, 0, nb), bb = fin_sum(A, 1, nb), mm = fin_sum(A, 2, nb);
-        const double hr = fin_sum(A, 3, nb);
+        double f[4];
+        fin_sums<4>(A, nb, f);
+        const double rr = f[0], bb = f[1], mm = f[2], hr = f[3];
         if (threadIdx.x == 0) {
             sc[S_RHO] = hr;
             sc[S_RR] = rr;
@@ -1238,14 +1265,18 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
             A.fl[F_STATE] = (rr <= A.tol * A.tol * bb) ? 1 : 0;
         }
     } else if (which == 1) {
-        const double rv = fin_sum(A, 0, nb);
+        double f[1];
+        fin_sums<1>(A, nb, f);
+        const double rv = f[0];
         if (threadIdx.x == 0) {
             sc[S_RV] = rv;
             if (rv == 0.0 || !isfinite(rv)) A.fl[F_STATE] = 2;
             else sc[S_ALPHA] = sc[S_RHO] / rv;
         }
     } else if (which == 2) {
-        const double ts = fin_sum(A, 0, nb), tt = fin_sum(A, 1, nb);
+        double f[2];
+        fin_sums<2>(A, nb, f);
+        const double ts = f[0], tt = f[1];
         if (threadIdx.x == 0) {
             sc[S_TS] = ts;
             sc[S_TT] = tt;
@@ -1255,7 +1286,9 @@ __global__ void __launch_bounds__(B2) fin2d_kernel(VecArgs A, int which, int nb)
             else sc[S_OMEGA] = tt == 0.0 ? 0.0 : ts / tt;
         }
     } else {
-        const double rho = fin_sum(A, 0, nb), rr = fin_sum(A, 1, nb);
+        double f[2];
+        fin_sums<2>(A, nb, f);
+        const double rho = f[0], rr = f[1];
         if (threadIdx.x == 0) {
             const int its = A.fl[F_ITS] + 1;
             A.fl[F_ITS] = its;
@@ -2029,7 +2062,7 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
         if (nbk > c->red_b)
             hipLaunchKernelGGL(red2d_kernel, dim3((nbk + c->red_b - 1) / c->red_b), dim3(B2), 0, st, A, which, k,
                                nbk);
-        hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(B2), 0, st, A, which, nbk);
+        hipLaunchKernelGGL(fin2d_kernel, dim3(1), dim3(FIN_T), 0, st, A, which, nbk);
     };
     int its_total = 0, state = 0;
     // iterations are enqueued in batches between convergence checks; the
