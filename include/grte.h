@@ -632,7 +632,8 @@ grte_status grte2d_set_solver(grte2d_ctx *ctx, double tol, int maxit);
  * (cell, pair) items (1..64, default 4; at most 16384 blocks of 256 threads),
  * and the per-block partial sums of the inner products are reduced in two
  * levels when there are more than `first_level` of them (1..16384, default
- * 2048: blocks of that many partials, then one block), else in one.  The
+ * 16384: blocks of that many partials, then one block), else by one block of
+ * 1024 threads.  The
  * results differ only in the order of the binary64 sums.  A small shape makes
  * a small grid run the many-block, two-level path of a large one (tests).
  * GRTE_E_INVAL outside those ranges. */
