@@ -472,10 +472,10 @@ def test_iteration_cap_holds_for_the_whole_solve():
 @pytest.mark.parametrize("case,shape", [("random", (1, 4)), ("two_material", (1, 2)), ("random", (3, 1))])
 def test_many_block_two_level_path_against_oracle(case, shape):
     """A launch shape of one or three items per thread and a first reduction
-    level of one to four partials makes these grids run the path of the
-    full-size workloads -- many blocks, the partial sums reduced in two
-    levels -- which the default shape only takes above ~2 million items;
-    the step still matches the oracle and the default shape's step."""
+    level of one to four partials makes these grids run many blocks whose
+    partial sums are reduced in two levels (the default shape sums any count
+    of partials in one block of 1024 threads); the step still matches the
+    oracle and the default shape's step."""
     if case == "random":
         w = random_state_2d(37, 29, 8, 8, m=0, eps=1e-2)
     else:
