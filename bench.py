@@ -401,7 +401,11 @@ def main_2d(args):
     elapsed_ms = start.elapsed_time(stop)
     ms, cnt = g.read_timing()
     N, P = w.nx * w.ny, w.P
-    launch_s = ms / max(cnt, 1) / 1e3
+    if cnt == 0:
+        # the events time the binary32 operator launches only
+        sys.exit("bench: no binary32 Krylov solve ran in the timed steps, so the operator kernel "
+                 "was not timed; the roofline needs at least one")
+    launch_s = ms / cnt / 1e3
     achieved = op2d_algorithmic_bytes(N, P) / launch_s / 1e9
     value = w.cell_angle_updates() * args.steps / (elapsed_ms / 1e3)
     line = {
