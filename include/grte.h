@@ -649,9 +649,10 @@ grte_status grte2d_set_launch_shape(grte2d_ctx *ctx, int items_per_thread, int f
  * tolerance, so that a solve takes several passes.  The prediction keeps
  * binary64 vectors when some cell's block inverse (diagonal plus the rank-one
  * angular coupling g of (4.5c)) has a Sherman-Morrison denominator
- * 1 - g sum_p omega_p / d_p below 1e-5: it falls like 1 / (a c beta) in stiff
- * cells, where binary32 directions would lose the near-isotropic mode the
- * inverse amplifies.  The correction's blocks are diagonal.  The info struct
+ * 1 - g sum_p omega_p / d_p below 1e-8: it falls like 1 / (a c beta) in stiff
+ * cells, where binary32 directions lose the near-isotropic mode the inverse
+ * amplifies (just above that level they take more iterations than binary64
+ * ones, each cheaper).  The correction's blocks are diagonal.  The info struct
  * reports the storage each solve used.  GRTE_E_INVAL for a NULL context or
  * narrow not 0 or 1. */
 grte_status grte2d_set_krylov_storage(grte2d_ctx *ctx, int narrow);

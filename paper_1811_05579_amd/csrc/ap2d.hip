@@ -64,9 +64,11 @@ constexpr double KRY_PASS_RED = 1e-5;
 // binary32 Krylov vectors only where every cell's block inverse amplifies
 // rounding by at most 1 / KRY_F32_GAP (its Sherman-Morrison denominator 1 - g
 // sum_p omega_p / d_p is at least KRY_F32_GAP; it falls like 1 / (a c beta) in
-// stiff cells, where a binary32 direction would carry too little of the
-// near-isotropic mode to precondition)
-constexpr double KRY_F32_GAP = 1e-5;
+// stiff cells, where a binary32 direction carries less and less of the
+// near-isotropic mode: below ~1e-8 the binary32 solve can diverge (a c beta
+// ~ 1e13), just above it it takes more iterations than a binary64 one, each
+// cheaper)
+constexpr double KRY_F32_GAP = 1e-8;
 // the recursion runs on to this fraction of the tolerance before the true
 // residual is taken: a restarted binary32 recursion stopped at the tolerance
 // itself leaves, on stiff systems whose residual sits at the rounding floor,

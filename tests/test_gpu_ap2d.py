@@ -108,7 +108,7 @@ def test_one_step_matches_oracle(nx, ny, nv, m, eps, seed, narrow):
     elif stiffness(w, w.T) < 1e3:
         # the prediction keeps binary64 vectors only where a cell's block inverse
         # is near singular: 1 - g sum_p omega_p / d_p >= 1 / (1 + a c beta) of
-        # (4.5c), above 1e-5 on these mild states
+        # (4.5c), above 1e-8 on these mild states
         assert info["pred_narrow"] == 1, info
     o, bar = oracle_with_bars(w, w.E, w.Ox, w.Oy, w.T)
     _compare(w, r, o, w.T, bar)
