@@ -268,7 +268,8 @@ def test_binary32_krylov_full_size_against_binary64_krylov():
     Krylov vectors in binary32 (passes of binary32 iterations inside binary64
     true-residual restarts) and in binary64 throughout: both meet the same
     binary64 residual tolerance, so the states agree to the solves' accuracy
-    (many column tiles, two-level reductions, several passes per solve)."""
+    (many column tiles, 16,384 block partials per inner product summed in one
+    launch, several passes per solve)."""
     w = config3()
     res, infos = [], []
     for narrow in (False, True):
@@ -287,6 +288,31 @@ def test_binary32_krylov_full_size_against_binary64_krylov():
     (E0, X0, Y0, T0), (E1, X1, Y1, T1) = res
     errs = {"T": _rel(T1, T0), "E": _rel(E1, E0), "Ox": _rel(X1, X0), "Oy": _rel(Y1, Y0)}
     print("config3, 3 steps, binary32 vs binary64 Krylov vectors:", {k: f"{v:.2e}" for k, v in errs.items()},
+          "iterations", [(i["pred_iters"], i["corr_iters"]) for i in infos], flush=True)
+    for k, v in errs.items():
+        assert v < 1e-10, (k, v)
+
+
+def test_full_size_one_level_reduction_against_two_levels():
+    """On the 1024 x 1024 workload an inner product has 16,384 block partials
+    (vector updates) or 4096 (operator products).  By default one block of
+    1024 threads sums them all; with a first level of 2048 they are summed by
+    blocks of 2048 partials and then one block.  The two steps differ only in
+    the order of the binary64 sums, so they agree to the solves' accuracy."""
+    w = config3()
+    res, infos = [], []
+    for shape in (None, (4, 2048)):
+        g = _ctx(w)
+        if shape is not None:
+            g.set_launch_shape(*shape)
+        r, info = gpu_step(g, w, w.E, w.Ox, w.Oy, w.T)
+        g.close()
+        assert info["status"] == 0, info
+        assert info["pred_converged"] and info["corr_converged"], info
+        res.append(r)
+        infos.append(info)
+    errs = {k: _rel(res[1][k], res[0][k]) for k in ("T", "E", "Ox", "Oy", "E_star", "D")}
+    print("config3, one level vs two levels:", {k: f"{v:.2e}" for k, v in errs.items()},
           "iterations", [(i["pred_iters"], i["corr_iters"]) for i in infos], flush=True)
     for k, v in errs.items():
         assert v < 1e-10, (k, v)
