@@ -679,11 +679,13 @@ __device__ __forceinline__ double precond_at(const Sys &S, double y, double id, 
 // angular sums stay within whole cells.
 constexpr int KI = 4;
 
-// p = r + beta (p - omega v); ph = B^{-1} p (+ dP)
+// p = r + beta (p - omega v), p = r in the first iteration of a pass (p and v
+// are not read then: they hold the last pass's vectors); ph = B^{-1} p (+ dP)
 template <class V>
 __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
+    const bool first = A.fl[F_ITS] == 0;
     const double beta = A.sc[S_BETA], omega = A.sc[S_OMEGA];
     const int P = A.S.P, lgP = A.S.lgP, n = (int)A.n, G = gridDim.x * B2;
     const V *__restrict__ r = (const V *)A.r;
@@ -701,8 +703,8 @@ __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
         for (int k = 0; k < KI; ++k) {
             const int t = t0 + k * G < n ? t0 + k * G : t0;
             rv[k] = r[t];
-            pv[k] = pp[t];
-            vv[k] = v[t];
+            pv[k] = first ? 0.0 : (double)pp[t];
+            vv[k] = first ? 0.0 : (double)v[t];
             id[k] = idg[t];
             dd[k] = dP ? dP[t >> lgP] : 0.0;
             pg[k] = A.S.corr ? 0.0 : pgc[t >> lgP];
@@ -711,7 +713,7 @@ __global__ void __launch_bounds__(B2) pupd2d_kernel(VecArgs A)
         for (int k = 0; k < KI; ++k) {
             const int t = t0 + k * G;
             if (t >= n) break;
-            const V pn = (V)(rv[k] + beta * (pv[k] - omega * vv[k]));
+            const V pn = first ? (V)rv[k] : (V)(rv[k] + beta * (pv[k] - omega * vv[k]));
             pp[t] = pn;
             ph[t] = (V)(precond_at(A.S, pn, id[k], pg[k], wp) + dd[k]);
         }
@@ -770,12 +772,14 @@ __global__ void __launch_bounds__(B2) ymom2d_kernel(VecArgs A, int which, int n)
 }
 
 // dx += alpha ph + omega sh (the pass's correction of x, stored as V and added
-// to the binary64 x when the pass ends); r = s - omega t (and its moment);
-// partial (h, r), (r, r)
+// to the binary64 x when the pass ends; dx = alpha ph + omega sh in the first
+// iteration of a pass, the last pass's dx not read); r = s - omega t (and its
+// moment); partial (h, r), (r, r)
 template <class V>
 __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 {
     if (A.fl[F_STATE] != 0) return;
+    const bool first = A.fl[F_ITS] == 0;
     const double alpha = A.sc[S_ALPHA], omega = A.sc[S_OMEGA];
     const int P = A.S.P, lgP = A.S.lgP, n = (int)A.n, G = gridDim.x * B2;
     const V *__restrict__ ph = (const V *)A.ph;
@@ -792,7 +796,7 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
 #pragma unroll
         for (int k = 0; k < KI; ++k) {
             const int t = t0 + k * G < n ? t0 + k * G : t0;
-            xv[k] = dx[t];
+            xv[k] = first ? 0.0 : (double)dx[t];
             pv[k] = ph[t];
             hv[k] = sh[t];
             sv[k] = sa[t];
@@ -803,7 +807,7 @@ __global__ void __launch_bounds__(B2) xupd2d_kernel(VecArgs A)
             const int t = t0 + k * G;
             if (t >= n) break;
             const int j = t >> lgP, p = t & (P - 1);
-            dx[t] = (V)(xv[k] + (alpha * pv[k] + omega * hv[k]));
+            dx[t] = first ? (V)(alpha * pv[k] + omega * hv[k]) : (V)(xv[k] + (alpha * pv[k] + omega * hv[k]));
             const V rs = (V)(sv[k] - omega * tv[k]);
             r[t] = rs;
             const double rv = rs;
@@ -1316,17 +1320,13 @@ __global__ void __launch_bounds__(B2) zero2_kernel(double *a, double *b, size_t 
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) a[t] = b[t] = 0.0;
 }
 
-template <class V>
-__global__ void __launch_bounds__(B2) zero3v_kernel(void *av, void *bv, void *cv, size_t n)
-{
-    V *a = (V *)av, *b = (V *)bv, *c = (V *)cv;
-    for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) a[t] = b[t] = c[t] = (V)0;
-}
-
 // x += dx at the end of a pass
 template <class V>
-__global__ void __launch_bounds__(B2) xadd_kernel(double *x, const void *dv, size_t n)
+__global__ void __launch_bounds__(B2) xadd_kernel(double *x, const void *dv, size_t n, const int *fl)
 {
+    // no iteration of the pass completed (a breakdown in its first): dx holds
+    // the last pass's correction, already added
+    if (fl[F_ITS] == 0) return;
     const V *d = (const V *)dv;
     for (int t = blockIdx.x * B2 + threadIdx.x; t < (int)n; t += gridDim.x * B2) x[t] += (double)d[t];
 }
@@ -2078,9 +2078,9 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
         hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(64), 0, st, c->fl);
         hipLaunchKernelGGL(residual2d_kernel<V>, dim3(nb), dim3(B2), 0, st, A);
         fin(0, 4, nb);
-        hipLaunchKernelGGL(zero3v_kernel<V>, dim3(nb), dim3(B2), 0, st, (void *)c->p, (void *)c->v, (void *)c->dxv,
-                           c->nE);
-        // the moments of p and v start from zero with them
+        // the recurrence of the isotropic correction's input starts from zero
+        // moments (the pass's first iteration takes p = r and dx = alpha ph +
+        // omega sh, so p, v and dx need no clearing)
         if (iso) hipLaunchKernelGGL(zero2_kernel, dim3(nbc), dim3(B2), 0, st, c->yP, c->mv, c->N);
         if (hipMemcpyAsync(c->h_fl, c->fl, F_NF * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
             return GRTE_E_HIP;
@@ -2146,7 +2146,7 @@ grte_status krylov_run(grte2d_ctx *c, const Sys &S, int &its_out, int &state_out
         }
         its_total += c->h_fl[F_ITS];
         pass_its[restart] = c->h_fl[F_ITS];
-        hipLaunchKernelGGL(xadd_kernel<V>, dim3(nb), dim3(B2), 0, st, c->x, (const void *)c->dxv, c->nE);
+        hipLaunchKernelGGL(xadd_kernel<V>, dim3(nb), dim3(B2), 0, st, c->x, (const void *)c->dxv, c->nE, c->fl);
         // the recursion's residual has met the tolerance (or broken down): the
         // next pass recomputes the true residual and restarts from it if needed
         if (c->h_fl[F_STATE] == 3 && its_total >= c->maxit) {
